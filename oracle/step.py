@@ -1,0 +1,159 @@
+"""One time step of the method, in the paper's segregated order (Section 3.1).
+
+Test infrastructure: the CPU oracle only.
+
+State (torch.float64, CPU):
+  alpha (nx,ny,nz)   liquid volume fraction
+  c     (nx,ny,nz)   vapour partial density rho_G theta omega (kg/m^3)
+  omega (nx,ny,nz)   vapour mass fraction in the gas
+  T     (nx,ny,nz)   temperature
+  p     (nx,ny,nz)   p_rgh
+  u (nx+1,ny,nz), v (nx,ny+1,nz), w (nx,ny,nz+1)   face velocities
+
+Order (the six steps of Section 3.1):
+  1. evaporation flux  (interface.geometry, raw_evaporation, redistribute)
+  2. alpha source      alpha1 = alpha - dt mdot/rho_L          (eq. 4)
+  3. advection         vof.advect                              (eq. 3)
+  4. properties        eq. 31 on alpha' clamped to [0, 1]; theta = max(1-alpha', theta_min)
+  5. energy, species (operators) and momentum predictor (momentum)
+  6. pressure (eq. 7) and velocity correction
+Species conservation reading: vapour lives in the gas fraction only; c is
+moved with the gas volume flux, gains mdot, and is updated after the
+implicit solve in flux form c = c' + dt mdot - dt sum_f K_f (omega_c - omega_nb),
+so the fuel mass h^3 sum(rho_L alpha + c) changes only by what crosses the
+boundary.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import interface, momentum, operators, thermo, vof
+
+
+def to_state(fields, prm, rho_G=None):
+    """Build the oracle state from numpy/torch initial fields (omega given)."""
+    st = {k: torch.as_tensor(v, dtype=torch.float64).clone() for k, v in fields.items()}
+    if rho_G is None:
+        rho_G = thermo.gas_density(prm)
+    theta = torch.clamp(1.0 - torch.clamp(st["alpha"], 0.0, 1.0), min=prm["theta_min"])
+    st["c"] = rho_G * theta * st["omega"]
+    return st
+
+
+def properties(alpha, prm, rho_G):
+    ab = torch.clamp(alpha, 0.0, 1.0)
+    rho = ab * prm["rho_L"] + (1.0 - ab) * rho_G
+    cp = ab * prm["cp_L"] + (1.0 - ab) * prm["cp_G"]
+    k = ab * prm["k_L"] + (1.0 - ab) * prm["k_G"]
+    theta = torch.clamp(1.0 - ab, min=prm["theta_min"])
+    return ab, rho, cp, k, theta
+
+
+def evaporation_source(st, prm, rho_G, D_v=None):
+    """Steps S1-S4: (mdot, mdot_raw, K, geometry)."""
+    if not prm["evaporation"]:
+        z = torch.zeros_like(st["alpha"])
+        return z, z, torch.zeros((), dtype=torch.float64), None
+    geo = interface.geometry(st["alpha"], prm)
+    mraw = interface.raw_evaporation(st["alpha"], st["T"], st["omega"], st["u"], st["v"], st["w"],
+                                     geo, prm, rho_G, D_v=D_v)
+    mdot, K = interface.redistribute(mraw, st["alpha"])
+    return mdot, mraw, K, geo
+
+
+def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record=None):
+    """Advance the state by one step.  Returns (new_state, diagnostics).
+
+    T_amb, D_v, dh_ev may be passed as tensors (for differentiation); they
+    default to the parameter values.  record, if a dict, receives the
+    intermediate fields of the step.
+    """
+    prm = dict(prm)
+    if dh_ev is not None:
+        prm["dh_ev"] = dh_ev
+    D = prm["D_v"] if D_v is None else D_v
+    Ta = prm["T_amb"] if T_amb is None else T_amb
+    tol = prm["tol"] if tol is None else tol
+    if rho_G is None:
+        rho_G = thermo.gas_density(prm, Ta)
+    dt, h = prm["dt"], prm["h"]
+    U = [st["u"], st["v"], st["w"]]
+
+    # 1. evaporation flux
+    mdot, mraw, K, geo = evaporation_source(st, prm, rho_G, D_v=D)
+    # 2. liquid source
+    alpha1 = st["alpha"] - dt * mdot / prm["rho_L"]
+    # 3. advection
+    alpha_p, c_p, T_p, B_L, B_v = vof.advect(alpha1, st["omega"], st["T"], st["c"], *U, prm, rho_G,
+                                             T_amb=Ta, advect_T=bool(prm["solve_energy"]))
+    # 4. properties
+    ab, rho, cp, k, theta = properties(alpha_p, prm, rho_G)
+    diag = {}
+    # 5a. energy
+    if prm["solve_energy"]:
+        m = rho * cp / dt
+        op, rb = operators.scalar_system(m, k, 1.0 / (h * h), 2.0 * prm["k_G"] / (h * h), Ta, U, prm)
+        b = m * T_p - mdot * prm["dh_ev"] + rb
+        T_new, itT, resT, okT = operators.pcg(op, b, T_p, tol, prm["maxit"])
+    else:
+        T_new, itT, resT, okT = st["T"], 0, 0.0, True
+    # 5b. species
+    mS = rho_G * theta / dt
+    KbS = 2.0 * rho_G * D / (h * h)
+    opS, _ = operators.scalar_system(mS, theta, rho_G * D / (h * h), KbS, 0.0, U, prm)
+    bS = c_p / dt + mdot
+    omega_p = c_p / (rho_G * theta)
+    om, itS, resS, okS = operators.pcg(opS, bS, omega_p, tol, prm["maxit"])
+    face_part = opS.apply(om) - mS * om
+    c_new = c_p + dt * mdot - dt * face_part
+    # vapour diffused out through ambient (Dirichlet) boundary faces
+    B_diff = torch.zeros((), dtype=torch.float64)
+    for axis in range(3):
+        Ka = torch.movedim(opS.K[axis], axis, 0)
+        oa = torch.movedim(om, axis, 0)
+        B_diff = B_diff + (Ka[0] * oa[0]).sum() + (Ka[-1] * oa[-1]).sum()
+    B_v = B_v + dt * h ** 3 * B_diff
+    omega_new = c_new / (rho_G * theta)
+    # 5c. momentum predictor
+    Us = momentum.predictor(U, ab, rho, prm)
+    # 6. pressure and correction
+    beta = 1.0 / rho
+    opP = operators.pressure_operator(beta, prm)
+    S = mdot * (1.0 / rho_G - 1.0 / prm["rho_L"])
+    bP = S - operators.divergence(*Us, h)
+    p_new, itP, resP, okP = operators.pcg(opP, bP, st["p"], tol, prm["maxit"])
+    Un = momentum.project(Us, p_new, rho, prm)
+
+    new = dict(alpha=alpha_p, c=c_new, omega=omega_new, T=T_new, p=p_new, u=Un[0], v=Un[1], w=Un[2])
+    vol = h ** 3
+    diag.update(
+        K=float(K), mdot_total=float(vol * mdot.sum()), B_L=float(B_L), B_v=float(B_v),
+        volume=float(vol * alpha_p.sum()),
+        fuel_mass=float(vol * (prm["rho_L"] * alpha_p + c_new).sum()),
+        fuel_mass_before=float(vol * (prm["rho_L"] * st["alpha"] + st["c"]).sum()),
+        alpha_min=float(alpha_p.min()), alpha_max=float(alpha_p.max()),
+        n_interface=0 if geo is None else int(geo["icells"].shape[0]),
+        iters=dict(T=itT, omega=itS, p=itP), res=dict(T=resT, omega=resS, p=resP),
+        converged=bool(okT and okS and okP),
+    )
+    if record is not None:
+        record.update(mdot=mdot, mraw=mraw, K=K, geo=geo, alpha1=alpha1, alpha_p=alpha_p, c_p=c_p,
+                      T_p=T_p, rho=rho, theta=theta, ustar=Us, bP=bP, rho_G=rho_G,
+                      B_L_adv=B_L, B_diff=B_diff)
+    return new, diag
+
+
+def droplet_volume(st, prm):
+    return float(prm["h"] ** 3 * st["alpha"].sum())
+
+
+def run(fields, prm, steps, tol=None, callback=None):
+    """Initial fields -> state after `steps` steps (and per-step diagnostics)."""
+    st = to_state(fields, prm)
+    diags = []
+    for n in range(steps):
+        st, d = step(st, prm, tol=tol)
+        diags.append(d)
+        if callback is not None:
+            callback(n, st, d)
+    return st, diags
