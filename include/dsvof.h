@@ -1,0 +1,176 @@
+/*
+ * dsvof -- one GPU (gfx950) time step of a VOF droplet-evaporation method:
+ * liquid-fraction transport with an interface evaporation source, implicit
+ * energy and vapour-species diffusion, and a variable-density pressure
+ * projection with gravity and a centripetal body force.
+ *
+ * Method: arXiv 2005.02867 (DropletSMOKE++), Sections 2-3.  The step follows
+ * the segregated order of Section 3.1 (evaporation flux, liquid source,
+ * interface advection, properties, momentum/energy/species, pressure and
+ * velocity correction), discretised on a uniform Cartesian grid.
+ *
+ * Grid and layout (all arrays are device pointers, IEEE binary64, dense):
+ *   cells (i, j, k), 0 <= i < nx ..., spacing h, centre ((i+.5)h, (j+.5)h, (k+.5)h);
+ *   cell array index  (i*ny + j)*nz + k          (z fastest)
+ *   u: (nx+1)*ny*nz   index (i*ny + j)*nz + k    (face i at x = i h)
+ *   v: nx*(ny+1)*nz   index (i*(ny+1) + j)*nz + k
+ *   w: nx*ny*(nz+1)   index (i*ny + j)*(nz+1) + k
+ * Boundaries (boundary-condition table of Section 3.2 mapped onto the box):
+ *   z- inlet, z+ outlet, x-/x+/y-/y+ outer wall; bc_mode selects natural or
+ *   forced convection, or an all-open far field.
+ *
+ * Memory ownership: the library never allocates device memory.  All device
+ * state lives in one caller-owned workspace of ds_workspace_bytes() bytes
+ * that must stay allocated and untouched while the handle uses it.  Field
+ * arrays passed to set/get are copied (device to device) on the given
+ * stream.  The library owns only the host handle (and a small pinned host
+ * buffer for scalars).
+ *
+ * Streams: every call enqueues work on `stream` (a hipStream_t; NULL means
+ * the null stream).  Calls that return host scalars synchronise that stream.
+ *
+ * Errors: every call returns a ds_status; ds_last_error() gives a message.
+ * No call throws.  A handle is not thread-safe.
+ */
+#ifndef DSVOF_H
+#define DSVOF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ds_grid ds_grid;
+
+typedef enum ds_status {
+  DS_OK = 0,
+  DS_ERR_ARG = -1,            /* invalid argument (nothing was changed)          */
+  DS_ERR_HIP = -2,            /* a HIP runtime call failed                        */
+  DS_ERR_NOT_CONVERGED = -3,  /* a linear solve hit maxit; the state advanced with
+                                 the last iterate; see ds_get_diagnostics()        */
+  DS_ERR_NONFINITE = -4,      /* a non-finite value appeared; state unspecified,
+                                 restore it with ds_set_fields()                   */
+  DS_ERR_STATE = -5           /* call out of order (e.g. step before set_fields)  */
+} ds_status;
+
+enum { DS_EQ_IDEAL = 0, DS_EQ_PENG_ROBINSON = 1 };
+enum { DS_BC_NATURAL = 0, DS_BC_FORCED = 1, DS_BC_FARFIELD = 2 };
+enum { DS_PREC_FP64 = 0, DS_PREC_MIXED = 1 };
+
+/* Physical and numerical parameters, SI units.  Property values are constant
+ * (the mixing rule of Section 2.7, eq. 31, blends liquid and gas values). */
+typedef struct ds_params {
+  double h;            /* grid spacing [m] */
+  double dt;           /* time step [s] */
+  double p;            /* thermodynamic pressure [Pa] */
+  double T_amb;        /* ambient gas temperature [K] (boundary value) */
+  double rho_L, cp_L, k_L;   /* liquid density, heat capacity, conductivity */
+  double cp_G, k_G;          /* gas heat capacity, conductivity */
+  double D_v;          /* vapour diffusivity in the gas [m^2/s] */
+  double dh_ev;        /* latent heat [J/kg] (energy sink and Clausius-Clapeyron) */
+  double M_v, M_G;     /* molar masses of fuel and ambient gas [kg/mol] */
+  double g[3];         /* gravity [m/s^2] */
+  double xi0;          /* centripetal potential intensity [m^2/s^2] (eq. 29) */
+  double Df;           /* fiber length scale in eq. 29 [m] */
+  double r_fib;        /* radius below which the potential is held constant [m] */
+  double w_in;         /* forced inflow velocity at z- [m/s] */
+  double x0[3];        /* droplet / fiber centre; origin of g.r [m] */
+  double Tc, Pc, acentric;         /* fuel critical data (Peng-Robinson) */
+  double Tc_G, Pc_G, acentric_G;   /* ambient gas critical data */
+  double kij;          /* binary interaction coefficient */
+  double T_ref, p_ref; /* Clausius-Clapeyron reference point */
+  double eps_int;      /* interface-cell threshold on alpha */
+  double theta_min;    /* lower bound of the gas fraction in the species system */
+  double tol;          /* relative residual tolerance of the linear solves */
+  int s_max;           /* longest interface-normal march, in cell lengths */
+  int maxit;           /* iteration cap of each linear solve */
+  int eq_model;        /* DS_EQ_* */
+  int bc_mode;         /* DS_BC_* */
+  int precision;       /* DS_PREC_*: FP64 solves, or FP32 sweeps + FP64 refinement */
+  int solve_energy;    /* 0: temperature frozen (isothermal runs) */
+  int evaporation;     /* 0: no evaporation source */
+  int reserved;
+} ds_params;
+
+/* Scalars of the most recent step (or evaporation/pressure call). */
+typedef struct ds_diagnostics {
+  double K;              /* redistribution constant of eq. 20 */
+  double mdot_total;     /* h^3 sum(mdot) [kg/s] */
+  double volume;         /* h^3 sum(alpha) [m^3] */
+  double fuel_mass;      /* h^3 sum(rho_L alpha + c) after the step [kg] */
+  double fuel_mass_before;
+  double B_L, B_v;       /* liquid / vapour mass that left the box during the step [kg] */
+  double alpha_min, alpha_max;
+  double res_T, res_omega, res_p;   /* final relative residuals */
+  double rho_G;          /* gas density used (eq. 24) */
+  int iters_T, iters_omega, iters_p;
+  int n_interface;       /* interface cells with a nonzero gradient */
+  int converged;         /* 1 if every solve met tol */
+  int refinements_p;     /* outer FP64 refinement rounds of the pressure solve */
+} ds_diagnostics;
+
+/* Validate parameters and create a host handle for an nx*ny*nz grid
+ * (each >= 2).  Host only.  Returns DS_ERR_ARG for invalid input. */
+int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out);
+
+/* Release the host handle.  The workspace is the caller's. */
+int ds_destroy_grid(ds_grid* g);
+
+/* Bytes of device workspace the handle needs (256-byte aligned base). */
+size_t ds_workspace_bytes(const ds_grid* g);
+
+/* Bind the workspace and load the state (Section 3.3: the caller builds the
+ * initial fields).  alpha, T, omega, p: cell arrays; u, v, w: face arrays.
+ * omega is the vapour mass fraction in the gas.  All pointers device,
+ * read-only here. */
+int ds_set_fields(ds_grid* g, const double* alpha, const double* T, const double* omega,
+                  const double* u, const double* v, const double* w, const double* p,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* Copy the state out (device pointers; any may be NULL to skip). */
+int ds_get_fields(ds_grid* g, double* alpha, double* T, double* omega, double* u,
+                  double* v, double* w, double* p, void* stream);
+
+/* Advance nsteps time steps (Section 3.1).  Synchronises the stream once per
+ * linear solve batch to test convergence.  Diagnostics refer to the last step. */
+int ds_step(ds_grid* g, int nsteps, void* stream);
+
+/* On the current state, without advancing alpha, T or omega: evaporation
+ * source (Section 2.4), momentum predictor with gravity and f_m (eq. 30),
+ * pressure solve (eq. 7) and velocity correction; p and u, v, w are updated. */
+int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res);
+
+/* Evaporation rate of the current state, eqs. 17-21: total h^3 sum(mdot)
+ * in kg/s, and optionally the volumetric source mdot (kg m^-3 s^-1) written
+ * to a caller device cell array (NULL to skip). */
+int ds_evaporation_rate(ds_grid* g, double* kg_per_s, double* mdot_or_null, void* stream);
+
+/* Liquid volume h^3 sum(alpha) of the current state [m^3]. */
+int ds_droplet_volume(ds_grid* g, double* m3, void* stream);
+
+/* Diagnostics of the last step / solve (host struct, no device work). */
+int ds_get_diagnostics(const ds_grid* g, ds_diagnostics* out);
+
+/* Internal fields of the last step, for parity tests: copies one array into
+ * a caller device buffer of the stated size. */
+enum {
+  DS_FIELD_MDOT_RAW = 0,   /* cells: mdot before redistribution (eq. 17)     */
+  DS_FIELD_MDOT = 1,       /* cells: mdot after redistribution (eq. 19)      */
+  DS_FIELD_ALPHA1 = 2,     /* cells: alpha after the liquid source (eq. 4)   */
+  DS_FIELD_C = 3,          /* cells: vapour partial density rho_G theta omega */
+  DS_FIELD_USTAR = 4,      /* u faces of the momentum predictor              */
+  DS_FIELD_VSTAR = 5,
+  DS_FIELD_WSTAR = 6,
+  DS_FIELD_ADJ = 7         /* cells: flat index of adj (as double), -1 if none,
+                              -2 off the interface                          */
+};
+int ds_get_internal(ds_grid* g, int which, double* dst, size_t count, void* stream);
+
+/* Message describing the last error on this handle ("" if none). */
+const char* ds_last_error(const ds_grid* g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSVOF_H */

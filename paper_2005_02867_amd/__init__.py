@@ -1,0 +1,244 @@
+"""MI355X (gfx950) VOF droplet-evaporation step: Python binding of libdsvof.
+
+The binding marshals arguments only: every step of the method runs in the
+HIP kernels of ``libdsvof.so`` (built in-tree by ``build.py``).  PyTorch
+supplies device memory (the caller-owned workspace and field tensors) and the
+current HIP stream.  Importing this module without the built library raises.
+
+Functions mirror the C ABI in ``include/dsvof.h`` (without the ``ds_``
+prefix); ``Grid`` bundles a handle with its workspace.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsvof.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2005_02867_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+DS_OK, DS_ERR_ARG, DS_ERR_HIP, DS_ERR_NOT_CONVERGED, DS_ERR_NONFINITE, DS_ERR_STATE = 0, -1, -2, -3, -4, -5
+FIELD_MDOT_RAW, FIELD_MDOT, FIELD_ALPHA1, FIELD_C, FIELD_USTAR, FIELD_VSTAR, FIELD_WSTAR, FIELD_ADJ = range(8)
+EXPORTS = ("ds_create_grid", "ds_destroy_grid", "ds_workspace_bytes", "ds_set_fields", "ds_get_fields",
+           "ds_step", "ds_solve_pressure", "ds_evaporation_rate", "ds_droplet_volume", "ds_get_diagnostics",
+           "ds_get_internal", "ds_last_error")
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("h", C.c_double), ("dt", C.c_double), ("p", C.c_double), ("T_amb", C.c_double),
+        ("rho_L", C.c_double), ("cp_L", C.c_double), ("k_L", C.c_double),
+        ("cp_G", C.c_double), ("k_G", C.c_double), ("D_v", C.c_double), ("dh_ev", C.c_double),
+        ("M_v", C.c_double), ("M_G", C.c_double), ("g", C.c_double * 3),
+        ("xi0", C.c_double), ("Df", C.c_double), ("r_fib", C.c_double), ("w_in", C.c_double),
+        ("x0", C.c_double * 3),
+        ("Tc", C.c_double), ("Pc", C.c_double), ("acentric", C.c_double),
+        ("Tc_G", C.c_double), ("Pc_G", C.c_double), ("acentric_G", C.c_double), ("kij", C.c_double),
+        ("T_ref", C.c_double), ("p_ref", C.c_double), ("eps_int", C.c_double), ("theta_min", C.c_double),
+        ("tol", C.c_double),
+        ("s_max", C.c_int), ("maxit", C.c_int), ("eq_model", C.c_int), ("bc_mode", C.c_int),
+        ("precision", C.c_int), ("solve_energy", C.c_int), ("evaporation", C.c_int), ("reserved", C.c_int),
+    ]
+
+
+class Diagnostics(C.Structure):
+    _fields_ = [
+        ("K", C.c_double), ("mdot_total", C.c_double), ("volume", C.c_double), ("fuel_mass", C.c_double),
+        ("fuel_mass_before", C.c_double), ("B_L", C.c_double), ("B_v", C.c_double),
+        ("alpha_min", C.c_double), ("alpha_max", C.c_double),
+        ("res_T", C.c_double), ("res_omega", C.c_double), ("res_p", C.c_double), ("rho_G", C.c_double),
+        ("iters_T", C.c_int), ("iters_omega", C.c_int), ("iters_p", C.c_int),
+        ("n_interface", C.c_int), ("converged", C.c_int), ("refinements_p", C.c_int),
+    ]
+
+
+_P = C.c_void_p
+_lib.ds_create_grid.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(Params), C.POINTER(_P)]
+_lib.ds_destroy_grid.argtypes = [_P]
+_lib.ds_workspace_bytes.argtypes = [_P]
+_lib.ds_workspace_bytes.restype = C.c_size_t
+_lib.ds_set_fields.argtypes = [_P] + [_P] * 7 + [_P, C.c_size_t, _P]
+_lib.ds_get_fields.argtypes = [_P] + [_P] * 7 + [_P]
+_lib.ds_step.argtypes = [_P, C.c_int, _P]
+_lib.ds_solve_pressure.argtypes = [_P, _P, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+_lib.ds_evaporation_rate.argtypes = [_P, C.POINTER(C.c_double), _P, _P]
+_lib.ds_droplet_volume.argtypes = [_P, C.POINTER(C.c_double), _P]
+_lib.ds_get_diagnostics.argtypes = [_P, C.POINTER(Diagnostics)]
+_lib.ds_get_internal.argtypes = [_P, C.c_int, _P, C.c_size_t, _P]
+_lib.ds_last_error.argtypes = [_P]
+_lib.ds_last_error.restype = C.c_char_p
+
+
+class DSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dsvof error {code}: {msg}")
+        self.code = code
+
+
+class NotConverged(DSError):
+    pass
+
+
+def _check(handle, code):
+    if code == DS_OK:
+        return
+    msg = _lib.ds_last_error(handle).decode() if handle else ""
+    raise (NotConverged if code == DS_ERR_NOT_CONVERGED else DSError)(code, msg)
+
+
+def make_params(prm: dict) -> Params:
+    P = Params()
+    for name, ctype in Params._fields_:
+        if name == "reserved":
+            continue
+        val = prm[name]
+        if name in ("g", "x0"):
+            setattr(P, name, (C.c_double * 3)(*[float(x) for x in val]))
+        else:
+            setattr(P, name, int(val) if ctype is C.c_int else float(val))
+    return P
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("fields must be contiguous float64 CUDA tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------ C-ABI mirrors
+def create_grid(nx, ny, nz, prm: dict):
+    h = _P()
+    P = make_params(prm)
+    code = _lib.ds_create_grid(int(nx), int(ny), int(nz), C.byref(P), C.byref(h))
+    if code != DS_OK:
+        raise DSError(code, "ds_create_grid rejected the parameters")
+    return h
+
+
+def destroy_grid(h):
+    _check(None, _lib.ds_destroy_grid(h))
+
+
+def workspace_bytes(h) -> int:
+    return int(_lib.ds_workspace_bytes(h))
+
+
+def set_fields(h, alpha, T, omega, u, v, w, p, workspace):
+    _check(h, _lib.ds_set_fields(h, _dptr(alpha), _dptr(T), _dptr(omega), _dptr(u), _dptr(v), _dptr(w),
+                                 _dptr(p), C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream()))
+
+
+def get_fields(h, alpha=None, T=None, omega=None, u=None, v=None, w=None, p=None):
+    _check(h, _lib.ds_get_fields(h, _dptr(alpha), _dptr(T), _dptr(omega), _dptr(u), _dptr(v), _dptr(w),
+                                 _dptr(p), _stream()))
+
+
+def step(h, nsteps=1):
+    _check(h, _lib.ds_step(h, int(nsteps), _stream()))
+
+
+def solve_pressure(h):
+    it = C.c_int()
+    res = C.c_double()
+    _check(h, _lib.ds_solve_pressure(h, _stream(), C.byref(it), C.byref(res)))
+    return it.value, res.value
+
+
+def evaporation_rate(h, mdot_out=None):
+    v = C.c_double()
+    _check(h, _lib.ds_evaporation_rate(h, C.byref(v), _dptr(mdot_out), _stream()))
+    return v.value
+
+
+def droplet_volume(h):
+    v = C.c_double()
+    _check(h, _lib.ds_droplet_volume(h, C.byref(v), _stream()))
+    return v.value
+
+
+def get_diagnostics(h) -> dict:
+    d = Diagnostics()
+    _check(h, _lib.ds_get_diagnostics(h, C.byref(d)))
+    return {name: getattr(d, name) for name, _ in Diagnostics._fields_}
+
+
+def get_internal(h, which, out):
+    _check(h, _lib.ds_get_internal(h, int(which), _dptr(out), out.numel(), _stream()))
+
+
+# ------------------------------------------------------------ convenience
+class Grid:
+    """A handle plus its torch-allocated workspace on the current CUDA device."""
+
+    def __init__(self, prm: dict, device="cuda"):
+        self.prm = dict(prm)
+        self.nx, self.ny, self.nz = int(prm["nx"]), int(prm["ny"]), int(prm["nz"])
+        self.device = torch.device(device)
+        self.h = create_grid(self.nx, self.ny, self.nz, prm)
+        nbytes = workspace_bytes(self.h)
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self.workspace = raw[off:off + nbytes]
+        self._raw = raw
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            _lib.ds_destroy_grid(h)
+            self.h = None
+
+    def shapes(self):
+        nx, ny, nz = self.nx, self.ny, self.nz
+        return dict(alpha=(nx, ny, nz), T=(nx, ny, nz), omega=(nx, ny, nz), p=(nx, ny, nz),
+                    u=(nx + 1, ny, nz), v=(nx, ny + 1, nz), w=(nx, ny, nz + 1))
+
+    def set_fields(self, fields: dict):
+        t = {}
+        for k, shp in self.shapes().items():
+            x = torch.as_tensor(fields[k], dtype=torch.float64).to(self.device).contiguous()
+            if tuple(x.shape) != shp:
+                raise ValueError(f"{k}: shape {tuple(x.shape)} != {shp}")
+            t[k] = x
+        set_fields(self.h, t["alpha"], t["T"], t["omega"], t["u"], t["v"], t["w"], t["p"], self.workspace)
+        torch.cuda.current_stream().synchronize()
+
+    def get_fields(self) -> dict:
+        out = {k: torch.empty(s, dtype=torch.float64, device=self.device) for k, s in self.shapes().items()}
+        get_fields(self.h, **out)
+        return out
+
+    def step(self, nsteps=1):
+        step(self.h, nsteps)
+
+    def solve_pressure(self):
+        return solve_pressure(self.h)
+
+    def evaporation_rate(self, return_field=False):
+        if return_field:
+            m = torch.empty((self.nx, self.ny, self.nz), dtype=torch.float64, device=self.device)
+            return evaporation_rate(self.h, m), m
+        return evaporation_rate(self.h)
+
+    def droplet_volume(self):
+        return droplet_volume(self.h)
+
+    def diagnostics(self):
+        return get_diagnostics(self.h)
+
+    def internal(self, which):
+        s = self.shapes()
+        shp = {FIELD_USTAR: s["u"], FIELD_VSTAR: s["v"], FIELD_WSTAR: s["w"]}.get(which, s["alpha"])
+        out = torch.empty(shp, dtype=torch.float64, device=self.device)
+        get_internal(self.h, which, out)
+        return out

@@ -1,0 +1,626 @@
+// Step kernels of the VOF droplet-evaporation method (arXiv 2005.02867,
+// Sections 2-3), FP64.  One thread per cell (or face), z fastest, each block
+// streaming one contiguous range (XCD-aware order, see block_range).
+#include <hip/hip_runtime.h>
+
+#include "ds_device.h"
+#include "ds_kernels.h"
+#include "ds_thermo.h"
+
+namespace dsv {
+
+int grid_blocks(long long n) {
+  long long nb = (n + BLOCK - 1) / BLOCK;
+  if (nb > MAX_BLOCKS) nb = MAX_BLOCKS;
+  nb = (nb + NXCD - 1) / NXCD * NXCD;
+  return (int)nb;
+}
+
+// ---------------------------------------------------------------- potential
+// xi = xi0 (Df/2) / max(r, r_fib) at cell centres (eq. 29), centre x0.
+__global__ void k_xi(DevParams P, double* xi) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+    int i, j, k;
+    decode(P, c, i, j, k);
+    const double x = (i + 0.5) * P.h - P.x0[0], y = (j + 0.5) * P.h - P.x0[1], z = (k + 0.5) * P.h - P.x0[2];
+    const double r = sqrt(x * x + y * y + z * z);
+    xi[c] = P.xi0 * (0.5 * P.Df) / fmax(r, P.r_fib);
+  }
+}
+
+// ---------------------------------------------------------------- S1-S3
+// Interface cells (eps < alpha < 1-eps): central-difference gradient with a
+// zero ghost outside the box, outward normal n = -grad/|grad|, march along n
+// to the first gas cell (adj), evaporation flux at adj (eqs. 12-14) times
+// |grad alpha| (eq. 17).  The march arithmetic is written with explicitly
+// rounded operations so that each product and sum rounds on its own.
+__device__ __forceinline__ double alpha_or0(const DevParams& P, const double* a, int i, int j, int k) {
+  if (i < 0 || j < 0 || k < 0 || i >= P.nx || j >= P.ny || k >= P.nz) return 0.0;
+  return a[cidx(P, i, j, k)];
+}
+
+__global__ void k_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
+                            const double* __restrict__ omega, const double* __restrict__ u,
+                            const double* __restrict__ v, const double* __restrict__ w,
+                            double* __restrict__ mraw, int* __restrict__ adj, double* partials,
+                            unsigned* counter, double* scal) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+    const double a = alpha[c];
+    double m = 0.0;
+    int hit = -2;
+    if (a > P.eps && a < 1.0 - P.eps) {
+      int i, j, k;
+      decode(P, c, i, j, k);
+      const double dx = __dsub_rn(alpha_or0(P, alpha, i + 1, j, k), alpha_or0(P, alpha, i - 1, j, k));
+      const double dy = __dsub_rn(alpha_or0(P, alpha, i, j + 1, k), alpha_or0(P, alpha, i, j - 1, k));
+      const double dz = __dsub_rn(alpha_or0(P, alpha, i, j, k + 1), alpha_or0(P, alpha, i, j, k - 1));
+      const double nrm =
+          __dsqrt_rn(__dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz)));
+      hit = -1;
+      if (nrm > 0.0) {
+        acc[2] += 1.0;
+        const double nx = __ddiv_rn(-dx, nrm), ny = __ddiv_rn(-dy, nrm), nz = __ddiv_rn(-dz, nrm);
+        const double bi = i + 0.5, bj = j + 0.5, bk = k + 0.5;
+        int ti = 0, tj = 0, tk = 0;
+        for (int s = 1; s <= P.smax; ++s) {
+          const double sd = (double)s;
+          ti = (int)floor(__dadd_rn(bi, __dmul_rn(sd, nx)));
+          tj = (int)floor(__dadd_rn(bj, __dmul_rn(sd, ny)));
+          tk = (int)floor(__dadd_rn(bk, __dmul_rn(sd, nz)));
+          if (ti < 0 || tj < 0 || tk < 0 || ti >= P.nx || tj >= P.ny || tk >= P.nz) break;
+          if (alpha[cidx(P, ti, tj, tk)] <= P.eps) {
+            hit = (int)cidx(P, ti, tj, tk);
+            break;
+          }
+        }
+        if (hit >= 0) {
+          const double di = ti - i, dj = tj - j, dk = tk - k;
+          const double d = P.h * sqrt(di * di + dj * dj + dk * dk);
+          const double wsat = mass_fraction(P, equilibrium_y(P, T[c]));
+          const double wa = omega[hit];
+          const double va = 0.5 * (u[uidx(P, ti, tj, tk)] + u[uidx(P, ti + 1, tj, tk)]) * nx +
+                            0.5 * (v[vidx(P, ti, tj, tk)] + v[vidx(P, ti, tj + 1, tk)]) * ny +
+                            0.5 * (w[widx(P, ti, tj, tk)] + w[widx(P, ti, tj, tk + 1)]) * nz;
+          const double jn = P.rho_G * P.D * (wsat - wa) / d + P.rho_G * wa * va;
+          m = jn * (nrm / (2.0 * P.h));
+        }
+      }
+      const double f = sqrt(fmax(a * (1.0 - a), 0.0));
+      acc[0] += m;
+      acc[1] += f * m;
+    }
+    mraw[c] = m;
+    adj[c] = hit;
+  }
+  const int ops[3] = {RSUM, RSUM, RSUM};
+  if (block_reduce_publish<3>(acc, ops, partials, counter)) {
+    double tot[3];
+    block_combine<3>(ops, partials, counter, tot);
+    if (threadIdx.x == 0) {
+      scal[SC_S1] = tot[0];
+      scal[SC_S2] = tot[1];
+      scal[SC_NINT] = tot[2];
+      scal[SC_K] = tot[1] != 0.0 ? tot[0] / tot[1] : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- S4 + eq. 4
+// mdot = K f(alpha) mdot_raw (eqs. 19-21), alpha1 = alpha - dt mdot / rho_L.
+__global__ void k_source(DevParams P, const double* __restrict__ alpha, const double* __restrict__ mraw,
+                         const double* __restrict__ scal, double* __restrict__ mdot,
+                         double* __restrict__ a1) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  const double K = scal[SC_K];
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+    const double a = alpha[c];
+    const double f = sqrt(fmax(a * (1.0 - a), 0.0));
+    const double m = K * f * mraw[c];
+    mdot[c] = m;
+    a1[c] = a - P.dt * m / P.rho_L;
+  }
+}
+
+// ---------------------------------------------------------------- S5
+// TVD (van Leer) face value along one grid line: face f lies between cells
+// f-1 and f; `line` points at cell 0 of the line, `st` is the stride.
+__device__ __forceinline__ double face_value(const double* __restrict__ phi, long long line, long long st,
+                                             int f, int na, double uf, double amb) {
+  if (f == 0) return uf > 0.0 ? amb : phi[line];
+  if (f == na) return uf < 0.0 ? amb : phi[line + (long long)(na - 1) * st];
+  if (uf == 0.0) return 0.0;
+  double C, D, U;
+  if (uf > 0.0) {
+    C = phi[line + (long long)(f - 1) * st];
+    D = phi[line + (long long)f * st];
+    U = (f >= 2) ? phi[line + (long long)(f - 2) * st] : C;
+  } else {
+    C = phi[line + (long long)f * st];
+    D = phi[line + (long long)(f - 1) * st];
+    U = (f + 1 <= na - 1) ? phi[line + (long long)(f + 1) * st] : C;
+  }
+  const double den = D - C;
+  if (den == 0.0) return C;
+  const double r = (C - U) / den;
+  const double ar = fabs(r);
+  const double psi = (r + ar) / (1.0 + ar);
+  return C + 0.5 * psi * den;
+}
+
+__global__ void k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
+                         const double* __restrict__ T, const double* __restrict__ c,
+                         const double* __restrict__ u, const double* __restrict__ v,
+                         const double* __restrict__ w, double* __restrict__ a_new,
+                         double* __restrict__ c_new, double* __restrict__ T_new, double* partials,
+                         unsigned* counter, double* scal) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  double acc[2] = {0.0, 0.0};   // outward liquid volume flux, vapour mass flux (per area)
+  for (long long cc = b0 + threadIdx.x; cc < b1; cc += BLOCK) {
+    int i, j, k;
+    decode(P, cc, i, j, k);
+    const int pos[3] = {i, j, k};
+    const int nn[3] = {P.nx, P.ny, P.nz};
+    const long long st[3] = {(long long)P.ny * P.nz, (long long)P.nz, 1};
+    const long long line[3] = {cc - (long long)i * st[0], cc - (long long)j * st[1], cc - (long long)k};
+    const double uf[3][2] = {{u[uidx(P, i, j, k)], u[uidx(P, i + 1, j, k)]},
+                             {v[vidx(P, i, j, k)], v[vidx(P, i, j + 1, k)]},
+                             {w[widx(P, i, j, k)], w[widx(P, i, j, k + 1)]}};
+    const double Tc = T[cc];
+    double da = 0.0, dc = 0.0, dT = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      double F[2], G[2], H[2];
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const int f = pos[ax] + sd;
+        const double ufv = uf[ax][sd];
+        const double af = face_value(a1, line[ax], st[ax], f, nn[ax], ufv, 0.0);
+        const double of = face_value(omega, line[ax], st[ax], f, nn[ax], ufv, 0.0);
+        F[sd] = ufv * af;
+        G[sd] = P.rho_G * of * (1.0 - af) * ufv;
+        if (P.solve_energy) {
+          const double Tf = face_value(T, line[ax], st[ax], f, nn[ax], ufv, P.T_amb);
+          H[sd] = ufv * (Tf - Tc);
+        } else {
+          H[sd] = 0.0;
+        }
+      }
+      da += F[1] - F[0];
+      dc += G[1] - G[0];
+      dT += H[1] - H[0];
+      if (pos[ax] == 0) {
+        acc[0] -= F[0];
+        acc[1] -= G[0];
+      }
+      if (pos[ax] == nn[ax] - 1) {
+        acc[0] += F[1];
+        acc[1] += G[1];
+      }
+    }
+    const double s = P.dt / P.h;
+    a_new[cc] = a1[cc] - s * da;
+    c_new[cc] = c[cc] - s * dc;
+    T_new[cc] = P.solve_energy ? Tc - s * dT : Tc;
+  }
+  const int ops[2] = {RSUM, RSUM};
+  if (block_reduce_publish<2>(acc, ops, partials, counter)) {
+    double tot[2];
+    block_combine<2>(ops, partials, counter, tot);
+    if (threadIdx.x == 0) {
+      const double area_dt = P.h * P.h * P.dt;
+      scal[SC_BL] = P.rho_L * area_dt * tot[0];
+      scal[SC_BV_ADV] = area_dt * tot[1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- S6-S8
+// Boundary face velocity of cell (i,j,k) on box face (ax, side).
+__device__ __forceinline__ double bface_u(const DevParams& P, const double* u, const double* v,
+                                          const double* w, int ax, int side, int i, int j, int k) {
+  if (ax == 0) return u[uidx(P, side ? i + 1 : i, j, k)];
+  if (ax == 1) return v[vidx(P, i, side ? j + 1 : j, k)];
+  return w[widx(P, i, j, side ? k + 1 : k)];
+}
+
+// Neighbour of (i,j,k) across face (ax, side); returns -1 outside the box.
+__device__ __forceinline__ long long nbr(const DevParams& P, int ax, int side, int i, int j, int k) {
+  const int d = side ? 1 : -1;
+  if (ax == 0) {
+    const int ii = i + d;
+    return (ii < 0 || ii >= P.nx) ? -1 : cidx(P, ii, j, k);
+  }
+  if (ax == 1) {
+    const int jj = j + d;
+    return (jj < 0 || jj >= P.ny) ? -1 : cidx(P, i, jj, k);
+  }
+  const int kk = k + d;
+  return (kk < 0 || kk >= P.nz) ? -1 : cidx(P, i, j, kk);
+}
+
+// Energy, eq. 8 after the advection: (rho cp/dt) T - div(k grad T) = (rho cp/dt) T' - mdot dh.
+__global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ Tp,
+                               const double* __restrict__ mdot, const double* __restrict__ u,
+                               const double* __restrict__ v, const double* __restrict__ w,
+                               double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  const double ih2 = 1.0 / (P.h * P.h);
+  const double Kb = 2.0 * P.k_G * ih2;
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+    int i, j, k;
+    decode(P, c, i, j, k);
+    const double ab = clamp01(a_new[c]);
+    const double rho = mix(ab, P.rho_L, P.rho_G), cp = mix(ab, P.cp_L, P.cp_G), kc = mix(ab, P.k_L, P.k_G);
+    const double m = rho * cp / P.dt;
+    double d = m, rhs = m * Tp[c] - mdot[c] * P.dh;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const long long nb = nbr(P, ax, sd, i, j, k);
+        if (nb >= 0) {
+          const double kn = mix(clamp01(a_new[nb]), P.k_L, P.k_G);
+          d += ih2 * 0.5 * (kc + kn);
+        } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
+          d += Kb;
+          rhs += Kb * P.T_amb;
+        }
+      }
+    qc[c] = kc;
+    diag[c] = d;
+    b[c] = rhs;
+  }
+}
+
+// Species, eq. 9 for c = rho_G theta omega: (rho_G theta/dt) w - div(rho_G D theta grad w) = c'/dt + mdot.
+__global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
+                                const double* __restrict__ mdot, const double* __restrict__ u,
+                                const double* __restrict__ v, const double* __restrict__ w,
+                                double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b,
+                                double* __restrict__ om0) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  const double sc = P.rho_G * P.D / (P.h * P.h);
+  const double Kb = 2.0 * sc;
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+    int i, j, k;
+    decode(P, c, i, j, k);
+    const double th = fmax(1.0 - clamp01(a_new[c]), P.theta_min);
+    double d = P.rho_G * th / P.dt;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const long long nb = nbr(P, ax, sd, i, j, k);
+        if (nb >= 0) {
+          const double tn = fmax(1.0 - clamp01(a_new[nb]), P.theta_min);
+          d += sc * 0.5 * (th + tn);
+        } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
+          d += Kb;
+        }
+      }
+    qc[c] = th;
+    diag[c] = d;
+    b[c] = cp_[c] / P.dt + mdot[c];
+    om0[c] = cp_[c] / (P.rho_G * th);
+  }
+}
+
+// Flux-form vapour update after the implicit solve; diffusive boundary outflow tally.
+__global__ void k_species_update(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
+                                 const double* __restrict__ mdot, const double* __restrict__ om,
+                                 const double* __restrict__ u, const double* __restrict__ v,
+                                 const double* __restrict__ w, double* __restrict__ cout,
+                                 double* __restrict__ omega, double* partials, unsigned* counter,
+                                 double* scal) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  const double sc = P.rho_G * P.D / (P.h * P.h);
+  const double Kb = 2.0 * sc;
+  double acc[1] = {0.0};
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+    int i, j, k;
+    decode(P, c, i, j, k);
+    const double th = fmax(1.0 - clamp01(a_new[c]), P.theta_min);
+    const double oc = om[c];
+    double face = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const long long nb = nbr(P, ax, sd, i, j, k);
+        if (nb >= 0) {
+          const double tn = fmax(1.0 - clamp01(a_new[nb]), P.theta_min);
+          face += sc * 0.5 * (th + tn) * (oc - om[nb]);
+        } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
+          face += Kb * oc;
+          acc[0] += Kb * oc;
+        }
+      }
+    const double cn = cp_[c] + P.dt * mdot[c] - P.dt * face;
+    cout[c] = cn;
+    omega[c] = cn / (P.rho_G * th);
+  }
+  const int ops[1] = {RSUM};
+  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+    double tot[1];
+    block_combine<1>(ops, partials, counter, tot);
+    if (threadIdx.x == 0) scal[SC_BV_DIFF] = P.dt * P.h * P.h * P.h * tot[0];
+  }
+}
+
+// ---------------------------------------------------------------- S9
+// Predictor on the faces normal to axis AX (eq. 30 / rho, mu = 0).
+template <int AX>
+__global__ void k_predictor(DevParams P, const double* __restrict__ a_new, const double* __restrict__ xi,
+                            const double* __restrict__ u, const double* __restrict__ v,
+                            const double* __restrict__ w, double* __restrict__ out) {
+  const int fx = P.nx + (AX == 0), fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
+  const long long nf = (long long)fx * fy * fz;
+  long long b0, b1;
+  block_range(nf, b0, b1);
+  const double* F = AX == 0 ? u : (AX == 1 ? v : w);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+    const int k = (int)(e % fz);
+    const long long t = e / fz;
+    const int j = (int)(t % fy);
+    const int i = (int)(t / fy);
+    const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
+    const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
+    const double uc = F[e];
+    if (fpos == 0 || fpos == nax) {
+      const int kind = P.kind[AX * 2 + (fpos == 0 ? 0 : 1)];
+      out[e] = kind == WALL ? 0.0 : (kind == INLET ? P.w_in : uc);
+      continue;
+    }
+    // strides of the face array
+    const long long sx = (long long)fy * fz, sy = fz, sz = 1;
+    const long long sA = AX == 0 ? sx : (AX == 1 ? sy : sz);
+    // normal advection, first-order upwind
+    const double back = (uc - F[e - sA]) / P.h, fwd = (F[e + sA] - uc) / P.h;
+    double adv = uc * (uc > 0.0 ? back : fwd);
+    // cells on both sides of the face
+    const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
+    // transverse advection: 4-point averaged transverse velocity, zero-gradient ghosts
+#pragma unroll
+    for (int bx = 0; bx < 3; ++bx) {
+      if (bx == AX) continue;
+      double vb;
+      if (bx == 0) {   // u averaged onto the face
+        vb = 0.25 * (u[uidx(P, iL, jL, kL)] + u[uidx(P, iL + 1, jL, kL)] + u[uidx(P, i, j, k)] + u[uidx(P, i + 1, j, k)]);
+      } else if (bx == 1) {
+        vb = 0.25 * (v[vidx(P, iL, jL, kL)] + v[vidx(P, iL, jL + 1, kL)] + v[vidx(P, i, j, k)] + v[vidx(P, i, j + 1, k)]);
+      } else {
+        vb = 0.25 * (w[widx(P, iL, jL, kL)] + w[widx(P, iL, jL, kL + 1)] + w[widx(P, i, j, k)] + w[widx(P, i, j, k + 1)]);
+      }
+      const int pb = bx == 0 ? i : (bx == 1 ? j : k);
+      const int nb_ = bx == 0 ? fx : (bx == 1 ? fy : fz);
+      const long long sb = bx == 0 ? sx : (bx == 1 ? sy : sz);
+      const double lo = pb >= 1 ? F[e - sb] : uc;
+      const double hi = pb <= nb_ - 2 ? F[e + sb] : uc;
+      const double d = vb > 0.0 ? (uc - lo) / P.h : (hi - uc) / P.h;
+      adv += vb * d;
+    }
+    const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
+    const double aL = clamp01(a_new[cL]), aR = clamp01(a_new[cR]);
+    const double rL = mix(aL, P.rho_L, P.rho_G), rR = mix(aR, P.rho_L, P.rho_G);
+    const double bf = 0.5 * (1.0 / rL + 1.0 / rR);
+    const double xf = (AX == 0 ? i : i + 0.5) * P.h - P.x0[0];
+    const double yf = (AX == 1 ? j : j + 0.5) * P.h - P.x0[1];
+    const double zf = (AX == 2 ? k : k + 0.5) * P.h - P.x0[2];
+    const double gr = P.g[0] * xf + P.g[1] * yf + P.g[2] * zf;
+    const double force = -gr * (rR - rL) / P.h * bf + 0.5 * (aL + aR) * (xi[cR] - xi[cL]) / P.h;
+    out[e] = uc - P.dt * adv + P.dt * force;
+  }
+}
+
+// ---------------------------------------------------------------- S10 setup
+// Pressure: sum_f (dt/h^2) (1/rho)_f (p_c - p_nb) = mdot (1/rho_G - 1/rho_L) - div u*.
+__global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ mdot,
+                                 const double* __restrict__ us, const double* __restrict__ vs,
+                                 const double* __restrict__ ws, double* __restrict__ qc,
+                                 double* __restrict__ diag, double* __restrict__ b) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  const double sc = P.dt / (P.h * P.h);
+  const double Ssc = 1.0 / P.rho_G - 1.0 / P.rho_L;
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+    int i, j, k;
+    decode(P, c, i, j, k);
+    const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, P.rho_G);
+    double d = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const long long nb = nbr(P, ax, sd, i, j, k);
+        if (nb >= 0) {
+          const double bn = 1.0 / mix(clamp01(a_new[nb]), P.rho_L, P.rho_G);
+          d += sc * 0.5 * (beta + bn);
+        } else if (pressure_dirichlet(P.kind[ax * 2 + sd])) {
+          d += 2.0 * sc * beta;
+        }
+      }
+    const double div = ((us[uidx(P, i + 1, j, k)] - us[uidx(P, i, j, k)]) +
+                        (vs[vidx(P, i, j + 1, k)] - vs[vidx(P, i, j, k)]) +
+                        (ws[widx(P, i, j, k + 1)] - ws[widx(P, i, j, k)])) / P.h;
+    qc[c] = beta;
+    diag[c] = d;
+    b[c] = mdot[c] * Ssc - div;
+  }
+}
+
+// ---------------------------------------------------------------- S11
+template <int AX>
+__global__ void k_project(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
+                          const double* __restrict__ Fs, double* __restrict__ F) {
+  const int fx = P.nx + (AX == 0), fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
+  const long long nf = (long long)fx * fy * fz;
+  long long b0, b1;
+  block_range(nf, b0, b1);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+    const int k = (int)(e % fz);
+    const long long t = e / fz;
+    const int j = (int)(t % fy);
+    const int i = (int)(t / fy);
+    const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
+    const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
+    const double us = Fs[e];
+    if (fpos == 0 || fpos == nax) {
+      const int side = fpos == 0 ? 0 : 1;
+      if (!pressure_dirichlet(P.kind[AX * 2 + side])) {
+        F[e] = us;
+      } else {
+        const int ic = AX == 0 ? (side ? i - 1 : i) : i;
+        const int jc = AX == 1 ? (side ? j - 1 : j) : j;
+        const int kc = AX == 2 ? (side ? k - 1 : k) : k;
+        const long long c = cidx(P, ic, jc, kc);
+        const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, P.rho_G);
+        F[e] = side ? us + 2.0 * P.dt * beta * p[c] / P.h : us - 2.0 * P.dt * beta * p[c] / P.h;
+      }
+      continue;
+    }
+    const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
+    const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
+    const double bL = 1.0 / mix(clamp01(a_new[cL]), P.rho_L, P.rho_G);
+    const double bR = 1.0 / mix(clamp01(a_new[cR]), P.rho_L, P.rho_G);
+    F[e] = us - P.dt * 0.5 * (bL + bR) * (p[cR] - p[cL]) / P.h;
+  }
+}
+
+// ---------------------------------------------------------------- S12
+__global__ void k_diagnostics(DevParams P, const double* __restrict__ alpha, const double* __restrict__ c,
+                              const double* __restrict__ T, const double* __restrict__ p,
+                              const double* __restrict__ mdot, double* partials, unsigned* counter,
+                              double* scal) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  double acc[6] = {0.0, 0.0, 0.0, __builtin_inf(), -__builtin_inf(), 0.0};
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+    const double a = alpha[e], cv = c[e];
+    acc[0] += a;
+    acc[1] += P.rho_L * a + cv;
+    acc[2] += mdot[e];
+    acc[3] = fmin(acc[3], a);
+    acc[4] = fmax(acc[4], a);
+    const double chk = a + cv + T[e] + p[e];
+    if (!isfinite(chk)) acc[5] += 1.0;
+  }
+  const int ops[6] = {RSUM, RSUM, RSUM, RMIN, RMAX, RSUM};
+  if (block_reduce_publish<6>(acc, ops, partials, counter)) {
+    double tot[6];
+    block_combine<6>(ops, partials, counter, tot);
+    if (threadIdx.x == 0) {
+      const double v = P.h * P.h * P.h;
+      scal[SC_VOL] = v * tot[0];
+      scal[SC_FUEL] = v * tot[1];
+      scal[SC_MDOT] = v * tot[2];
+      scal[SC_AMIN] = tot[3];
+      scal[SC_AMAX] = tot[4];
+      scal[SC_NONFINITE] = tot[5];
+    }
+  }
+}
+
+// c = rho_G theta omega with theta = max(1 - alpha, theta_min).
+__global__ void k_c_from_omega(DevParams P, const double* __restrict__ alpha, const double* __restrict__ omega,
+                               double* __restrict__ c) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK)
+    c[e] = P.rho_G * fmax(1.0 - clamp01(alpha[e]), P.theta_min) * omega[e];
+}
+
+__global__ void k_fill(double* x, double v, long long n) {
+  long long b0, b1;
+  block_range(n, b0, b1);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) x[e] = v;
+}
+__global__ void k_int_to_double(const int* s, double* d, long long n) {
+  long long b0, b1;
+  block_range(n, b0, b1);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) d[e] = (double)s[e];
+}
+
+// ---------------------------------------------------------------- launchers
+void launch_xi(const DevParams& P, double* xi, hipStream_t s) {
+  k_xi<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, xi);
+}
+void launch_interface(const DevParams& P, const double* alpha, const double* T, const double* omega,
+                      const double* u, const double* v, const double* w, double* mraw, int* adj,
+                      double* partials, unsigned* counter, double* scal, hipStream_t s) {
+  k_interface<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, alpha, T, omega, u, v, w, mraw, adj, partials, counter, scal);
+}
+void launch_source(const DevParams& P, const double* alpha, const double* mraw, const double* scal,
+                   double* mdot, double* a1, hipStream_t s) {
+  k_source<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, alpha, mraw, scal, mdot, a1);
+}
+void launch_advect(const DevParams& P, const double* a1, const double* omega, const double* T,
+                   const double* c, const double* u, const double* v, const double* w, double* a_new,
+                   double* c_new, double* T_new, double* partials, unsigned* counter, double* scal,
+                   hipStream_t s) {
+  k_advect<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a1, omega, T, c, u, v, w, a_new, c_new, T_new, partials, counter, scal);
+}
+void launch_energy_setup(const DevParams& P, const double* a_new, const double* T_prime,
+                         const double* mdot, const double* u, const double* v, const double* w,
+                         double* qc, double* diag, double* b, hipStream_t s) {
+  k_energy_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, T_prime, mdot, u, v, w, qc, diag, b);
+}
+void launch_species_setup(const DevParams& P, const double* a_new, const double* c_prime,
+                          const double* mdot, const double* u, const double* v, const double* w,
+                          double* qc, double* diag, double* b, double* om0, hipStream_t s) {
+  k_species_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, u, v, w, qc, diag, b, om0);
+}
+void launch_species_update(const DevParams& P, const double* a_new, const double* c_prime,
+                           const double* mdot, const double* om, const double* u, const double* v,
+                           const double* w, double* c, double* omega, double* partials,
+                           unsigned* counter, double* scal, hipStream_t s) {
+  k_species_update<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, om, u, v, w, c, omega, partials, counter, scal);
+}
+void launch_predictor(const DevParams& P, const double* a_new, const double* xi, const double* u,
+                      const double* v, const double* w, double* us, double* vs, double* ws,
+                      hipStream_t s) {
+  const long long nu = (long long)(P.nx + 1) * P.ny * P.nz, nv = (long long)P.nx * (P.ny + 1) * P.nz,
+                  nw = (long long)P.nx * P.ny * (P.nz + 1);
+  k_predictor<0><<<grid_blocks(nu), BLOCK, 0, s>>>(P, a_new, xi, u, v, w, us);
+  k_predictor<1><<<grid_blocks(nv), BLOCK, 0, s>>>(P, a_new, xi, u, v, w, vs);
+  k_predictor<2><<<grid_blocks(nw), BLOCK, 0, s>>>(P, a_new, xi, u, v, w, ws);
+}
+void launch_pressure_setup(const DevParams& P, const double* a_new, const double* mdot,
+                           const double* us, const double* vs, const double* ws, double* qc,
+                           double* diag, double* b, hipStream_t s) {
+  k_pressure_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, mdot, us, vs, ws, qc, diag, b);
+}
+void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
+                    const double* vs, const double* ws, double* u, double* v, double* w,
+                    hipStream_t s) {
+  const long long nu = (long long)(P.nx + 1) * P.ny * P.nz, nv = (long long)P.nx * (P.ny + 1) * P.nz,
+                  nw = (long long)P.nx * P.ny * (P.nz + 1);
+  k_project<0><<<grid_blocks(nu), BLOCK, 0, s>>>(P, a_new, p, us, u);
+  k_project<1><<<grid_blocks(nv), BLOCK, 0, s>>>(P, a_new, p, vs, v);
+  k_project<2><<<grid_blocks(nw), BLOCK, 0, s>>>(P, a_new, p, ws, w);
+}
+void launch_diagnostics(const DevParams& P, const double* alpha, const double* c, const double* T,
+                        const double* p, const double* mdot, double* partials, unsigned* counter,
+                        double* scal, hipStream_t s) {
+  k_diagnostics<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, alpha, c, T, p, mdot, partials, counter, scal);
+}
+void launch_c_from_omega(const DevParams& P, const double* alpha, const double* omega, double* c, hipStream_t s) {
+  k_c_from_omega<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, alpha, omega, c);
+}
+void launch_fill(double* x, double v, long long n, hipStream_t s) {
+  k_fill<<<grid_blocks(n), BLOCK, 0, s>>>(x, v, n);
+}
+void launch_int_to_double(const int* src, double* dst, long long n, hipStream_t s) {
+  k_int_to_double<<<grid_blocks(n), BLOCK, 0, s>>>(src, dst, n);
+}
+
+}  // namespace dsv

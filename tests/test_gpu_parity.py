@@ -1,0 +1,184 @@
+"""GPU (HIP, gfx950) vs CPU oracle, through the C ABI.
+
+FP64 path: every field after every step within 1e-9 relative (per-field
+2-norm, both sides solving to 1e-13); integer decisions (interface class,
+adj association) bit-exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import step as S
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("alpha", "T", "omega", "p", "u", "v", "w")
+TOL = 1e-9
+
+
+def _lib():
+    import paper_2005_02867_amd as ds
+    return ds
+
+
+def _rel(a, b):
+    a = torch.as_tensor(a, dtype=torch.float64).cpu()
+    b = torch.as_tensor(b, dtype=torch.float64).cpu()
+    nb = float(torch.linalg.vector_norm(b))
+    d = float(torch.linalg.vector_norm(a - b))
+    return d / nb if nb > 0 else d
+
+
+def _compare(g_fields, st, where, tol=TOL):
+    errs = {}
+    for k in FIELDS:
+        errs[k] = _rel(g_fields[k], st[k])
+    bad = {k: e for k, e in errs.items() if not e <= tol}
+    assert not bad, f"{where}: {bad} (all: {errs})"
+    return errs
+
+
+def _grid_params(name="C1", n=(17, 19, 23), L=None, **kw):
+    prm, run = W.config(name, **kw)
+    h = prm["h"] if L is None else L / n[0]
+    prm = W.finalize(dict(prm, nx=n[0], ny=n[1], nz=n[2], h=h, x0=None))
+    return prm, run
+
+
+def _run_both(prm, fields, steps, tol_solve=1e-13, check_each=True):
+    ds = _lib()
+    prm = dict(prm, tol=tol_solve)
+    print(f"case nx={prm['nx']} ny={prm['ny']} nz={prm['nz']} bc={prm['bc_mode']} eq={prm['eq_model']} "
+          f"steps={steps}", flush=True)
+    g = ds.Grid(prm)
+    g.set_fields(fields)
+    st = S.to_state(fields, prm)
+    worst = {}
+    for n in range(steps):
+        g.step(1)
+        st, d = S.step(st, prm)
+        gd = g.diagnostics()
+        if check_each or n == steps - 1:
+            e = _compare(g.get_fields(), st, f"step {n}")
+            for k, v in e.items():
+                worst[k] = max(worst.get(k, 0.0), v)
+            assert gd["n_interface"] == d["n_interface"], (gd["n_interface"], d["n_interface"])
+            assert gd["K"] == pytest.approx(d["K"], rel=1e-11)
+            assert gd["mdot_total"] == pytest.approx(d["mdot_total"], rel=1e-10, abs=1e-30)
+            assert gd["volume"] == pytest.approx(d["volume"], rel=1e-12)
+    return g, st, worst
+
+
+@pytest.mark.parametrize("mode", [W.BC_NATURAL, W.BC_FORCED, W.BC_FARFIELD])
+def test_step_parity_ragged_grid(mode):
+    """Ragged 17x19x23 grid (several 256-thread ranges plus a tail), random
+    droplet state with flow, 3 steps."""
+    prm, _ = _grid_params(n=(17, 19, 23), L=17 * 1.25e-4, bc_mode=mode, w_in=0.2 if mode == W.BC_FORCED else 0.0)
+    f = W.random_fields(prm, seed=7)
+    _run_both(prm, f, steps=3)
+
+
+def test_step_parity_c1_twenty_steps():
+    """Configuration C1 (32^3, natural convection, ideal equilibrium), every
+    step of the 20-step run."""
+    prm, run = W.config("C1")
+    f = W.initial_fields(prm, **run)
+    g, st, worst = _run_both(prm, f, steps=run["steps"])
+    print("worst relative errors over 20 steps:", worst)
+
+
+def test_step_parity_peng_robinson():
+    """Non-ideal equilibrium (20 bar, Peng-Robinson) on a 24^3 cut of C3."""
+    prm, run = W.scaled("C3", 24)
+    prm = dict(prm, precision=0)
+    f = W.initial_fields(prm, D0=1e-3, seed=1, T_noise=0.02)
+    _run_both(prm, f, steps=3)
+
+
+def test_interface_decisions_bit_exact():
+    """Interface class and the int -> adj association agree exactly; the raw
+    source agrees to rounding."""
+    ds = _lib()
+    from oracle import interface as I, thermo as th
+    prm, _ = _grid_params(n=(24, 26, 28), L=24 * 1.25e-4)
+    f = W.random_fields(prm, seed=3)
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    total, mdot = g.evaporation_rate(return_field=True)
+    st = S.to_state(f, prm)
+    geo = I.geometry(st["alpha"], prm)
+    rho_G = th.gas_density(prm)
+    mraw = I.raw_evaporation(st["alpha"], st["T"], st["omega"], st["u"], st["v"], st["w"], geo, prm, rho_G)
+    adj_gpu = g.internal(ds.FIELD_ADJ).cpu().numpy().astype(np.int64)
+    expect = np.full(adj_gpu.shape, -2, dtype=np.int64)
+    ic = geo["icells"].numpy()
+    a = st["alpha"].numpy()
+    eps = prm["eps_int"]
+    band = (a > eps) & (a < 1 - eps)
+    expect[band] = -1
+    flat = lambda ijk: (ijk[:, 0] * prm["ny"] + ijk[:, 1]) * prm["nz"] + ijk[:, 2]
+    found = geo["found"].numpy()
+    expect[ic[found, 0], ic[found, 1], ic[found, 2]] = flat(geo["adj"].numpy()[found])
+    assert np.array_equal(adj_gpu, expect)
+    assert _rel(g.internal(ds.FIELD_MDOT_RAW), mraw) < 1e-12
+    mdot_o, K = I.redistribute(mraw, st["alpha"])
+    assert _rel(mdot, mdot_o) < 1e-12
+    assert total == pytest.approx(prm["h"] ** 3 * float(mdot_o.sum()), rel=1e-12)
+
+
+def test_solve_pressure_static_droplet():
+    """One projection from rest with the centripetal force only."""
+    ds = _lib()
+    prm, run = W.config("C1", g=(0.0, 0.0, 0.0), evaporation=0, solve_energy=0, tol=1e-13)
+    f = W.initial_fields(prm, D0=1e-3)
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    it, res = g.solve_pressure()
+    assert res <= 1e-13
+    new, d = S.step(S.to_state(f, prm), prm)
+    out = g.get_fields()
+    assert _rel(out["p"], new["p"]) < TOL
+    for k in "uvw":
+        assert _rel(out[k], new[k]) < 1e-8
+
+
+def test_determinism_bitwise():
+    ds = _lib()
+    prm, run = W.config("C1")
+    f = W.initial_fields(prm, **run)
+    outs = []
+    for _ in range(2):
+        g = ds.Grid(prm)
+        g.set_fields(f)
+        g.step(3)
+        outs.append(g.get_fields())
+    for k in FIELDS:
+        assert torch.equal(outs[0][k], outs[1][k]), k
+
+
+def test_error_paths():
+    ds = _lib()
+    prm, run = W.config("C1")
+    f = W.initial_fields(prm, **run)
+    g = ds.Grid(prm)
+    with pytest.raises(ds.DSError) as e:
+        g.step(1)
+    assert e.value.code == ds.DS_ERR_STATE
+    g2 = ds.Grid(dict(prm, maxit=1))
+    g2.set_fields(f)
+    with pytest.raises(ds.NotConverged):
+        g2.step(1)
+    assert g2.diagnostics()["converged"] == 0
+    bad = dict(f)
+    bad["T"] = bad["T"].copy()
+    bad["T"][3, 4, 5] = float("nan")
+    g3 = ds.Grid(prm)
+    with pytest.raises(ds.DSError) as e:
+        g3.set_fields(bad)
+    assert e.value.code == ds.DS_ERR_NONFINITE
+    with pytest.raises(ds.DSError):
+        ds.create_grid(1, 4, 4, prm)
