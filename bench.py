@@ -26,6 +26,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256, help="grid cells per axis (default: the 256^3 workload)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--jacobi", action="store_true", help="Jacobi-PCG pressure solve instead of multigrid")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
@@ -39,7 +40,7 @@ def main():
     prm, run = W.config("C3")
     if args.n != 256:
         prm, run = W.scaled("C3", args.n)
-    prm = dict(prm, precision=0 if args.precision == "fp64" else 1)
+    prm = dict(prm, precision=0 if args.precision == "fp64" else 1, pressure_precond=0 if args.jacobi else 1)
     f = W.initial_fields(prm, **run)
     torch.cuda.set_device(0)
     g = ds.Grid(prm)
@@ -54,7 +55,7 @@ def main():
     for k in range(args.steps):
         g.step(1)
         d = g.diagnostics()
-        iters.append((d["iters_T"], d["iters_omega"], d["iters_p"]))
+        iters.append((d["iters_T"], d["iters_omega"], d["iters_p"], d["refinements_p"]))
         print(f"# step {k} iters T/omega/p {iters[-1]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()

@@ -90,7 +90,7 @@ typedef struct ds_params {
   int precision;       /* DS_PREC_*: FP64 solves, or FP32 sweeps + FP64 refinement */
   int solve_energy;    /* 0: temperature frozen (isothermal runs) */
   int evaporation;     /* 0: no evaporation source */
-  int reserved;
+  int pressure_precond; /* 0: Jacobi-PCG, 1: geometric-multigrid PCG (FP64 path) */
 } ds_params;
 
 /* Scalars of the most recent step (or evaporation/pressure call). */

@@ -42,7 +42,7 @@ class Params(C.Structure):
         ("T_ref", C.c_double), ("p_ref", C.c_double), ("eps_int", C.c_double), ("theta_min", C.c_double),
         ("tol", C.c_double),
         ("s_max", C.c_int), ("maxit", C.c_int), ("eq_model", C.c_int), ("bc_mode", C.c_int),
-        ("precision", C.c_int), ("solve_energy", C.c_int), ("evaporation", C.c_int), ("reserved", C.c_int),
+        ("precision", C.c_int), ("solve_energy", C.c_int), ("evaporation", C.c_int), ("pressure_precond", C.c_int),
     ]
 
 
@@ -94,9 +94,7 @@ def _check(handle, code):
 def make_params(prm: dict) -> Params:
     P = Params()
     for name, ctype in Params._fields_:
-        if name == "reserved":
-            continue
-        val = prm[name]
+        val = prm.get(name, 1) if name == "pressure_precond" else prm[name]
         if name in ("g", "x0"):
             setattr(P, name, (C.c_double * 3)(*[float(x) for x in val]))
         else:

@@ -12,6 +12,7 @@
 #include "../../include/dsvof.h"
 #include "ds_device.h"
 #include "ds_kernels.h"
+#include "ds_mg.h"
 
 using namespace dsv;
 
@@ -57,13 +58,21 @@ struct ds_grid {
   double* partials = nullptr;
   unsigned* counters = nullptr;
   double* scal = nullptr;
-  SolveStatus* status = nullptr;   // 3 solves
+  SolveStatus* status = nullptr;   // T, omega, p, inner FP32 solve
+  double* p_alt = nullptr;         // second CG direction buffer
+  MgHier<double> H64;
+  MgHier<float> H32;
+  Lev<double> L0;                  // fine-level dimensions and tiles (operator pointers set per solve)
+  float *qc32 = nullptr, *diag32 = nullptr;
+  float *e32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p32alt = nullptr, *q32 = nullptr;
+  int dirmask = 0;                 // p_rgh = 0 box faces
+  int batch_p = 4;
   // pinned host mirrors
   double* h_scal = nullptr;
-  SolveStatus* h_status = nullptr;
+  SolveStatus* h_status = nullptr;   // 4 slots
   ds_diagnostics diag_out{};
   double fuel_mass_prev = 0.0;
-  int batch[3] = {16, 16, 32};
+  int batch[3] = {8, 8, 8};
 };
 
 namespace {
@@ -129,38 +138,194 @@ size_t carve(ds_grid* g, char* base) {
   g->partials = L.take<double>(base, (size_t)MAX_BLOCKS * MAX_RED);
   g->counters = L.take<unsigned>(base, CT_COUNT);
   g->scal = L.take<double>(base, SC_COUNT);
-  g->status = L.take<SolveStatus>(base, 3);
+  g->status = L.take<SolveStatus>(base, 4);
+  g->p_alt = L.take<double>(base, n);
+  // FP64 multigrid levels (level 0 uses qc/diag of the pressure system)
+  MgHier<double>& H = g->H64;
+  H.lev[0].qc = g->qc;
+  H.lev[0].diag = g->diag;
+  for (int l = 0; l < H.nlev; ++l) {
+    const long long nl = H.lev[l].n;
+    if (l > 0) {
+      H.lev[l].qc = L.take<double>(base, nl);
+      H.lev[l].diag = L.take<double>(base, nl);
+      H.r[l] = L.take<double>(base, nl);
+    }
+    H.x[l] = L.take<double>(base, nl);
+    H.t[l] = L.take<double>(base, nl);
+  }
+  if (g->prm.precision == DS_PREC_MIXED) {
+    MgHier<float>& F = g->H32;
+    g->qc32 = L.take<float>(base, n);
+    g->diag32 = L.take<float>(base, n);
+    F.lev[0].qc = g->qc32;
+    F.lev[0].diag = g->diag32;
+    for (int l = 0; l < F.nlev; ++l) {
+      const long long nl = F.lev[l].n;
+      if (l > 0) {
+        F.lev[l].qc = L.take<float>(base, nl);
+        F.lev[l].diag = L.take<float>(base, nl);
+        F.r[l] = L.take<float>(base, nl);
+      }
+      F.x[l] = L.take<float>(base, nl);
+      F.t[l] = L.take<float>(base, nl);
+    }
+    g->e32 = L.take<float>(base, n);
+    g->r32 = L.take<float>(base, n);
+    g->p32 = L.take<float>(base, n);
+    g->p32alt = L.take<float>(base, n);
+    g->q32 = L.take<float>(base, n);
+  }
   return L.off;
 }
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Jacobi-PCG solve of one system (0 = T, 1 = omega, 2 = p); x holds the warm start.
-int solve(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res) {
-  SolveStatus init{};
-  init.tol = g->prm.tol;
-  init.maxit = g->prm.maxit;
-  SolveStatus* st = g->status + sys;
-  HIPCHK(g, hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
-  launch_pcg_init(g->dp, sc, g->qc, g->diag, g->b, x, g->r, g->pd, st, g->partials, g->counters + CT_SOLVE0, s);
-  launch_zero_if_flagged(x, g->n, st, s);
-  HIPCHK(g, hipMemcpyAsync(g->h_status + sys, st, sizeof(SolveStatus), hipMemcpyDeviceToHost, s));
+template <class T>
+void build_hier(MgHier<T>& H, int nx, int ny, int nz, double h, double dt) {
+  H.nlev = 0;
+  double hl = h;
+  for (;;) {
+    Lev<T>& L = H.lev[H.nlev++];
+    lev_dims(L, nx, ny, nz, dt / (hl * hl));
+    if (std::min(nx, std::min(ny, nz)) < 4 || H.nlev == MG_MAXLEV) break;
+    nx = (nx + 1) / 2;
+    ny = (ny + 1) / 2;
+    nz = (nz + 1) / 2;
+    hl *= 2.0;
+  }
+}
+
+int sync_status(ds_grid* g, int slot, hipStream_t s) {
+  HIPCHK(g, hipMemcpyAsync(g->h_status + slot, g->status + slot, sizeof(SolveStatus), hipMemcpyDeviceToHost, s));
   HIPCHK(g, hipStreamSynchronize(s));
-  while (!g->h_status[sys].done) {
-    const int m = g->batch[sys];
-    for (int t = 0; t < m; ++t)
-      launch_pcg_iter(g->dp, sc, g->qc, g->diag, x, g->r, g->pd, g->q, st, g->partials,
-                      g->counters + CT_SOLVE1, s);
-    HIPCHK(g, hipGetLastError());
-    HIPCHK(g, hipMemcpyAsync(g->h_status + sys, st, sizeof(SolveStatus), hipMemcpyDeviceToHost, s));
-    HIPCHK(g, hipStreamSynchronize(s));
+  return DS_OK;
+}
+
+int init_status(ds_grid* g, int slot, double tol, int maxit, hipStream_t s) {
+  SolveStatus init{};
+  init.tol = tol;
+  init.maxit = maxit;
+  HIPCHK(g, hipMemcpyAsync(g->status + slot, &init, sizeof(init), hipMemcpyHostToDevice, s));
+  return DS_OK;
+}
+
+// Iterations enqueued between host convergence tests: about half of the
+// previous solve's count, so most solves finish in two or three batches.
+int& batch_of(ds_grid* g, int sys) { return sys == 2 ? g->batch_p : g->batch[sys]; }
+
+// FP64 preconditioned CG on the system in qc/diag (scale sc), right-hand side
+// b, warm start in x.  sys: 0 = energy, 1 = species (Jacobi), 2 = pressure
+// (multigrid when enabled, Jacobi otherwise).
+int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res) {
+  int st;
+  Lev<double> L = g->L0;
+  L.sc = sc;
+  L.qc = g->qc;
+  L.diag = g->diag;
+  MgHier<double>* H = nullptr;
+  if (sys == 2 && g->prm.pressure_precond == 1) {
+    H = &g->H64;
+    H->lev[0] = L;
+    mg_setup_levels(*H, g->dirmask, s);
+  }
+  SolveStatus* ss = g->status + sys;
+  if ((st = init_status(g, sys, g->prm.tol, g->prm.maxit, s)) != DS_OK) return st;
+  launch_resid64(L, g->b, x, g->r, ss, g->partials, g->counters + CT_SOLVE0, true, s);
+  launch_zero_if_flagged(x, g->n, ss, s);
+  HIPCHK(g, hipGetLastError());
+  if ((st = sync_status(g, sys, s)) != DS_OK) return st;
+  if (!g->h_status[sys].done) {
+    CgVecs<double> V{x, g->r, g->pd, g->p_alt, g->q};
+    double* z = nullptr;
+    cg_start(L, H, V, &z, ss, g->partials, g->counters + CT_SOLVE0, s);
+    bool first = true;
+    while (!g->h_status[sys].done) {
+      for (int t = 0; t < batch_of(g, sys); ++t) {
+        cg_iteration(L, H, V, &z, ss, g->partials, g->counters + CT_SOLVE0, first, s);
+        first = false;
+      }
+      HIPCHK(g, hipGetLastError());
+      if ((st = sync_status(g, sys, s)) != DS_OK) return st;
+    }
   }
   const SolveStatus& h = g->h_status[sys];
-  // next batch: about a third of this solve's count, at least 4 iterations
-  g->batch[sys] = std::max(4, std::min(512, h.it / 3 + 1));
+  batch_of(g, sys) = std::max(2, std::min(256, h.it / 2 + 1));
   *iters = h.it;
   *res = h.res;
+  if (sys == 2) g->diag_out.refinements_p = 0;
   return h.done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
+}
+
+// Precision form of one solve: FP64 residual r = b - A x; FP32 preconditioned
+// CG for the correction A e = r to an inner tolerance (FP32 vectors, operator
+// and sweeps, FP64 dot products); x += e in FP64; repeat until ||r|| <= tol ||b||.
+int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res) {
+  int st;
+  Lev<double> L = g->L0;
+  L.sc = sc;
+  L.qc = g->qc;
+  L.diag = g->diag;
+  Lev<float> F;
+  lev_dims(F, L.nx, L.ny, L.nz, sc);
+  F.qc = g->qc32;
+  F.diag = g->diag32;
+  launch_to_float(g->qc, g->qc32, g->n, s);
+  launch_to_float(g->diag, g->diag32, g->n, s);
+  MgHier<float>* H = nullptr;
+  if (sys == 2 && g->prm.pressure_precond == 1) {
+    H = &g->H32;
+    H->lev[0] = F;
+    mg_setup_levels(*H, g->dirmask, s);
+  }
+  SolveStatus* so = g->status + sys;
+  SolveStatus* si = g->status + 3;
+  const double inner_tol = 1e-5;
+  const int max_rounds = 12;
+  if ((st = init_status(g, sys, g->prm.tol, g->prm.maxit, s)) != DS_OK) return st;
+  launch_resid64(L, g->b, x, g->r, so, g->partials, g->counters + CT_SOLVE0, true, s);
+  launch_zero_if_flagged(x, g->n, so, s);
+  HIPCHK(g, hipGetLastError());
+  if ((st = sync_status(g, sys, s)) != DS_OK) return st;
+  int total = 0, rounds = 0, inner_fail = 0;
+  while (!g->h_status[sys].done && rounds < max_rounds && !inner_fail) {
+    if ((st = init_status(g, 3, inner_tol, g->prm.maxit, s)) != DS_OK) return st;
+    launch_inner_init<float>(F, g->r, g->r32, g->e32, si, g->partials, g->counters + CT_SOLVE1, s);
+    CgVecs<float> V{g->e32, g->r32, g->p32, g->p32alt, g->q32};
+    float* z = nullptr;
+    cg_start(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, s);
+    bool first = true;
+    do {
+      for (int t = 0; t < batch_of(g, sys); ++t) {
+        cg_iteration(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, first, s);
+        first = false;
+      }
+      HIPCHK(g, hipGetLastError());
+      if ((st = sync_status(g, 3, s)) != DS_OK) return st;
+    } while (!g->h_status[3].done);
+    total += g->h_status[3].it;
+    inner_fail = g->h_status[3].done == 2;
+    launch_add_correction<float>(F, x, g->e32, s);
+    launch_resid64(L, g->b, x, g->r, so, g->partials, g->counters + CT_SOLVE0, false, s);
+    HIPCHK(g, hipGetLastError());
+    if ((st = sync_status(g, sys, s)) != DS_OK) return st;
+    ++rounds;
+  }
+  batch_of(g, sys) = std::max(2, std::min(256, total / std::max(1, 2 * rounds) + 1));
+  *iters = total;
+  *res = g->h_status[sys].res;
+  if (sys == 2) g->diag_out.refinements_p = rounds;
+  return g->h_status[sys].done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
+}
+
+int solve(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res) {
+  if (g->prm.precision == DS_PREC_MIXED) return cg_solve_mixed(g, sys, sc, x, s, iters, res);
+  return cg_solve64(g, sys, sc, x, s, iters, res);
+}
+
+int solve_pressure_system(ds_grid* g, hipStream_t s, int* iters, double* res) {
+  const DevParams& P = g->dp;
+  return solve(g, 2, P.dt / (P.h * P.h), g->p, s, iters, res);
 }
 
 int evaporation_source(ds_grid* g, hipStream_t s) {
@@ -215,7 +380,7 @@ int one_step(ds_grid* g, hipStream_t s) {
   launch_predictor(P, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, s);
   // 6. pressure (warm start p^n) and correction
   launch_pressure_setup(P, g->a_new, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s);
-  st = solve(g, 2, P.dt / (P.h * P.h), g->p, s, &D.iters_p, &D.res_p);
+  st = solve_pressure_system(g, s, &D.iters_p, &D.res_p);
   if (st == DS_ERR_NOT_CONVERGED) rc = st;
   else if (st != DS_OK) return st;
   launch_project(P, g->a_new, g->p, g->us, g->vs, g->ws, g->u, g->v, g->w, s);
@@ -236,7 +401,6 @@ int one_step(ds_grid* g, hipStream_t s) {
   D.alpha_max = sc[SC_AMAX];
   D.rho_G = P.rho_G;
   D.converged = rc == DS_OK;
-  D.refinements_p = 0;
   g->fuel_mass_prev = D.fuel_mass;
   if (sc[SC_NONFINITE] != 0.0) return fail(g, DS_ERR_NONFINITE, "non-finite values after the step");
   if (rc != DS_OK) fail(g, rc, "a linear solve reached maxit (T %d, omega %d, p %d iterations)", D.iters_T,
@@ -262,7 +426,8 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
       !finite_pos(prm->T_ref) || !finite_pos(prm->p_ref) || !(prm->eps_int > 0 && prm->eps_int < 0.5) ||
       !finite_pos(prm->theta_min) || !(prm->tol > 0) || prm->maxit < 1 || prm->s_max < 1 ||
       prm->eq_model < 0 || prm->eq_model > 1 || prm->bc_mode < 0 || prm->bc_mode > 2 ||
-      prm->precision < 0 || prm->precision > 1 || !finite_pos(prm->r_fib))
+      prm->precision < 0 || prm->precision > 1 || !finite_pos(prm->r_fib) || prm->pressure_precond < 0 ||
+      prm->pressure_precond > 1)
     return DS_ERR_ARG;
   if (prm->eq_model == DS_EQ_PENG_ROBINSON &&
       (!finite_pos(prm->Tc) || !finite_pos(prm->Pc) || !finite_pos(prm->Tc_G) || !finite_pos(prm->Pc_G)))
@@ -329,9 +494,18 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
       else kind = prm->bc_mode == DS_BC_FORCED ? INLET : OPEN;
       P.kind[ax * 2 + sd] = kind;
     }
+  for (int ax = 0; ax < 3; ++ax)
+    for (int sd = 0; sd < 2; ++sd)
+      if (pressure_dirichlet(P.kind[ax * 2 + sd])) g->dirmask |= 1 << (ax * 2 + sd);
+  lev_dims(g->L0, nx, ny, nz, 1.0);
+  if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
+  if (prm->precision == DS_PREC_MIXED) {
+    if (prm->pressure_precond == 1) build_hier(g->H32, nx, ny, nz, prm->h, prm->dt);
+    else lev_dims(g->H32.lev[0], nx, ny, nz, 1.0), g->H32.nlev = 1;
+  }
   g->ws_bytes = carve(g, nullptr);
   if (hipHostMalloc((void**)&g->h_scal, SC_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&g->h_status, 3 * sizeof(SolveStatus), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&g->h_status, 4 * sizeof(SolveStatus), hipHostMallocDefault) != hipSuccess) {
     if (g->h_scal) (void)hipHostFree(g->h_scal);
     delete g;
     return DS_ERR_HIP;
@@ -429,7 +603,7 @@ int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res) {
   launch_pressure_setup(P, g->alpha, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s);
   int it = 0;
   double res = 0.0;
-  st = solve(g, 2, P.dt / (P.h * P.h), g->p, s, &it, &res);
+  st = solve_pressure_system(g, s, &it, &res);
   if (st != DS_OK && st != DS_ERR_NOT_CONVERGED) return st;
   launch_project(P, g->alpha, g->p, g->us, g->vs, g->ws, g->u, g->v, g->w, s);
   HIPCHK(g, hipGetLastError());

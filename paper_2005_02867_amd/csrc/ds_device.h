@@ -170,6 +170,6 @@ __device__ __forceinline__ bool scalar_dirichlet(int kind, double uface, int sid
   if (kind == INLET || kind == FARFIELD) return true;
   return side == 0 ? (uface > 0.0) : (uface < 0.0);
 }
-__device__ __forceinline__ bool pressure_dirichlet(int kind) { return kind == OPEN || kind == FARFIELD; }
+__host__ __device__ __forceinline__ bool pressure_dirichlet(int kind) { return kind == OPEN || kind == FARFIELD; }
 
 }  // namespace dsv

@@ -55,14 +55,4 @@ void launch_c_from_omega(const DevParams& P, const double* alpha, const double* 
 void launch_fill(double* x, double v, long long n, hipStream_t s);
 void launch_int_to_double(const int* src, double* dst, long long n, hipStream_t s);
 
-// ---- solver kernels (k_solver.hip)
-// Operator: (A x)_c = diag_c x_c - sum_nb sc * (q_c + q_nb)/2 * x_nb over interior neighbours.
-void launch_pcg_init(const DevParams& P, double sc, const double* qc, const double* diag,
-                     const double* b, const double* x, double* r, double* pdir, SolveStatus* st,
-                     double* partials, unsigned* counter, hipStream_t s);
-void launch_pcg_iter(const DevParams& P, double sc, const double* qc, const double* diag,
-                     double* x, double* r, double* pdir, double* q, SolveStatus* st,
-                     double* partials, unsigned* counters, hipStream_t s);
-void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s);
-
 }  // namespace dsv

@@ -1,0 +1,87 @@
+// Level descriptors, tile mapping and launchers of the conjugate-gradient
+// solvers (Jacobi or geometric multigrid preconditioning, FP64 or FP32).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "ds_device.h"
+
+namespace dsv {
+
+constexpr int MG_MAXLEV = 12;
+constexpr int TK = 64;   // tile extent along z (one wavefront)
+constexpr int TJ = 4;    // tile extent along y (four wavefronts per block)
+
+// One level's operator: (A x)_c = diag_c x_c - sc/2 sum_nb (q_c + q_nb) x_nb,
+// plus its 64x4 tile decomposition.
+template <class T>
+struct Lev {
+  int nx, ny, nz;
+  int ntk, ntj;
+  unsigned ntiles;
+  long long n;
+  T sc;
+  const T* qc;
+  const T* diag;
+};
+
+template <class T>
+inline void lev_dims(Lev<T>& L, int nx, int ny, int nz, double sc) {
+  L.nx = nx;
+  L.ny = ny;
+  L.nz = nz;
+  L.ntk = (nz + TK - 1) / TK;
+  L.ntj = (ny + TJ - 1) / TJ;
+  L.ntiles = (unsigned)L.ntk * (unsigned)L.ntj * (unsigned)nx;
+  L.n = (long long)nx * ny * nz;
+  L.sc = (T)sc;
+}
+
+template <class T>
+struct MgHier {
+  int nlev = 0;
+  Lev<T> lev[MG_MAXLEV];
+  T* r[MG_MAXLEV] = {};   // level right-hand sides (level 0: the CG residual, not stored here)
+  T* x[MG_MAXLEV] = {};   // level iterates (ping-pong with t)
+  T* t[MG_MAXLEV] = {};
+  double omega = 0.8;     // damped Jacobi weight
+  int nu = 2;             // pre = post smoothing sweeps
+  int coarse_sweeps = 16; // sweeps on the coarsest level
+};
+
+// CG work vectors of one precision.
+template <class T>
+struct CgVecs {
+  T* x;        // solution (FP64 path) or correction (inner FP32 path)
+  T* r;        // residual
+  T* p;        // direction (ping-pong with p_alt)
+  T* p_alt;
+  T* q;        // A p
+};
+
+// dirmask bit (axis*2 + side) set: p_rgh = 0 on that box face.
+template <class T>
+void mg_setup_levels(MgHier<T>& H, int dirmask, hipStream_t s);
+
+// Enqueue the start of a solve whose residual is already in V.r (and whose
+// status holds bnorm): z = M^-1 r, rz = <r, z>.  Then iterations.
+template <class T>
+void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
+              unsigned* counters, hipStream_t s);
+template <class T>
+void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
+                  unsigned* counters, bool first, hipStream_t s);
+
+// r = b - A x (FP64), ||b|| (if set_bnorm), ||r|| -> status (done if ||r|| <= tol ||b||).
+void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
+                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s);
+void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s);
+template <class T>
+void launch_inner_init(const Lev<T>& L, const double* r64, T* r, T* x, SolveStatus* st, double* partials,
+                       unsigned* counter, hipStream_t s);
+template <class T>
+void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s);
+void launch_to_float(const double* a, float* b, long long n, hipStream_t s);
+
+}  // namespace dsv

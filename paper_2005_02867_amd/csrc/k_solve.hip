@@ -1,0 +1,476 @@
+// Matrix-free preconditioned conjugate gradients for the symmetric positive
+// definite 7-point systems of the step (implicit Euler of eqs. 7-9):
+//   (A x)_c = diag_c x_c - sc/2 sum_{interior nb} (q_c + q_nb) x_nb,
+// diag holding the Helmholtz term, the face sum and the Dirichlet boundary
+// coefficients.  Preconditioners: Jacobi (energy, species) or a geometric
+// multigrid V-cycle (pressure).
+//
+// Multigrid: every level carries the same operator form, q averaged over the
+// (up to 8) children of a coarse cell, sc = dt/H^2 on a level of spacing H,
+// p_rgh = 0 box faces adding 2 sc q_c to the diagonal; restriction P^T/8,
+// piecewise-constant prolongation, damped Jacobi with equal pre/post sweep
+// counts, so the V-cycle is a symmetric positive definite preconditioner.
+//
+// Kernels are templated on the vector type (double, or float for the FP32
+// inner solves of the mixed-precision form); dot products always accumulate
+// in FP64, combined in a fixed order (deterministic).  Each kernel reads the
+// device-side status first and returns when the solve has finished, so the
+// host enqueues iterations in batches and tests convergence once per batch.
+//
+// Work decomposition: 64 (z) x 4 (y) cell tiles, one cell per thread, no
+// integer division per cell.  XCD x (blocks are dealt to the 8 XCDs
+// round-robin) owns one contiguous eighth of the tiles, i.e. a slab of
+// x-planes, so stencil neighbours are served from that XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ds_device.h"
+#include "ds_kernels.h"
+#include "ds_mg.h"
+
+namespace dsv {
+
+__device__ __forceinline__ void tile_span(unsigned ntiles, unsigned& t0, unsigned& t1, unsigned& step) {
+  const unsigned nb = gridDim.x, per = nb / NXCD, xcd = blockIdx.x % NXCD, local = blockIdx.x / NXCD;
+  const unsigned chunk = (ntiles + NXCD - 1) / NXCD;
+  t0 = xcd * chunk + local;
+  t1 = min((xcd + 1) * chunk, ntiles);
+  step = per;
+}
+
+template <class T>
+__device__ __forceinline__ bool tile_cell(const Lev<T>& L, unsigned t, int& i, int& j, int& k, long long& c) {
+  const unsigned kt = t % (unsigned)L.ntk;
+  const unsigned r = t / (unsigned)L.ntk;
+  const unsigned jt = r % (unsigned)L.ntj;
+  i = (int)(r / (unsigned)L.ntj);
+  k = (int)kt * TK + (int)(threadIdx.x & (TK - 1));
+  j = (int)jt * TJ + (int)(threadIdx.x / TK);
+  c = ((long long)i * L.ny + j) * L.nz + k;
+  return j < L.ny && k < L.nz;
+}
+
+static int tile_blocks(unsigned ntiles) {
+  unsigned nb = std::min<unsigned>(std::max<unsigned>(ntiles, NXCD), MAX_BLOCKS);
+  return (int)((nb + NXCD - 1) / NXCD * NXCD);
+}
+
+// Loop over this block's cells: declares i, j, k (cell) and c (flat index).
+#define FOR_CELLS(L, i, j, k, c)               \
+  unsigned t0_, t1_, st_;                      \
+  tile_span((L).ntiles, t0_, t1_, st_);        \
+  int i, j, k;                                 \
+  long long c;                                 \
+  for (unsigned t_ = t0_; t_ < t1_; t_ += st_) \
+    if (tile_cell(L, t_, i, j, k, c))
+
+// Off-diagonal sum_nb (q_c + q_nb) x_nb, with the neighbour values given by xf(offset).
+template <class T, class F>
+__device__ __forceinline__ T off_sum(const Lev<T>& L, long long c, int i, int j, int k, F xf) {
+  const T q = L.qc[c];
+  const long long sx = (long long)L.ny * L.nz, sy = L.nz;
+  T off = 0;
+  if (i > 0) off += (q + L.qc[c - sx]) * xf(c - sx);
+  if (i < L.nx - 1) off += (q + L.qc[c + sx]) * xf(c + sx);
+  if (j > 0) off += (q + L.qc[c - sy]) * xf(c - sy);
+  if (j < L.ny - 1) off += (q + L.qc[c + sy]) * xf(c + sy);
+  if (k > 0) off += (q + L.qc[c - 1]) * xf(c - 1);
+  if (k < L.nz - 1) off += (q + L.qc[c + 1]) * xf(c + 1);
+  return off;
+}
+
+template <class T>
+__device__ __forceinline__ T apply_at(const Lev<T>& L, const T* __restrict__ x, long long c, int i, int j, int k) {
+  return L.diag[c] * x[c] - T(0.5) * L.sc * off_sum(L, c, i, j, k, [&](long long f) { return x[f]; });
+}
+
+// ------------------------------------------------------------ multigrid setup
+template <class T>
+__global__ void k_mg_coarsen_q(Lev<T> F, Lev<T> C, T* __restrict__ qout) {
+  FOR_CELLS(C, I, J, K, c) {
+    double s = 0.0;
+    int cnt = 0;
+    for (int di = 0; di < 2; ++di)
+      for (int dj = 0; dj < 2; ++dj)
+        for (int dk = 0; dk < 2; ++dk) {
+          const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+          if (i < F.nx && j < F.ny && k < F.nz) {
+            s += (double)F.qc[((long long)i * F.ny + j) * F.nz + k];
+            ++cnt;
+          }
+        }
+    qout[c] = (T)(s / cnt);
+  }
+}
+
+template <class T>
+__global__ void k_mg_diag(Lev<T> L, int dirmask, T* __restrict__ dout) {
+  FOR_CELLS(L, i, j, k, c) {
+    const double q = (double)L.qc[c], sc = (double)L.sc;
+    const long long sx = (long long)L.ny * L.nz, sy = L.nz;
+    double d = 0.0;
+    if (i > 0) d += sc * 0.5 * (q + (double)L.qc[c - sx]); else if (dirmask & 1) d += 2.0 * sc * q;
+    if (i < L.nx - 1) d += sc * 0.5 * (q + (double)L.qc[c + sx]); else if (dirmask & 2) d += 2.0 * sc * q;
+    if (j > 0) d += sc * 0.5 * (q + (double)L.qc[c - sy]); else if (dirmask & 4) d += 2.0 * sc * q;
+    if (j < L.ny - 1) d += sc * 0.5 * (q + (double)L.qc[c + sy]); else if (dirmask & 8) d += 2.0 * sc * q;
+    if (k > 0) d += sc * 0.5 * (q + (double)L.qc[c - 1]); else if (dirmask & 16) d += 2.0 * sc * q;
+    if (k < L.nz - 1) d += sc * 0.5 * (q + (double)L.qc[c + 1]); else if (dirmask & 32) d += 2.0 * sc * q;
+    dout[c] = (T)d;
+  }
+}
+
+// ------------------------------------------------------------ V-cycle pieces
+template <class T>
+__global__ void k_mg_smooth_zero(Lev<T> L, const T* __restrict__ r, T* __restrict__ x, T omega,
+                                 const SolveStatus* st) {
+  if (st->done) return;
+  FOR_CELLS(L, i, j, k, c) { x[c] = omega * r[c] / L.diag[c]; }
+}
+
+// Publish <r, z> of the preconditioned residual: beta = rz_new/rz (unless first).
+__device__ __forceinline__ void publish_rz(double acc0, SolveStatus* st, double* partials, unsigned* counter,
+                                           int first) {
+  double acc[1] = {acc0};
+  const int ops[1] = {RSUM};
+  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+    double t[1];
+    block_combine<1>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      if (!first) st->beta = t[0] / st->rz;
+      st->rz = t[0];
+    }
+  }
+}
+
+// x_out = x_in + omega (r - A x_in)/diag; with DOT, also <r, x_out>.
+template <class T, bool DOT>
+__global__ void k_mg_smooth(Lev<T> L, const T* __restrict__ r, const T* __restrict__ xin, T* __restrict__ xout,
+                            T omega, SolveStatus* st, double* partials, unsigned* counter, int first) {
+  if (st->done) return;
+  double acc = 0.0;
+  FOR_CELLS(L, i, j, k, c) {
+    const T rc = r[c];
+    const T xn = xin[c] + omega * (rc - apply_at(L, xin, c, i, j, k)) / L.diag[c];
+    xout[c] = xn;
+    if (DOT) acc += (double)rc * (double)xn;
+  }
+  if (DOT) publish_rz(acc, st, partials, counter, first);
+}
+
+// Coarse residual: rc[C] = (1/8) sum_children (r - A x).
+template <class T>
+__global__ void k_mg_restrict(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+                              T* __restrict__ rc, const SolveStatus* st) {
+  if (st->done) return;
+  FOR_CELLS(C, I, J, K, cc) {
+    T s = 0;
+    for (int di = 0; di < 2; ++di)
+      for (int dj = 0; dj < 2; ++dj)
+        for (int dk = 0; dk < 2; ++dk) {
+          const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+          if (i < F.nx && j < F.ny && k < F.nz) {
+            const long long f = ((long long)i * F.ny + j) * F.nz + k;
+            s += r[f] - apply_at(F, x, f, i, j, k);
+          }
+        }
+    rc[cc] = T(0.125) * s;
+  }
+}
+
+// x' = x + P xc (piecewise constant), then one smoothing sweep on x'.
+template <class T, bool DOT>
+__global__ void k_mg_prolong_smooth(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+                                    const T* __restrict__ xc, T* __restrict__ xout, T omega, SolveStatus* st,
+                                    double* partials, unsigned* counter, int first) {
+  if (st->done) return;
+  double acc = 0.0;
+  const long long sx = (long long)F.ny * F.nz, sy = F.nz;
+  FOR_CELLS(F, i, j, k, c) {
+    auto par = [&](int ii, int jj, int kk) -> long long {
+      return ((long long)(ii >> 1) * C.ny + (jj >> 1)) * C.nz + (kk >> 1);
+    };
+    const T q = F.qc[c];
+    T off = 0;
+    if (i > 0) off += (q + F.qc[c - sx]) * (x[c - sx] + xc[par(i - 1, j, k)]);
+    if (i < F.nx - 1) off += (q + F.qc[c + sx]) * (x[c + sx] + xc[par(i + 1, j, k)]);
+    if (j > 0) off += (q + F.qc[c - sy]) * (x[c - sy] + xc[par(i, j - 1, k)]);
+    if (j < F.ny - 1) off += (q + F.qc[c + sy]) * (x[c + sy] + xc[par(i, j + 1, k)]);
+    if (k > 0) off += (q + F.qc[c - 1]) * (x[c - 1] + xc[par(i, j, k - 1)]);
+    if (k < F.nz - 1) off += (q + F.qc[c + 1]) * (x[c + 1] + xc[par(i, j, k + 1)]);
+    const long long pc = par(i, j, k);
+    const T x0 = x[c] + xc[pc];
+    const T rc = r[c];
+    const T Ax = F.diag[c] * x0 - T(0.5) * F.sc * off;
+    const T xn = x0 + omega * (rc - Ax) / F.diag[c];
+    xout[c] = xn;
+    if (DOT) acc += (double)rc * (double)xn;
+  }
+  if (DOT) publish_rz(acc, st, partials, counter, first);
+}
+
+// ------------------------------------------------------------ CG pieces
+__global__ void k_resid64(Lev<double> L, const double* __restrict__ b, const double* __restrict__ x,
+                          double* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
+                          int set_bnorm) {
+  double acc[2] = {0.0, 0.0};
+  FOR_CELLS(L, i, j, k, c) {
+    const double bc = b[c];
+    const double rc = bc - apply_at(L, x, c, i, j, k);
+    r[c] = rc;
+    acc[0] += bc * bc;
+    acc[1] += rc * rc;
+  }
+  const int ops[2] = {RSUM, RSUM};
+  if (block_reduce_publish<2>(acc, ops, partials, counter)) {
+    double t[2];
+    block_combine<2>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      if (set_bnorm) {
+        st->bb = t[0];
+        st->bnorm = sqrt(t[0]);
+        st->it = 0;
+      }
+      st->rr = t[1];
+      st->zero = st->bb == 0.0;
+      st->res = st->bb == 0.0 ? 0.0 : sqrt(t[1]) / st->bnorm;
+      st->done = (st->bb == 0.0 || st->res <= st->tol) ? 1 : 0;
+    }
+  }
+}
+
+// Inner-solve start: r = (T) r64, x = 0; the inner reference norm is ||r||.
+template <class T>
+__global__ void k_inner_init(Lev<T> L, const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ x,
+                             SolveStatus* st, double* partials, unsigned* counter) {
+  double acc[1] = {0.0};
+  FOR_CELLS(L, i, j, k, c) {
+    const T v = (T)r64[c];
+    r[c] = v;
+    x[c] = 0;
+    acc[0] += (double)v * (double)v;
+  }
+  const int ops[1] = {RSUM};
+  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+    double t[1];
+    block_combine<1>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      st->bb = t[0];
+      st->bnorm = sqrt(t[0]);
+      st->rr = t[0];
+      st->res = t[0] == 0.0 ? 0.0 : 1.0;
+      st->it = 0;
+      st->zero = t[0] == 0.0;
+      st->done = t[0] == 0.0 ? 1 : 0;
+    }
+  }
+}
+
+// Jacobi start: rz = sum r^2/diag.
+template <class T>
+__global__ void k_jac_rz(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter) {
+  if (st->done) return;
+  double acc = 0.0;
+  FOR_CELLS(L, i, j, k, c) {
+    const double rc = (double)r[c];
+    acc += rc * rc / (double)L.diag[c];
+  }
+  publish_rz(acc, st, partials, counter, 1);
+}
+
+// p_out = z + beta p_in (z = r/diag for Jacobi), q = A p_out, <p, q> -> alpha.
+template <class T, bool JAC>
+__global__ void k_cg_dir_spmv(Lev<T> L, const T* __restrict__ z, const T* __restrict__ r, const T* __restrict__ pin,
+                              T* __restrict__ pout, T* __restrict__ q, SolveStatus* st, double* partials,
+                              unsigned* counter, int first) {
+  if (st->done) return;
+  const T be = first ? T(0) : (T)st->beta;
+  double acc[1] = {0.0};
+  FOR_CELLS(L, i, j, k, c) {
+    auto pn = [&](long long f) -> T {
+      const T zf = JAC ? r[f] / L.diag[f] : z[f];
+      return first ? zf : zf + be * pin[f];
+    };
+    const T pc = pn(c);
+    const T y = L.diag[c] * pc - T(0.5) * L.sc * off_sum(L, c, i, j, k, pn);
+    pout[c] = pc;
+    q[c] = y;
+    acc[0] += (double)pc * (double)y;
+  }
+  const int ops[1] = {RSUM};
+  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+    double t[1];
+    block_combine<1>(ops, partials, counter, t);
+    if (threadIdx.x == 0) st->alpha = st->rz / t[0];
+  }
+}
+
+// x += alpha p, r -= alpha q, ||r|| -> convergence; Jacobi: rz -> beta.
+template <class T, bool JAC>
+__global__ void k_cg_update(Lev<T> L, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                            const T* __restrict__ q, SolveStatus* st, double* partials, unsigned* counter) {
+  if (st->done) return;
+  const T a = (T)st->alpha;
+  double acc[2] = {0.0, 0.0};
+  FOR_CELLS(L, i, j, k, c) {
+    x[c] += a * p[c];
+    const T rc = r[c] - a * q[c];
+    r[c] = rc;
+    acc[0] += (double)rc * (double)rc;
+    if (JAC) acc[1] += (double)rc * (double)rc / (double)L.diag[c];
+  }
+  const int ops[2] = {RSUM, RSUM};
+  if (block_reduce_publish<2>(acc, ops, partials, counter)) {
+    double t[2];
+    block_combine<2>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      st->it += 1;
+      st->rr = t[0];
+      st->res = sqrt(t[0]) / st->bnorm;
+      if (st->res <= st->tol) {
+        st->done = 1;
+      } else if (st->it >= st->maxit) {
+        st->done = 2;
+      } else if (JAC) {
+        st->beta = t[1] / st->rz;
+        st->rz = t[1];
+      }
+    }
+  }
+}
+
+template <class T>
+__global__ void k_add_correction(Lev<T> L, double* __restrict__ x, const T* __restrict__ e) {
+  FOR_CELLS(L, i, j, k, c) { x[c] += (double)e[c]; }
+}
+
+__global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, long long n) {
+  long long b0, b1;
+  block_range(n, b0, b1);
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) b[c] = (float)a[c];
+}
+
+__global__ void k_zero_if_flagged(double* x, long long n, const SolveStatus* st) {
+  if (!st->zero) return;
+  long long b0, b1;
+  block_range(n, b0, b1);
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) x[c] = 0.0;
+}
+
+// ------------------------------------------------------------ host side
+template <class T>
+void mg_setup_levels(MgHier<T>& H, int dirmask, hipStream_t s) {
+  for (int l = 1; l < H.nlev; ++l) {
+    Lev<T>& C = H.lev[l];
+    k_mg_coarsen_q<T><<<tile_blocks(C.ntiles), BLOCK, 0, s>>>(H.lev[l - 1], C, const_cast<T*>(C.qc));
+    k_mg_diag<T><<<tile_blocks(C.ntiles), BLOCK, 0, s>>>(C, dirmask, const_cast<T*>(C.diag));
+  }
+}
+
+// Approximately solve A_l x = r from x = 0; the buffer holding x is returned in *out.
+template <class T>
+static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* partials, unsigned* counter,
+                      bool dot_first, bool dot, hipStream_t s, T** out) {
+  const Lev<T>& L = H.lev[l];
+  const T om = (T)H.omega;
+  T* a = H.x[l];
+  T* b = H.t[l];
+  const int nb = tile_blocks(L.ntiles);
+  const bool coarsest = (l == H.nlev - 1);
+  const int pre = coarsest ? std::max(2, H.coarse_sweeps) : H.nu;
+  k_mg_smooth_zero<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
+  for (int t = 1; t < pre; ++t) {
+    if (coarsest && dot && t == pre - 1)
+      k_mg_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, dot_first);
+    else
+      k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
+    std::swap(a, b);
+  }
+  if (coarsest) {
+    *out = a;
+    return;
+  }
+  const Lev<T>& C = H.lev[l + 1];
+  k_mg_restrict<T><<<tile_blocks(C.ntiles), BLOCK, 0, s>>>(L, C, r, a, H.r[l + 1], st);
+  T* xc = nullptr;
+  mg_vcycle(H, l + 1, H.r[l + 1], st, partials, counter, false, false, s, &xc);
+  for (int t = 0; t < H.nu; ++t) {
+    const bool d = dot && t == H.nu - 1;
+    if (t == 0) {
+      if (d)
+        k_mg_prolong_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, dot_first);
+      else
+        k_mg_prolong_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, 0);
+    } else {
+      if (d)
+        k_mg_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, dot_first);
+      else
+        k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
+    }
+    std::swap(a, b);
+  }
+  *out = a;
+}
+
+template <class T>
+void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
+              unsigned* counters, hipStream_t s) {
+  if (H) {
+    mg_vcycle(*H, 0, V.r, st, partials, counters + 2, true, true, s, z);
+  } else {
+    *z = nullptr;
+    k_jac_rz<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2);
+  }
+}
+
+template <class T>
+void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
+                  unsigned* counters, bool first, hipStream_t s) {
+  const int nb = tile_blocks(L.ntiles);
+  if (H) {
+    k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(L, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+    std::swap(V.p, V.p_alt);
+    k_cg_update<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
+    mg_vcycle(*H, 0, V.r, st, partials, counters + 2, false, true, s, z);
+  } else {
+    k_cg_dir_spmv<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+    std::swap(V.p, V.p_alt);
+    k_cg_update<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
+  }
+}
+
+void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
+                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s) {
+  k_resid64<<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);
+}
+void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s) {
+  k_zero_if_flagged<<<grid_blocks(n), BLOCK, 0, s>>>(x, n, st);
+}
+template <class T>
+void launch_inner_init(const Lev<T>& L, const double* r64, T* r, T* x, SolveStatus* st, double* partials,
+                       unsigned* counter, hipStream_t s) {
+  k_inner_init<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, r64, r, x, st, partials, counter);
+}
+template <class T>
+void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s) {
+  k_add_correction<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, x, e);
+}
+void launch_to_float(const double* a, float* b, long long n, hipStream_t s) {
+  k_to_float<<<grid_blocks(n), BLOCK, 0, s>>>(a, b, n);
+}
+
+template void mg_setup_levels<double>(MgHier<double>&, int, hipStream_t);
+template void mg_setup_levels<float>(MgHier<float>&, int, hipStream_t);
+template void cg_start<double>(const Lev<double>&, MgHier<double>*, CgVecs<double>&, double**, SolveStatus*,
+                               double*, unsigned*, hipStream_t);
+template void cg_start<float>(const Lev<float>&, MgHier<float>*, CgVecs<float>&, float**, SolveStatus*, double*,
+                              unsigned*, hipStream_t);
+template void cg_iteration<double>(const Lev<double>&, MgHier<double>*, CgVecs<double>&, double**, SolveStatus*,
+                                   double*, unsigned*, bool, hipStream_t);
+template void cg_iteration<float>(const Lev<float>&, MgHier<float>*, CgVecs<float>&, float**, SolveStatus*,
+                                  double*, unsigned*, bool, hipStream_t);
+template void launch_inner_init<float>(const Lev<float>&, const double*, float*, float*, SolveStatus*, double*,
+                                       unsigned*, hipStream_t);
+template void launch_add_correction<float>(const Lev<float>&, double*, const float*, hipStream_t);
+
+}  // namespace dsv

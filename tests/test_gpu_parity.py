@@ -182,3 +182,41 @@ def test_error_paths():
     assert e.value.code == ds.DS_ERR_NONFINITE
     with pytest.raises(ds.DSError):
         ds.create_grid(1, 4, 4, prm)
+
+
+def test_step_parity_jacobi_pressure():
+    """The plain Jacobi-PCG pressure path agrees with the oracle as well."""
+    prm, _ = _grid_params(n=(17, 19, 23), L=17 * 1.25e-4, pressure_precond=0)
+    f = W.random_fields(prm, seed=11)
+    _run_both(prm, f, steps=2)
+
+
+def test_step_parity_mixed_precision_refined():
+    """FP32 sweeps + FP64 refinement to 1e-13 reaches the FP64 discrete
+    solution: same 1e-9 bar against the oracle on C1, 10 steps."""
+    prm, run = W.config("C1", precision=W.PREC_MIXED)
+    f = W.initial_fields(prm, **run)
+    g, st, worst = _run_both(prm, f, steps=10)
+    assert g.diagnostics()["refinements_p"] >= 1
+
+
+def test_precision_form_volume_after_200_steps():
+    """Precision form at the configuration tolerance (1e-10): droplet volume
+    after 200 steps within 1e-6 relative of the FP64 GPU path (96^3 cut of
+    the 20 bar Peng-Robinson case)."""
+    ds = _lib()
+    prm, run = W.scaled("C3", 96)
+    f = W.initial_fields(prm, **run)
+    vols = {}
+    for prec in (W.PREC_FP64, W.PREC_MIXED):
+        print(f"precision {prec}: 200 steps at 96^3", flush=True)
+        g = ds.Grid(dict(prm, precision=prec))
+        g.set_fields(f)
+        g.step(200)
+        vols[prec] = g.droplet_volume()
+        d = g.diagnostics()
+        rel = abs(d["fuel_mass"] - d["fuel_mass_before"] + d["B_L"] + d["B_v"]) / d["fuel_mass_before"]
+        assert rel <= 1e-10, rel
+    rel = abs(vols[W.PREC_MIXED] - vols[W.PREC_FP64]) / vols[W.PREC_FP64]
+    print("volume FP64", vols[W.PREC_FP64], "mixed", vols[W.PREC_MIXED], "rel", rel)
+    assert rel <= 1e-6

@@ -48,6 +48,7 @@ _BASE = dict(
     tol=1e-10, maxit=20000,
     eq_model=EQ_IDEAL, bc_mode=BC_NATURAL, precision=PREC_FP64,
     solve_energy=1, evaporation=1,
+    pressure_precond=1,
 )
 
 # name -> (overrides, run description)
