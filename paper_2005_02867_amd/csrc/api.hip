@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -67,6 +68,9 @@ struct ds_grid {
   float *e32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p32alt = nullptr, *q32 = nullptr;
   int dirmask = 0;                 // p_rgh = 0 box faces
   int batch_p = 4;
+  struct {
+    double inner_min = 2e-6;   // smallest FP32 inner relative tolerance
+  } tune;
   // pinned host mirrors
   double* h_scal = nullptr;
   SolveStatus* h_status = nullptr;   // 4 slots
@@ -181,14 +185,22 @@ size_t carve(ds_grid* g, char* base) {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Multigrid shape: damped-Jacobi sweeps, coarsest-level sweeps and the
+// smallest extent that is still coarsened (overridable for tuning through
+// DSVOF_MG_NU, DSVOF_MG_COARSE, DSVOF_MG_MINDIM).
 template <class T>
 void build_hier(MgHier<T>& H, int nx, int ny, int nz, double h, double dt) {
   H.nlev = 0;
   double hl = h;
+  int mindim = 8;
+  if (const char* e = getenv("DSVOF_MG_NU")) H.nu = std::max(1, atoi(e));
+  if (const char* e = getenv("DSVOF_MG_COARSE")) H.coarse_sweeps = std::max(2, atoi(e));
+  if (const char* e = getenv("DSVOF_MG_MINDIM")) mindim = std::max(4, atoi(e));
+  if (const char* e = getenv("DSVOF_MG_OMEGA")) H.omega = atof(e);
   for (;;) {
     Lev<T>& L = H.lev[H.nlev++];
     lev_dims(L, nx, ny, nz, dt / (hl * hl));
-    if (std::min(nx, std::min(ny, nz)) < 4 || H.nlev == MG_MAXLEV) break;
+    if (std::min(nx, std::min(ny, nz)) < mindim || H.nlev == MG_MAXLEV) break;
     nx = (nx + 1) / 2;
     ny = (ny + 1) / 2;
     nz = (nz + 1) / 2;
@@ -280,7 +292,6 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   }
   SolveStatus* so = g->status + sys;
   SolveStatus* si = g->status + 3;
-  const double inner_tol = 1e-5;
   const int max_rounds = 12;
   if ((st = init_status(g, sys, g->prm.tol, g->prm.maxit, s)) != DS_OK) return st;
   launch_resid64(L, g->b, x, g->r, so, g->partials, g->counters + CT_SOLVE0, true, s);
@@ -289,6 +300,10 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   if ((st = sync_status(g, sys, s)) != DS_OK) return st;
   int total = 0, rounds = 0, inner_fail = 0;
   while (!g->h_status[sys].done && rounds < max_rounds && !inner_fail) {
+    // Ask the FP32 solve for the reduction still needed (with a margin), but
+    // not below what FP32 arithmetic reliably attains.
+    const double need = 0.5 * g->prm.tol / std::max(g->h_status[sys].res, 1e-300);
+    const double inner_tol = std::min(0.5, std::max(g->tune.inner_min, need));
     if ((st = init_status(g, 3, inner_tol, g->prm.maxit, s)) != DS_OK) return st;
     launch_inner_init<float>(F, g->r, g->r32, g->e32, si, g->partials, g->counters + CT_SOLVE1, s);
     CgVecs<float> V{g->e32, g->r32, g->p32, g->p32alt, g->q32};
@@ -498,6 +513,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
     for (int sd = 0; sd < 2; ++sd)
       if (pressure_dirichlet(P.kind[ax * 2 + sd])) g->dirmask |= 1 << (ax * 2 + sd);
   lev_dims(g->L0, nx, ny, nz, 1.0);
+  if (const char* e = getenv("DSVOF_INNER_MIN")) g->tune.inner_min = atof(e);
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {
     if (prm->pressure_precond == 1) build_hier(g->H32, nx, ny, nz, prm->h, prm->dt);

@@ -45,7 +45,7 @@ struct MgHier {
   T* r[MG_MAXLEV] = {};   // level right-hand sides (level 0: the CG residual, not stored here)
   T* x[MG_MAXLEV] = {};   // level iterates (ping-pong with t)
   T* t[MG_MAXLEV] = {};
-  double omega = 0.8;     // damped Jacobi weight
+  double omega = 0.9;     // damped Jacobi weight
   int nu = 2;             // pre = post smoothing sweeps
   int coarse_sweeps = 16; // sweeps on the coarsest level
 };
