@@ -81,6 +81,7 @@ typedef struct ds_params {
   double kij;          /* binary interaction coefficient */
   double T_ref, p_ref; /* Clausius-Clapeyron reference point */
   double eps_int;      /* interface-cell threshold on alpha */
+  double eps_gas;      /* a cell with alpha <= eps_gas counts as gas for the adj march */
   double theta_min;    /* lower bound of the gas fraction in the species system */
   double tol;          /* relative residual tolerance of the linear solves */
   int s_max;           /* longest interface-normal march, in cell lengths */
@@ -90,7 +91,8 @@ typedef struct ds_params {
   int precision;       /* DS_PREC_*: FP64 solves, or FP32 sweeps + FP64 refinement */
   int solve_energy;    /* 0: temperature frozen (isothermal runs) */
   int evaporation;     /* 0: no evaporation source */
-  int pressure_precond; /* 0: Jacobi-PCG, 1: geometric-multigrid PCG (FP64 path) */
+  int pressure_precond; /* 0: Jacobi-PCG, 1: geometric-multigrid PCG */
+  int liquid_transport; /* 1: alpha moves with the divergence-free part of u (default); 0: with u */
 } ds_params;
 
 /* Scalars of the most recent step (or evaporation/pressure call). */
@@ -108,6 +110,8 @@ typedef struct ds_diagnostics {
   int n_interface;       /* interface cells with a nonzero gradient */
   int converged;         /* 1 if every solve met tol */
   int refinements_p;     /* outer FP64 refinement rounds of the pressure solve */
+  int iters_phi;         /* iterations of the liquid-transport potential solve */
+  double res_phi;
 } ds_diagnostics;
 
 /* Validate parameters and create a host handle for an nx*ny*nz grid
@@ -166,6 +170,18 @@ enum {
                               -2 off the interface                          */
 };
 int ds_get_internal(ds_grid* g, int which, double* dst, size_t count, void* stream);
+
+/* Measurement hook.  With timing enabled, HIP events on the caller's stream
+ * bracket every launch of the pressure solve's fine-level conjugate-gradient
+ * operator kernel (direction update p = z + beta p fused with the
+ * matrix-free product q = A p and <p, q>) that performs an iteration;
+ * ds_get_kernel_timing returns the mean duration in microseconds, the number
+ * of timed launches and the kernel's algorithmic bytes per launch (each
+ * array it streams counted once: z, p, q_coef, diag read; p, q written).
+ * Enabling resets the accumulators.  The event pool is created on first use
+ * (host-side HIP objects, no device memory). */
+int ds_set_kernel_timing(ds_grid* g, int enable);
+int ds_get_kernel_timing(const ds_grid* g, double* avg_us, long long* launches, double* bytes_per_launch);
 
 /* Message describing the last error on this handle ("" if none). */
 const char* ds_last_error(const ds_grid* g);

@@ -55,6 +55,7 @@ def geometry(alpha, prm):
       dist     (m,) centre distance int -> adj in m (0 where none)
     """
     eps = prm["eps_int"]
+    eps_gas = prm.get("eps_gas", eps)
     h = prm["h"]
     shape = alpha.shape
     alpha = alpha.detach()
@@ -80,7 +81,7 @@ def geometry(alpha, prm):
         active = ~found & ~stopped
         stopped |= active & ~inside
         t = torch.where(inside[:, None], target, torch.zeros_like(target))
-        is_gas = alpha[t[:, 0], t[:, 1], t[:, 2]] <= eps
+        is_gas = alpha[t[:, 0], t[:, 1], t[:, 2]] <= eps_gas
         hit = active & inside & is_gas
         adj[hit] = target[hit]
         found |= hit

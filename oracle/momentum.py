@@ -143,3 +143,23 @@ def project(Ustar, p, rho, prm):
             F[-1] = F[-1] + 2.0 * dt * b_[-1] * p_[-1] / h
         out.append(torch.movedim(F, 0, a))
     return out
+
+
+def solenoidal_part(U, prm, tol=None, maxit=None):
+    """Discretely divergence-free part of the face velocity field:
+    U_s = U - G phi with D G phi = D U (G: face gradient, D: divergence, the
+    same boundary kinds as the pressure: phi = 0 half a cell outside open
+    faces, no flux through walls and inlets).  Used to move the liquid
+    marker: the Stefan expansion (volume created in the gas) carries no
+    liquid.  Returns (U_s, phi, iterations)."""
+    from . import operators
+    dt, h = prm["dt"], prm["h"]
+    shape = (prm["nx"], prm["ny"], prm["nz"])
+    ones = torch.full(shape, 1.0 / dt, dtype=torch.float64)     # (dt/h^2) * (1/dt) = 1/h^2 per face
+    op = operators.pressure_operator(ones, prm)
+    b = -operators.divergence(*U, h)
+    phi, it, res, ok = operators.pcg(op, b, torch.zeros(shape, dtype=torch.float64),
+                                     prm["tol"] if tol is None else tol,
+                                     prm["maxit"] if maxit is None else maxit)
+    Us = project(U, phi, torch.full(shape, dt, dtype=torch.float64), prm)   # dt/rho = 1
+    return Us, phi, it

@@ -83,9 +83,13 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     mdot, mraw, K, geo = evaporation_source(st, prm, rho_G, D_v=D)
     # 2. liquid source
     alpha1 = st["alpha"] - dt * mdot / prm["rho_L"]
-    # 3. advection
+    # 3. advection: the liquid marker moves with the divergence-free part of u^n
+    if prm["liquid_transport"]:
+        U_liq, phi, it_phi = momentum.solenoidal_part(U, prm, tol=tol)
+    else:
+        U_liq, phi, it_phi = None, None, 0
     alpha_p, c_p, T_p, B_L, B_v = vof.advect(alpha1, st["omega"], st["T"], st["c"], *U, prm, rho_G,
-                                             T_amb=Ta, advect_T=bool(prm["solve_energy"]))
+                                             T_amb=Ta, advect_T=bool(prm["solve_energy"]), U_liq=U_liq)
     # 4. properties
     ab, rho, cp, k, theta = properties(alpha_p, prm, rho_G)
     diag = {}

@@ -60,9 +60,11 @@ def _back(axis, t):
     return torch.movedim(t, 0, axis)
 
 
-def advect(alpha1, omega, T, c, u, v, w, prm, rho_G, T_amb=None, advect_T=True):
+def advect(alpha1, omega, T, c, u, v, w, prm, rho_G, T_amb=None, advect_T=True, U_liq=None):
     """One advection step.  Returns alpha', c', T' and the boundary outflow
-    tallies (kg of liquid, kg of vapour leaving the box during dt)."""
+    tallies (kg of liquid, kg of vapour leaving the box during dt).
+    U_liq (optional): face velocities that move the liquid marker; the
+    vapour and temperature move with (u, v, w)."""
     dt, h = prm["dt"], prm["h"]
     Ta = prm["T_amb"] if T_amb is None else T_amb
     dalpha = torch.zeros_like(alpha1)
@@ -77,7 +79,11 @@ def advect(alpha1, omega, T, c, u, v, w, prm, rho_G, T_amb=None, advect_T=True):
         uf_ = _along(axis, uf)
         af = limited_face_values(a_, uf_, 0.0)
         of = limited_face_values(o_, uf_, 0.0)
-        F = uf_ * af                                  # liquid volume flux / area
+        if U_liq is None:
+            F = uf_ * af                              # liquid volume flux / area
+        else:
+            ul_ = _along(axis, U_liq[axis])
+            F = ul_ * limited_face_values(a_, ul_, 0.0)
         G = rho_G * of * (1.0 - af) * uf_             # vapour mass flux / area
         dalpha += _back(axis, F[1:] - F[:-1])
         dc += _back(axis, G[1:] - G[:-1])

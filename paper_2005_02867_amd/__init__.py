@@ -26,7 +26,7 @@ DS_OK, DS_ERR_ARG, DS_ERR_HIP, DS_ERR_NOT_CONVERGED, DS_ERR_NONFINITE, DS_ERR_ST
 FIELD_MDOT_RAW, FIELD_MDOT, FIELD_ALPHA1, FIELD_C, FIELD_USTAR, FIELD_VSTAR, FIELD_WSTAR, FIELD_ADJ = range(8)
 EXPORTS = ("ds_create_grid", "ds_destroy_grid", "ds_workspace_bytes", "ds_set_fields", "ds_get_fields",
            "ds_step", "ds_solve_pressure", "ds_evaporation_rate", "ds_droplet_volume", "ds_get_diagnostics",
-           "ds_get_internal", "ds_last_error")
+           "ds_get_internal", "ds_last_error", "ds_set_kernel_timing", "ds_get_kernel_timing")
 
 
 class Params(C.Structure):
@@ -39,10 +39,12 @@ class Params(C.Structure):
         ("x0", C.c_double * 3),
         ("Tc", C.c_double), ("Pc", C.c_double), ("acentric", C.c_double),
         ("Tc_G", C.c_double), ("Pc_G", C.c_double), ("acentric_G", C.c_double), ("kij", C.c_double),
-        ("T_ref", C.c_double), ("p_ref", C.c_double), ("eps_int", C.c_double), ("theta_min", C.c_double),
+        ("T_ref", C.c_double), ("p_ref", C.c_double), ("eps_int", C.c_double), ("eps_gas", C.c_double),
+        ("theta_min", C.c_double),
         ("tol", C.c_double),
         ("s_max", C.c_int), ("maxit", C.c_int), ("eq_model", C.c_int), ("bc_mode", C.c_int),
         ("precision", C.c_int), ("solve_energy", C.c_int), ("evaporation", C.c_int), ("pressure_precond", C.c_int),
+        ("liquid_transport", C.c_int),
     ]
 
 
@@ -54,6 +56,7 @@ class Diagnostics(C.Structure):
         ("res_T", C.c_double), ("res_omega", C.c_double), ("res_p", C.c_double), ("rho_G", C.c_double),
         ("iters_T", C.c_int), ("iters_omega", C.c_int), ("iters_p", C.c_int),
         ("n_interface", C.c_int), ("converged", C.c_int), ("refinements_p", C.c_int),
+        ("iters_phi", C.c_int), ("res_phi", C.c_double),
     ]
 
 
@@ -70,6 +73,8 @@ _lib.ds_evaporation_rate.argtypes = [_P, C.POINTER(C.c_double), _P, _P]
 _lib.ds_droplet_volume.argtypes = [_P, C.POINTER(C.c_double), _P]
 _lib.ds_get_diagnostics.argtypes = [_P, C.POINTER(Diagnostics)]
 _lib.ds_get_internal.argtypes = [_P, C.c_int, _P, C.c_size_t, _P]
+_lib.ds_set_kernel_timing.argtypes = [_P, C.c_int]
+_lib.ds_get_kernel_timing.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
 _lib.ds_last_error.argtypes = [_P]
 _lib.ds_last_error.restype = C.c_char_p
 
@@ -94,7 +99,12 @@ def _check(handle, code):
 def make_params(prm: dict) -> Params:
     P = Params()
     for name, ctype in Params._fields_:
-        val = prm.get(name, 1) if name == "pressure_precond" else prm[name]
+        if name in ("pressure_precond", "liquid_transport"):
+            val = prm.get(name, 1)
+        elif name == "eps_gas":
+            val = prm.get(name, prm["eps_int"])
+        else:
+            val = prm[name]
         if name in ("g", "x0"):
             setattr(P, name, (C.c_double * 3)(*[float(x) for x in val]))
         else:
@@ -175,6 +185,18 @@ def get_internal(h, which, out):
     _check(h, _lib.ds_get_internal(h, int(which), _dptr(out), out.numel(), _stream()))
 
 
+def set_kernel_timing(h, enable=True):
+    _check(h, _lib.ds_set_kernel_timing(h, 1 if enable else 0))
+
+
+def get_kernel_timing(h):
+    avg = C.c_double()
+    cnt = C.c_longlong()
+    nb = C.c_double()
+    _check(h, _lib.ds_get_kernel_timing(h, C.byref(avg), C.byref(cnt), C.byref(nb)))
+    return dict(avg_us=avg.value, launches=cnt.value, bytes_per_launch=nb.value)
+
+
 # ------------------------------------------------------------ convenience
 class Grid:
     """A handle plus its torch-allocated workspace on the current CUDA device."""
@@ -233,6 +255,12 @@ class Grid:
 
     def diagnostics(self):
         return get_diagnostics(self.h)
+
+    def set_kernel_timing(self, enable=True):
+        set_kernel_timing(self.h, enable)
+
+    def kernel_timing(self):
+        return get_kernel_timing(self.h)
 
     def internal(self, which):
         s = self.shapes()

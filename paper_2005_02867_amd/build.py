@@ -1,6 +1,8 @@
 """Build the dsvof HIP library (gfx950) in-tree: paper_2005_02867_amd/libdsvof.so.
 
-    python -m paper_2005_02867_amd.build
+    python paper_2005_02867_amd/build.py
+
+(Run by path: importing the package itself loads the library.)
 """
 from __future__ import annotations
 

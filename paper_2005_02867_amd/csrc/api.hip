@@ -61,6 +61,7 @@ struct ds_grid {
   double* scal = nullptr;
   SolveStatus* status = nullptr;   // T, omega, p, inner FP32 solve
   double* p_alt = nullptr;         // second CG direction buffer
+  double* phi = nullptr;           // potential of the divergent part of u (warm start kept)
   MgHier<double> H64;
   MgHier<float> H32;
   Lev<double> L0;                  // fine-level dimensions and tiles (operator pointers set per solve)
@@ -71,6 +72,13 @@ struct ds_grid {
   struct {
     double inner_min = 2e-6;   // smallest FP32 inner relative tolerance
   } tune;
+  // live timing of the pressure solve's fine-level operator kernel
+  static constexpr int NEV = 256;
+  bool timing = false;
+  hipEvent_t ev[2 * NEV] = {};
+  double t_sum_ms = 0.0;
+  long long t_count = 0;
+  double t_bytes = 0.0;
   // pinned host mirrors
   double* h_scal = nullptr;
   SolveStatus* h_status = nullptr;   // 4 slots
@@ -144,6 +152,7 @@ size_t carve(ds_grid* g, char* base) {
   g->scal = L.take<double>(base, SC_COUNT);
   g->status = L.take<SolveStatus>(base, 4);
   g->p_alt = L.take<double>(base, n);
+  g->phi = L.take<double>(base, n);
   // FP64 multigrid levels (level 0 uses qc/diag of the pressure system)
   MgHier<double>& H = g->H64;
   H.lev[0].qc = g->qc;
@@ -222,6 +231,19 @@ int init_status(ds_grid* g, int slot, double tol, int maxit, hipStream_t s) {
   return DS_OK;
 }
 
+// After a batch sync: add the durations of the operator launches that did
+// work (the first `did` of the batch; later ones returned at once).
+void accumulate_timing(ds_grid* g, int did, double bytes_per_launch) {
+  for (int t = 0; t < did && t < ds_grid::NEV; ++t) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g->ev[2 * t], g->ev[2 * t + 1]) == hipSuccess) {
+      g->t_sum_ms += ms;
+      g->t_count += 1;
+      g->t_bytes = bytes_per_launch;
+    }
+  }
+}
+
 // Iterations enqueued between host convergence tests: about half of the
 // previous solve's count, so most solves finish in two or three batches.
 int& batch_of(ds_grid* g, int sys) { return sys == 2 ? g->batch_p : g->batch[sys]; }
@@ -252,13 +274,18 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
     double* z = nullptr;
     cg_start(L, H, V, &z, ss, g->partials, g->counters + CT_SOLVE0, s);
     bool first = true;
+    const bool timed = g->timing && H;
     while (!g->h_status[sys].done) {
-      for (int t = 0; t < batch_of(g, sys); ++t) {
-        cg_iteration(L, H, V, &z, ss, g->partials, g->counters + CT_SOLVE0, first, s);
+      const int it0 = g->h_status[sys].it;
+      const int m = timed ? std::min(batch_of(g, sys), (int)ds_grid::NEV) : batch_of(g, sys);
+      for (int t = 0; t < m; ++t) {
+        cg_iteration(L, H, V, &z, ss, g->partials, g->counters + CT_SOLVE0, first, s,
+                     timed ? g->ev[2 * t] : nullptr, timed ? g->ev[2 * t + 1] : nullptr);
         first = false;
       }
       HIPCHK(g, hipGetLastError());
       if ((st = sync_status(g, sys, s)) != DS_OK) return st;
+      if (timed) accumulate_timing(g, g->h_status[sys].it - it0, 48.0 * (double)g->n);
     }
   }
   const SolveStatus& h = g->h_status[sys];
@@ -306,17 +333,24 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     const double inner_tol = std::min(0.5, std::max(g->tune.inner_min, need));
     if ((st = init_status(g, 3, inner_tol, g->prm.maxit, s)) != DS_OK) return st;
     launch_inner_init<float>(F, g->r, g->r32, g->e32, si, g->partials, g->counters + CT_SOLVE1, s);
+    g->h_status[3].it = 0;
+    g->h_status[3].done = 0;
     CgVecs<float> V{g->e32, g->r32, g->p32, g->p32alt, g->q32};
     float* z = nullptr;
     cg_start(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, s);
     bool first = true;
+    const bool timed = g->timing && H;
     do {
-      for (int t = 0; t < batch_of(g, sys); ++t) {
-        cg_iteration(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, first, s);
+      const int it0 = g->h_status[3].it;
+      const int m = timed ? std::min(batch_of(g, sys), (int)ds_grid::NEV) : batch_of(g, sys);
+      for (int t = 0; t < m; ++t) {
+        cg_iteration(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, first, s,
+                     timed ? g->ev[2 * t] : nullptr, timed ? g->ev[2 * t + 1] : nullptr);
         first = false;
       }
       HIPCHK(g, hipGetLastError());
       if ((st = sync_status(g, 3, s)) != DS_OK) return st;
+      if (timed) accumulate_timing(g, g->h_status[3].it - it0, 24.0 * (double)g->n);
     } while (!g->h_status[3].done);
     total += g->h_status[3].it;
     inner_fail = g->h_status[3].done == 2;
@@ -370,9 +404,18 @@ int one_step(ds_grid* g, hipStream_t s) {
   D.fuel_mass_before = g->fuel_mass_prev;
   // 1-2. evaporation source and liquid source
   if ((st = evaporation_source(g, s)) != DS_OK) return st;
-  // 3. advection of alpha1, c, T with u^n
-  launch_advect(P, g->a1, g->omega, g->T, g->c, g->u, g->v, g->w, g->a_new, g->c_new, g->T_new,
-                g->partials, g->counters + CT_ADV, g->scal, s);
+  // 3. advection of alpha1 with the divergence-free part of u^n, c and T with u^n
+  if (g->prm.liquid_transport) {
+    launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s);
+    st = solve(g, 2, P.dt / (P.h * P.h), g->phi, s, &D.iters_phi, &D.res_phi);
+    if (st == DS_ERR_NOT_CONVERGED) rc = st;
+    else if (st != DS_OK) return st;
+  } else {
+    D.iters_phi = 0;
+    D.res_phi = 0.0;
+  }
+  launch_advect(P, g->a1, g->omega, g->T, g->c, g->u, g->v, g->w, g->prm.liquid_transport ? g->phi : nullptr,
+                g->a_new, g->c_new, g->T_new, g->partials, g->counters + CT_ADV, g->scal, s);
   // 5a. energy (warm start T')
   if (P.solve_energy) {
     launch_energy_setup(P, g->a_new, g->T_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, s);
@@ -438,11 +481,11 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (!finite_pos(prm->h) || !finite_pos(prm->dt) || !finite_pos(prm->p) || !finite_pos(prm->T_amb) ||
       !finite_pos(prm->rho_L) || !finite_pos(prm->cp_L) || !finite_pos(prm->cp_G) || prm->k_L < 0 ||
       prm->k_G < 0 || !finite_pos(prm->D_v) || !finite_pos(prm->M_v) || !finite_pos(prm->M_G) ||
-      !finite_pos(prm->T_ref) || !finite_pos(prm->p_ref) || !(prm->eps_int > 0 && prm->eps_int < 0.5) ||
+      !finite_pos(prm->T_ref) || !finite_pos(prm->p_ref) || !(prm->eps_int > 0 && prm->eps_int < 0.5) || !(prm->eps_gas >= prm->eps_int && prm->eps_gas <= 0.5) ||
       !finite_pos(prm->theta_min) || !(prm->tol > 0) || prm->maxit < 1 || prm->s_max < 1 ||
       prm->eq_model < 0 || prm->eq_model > 1 || prm->bc_mode < 0 || prm->bc_mode > 2 ||
       prm->precision < 0 || prm->precision > 1 || !finite_pos(prm->r_fib) || prm->pressure_precond < 0 ||
-      prm->pressure_precond > 1)
+      prm->pressure_precond > 1 || prm->liquid_transport < 0 || prm->liquid_transport > 1)
     return DS_ERR_ARG;
   if (prm->eq_model == DS_EQ_PENG_ROBINSON &&
       (!finite_pos(prm->Tc) || !finite_pos(prm->Pc) || !finite_pos(prm->Tc_G) || !finite_pos(prm->Pc_G)))
@@ -490,6 +533,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   P.T_ref = prm->T_ref;
   P.p_ref = prm->p_ref;
   P.eps = prm->eps_int;
+  P.eps_gas = prm->eps_gas;
   P.theta_min = prm->theta_min;
   P.eq_model = prm->eq_model;
   P.solve_energy = prm->solve_energy;
@@ -532,6 +576,8 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
 
 int ds_destroy_grid(ds_grid* g) {
   if (!g) return DS_ERR_ARG;
+  for (int e = 0; e < 2 * ds_grid::NEV; ++e)
+    if (g->ev[e]) (void)hipEventDestroy(g->ev[e]);
   if (g->h_scal) (void)hipHostFree(g->h_scal);
   if (g->h_status) (void)hipHostFree(g->h_status);
   delete g;
@@ -563,6 +609,7 @@ int ds_set_fields(ds_grid* g, const double* alpha, const double* T, const double
   HIPCHK(g, hipMemsetAsync(g->scal, 0, SC_COUNT * sizeof(double), s));
   HIPCHK(g, hipMemsetAsync(g->mdot, 0, nb, s));
   HIPCHK(g, hipMemsetAsync(g->mraw, 0, nb, s));
+  HIPCHK(g, hipMemsetAsync(g->phi, 0, nb, s));
   launch_xi(g->dp, g->xi, s);
   // conservative vapour variable c = rho_G theta omega (gas fraction only)
   launch_c_from_omega(g->dp, g->alpha, g->omega, g->c, s);
@@ -681,6 +728,24 @@ int ds_get_internal(ds_grid* g, int which, double* dst, size_t count, void* stre
   if (which == DS_FIELD_ADJ) launch_int_to_double(g->adj, dst, g->n, s);
   else HIPCHK(g, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(g, hipGetLastError());
+  return DS_OK;
+}
+
+int ds_set_kernel_timing(ds_grid* g, int enable) {
+  if (!g) return DS_ERR_ARG;
+  if (enable && !g->ev[0])
+    for (int e = 0; e < 2 * ds_grid::NEV; ++e) HIPCHK(g, hipEventCreate(&g->ev[e]));
+  g->timing = enable != 0;
+  g->t_sum_ms = 0.0;
+  g->t_count = 0;
+  return DS_OK;
+}
+
+int ds_get_kernel_timing(const ds_grid* g, double* avg_us, long long* launches, double* bytes_per_launch) {
+  if (!g) return DS_ERR_ARG;
+  if (avg_us) *avg_us = g->t_count ? 1e3 * g->t_sum_ms / (double)g->t_count : 0.0;
+  if (launches) *launches = g->t_count;
+  if (bytes_per_launch) *bytes_per_launch = g->t_bytes;
   return DS_OK;
 }
 

@@ -23,7 +23,7 @@ struct DevParams {
   double g[3], x0[3];
   double xi0, Df, r_fib, w_in;
   double Tc, Pc, om, Tc_G, Pc_G, om_G, kij, T_ref, p_ref;
-  double eps, theta_min, rho_G;
+  double eps, eps_gas, theta_min, rho_G;
   int kind[6];                      // box face kinds, index axis*2 + side
   int eq_model, solve_energy, evaporation;
 };

@@ -26,9 +26,11 @@ void launch_interface(const DevParams& P, const double* alpha, const double* T, 
 void launch_source(const DevParams& P, const double* alpha, const double* mraw, const double* scal,
                    double* mdot, double* a1, hipStream_t s);
 void launch_advect(const DevParams& P, const double* a1, const double* omega, const double* T,
-                   const double* c, const double* u, const double* v, const double* w, double* a_new,
-                   double* c_new, double* T_new, double* partials, unsigned* counter, double* scal,
+                   const double* c, const double* u, const double* v, const double* w, const double* phi,
+                   double* a_new, double* c_new, double* T_new, double* partials, unsigned* counter, double* scal,
                    hipStream_t s);
+void launch_div_setup(const DevParams& P, const double* u, const double* v, const double* w, double* qc,
+                      double* diag, double* b, hipStream_t s);
 void launch_energy_setup(const DevParams& P, const double* a_new, const double* T_prime,
                          const double* mdot, const double* u, const double* v, const double* w,
                          double* qc, double* diag, double* b, hipStream_t s);

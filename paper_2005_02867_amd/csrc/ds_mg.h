@@ -69,9 +69,11 @@ void mg_setup_levels(MgHier<T>& H, int dirmask, hipStream_t s);
 template <class T>
 void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
               unsigned* counters, hipStream_t s);
+// ev0/ev1 (may be null): events recorded just before and after the operator
+// kernel (direction update + matrix-free product) of a multigrid iteration.
 template <class T>
 void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
-                  unsigned* counters, bool first, hipStream_t s);
+                  unsigned* counters, bool first, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // r = b - A x (FP64), ||b|| (if set_bnorm), ||r|| -> status (done if ||r|| <= tol ||b||).
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,

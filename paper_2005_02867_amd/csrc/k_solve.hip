@@ -21,6 +21,7 @@
 // integer division per cell.  XCD x (blocks are dealt to the 8 XCDs
 // round-robin) owns one contiguous eighth of the tiles, i.e. a slab of
 // x-planes, so stencil neighbours are served from that XCD's L2.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -425,10 +426,16 @@ void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* s
 
 template <class T>
 void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
-                  unsigned* counters, bool first, hipStream_t s) {
+                  unsigned* counters, bool first, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int nb = tile_blocks(L.ntiles);
   if (H) {
-    k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(L, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+    if (ev0) {
+      // events attached to the dispatch itself: kernel start and end times
+      hipExtLaunchKernelGGL(k_cg_dir_spmv<T, false>, dim3(nb), dim3(BLOCK), 0, s, ev0, ev1, 0, L, (const T*)*z,
+                            (const T*)V.r, (const T*)V.p, V.p_alt, V.q, st, partials, counters, (int)first);
+    } else {
+      k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(L, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+    }
     std::swap(V.p, V.p_alt);
     k_cg_update<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
     mg_vcycle(*H, 0, V.r, st, partials, counters + 2, false, true, s, z);
@@ -466,9 +473,9 @@ template void cg_start<double>(const Lev<double>&, MgHier<double>*, CgVecs<doubl
 template void cg_start<float>(const Lev<float>&, MgHier<float>*, CgVecs<float>&, float**, SolveStatus*, double*,
                               unsigned*, hipStream_t);
 template void cg_iteration<double>(const Lev<double>&, MgHier<double>*, CgVecs<double>&, double**, SolveStatus*,
-                                   double*, unsigned*, bool, hipStream_t);
+                                   double*, unsigned*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void cg_iteration<float>(const Lev<float>&, MgHier<float>*, CgVecs<float>&, float**, SolveStatus*,
-                                  double*, unsigned*, bool, hipStream_t);
+                                  double*, unsigned*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_inner_init<float>(const Lev<float>&, const double*, float*, float*, SolveStatus*, double*,
                                        unsigned*, hipStream_t);
 template void launch_add_correction<float>(const Lev<float>&, double*, const float*, hipStream_t);

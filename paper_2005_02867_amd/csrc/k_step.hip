@@ -73,7 +73,7 @@ __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const
           tj = (int)floor(__dadd_rn(bj, __dmul_rn(sd, ny)));
           tk = (int)floor(__dadd_rn(bk, __dmul_rn(sd, nz)));
           if (ti < 0 || tj < 0 || tk < 0 || ti >= P.nx || tj >= P.ny || tk >= P.nz) break;
-          if (alpha[cidx(P, ti, tj, tk)] <= P.eps) {
+          if (alpha[cidx(P, ti, tj, tk)] <= P.eps_gas) {
             hit = (int)cidx(P, ti, tj, tk);
             break;
           }
@@ -153,10 +153,23 @@ __device__ __forceinline__ double face_value(const double* __restrict__ phi, lon
   return C + 0.5 * psi * den;
 }
 
+// Liquid-marker face velocity: the divergence-free part u - G phi (phi = 0
+// half a cell outside open faces; walls and inlets keep their value).
+__device__ __forceinline__ double liquid_face_u(const DevParams& P, const double* __restrict__ phi, double uf,
+                                                long long line, long long st, int f, int na, int ax) {
+  if (!phi) return uf;
+  if (f == 0 || f == na) {
+    if (!pressure_dirichlet(P.kind[ax * 2 + (f == 0 ? 0 : 1)])) return uf;
+    const double pc = phi[line + (long long)(f == 0 ? 0 : na - 1) * st];
+    return f == 0 ? uf - 2.0 * pc / P.h : uf + 2.0 * pc / P.h;
+  }
+  return uf - (phi[line + (long long)f * st] - phi[line + (long long)(f - 1) * st]) / P.h;
+}
+
 __global__ void k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
                          const double* __restrict__ T, const double* __restrict__ c,
                          const double* __restrict__ u, const double* __restrict__ v,
-                         const double* __restrict__ w, double* __restrict__ a_new,
+                         const double* __restrict__ w, const double* __restrict__ phi, double* __restrict__ a_new,
                          double* __restrict__ c_new, double* __restrict__ T_new, double* partials,
                          unsigned* counter, double* scal) {
   long long b0, b1;
@@ -183,7 +196,12 @@ __global__ void k_advect(DevParams P, const double* __restrict__ a1, const doubl
         const double ufv = uf[ax][sd];
         const double af = face_value(a1, line[ax], st[ax], f, nn[ax], ufv, 0.0);
         const double of = face_value(omega, line[ax], st[ax], f, nn[ax], ufv, 0.0);
-        F[sd] = ufv * af;
+        if (phi) {
+          const double ul = liquid_face_u(P, phi, ufv, line[ax], st[ax], f, nn[ax], ax);
+          F[sd] = ul * face_value(a1, line[ax], st[ax], f, nn[ax], ul, 0.0);
+        } else {
+          F[sd] = ufv * af;
+        }
         G[sd] = P.rho_G * of * (1.0 - af) * ufv;
         if (P.solve_energy) {
           const double Tf = face_value(T, line[ax], st[ax], f, nn[ax], ufv, P.T_amb);
@@ -458,6 +476,35 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
   }
 }
 
+// ---------------------------------------------------------------- liquid transport velocity
+// System D G phi = D u for the divergence-free part u - G phi of the face
+// velocities (same boundary kinds as the pressure), written in the pressure
+// operator's form with q = 1/dt: (dt/h^2)(1/dt) = 1/h^2 per face.
+__global__ void k_div_setup(DevParams P, const double* __restrict__ u, const double* __restrict__ v,
+                            const double* __restrict__ w, double* __restrict__ qc, double* __restrict__ diag,
+                            double* __restrict__ b) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  const double ih2 = 1.0 / (P.h * P.h);
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+    int i, j, k;
+    decode(P, c, i, j, k);
+    double d = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        if (nbr(P, ax, sd, i, j, k) >= 0) d += ih2;
+        else if (pressure_dirichlet(P.kind[ax * 2 + sd])) d += 2.0 * ih2;
+      }
+    const double div = ((u[uidx(P, i + 1, j, k)] - u[uidx(P, i, j, k)]) + (v[vidx(P, i, j + 1, k)] - v[vidx(P, i, j, k)]) +
+                        (w[widx(P, i, j, k + 1)] - w[widx(P, i, j, k)])) / P.h;
+    qc[c] = 1.0 / P.dt;
+    diag[c] = d;
+    b[c] = -div;
+  }
+}
+
 // ---------------------------------------------------------------- S11
 template <int AX>
 __global__ void k_project(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
@@ -564,10 +611,11 @@ void launch_source(const DevParams& P, const double* alpha, const double* mraw, 
   k_source<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, alpha, mraw, scal, mdot, a1);
 }
 void launch_advect(const DevParams& P, const double* a1, const double* omega, const double* T,
-                   const double* c, const double* u, const double* v, const double* w, double* a_new,
-                   double* c_new, double* T_new, double* partials, unsigned* counter, double* scal,
+                   const double* c, const double* u, const double* v, const double* w, const double* phi,
+                   double* a_new, double* c_new, double* T_new, double* partials, unsigned* counter, double* scal,
                    hipStream_t s) {
-  k_advect<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a1, omega, T, c, u, v, w, a_new, c_new, T_new, partials, counter, scal);
+  k_advect<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a1, omega, T, c, u, v, w, phi, a_new, c_new, T_new, partials, counter,
+                                              scal);
 }
 void launch_energy_setup(const DevParams& P, const double* a_new, const double* T_prime,
                          const double* mdot, const double* u, const double* v, const double* w,
@@ -598,6 +646,10 @@ void launch_pressure_setup(const DevParams& P, const double* a_new, const double
                            const double* us, const double* vs, const double* ws, double* qc,
                            double* diag, double* b, hipStream_t s) {
   k_pressure_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, mdot, us, vs, ws, qc, diag, b);
+}
+void launch_div_setup(const DevParams& P, const double* u, const double* v, const double* w, double* qc,
+                      double* diag, double* b, hipStream_t s) {
+  k_div_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, u, v, w, qc, diag, b);
 }
 void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
                     const double* vs, const double* ws, double* u, double* v, double* w,

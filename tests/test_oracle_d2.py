@@ -1,0 +1,48 @@
+"""The d^2 law (Section 4.1: after the initial transient the squared
+diameter falls linearly in time) for a motionless droplet with zero gravity
+and no centripetal force, isothermal at 300 K and 1 bar, far-field
+boundaries: the oracle's d^2 is linear in time and its slope, and the
+instantaneous rate, match the classical quasi-steady Stefan result
+    mdot = 4 pi rho_G D a ln(1 + B_M) * C_box/C_inf,  B_M = w_s/(1 - w_s),
+    d(d^2)/dt = -8 rho_G D ln(1 + B_M)/rho_L * C_box/C_inf,
+where C_box/C_inf is the capacitance of the sphere in the grounded cube
+(tests/golden/cube_capacitance.json, an independent Laplace solve).
+
+At 32^3 (R/h = 4) the diffuse interface costs a few percent (the
+volume-equivalent radius of the 1.5-cell tanh profile exceeds the alpha = 1/2
+radius); the bar is 12%.  The GPU path, equal to the oracle to 1e-9 per step,
+checks the same law at 64^3-128^3 with tighter bars."""
+import math
+
+import numpy as np
+
+import workloads as W
+from oracle import step as S
+from tests.d2_case import d2_case
+
+
+def test_d2_law_oracle_32cubed():
+    prm, ref = d2_case(32)
+    f = W.initial_fields(prm, D0=ref["D0"])
+    st = S.to_state(f, prm)
+    steps = 150
+    t, d2, rate = [], [], []
+    for k in range(steps):
+        st, d = S.step(st, prm)
+        t.append((k + 1) * prm["dt"])
+        d2.append((6.0 * d["volume"] / math.pi) ** (2.0 / 3.0))
+        a = (3.0 * d["volume"] / (4.0 * math.pi)) ** (1.0 / 3.0)
+        rate.append(d["mdot_total"] / ref["mdot_qs"](a))
+        assert d["alpha_max"] > 0.98            # the droplet core stays liquid
+    t = np.array(t)
+    d2 = np.array(d2)
+    half = steps // 2
+    A = np.polyfit(t[half:], d2[half:], 1)
+    resid = d2[half:] - np.polyval(A, t[half:])
+    R2 = 1.0 - resid.var() / d2[half:].var()
+    a_mid = 0.5 * math.sqrt(d2[3 * steps // 4])
+    K_expect = ref["Kd2"] * ref["box_ratio"](a_mid)
+    print("R2", R2, "slope/K", -A[0] / K_expect, "rate/qs", rate[-1])
+    assert R2 >= 0.999
+    assert abs(-A[0] / K_expect - 1.0) < 0.12
+    assert abs(rate[-1] - 1.0) < 0.12

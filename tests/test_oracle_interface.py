@@ -24,11 +24,12 @@ def _planar(nx=24, ny=3, nz=3, width=1.5, x_int=None, flip=False, **kw):
     return prm, torch.tensor(alpha)
 
 
-@pytest.mark.parametrize("flip", [False, True])
-def test_planar_interface_by_hand(flip):
-    """Liquid slab: normals are exactly -+x, adj is the first gas cell along
-    the normal, and mdot_raw = rho_G D (w_sat(T_int) - w_adj)/d * |dalpha/dx|."""
-    prm, alpha = _planar(flip=flip)
+@pytest.mark.parametrize("flip,eps_gas", [(False, 0.5), (True, 0.5), (False, 1e-3), (True, 0.1)])
+def test_planar_interface_by_hand(flip, eps_gas):
+    """Liquid slab: normals are exactly -+x, adj is the first gas cell
+    (alpha <= eps_gas) along the normal, and
+    mdot_raw = rho_G D (w_sat(T_int) - w_adj)/d * |dalpha/dx|."""
+    prm, alpha = _planar(flip=flip, eps_gas=eps_gas)
     nx, ny, nz, h = prm["nx"], prm["ny"], prm["nz"], prm["h"]
     rng = np.random.default_rng(0)
     T = torch.tensor(rng.uniform(290, 340, (nx, ny, nz)))
@@ -40,6 +41,7 @@ def test_planar_interface_by_hand(flip):
     geo = I.geometry(alpha, prm)
     mraw = I.raw_evaporation(alpha, T, omega, u, v, w, geo, prm, rho_G)
     eps = prm["eps_int"]
+    eps_gas = prm["eps_gas"]
     a = alpha[:, 0, 0].numpy()
     expect = np.zeros((nx, ny, nz))
     for i in range(nx):
@@ -49,7 +51,7 @@ def test_planar_interface_by_hand(flip):
         hi = a[i + 1] if i < nx - 1 else 0.0
         step = 1 if hi < lo else -1            # towards the gas
         j = i + step
-        while 0 <= j < nx and a[j] > eps:
+        while 0 <= j < nx and a[j] > eps_gas:
             j += step
         assert 0 <= j < nx and abs(j - i) <= prm["s_max"]
         d = abs(j - i) * h
