@@ -84,6 +84,7 @@ typedef struct ds_params {
   double eps_gas;      /* a cell with alpha <= eps_gas counts as gas for the adj march */
   double theta_min;    /* lower bound of the gas fraction in the species system */
   double tol;          /* relative residual tolerance of the linear solves */
+  double tol_phi;      /* tolerance of the liquid-transport potential solve */
   int s_max;           /* longest interface-normal march, in cell lengths */
   int maxit;           /* iteration cap of each linear solve */
   int eq_model;        /* DS_EQ_* */
@@ -182,6 +183,13 @@ int ds_get_internal(ds_grid* g, int which, double* dst, size_t count, void* stre
  * (host-side HIP objects, no device memory). */
 int ds_set_kernel_timing(ds_grid* g, int enable);
 int ds_get_kernel_timing(const ds_grid* g, double* avg_us, long long* launches, double* bytes_per_launch);
+
+/* Measurement hook: replays the same operator kernel `reps` times back to
+ * back on the current pressure system (the last one assembled by a step or
+ * pressure solve, in the handle's precision) between two events on `stream`
+ * and returns the mean duration (us) and the algorithmic bytes per launch.
+ * Only solver scratch vectors are written; the state is untouched. */
+int ds_time_operator_kernel(ds_grid* g, int reps, double* avg_us, double* bytes_per_launch, void* stream);
 
 /* Message describing the last error on this handle ("" if none). */
 const char* ds_last_error(const ds_grid* g);

@@ -85,7 +85,7 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     alpha1 = st["alpha"] - dt * mdot / prm["rho_L"]
     # 3. advection: the liquid marker moves with the divergence-free part of u^n
     if prm["liquid_transport"]:
-        U_liq, phi, it_phi = momentum.solenoidal_part(U, prm, tol=tol)
+        U_liq, phi, it_phi = momentum.solenoidal_part(U, prm, tol=prm["tol_phi"])
     else:
         U_liq, phi, it_phi = None, None, 0
     alpha_p, c_p, T_p, B_L, B_v = vof.advect(alpha1, st["omega"], st["T"], st["c"], *U, prm, rho_G,

@@ -26,7 +26,8 @@ DS_OK, DS_ERR_ARG, DS_ERR_HIP, DS_ERR_NOT_CONVERGED, DS_ERR_NONFINITE, DS_ERR_ST
 FIELD_MDOT_RAW, FIELD_MDOT, FIELD_ALPHA1, FIELD_C, FIELD_USTAR, FIELD_VSTAR, FIELD_WSTAR, FIELD_ADJ = range(8)
 EXPORTS = ("ds_create_grid", "ds_destroy_grid", "ds_workspace_bytes", "ds_set_fields", "ds_get_fields",
            "ds_step", "ds_solve_pressure", "ds_evaporation_rate", "ds_droplet_volume", "ds_get_diagnostics",
-           "ds_get_internal", "ds_last_error", "ds_set_kernel_timing", "ds_get_kernel_timing")
+           "ds_get_internal", "ds_last_error", "ds_set_kernel_timing", "ds_get_kernel_timing",
+           "ds_time_operator_kernel")
 
 
 class Params(C.Structure):
@@ -41,7 +42,7 @@ class Params(C.Structure):
         ("Tc_G", C.c_double), ("Pc_G", C.c_double), ("acentric_G", C.c_double), ("kij", C.c_double),
         ("T_ref", C.c_double), ("p_ref", C.c_double), ("eps_int", C.c_double), ("eps_gas", C.c_double),
         ("theta_min", C.c_double),
-        ("tol", C.c_double),
+        ("tol", C.c_double), ("tol_phi", C.c_double),
         ("s_max", C.c_int), ("maxit", C.c_int), ("eq_model", C.c_int), ("bc_mode", C.c_int),
         ("precision", C.c_int), ("solve_energy", C.c_int), ("evaporation", C.c_int), ("pressure_precond", C.c_int),
         ("liquid_transport", C.c_int),
@@ -75,6 +76,7 @@ _lib.ds_get_diagnostics.argtypes = [_P, C.POINTER(Diagnostics)]
 _lib.ds_get_internal.argtypes = [_P, C.c_int, _P, C.c_size_t, _P]
 _lib.ds_set_kernel_timing.argtypes = [_P, C.c_int]
 _lib.ds_get_kernel_timing.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
+_lib.ds_time_operator_kernel.argtypes = [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]
 _lib.ds_last_error.argtypes = [_P]
 _lib.ds_last_error.restype = C.c_char_p
 
@@ -103,6 +105,8 @@ def make_params(prm: dict) -> Params:
             val = prm.get(name, 1)
         elif name == "eps_gas":
             val = prm.get(name, prm["eps_int"])
+        elif name == "tol_phi":
+            val = prm.get(name, prm["tol"])
         else:
             val = prm[name]
         if name in ("g", "x0"):
@@ -197,6 +201,13 @@ def get_kernel_timing(h):
     return dict(avg_us=avg.value, launches=cnt.value, bytes_per_launch=nb.value)
 
 
+def time_operator_kernel(h, reps=50):
+    us = C.c_double()
+    nb = C.c_double()
+    _check(h, _lib.ds_time_operator_kernel(h, int(reps), C.byref(us), C.byref(nb), _stream()))
+    return dict(avg_us=us.value, bytes_per_launch=nb.value, reps=int(reps))
+
+
 # ------------------------------------------------------------ convenience
 class Grid:
     """A handle plus its torch-allocated workspace on the current CUDA device."""
@@ -261,6 +272,9 @@ class Grid:
 
     def kernel_timing(self):
         return get_kernel_timing(self.h)
+
+    def time_operator_kernel(self, reps=50):
+        return time_operator_kernel(self.h, reps)
 
     def internal(self, which):
         s = self.shapes()

@@ -251,7 +251,7 @@ int& batch_of(ds_grid* g, int sys) { return sys == 2 ? g->batch_p : g->batch[sys
 // FP64 preconditioned CG on the system in qc/diag (scale sc), right-hand side
 // b, warm start in x.  sys: 0 = energy, 1 = species (Jacobi), 2 = pressure
 // (multigrid when enabled, Jacobi otherwise).
-int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res) {
+int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
   int st;
   Lev<double> L = g->L0;
   L.sc = sc;
@@ -264,7 +264,7 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
     mg_setup_levels(*H, g->dirmask, s);
   }
   SolveStatus* ss = g->status + sys;
-  if ((st = init_status(g, sys, g->prm.tol, g->prm.maxit, s)) != DS_OK) return st;
+  if ((st = init_status(g, sys, tol, g->prm.maxit, s)) != DS_OK) return st;
   launch_resid64(L, g->b, x, g->r, ss, g->partials, g->counters + CT_SOLVE0, true, s);
   launch_zero_if_flagged(x, g->n, ss, s);
   HIPCHK(g, hipGetLastError());
@@ -299,7 +299,7 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
 // Precision form of one solve: FP64 residual r = b - A x; FP32 preconditioned
 // CG for the correction A e = r to an inner tolerance (FP32 vectors, operator
 // and sweeps, FP64 dot products); x += e in FP64; repeat until ||r|| <= tol ||b||.
-int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res) {
+int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
   int st;
   Lev<double> L = g->L0;
   L.sc = sc;
@@ -320,7 +320,7 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   SolveStatus* so = g->status + sys;
   SolveStatus* si = g->status + 3;
   const int max_rounds = 12;
-  if ((st = init_status(g, sys, g->prm.tol, g->prm.maxit, s)) != DS_OK) return st;
+  if ((st = init_status(g, sys, tol, g->prm.maxit, s)) != DS_OK) return st;
   launch_resid64(L, g->b, x, g->r, so, g->partials, g->counters + CT_SOLVE0, true, s);
   launch_zero_if_flagged(x, g->n, so, s);
   HIPCHK(g, hipGetLastError());
@@ -329,7 +329,7 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   while (!g->h_status[sys].done && rounds < max_rounds && !inner_fail) {
     // Ask the FP32 solve for the reduction still needed (with a margin), but
     // not below what FP32 arithmetic reliably attains.
-    const double need = 0.5 * g->prm.tol / std::max(g->h_status[sys].res, 1e-300);
+    const double need = 0.5 * tol / std::max(g->h_status[sys].res, 1e-300);
     const double inner_tol = std::min(0.5, std::max(g->tune.inner_min, need));
     if ((st = init_status(g, 3, inner_tol, g->prm.maxit, s)) != DS_OK) return st;
     launch_inner_init<float>(F, g->r, g->r32, g->e32, si, g->partials, g->counters + CT_SOLVE1, s);
@@ -367,9 +367,12 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   return g->h_status[sys].done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
 }
 
+int solve(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
+  if (g->prm.precision == DS_PREC_MIXED) return cg_solve_mixed(g, sys, sc, x, s, iters, res, tol);
+  return cg_solve64(g, sys, sc, x, s, iters, res, tol);
+}
 int solve(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res) {
-  if (g->prm.precision == DS_PREC_MIXED) return cg_solve_mixed(g, sys, sc, x, s, iters, res);
-  return cg_solve64(g, sys, sc, x, s, iters, res);
+  return solve(g, sys, sc, x, s, iters, res, g->prm.tol);
 }
 
 int solve_pressure_system(ds_grid* g, hipStream_t s, int* iters, double* res) {
@@ -407,7 +410,7 @@ int one_step(ds_grid* g, hipStream_t s) {
   // 3. advection of alpha1 with the divergence-free part of u^n, c and T with u^n
   if (g->prm.liquid_transport) {
     launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s);
-    st = solve(g, 2, P.dt / (P.h * P.h), g->phi, s, &D.iters_phi, &D.res_phi);
+    st = solve(g, 2, P.dt / (P.h * P.h), g->phi, s, &D.iters_phi, &D.res_phi, g->prm.tol_phi);
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
   } else {
@@ -482,7 +485,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
       !finite_pos(prm->rho_L) || !finite_pos(prm->cp_L) || !finite_pos(prm->cp_G) || prm->k_L < 0 ||
       prm->k_G < 0 || !finite_pos(prm->D_v) || !finite_pos(prm->M_v) || !finite_pos(prm->M_G) ||
       !finite_pos(prm->T_ref) || !finite_pos(prm->p_ref) || !(prm->eps_int > 0 && prm->eps_int < 0.5) || !(prm->eps_gas >= prm->eps_int && prm->eps_gas <= 0.5) ||
-      !finite_pos(prm->theta_min) || !(prm->tol > 0) || prm->maxit < 1 || prm->s_max < 1 ||
+      !finite_pos(prm->theta_min) || !(prm->tol > 0) || !(prm->tol_phi > 0) || prm->maxit < 1 || prm->s_max < 1 ||
       prm->eq_model < 0 || prm->eq_model > 1 || prm->bc_mode < 0 || prm->bc_mode > 2 ||
       prm->precision < 0 || prm->precision > 1 || !finite_pos(prm->r_fib) || prm->pressure_precond < 0 ||
       prm->pressure_precond > 1 || prm->liquid_transport < 0 || prm->liquid_transport > 1)
@@ -746,6 +749,43 @@ int ds_get_kernel_timing(const ds_grid* g, double* avg_us, long long* launches, 
   if (avg_us) *avg_us = g->t_count ? 1e3 * g->t_sum_ms / (double)g->t_count : 0.0;
   if (launches) *launches = g->t_count;
   if (bytes_per_launch) *bytes_per_launch = g->t_bytes;
+  return DS_OK;
+}
+
+int ds_time_operator_kernel(ds_grid* g, int reps, double* avg_us, double* bytes_per_launch, void* stream) {
+  if (!g || reps < 1 || !avg_us) return DS_ERR_ARG;
+  if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
+  hipStream_t s = S(stream);
+  if (!g->ev[0])
+    for (int e = 0; e < 2 * ds_grid::NEV; ++e) HIPCHK(g, hipEventCreate(&g->ev[e]));
+  SolveStatus init{};
+  init.beta = 0.5;
+  init.rz = 1.0;
+  init.tol = 0.0;
+  init.maxit = 1 << 30;
+  SolveStatus* st = g->status + 3;
+  HIPCHK(g, hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+  double us;
+  const DevParams& P = g->dp;
+  if (g->prm.precision == DS_PREC_MIXED) {
+    Lev<float> F;
+    lev_dims(F, P.nx, P.ny, P.nz, P.dt / (P.h * P.h));
+    F.qc = g->qc32;
+    F.diag = g->diag32;
+    us = replay_operator_kernel<float>(F, g->r32, g->p32, g->p32alt, g->q32, st, g->partials,
+                                       g->counters + CT_MISC, reps, s, g->ev[0], g->ev[1]);
+    if (bytes_per_launch) *bytes_per_launch = 24.0 * (double)g->n;
+  } else {
+    Lev<double> L = g->L0;
+    L.sc = P.dt / (P.h * P.h);
+    L.qc = g->qc;
+    L.diag = g->diag;
+    us = replay_operator_kernel<double>(L, g->r, g->pd, g->p_alt, g->q, st, g->partials, g->counters + CT_MISC,
+                                        reps, s, g->ev[0], g->ev[1]);
+    if (bytes_per_launch) *bytes_per_launch = 48.0 * (double)g->n;
+  }
+  if (us < 0) return fail(g, DS_ERR_HIP, "event timing failed");
+  *avg_us = us;
   return DS_OK;
 }
 

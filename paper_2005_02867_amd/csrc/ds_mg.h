@@ -75,6 +75,11 @@ template <class T>
 void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
                   unsigned* counters, bool first, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+template <class T>
+double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout, T* q, SolveStatus* st,
+                              double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1);
+
 // r = b - A x (FP64), ||b|| (if set_bnorm), ||r|| -> status (done if ||r|| <= tol ||b||).
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
                     double* partials, unsigned* counter, bool set_bnorm, hipStream_t s);

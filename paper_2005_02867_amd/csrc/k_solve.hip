@@ -446,6 +446,31 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
   }
 }
 
+// Back-to-back launches of the multigrid CG operator kernel (direction
+// update with beta from st, matrix-free product, <p, q>) between two events;
+// returns the mean duration in microseconds.  Same kernel and launch shape
+// as inside the pressure solve.
+template <class T>
+double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout, T* q, SolveStatus* st,
+                              double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1) {
+  const int nb = tile_blocks(L.ntiles);
+  k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
+  if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
+  for (int t = 0; t < reps; ++t)
+    k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
+  if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+  return 1e3 * (double)ms / reps;
+}
+template double replay_operator_kernel<double>(const Lev<double>&, const double*, const double*, double*, double*,
+                                               SolveStatus*, double*, unsigned*, int, hipStream_t, hipEvent_t,
+                                               hipEvent_t);
+template double replay_operator_kernel<float>(const Lev<float>&, const float*, const float*, float*, float*,
+                                              SolveStatus*, double*, unsigned*, int, hipStream_t, hipEvent_t,
+                                              hipEvent_t);
+
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
                     double* partials, unsigned* counter, bool set_bnorm, hipStream_t s) {
   k_resid64<<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);

@@ -51,7 +51,7 @@ def _grid_params(name="C1", n=(17, 19, 23), L=None, **kw):
 
 def _run_both(prm, fields, steps, tol_solve=1e-13, check_each=True):
     ds = _lib()
-    prm = dict(prm, tol=tol_solve)
+    prm = dict(prm, tol=tol_solve, tol_phi=tol_solve)
     print(f"case nx={prm['nx']} ny={prm['ny']} nz={prm['nz']} bc={prm['bc_mode']} eq={prm['eq_model']} "
           f"steps={steps}", flush=True)
     g = ds.Grid(prm)
@@ -133,7 +133,7 @@ def test_interface_decisions_bit_exact():
 def test_solve_pressure_static_droplet():
     """One projection from rest with the centripetal force only."""
     ds = _lib()
-    prm, run = W.config("C1", g=(0.0, 0.0, 0.0), evaporation=0, solve_energy=0, tol=1e-13)
+    prm, run = W.config("C1", g=(0.0, 0.0, 0.0), evaporation=0, solve_energy=0, tol=1e-13, tol_phi=1e-13)
     f = W.initial_fields(prm, D0=1e-3)
     g = ds.Grid(prm)
     g.set_fields(f)

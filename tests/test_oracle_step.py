@@ -55,7 +55,7 @@ def test_liquid_budget_exact():
 def test_projection_divergence_matches_stefan_source():
     """div_h u^{n+1} = mdot (1/rho_G - 1/rho_L) to the solve tolerance, and the
     net outflow through the box equals h^3 sum S (divergence theorem)."""
-    prm, run = _cfg("C1", n=16, tol=1e-13)
+    prm, run = _cfg("C1", n=16, tol=1e-13, tol_phi=1e-13)
     f = W.initial_fields(prm, D0=1e-3, seed=0, T_noise=0.01)
     st = S.to_state(f, prm)
     rec = {}
@@ -101,7 +101,7 @@ def test_free_fall_acceleration():
     of a sphere); the error falls with the grid spacing."""
     errs = []
     for n in (16, 32):
-        prm, run = _cfg("C1", n=n, evaporation=0, solve_energy=0, xi0=0.0, tol=1e-13)
+        prm, run = _cfg("C1", n=n, evaporation=0, solve_energy=0, xi0=0.0, tol=1e-13, tol_phi=1e-13)
         f = W.initial_fields(prm, D0=1e-3)
         st = S.to_state(f, prm)
         new, d = S.step(st, prm)
@@ -119,7 +119,7 @@ def test_static_droplet_pressure_matches_force_balance():
     the force impulse (Section 2.6)."""
     errs = []
     for n in (32, 64):
-        prm, run = _cfg("C1", n=n, g=(0.0, 0.0, 0.0), evaporation=0, solve_energy=0, tol=1e-13)
+        prm, run = _cfg("C1", n=n, g=(0.0, 0.0, 0.0), evaporation=0, solve_energy=0, tol=1e-13, tol_phi=1e-13)
         f = W.initial_fields(prm, D0=1e-3)
         st = S.to_state(f, prm)
         new, d = S.step(st, prm)
@@ -150,7 +150,7 @@ def test_static_droplet_pressure_matches_force_balance():
 
 def test_mirror_symmetry():
     """No noise, g = 0, farfield boundaries: the state stays mirror-symmetric."""
-    prm, run = _cfg("C1", n=14, g=(0.0, 0.0, 0.0), bc_mode=W.BC_FARFIELD, tol=1e-13)
+    prm, run = _cfg("C1", n=14, g=(0.0, 0.0, 0.0), bc_mode=W.BC_FARFIELD, tol=1e-13, tol_phi=1e-13)
     f = W.initial_fields(prm, D0=1e-3)
     st = S.to_state(f, prm)
     for _ in range(3):

@@ -45,7 +45,7 @@ _BASE = dict(
     Tc_G=126.2, Pc_G=33.98e5, acentric_G=0.0372,
     T_ref=371.58, p_ref=101325.0,
     eps_int=1e-3, eps_gas=0.5, theta_min=1e-8, s_max=16,
-    tol=1e-10, maxit=20000,
+    tol=1e-10, tol_phi=1e-8, maxit=20000,
     eq_model=EQ_IDEAL, bc_mode=BC_NATURAL, precision=PREC_FP64,
     solve_energy=1, evaporation=1,
     pressure_precond=1, liquid_transport=1,
