@@ -24,6 +24,8 @@ Readings of the paper taken here (each listed in the design notes):
 * eqs. 19-21: mdot = K f(alpha) mdot_raw with f = sqrt(alpha(1-alpha)) and K
   the ratio of the two volume integrals (sums over all cells); K = 0 when the
   denominator vanishes.
+The geometry stays differentiable in alpha (|grad alpha| and the normal);
+classes, the march and adj are integer decisions and carry no derivative.
 """
 from __future__ import annotations
 
@@ -58,9 +60,11 @@ def geometry(alpha, prm):
     eps_gas = prm.get("eps_gas", eps)
     h = prm["h"]
     shape = alpha.shape
-    alpha = alpha.detach()
     dx, dy, dz = central_differences(alpha)
-    norm = torch.sqrt((dx * dx + dy * dy) + dz * dz)
+    sq = (dx * dx + dy * dy) + dz * dz
+    # sqrt written so that a zero gradient has a zero (not NaN) derivative
+    norm = torch.where(sq > 0.0, torch.sqrt(torch.where(sq > 0.0, sq, torch.ones_like(sq))),
+                       torch.zeros_like(sq))
     gradmag = norm / (2.0 * h)
     cls = torch.full(shape, INTERFACE, dtype=torch.int64)
     cls[alpha <= eps] = GAS
@@ -121,7 +125,8 @@ def raw_evaporation(alpha, T, omega, u, v, w, geo, prm, rho_G, D_v=None):
 
 def redistribute(mraw, alpha):
     """Eqs. 19-21: mdot = K f(alpha) mdot_raw, K preserving the volume integral."""
-    f = torch.sqrt(torch.clamp(alpha * (1.0 - alpha), min=0.0))
+    q = torch.clamp(alpha * (1.0 - alpha), min=0.0)
+    f = torch.where(q > 0.0, torch.sqrt(torch.where(q > 0.0, q, torch.ones_like(q))), torch.zeros_like(q))
     S1 = mraw.sum()
     S2 = (f * mraw).sum()
     if float(S2) == 0.0:

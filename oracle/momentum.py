@@ -145,7 +145,7 @@ def project(Ustar, p, rho, prm):
     return out
 
 
-def solenoidal_part(U, prm, tol=None, maxit=None):
+def solenoidal_part(U, prm, tol=None, maxit=None, solver=None):
     """Discretely divergence-free part of the face velocity field:
     U_s = U - G phi with D G phi = D U (G: face gradient, D: divergence, the
     same boundary kinds as the pressure: phi = 0 half a cell outside open
@@ -158,8 +158,9 @@ def solenoidal_part(U, prm, tol=None, maxit=None):
     ones = torch.full(shape, 1.0 / dt, dtype=torch.float64)     # (dt/h^2) * (1/dt) = 1/h^2 per face
     op = operators.pressure_operator(ones, prm)
     b = -operators.divergence(*U, h)
-    phi, it, res, ok = operators.pcg(op, b, torch.zeros(shape, dtype=torch.float64),
-                                     prm["tol"] if tol is None else tol,
-                                     prm["maxit"] if maxit is None else maxit)
+    solve = operators.pcg if solver is None else solver
+    phi, it, res, ok = solve(op, b, torch.zeros(shape, dtype=torch.float64),
+                             prm["tol"] if tol is None else tol,
+                             prm["maxit"] if maxit is None else maxit)
     Us = project(U, phi, torch.full(shape, dt, dtype=torch.float64), prm)   # dt/rho = 1
     return Us, phi, it

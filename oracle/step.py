@@ -61,13 +61,17 @@ def evaporation_source(st, prm, rho_G, D_v=None):
     return mdot, mraw, K, geo
 
 
-def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record=None):
+def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record=None, solver=None):
     """Advance the state by one step.  Returns (new_state, diagnostics).
 
     T_amb, D_v, dh_ev may be passed as tensors (for differentiation); they
     default to the parameter values.  record, if a dict, receives the
-    intermediate fields of the step.
+    intermediate fields of the step.  solver(op, b, x0, tol, maxit) ->
+    (x, iters, rel_res, converged) replaces operators.pcg for every linear
+    solve of the step (the differentiation form passes one with an implicit
+    derivative).
     """
+    solve = operators.pcg if solver is None else solver
     prm = dict(prm)
     if dh_ev is not None:
         prm["dh_ev"] = dh_ev
@@ -85,7 +89,7 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     alpha1 = st["alpha"] - dt * mdot / prm["rho_L"]
     # 3. advection: the liquid marker moves with the divergence-free part of u^n
     if prm["liquid_transport"]:
-        U_liq, phi, it_phi = momentum.solenoidal_part(U, prm, tol=prm["tol_phi"])
+        U_liq, phi, it_phi = momentum.solenoidal_part(U, prm, tol=prm["tol_phi"], solver=solve)
     else:
         U_liq, phi, it_phi = None, None, 0
     alpha_p, c_p, T_p, B_L, B_v = vof.advect(alpha1, st["omega"], st["T"], st["c"], *U, prm, rho_G,
@@ -98,7 +102,7 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
         m = rho * cp / dt
         op, rb = operators.scalar_system(m, k, 1.0 / (h * h), 2.0 * prm["k_G"] / (h * h), Ta, U, prm)
         b = m * T_p - mdot * prm["dh_ev"] + rb
-        T_new, itT, resT, okT = operators.pcg(op, b, T_p, tol, prm["maxit"])
+        T_new, itT, resT, okT = solve(op, b, T_p, tol, prm["maxit"])
     else:
         T_new, itT, resT, okT = st["T"], 0, 0.0, True
     # 5b. species
@@ -107,7 +111,7 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     opS, _ = operators.scalar_system(mS, theta, rho_G * D / (h * h), KbS, 0.0, U, prm)
     bS = c_p / dt + mdot
     omega_p = c_p / (rho_G * theta)
-    om, itS, resS, okS = operators.pcg(opS, bS, omega_p, tol, prm["maxit"])
+    om, itS, resS, okS = solve(opS, bS, omega_p, tol, prm["maxit"])
     face_part = opS.apply(om) - mS * om
     c_new = c_p + dt * mdot - dt * face_part
     # vapour diffused out through ambient (Dirichlet) boundary faces
@@ -125,7 +129,7 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     opP = operators.pressure_operator(beta, prm)
     S = mdot * (1.0 / rho_G - 1.0 / prm["rho_L"])
     bP = S - operators.divergence(*Us, h)
-    p_new, itP, resP, okP = operators.pcg(opP, bP, st["p"], tol, prm["maxit"])
+    p_new, itP, resP, okP = solve(opP, bP, st["p"], tol, prm["maxit"])
     Un = momentum.project(Us, p_new, rho, prm)
 
     new = dict(alpha=alpha_p, c=c_new, omega=omega_new, T=T_new, p=p_new, u=Un[0], v=Un[1], w=Un[2])

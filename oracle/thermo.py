@@ -141,14 +141,85 @@ def equilibrium_residual(T, y, prm):
     return (np.log(p0) + ln_phi_pure + vL * (p - p0) / (R_GAS * T)) - (math.log(p) + np.log(y) + ln_phihat)
 
 
+def _richardson(f, x, step):
+    """df/dx by central differences at steps `step` and `step`/2, combined
+    by Richardson extrapolation (error O(step^4))."""
+    d1 = (f(x + step) - f(x - step)) / (2.0 * step)
+    d2 = (f(x + 0.5 * step) - f(x - 0.5 * step)) / step
+    return (4.0 * d2 - d1) / 3.0
+
+
+def _prm_float(prm):
+    q = dict(prm)
+    q["dh_ev"] = float(q["dh_ev"])
+    return q
+
+
+class _PRSaturation(torch.autograd.Function):
+    """omega_sat(T) of the Peng-Robinson model as a differentiable function
+    of T (per cell) and dh_ev.  The value is the converged fixed point of
+    eq. 23; its derivatives are taken by Richardson-extrapolated central
+    differences of that converged root (steps 0.05 K and 1e-4 dh_ev)."""
+
+    @staticmethod
+    def forward(ctx, T, dh, prm):
+        q = _prm_float(prm)
+        q["dh_ev"] = float(dh)
+        Tn = T.detach().cpu().numpy()
+        ctx.save_for_backward(T, dh)
+        ctx.q = q
+        return torch.as_tensor(mass_fraction(equilibrium_y(Tn, q), q), dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gbar):
+        T, dh = ctx.saved_tensors
+        q = ctx.q
+        Tn = T.detach().cpu().numpy()
+
+        def w_of_T(t):
+            return mass_fraction(equilibrium_y(t, q), q)
+
+        def w_of_dh(d):
+            qq = dict(q)
+            qq["dh_ev"] = d
+            return mass_fraction(equilibrium_y(Tn, qq), qq)
+
+        dT = torch.as_tensor(_richardson(w_of_T, Tn, 0.05), dtype=torch.float64)
+        ddh = torch.as_tensor(_richardson(w_of_dh, q["dh_ev"], 1e-4 * q["dh_ev"]), dtype=torch.float64)
+        return gbar * dT, (gbar * ddh).sum().reshape(dh.shape), None
+
+
+class _PRGasZ(torch.autograd.Function):
+    """Peng-Robinson Z of the ambient gas as a differentiable function of
+    T_amb (Richardson-extrapolated central differences, step 0.05 K)."""
+
+    @staticmethod
+    def forward(ctx, T, prm):
+        ctx.save_for_backward(T)
+        ctx.prm = prm
+        return torch.as_tensor(float(pr_Z_pure_gas(float(T), prm["p"], prm)), dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gbar):
+        (T,) = ctx.saved_tensors
+        prm = ctx.prm
+        dZ = _richardson(lambda t: float(pr_Z_pure_gas(t, prm["p"], prm)), float(T), 0.05)
+        return gbar * dZ, None
+
+
 def saturation_omega(T, prm):
     """Interface vapour mass fraction omega_sat(T_int) (torch in, torch out).
 
-    The ideal model stays in torch (differentiable in T and dh_ev); the PR
-    model is evaluated in numpy and returned detached."""
+    The ideal model stays in torch (differentiable in T and dh_ev).  The PR
+    model is evaluated in numpy; when T requires a gradient or dh_ev is a
+    tensor, its derivative comes from _PRSaturation."""
     if prm["eq_model"] == 0:
         y = torch.clamp(vapour_pressure(T, prm) / prm["p"], max=1.0 - 1e-12)
         return mass_fraction(y, prm)
+    dh = prm["dh_ev"]
+    if T.requires_grad or isinstance(dh, torch.Tensor):
+        dh_t = dh if isinstance(dh, torch.Tensor) else torch.tensor(float(dh), dtype=torch.float64)
+        return _PRSaturation.apply(T, dh_t, _prm_float(prm))
     y = equilibrium_y(T.detach().cpu().numpy(), prm)
     return torch.as_tensor(mass_fraction(y, prm), dtype=torch.float64)
 
@@ -158,6 +229,8 @@ def gas_density(prm, T_amb=None):
     T = prm["T_amb"] if T_amb is None else T_amb
     if prm["eq_model"] == 0:
         Z = 1.0
+    elif isinstance(T, torch.Tensor) and T.requires_grad:
+        Z = _PRGasZ.apply(T, _prm_float(prm))
     else:
         Tf = float(T.detach()) if isinstance(T, torch.Tensor) else float(T)
         Z = float(pr_Z_pure_gas(Tf, prm["p"], prm))
