@@ -54,6 +54,41 @@ def timed_run(ds, torch, prm, fields, steps, warmup, timing=False):
     return dict(seconds=t1 - t0, iters=iters, kernel=kt, replay=rep, volume=d["volume"], diag=d)
 
 
+def adjoint_cost(ds, torch, W):
+    """Differentiation workload (96^3 over 5 mm, 1 bar / 873 K, 100 steps):
+    seconds of the forward run, of ds_forward_record and of the reverse sweep
+    (ds_adjoint) with every state stored and with a checkpoint every 10 steps."""
+    prm, run = W.config("C4")
+    f = W.initial_fields(prm, **run)
+    steps = run["steps"]
+    out = {"workload": "96^3 over 5 mm, 1.0 mm droplet, 1 bar N2 at 873 K, natural convection, 100 steps of 1e-5 s, "
+                       "FP64, J = droplet volume", "steps": steps}
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    g.step(2)                                  # warm-up (kernels loaded, batch sizes settled)
+    g.set_fields(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    out["forward_s"] = time.perf_counter() - t0
+    del g
+    for ckpt in (1, 10):
+        g = ds.Grid(prm)
+        g.set_fields(f)
+        t0 = time.perf_counter()
+        g.forward_record(steps, ckpt)
+        t1 = time.perf_counter()
+        r = g.adjoint(1.0, fields=False)
+        t2 = time.perf_counter()
+        out[f"ckpt{ckpt}"] = {"record_s": t1 - t0, "reverse_s": t2 - t1,
+                              "reverse_over_forward": (t2 - t1) / out["forward_s"],
+                              "dV_dD_v": r["D_v"], "dV_ddh_ev": r["dh_ev"], "dV_dT_amb": r["T_amb"]}
+        del g
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(prm, fields, jacobi_iters_p, sample_iters=8):
     """The CPU oracle (torch float64, host cores) on a bounded sample of the
     same workload: one oracle step from the initial state with its pressure
@@ -105,6 +140,7 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="cells per axis (256 = the benchmark workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -170,6 +206,12 @@ def main():
                        "operator_kernel_GBs": rp64["bytes_per_launch"] / (rp64["avg_us"] * 1e-6) / 1e9}
         out["speedup_mixed_vs_fp64"] = out["value"] / v64
         out["volume_rel_diff_mixed_vs_fp64"] = abs(mixed["volume"] - fp64["volume"]) / fp64["volume"]
+    if not args.no_adjoint:
+        log("adjoint cost: 96^3, 100 steps")
+        out["adjoint"] = adjoint_cost(ds, torch, W)
+        log(f"  forward {out['adjoint']['forward_s']:.3f} s, reverse/forward "
+            f"{out['adjoint']['ckpt1']['reverse_over_forward']:.2f} (every state stored), "
+            f"{out['adjoint']['ckpt10']['reverse_over_forward']:.2f} (checkpoint every 10)")
     if not args.no_cpu:
         log("GPU Jacobi-PCG step (pressure iteration count for the CPU extrapolation)")
         g = ds.Grid(dict(prm, precision=W.PREC_FP64, pressure_precond=0))

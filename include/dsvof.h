@@ -191,6 +191,57 @@ int ds_get_kernel_timing(const ds_grid* g, double* avg_us, long long* launches, 
  * Only solver scratch vectors are written; the state is untouched. */
 int ds_time_operator_kernel(ds_grid* g, int reps, double* avg_us, double* bytes_per_launch, void* stream);
 
+/* ---- Differentiation form: derivative of the liquid volume after a run.
+ *
+ * J = dJ_dV * V_N with V_N = h^3 sum(alpha) after nsteps steps (the droplet
+ * volume whose evolution Section 4 follows).  The reverse sweep gives
+ * dJ/d(D_v, dh_ev, T_amb) and dJ/d(initial alpha, T, omega, u, v, w).
+ * Method: the exact derivative of the discrete step of Section 3.1 with its
+ * integer decisions held (interface classes and adj of eqs. 15-17, donor and
+ * limiter branches, inletOutlet switches, the clamps of the mixing rule of
+ * eq. 31); linear solves (eqs. 7-9 and the liquid-transport potential)
+ * differentiated implicitly with the same operators; Peng-Robinson
+ * equilibrium (eqs. 22-25) by the implicit-function rule.  T_amb acts through
+ * the gas density (eq. 24), the ambient boundary temperature and the inflow
+ * face temperature; its effect through the initial temperature field is the
+ * caller's (chain it with dJ/dT0).  The initial pressure only warm-starts the
+ * first solve and carries no derivative.
+ *
+ * Memory: the tape is caller-owned device memory (256-byte aligned) of
+ * ds_tape_bytes() bytes holding the adjoint arrays (about 25 arrays of the
+ * grid) and the stored states: a checkpoint every ckpt_every steps, the final
+ * state, and ckpt_every-1 segment states recomputed during the reverse sweep
+ * (about 10 arrays of the grid per stored state).  ckpt_every = 1 stores every
+ * state and recomputes none; larger values trade one extra forward pass for
+ * memory.  The tape must stay allocated and untouched between
+ * ds_forward_record and ds_adjoint.  The library still allocates nothing. */
+
+/* Tape size for nsteps steps with a checkpoint every ckpt_every steps
+ * (0 on invalid arguments).  Host only. */
+size_t ds_tape_bytes(const ds_grid* g, int nsteps, int ckpt_every);
+
+/* Advance nsteps steps exactly as ds_step does, storing checkpoints in the
+ * tape.  Returns ds_step's status (DS_ERR_NOT_CONVERGED if a solve hit
+ * maxit).  DS_ERR_ARG for a small or misaligned tape, DS_ERR_STATE before
+ * ds_set_fields.  Synchronises the stream at the end. */
+int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t tape_bytes, void* stream);
+
+/* Reverse sweep over the recorded run.  grads: host double[3] receiving
+ * dJ/dD_v, dJ/ddh_ev, dJ/dT_amb.  dalpha0, dT0, domega0 (cell arrays) and
+ * du0, dv0, dw0 (face arrays): device buffers receiving dJ/d(initial
+ * field), each may be NULL.  Afterwards the handle holds the final state of
+ * the run again (as after ds_forward_record).  DS_ERR_STATE without a
+ * recorded run; DS_ERR_NOT_CONVERGED if an adjoint solve hit maxit (results
+ * are still written); DS_ERR_NONFINITE for a non-finite gradient.
+ * Synchronises the stream. */
+int ds_adjoint(ds_grid* g, double dJ_dV, double* grads, double* dalpha0, double* dT0, double* domega0,
+               double* du0, double* dv0, double* dw0, void* stream);
+
+/* Iterations of the adjoint linear solves of the last ds_adjoint, summed
+ * over the steps: iters4[0] pressure, [1] species, [2] energy, [3] liquid-
+ * transport potential.  Host only. */
+int ds_get_adjoint_iterations(const ds_grid* g, int* iters4);
+
 /* Message describing the last error on this handle ("" if none). */
 const char* ds_last_error(const ds_grid* g);
 

@@ -27,7 +27,8 @@ FIELD_MDOT_RAW, FIELD_MDOT, FIELD_ALPHA1, FIELD_C, FIELD_USTAR, FIELD_VSTAR, FIE
 EXPORTS = ("ds_create_grid", "ds_destroy_grid", "ds_workspace_bytes", "ds_set_fields", "ds_get_fields",
            "ds_step", "ds_solve_pressure", "ds_evaporation_rate", "ds_droplet_volume", "ds_get_diagnostics",
            "ds_get_internal", "ds_last_error", "ds_set_kernel_timing", "ds_get_kernel_timing",
-           "ds_time_operator_kernel")
+           "ds_time_operator_kernel", "ds_tape_bytes", "ds_forward_record", "ds_adjoint",
+           "ds_get_adjoint_iterations")
 
 
 class Params(C.Structure):
@@ -77,6 +78,11 @@ _lib.ds_get_internal.argtypes = [_P, C.c_int, _P, C.c_size_t, _P]
 _lib.ds_set_kernel_timing.argtypes = [_P, C.c_int]
 _lib.ds_get_kernel_timing.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
 _lib.ds_time_operator_kernel.argtypes = [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]
+_lib.ds_tape_bytes.argtypes = [_P, C.c_int, C.c_int]
+_lib.ds_tape_bytes.restype = C.c_size_t
+_lib.ds_forward_record.argtypes = [_P, C.c_int, C.c_int, _P, C.c_size_t, _P]
+_lib.ds_adjoint.argtypes = [_P, C.c_double, C.POINTER(C.c_double)] + [_P] * 6 + [_P]
+_lib.ds_get_adjoint_iterations.argtypes = [_P, C.POINTER(C.c_int)]
 _lib.ds_last_error.argtypes = [_P]
 _lib.ds_last_error.restype = C.c_char_p
 
@@ -208,6 +214,28 @@ def time_operator_kernel(h, reps=50):
     return dict(avg_us=us.value, bytes_per_launch=nb.value, reps=int(reps))
 
 
+def tape_bytes(h, nsteps, ckpt_every=1) -> int:
+    return int(_lib.ds_tape_bytes(h, int(nsteps), int(ckpt_every)))
+
+
+def forward_record(h, nsteps, ckpt_every, tape):
+    _check(h, _lib.ds_forward_record(h, int(nsteps), int(ckpt_every), C.c_void_p(tape.data_ptr()), tape.numel(),
+                                     _stream()))
+
+
+def adjoint(h, dJ_dV=1.0, dalpha0=None, dT0=None, domega0=None, du0=None, dv0=None, dw0=None):
+    g = (C.c_double * 3)()
+    _check(h, _lib.ds_adjoint(h, float(dJ_dV), g, _dptr(dalpha0), _dptr(dT0), _dptr(domega0), _dptr(du0),
+                              _dptr(dv0), _dptr(dw0), _stream()))
+    return [g[0], g[1], g[2]]
+
+
+def get_adjoint_iterations(h):
+    it = (C.c_int * 4)()
+    _check(h, _lib.ds_get_adjoint_iterations(h, it))
+    return dict(p=it[0], omega=it[1], T=it[2], phi=it[3])
+
+
 # ------------------------------------------------------------ convenience
 class Grid:
     """A handle plus its torch-allocated workspace on the current CUDA device."""
@@ -225,7 +253,7 @@ class Grid:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _lib is not None:
             _lib.ds_destroy_grid(h)
             self.h = None
 
@@ -276,9 +304,71 @@ class Grid:
     def time_operator_kernel(self, reps=50):
         return time_operator_kernel(self.h, reps)
 
+    def forward_record(self, nsteps, ckpt_every=1):
+        """Run nsteps steps storing the tape for adjoint() (allocated here, on
+        the grid's device, and kept until the next record)."""
+        nbytes = tape_bytes(self.h, nsteps, ckpt_every)
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._tape_raw = raw
+        self.tape = raw[off:off + nbytes]
+        forward_record(self.h, nsteps, ckpt_every, self.tape)
+
+    def adjoint(self, dJ_dV=1.0, fields=True):
+        """dJ/d(D_v, dh_ev, T_amb) for J = dJ_dV * droplet volume after the
+        recorded run, and (fields=True) dJ/d(initial alpha, T, omega, u, v, w)."""
+        out = None
+        if fields:
+            out = {k: torch.empty(sh, dtype=torch.float64, device=self.device)
+                   for k, sh in self.shapes().items() if k != "p"}
+            g = adjoint(self.h, dJ_dV, out["alpha"], out["T"], out["omega"], out["u"], out["v"], out["w"])
+        else:
+            g = adjoint(self.h, dJ_dV)
+        return dict(D_v=g[0], dh_ev=g[1], T_amb=g[2], fields=out)
+
+    def adjoint_iterations(self):
+        return get_adjoint_iterations(self.h)
+
     def internal(self, which):
         s = self.shapes()
         shp = {FIELD_USTAR: s["u"], FIELD_VSTAR: s["v"], FIELD_WSTAR: s["w"]}.get(which, s["alpha"])
         out = torch.empty(shp, dtype=torch.float64, device=self.device)
         get_internal(self.h, which, out)
         return out
+
+
+class DropletVolume(torch.autograd.Function):
+    """V_N = h^3 sum(alpha) after `steps` steps of the library's step, as a
+    differentiable function of (D_v, dh_ev, T_amb) and the initial fields
+    alpha0, T0, omega0, u0, v0, w0 (float64 CUDA tensors; p0 only warm-starts).
+
+    The forward runs ds_forward_record; the backward runs the library's
+    reverse sweep (ds_adjoint).  Use through droplet_volume_after()."""
+
+    @staticmethod
+    def forward(ctx, D_v, dh_ev, T_amb, alpha0, T0, omega0, u0, v0, w0, p0, prm, steps, ckpt_every):
+        q = dict(prm, D_v=float(D_v), dh_ev=float(dh_ev), T_amb=float(T_amb))
+        g = Grid(q, device=alpha0.device)
+        g.set_fields(dict(alpha=alpha0.detach(), T=T0.detach(), omega=omega0.detach(), u=u0.detach(),
+                          v=v0.detach(), w=w0.detach(), p=p0.detach()))
+        g.forward_record(int(steps), int(ckpt_every))
+        V = g.droplet_volume()
+        ctx.g = g
+        return torch.tensor(V, dtype=torch.float64, device=alpha0.device)
+
+    @staticmethod
+    def backward(ctx, gV):
+        r = ctx.g.adjoint(float(gV), fields=True)
+        f = r["fields"]
+        dev = f["alpha"].device
+        scal = [torch.tensor(r[k], dtype=torch.float64, device=dev) for k in ("D_v", "dh_ev", "T_amb")]
+        ctx.g = None
+        return (*scal, f["alpha"], f["T"], f["omega"], f["u"], f["v"], f["w"], None, None, None, None)
+
+
+def droplet_volume_after(prm, fields, steps, D_v, dh_ev, T_amb, ckpt_every=1):
+    """Differentiable droplet volume after `steps` steps (see DropletVolume).
+    D_v, dh_ev, T_amb: 0-d float64 tensors (may require grad); fields: dict of
+    float64 CUDA tensors alpha, T, omega, u, v, w, p."""
+    return DropletVolume.apply(D_v, dh_ev, T_amb, fields["alpha"], fields["T"], fields["omega"], fields["u"],
+                               fields["v"], fields["w"], fields["p"], prm, steps, ckpt_every)

@@ -85,6 +85,18 @@ struct ds_grid {
   ds_diagnostics diag_out{};
   double fuel_mass_prev = 0.0;
   int batch[3] = {8, 8, 8};
+  // differentiation form: arrays carved from the caller's tape
+  char* tape = nullptr;
+  size_t tape_bytes = 0, tape_slot_off = 0;
+  int tape_steps = 0, tape_ckpt = 0;
+  bool recorded = false;
+  double fuel_mass_final = 0.0;
+  ds_diagnostics diag_final{};
+  double *A_al = nullptr, *A_c = nullptr, *A_om = nullptr, *A_T = nullptr, *A_ab = nullptr, *A_md = nullptr;
+  double *A_cp = nullptr, *A_Tp = nullptr, *A_a1 = nullptr, *lam = nullptr, *grad = nullptr;
+  double *A_U[3] = {}, *A_Us[3] = {}, *A_Ul[3] = {}, *Q[6] = {};
+  double* h_grad = nullptr;          // pinned host mirror of grad
+  int adj_iters[4] = {0, 0, 0, 0};   // adjoint solve iterations: p, omega, T, phi (last ds_adjoint)
 };
 
 namespace {
@@ -190,6 +202,79 @@ size_t carve(ds_grid* g, char* base) {
     g->q32 = L.take<float>(base, n);
   }
   return L.off;
+}
+
+// State of one step boundary on the tape: the state at the start of step k,
+// and the solver outputs of step k-1 that the reverse sweep reuses (the
+// liquid-transport potential, which is also step k's warm start, and the
+// species solution omega~).
+struct Slot {
+  double *alpha, *c, *omega, *T, *p, *phi, *omt, *u, *v, *w;
+};
+
+size_t slot_bytes(const ds_grid* g) {
+  return 7 * align256(g->n * sizeof(double)) + align256(g->nu * sizeof(double)) +
+         align256(g->nv * sizeof(double)) + align256(g->nw * sizeof(double));
+}
+
+int tape_nckpt(int nsteps, int ckpt) { return (nsteps + ckpt - 1) / ckpt; }
+int tape_nslots(int nsteps, int ckpt) { return tape_nckpt(nsteps, ckpt) + 1 + (ckpt > 1 ? ckpt - 1 : 0); }
+
+// Bytes of the adjoint arrays and accumulators at the head of the tape (the
+// layout carve_tape produces).
+size_t tape_adjoint_bytes(const ds_grid* g) {
+  const size_t cb = align256(g->n * sizeof(double));
+  const size_t fb = align256(g->nu * sizeof(double)) + align256(g->nv * sizeof(double)) +
+                    align256(g->nw * sizeof(double));
+  return 10 * cb + 5 * fb + align256(GR_COUNT * sizeof(double));
+}
+
+size_t tape_total_bytes(const ds_grid* g, int nsteps, int ckpt) {
+  return tape_adjoint_bytes(g) + (size_t)tape_nslots(nsteps, ckpt) * slot_bytes(g);
+}
+
+// Tape layout: adjoint arrays, gradient accumulators, then the slots
+// (checkpoints at steps 0, C, 2C, ..., the final state, and C-1 segment slots).
+void carve_tape(ds_grid* g, char* base) {
+  Layout L;
+  const long long n = g->n;
+  const long long nf[3] = {g->nu, g->nv, g->nw};
+  g->A_al = L.take<double>(base, n);
+  g->A_c = L.take<double>(base, n);
+  g->A_om = L.take<double>(base, n);
+  g->A_T = L.take<double>(base, n);
+  g->A_ab = L.take<double>(base, n);
+  g->A_md = L.take<double>(base, n);
+  g->A_cp = L.take<double>(base, n);
+  g->A_Tp = L.take<double>(base, n);
+  g->A_a1 = L.take<double>(base, n);
+  g->lam = L.take<double>(base, n);
+  for (int a = 0; a < 3; ++a) {
+    g->A_U[a] = L.take<double>(base, nf[a]);
+    g->A_Us[a] = L.take<double>(base, nf[a]);
+    g->A_Ul[a] = L.take<double>(base, nf[a]);
+    g->Q[2 * a] = L.take<double>(base, nf[a]);
+    g->Q[2 * a + 1] = L.take<double>(base, nf[a]);
+  }
+  g->grad = L.take<double>(base, GR_COUNT);
+  g->tape_slot_off = L.off;
+}
+
+Slot slot_at(const ds_grid* g, int idx) {
+  char* p = g->tape + g->tape_slot_off + (size_t)idx * slot_bytes(g);
+  Slot sl;
+  const size_t cb = align256(g->n * sizeof(double));
+  double** cells[7] = {&sl.alpha, &sl.c, &sl.omega, &sl.T, &sl.p, &sl.phi, &sl.omt};
+  for (int q = 0; q < 7; ++q) {
+    *cells[q] = reinterpret_cast<double*>(p);
+    p += cb;
+  }
+  sl.u = reinterpret_cast<double*>(p);
+  p += align256(g->nu * sizeof(double));
+  sl.v = reinterpret_cast<double*>(p);
+  p += align256(g->nv * sizeof(double));
+  sl.w = reinterpret_cast<double*>(p);
+  return sl;
 }
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -469,6 +554,142 @@ int one_step(ds_grid* g, hipStream_t s) {
   return rc;
 }
 
+// ---------------------------------------------------------------- differentiation form
+int save_slot(ds_grid* g, const Slot& sl, hipStream_t s) {
+  const size_t nb = g->n * sizeof(double);
+  const std::pair<double*, const double*> cp[7] = {{sl.alpha, g->alpha}, {sl.c, g->c},   {sl.omega, g->omega},
+                                                   {sl.T, g->T},         {sl.p, g->p},   {sl.phi, g->phi},
+                                                   {sl.omt, g->om_new}};
+  for (const auto& q : cp) HIPCHK(g, hipMemcpyAsync(q.first, q.second, nb, hipMemcpyDeviceToDevice, s));
+  HIPCHK(g, hipMemcpyAsync(sl.u, g->u, g->nu * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(g, hipMemcpyAsync(sl.v, g->v, g->nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(g, hipMemcpyAsync(sl.w, g->w, g->nw * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return DS_OK;
+}
+
+int load_slot(ds_grid* g, const Slot& sl, hipStream_t s) {
+  const size_t nb = g->n * sizeof(double);
+  const std::pair<double*, const double*> cp[7] = {{g->alpha, sl.alpha}, {g->c, sl.c},     {g->omega, sl.omega},
+                                                   {g->T, sl.T},         {g->p, sl.p},     {g->phi, sl.phi},
+                                                   {g->om_new, sl.omt}};
+  for (const auto& q : cp) HIPCHK(g, hipMemcpyAsync(q.first, q.second, nb, hipMemcpyDeviceToDevice, s));
+  HIPCHK(g, hipMemcpyAsync(g->u, sl.u, g->nu * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(g, hipMemcpyAsync(g->v, sl.v, g->nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(g, hipMemcpyAsync(g->w, sl.w, g->nw * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return DS_OK;
+}
+
+// d rho_G / d T_amb of eq. 24 (ideal gas, or the Peng-Robinson Z of the
+// ambient gas by the implicit-function rule on its cubic).
+double host_drhoG_dT(const ds_params& q, double rho_G) {
+  const double T = q.T_amb;
+  if (q.eq_model != DS_EQ_PENG_ROBINSON) return -rho_G / T;
+  const double Z = host_pr_Z(T, q.p, q.Tc_G, q.Pc_G, q.acentric_G);
+  const double kap = 0.37464 + 1.54226 * q.acentric_G - 0.26992 * q.acentric_G * q.acentric_G;
+  const double K0 = 0.45724 * R_GAS * R_GAS * q.Tc_G * q.Tc_G / q.Pc_G;
+  const double sq = 1.0 + kap * (1.0 - std::sqrt(T / q.Tc_G));
+  const double a = K0 * sq * sq;
+  const double da = 2.0 * K0 * sq * (-kap / (2.0 * std::sqrt(T * q.Tc_G)));
+  const double b = 0.07780 * R_GAS * q.Tc_G / q.Pc_G;
+  const double A = a * q.p / (R_GAS * T * R_GAS * T), B = b * q.p / (R_GAS * T);
+  const double dA = q.p / (R_GAS * R_GAS) * (da / (T * T) - 2.0 * a / (T * T * T));
+  const double dB = -B / T;
+  const double c2 = -(1.0 - B), c1 = A - 3.0 * B * B - 2.0 * B;
+  const double FZ = (3.0 * Z + 2.0 * c2) * Z + c1;
+  const double FA = Z - B;
+  const double FB = Z * Z + (-6.0 * B - 2.0) * Z + (-A + 2.0 * B + 3.0 * B * B);
+  const double dZ = -(FA * dA + FB * dB) / FZ;
+  return -rho_G * (1.0 / T + dZ / Z);
+}
+
+// Adjoint solve A lam = b (b in g->b).  Adjoint right-hand sides can be
+// tiny (far-field tails of alpha reach the box faces at 1e-150 and below),
+// where the squared norms of conjugate gradients underflow; b is therefore
+// scaled by a power of two (exactly) to a maximum in [1/2, 1) and lam scaled back.
+int adj_solve(ds_grid* g, int sys, double sc, double tol, int slot, hipStream_t s, int* rc) {
+  launch_absmax(g->b, g->n, g->partials, g->counters + CT_ADJ, g->scal + SC_ABSMAX, s);
+  HIPCHK(g, hipGetLastError());
+  HIPCHK(g, hipMemcpyAsync(g->h_scal + SC_ABSMAX, g->scal + SC_ABSMAX, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(g, hipStreamSynchronize(s));
+  const double bmax = g->h_scal[SC_ABSMAX];
+  launch_fill(g->lam, 0.0, g->n, s);
+  if (bmax == 0.0) return DS_OK;
+  if (!std::isfinite(bmax)) return fail(g, DS_ERR_NONFINITE, "non-finite adjoint right-hand side");
+  int ex = 0;
+  std::frexp(bmax, &ex);
+  launch_scale(g->b, std::ldexp(1.0, -ex), g->n, s);
+  int it = 0;
+  double res = 0.0;
+  const int st = solve(g, sys, sc, g->lam, s, &it, &res, tol);
+  g->adj_iters[slot] += it;
+  if (st == DS_ERR_NOT_CONVERGED) *rc = st;
+  else if (st != DS_OK) return st;
+  launch_scale(g->lam, std::ldexp(1.0, ex), g->n, s);
+  HIPCHK(g, hipGetLastError());
+  return DS_OK;
+}
+
+// Reverse of one step: replay the explicit stages of the step from `cur`
+// (the solves' results come from `nxt`), then apply the transposed stages in
+// reverse order to the adjoint state held in A_al, A_c, A_om, A_T, A_U.
+int reverse_step(ds_grid* g, const Slot& cur, const Slot& nxt, hipStream_t s, int* rc) {
+  const DevParams& P = g->dp;
+  int st;
+  unsigned* cadj = g->counters + CT_ADJ;
+  // replay: interface source, liquid source, advection, predictor
+  if (P.evaporation) {
+    launch_interface(P, cur.alpha, cur.T, cur.omega, cur.u, cur.v, cur.w, g->mraw, g->adj, g->partials,
+                     g->counters + CT_IFACE, g->scal, s);
+  } else {
+    launch_fill(g->mraw, 0.0, g->n, s);
+    launch_fill(g->scal + SC_K, 0.0, 4, s);
+  }
+  launch_source(P, cur.alpha, g->mraw, g->scal, g->mdot, g->a1, s);
+  const double* phi = g->prm.liquid_transport ? nxt.phi : nullptr;
+  launch_advect(P, g->a1, cur.omega, cur.T, cur.c, cur.u, cur.v, cur.w, phi, g->a_new, g->c_new, g->T_new,
+                g->partials, g->counters + CT_ADV, g->scal, s);
+  launch_predictor(P, g->a_new, g->xi, cur.u, cur.v, cur.w, g->us, g->vs, g->ws, s);
+  HIPCHK(g, hipGetLastError());
+  // projection and pressure (S11, S10)
+  launch_pressure_setup(P, g->a_new, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s);
+  launch_adj_project(P, g->a_new, nxt.p, g->A_U, g->b, g->A_ab, g->partials, cadj, g->grad, s);
+  if ((st = adj_solve(g, 2, P.dt / (P.h * P.h), g->prm.tol, 0, s, rc)) != DS_OK) return st;
+  launch_adj_pressure(P, g->a_new, nxt.p, g->lam, g->mdot, g->A_ab, g->A_md, g->partials, cadj, g->grad, s);
+  // predictor (S9)
+  launch_adj_predictor(P, g->a_new, g->xi, g->A_U, g->A_Us, g->Q, g->lam, cur.u, cur.v, cur.w, g->A_ab, g->partials,
+                       cadj, g->grad, s);
+  // species (S8)
+  launch_species_setup(P, g->a_new, g->c_new, g->mdot, cur.u, cur.v, cur.w, g->qc, g->diag, g->b, nullptr, s);
+  launch_adj_species_rhs(P, g->a_new, nxt.omt, g->A_om, g->A_c, g->b, g->A_ab, g->partials, cadj, g->grad, s);
+  if ((st = adj_solve(g, 1, P.rho_G * P.D / (P.h * P.h), g->prm.tol, 1, s, rc)) != DS_OK) return st;
+  launch_adj_species(P, g->a_new, nxt.omt, g->lam, cur.u, cur.v, cur.w, g->A_ab, g->A_cp, g->A_md, g->partials, cadj,
+                     g->grad, s);
+  // energy (S7)
+  if (P.solve_energy) {
+    launch_energy_setup(P, g->a_new, g->T_new, g->mdot, cur.u, cur.v, cur.w, g->qc, g->diag, g->b, s);
+    HIPCHK(g, hipMemcpyAsync(g->b, g->A_T, g->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if ((st = adj_solve(g, 0, 1.0 / (P.h * P.h), g->prm.tol, 2, s, rc)) != DS_OK) return st;
+    launch_adj_energy(P, g->a_new, g->T_new, nxt.T, g->lam, g->mdot, cur.u, cur.v, cur.w, g->A_ab, g->A_Tp, g->A_md,
+                      g->partials, cadj, g->grad, s);
+  }
+  // advection (S5) and the liquid-transport potential
+  launch_adj_advect(P, g->a1, cur.omega, cur.T, cur.u, cur.v, cur.w, phi, g->a_new, g->A_al, g->A_ab, g->A_cp,
+                    g->A_Tp, g->A_U, g->A_Ul, g->A_a1, g->A_om, g->A_T, g->A_c, g->partials, cadj, g->grad, s);
+  if (phi) {
+    launch_div_setup(P, cur.u, cur.v, cur.w, g->qc, g->diag, g->b, s);
+    launch_adj_phi_rhs(P, g->A_Ul, g->b, s);
+    if ((st = adj_solve(g, 2, P.dt / (P.h * P.h), g->prm.tol_phi, 3, s, rc)) != DS_OK) return st;
+    launch_adj_phi_faces(P, g->A_Ul, g->lam, g->A_U, s);
+  }
+  // liquid source, redistribution, interface flux (eq. 4, S4, S1-S3)
+  launch_adj_source(P, cur.alpha, g->mraw, g->A_a1, g->A_md, g->A_al, g->scal, g->partials, cadj, g->grad, s);
+  if (P.evaporation)
+    launch_adj_interface(P, cur.alpha, cur.T, cur.omega, cur.u, cur.v, cur.w, g->mraw, g->adj, g->A_md, g->scal,
+                         g->A_al, g->A_T, g->A_om, g->A_U, g->partials, cadj, g->grad, s);
+  HIPCHK(g, hipGetLastError());
+  return DS_OK;
+}
+
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 }  // namespace
@@ -568,8 +789,10 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   }
   g->ws_bytes = carve(g, nullptr);
   if (hipHostMalloc((void**)&g->h_scal, SC_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&g->h_status, 4 * sizeof(SolveStatus), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&g->h_status, 4 * sizeof(SolveStatus), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&g->h_grad, GR_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     if (g->h_scal) (void)hipHostFree(g->h_scal);
+    if (g->h_status) (void)hipHostFree(g->h_status);
     delete g;
     return DS_ERR_HIP;
   }
@@ -583,6 +806,7 @@ int ds_destroy_grid(ds_grid* g) {
     if (g->ev[e]) (void)hipEventDestroy(g->ev[e]);
   if (g->h_scal) (void)hipHostFree(g->h_scal);
   if (g->h_status) (void)hipHostFree(g->h_status);
+  if (g->h_grad) (void)hipHostFree(g->h_grad);
   delete g;
   return DS_OK;
 }
@@ -786,6 +1010,114 @@ int ds_time_operator_kernel(ds_grid* g, int reps, double* avg_us, double* bytes_
   }
   if (us < 0) return fail(g, DS_ERR_HIP, "event timing failed");
   *avg_us = us;
+  return DS_OK;
+}
+
+size_t ds_tape_bytes(const ds_grid* g, int nsteps, int ckpt_every) {
+  if (!g || nsteps < 1 || ckpt_every < 1) return 0;
+  return tape_total_bytes(g, nsteps, std::min(ckpt_every, nsteps));
+}
+
+int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t tape_bytes, void* stream) {
+  if (!g) return DS_ERR_ARG;
+  if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
+  if (nsteps < 1 || ckpt_every < 1 || !tape) return fail(g, DS_ERR_ARG, "nsteps and ckpt_every must be >= 1, tape non-null");
+  const int C = std::min(ckpt_every, nsteps);
+  const size_t need = tape_total_bytes(g, nsteps, C);
+  if (tape_bytes < need) return fail(g, DS_ERR_ARG, "tape too small: %zu < %zu bytes", tape_bytes, need);
+  if (reinterpret_cast<uintptr_t>(tape) % 256 != 0) return fail(g, DS_ERR_ARG, "tape not 256-byte aligned");
+  hipStream_t s = S(stream);
+  g->recorded = false;
+  g->tape = static_cast<char*>(tape);
+  g->tape_bytes = tape_bytes;
+  g->tape_steps = nsteps;
+  g->tape_ckpt = C;
+  carve_tape(g, g->tape);
+  const int nck = tape_nckpt(nsteps, C);
+  int st, rc = DS_OK;
+  if ((st = save_slot(g, slot_at(g, 0), s)) != DS_OK) return st;
+  for (int k = 0; k < nsteps; ++k) {
+    st = one_step(g, s);
+    if (st == DS_ERR_NOT_CONVERGED) rc = st;
+    else if (st != DS_OK) return st;
+    if ((k + 1) % C == 0 && k + 1 < nsteps)
+      if ((st = save_slot(g, slot_at(g, (k + 1) / C), s)) != DS_OK) return st;
+  }
+  if ((st = save_slot(g, slot_at(g, nck), s)) != DS_OK) return st;
+  HIPCHK(g, hipStreamSynchronize(s));
+  g->fuel_mass_final = g->fuel_mass_prev;
+  g->diag_final = g->diag_out;
+  g->recorded = true;
+  if (rc == DS_OK) g->err.clear();
+  return rc;
+}
+
+int ds_adjoint(ds_grid* g, double dJ_dV, double* grads, double* dalpha0, double* dT0, double* domega0, double* du0,
+               double* dv0, double* dw0, void* stream) {
+  if (!g || !grads) return DS_ERR_ARG;
+  if (!g->recorded) return fail(g, DS_ERR_STATE, "ds_forward_record has not been called");
+  if (!std::isfinite(dJ_dV)) return fail(g, DS_ERR_ARG, "dJ_dV is not finite");
+  hipStream_t s = S(stream);
+  const DevParams& P = g->dp;
+  const int N = g->tape_steps, C = g->tape_ckpt, nck = tape_nckpt(N, C);
+  int st, rc = DS_OK;
+  for (int q = 0; q < 4; ++q) g->adj_iters[q] = 0;
+  // adjoint of V_N = h^3 sum(alpha^N)
+  launch_fill(g->A_al, P.h * P.h * P.h * dJ_dV, g->n, s);
+  launch_fill(g->A_c, 0.0, g->n, s);
+  launch_fill(g->A_om, 0.0, g->n, s);
+  launch_fill(g->A_T, 0.0, g->n, s);
+  launch_fill(g->A_U[0], 0.0, g->nu, s);
+  launch_fill(g->A_U[1], 0.0, g->nv, s);
+  launch_fill(g->A_U[2], 0.0, g->nw, s);
+  launch_fill(g->grad, 0.0, GR_COUNT, s);
+  HIPCHK(g, hipGetLastError());
+  for (int sg = nck - 1; sg >= 0; --sg) {
+    const int n0 = sg * C, n1 = std::min(N, n0 + C);
+    // recompute the segment's states from its checkpoint (segment slots q = 0.. hold steps n0+1+q)
+    if (n1 - n0 > 1) {
+      if ((st = load_slot(g, slot_at(g, sg), s)) != DS_OK) return st;
+      for (int k = n0; k < n1 - 1; ++k) {
+        st = one_step(g, s);
+        if (st != DS_OK && st != DS_ERR_NOT_CONVERGED) return st;
+        if ((st = save_slot(g, slot_at(g, nck + 1 + (k - n0)), s)) != DS_OK) return st;
+      }
+    }
+    for (int n = n1 - 1; n >= n0; --n) {
+      const Slot cur = n == n0 ? slot_at(g, sg) : slot_at(g, nck + 1 + (n - n0 - 1));
+      const Slot nxt = n + 1 == n1 ? (n1 == N ? slot_at(g, nck) : slot_at(g, sg + 1)) : slot_at(g, nck + 1 + (n - n0));
+      if ((st = reverse_step(g, cur, nxt, s, &rc)) != DS_OK) return st;
+    }
+  }
+  const Slot s0 = slot_at(g, 0);
+  launch_adj_init_c(P, s0.alpha, s0.omega, g->A_c, g->A_al, g->A_om, g->partials, g->counters + CT_ADJ, g->grad, s);
+  HIPCHK(g, hipGetLastError());
+  HIPCHK(g, hipMemcpyAsync(g->h_grad, g->grad, GR_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+  const size_t nb = g->n * sizeof(double);
+  if (dalpha0) HIPCHK(g, hipMemcpyAsync(dalpha0, g->A_al, nb, hipMemcpyDeviceToDevice, s));
+  if (dT0) HIPCHK(g, hipMemcpyAsync(dT0, g->A_T, nb, hipMemcpyDeviceToDevice, s));
+  if (domega0) HIPCHK(g, hipMemcpyAsync(domega0, g->A_om, nb, hipMemcpyDeviceToDevice, s));
+  if (du0) HIPCHK(g, hipMemcpyAsync(du0, g->A_U[0], g->nu * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (dv0) HIPCHK(g, hipMemcpyAsync(dv0, g->A_U[1], g->nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (dw0) HIPCHK(g, hipMemcpyAsync(dw0, g->A_U[2], g->nw * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // the handle continues from the final state
+  if ((st = load_slot(g, slot_at(g, nck), s)) != DS_OK) return st;
+  HIPCHK(g, hipStreamSynchronize(s));
+  g->fuel_mass_prev = g->fuel_mass_final;
+  g->diag_out = g->diag_final;
+  grads[0] = g->h_grad[GR_D];
+  grads[1] = g->h_grad[GR_DH];
+  grads[2] = g->h_grad[GR_TAMB] + g->h_grad[GR_RHOG] * host_drhoG_dT(g->prm, P.rho_G);
+  if (!std::isfinite(grads[0]) || !std::isfinite(grads[1]) || !std::isfinite(grads[2]))
+    return fail(g, DS_ERR_NONFINITE, "non-finite gradient");
+  if (rc != DS_OK) return fail(g, rc, "an adjoint linear solve reached maxit");
+  g->err.clear();
+  return DS_OK;
+}
+
+int ds_get_adjoint_iterations(const ds_grid* g, int* iters4) {
+  if (!g || !iters4) return DS_ERR_ARG;
+  for (int q = 0; q < 4; ++q) iters4[q] = g->adj_iters[q];
   return DS_OK;
 }
 

@@ -11,10 +11,13 @@ enum Scalar {
   SC_K = 0, SC_S1, SC_S2, SC_NINT,
   SC_BL, SC_BV_ADV, SC_BV_DIFF,
   SC_VOL, SC_FUEL, SC_MDOT, SC_AMIN, SC_AMAX, SC_NONFINITE,
+  SC_ABSMAX,
   SC_COUNT
 };
 // Reduction counters (one per reduction site).
-enum Counter { CT_IFACE = 0, CT_ADV, CT_SPEC, CT_DIAG, CT_SOLVE0, CT_SOLVE1, CT_SOLVE2, CT_MISC, CT_COUNT };
+enum Counter { CT_IFACE = 0, CT_ADV, CT_SPEC, CT_DIAG, CT_SOLVE0, CT_SOLVE1, CT_SOLVE2, CT_MISC, CT_ADJ, CT_COUNT };
+// Device gradient accumulators of the differentiation form.
+enum Grad { GR_D = 0, GR_DH, GR_TAMB, GR_RHOG, GR_S1B, GR_S2B, GR_COUNT };
 
 int grid_blocks(long long n);   // streaming grid size (multiple of 8)
 
@@ -55,6 +58,46 @@ void launch_diagnostics(const DevParams& P, const double* alpha, const double* c
                         double* scal, hipStream_t s);
 void launch_c_from_omega(const DevParams& P, const double* alpha, const double* omega, double* c, hipStream_t s);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
+// max |x| (non-finite entries give +inf) -> *out; x *= a
+void launch_absmax(const double* x, long long n, double* partials, unsigned* counter, double* out, hipStream_t s);
+void launch_scale(double* x, double a, long long n, hipStream_t s);
+
+// ---- adjoint kernels (k_adjoint.hip), in the order of the reverse step
+void launch_adj_project(const DevParams& P, const double* a_new, const double* p, double* const AU[3], double* b,
+                        double* A_ab, double* partials, unsigned* counter, double* grad, hipStream_t s);
+void launch_adj_pressure(const DevParams& P, const double* a_new, const double* p, const double* lam,
+                         const double* mdot, double* A_ab, double* A_md, double* partials, unsigned* counter,
+                         double* grad, hipStream_t s);
+void launch_adj_predictor(const DevParams& P, const double* a_new, const double* xi, double* const AU[3],
+                          double* const AUs[3], double* const Q[6], const double* lam, const double* u,
+                          const double* v, const double* w, double* A_ab, double* partials, unsigned* counter,
+                          double* grad, hipStream_t s);
+void launch_adj_species_rhs(const DevParams& P, const double* a_new, const double* omt, const double* A_om,
+                            const double* A_c, double* b, double* A_ab, double* partials, unsigned* counter,
+                            double* grad, hipStream_t s);
+void launch_adj_species(const DevParams& P, const double* a_new, const double* omt, const double* lam,
+                        const double* u, const double* v, const double* w, double* A_ab, double* A_cp, double* A_md,
+                        double* partials, unsigned* counter, double* grad, hipStream_t s);
+void launch_adj_energy(const DevParams& P, const double* a_new, const double* Tp, const double* Tn, const double* lam,
+                       const double* mdot, const double* u, const double* v, const double* w, double* A_ab,
+                       double* A_Tp, double* A_md, double* partials, unsigned* counter, double* grad, hipStream_t s);
+void launch_adj_advect(const DevParams& P, const double* a1, const double* omega, const double* T, const double* u,
+                       const double* v, const double* w, const double* phi, const double* a_new, const double* A_al,
+                       const double* A_ab, const double* A_cp, const double* A_Tp, double* const AU[3],
+                       double* const AUl[3], double* A_a1, double* A_om, double* A_T, double* A_c, double* partials,
+                       unsigned* counter, double* grad, hipStream_t s);
+void launch_adj_phi_rhs(const DevParams& P, double* const AUl[3], double* b, hipStream_t s);
+void launch_adj_phi_faces(const DevParams& P, double* const AUl[3], const double* lam, double* const AU[3],
+                          hipStream_t s);
+void launch_adj_source(const DevParams& P, const double* alpha, const double* mraw, const double* A_a1, double* A_md,
+                       double* A_al, const double* scal, double* partials, unsigned* counter, double* grad,
+                       hipStream_t s);
+void launch_adj_interface(const DevParams& P, const double* alpha, const double* T, const double* omega,
+                          const double* u, const double* v, const double* w, const double* mraw, const int* adj,
+                          const double* A_md, const double* scal, double* A_al, double* A_T, double* A_om,
+                          double* const AU[3], double* partials, unsigned* counter, double* grad, hipStream_t s);
+void launch_adj_init_c(const DevParams& P, const double* alpha, const double* omega, const double* A_c, double* A_al,
+                       double* A_om, double* partials, unsigned* counter, double* grad, hipStream_t s);
 void launch_int_to_double(const int* src, double* dst, long long n, hipStream_t s);
 
 }  // namespace dsv

@@ -143,6 +143,32 @@ __device__ inline double equilibrium_y(const DevParams& P, double T) {
   return y;
 }
 
+// y(T) with its derivatives in T and dh_ev: closed form for the ideal model,
+// the implicit-function rule on g(y, T, dh) = 0 for Peng-Robinson
+// (dy = -g_T dT/g_y - g_dh ddh/g_y, partials by dual numbers).  A value held
+// at the cap 1 - 1e-12 has zero derivatives.
+__device__ inline double equilibrium_y_grad(const DevParams& P, double T, double& dT, double& ddh) {
+  const double cap = 1.0 - 1e-12;
+  const double y = equilibrium_y(P, T);
+  dT = 0.0;
+  ddh = 0.0;
+  if (P.eq_model == 0) {
+    const double yr = vapour_pressure(P, T, P.dh) / P.p;
+    if (yr <= cap) {
+      dT = yr * (P.dh * P.M_v / R_GAS) / (T * T);
+      ddh = -yr * (P.M_v / R_GAS) * (1.0 / T - 1.0 / P.T_ref);
+    }
+    return y;
+  }
+  if (y >= cap) return y;
+  const dual gy = dlog(mkd(y, 1.0)) + pr_lnphi_fuel<dual>(P, mkd(T), mkd(P.p), mkd(y, 1.0));
+  const dual gT = pr_lnphi_fuel<dual>(P, mkd(T, 1.0), mkd(P.p), mkd(y)) - pr_lnrhs<dual>(P, mkd(T, 1.0), mkd(P.dh));
+  const dual gH = -pr_lnrhs<dual>(P, mkd(T), mkd(P.dh, 1.0));
+  dT = -gT.d / gy.d;
+  ddh = -gH.d / gy.d;
+  return y;
+}
+
 __device__ __forceinline__ double mass_fraction(const DevParams& P, double y) {
   return y * P.M_v / (y * P.M_v + (1.0 - y) * P.M_G);
 }

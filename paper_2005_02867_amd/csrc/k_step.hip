@@ -5,6 +5,7 @@
 
 #include "ds_device.h"
 #include "ds_kernels.h"
+#include "ds_stencil.h"
 #include "ds_thermo.h"
 
 namespace dsv {
@@ -36,11 +37,6 @@ __global__ void k_xi(DevParams P, double* xi) {
 // to the first gas cell (adj), evaporation flux at adj (eqs. 12-14) times
 // |grad alpha| (eq. 17).  The march arithmetic is written with explicitly
 // rounded operations so that each product and sum rounds on its own.
-__device__ __forceinline__ double alpha_or0(const DevParams& P, const double* a, int i, int j, int k) {
-  if (i < 0 || j < 0 || k < 0 || i >= P.nx || j >= P.ny || k >= P.nz) return 0.0;
-  return a[cidx(P, i, j, k)];
-}
-
 __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
                             const double* __restrict__ omega, const double* __restrict__ u,
                             const double* __restrict__ v, const double* __restrict__ w,
@@ -128,44 +124,6 @@ __global__ void k_source(DevParams P, const double* __restrict__ alpha, const do
 }
 
 // ---------------------------------------------------------------- S5
-// TVD (van Leer) face value along one grid line: face f lies between cells
-// f-1 and f; `line` points at cell 0 of the line, `st` is the stride.
-__device__ __forceinline__ double face_value(const double* __restrict__ phi, long long line, long long st,
-                                             int f, int na, double uf, double amb) {
-  if (f == 0) return uf > 0.0 ? amb : phi[line];
-  if (f == na) return uf < 0.0 ? amb : phi[line + (long long)(na - 1) * st];
-  if (uf == 0.0) return 0.0;
-  double C, D, U;
-  if (uf > 0.0) {
-    C = phi[line + (long long)(f - 1) * st];
-    D = phi[line + (long long)f * st];
-    U = (f >= 2) ? phi[line + (long long)(f - 2) * st] : C;
-  } else {
-    C = phi[line + (long long)f * st];
-    D = phi[line + (long long)(f - 1) * st];
-    U = (f + 1 <= na - 1) ? phi[line + (long long)(f + 1) * st] : C;
-  }
-  const double den = D - C;
-  if (den == 0.0) return C;
-  const double r = (C - U) / den;
-  const double ar = fabs(r);
-  const double psi = (r + ar) / (1.0 + ar);
-  return C + 0.5 * psi * den;
-}
-
-// Liquid-marker face velocity: the divergence-free part u - G phi (phi = 0
-// half a cell outside open faces; walls and inlets keep their value).
-__device__ __forceinline__ double liquid_face_u(const DevParams& P, const double* __restrict__ phi, double uf,
-                                                long long line, long long st, int f, int na, int ax) {
-  if (!phi) return uf;
-  if (f == 0 || f == na) {
-    if (!pressure_dirichlet(P.kind[ax * 2 + (f == 0 ? 0 : 1)])) return uf;
-    const double pc = phi[line + (long long)(f == 0 ? 0 : na - 1) * st];
-    return f == 0 ? uf - 2.0 * pc / P.h : uf + 2.0 * pc / P.h;
-  }
-  return uf - (phi[line + (long long)f * st] - phi[line + (long long)(f - 1) * st]) / P.h;
-}
-
 __global__ void k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
                          const double* __restrict__ T, const double* __restrict__ c,
                          const double* __restrict__ u, const double* __restrict__ v,
@@ -240,29 +198,6 @@ __global__ void k_advect(DevParams P, const double* __restrict__ a1, const doubl
 }
 
 // ---------------------------------------------------------------- S6-S8
-// Boundary face velocity of cell (i,j,k) on box face (ax, side).
-__device__ __forceinline__ double bface_u(const DevParams& P, const double* u, const double* v,
-                                          const double* w, int ax, int side, int i, int j, int k) {
-  if (ax == 0) return u[uidx(P, side ? i + 1 : i, j, k)];
-  if (ax == 1) return v[vidx(P, i, side ? j + 1 : j, k)];
-  return w[widx(P, i, j, side ? k + 1 : k)];
-}
-
-// Neighbour of (i,j,k) across face (ax, side); returns -1 outside the box.
-__device__ __forceinline__ long long nbr(const DevParams& P, int ax, int side, int i, int j, int k) {
-  const int d = side ? 1 : -1;
-  if (ax == 0) {
-    const int ii = i + d;
-    return (ii < 0 || ii >= P.nx) ? -1 : cidx(P, ii, j, k);
-  }
-  if (ax == 1) {
-    const int jj = j + d;
-    return (jj < 0 || jj >= P.ny) ? -1 : cidx(P, i, jj, k);
-  }
-  const int kk = k + d;
-  return (kk < 0 || kk >= P.nz) ? -1 : cidx(P, i, j, kk);
-}
-
 // Energy, eq. 8 after the advection: (rho cp/dt) T - div(k grad T) = (rho cp/dt) T' - mdot dh.
 __global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ Tp,
                                const double* __restrict__ mdot, const double* __restrict__ u,
@@ -328,7 +263,7 @@ __global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, c
     qc[c] = th;
     diag[c] = d;
     b[c] = cp_[c] / P.dt + mdot[c];
-    om0[c] = cp_[c] / (P.rho_G * th);
+    if (om0) om0[c] = cp_[c] / (P.rho_G * th);
   }
 }
 
@@ -591,6 +526,27 @@ __global__ void k_fill(double* x, double v, long long n) {
   block_range(n, b0, b1);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) x[e] = v;
 }
+__global__ void k_absmax(const double* __restrict__ x, long long n, double* partials, unsigned* counter,
+                         double* out) {
+  long long b0, b1;
+  block_range(n, b0, b1);
+  double acc[1] = {0.0};
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+    const double v = fabs(x[e]);
+    acc[0] = isfinite(v) ? fmax(acc[0], v) : __builtin_inf();
+  }
+  const int ops[1] = {RMAX};
+  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+    double tot[1];
+    block_combine<1>(ops, partials, counter, tot);
+    if (threadIdx.x == 0) *out = tot[0];
+  }
+}
+__global__ void k_scale(double* x, double a, long long n) {
+  long long b0, b1;
+  block_range(n, b0, b1);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) x[e] *= a;
+}
 __global__ void k_int_to_double(const int* s, double* d, long long n) {
   long long b0, b1;
   block_range(n, b0, b1);
@@ -670,6 +626,12 @@ void launch_c_from_omega(const DevParams& P, const double* alpha, const double* 
 }
 void launch_fill(double* x, double v, long long n, hipStream_t s) {
   k_fill<<<grid_blocks(n), BLOCK, 0, s>>>(x, v, n);
+}
+void launch_absmax(const double* x, long long n, double* partials, unsigned* counter, double* out, hipStream_t s) {
+  k_absmax<<<grid_blocks(n), BLOCK, 0, s>>>(x, n, partials, counter, out);
+}
+void launch_scale(double* x, double a, long long n, hipStream_t s) {
+  k_scale<<<grid_blocks(n), BLOCK, 0, s>>>(x, a, n);
 }
 void launch_int_to_double(const int* src, double* dst, long long n, hipStream_t s) {
   k_int_to_double<<<grid_blocks(n), BLOCK, 0, s>>>(src, dst, n);
