@@ -358,6 +358,429 @@ __global__ void k_zero_if_flagged(double* x, long long n, const SolveStatus* st)
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) x[c] = 0.0;
 }
 
+// ------------------------------------------------------------ z-vectorised kernels
+// Levels whose nz is a multiple of VW<T> (4 floats or 2 doubles, 16 bytes)
+// run these variants: each thread owns VW consecutive z cells, loaded and
+// stored as one 16-byte vector, so a wavefront moves 1 KiB per load
+// instruction instead of 256 B (float).  Items (i, j, kv) are numbered
+// z-fastest; each XCD streams one contiguous eighth of them.  The
+// arithmetic and its order per cell are those of the scalar kernels above.
+template <class T>
+struct VW;
+template <>
+struct VW<float> {
+  static constexpr int n = 4;
+  typedef float4 vec;
+};
+template <>
+struct VW<double> {
+  static constexpr int n = 2;
+  typedef double2 vec;
+};
+
+template <class T>
+__device__ __forceinline__ void ldv(const T* __restrict__ p, T (&o)[VW<T>::n]) {
+  const typename VW<T>::vec v = *reinterpret_cast<const typename VW<T>::vec*>(p);
+  if constexpr (VW<T>::n == 4) {
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  } else {
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+}
+template <class T>
+__device__ __forceinline__ void stv(T* __restrict__ p, const T (&o)[VW<T>::n]) {
+  typename VW<T>::vec v;
+  if constexpr (VW<T>::n == 4) {
+    v.x = o[0];
+    v.y = o[1];
+    v.z = o[2];
+    v.w = o[3];
+  } else {
+    v.x = o[0];
+    v.y = o[1];
+  }
+  *reinterpret_cast<typename VW<T>::vec*>(p) = v;
+}
+
+template <class T>
+inline bool use_vec(const Lev<T>& L) {
+  return L.nz % VW<T>::n == 0;
+}
+template <class T>
+inline long long vec_items(const Lev<T>& L) {
+  return (long long)L.nx * L.ny * (L.nz / VW<T>::n);
+}
+static int vec_blocks(long long items) {
+  long long nb = (items + BLOCK - 1) / BLOCK;
+  nb = std::min<long long>(std::max<long long>(nb, NXCD), 1024);
+  return (int)((nb + NXCD - 1) / NXCD * NXCD);
+}
+
+// Loop over this block's items: declares i, j, kv and c (flat index of the first cell).
+#define FOR_ITEMS(L, T, i, j, kv, c)                                                                         \
+  const int nzv_ = (L).nz / VW<T>::n;                                                                     \
+  const long long nit_ = (long long)(L).nx * (L).ny * nzv_;                                               \
+  const unsigned per_ = gridDim.x / NXCD, loc_ = blockIdx.x / NXCD, xcd_ = blockIdx.x % NXCD;              \
+  const long long chk_ = (nit_ + NXCD - 1) / NXCD;                                                        \
+  const long long e0_ = (long long)xcd_ * chk_, e1_ = min(nit_, e0_ + chk_);                              \
+  int i, j, kv;                                                                                           \
+  long long c;                                                                                            \
+  for (long long e_ = e0_ + (long long)loc_ * BLOCK + threadIdx.x; e_ < e1_; e_ += (long long)per_ * BLOCK) \
+    if ((kv = (int)(e_ % nzv_)), (j = (int)((e_ / nzv_) % (L).ny)), (i = (int)(e_ / nzv_ / (L).ny)),        \
+        (c = ((long long)i * (L).ny + j) * (L).nz + (long long)kv * VW<T>::n), true)
+
+// off[v] = sum_nb (q_v + q_nb) x_nb for the VW cells at c, in the scalar
+// kernels' order (x-, x+, y-, y+, z-, z+).  xc: the cells' own x values;
+// lx(f, out): vector of x at f; sx(f): scalar x at f.
+template <class T, class LX, class SX>
+__device__ __forceinline__ void off_sum_v(const Lev<T>& L, long long c, int i, int j, int kv, const T (&qv)[VW<T>::n],
+                                          const T (&xc)[VW<T>::n], LX lx, SX sx, T (&off)[VW<T>::n]) {
+  constexpr int V = VW<T>::n;
+  const long long sxs = (long long)L.ny * L.nz, sys = L.nz;
+  const int nzv = L.nz / V;
+#pragma unroll
+  for (int v = 0; v < V; ++v) off[v] = 0;
+  auto nbv = [&](long long f) {
+    T g[V], x[V];
+    ldv<T>(L.qc + f, g);
+    lx(f, x);
+#pragma unroll
+    for (int v = 0; v < V; ++v) off[v] += (qv[v] + g[v]) * x[v];
+  };
+  if (i > 0) nbv(c - sxs);
+  if (i < L.nx - 1) nbv(c + sxs);
+  if (j > 0) nbv(c - sys);
+  if (j < L.ny - 1) nbv(c + sys);
+  // z-: inside the vector, or the scalar before it
+  if (kv > 0) off[0] += (qv[0] + L.qc[c - 1]) * sx(c - 1);
+#pragma unroll
+  for (int v = 1; v < V; ++v) off[v] += (qv[v] + qv[v - 1]) * xc[v - 1];
+  // z+
+#pragma unroll
+  for (int v = 0; v < V - 1; ++v) off[v] += (qv[v] + qv[v + 1]) * xc[v + 1];
+  if (kv < nzv - 1) off[V - 1] += (qv[V - 1] + L.qc[c + V]) * sx(c + V);
+}
+
+template <class T>
+__device__ __forceinline__ void apply_v(const Lev<T>& L, const T* __restrict__ x, long long c, int i, int j, int kv,
+                                        const T (&xc)[VW<T>::n], T (&y)[VW<T>::n]) {
+  constexpr int V = VW<T>::n;
+  T qv[V], dg[V], off[V];
+  ldv<T>(L.qc + c, qv);
+  ldv<T>(L.diag + c, dg);
+  off_sum_v<T>(L, c, i, j, kv, qv, xc, [&](long long f, T(&o)[V]) { ldv<T>(x + f, o); },
+               [&](long long f) { return x[f]; }, off);
+#pragma unroll
+  for (int v = 0; v < V; ++v) y[v] = dg[v] * xc[v] - T(0.5) * L.sc * off[v];
+}
+
+template <class T>
+__global__ void k_mg_smooth_zero_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ x, T omega,
+                                   const SolveStatus* st) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n;
+  FOR_ITEMS(L, T, i, j, kv, c) {
+    T rv[V], dv[V], o[V];
+    ldv<T>(r + c, rv);
+    ldv<T>(L.diag + c, dv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = omega * rv[v] / dv[v];
+    stv<T>(x + c, o);
+  }
+}
+
+template <class T, bool DOT>
+__global__ void k_mg_smooth_v(Lev<T> L, const T* __restrict__ r, const T* __restrict__ xin, T* __restrict__ xout,
+                              T omega, SolveStatus* st, double* partials, unsigned* counter, int first) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n;
+  double acc = 0.0;
+  FOR_ITEMS(L, T, i, j, kv, c) {
+    T rv[V], xv[V], ax[V], dv[V], o[V];
+    ldv<T>(r + c, rv);
+    ldv<T>(xin + c, xv);
+    ldv<T>(L.diag + c, dv);
+    apply_v<T>(L, xin, c, i, j, kv, xv, ax);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      o[v] = xv[v] + omega * (rv[v] - ax[v]) / dv[v];
+      if (DOT) acc += (double)rv[v] * (double)o[v];
+    }
+    stv<T>(xout + c, o);
+  }
+  if (DOT) publish_rz(acc, st, partials, counter, first);
+}
+
+// Coarse residual for VW/2 coarse cells per thread (fine rows of VW cells).
+template <class T>
+__global__ void k_mg_restrict_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+                                T* __restrict__ rc, const SolveStatus* st) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n, H = V / 2;
+  // items over the fine level's (I, J, kv) with I, J coarse rows: numbered as a
+  // level of C.nx x C.ny x (F.nz / V) vector items
+  Lev<T> G = C;
+  G.nz = F.nz;   // kv ranges over F.nz / V
+  FOR_ITEMS(G, T, I, J, kv, c_unused) {
+    (void)c_unused;
+    T s[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) s[h] = 0;
+    for (int di = 0; di < 2; ++di)
+      for (int dj = 0; dj < 2; ++dj) {
+        const int i = 2 * I + di, j = 2 * J + dj;
+        if (i >= F.nx || j >= F.ny) continue;
+        const long long f = ((long long)i * F.ny + j) * F.nz + (long long)kv * V;
+        T xv[V], rv[V], ax[V];
+        ldv<T>(x + f, xv);
+        ldv<T>(r + f, rv);
+        apply_v<T>(F, x, f, i, j, kv, xv, ax);
+#pragma unroll
+        for (int h = 0; h < H; ++h) s[h] += (rv[2 * h] - ax[2 * h]) + (rv[2 * h + 1] - ax[2 * h + 1]);
+      }
+    const long long cc = ((long long)I * C.ny + J) * C.nz + (long long)kv * H;
+#pragma unroll
+    for (int h = 0; h < H; ++h) rc[cc + h] = T(0.125) * s[h];
+  }
+}
+
+// x' = x + P xc then one sweep (VW fine cells per thread).
+template <class T, bool DOT>
+__global__ void k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+                                      const T* __restrict__ xc, T* __restrict__ xout, T omega, SolveStatus* st,
+                                      double* partials, unsigned* counter, int first) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n;
+  double acc = 0.0;
+  const long long sxs = (long long)F.ny * F.nz;
+  FOR_ITEMS(F, T, i, j, kv, c) {
+    // x + P xc for the vector of fine row (ii, jj) starting at fine index f (first z = kv*V)
+    auto row = [&](long long f, T(&o)[V]) {
+      const long long rr = f / F.nz;   // ii*ny + jj
+      const int jj = (int)(rr % F.ny), ii = (int)(rr / F.ny);
+      const long long pb = ((long long)(ii >> 1) * C.ny + (jj >> 1)) * C.nz + (long long)kv * (V / 2);
+      ldv<T>(x + f, o);
+#pragma unroll
+      for (int v = 0; v < V; ++v) o[v] += xc[pb + (v >> 1)];
+    };
+    auto one = [&](long long f) -> T {
+      const long long rr = f / F.nz;
+      const int kk = (int)(f - rr * F.nz);
+      const int jj = (int)(rr % F.ny), ii = (int)(rr / F.ny);
+      return x[f] + xc[((long long)(ii >> 1) * C.ny + (jj >> 1)) * C.nz + (kk >> 1)];
+    };
+    T x0[V], rv[V], qv[V], dv[V], off[V], o[V];
+    row(c, x0);
+    ldv<T>(r + c, rv);
+    ldv<T>(F.qc + c, qv);
+    ldv<T>(F.diag + c, dv);
+    off_sum_v<T>(F, c, i, j, kv, qv, x0, row, one, off);
+    (void)sxs;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const T Ax = dv[v] * x0[v] - T(0.5) * F.sc * off[v];
+      o[v] = x0[v] + omega * (rv[v] - Ax) / dv[v];
+      if (DOT) acc += (double)rv[v] * (double)o[v];
+    }
+    stv<T>(xout + c, o);
+  }
+  if (DOT) publish_rz(acc, st, partials, counter, first);
+}
+
+__global__ void k_resid64_v(Lev<double> L, const double* __restrict__ b, const double* __restrict__ x,
+                            double* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
+                            int set_bnorm) {
+  constexpr int V = VW<double>::n;
+  double acc[2] = {0.0, 0.0};
+  FOR_ITEMS(L, double, i, j, kv, c) {
+    double bv[V], xv[V], ax[V], o[V];
+    ldv<double>(b + c, bv);
+    ldv<double>(x + c, xv);
+    apply_v<double>(L, x, c, i, j, kv, xv, ax);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      o[v] = bv[v] - ax[v];
+      acc[0] += bv[v] * bv[v];
+      acc[1] += o[v] * o[v];
+    }
+    stv<double>(r + c, o);
+  }
+  const int ops[2] = {RSUM, RSUM};
+  if (block_reduce_publish<2>(acc, ops, partials, counter)) {
+    double t[2];
+    block_combine<2>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      if (set_bnorm) {
+        st->bb = t[0];
+        st->bnorm = sqrt(t[0]);
+        st->it = 0;
+      }
+      st->rr = t[1];
+      st->zero = st->bb == 0.0;
+      st->res = st->bb == 0.0 ? 0.0 : sqrt(t[1]) / st->bnorm;
+      st->done = (st->bb == 0.0 || st->res <= st->tol) ? 1 : 0;
+    }
+  }
+}
+
+template <class T>
+__global__ void k_inner_init_v(Lev<T> L, const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ x,
+                               SolveStatus* st, double* partials, unsigned* counter) {
+  constexpr int V = VW<T>::n;
+  double acc[1] = {0.0};
+  FOR_ITEMS(L, T, i, j, kv, c) {
+    T rv[V], zv[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      rv[v] = (T)r64[c + v];
+      zv[v] = 0;
+      acc[0] += (double)rv[v] * (double)rv[v];
+    }
+    stv<T>(r + c, rv);
+    stv<T>(x + c, zv);
+  }
+  const int ops[1] = {RSUM};
+  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+    double t[1];
+    block_combine<1>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      st->bb = t[0];
+      st->bnorm = sqrt(t[0]);
+      st->rr = t[0];
+      st->res = t[0] == 0.0 ? 0.0 : 1.0;
+      st->it = 0;
+      st->zero = t[0] == 0.0;
+      st->done = t[0] == 0.0 ? 1 : 0;
+    }
+  }
+}
+
+template <class T>
+__global__ void k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n;
+  double acc = 0.0;
+  FOR_ITEMS(L, T, i, j, kv, c) {
+    T rv[V], dv[V];
+    ldv<T>(r + c, rv);
+    ldv<T>(L.diag + c, dv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc += (double)rv[v] * (double)rv[v] / (double)dv[v];
+  }
+  publish_rz(acc, st, partials, counter, 1);
+}
+
+template <class T, bool JAC>
+__global__ void k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restrict__ r,
+                                const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ q, SolveStatus* st,
+                                double* partials, unsigned* counter, int first) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n;
+  const T be = first ? T(0) : (T)st->beta;
+  double acc[1] = {0.0};
+  auto pnv = [&](long long f, T(&o)[V]) {
+    if (JAC) {
+      T rv[V], dv[V];
+      ldv<T>(r + f, rv);
+      ldv<T>(L.diag + f, dv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) o[v] = rv[v] / dv[v];
+    } else {
+      ldv<T>(z + f, o);
+    }
+    if (!first) {
+      T pv[V];
+      ldv<T>(pin + f, pv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) o[v] = o[v] + be * pv[v];
+    }
+  };
+  auto pns = [&](long long f) -> T {
+    const T zf = JAC ? r[f] / L.diag[f] : z[f];
+    return first ? zf : zf + be * pin[f];
+  };
+  FOR_ITEMS(L, T, i, j, kv, c) {
+    T pc[V], qv[V], dv[V], off[V], y[V];
+    pnv(c, pc);
+    ldv<T>(L.qc + c, qv);
+    ldv<T>(L.diag + c, dv);
+    off_sum_v<T>(L, c, i, j, kv, qv, pc, pnv, pns, off);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      y[v] = dv[v] * pc[v] - T(0.5) * L.sc * off[v];
+      acc[0] += (double)pc[v] * (double)y[v];
+    }
+    stv<T>(pout + c, pc);
+    stv<T>(q + c, y);
+  }
+  const int ops[1] = {RSUM};
+  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+    double t[1];
+    block_combine<1>(ops, partials, counter, t);
+    if (threadIdx.x == 0) st->alpha = st->rz / t[0];
+  }
+}
+
+template <class T, bool JAC>
+__global__ void k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                              const T* __restrict__ q, SolveStatus* st, double* partials, unsigned* counter) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n;
+  const T a = (T)st->alpha;
+  double acc[2] = {0.0, 0.0};
+  FOR_ITEMS(L, T, i, j, kv, c) {
+    T xv[V], rv[V], pv[V], qv[V];
+    ldv<T>(x + c, xv);
+    ldv<T>(r + c, rv);
+    ldv<T>(p + c, pv);
+    ldv<T>(q + c, qv);
+    T dv[V];
+    if (JAC) ldv<T>(L.diag + c, dv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      xv[v] += a * pv[v];
+      rv[v] = rv[v] - a * qv[v];
+      acc[0] += (double)rv[v] * (double)rv[v];
+      if (JAC) acc[1] += (double)rv[v] * (double)rv[v] / (double)dv[v];
+    }
+    stv<T>(x + c, xv);
+    stv<T>(r + c, rv);
+  }
+  const int ops[2] = {RSUM, RSUM};
+  if (block_reduce_publish<2>(acc, ops, partials, counter)) {
+    double t[2];
+    block_combine<2>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      st->it += 1;
+      st->rr = t[0];
+      st->res = sqrt(t[0]) / st->bnorm;
+      if (st->res <= st->tol) {
+        st->done = 1;
+      } else if (st->it >= st->maxit) {
+        st->done = 2;
+      } else if (JAC) {
+        st->beta = t[1] / st->rz;
+        st->rz = t[1];
+      }
+    }
+  }
+}
+
+template <class T>
+__global__ void k_add_correction_v(Lev<T> L, double* __restrict__ x, const T* __restrict__ e) {
+  constexpr int V = VW<T>::n;
+  FOR_ITEMS(L, T, i, j, kv, c) {
+    T ev[V];
+    ldv<T>(e + c, ev);
+#pragma unroll
+    for (int v = 0; v < V; ++v) x[c + v] += (double)ev[v];
+  }
+}
+
 // ------------------------------------------------------------ host side
 template <class T>
 void mg_setup_levels(MgHier<T>& H, int dirmask, hipStream_t s) {
@@ -376,15 +799,23 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   const T om = (T)H.omega;
   T* a = H.x[l];
   T* b = H.t[l];
-  const int nb = tile_blocks(L.ntiles);
+  const bool vec = use_vec(L);
+  const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
   const bool coarsest = (l == H.nlev - 1);
   const int pre = coarsest ? std::max(2, H.coarse_sweeps) : H.nu;
-  k_mg_smooth_zero<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
+  auto smooth = [&](bool d, int df) {
+    if (vec) {
+      if (d) k_mg_smooth_v<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, df);
+      else k_mg_smooth_v<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
+    } else {
+      if (d) k_mg_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, df);
+      else k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
+    }
+  };
+  if (vec) k_mg_smooth_zero_v<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
+  else k_mg_smooth_zero<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
   for (int t = 1; t < pre; ++t) {
-    if (coarsest && dot && t == pre - 1)
-      k_mg_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, dot_first);
-    else
-      k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
+    smooth(coarsest && dot && t == pre - 1, dot_first);
     std::swap(a, b);
   }
   if (coarsest) {
@@ -392,21 +823,27 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
     return;
   }
   const Lev<T>& C = H.lev[l + 1];
-  k_mg_restrict<T><<<tile_blocks(C.ntiles), BLOCK, 0, s>>>(L, C, r, a, H.r[l + 1], st);
+  if (vec) {
+    Lev<T> G = C;
+    G.nz = L.nz;
+    k_mg_restrict_v<T><<<vec_blocks(vec_items(G)), BLOCK, 0, s>>>(L, C, r, a, H.r[l + 1], st);
+  } else {
+    k_mg_restrict<T><<<tile_blocks(C.ntiles), BLOCK, 0, s>>>(L, C, r, a, H.r[l + 1], st);
+  }
   T* xc = nullptr;
   mg_vcycle(H, l + 1, H.r[l + 1], st, partials, counter, false, false, s, &xc);
   for (int t = 0; t < H.nu; ++t) {
     const bool d = dot && t == H.nu - 1;
     if (t == 0) {
-      if (d)
-        k_mg_prolong_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, dot_first);
-      else
-        k_mg_prolong_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, 0);
+      if (vec) {
+        if (d) k_mg_prolong_smooth_v<T, true><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, dot_first);
+        else k_mg_prolong_smooth_v<T, false><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, 0);
+      } else {
+        if (d) k_mg_prolong_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, dot_first);
+        else k_mg_prolong_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, 0);
+      }
     } else {
-      if (d)
-        k_mg_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, dot_first);
-      else
-        k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
+      smooth(d, dot_first);
     }
     std::swap(a, b);
   }
@@ -420,29 +857,39 @@ void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* s
     mg_vcycle(*H, 0, V.r, st, partials, counters + 2, true, true, s, z);
   } else {
     *z = nullptr;
-    k_jac_rz<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2);
+    if (use_vec(L)) k_jac_rz_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2);
+    else k_jac_rz<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2);
   }
 }
 
 template <class T>
 void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
                   unsigned* counters, bool first, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  const int nb = tile_blocks(L.ntiles);
+  const bool vec = use_vec(L);
+  const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
   if (H) {
+    auto kdir = vec ? k_cg_dir_spmv_v<T, false> : k_cg_dir_spmv<T, false>;
     if (ev0) {
       // events attached to the dispatch itself: kernel start and end times
-      hipExtLaunchKernelGGL(k_cg_dir_spmv<T, false>, dim3(nb), dim3(BLOCK), 0, s, ev0, ev1, 0, L, (const T*)*z,
-                            (const T*)V.r, (const T*)V.p, V.p_alt, V.q, st, partials, counters, (int)first);
+      hipExtLaunchKernelGGL(kdir, dim3(nb), dim3(BLOCK), 0, s, ev0, ev1, 0, L, (const T*)*z, (const T*)V.r,
+                            (const T*)V.p, V.p_alt, V.q, st, partials, counters, (int)first);
     } else {
-      k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(L, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      kdir<<<nb, BLOCK, 0, s>>>(L, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
     }
     std::swap(V.p, V.p_alt);
-    k_cg_update<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
+    if (vec) k_cg_update_v<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
+    else k_cg_update<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
     mg_vcycle(*H, 0, V.r, st, partials, counters + 2, false, true, s, z);
   } else {
-    k_cg_dir_spmv<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
-    std::swap(V.p, V.p_alt);
-    k_cg_update<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
+    if (vec) {
+      k_cg_dir_spmv_v<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      std::swap(V.p, V.p_alt);
+      k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
+    } else {
+      k_cg_dir_spmv<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      std::swap(V.p, V.p_alt);
+      k_cg_update<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
+    }
   }
 }
 
@@ -454,11 +901,12 @@ template <class T>
 double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout, T* q, SolveStatus* st,
                               double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                               hipEvent_t e1) {
-  const int nb = tile_blocks(L.ntiles);
-  k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
+  const bool vec = use_vec(L);
+  const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
+  auto kdir = vec ? k_cg_dir_spmv_v<T, false> : k_cg_dir_spmv<T, false>;
+  kdir<<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-  for (int t = 0; t < reps; ++t)
-    k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
+  for (int t = 0; t < reps; ++t) kdir<<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
   if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
@@ -473,7 +921,10 @@ template double replay_operator_kernel<float>(const Lev<float>&, const float*, c
 
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
                     double* partials, unsigned* counter, bool set_bnorm, hipStream_t s) {
-  k_resid64<<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);
+  if (use_vec(L))
+    k_resid64_v<<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);
+  else
+    k_resid64<<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);
 }
 void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s) {
   k_zero_if_flagged<<<grid_blocks(n), BLOCK, 0, s>>>(x, n, st);
@@ -481,11 +932,13 @@ void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipSt
 template <class T>
 void launch_inner_init(const Lev<T>& L, const double* r64, T* r, T* x, SolveStatus* st, double* partials,
                        unsigned* counter, hipStream_t s) {
-  k_inner_init<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, r64, r, x, st, partials, counter);
+  if (use_vec(L)) k_inner_init_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, r64, r, x, st, partials, counter);
+  else k_inner_init<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, r64, r, x, st, partials, counter);
 }
 template <class T>
 void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s) {
-  k_add_correction<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, x, e);
+  if (use_vec(L)) k_add_correction_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, x, e);
+  else k_add_correction<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, x, e);
 }
 void launch_to_float(const double* a, float* b, long long n, hipStream_t s) {
   k_to_float<<<grid_blocks(n), BLOCK, 0, s>>>(a, b, n);
