@@ -46,7 +46,7 @@ struct MgHier {
   T* x[MG_MAXLEV] = {};   // level iterates (ping-pong with t)
   T* t[MG_MAXLEV] = {};
   double omega = 0.9;     // damped Jacobi weight
-  int nu = 2;             // pre = post smoothing sweeps
+  int nu = 4;             // pre = post smoothing sweeps
   int coarse_sweeps = 16; // sweeps on the coarsest level
 };
 
@@ -65,10 +65,12 @@ template <class T>
 void mg_setup_levels(MgHier<T>& H, int dirmask, hipStream_t s);
 
 // Enqueue the start of a solve whose residual is already in V.r (and whose
-// status holds bnorm): z = M^-1 r, rz = <r, z>.  Then iterations.
+// status holds bnorm): z = M^-1 r, rz = <r, z>.  Then iterations.  With
+// keep_direction (a residual replacement inside a running solve), also
+// beta = rz_new/rz_old, so the next iteration continues the direction in V.p.
 template <class T>
 void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
-              unsigned* counters, hipStream_t s);
+              unsigned* counters, hipStream_t s, bool keep_direction = false);
 // ev0/ev1 (may be null): events recorded just before and after the operator
 // kernel (direction update + matrix-free product) of a multigrid iteration.
 template <class T>

@@ -210,6 +210,55 @@ __global__ void k_mg_prolong_smooth(Lev<T> F, Lev<T> C, const T* __restrict__ r,
   if (DOT) publish_rz(acc, st, partials, counter, first);
 }
 
+// All sweeps of the coarsest level in one workgroup (the level fits in LDS):
+// x = omega r/diag, then sweeps-1 damped-Jacobi sweeps, ping-pong in LDS;
+// with DOT the last sweep also publishes <r, x>.  Replaces `sweeps` launches
+// of a few microseconds each by one.
+constexpr int COARSE_MAX = 1024;   // cells of a level solved this way
+template <class T, bool DOT>
+__global__ void __launch_bounds__(BLOCK) k_mg_coarse(Lev<T> L, const T* __restrict__ r, T* __restrict__ xout,
+                                                     T omega, int sweeps, SolveStatus* st, double* partials,
+                                                     unsigned* counter, int first) {
+  if (st->done) return;
+  __shared__ T sr[COARSE_MAX], sq[COARSE_MAX], sd[COARSE_MAX], xa[COARSE_MAX], xb[COARSE_MAX];
+  const int n = (int)L.n;
+  for (int c = threadIdx.x; c < n; c += BLOCK) {
+    sr[c] = r[c];
+    sq[c] = L.qc[c];
+    sd[c] = L.diag[c];
+    xa[c] = omega * sr[c] / sd[c];
+  }
+  __syncthreads();
+  T* a = xa;
+  T* b = xb;
+  const int sx = L.ny * L.nz, sy = L.nz;
+  double acc = 0.0;
+  for (int t = 1; t < sweeps; ++t) {
+    const bool last = t == sweeps - 1;
+    for (int c = threadIdx.x; c < n; c += BLOCK) {
+      const int k = c % L.nz, j = (c / L.nz) % L.ny, i = c / sx;
+      const T q = sq[c];
+      T off = 0;
+      if (i > 0) off += (q + sq[c - sx]) * a[c - sx];
+      if (i < L.nx - 1) off += (q + sq[c + sx]) * a[c + sx];
+      if (j > 0) off += (q + sq[c - sy]) * a[c - sy];
+      if (j < L.ny - 1) off += (q + sq[c + sy]) * a[c + sy];
+      if (k > 0) off += (q + sq[c - 1]) * a[c - 1];
+      if (k < L.nz - 1) off += (q + sq[c + 1]) * a[c + 1];
+      const T ax = sd[c] * a[c] - T(0.5) * L.sc * off;
+      const T xn = a[c] + omega * (sr[c] - ax) / sd[c];
+      b[c] = xn;
+      if (DOT && last) acc += (double)sr[c] * (double)xn;
+    }
+    __syncthreads();
+    T* tmp = a;
+    a = b;
+    b = tmp;
+  }
+  for (int c = threadIdx.x; c < n; c += BLOCK) xout[c] = a[c];
+  if (DOT) publish_rz(acc, st, partials, counter, first);
+}
+
 // ------------------------------------------------------------ CG pieces
 __global__ void k_resid64(Lev<double> L, const double* __restrict__ b, const double* __restrict__ x,
                           double* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
@@ -269,14 +318,15 @@ __global__ void k_inner_init(Lev<T> L, const double* __restrict__ r64, T* __rest
 
 // Jacobi start: rz = sum r^2/diag.
 template <class T>
-__global__ void k_jac_rz(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter) {
+__global__ void k_jac_rz(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
+                         int first) {
   if (st->done) return;
   double acc = 0.0;
   FOR_CELLS(L, i, j, k, c) {
     const double rc = (double)r[c];
     acc += rc * rc / (double)L.diag[c];
   }
-  publish_rz(acc, st, partials, counter, 1);
+  publish_rz(acc, st, partials, counter, first);
 }
 
 // p_out = z + beta p_in (z = r/diag for Jacobi), q = A p_out, <p, q> -> alpha.
@@ -660,7 +710,8 @@ __global__ void k_inner_init_v(Lev<T> L, const double* __restrict__ r64, T* __re
 }
 
 template <class T>
-__global__ void k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter) {
+__global__ void k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
+                           int first) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
   double acc = 0.0;
@@ -671,7 +722,7 @@ __global__ void k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, d
 #pragma unroll
     for (int v = 0; v < V; ++v) acc += (double)rv[v] * (double)rv[v] / (double)dv[v];
   }
-  publish_rz(acc, st, partials, counter, 1);
+  publish_rz(acc, st, partials, counter, first);
 }
 
 template <class T, bool JAC>
@@ -812,6 +863,12 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
       else k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
     }
   };
+  if (coarsest && L.n <= COARSE_MAX) {
+    if (dot) k_mg_coarse<T, true><<<1, BLOCK, 0, s>>>(L, r, a, om, pre, st, partials, counter, dot_first);
+    else k_mg_coarse<T, false><<<1, BLOCK, 0, s>>>(L, r, a, om, pre, st, partials, counter, 0);
+    *out = a;
+    return;
+  }
   if (vec) k_mg_smooth_zero_v<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
   else k_mg_smooth_zero<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
   for (int t = 1; t < pre; ++t) {
@@ -852,13 +909,14 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
 
 template <class T>
 void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
-              unsigned* counters, hipStream_t s) {
+              unsigned* counters, hipStream_t s, bool keep_direction) {
+  const int first = keep_direction ? 0 : 1;
   if (H) {
-    mg_vcycle(*H, 0, V.r, st, partials, counters + 2, true, true, s, z);
+    mg_vcycle(*H, 0, V.r, st, partials, counters + 2, first != 0, true, s, z);
   } else {
     *z = nullptr;
-    if (use_vec(L)) k_jac_rz_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2);
-    else k_jac_rz<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2);
+    if (use_vec(L)) k_jac_rz_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2, first);
+    else k_jac_rz<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2, first);
   }
 }
 
@@ -947,9 +1005,9 @@ void launch_to_float(const double* a, float* b, long long n, hipStream_t s) {
 template void mg_setup_levels<double>(MgHier<double>&, int, hipStream_t);
 template void mg_setup_levels<float>(MgHier<float>&, int, hipStream_t);
 template void cg_start<double>(const Lev<double>&, MgHier<double>*, CgVecs<double>&, double**, SolveStatus*,
-                               double*, unsigned*, hipStream_t);
+                               double*, unsigned*, hipStream_t, bool);
 template void cg_start<float>(const Lev<float>&, MgHier<float>*, CgVecs<float>&, float**, SolveStatus*, double*,
-                              unsigned*, hipStream_t);
+                              unsigned*, hipStream_t, bool);
 template void cg_iteration<double>(const Lev<double>&, MgHier<double>*, CgVecs<double>&, double**, SolveStatus*,
                                    double*, unsigned*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void cg_iteration<float>(const Lev<float>&, MgHier<float>*, CgVecs<float>&, float**, SolveStatus*,
