@@ -24,6 +24,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
+# HBM bytes per launch of the fine-level sweep from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE (separate runs of `bench.py --counters-pass`), each scaled by
+# the ratio of known bytes to the counter's reading for a 1 GiB device copy in
+# the same run; None until measured for the current kernel.
+# Measured for the fine-level sweep of the 256^3 workload: FETCH_SIZE 134769 KiB
+# x 2.000 (the 1 GiB copy reads 524300 KiB) + WRITE_SIZE 65536 KiB x 1.000.
+TRAFFIC_SMOOTH = (134769.0 * (1048576.0 / 524300.0) + 65536.0) * 1024.0
 
 
 def log(msg):
@@ -51,7 +58,8 @@ def timed_run(ds, torch, prm, fields, steps, warmup, timing=False):
     d = g.diagnostics()
     # the same operator kernel replayed back to back on the live pressure system
     rep = g.time_operator_kernel(50) if timing else None
-    return dict(seconds=t1 - t0, iters=iters, kernel=kt, replay=rep, volume=d["volume"], diag=d)
+    rep_s = g.time_kernel(1, 50) if timing else None      # fine-level multigrid sweep
+    return dict(seconds=t1 - t0, iters=iters, kernel=kt, replay=rep, replay_smooth=rep_s, volume=d["volume"], diag=d)
 
 
 def adjoint_cost(ds, torch, W):
@@ -141,6 +149,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
+    ap.add_argument("--counters-pass", action="store_true",
+                    help="short run for hardware-counter passes: one step of the workload, 5 replayed launches of "
+                         "the fine-level sweep, then 3 device copies of 1 GiB (the counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -160,6 +171,19 @@ def main():
     fields = W.initial_fields(prm, **run)
     ncell = prm["nx"] * prm["ny"] * prm["nz"]
 
+    if args.counters_pass:
+        g = ds.Grid(dict(prm, precision=W.PREC_MIXED))
+        g.set_fields(fields)
+        g.step(1)
+        r = g.time_kernel(1, 5)
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_pass": True, "smooth_avg_us": r["avg_us"], "smooth_bytes": r["bytes_per_launch"],
+                          "copy_bytes": 1 << 30}))
+        return
     log(f"precision form (FP32 + FP64 refinement): warmup {args.warmup}, timing {args.steps} steps")
     mixed = timed_run(ds, torch, dict(prm, precision=W.PREC_MIXED), fields, args.steps, args.warmup, timing=True)
     log(f"  {mixed['seconds'] * 1e3 / args.steps:.2f} ms/step, iters {mixed['iters'][-1]}")
@@ -169,18 +193,26 @@ def main():
         fp64 = timed_run(ds, torch, dict(prm, precision=W.PREC_FP64), fields, args.steps, args.warmup, timing=True)
         log(f"  {fp64['seconds'] * 1e3 / args.steps:.2f} ms/step, iters {fp64['iters'][-1]}")
 
+    rs = mixed["replay_smooth"]
     rp = mixed["replay"]
     kt = mixed["kernel"]
-    achieved = rp["bytes_per_launch"] / (rp["avg_us"] * 1e-6) / 1e9
+    achieved = rs["bytes_per_launch"] / (rs["avg_us"] * 1e-6) / 1e9
     roofline = {
-        "kernel": "k_cg_dir_spmv<float,false> (pressure-type CG operator: p = z + beta p fused with q = A p "
-                  "and <p,q>, FP32, 24 B/cell)",
+        "kernel": "k_mg_smooth_v<float,false> (fine-level damped-Jacobi sweep of the multigrid preconditioner, "
+                  "FP32, reads r, x, q_coef, diag and writes x: 20 B/cell; the largest share of step time)",
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_SMOOTH,
+        "avg_us": rs["avg_us"], "bytes_per_launch": rs["bytes_per_launch"],
+        "timing": f"HIP events around {rs['reps']} back-to-back launches on the live pressure system after the "
+                  f"timed steps (stream of the launches)",
+    }
+    ach_op = rp["bytes_per_launch"] / (rp["avg_us"] * 1e-6) / 1e9
+    roofline_op = {
+        "kernel": "k_cg_dir_spmv_v<float,false> (pressure-type CG operator: p = z + beta p fused with q = A p "
+                  "and <p,q>, FP32, 24 B/cell)",
+        "bound": "hbm", "achieved": ach_op, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_op / HBM_PEAK_GBS,
         "avg_us": rp["avg_us"], "bytes_per_launch": rp["bytes_per_launch"],
-        "timing": f"HIP events around {rp['reps']} back-to-back launches on the live pressure system after the "
-                  f"timed steps; events on each in-step dispatch read {kt['avg_us']:.1f} us over "
-                  f"{kt['launches']} launches (timestamp packets add cache work around the kernel)",
+        "in_step_avg_us": kt["avg_us"], "in_step_launches": kt["launches"],
     }
     out = {
         "metric": "cell-steps/s at 256^3 (FP32+refine vs FP64), % HBM peak, adjoint/fwd cost",
@@ -195,6 +227,7 @@ def main():
                                f"dt 5e-6 s, tol 1e-10", "cells": ncell,
                    "iters_T_omega_p_rounds_phi": mixed["iters"][-1]},
         "roofline": roofline,
+        "roofline_cg_operator": roofline_op,
     }
     if fp64:
         v64 = ncell * args.steps / fp64["seconds"]

@@ -242,6 +242,17 @@ int ds_adjoint(ds_grid* g, double dJ_dV, double* grads, double* dalpha0, double*
  * transport potential.  Host only. */
 int ds_get_adjoint_iterations(const ds_grid* g, int* iters4);
 
+/* Measurement hook: replays one solver kernel `reps` times back to back on
+ * the current pressure system (as ds_time_operator_kernel) and returns its
+ * mean duration (us) and algorithmic bytes per launch.
+ *   DS_KERNEL_CG_OPERATOR: the conjugate-gradient operator kernel (above);
+ *   DS_KERNEL_MG_SMOOTH: one damped-Jacobi sweep of the multigrid
+ *     preconditioner on the fine level (reads r, x, q_coef, diag; writes x:
+ *     5 arrays).  Needs pressure_precond = 1.
+ * Only solver scratch vectors are written.  DS_ERR_ARG for an unknown kernel. */
+enum { DS_KERNEL_CG_OPERATOR = 0, DS_KERNEL_MG_SMOOTH = 1 };
+int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* bytes_per_launch, void* stream);
+
 /* Message describing the last error on this handle ("" if none). */
 const char* ds_last_error(const ds_grid* g);
 

@@ -28,7 +28,8 @@ EXPORTS = ("ds_create_grid", "ds_destroy_grid", "ds_workspace_bytes", "ds_set_fi
            "ds_step", "ds_solve_pressure", "ds_evaporation_rate", "ds_droplet_volume", "ds_get_diagnostics",
            "ds_get_internal", "ds_last_error", "ds_set_kernel_timing", "ds_get_kernel_timing",
            "ds_time_operator_kernel", "ds_tape_bytes", "ds_forward_record", "ds_adjoint",
-           "ds_get_adjoint_iterations")
+           "ds_get_adjoint_iterations", "ds_time_kernel")
+KERNEL_CG_OPERATOR, KERNEL_MG_SMOOTH = 0, 1
 
 
 class Params(C.Structure):
@@ -83,6 +84,7 @@ _lib.ds_tape_bytes.restype = C.c_size_t
 _lib.ds_forward_record.argtypes = [_P, C.c_int, C.c_int, _P, C.c_size_t, _P]
 _lib.ds_adjoint.argtypes = [_P, C.c_double, C.POINTER(C.c_double)] + [_P] * 6 + [_P]
 _lib.ds_get_adjoint_iterations.argtypes = [_P, C.POINTER(C.c_int)]
+_lib.ds_time_kernel.argtypes = [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]
 _lib.ds_last_error.argtypes = [_P]
 _lib.ds_last_error.restype = C.c_char_p
 
@@ -236,6 +238,13 @@ def get_adjoint_iterations(h):
     return dict(p=it[0], omega=it[1], T=it[2], phi=it[3])
 
 
+def time_kernel(h, which, reps=50):
+    us = C.c_double()
+    nb = C.c_double()
+    _check(h, _lib.ds_time_kernel(h, int(which), int(reps), C.byref(us), C.byref(nb), _stream()))
+    return dict(avg_us=us.value, bytes_per_launch=nb.value, reps=int(reps))
+
+
 # ------------------------------------------------------------ convenience
 class Grid:
     """A handle plus its torch-allocated workspace on the current CUDA device."""
@@ -303,6 +312,9 @@ class Grid:
 
     def time_operator_kernel(self, reps=50):
         return time_operator_kernel(self.h, reps)
+
+    def time_kernel(self, which, reps=50):
+        return time_kernel(self.h, which, reps)
 
     def forward_record(self, nsteps, ckpt_every=1):
         """Run nsteps steps storing the tape for adjoint() (allocated here, on

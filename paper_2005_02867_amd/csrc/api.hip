@@ -70,7 +70,8 @@ struct ds_grid {
   int dirmask = 0;                 // p_rgh = 0 box faces
   int batch_p = 4;
   struct {
-    double inner_min = 1e-3;   // smallest FP32 inner relative tolerance per round
+    double inner_min = 1e-3;   // smallest FP32 inner relative tolerance per round (pressure-type)
+    double inner_min_jac = 1e-6;  // the same for the energy and species systems
   } tune;
   // live timing of the pressure solve's fine-level operator kernel
   static constexpr int NEV = 256;
@@ -415,7 +416,8 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     // Ask the FP32 solve for the reduction still needed (with a margin), but
     // not below what FP32 arithmetic reliably attains.
     const double need = 0.5 * tol / std::max(g->h_status[sys].res, 1e-300);
-    const double inner_tol = std::min(0.5, std::max(g->tune.inner_min, need));
+    const double floor = H || sys == 2 ? g->tune.inner_min : g->tune.inner_min_jac;
+    const double inner_tol = std::min(0.5, std::max(floor, need));
     if ((st = init_status(g, 3, inner_tol, g->prm.maxit, s)) != DS_OK) return st;
     launch_inner_init<float>(F, g->r, g->r32, g->e32, si, g->partials, g->counters + CT_SOLVE1, s);
     g->h_status[3].it = 0;
@@ -782,6 +784,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
       if (pressure_dirichlet(P.kind[ax * 2 + sd])) g->dirmask |= 1 << (ax * 2 + sd);
   lev_dims(g->L0, nx, ny, nz, 1.0);
   if (const char* e = getenv("DSVOF_INNER_MIN")) g->tune.inner_min = atof(e);
+  if (const char* e = getenv("DSVOF_INNER_MIN_JAC")) g->tune.inner_min_jac = atof(e);
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {
     if (prm->pressure_precond == 1) build_hier(g->H32, nx, ny, nz, prm->h, prm->dt);
@@ -977,7 +980,14 @@ int ds_get_kernel_timing(const ds_grid* g, double* avg_us, long long* launches, 
 }
 
 int ds_time_operator_kernel(ds_grid* g, int reps, double* avg_us, double* bytes_per_launch, void* stream) {
+  return ds_time_kernel(g, DS_KERNEL_CG_OPERATOR, reps, avg_us, bytes_per_launch, stream);
+}
+
+int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* bytes_per_launch, void* stream) {
   if (!g || reps < 1 || !avg_us) return DS_ERR_ARG;
+  if (which != DS_KERNEL_CG_OPERATOR && which != DS_KERNEL_MG_SMOOTH) return fail(g, DS_ERR_ARG, "unknown kernel %d", which);
+  if (which == DS_KERNEL_MG_SMOOTH && g->prm.pressure_precond != 1)
+    return fail(g, DS_ERR_ARG, "the multigrid smoother needs pressure_precond = 1");
   if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
   hipStream_t s = S(stream);
   if (!g->ev[0])
@@ -991,22 +1001,31 @@ int ds_time_operator_kernel(ds_grid* g, int reps, double* avg_us, double* bytes_
   HIPCHK(g, hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
   double us;
   const DevParams& P = g->dp;
+  const bool smooth = which == DS_KERNEL_MG_SMOOTH;
   if (g->prm.precision == DS_PREC_MIXED) {
     Lev<float> F;
     lev_dims(F, P.nx, P.ny, P.nz, P.dt / (P.h * P.h));
     F.qc = g->qc32;
     F.diag = g->diag32;
-    us = replay_operator_kernel<float>(F, g->r32, g->p32, g->p32alt, g->q32, st, g->partials,
-                                       g->counters + CT_MISC, reps, s, g->ev[0], g->ev[1]);
-    if (bytes_per_launch) *bytes_per_launch = 24.0 * (double)g->n;
+    if (smooth)
+      us = replay_smooth_kernel<float>(F, g->r32, g->H32.x[0], g->H32.t[0], st, reps, g->H32.omega, s, g->ev[0],
+                                       g->ev[1]);
+    else
+      us = replay_operator_kernel<float>(F, g->r32, g->p32, g->p32alt, g->q32, st, g->partials,
+                                         g->counters + CT_MISC, reps, s, g->ev[0], g->ev[1]);
+    if (bytes_per_launch) *bytes_per_launch = (smooth ? 20.0 : 24.0) * (double)g->n;
   } else {
     Lev<double> L = g->L0;
     L.sc = P.dt / (P.h * P.h);
     L.qc = g->qc;
     L.diag = g->diag;
-    us = replay_operator_kernel<double>(L, g->r, g->pd, g->p_alt, g->q, st, g->partials, g->counters + CT_MISC,
-                                        reps, s, g->ev[0], g->ev[1]);
-    if (bytes_per_launch) *bytes_per_launch = 48.0 * (double)g->n;
+    if (smooth)
+      us = replay_smooth_kernel<double>(L, g->r, g->H64.x[0], g->H64.t[0], st, reps, g->H64.omega, s, g->ev[0],
+                                        g->ev[1]);
+    else
+      us = replay_operator_kernel<double>(L, g->r, g->pd, g->p_alt, g->q, st, g->partials, g->counters + CT_MISC,
+                                          reps, s, g->ev[0], g->ev[1]);
+    if (bytes_per_launch) *bytes_per_launch = (smooth ? 40.0 : 48.0) * (double)g->n;
   }
   if (us < 0) return fail(g, DS_ERR_HIP, "event timing failed");
   *avg_us = us;

@@ -82,6 +82,10 @@ double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout
                               double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                               hipEvent_t e1);
 
+template <class T>
+double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, SolveStatus* st, int reps,
+                            double omega, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+
 // r = b - A x (FP64), ||b|| (if set_bnorm), ||r|| -> status (done if ||r|| <= tol ||b||).
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
                     double* partials, unsigned* counter, bool set_bnorm, hipStream_t s);

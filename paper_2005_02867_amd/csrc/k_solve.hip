@@ -543,6 +543,38 @@ __global__ void k_mg_smooth_zero_v(Lev<T> L, const T* __restrict__ r, T* __restr
   }
 }
 
+// The first two sweeps from x = 0 in one pass: x1 = omega r/diag is formed
+// on the fly (also at the neighbours), x2 = x1 + omega (r - A x1)/diag.
+template <class T>
+__global__ void k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ xout, T omega,
+                                  const SolveStatus* st) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n;
+  auto x1v = [&](long long f, T(&o)[V]) {
+    T rv[V], dv[V];
+    ldv<T>(r + f, rv);
+    ldv<T>(L.diag + f, dv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = omega * rv[v] / dv[v];
+  };
+  auto x1s = [&](long long f) -> T { return omega * r[f] / L.diag[f]; };
+  FOR_ITEMS(L, T, i, j, kv, c) {
+    T rv[V], dv[V], qv[V], x1[V], off[V], o[V];
+    ldv<T>(r + c, rv);
+    ldv<T>(L.diag + c, dv);
+    ldv<T>(L.qc + c, qv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) x1[v] = omega * rv[v] / dv[v];
+    off_sum_v<T>(L, c, i, j, kv, qv, x1, x1v, x1s, off);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const T ax = dv[v] * x1[v] - T(0.5) * L.sc * off[v];
+      o[v] = x1[v] + omega * (rv[v] - ax) / dv[v];
+    }
+    stv<T>(xout + c, o);
+  }
+}
+
 template <class T, bool DOT>
 __global__ void k_mg_smooth_v(Lev<T> L, const T* __restrict__ r, const T* __restrict__ xin, T* __restrict__ xout,
                               T omega, SolveStatus* st, double* partials, unsigned* counter, int first) {
@@ -869,9 +901,16 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
     *out = a;
     return;
   }
-  if (vec) k_mg_smooth_zero_v<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
-  else k_mg_smooth_zero<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
-  for (int t = 1; t < pre; ++t) {
+  int t0 = 1;
+  if (vec && pre >= 2 && !(coarsest && dot && pre == 2)) {
+    k_mg_smooth_two_v<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
+    t0 = 2;
+  } else if (vec) {
+    k_mg_smooth_zero_v<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
+  } else {
+    k_mg_smooth_zero<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
+  }
+  for (int t = t0; t < pre; ++t) {
     smooth(coarsest && dot && t == pre - 1, dot_first);
     std::swap(a, b);
   }
@@ -970,6 +1009,27 @@ double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
   return 1e3 * (double)ms / reps;
 }
+// Back-to-back launches of the fine level's damped-Jacobi sweep (the
+// multigrid smoother) between two events; mean duration in microseconds.
+template <class T>
+double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, SolveStatus* st, int reps,
+                            double omega, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const bool vec = use_vec(L);
+  const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
+  auto ks = vec ? k_mg_smooth_v<T, false> : k_mg_smooth<T, false>;
+  ks<<<nb, BLOCK, 0, s>>>(L, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
+  if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
+  for (int t = 0; t < reps; ++t) ks<<<nb, BLOCK, 0, s>>>(L, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
+  if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+  return 1e3 * (double)ms / reps;
+}
+template double replay_smooth_kernel<double>(const Lev<double>&, const double*, const double*, double*, SolveStatus*,
+                                             int, double, hipStream_t, hipEvent_t, hipEvent_t);
+template double replay_smooth_kernel<float>(const Lev<float>&, const float*, const float*, float*, SolveStatus*, int,
+                                            double, hipStream_t, hipEvent_t, hipEvent_t);
+
 template double replay_operator_kernel<double>(const Lev<double>&, const double*, const double*, double*, double*,
                                                SolveStatus*, double*, unsigned*, int, hipStream_t, hipEvent_t,
                                                hipEvent_t);
