@@ -184,7 +184,7 @@ def main():
         print(json.dumps({"counters_pass": True, "smooth_avg_us": r["avg_us"], "smooth_bytes": r["bytes_per_launch"],
                           "copy_bytes": 1 << 30}))
         return
-    log(f"precision form (FP32 + FP64 refinement): warmup {args.warmup}, timing {args.steps} steps")
+    log(f"precision form (FP32 multigrid and FP32 CG rounds, FP64 residuals): warmup {args.warmup}, timing {args.steps} steps")
     mixed = timed_run(ds, torch, dict(prm, precision=W.PREC_MIXED), fields, args.steps, args.warmup, timing=True)
     log(f"  {mixed['seconds'] * 1e3 / args.steps:.2f} ms/step, iters {mixed['iters'][-1]}")
     fp64 = None
@@ -208,11 +208,10 @@ def main():
     }
     ach_op = rp["bytes_per_launch"] / (rp["avg_us"] * 1e-6) / 1e9
     roofline_op = {
-        "kernel": "k_cg_dir_spmv_v<float,false> (pressure-type CG operator: p = z + beta p fused with q = A p "
-                  "and <p,q>, FP32, 24 B/cell)",
+        "kernel": "k_cg_dir_spmv_z32_v (pressure CG operator of the precision form: p = z + beta p with z in FP32, "
+                  "fused with q = A p and <p,q> in FP64; 44 B/cell)",
         "bound": "hbm", "achieved": ach_op, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_op / HBM_PEAK_GBS,
         "avg_us": rp["avg_us"], "bytes_per_launch": rp["bytes_per_launch"],
-        "in_step_avg_us": kt["avg_us"], "in_step_launches": kt["launches"],
     }
     out = {
         "metric": "cell-steps/s at 256^3 (FP32+refine vs FP64), % HBM peak, adjoint/fwd cost",

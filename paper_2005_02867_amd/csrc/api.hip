@@ -72,6 +72,7 @@ struct ds_grid {
   struct {
     double inner_min = 1e-3;   // smallest FP32 inner relative tolerance per round (pressure-type)
     double inner_min_jac = 1e-6;  // the same for the energy and species systems
+    int mg32 = 1;                 // multigrid systems: FP64 CG with the FP32 V-cycle
   } tune;
   // live timing of the pressure solve's fine-level operator kernel
   static constexpr int NEV = 256;
@@ -288,7 +289,8 @@ void build_hier(MgHier<T>& H, int nx, int ny, int nz, double h, double dt) {
   H.nlev = 0;
   double hl = h;
   int mindim = 8;
-  if (const char* e = getenv("DSVOF_MG_NU")) H.nu = std::max(1, atoi(e));
+  if (const char* e = getenv("DSVOF_MG_NU")) H.nu = H.nu_fine = std::max(1, atoi(e));
+  if (const char* e = getenv("DSVOF_MG_NU_FINE")) H.nu_fine = std::max(1, atoi(e));
   if (const char* e = getenv("DSVOF_MG_COARSE")) H.coarse_sweeps = std::max(2, atoi(e));
   if (const char* e = getenv("DSVOF_MG_MINDIM")) mindim = std::max(4, atoi(e));
   if (const char* e = getenv("DSVOF_MG_OMEGA")) H.omega = atof(e);
@@ -454,8 +456,61 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   return g->h_status[sys].done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
 }
 
+// Precision form of a multigrid-preconditioned solve: FP64 conjugate
+// gradients (operator, vectors, dot products) with the V-cycle -- the bulk of
+// each iteration's memory traffic -- in FP32 on FP32 copies of the operator.
+// No restarts: the FP64 recurrence converges to tol like cg_solve64.
+int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
+  int st;
+  const int sys = 2;
+  Lev<double> L = g->L0;
+  L.sc = sc;
+  L.qc = g->qc;
+  L.diag = g->diag;
+  Lev<float> F;
+  lev_dims(F, L.nx, L.ny, L.nz, sc);
+  F.qc = g->qc32;
+  F.diag = g->diag32;
+  launch_to_float(g->qc, g->qc32, g->n, s);
+  launch_to_float(g->diag, g->diag32, g->n, s);
+  MgHier<float>& H = g->H32;
+  H.lev[0] = F;
+  mg_setup_levels(H, g->dirmask, s);
+  SolveStatus* ss = g->status + sys;
+  if ((st = init_status(g, sys, tol, g->prm.maxit, s)) != DS_OK) return st;
+  launch_resid64(L, g->b, x, g->r, ss, g->partials, g->counters + CT_SOLVE0, true, s);
+  launch_zero_if_flagged(x, g->n, ss, s);
+  HIPCHK(g, hipGetLastError());
+  if ((st = sync_status(g, sys, s)) != DS_OK) return st;
+  if (!g->h_status[sys].done) {
+    CgVecs<double> V{x, g->r, g->pd, g->p_alt, g->q};
+    float* z = nullptr;
+    cg_start_mg32(L, H, g->r, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, s);
+    bool first = true;
+    while (!g->h_status[sys].done) {
+      const int m = batch_of(g, sys);
+      for (int t = 0; t < m; ++t) {
+        cg_iteration_mg32(L, H, V, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, first, s);
+        first = false;
+      }
+      HIPCHK(g, hipGetLastError());
+      if ((st = sync_status(g, sys, s)) != DS_OK) return st;
+    }
+  }
+  const SolveStatus& h = g->h_status[sys];
+  batch_of(g, sys) = std::max(2, std::min(256, h.it / 2 + 1));
+  *iters = h.it;
+  *res = h.res;
+  g->diag_out.refinements_p = 0;
+  return h.done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
+}
+
 int solve(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
-  if (g->prm.precision == DS_PREC_MIXED) return cg_solve_mixed(g, sys, sc, x, s, iters, res, tol);
+  if (g->prm.precision == DS_PREC_MIXED) {
+    if (sys == 2 && g->prm.pressure_precond == 1 && g->tune.mg32 && mg32_supported(g->L0))
+      return cg_solve64_mg32(g, sc, x, s, iters, res, tol);
+    return cg_solve_mixed(g, sys, sc, x, s, iters, res, tol);
+  }
   return cg_solve64(g, sys, sc, x, s, iters, res, tol);
 }
 int solve(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res) {
@@ -785,6 +840,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   lev_dims(g->L0, nx, ny, nz, 1.0);
   if (const char* e = getenv("DSVOF_INNER_MIN")) g->tune.inner_min = atof(e);
   if (const char* e = getenv("DSVOF_INNER_MIN_JAC")) g->tune.inner_min_jac = atof(e);
+  if (const char* e = getenv("DSVOF_MG32")) g->tune.mg32 = atoi(e);
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {
     if (prm->pressure_precond == 1) build_hier(g->H32, nx, ny, nz, prm->h, prm->dt);
@@ -1007,13 +1063,25 @@ int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* byte
     lev_dims(F, P.nx, P.ny, P.nz, P.dt / (P.h * P.h));
     F.qc = g->qc32;
     F.diag = g->diag32;
-    if (smooth)
+    const bool z32 = g->prm.pressure_precond == 1 && g->tune.mg32 && mg32_supported(g->L0);
+    if (smooth) {
       us = replay_smooth_kernel<float>(F, g->r32, g->H32.x[0], g->H32.t[0], st, reps, g->H32.omega, s, g->ev[0],
                                        g->ev[1]);
-    else
+      if (bytes_per_launch) *bytes_per_launch = 20.0 * (double)g->n;
+    } else if (z32) {
+      // the pressure solve's operator: FP64 with the FP32 preconditioned residual z
+      Lev<double> L = g->L0;
+      L.sc = P.dt / (P.h * P.h);
+      L.qc = g->qc;
+      L.diag = g->diag;
+      us = replay_operator_z32(L, g->r32, g->pd, g->p_alt, g->q, st, g->partials, g->counters + CT_MISC, reps, s,
+                               g->ev[0], g->ev[1]);
+      if (bytes_per_launch) *bytes_per_launch = 44.0 * (double)g->n;
+    } else {
       us = replay_operator_kernel<float>(F, g->r32, g->p32, g->p32alt, g->q32, st, g->partials,
                                          g->counters + CT_MISC, reps, s, g->ev[0], g->ev[1]);
-    if (bytes_per_launch) *bytes_per_launch = (smooth ? 20.0 : 24.0) * (double)g->n;
+      if (bytes_per_launch) *bytes_per_launch = 24.0 * (double)g->n;
+    }
   } else {
     Lev<double> L = g->L0;
     L.sc = P.dt / (P.h * P.h);

@@ -47,6 +47,7 @@ struct MgHier {
   T* t[MG_MAXLEV] = {};
   double omega = 0.9;     // damped Jacobi weight
   int nu = 4;             // pre = post smoothing sweeps
+  int nu_fine = 4;        // the same on the finest level
   int coarse_sweeps = 16; // sweeps on the coarsest level
 };
 
@@ -85,6 +86,18 @@ double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout
 template <class T>
 double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, SolveStatus* st, int reps,
                             double omega, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+
+// FP64 conjugate gradients preconditioned by the FP32 multigrid V-cycle
+// (operator, vectors and dot products in FP64; the V-cycle's sweeps, its
+// operator copies and r, z in FP32).  Needs mg32_supported(L).
+bool mg32_supported(const Lev<double>& L);
+double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
+                           SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1);
+void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, float* r32, float** z, SolveStatus* st,
+                   double* partials, unsigned* counters, hipStream_t s);
+void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V, float* r32, float** z,
+                       SolveStatus* st, double* partials, unsigned* counters, bool first, hipStream_t s);
 
 // r = b - A x (FP64), ||b|| (if set_bnorm), ||r|| -> status (done if ||r|| <= tol ||b||).
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,

@@ -853,6 +853,89 @@ __global__ void k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, co
   }
 }
 
+// FP64 CG with the FP32 multigrid preconditioner: the update also stores
+// r in FP32 for the V-cycle; the direction update reads z in FP32.
+__global__ void k_cg_update_r32_v(Lev<double> L, double* __restrict__ x, double* __restrict__ r,
+                                  const double* __restrict__ p, const double* __restrict__ q, float* __restrict__ r32,
+                                  SolveStatus* st, double* partials, unsigned* counter) {
+  if (st->done) return;
+  constexpr int V = VW<double>::n;
+  const double a = st->alpha;
+  double acc[1] = {0.0};
+  FOR_ITEMS(L, double, i, j, kv, c) {
+    double xv[V], rv[V], pv[V], qv[V];
+    ldv<double>(x + c, xv);
+    ldv<double>(r + c, rv);
+    ldv<double>(p + c, pv);
+    ldv<double>(q + c, qv);
+    float2 rf;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      xv[v] += a * pv[v];
+      rv[v] = rv[v] - a * qv[v];
+      acc[0] += rv[v] * rv[v];
+    }
+    rf.x = (float)rv[0];
+    rf.y = (float)rv[1];
+    stv<double>(x + c, xv);
+    stv<double>(r + c, rv);
+    *reinterpret_cast<float2*>(r32 + c) = rf;
+  }
+  const int ops[1] = {RSUM};
+  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+    double t[1];
+    block_combine<1>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      st->it += 1;
+      st->rr = t[0];
+      st->res = sqrt(t[0]) / st->bnorm;
+      if (st->res <= st->tol) st->done = 1;
+      else if (st->it >= st->maxit) st->done = 2;
+    }
+  }
+}
+
+__global__ void k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const double* __restrict__ pin,
+                                    double* __restrict__ pout, double* __restrict__ q, SolveStatus* st,
+                                    double* partials, unsigned* counter, int first) {
+  if (st->done) return;
+  constexpr int V = VW<double>::n;
+  const double be = first ? 0.0 : st->beta;
+  double acc[1] = {0.0};
+  auto pnv = [&](long long f, double(&o)[V]) {
+    const float2 zf = *reinterpret_cast<const float2*>(z + f);
+    o[0] = (double)zf.x;
+    o[1] = (double)zf.y;
+    if (!first) {
+      double pv[V];
+      ldv<double>(pin + f, pv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) o[v] = o[v] + be * pv[v];
+    }
+  };
+  auto pns = [&](long long f) -> double { return first ? (double)z[f] : (double)z[f] + be * pin[f]; };
+  FOR_ITEMS(L, double, i, j, kv, c) {
+    double pc[V], qv[V], dv[V], off[V], y[V];
+    pnv(c, pc);
+    ldv<double>(L.qc + c, qv);
+    ldv<double>(L.diag + c, dv);
+    off_sum_v<double>(L, c, i, j, kv, qv, pc, pnv, pns, off);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      y[v] = dv[v] * pc[v] - 0.5 * L.sc * off[v];
+      acc[0] += pc[v] * y[v];
+    }
+    stv<double>(pout + c, pc);
+    stv<double>(q + c, y);
+  }
+  const int ops[1] = {RSUM};
+  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+    double t[1];
+    block_combine<1>(ops, partials, counter, t);
+    if (threadIdx.x == 0) st->alpha = st->rz / t[0];
+  }
+}
+
 template <class T>
 __global__ void k_add_correction_v(Lev<T> L, double* __restrict__ x, const T* __restrict__ e) {
   constexpr int V = VW<T>::n;
@@ -885,7 +968,8 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   const bool vec = use_vec(L);
   const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
   const bool coarsest = (l == H.nlev - 1);
-  const int pre = coarsest ? std::max(2, H.coarse_sweeps) : H.nu;
+  const int nu = l == 0 ? H.nu_fine : H.nu;
+  const int pre = coarsest ? std::max(2, H.coarse_sweeps) : nu;
   auto smooth = [&](bool d, int df) {
     if (vec) {
       if (d) k_mg_smooth_v<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, df);
@@ -928,8 +1012,8 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   }
   T* xc = nullptr;
   mg_vcycle(H, l + 1, H.r[l + 1], st, partials, counter, false, false, s, &xc);
-  for (int t = 0; t < H.nu; ++t) {
-    const bool d = dot && t == H.nu - 1;
+  for (int t = 0; t < nu; ++t) {
+    const bool d = dot && t == nu - 1;
     if (t == 0) {
       if (vec) {
         if (d) k_mg_prolong_smooth_v<T, true><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, dot_first);
@@ -1060,6 +1144,34 @@ void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s
 }
 void launch_to_float(const double* a, float* b, long long n, hipStream_t s) {
   k_to_float<<<grid_blocks(n), BLOCK, 0, s>>>(a, b, n);
+}
+
+// FP64 CG preconditioned by the FP32 V-cycle (levels whose nz is even).
+void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, float* r32, float** z, SolveStatus* st,
+                   double* partials, unsigned* counters, hipStream_t s) {
+  k_to_float<<<grid_blocks(L.n), BLOCK, 0, s>>>(r64, r32, L.n);
+  mg_vcycle(H, 0, r32, st, partials, counters + 2, true, true, s, z);
+}
+void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V, float* r32, float** z,
+                       SolveStatus* st, double* partials, unsigned* counters, bool first, hipStream_t s) {
+  const int nb = vec_blocks(vec_items(L));
+  k_cg_dir_spmv_z32_v<<<nb, BLOCK, 0, s>>>(L, *z, V.p, V.p_alt, V.q, st, partials, counters, first);
+  std::swap(V.p, V.p_alt);
+  k_cg_update_r32_v<<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, r32, st, partials, counters + 1);
+  mg_vcycle(H, 0, r32, st, partials, counters + 2, false, true, s, z);
+}
+bool mg32_supported(const Lev<double>& L) { return use_vec(L); }
+double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
+                           SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1) {
+  const int nb = vec_blocks(vec_items(L));
+  k_cg_dir_spmv_z32_v<<<nb, BLOCK, 0, s>>>(L, z, pin, pout, q, st, partials, counter, 0);
+  if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
+  for (int t = 0; t < reps; ++t) k_cg_dir_spmv_z32_v<<<nb, BLOCK, 0, s>>>(L, z, pin, pout, q, st, partials, counter, 0);
+  if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+  return 1e3 * (double)ms / reps;
 }
 
 template void mg_setup_levels<double>(MgHier<double>&, int, hipStream_t);
