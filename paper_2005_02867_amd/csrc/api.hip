@@ -33,7 +33,7 @@ double host_pr_Z(double T, double p, double Tc, double Pc, double om) {
     const double f = ((z + c2) * z + c1) * z + c0, fp = (3.0 * z + 2.0 * c2) * z + c1;
     const double dz = f / fp;
     z -= dz;
-    if (std::fabs(dz) <= 1e-16 * std::fabs(z)) break;
+    if (std::fabs(dz) <= 4.5e-16 * std::fabs(z)) break;
   }
   return z;
 }
@@ -67,6 +67,8 @@ struct ds_grid {
   Lev<double> L0;                  // fine-level dimensions and tiles (operator pointers set per solve)
   float *qc32 = nullptr, *diag32 = nullptr;
   float *e32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p32alt = nullptr, *q32 = nullptr;
+  double* zj = nullptr;            // Jacobi z = r/diag (FP64 solves)
+  float* zj32 = nullptr;           // the same for the FP32 rounds
   int dirmask = 0;                 // p_rgh = 0 box faces
   int batch_p = 4;
   struct {
@@ -167,6 +169,7 @@ size_t carve(ds_grid* g, char* base) {
   g->status = L.take<SolveStatus>(base, 4);
   g->p_alt = L.take<double>(base, n);
   g->phi = L.take<double>(base, n);
+  g->zj = L.take<double>(base, n);
   // FP64 multigrid levels (level 0 uses qc/diag of the pressure system)
   MgHier<double>& H = g->H64;
   H.lev[0].qc = g->qc;
@@ -202,6 +205,7 @@ size_t carve(ds_grid* g, char* base) {
     g->p32 = L.take<float>(base, n);
     g->p32alt = L.take<float>(base, n);
     g->q32 = L.take<float>(base, n);
+    g->zj32 = L.take<float>(base, n);
   }
   return L.off;
 }
@@ -358,7 +362,7 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
   HIPCHK(g, hipGetLastError());
   if ((st = sync_status(g, sys, s)) != DS_OK) return st;
   if (!g->h_status[sys].done) {
-    CgVecs<double> V{x, g->r, g->pd, g->p_alt, g->q};
+    CgVecs<double> V{x, g->r, g->pd, g->p_alt, g->q, H ? nullptr : g->zj};
     double* z = nullptr;
     cg_start(L, H, V, &z, ss, g->partials, g->counters + CT_SOLVE0, s);
     bool first = true;
@@ -424,7 +428,7 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     launch_inner_init<float>(F, g->r, g->r32, g->e32, si, g->partials, g->counters + CT_SOLVE1, s);
     g->h_status[3].it = 0;
     g->h_status[3].done = 0;
-    CgVecs<float> V{g->e32, g->r32, g->p32, g->p32alt, g->q32};
+    CgVecs<float> V{g->e32, g->r32, g->p32, g->p32alt, g->q32, H ? nullptr : g->zj32};
     float* z = nullptr;
     cg_start(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, s);
     bool first = true;

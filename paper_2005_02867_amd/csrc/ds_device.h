@@ -53,11 +53,25 @@ __device__ __forceinline__ long long widx(const DevParams& P, int i, int j, int 
   return ((long long)i * P.ny + j) * (P.nz + 1) + k;
 }
 
+// Cell (i, j, k) of flat index c.  Grids hold fewer than 2^31 cells (checked
+// at creation), so 32-bit unsigned division is exact and much cheaper than
+// the 64-bit form.
 __device__ __forceinline__ void decode(const DevParams& P, long long c, int& i, int& j, int& k) {
-  k = (int)(c % P.nz);
-  long long t = c / P.nz;
-  j = (int)(t % P.ny);
-  i = (int)(t / P.ny);
+  const unsigned cu = (unsigned)c, nz = (unsigned)P.nz, ny = (unsigned)P.ny;
+  const unsigned t = cu / nz;
+  k = (int)(cu - t * nz);
+  j = (int)(t % ny);
+  i = (int)(t / ny);
+}
+
+// (i, j, k) of flat index e in an array of extents (., fy, fz) (face arrays;
+// fewer than 2^31 entries, so 32-bit unsigned division is exact).
+__device__ __forceinline__ void decode3(long long e, int fy, int fz, int& i, int& j, int& k) {
+  const unsigned eu = (unsigned)e, uz = (unsigned)fz, uy = (unsigned)fy;
+  const unsigned t = eu / uz;
+  k = (int)(eu - t * uz);
+  j = (int)(t % uy);
+  i = (int)(t / uy);
 }
 
 // Contiguous range of items handled by this block.  Blocks are dealt to the

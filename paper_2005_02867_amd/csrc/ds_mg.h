@@ -59,6 +59,7 @@ struct CgVecs {
   T* p;        // direction (ping-pong with p_alt)
   T* p_alt;
   T* q;        // A p
+  T* zj = nullptr;   // Jacobi: z = r/diag stored by the update (vectorised levels)
 };
 
 // dirmask bit (axis*2 + side) set: p_rgh = 0 on that box face.

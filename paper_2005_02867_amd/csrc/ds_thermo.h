@@ -66,7 +66,9 @@ __device__ inline double pr_root_value(double A, double B) {
     const double fp = (3.0 * z + 2.0 * c2) * z + c1;
     const double dz = f / fp;
     z -= dz;
-    if (fabs(dz) <= 1e-16 * fabs(z)) break;
+    // converged to within two units in the last place (a tighter test is
+    // never met once the iterate oscillates by one ulp)
+    if (fabs(dz) <= 4.5e-16 * fabs(z)) break;
   }
   return z;
 }

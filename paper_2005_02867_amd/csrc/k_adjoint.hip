@@ -137,10 +137,7 @@ __device__ __forceinline__ long long fidx(const DevParams& P, int ax, int i, int
 
 __device__ __forceinline__ void decode_face(const DevParams& P, int ax, long long e, int& i, int& j, int& k) {
   const int fy = P.ny + (ax == 1), fz = P.nz + (ax == 2);
-  k = (int)(e % fz);
-  const long long t = e / fz;
-  j = (int)(t % fy);
-  i = (int)(t / fy);
+  decode3(e, fy, fz, i, j, k);
 }
 
 // d div_c/d U_e transposed: the adjoint of b = -div(U) at face f of a line
@@ -273,10 +270,8 @@ __global__ void k_adj_pred_a(DevParams P, const double* __restrict__ A_U, const 
   const double* F = AX == 0 ? u : (AX == 1 ? v : w);
   const long long sx = (long long)fy * fz, sy = fz, sz = 1;
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
-    const int k = (int)(e % fz);
-    const long long t = e / fz;
-    const int j = (int)(t % fy);
-    const int i = (int)(t / fy);
+    int i, j, k;
+    decode3(e, fy, fz, i, j, k);
     const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
     const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
     const long long line = AX == 0 ? cidx(P, 0, j, k) : (AX == 1 ? cidx(P, i, 0, k) : cidx(P, i, j, 0));
@@ -322,10 +317,8 @@ __global__ void k_adj_pred_b(DevParams P, const double* __restrict__ A_Us, const
   const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
   const double ih = 1.0 / P.h;
   for (long long x = b0 + threadIdx.x; x < b1; x += BLOCK) {
-    const int k = (int)(x % fz);
-    const long long t = x / fz;
-    const int j = (int)(t % fy);
-    const int i = (int)(t / fy);
+    int i, j, k;
+    decode3(x, fy, fz, i, j, k);
     const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
     const bool interior = fpos >= 1 && fpos <= nax - 1;
     double acc;
@@ -579,10 +572,8 @@ __global__ void k_adj_adv_faces(DevParams P, const double* __restrict__ a1, cons
   const double sa = P.dt / P.h;
   double acc[2] = {0.0, 0.0};   // rho_G, T_amb
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
-    const int k = (int)(e % fz);
-    const long long t = e / fz;
-    const int j = (int)(t % fy);
-    const int i = (int)(t / fy);
+    int i, j, k;
+    decode3(e, fy, fz, i, j, k);
     const int f = AX == 0 ? i : (AX == 1 ? j : k);
     const int na = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
     const long long line = AX == 0 ? cidx(P, 0, j, k) : (AX == 1 ? cidx(P, i, 0, k) : cidx(P, i, j, 0));
@@ -715,10 +706,8 @@ __global__ void k_adj_phi_faces(DevParams P, const double* __restrict__ A_Ul, co
   long long b0, b1;
   block_range(nf, b0, b1);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
-    const int k = (int)(e % fz);
-    const long long t = e / fz;
-    const int j = (int)(t % fy);
-    const int i = (int)(t / fy);
+    int i, j, k;
+    decode3(e, fy, fz, i, j, k);
     const int f = AX == 0 ? i : (AX == 1 ? j : k);
     const int na = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
     const long long line = AX == 0 ? cidx(P, 0, j, k) : (AX == 1 ? cidx(P, i, 0, k) : cidx(P, i, j, 0));

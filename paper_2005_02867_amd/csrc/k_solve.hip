@@ -471,6 +471,7 @@ static int vec_blocks(long long items) {
 }
 
 // Loop over this block's items: declares i, j, kv and c (flat index of the first cell).
+// Item counts stay below 2^31, so the decode uses 32-bit unsigned division.
 #define FOR_ITEMS(L, T, i, j, kv, c)                                                                         \
   const int nzv_ = (L).nz / VW<T>::n;                                                                     \
   const long long nit_ = (long long)(L).nx * (L).ny * nzv_;                                               \
@@ -479,8 +480,10 @@ static int vec_blocks(long long items) {
   const long long e0_ = (long long)xcd_ * chk_, e1_ = min(nit_, e0_ + chk_);                              \
   int i, j, kv;                                                                                           \
   long long c;                                                                                            \
+  unsigned t_;                                                                                            \
   for (long long e_ = e0_ + (long long)loc_ * BLOCK + threadIdx.x; e_ < e1_; e_ += (long long)per_ * BLOCK) \
-    if ((kv = (int)(e_ % nzv_)), (j = (int)((e_ / nzv_) % (L).ny)), (i = (int)(e_ / nzv_ / (L).ny)),        \
+    if ((t_ = (unsigned)e_ / (unsigned)nzv_), (kv = (int)((unsigned)e_ - t_ * (unsigned)nzv_)),             \
+        (j = (int)(t_ % (unsigned)(L).ny)), (i = (int)(t_ / (unsigned)(L).ny)),                               \
         (c = ((long long)i * (L).ny + j) * (L).nz + (long long)kv * VW<T>::n), true)
 
 // off[v] = sum_nb (q_v + q_nb) x_nb for the VW cells at c, in the scalar
@@ -743,16 +746,20 @@ __global__ void k_inner_init_v(Lev<T> L, const double* __restrict__ r64, T* __re
 
 template <class T>
 __global__ void k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
-                           int first) {
+                           int first, T* __restrict__ zout) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
   double acc = 0.0;
   FOR_ITEMS(L, T, i, j, kv, c) {
-    T rv[V], dv[V];
+    T rv[V], dv[V], zv[V];
     ldv<T>(r + c, rv);
     ldv<T>(L.diag + c, dv);
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc += (double)rv[v] * (double)rv[v] / (double)dv[v];
+    for (int v = 0; v < V; ++v) {
+      acc += (double)rv[v] * (double)rv[v] / (double)dv[v];
+      zv[v] = rv[v] / dv[v];
+    }
+    if (zout) stv<T>(zout + c, zv);
   }
   publish_rz(acc, st, partials, counter, first);
 }
@@ -810,7 +817,8 @@ __global__ void k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __re
 
 template <class T, bool JAC>
 __global__ void k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                              const T* __restrict__ q, SolveStatus* st, double* partials, unsigned* counter) {
+                              const T* __restrict__ q, SolveStatus* st, double* partials, unsigned* counter,
+                              T* __restrict__ zout) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
   const T a = (T)st->alpha;
@@ -821,17 +829,21 @@ __global__ void k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, co
     ldv<T>(r + c, rv);
     ldv<T>(p + c, pv);
     ldv<T>(q + c, qv);
-    T dv[V];
+    T dv[V], zv[V];
     if (JAC) ldv<T>(L.diag + c, dv);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       xv[v] += a * pv[v];
       rv[v] = rv[v] - a * qv[v];
       acc[0] += (double)rv[v] * (double)rv[v];
-      if (JAC) acc[1] += (double)rv[v] * (double)rv[v] / (double)dv[v];
+      if (JAC) {
+        acc[1] += (double)rv[v] * (double)rv[v] / (double)dv[v];
+        zv[v] = rv[v] / dv[v];
+      }
     }
     stv<T>(x + c, xv);
     stv<T>(r + c, rv);
+    if (JAC && zout) stv<T>(zout + c, zv);
   }
   const int ops[2] = {RSUM, RSUM};
   if (block_reduce_publish<2>(acc, ops, partials, counter)) {
@@ -1038,7 +1050,8 @@ void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* s
     mg_vcycle(*H, 0, V.r, st, partials, counters + 2, first != 0, true, s, z);
   } else {
     *z = nullptr;
-    if (use_vec(L)) k_jac_rz_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2, first);
+    if (use_vec(L))
+      k_jac_rz_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2, first, V.zj);
     else k_jac_rz<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2, first);
   }
 }
@@ -1058,14 +1071,19 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
       kdir<<<nb, BLOCK, 0, s>>>(L, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
     }
     std::swap(V.p, V.p_alt);
-    if (vec) k_cg_update_v<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
+    if (vec) k_cg_update_v<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
     else k_cg_update<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
     mg_vcycle(*H, 0, V.r, st, partials, counters + 2, false, true, s, z);
   } else {
-    if (vec) {
+    if (vec && V.zj) {
+      // z = r/diag was stored by the previous update (or the start)
+      k_cg_dir_spmv_v<T, false><<<nb, BLOCK, 0, s>>>(L, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      std::swap(V.p, V.p_alt);
+      k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, V.zj);
+    } else if (vec) {
       k_cg_dir_spmv_v<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
       std::swap(V.p, V.p_alt);
-      k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
+      k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
     } else {
       k_cg_dir_spmv<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
       std::swap(V.p, V.p_alt);

@@ -322,10 +322,8 @@ __global__ void k_predictor(DevParams P, const double* __restrict__ a_new, const
   block_range(nf, b0, b1);
   const double* F = AX == 0 ? u : (AX == 1 ? v : w);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
-    const int k = (int)(e % fz);
-    const long long t = e / fz;
-    const int j = (int)(t % fy);
-    const int i = (int)(t / fy);
+    int i, j, k;
+    decode3(e, fy, fz, i, j, k);
     const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
     const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
     const double uc = F[e];
@@ -449,10 +447,8 @@ __global__ void k_project(DevParams P, const double* __restrict__ a_new, const d
   long long b0, b1;
   block_range(nf, b0, b1);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
-    const int k = (int)(e % fz);
-    const long long t = e / fz;
-    const int j = (int)(t % fy);
-    const int i = (int)(t / fy);
+    int i, j, k;
+    decode3(e, fy, fz, i, j, k);
     const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
     const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
     const double us = Fs[e];
