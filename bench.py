@@ -97,6 +97,66 @@ def adjoint_cost(ds, torch, W):
     return out
 
 
+def other_configs(ds, torch, W, steps=5, warmup=2):
+    """Throughput of the other configurations (parity-test cases; not the
+    headline): FP64 and precision form, `steps` timed steps after `warmup`."""
+    out = {}
+    for name in ("C1", "C2", "C4", "C5"):
+        prm, run = W.config(name)
+        f = W.initial_fields(prm, **run)
+        ncell = prm["nx"] * prm["ny"] * prm["nz"]
+        res = {"cells": ncell}
+        for label, prec in (("fp64", W.PREC_FP64), ("precision_form", W.PREC_MIXED)):
+            g = ds.Grid(dict(prm, precision=prec))
+            g.set_fields(f)
+            g.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            d = g.diagnostics()
+            res[label] = {"cell_steps_per_s": ncell * steps / dt, "ms_per_step": dt * 1e3 / steps,
+                          "iters_T_omega_p_phi": [d["iters_T"], d["iters_omega"], d["iters_p"], d["iters_phi"]]}
+            del g
+            torch.cuda.empty_cache()
+        out[name] = res
+        log(f"  {name} {prm['nx']}^3: FP64 {res['fp64']['ms_per_step']:.2f} ms/step, precision form "
+            f"{res['precision_form']['ms_per_step']:.2f} ms/step")
+    return out
+
+
+def adjoint_cost_384(ds, torch, W, steps=10, ckpt=5):
+    """Adjoint cost at 384^3 (10 bar, Peng-Robinson, forced 1 m/s, precision
+    form): reverse sweep over `steps` steps with a checkpoint every `ckpt`,
+    against the forward run of the same steps."""
+    prm, run = W.config("C5")
+    f = W.initial_fields(prm, **run)
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    g.step(1)
+    g.set_fields(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    del g
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    t0 = time.perf_counter()
+    g.forward_record(steps, ckpt)
+    t1 = time.perf_counter()
+    r = g.adjoint(1.0, fields=False)
+    t2 = time.perf_counter()
+    del g
+    torch.cuda.empty_cache()
+    return {"workload": f"384^3 over 10 mm, 2.0 mm droplet, 10 bar, Peng-Robinson, forced 1 m/s, precision form, "
+                        f"{steps} steps from the initial state, checkpoint every {ckpt}",
+            "forward_s": fwd, "record_s": t1 - t0, "reverse_s": t2 - t1, "reverse_over_forward": (t2 - t1) / fwd,
+            "dV_dD_v": r["D_v"], "dV_ddh_ev": r["dh_ev"], "dV_dT_amb": r["T_amb"]}
+
+
 def cpu_baseline(prm, fields, jacobi_iters_p, sample_iters=8):
     """The CPU oracle (torch float64, host cores) on a bounded sample of the
     same workload: one oracle step from the initial state with its two
@@ -150,6 +210,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
+    ap.add_argument("--configs", action="store_true",
+                    help="also time the other configurations (32^3 ... 384^3) and the 384^3 adjoint")
     ap.add_argument("--counters-pass", action="store_true",
                     help="short run for hardware-counter passes: one step of the workload, 5 replayed launches of "
                          "the fine-level sweep, then 3 device copies of 1 GiB (the counter calibration)")
@@ -245,6 +307,12 @@ def main():
         log(f"  forward {out['adjoint']['forward_s']:.3f} s, reverse/forward "
             f"{out['adjoint']['ckpt1']['reverse_over_forward']:.2f} (every state stored), "
             f"{out['adjoint']['ckpt10']['reverse_over_forward']:.2f} (checkpoint every 10)")
+    if args.configs:
+        log("other configurations")
+        out["other_configs"] = other_configs(ds, torch, W)
+        log("adjoint cost at 384^3")
+        out["adjoint_384"] = adjoint_cost_384(ds, torch, W)
+        log(f"  reverse/forward {out['adjoint_384']['reverse_over_forward']:.2f}")
     if not args.no_cpu:
         log("GPU Jacobi-PCG step (pressure iteration count for the CPU extrapolation)")
         g = ds.Grid(dict(prm, precision=W.PREC_FP64, pressure_precond=0))
