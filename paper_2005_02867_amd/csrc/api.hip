@@ -56,6 +56,8 @@ struct ds_grid {
   double *mraw = nullptr, *mdot = nullptr, *us = nullptr, *vs = nullptr, *ws = nullptr, *xi = nullptr;
   double *b = nullptr, *r = nullptr, *pd = nullptr, *q = nullptr, *diag = nullptr, *qc = nullptr;
   int* adj = nullptr;
+  int* band = nullptr;             // per-block lists of interface cells
+  int* band_count = nullptr;
   double* partials = nullptr;
   unsigned* counters = nullptr;
   double* scal = nullptr;
@@ -163,6 +165,8 @@ size_t carve(ds_grid* g, char* base) {
   g->diag = L.take<double>(base, n);
   g->qc = L.take<double>(base, n);
   g->adj = L.take<int>(base, n);
+  g->band = L.take<int>(base, (size_t)interface_band_capacity(n));
+  g->band_count = L.take<int>(base, MAX_BLOCKS);
   g->partials = L.take<double>(base, (size_t)MAX_BLOCKS * MAX_RED);
   g->counters = L.take<unsigned>(base, CT_COUNT);
   g->scal = L.take<double>(base, SC_COUNT);
@@ -529,7 +533,7 @@ int solve_pressure_system(ds_grid* g, hipStream_t s, int* iters, double* res) {
 int evaporation_source(ds_grid* g, hipStream_t s) {
   const DevParams& P = g->dp;
   if (P.evaporation) {
-    launch_interface(P, g->alpha, g->T, g->omega, g->u, g->v, g->w, g->mraw, g->adj, g->partials,
+    launch_interface(P, g->alpha, g->T, g->omega, g->u, g->v, g->w, g->mraw, g->adj, g->band, g->band_count, g->partials,
                      g->counters + CT_IFACE, g->scal, s);
   } else {
     launch_fill(g->mraw, 0.0, g->n, s);
@@ -699,7 +703,7 @@ int reverse_step(ds_grid* g, const Slot& cur, const Slot& nxt, hipStream_t s, in
   unsigned* cadj = g->counters + CT_ADJ;
   // replay: interface source, liquid source, advection, predictor
   if (P.evaporation) {
-    launch_interface(P, cur.alpha, cur.T, cur.omega, cur.u, cur.v, cur.w, g->mraw, g->adj, g->partials,
+    launch_interface(P, cur.alpha, cur.T, cur.omega, cur.u, cur.v, cur.w, g->mraw, g->adj, g->band, g->band_count, g->partials,
                      g->counters + CT_IFACE, g->scal, s);
   } else {
     launch_fill(g->mraw, 0.0, g->n, s);

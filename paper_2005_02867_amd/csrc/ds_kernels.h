@@ -23,9 +23,12 @@ int grid_blocks(long long n);   // streaming grid size (multiple of 8)
 
 // ---- step kernels (k_step.hip)
 void launch_xi(const DevParams& P, double* xi, hipStream_t s);
+// Interface cells in two passes (a scan writing per-block lists of interface
+// cells into band/band_count, then the march and flux on those cells only).
 void launch_interface(const DevParams& P, const double* alpha, const double* T, const double* omega,
-                      const double* u, const double* v, const double* w, double* mraw, int* adj,
-                      double* partials, unsigned* counter, double* scal, hipStream_t s);
+                      const double* u, const double* v, const double* w, double* mraw, int* adj, int* band,
+                      int* band_count, double* partials, unsigned* counter, double* scal, hipStream_t s);
+long long interface_band_capacity(long long n);   // ints needed for `band`
 void launch_source(const DevParams& P, const double* alpha, const double* mraw, const double* scal,
                    double* mdot, double* a1, hipStream_t s);
 void launch_advect(const DevParams& P, const double* a1, const double* omega, const double* T,

@@ -37,59 +37,108 @@ __global__ void k_xi(DevParams P, double* xi) {
 // to the first gas cell (adj), evaporation flux at adj (eqs. 12-14) times
 // |grad alpha| (eq. 17).  The march arithmetic is written with explicitly
 // rounded operations so that each product and sum rounds on its own.
+// Pass 1 (light, all cells): mraw = 0, adj = -2 off the interface; every
+// interface cell (eps < alpha < 1 - eps) is appended, in cell order, to this
+// block's list (wave ballots give each lane its slot), so pass 2 runs the
+// march and the phase equilibrium only where they apply, one cell per lane.
+__global__ void __launch_bounds__(BLOCK) k_interface_scan(DevParams P, const double* __restrict__ alpha,
+                                                         double* __restrict__ mraw, int* __restrict__ adj,
+                                                         int* __restrict__ band, int* __restrict__ band_count) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  __shared__ int wave_cnt[BLOCK / 64];
+  __shared__ int base_sh;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const long long cap = (long long)((P.n + gridDim.x - 1) / gridDim.x + BLOCK - 1) / BLOCK * BLOCK;
+  int* list = band + (long long)blockIdx.x * cap;
+  if (threadIdx.x == 0) base_sh = 0;
+  __syncthreads();
+  const long long span = b1 > b0 ? b1 - b0 : 0;
+  for (long long off = 0; off < span; off += BLOCK) {
+    const long long c = b0 + off + threadIdx.x;
+    bool cand = false;
+    if (c < b1) {
+      const double a = alpha[c];
+      cand = a > P.eps && a < 1.0 - P.eps;
+      mraw[c] = 0.0;
+      adj[c] = cand ? -1 : -2;
+    }
+    const unsigned long long m = __ballot(cand);
+    if (lane == 0) wave_cnt[wid] = __popcll(m);
+    __syncthreads();
+    int before = base_sh;
+    for (int w = 0; w < wid; ++w) before += wave_cnt[w];
+    if (cand) list[before + __popcll(m & ((1ull << lane) - 1ull))] = (int)c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < BLOCK / 64; ++w) tot += wave_cnt[w];
+      base_sh += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) band_count[blockIdx.x] = base_sh;
+}
+
+// Pass 2 (interface cells of each block's list): central-difference gradient
+// with a zero ghost outside the box, outward normal n = -grad/|grad|, march
+// along n to the first gas cell (adj), evaporation flux at adj (eqs. 12-14)
+// times |grad alpha| (eq. 17); the sums of eq. 20 and the interface count.
+// The march arithmetic is written with explicitly rounded operations so that
+// each product and sum rounds on its own.
 __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
                             const double* __restrict__ omega, const double* __restrict__ u,
                             const double* __restrict__ v, const double* __restrict__ w,
+                            const int* __restrict__ band, const int* __restrict__ band_count,
                             double* __restrict__ mraw, int* __restrict__ adj, double* partials,
                             unsigned* counter, double* scal) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
   double acc[3] = {0.0, 0.0, 0.0};
-  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+  const long long cap = (long long)((P.n + gridDim.x - 1) / gridDim.x + BLOCK - 1) / BLOCK * BLOCK;
+  const int* list = band + (long long)blockIdx.x * cap;
+  const int cnt = band_count[blockIdx.x];
+  for (int t = threadIdx.x; t < cnt; t += BLOCK) {
+    const long long c = list[t];
     const double a = alpha[c];
     double m = 0.0;
-    int hit = -2;
-    if (a > P.eps && a < 1.0 - P.eps) {
-      int i, j, k;
-      decode(P, c, i, j, k);
-      const double dx = __dsub_rn(alpha_or0(P, alpha, i + 1, j, k), alpha_or0(P, alpha, i - 1, j, k));
-      const double dy = __dsub_rn(alpha_or0(P, alpha, i, j + 1, k), alpha_or0(P, alpha, i, j - 1, k));
-      const double dz = __dsub_rn(alpha_or0(P, alpha, i, j, k + 1), alpha_or0(P, alpha, i, j, k - 1));
-      const double nrm =
-          __dsqrt_rn(__dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz)));
-      hit = -1;
-      if (nrm > 0.0) {
-        acc[2] += 1.0;
-        const double nx = __ddiv_rn(-dx, nrm), ny = __ddiv_rn(-dy, nrm), nz = __ddiv_rn(-dz, nrm);
-        const double bi = i + 0.5, bj = j + 0.5, bk = k + 0.5;
-        int ti = 0, tj = 0, tk = 0;
-        for (int s = 1; s <= P.smax; ++s) {
-          const double sd = (double)s;
-          ti = (int)floor(__dadd_rn(bi, __dmul_rn(sd, nx)));
-          tj = (int)floor(__dadd_rn(bj, __dmul_rn(sd, ny)));
-          tk = (int)floor(__dadd_rn(bk, __dmul_rn(sd, nz)));
-          if (ti < 0 || tj < 0 || tk < 0 || ti >= P.nx || tj >= P.ny || tk >= P.nz) break;
-          if (alpha[cidx(P, ti, tj, tk)] <= P.eps_gas) {
-            hit = (int)cidx(P, ti, tj, tk);
-            break;
-          }
-        }
-        if (hit >= 0) {
-          const double di = ti - i, dj = tj - j, dk = tk - k;
-          const double d = P.h * sqrt(di * di + dj * dj + dk * dk);
-          const double wsat = mass_fraction(P, equilibrium_y(P, T[c]));
-          const double wa = omega[hit];
-          const double va = 0.5 * (u[uidx(P, ti, tj, tk)] + u[uidx(P, ti + 1, tj, tk)]) * nx +
-                            0.5 * (v[vidx(P, ti, tj, tk)] + v[vidx(P, ti, tj + 1, tk)]) * ny +
-                            0.5 * (w[widx(P, ti, tj, tk)] + w[widx(P, ti, tj, tk + 1)]) * nz;
-          const double jn = P.rho_G * P.D * (wsat - wa) / d + P.rho_G * wa * va;
-          m = jn * (nrm / (2.0 * P.h));
+    int hit = -1;
+    int i, j, k;
+    decode(P, c, i, j, k);
+    const double dx = __dsub_rn(alpha_or0(P, alpha, i + 1, j, k), alpha_or0(P, alpha, i - 1, j, k));
+    const double dy = __dsub_rn(alpha_or0(P, alpha, i, j + 1, k), alpha_or0(P, alpha, i, j - 1, k));
+    const double dz = __dsub_rn(alpha_or0(P, alpha, i, j, k + 1), alpha_or0(P, alpha, i, j, k - 1));
+    const double nrm =
+        __dsqrt_rn(__dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz)));
+    if (nrm > 0.0) {
+      acc[2] += 1.0;
+      const double nx = __ddiv_rn(-dx, nrm), ny = __ddiv_rn(-dy, nrm), nz = __ddiv_rn(-dz, nrm);
+      const double bi = i + 0.5, bj = j + 0.5, bk = k + 0.5;
+      int ti = 0, tj = 0, tk = 0;
+      for (int s = 1; s <= P.smax; ++s) {
+        const double sd = (double)s;
+        ti = (int)floor(__dadd_rn(bi, __dmul_rn(sd, nx)));
+        tj = (int)floor(__dadd_rn(bj, __dmul_rn(sd, ny)));
+        tk = (int)floor(__dadd_rn(bk, __dmul_rn(sd, nz)));
+        if (ti < 0 || tj < 0 || tk < 0 || ti >= P.nx || tj >= P.ny || tk >= P.nz) break;
+        if (alpha[cidx(P, ti, tj, tk)] <= P.eps_gas) {
+          hit = (int)cidx(P, ti, tj, tk);
+          break;
         }
       }
-      const double f = sqrt(fmax(a * (1.0 - a), 0.0));
-      acc[0] += m;
-      acc[1] += f * m;
+      if (hit >= 0) {
+        const double di = ti - i, dj = tj - j, dk = tk - k;
+        const double d = P.h * sqrt(di * di + dj * dj + dk * dk);
+        const double wsat = mass_fraction(P, equilibrium_y(P, T[c]));
+        const double wa = omega[hit];
+        const double va = 0.5 * (u[uidx(P, ti, tj, tk)] + u[uidx(P, ti + 1, tj, tk)]) * nx +
+                          0.5 * (v[vidx(P, ti, tj, tk)] + v[vidx(P, ti, tj + 1, tk)]) * ny +
+                          0.5 * (w[widx(P, ti, tj, tk)] + w[widx(P, ti, tj, tk + 1)]) * nz;
+        const double jn = P.rho_G * P.D * (wsat - wa) / d + P.rho_G * wa * va;
+        m = jn * (nrm / (2.0 * P.h));
+      }
     }
+    const double f = sqrt(fmax(a * (1.0 - a), 0.0));
+    acc[0] += m;
+    acc[1] += f * m;
     mraw[c] = m;
     adj[c] = hit;
   }
@@ -554,9 +603,16 @@ void launch_xi(const DevParams& P, double* xi, hipStream_t s) {
   k_xi<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, xi);
 }
 void launch_interface(const DevParams& P, const double* alpha, const double* T, const double* omega,
-                      const double* u, const double* v, const double* w, double* mraw, int* adj,
-                      double* partials, unsigned* counter, double* scal, hipStream_t s) {
-  k_interface<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, alpha, T, omega, u, v, w, mraw, adj, partials, counter, scal);
+                      const double* u, const double* v, const double* w, double* mraw, int* adj, int* band,
+                      int* band_count, double* partials, unsigned* counter, double* scal, hipStream_t s) {
+  const int nb = grid_blocks(P.n);
+  k_interface_scan<<<nb, BLOCK, 0, s>>>(P, alpha, mraw, adj, band, band_count);
+  k_interface<<<nb, BLOCK, 0, s>>>(P, alpha, T, omega, u, v, w, band, band_count, mraw, adj, partials, counter, scal);
+}
+long long interface_band_capacity(long long n) {
+  const int nb = grid_blocks(n);
+  const long long cap = ((n + nb - 1) / nb + BLOCK - 1) / BLOCK * BLOCK;
+  return cap * nb;
 }
 void launch_source(const DevParams& P, const double* alpha, const double* mraw, const double* scal,
                    double* mdot, double* a1, hipStream_t s) {
