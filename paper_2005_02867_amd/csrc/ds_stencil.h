@@ -28,12 +28,12 @@ __device__ __forceinline__ double face_value(const double* __restrict__ phi, lon
     D = phi[line + (long long)(f - 1) * st];
     U = (f + 1 <= na - 1) ? phi[line + (long long)(f + 1) * st] : C;
   }
-  const double den = D - C;
-  if (den == 0.0) return C;
-  const double r = (C - U) / den;
-  const double ar = fabs(r);
-  const double psi = (r + ar) / (1.0 + ar);
-  return C + 0.5 * psi * den;
+  // van Leer: with r = (C - U)/(D - C) and psi = (r + |r|)/(1 + |r|), the face
+  // value C + psi (D - C)/2 equals C + (C - U)(D - C)/(D - U) for r > 0 and C
+  // otherwise -- one division instead of two.
+  const double den = D - C, up = C - U;
+  if (!((up > 0.0 && den > 0.0) || (up < 0.0 && den < 0.0))) return C;
+  return C + up * den / (D - U);
 }
 
 // Liquid-marker face velocity: the divergence-free part u - G phi (phi = 0
