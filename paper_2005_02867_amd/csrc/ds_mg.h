@@ -15,9 +15,17 @@ constexpr int TJ = 4;    // tile extent along y (four wavefronts per block)
 
 // One level's operator: (A x)_c = diag_c x_c - sc/2 sum_nb (q_c + q_nb) x_nb,
 // plus its 64x4 tile decomposition.
+// Rows of y per slab in the item order of the z-vectorised kernels: items
+// run z-fastest, then y within a slab of `ytile` rows, then x, then slab.
+// Neighbours in x are then one slab-plane apart instead of a full plane,
+// which keeps the x-1, x, x+1 working set of a streaming pass inside one
+// XCD's L2.  0 or a value not dividing ny: whole planes.
+extern int g_vec_ytile;
+
 template <class T>
 struct Lev {
   int nx, ny, nz;
+  int ytile;
   int ntk, ntj;
   unsigned ntiles;
   long long n;
@@ -31,6 +39,7 @@ inline void lev_dims(Lev<T>& L, int nx, int ny, int nz, double sc) {
   L.nx = nx;
   L.ny = ny;
   L.nz = nz;
+  L.ytile = (g_vec_ytile > 0 && ny % g_vec_ytile == 0) ? g_vec_ytile : ny;
   L.ntk = (nz + TK - 1) / TK;
   L.ntj = (ny + TJ - 1) / TJ;
   L.ntiles = (unsigned)L.ntk * (unsigned)L.ntj * (unsigned)nx;
@@ -92,6 +101,8 @@ double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, 
 // (operator, vectors and dot products in FP64; the V-cycle's sweeps, its
 // operator copies and r, z in FP32).  Needs mg32_supported(L).
 bool mg32_supported(const Lev<double>& L);
+// Largest grid of the z-vectorised kernels (rounded to a multiple of 8).
+void set_vec_max_blocks(int nb);
 double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1);

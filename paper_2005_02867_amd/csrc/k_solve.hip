@@ -455,117 +455,162 @@ __device__ __forceinline__ void stv(T* __restrict__ p, const T (&o)[VW<T>::n]) {
   }
   *reinterpret_cast<typename VW<T>::vec*>(p) = v;
 }
+// Element e of an array through a 32-bit byte offset: loads and stores then
+// take the scalar-base + 32-bit-offset form (one VGPR per address, shared by
+// every array indexed alike).  use_vec() keeps each array below 4 GiB.
+template <class T>
+__device__ __forceinline__ T* at(T* p, unsigned e) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + e * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T* at(const T* p, unsigned e) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + e * (unsigned)sizeof(T));
+}
 
+// The vectorised kernels run at most 1024 blocks of 4 waves, i.e. 4 waves per
+// SIMD: the compiler may use up to 128 VGPRs and keep every load of an item
+// in flight before the first wait.
+#define VEC_KERNEL __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 4)))
+
+// Vectorised kernels: nz a multiple of the vector width and every array
+// (FP64 ones included) below 4 GiB, so 32-bit byte offsets address it.
 template <class T>
 inline bool use_vec(const Lev<T>& L) {
-  return L.nz % VW<T>::n == 0;
+  return L.nz % VW<T>::n == 0 && L.n < (1LL << 29);
 }
 template <class T>
 inline long long vec_items(const Lev<T>& L) {
   return (long long)L.nx * L.ny * (L.nz / VW<T>::n);
 }
+int g_vec_ytile = 0;
+static int g_vec_max_blocks = 1024;
+void set_vec_max_blocks(int nb) {
+  // every vectorised kernel publishes at most 2 partials per block
+  nb = std::min(std::max(nb, NXCD), MAX_BLOCKS * MAX_RED / 2);
+  g_vec_max_blocks = nb / NXCD * NXCD;
+}
 static int vec_blocks(long long items) {
   long long nb = (items + BLOCK - 1) / BLOCK;
-  nb = std::min<long long>(std::max<long long>(nb, NXCD), 1024);
+  nb = std::min<long long>(std::max<long long>(nb, NXCD), g_vec_max_blocks);
   return (int)((nb + NXCD - 1) / NXCD * NXCD);
 }
 
 // Loop over this block's items: declares i, j, kv and c (flat index of the first cell).
-// Item counts stay below 2^31, so the decode uses 32-bit unsigned division.
+// Item order: kv fastest, then j within a slab of L.ytile rows, then i, then
+// the slab.  Cell counts stay below 2^29 (use_vec), so items, cells and the
+// decode all use 32-bit unsigned arithmetic.
 #define FOR_ITEMS(L, T, i, j, kv, c)                                                                         \
   const int nzv_ = (L).nz / VW<T>::n;                                                                     \
-  const long long nit_ = (long long)(L).nx * (L).ny * nzv_;                                               \
+  const unsigned nit_ = (unsigned)(L).nx * (unsigned)(L).ny * (unsigned)nzv_;                             \
   const unsigned per_ = gridDim.x / NXCD, loc_ = blockIdx.x / NXCD, xcd_ = blockIdx.x % NXCD;              \
-  const long long chk_ = (nit_ + NXCD - 1) / NXCD;                                                        \
-  const long long e0_ = (long long)xcd_ * chk_, e1_ = min(nit_, e0_ + chk_);                              \
+  const unsigned yt_ = (unsigned)(L).ytile;                                                               \
+  const unsigned chk_ = (nit_ + NXCD - 1) / NXCD;                                                         \
+  const unsigned e0_ = xcd_ * chk_, e1_ = min(nit_, e0_ + chk_);                                          \
   int i, j, kv;                                                                                           \
-  long long c;                                                                                            \
-  unsigned t_;                                                                                            \
-  for (long long e_ = e0_ + (long long)loc_ * BLOCK + threadIdx.x; e_ < e1_; e_ += (long long)per_ * BLOCK) \
-    if ((t_ = (unsigned)e_ / (unsigned)nzv_), (kv = (int)((unsigned)e_ - t_ * (unsigned)nzv_)),             \
-        (j = (int)(t_ % (unsigned)(L).ny)), (i = (int)(t_ / (unsigned)(L).ny)),                               \
-        (c = ((long long)i * (L).ny + j) * (L).nz + (long long)kv * VW<T>::n), true)
+  unsigned c;                                                                                             \
+  unsigned t_, u_;                                                                                        \
+  for (unsigned e_ = e0_ + loc_ * BLOCK + threadIdx.x; e_ < e1_; e_ += per_ * BLOCK)                      \
+    if ((t_ = e_ / (unsigned)nzv_), (kv = (int)(e_ - t_ * (unsigned)nzv_)),                                 \
+        (u_ = t_ / yt_), (j = (int)(t_ - u_ * yt_)), (i = (int)(u_ % (unsigned)(L).nx)),                     \
+        (j += (int)(u_ / (unsigned)(L).nx * yt_)),                                                          \
+        (c = ((unsigned)i * (unsigned)(L).ny + (unsigned)j) * (unsigned)(L).nz + (unsigned)kv * VW<T>::n), true)
 
 // off[v] = sum_nb (q_v + q_nb) x_nb for the VW cells at c, in the scalar
 // kernels' order (x-, x+, y-, y+, z-, z+).  xc: the cells' own x values;
-// lx(f, out): vector of x at f; sx(f): scalar x at f.
+// lx(f, out): vector of x at f; sx(f): scalar x at f.  The neighbour loads
+// take no branch: a missing neighbour (domain edge) reads the cell itself and
+// a select drops its term, so every load of the item is issued before the
+// first wait instead of one neighbour's round trip after another.
 template <class T, class LX, class SX>
-__device__ __forceinline__ void off_sum_v(const Lev<T>& L, long long c, int i, int j, int kv, const T (&qv)[VW<T>::n],
+__device__ __forceinline__ void off_sum_v(const Lev<T>& L, unsigned c, int i, int j, int kv, const T (&qv)[VW<T>::n],
                                           const T (&xc)[VW<T>::n], LX lx, SX sx, T (&off)[VW<T>::n]) {
   constexpr int V = VW<T>::n;
-  const long long sxs = (long long)L.ny * L.nz, sys = L.nz;
+  const unsigned sxs = (unsigned)L.ny * (unsigned)L.nz, sys = (unsigned)L.nz;
   const int nzv = L.nz / V;
+  const bool has[4] = {i > 0, i < L.nx - 1, j > 0, j < L.ny - 1};
+  const unsigned f[4] = {has[0] ? c - sxs : c, has[1] ? c + sxs : c, has[2] ? c - sys : c, has[3] ? c + sys : c};
+  const bool zm = kv > 0, zp = kv < nzv - 1;
+  const unsigned fm = zm ? c - 1 : c, fp = zp ? c + V : c;
+  T g[4][V], x[4][V];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    ldv<T>(at(L.qc, f[n]), g[n]);
+    lx(f[n], x[n]);
+  }
+  const T gm = *at(L.qc, fm), xm = sx(fm), gp = *at(L.qc, fp), xp = sx(fp);
 #pragma unroll
   for (int v = 0; v < V; ++v) off[v] = 0;
-  auto nbv = [&](long long f) {
-    T g[V], x[V];
-    ldv<T>(L.qc + f, g);
-    lx(f, x);
 #pragma unroll
-    for (int v = 0; v < V; ++v) off[v] += (qv[v] + g[v]) * x[v];
-  };
-  if (i > 0) nbv(c - sxs);
-  if (i < L.nx - 1) nbv(c + sxs);
-  if (j > 0) nbv(c - sys);
-  if (j < L.ny - 1) nbv(c + sys);
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const T t = off[v] + (qv[v] + g[n][v]) * x[n][v];
+      off[v] = has[n] ? t : off[v];
+    }
   // z-: inside the vector, or the scalar before it
-  if (kv > 0) off[0] += (qv[0] + L.qc[c - 1]) * sx(c - 1);
+  {
+    const T t = off[0] + (qv[0] + gm) * xm;
+    off[0] = zm ? t : off[0];
+  }
 #pragma unroll
   for (int v = 1; v < V; ++v) off[v] += (qv[v] + qv[v - 1]) * xc[v - 1];
   // z+
 #pragma unroll
   for (int v = 0; v < V - 1; ++v) off[v] += (qv[v] + qv[v + 1]) * xc[v + 1];
-  if (kv < nzv - 1) off[V - 1] += (qv[V - 1] + L.qc[c + V]) * sx(c + V);
+  {
+    const T t = off[V - 1] + (qv[V - 1] + gp) * xp;
+    off[V - 1] = zp ? t : off[V - 1];
+  }
 }
 
 template <class T>
-__device__ __forceinline__ void apply_v(const Lev<T>& L, const T* __restrict__ x, long long c, int i, int j, int kv,
+__device__ __forceinline__ void apply_v(const Lev<T>& L, const T* __restrict__ x, unsigned c, int i, int j, int kv,
                                         const T (&xc)[VW<T>::n], T (&y)[VW<T>::n]) {
   constexpr int V = VW<T>::n;
   T qv[V], dg[V], off[V];
-  ldv<T>(L.qc + c, qv);
-  ldv<T>(L.diag + c, dg);
-  off_sum_v<T>(L, c, i, j, kv, qv, xc, [&](long long f, T(&o)[V]) { ldv<T>(x + f, o); },
-               [&](long long f) { return x[f]; }, off);
+  ldv<T>(at(L.qc, c), qv);
+  ldv<T>(at(L.diag, c), dg);
+  off_sum_v<T>(L, c, i, j, kv, qv, xc, [&](unsigned f, T(&o)[V]) { ldv<T>(at(x, f), o); },
+               [&](unsigned f) { return *at(x, f); }, off);
 #pragma unroll
   for (int v = 0; v < V; ++v) y[v] = dg[v] * xc[v] - T(0.5) * L.sc * off[v];
 }
 
 template <class T>
-__global__ void k_mg_smooth_zero_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ x, T omega,
+VEC_KERNEL k_mg_smooth_zero_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ x, T omega,
                                    const SolveStatus* st) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
   FOR_ITEMS(L, T, i, j, kv, c) {
     T rv[V], dv[V], o[V];
-    ldv<T>(r + c, rv);
-    ldv<T>(L.diag + c, dv);
+    ldv<T>(at(r, c), rv);
+    ldv<T>(at(L.diag, c), dv);
 #pragma unroll
     for (int v = 0; v < V; ++v) o[v] = omega * rv[v] / dv[v];
-    stv<T>(x + c, o);
+    stv<T>(at(x, c), o);
   }
 }
 
 // The first two sweeps from x = 0 in one pass: x1 = omega r/diag is formed
 // on the fly (also at the neighbours), x2 = x1 + omega (r - A x1)/diag.
 template <class T>
-__global__ void k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ xout, T omega,
+VEC_KERNEL k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ xout, T omega,
                                   const SolveStatus* st) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
-  auto x1v = [&](long long f, T(&o)[V]) {
+  auto x1v = [&](unsigned f, T(&o)[V]) {
     T rv[V], dv[V];
-    ldv<T>(r + f, rv);
-    ldv<T>(L.diag + f, dv);
+    ldv<T>(at(r, f), rv);
+    ldv<T>(at(L.diag, f), dv);
 #pragma unroll
     for (int v = 0; v < V; ++v) o[v] = omega * rv[v] / dv[v];
   };
-  auto x1s = [&](long long f) -> T { return omega * r[f] / L.diag[f]; };
+  auto x1s = [&](unsigned f) -> T { return omega * *at(r, f) / *at(L.diag, f); };
   FOR_ITEMS(L, T, i, j, kv, c) {
     T rv[V], dv[V], qv[V], x1[V], off[V], o[V];
-    ldv<T>(r + c, rv);
-    ldv<T>(L.diag + c, dv);
-    ldv<T>(L.qc + c, qv);
+    ldv<T>(at(r, c), rv);
+    ldv<T>(at(L.diag, c), dv);
+    ldv<T>(at(L.qc, c), qv);
 #pragma unroll
     for (int v = 0; v < V; ++v) x1[v] = omega * rv[v] / dv[v];
     off_sum_v<T>(L, c, i, j, kv, qv, x1, x1v, x1s, off);
@@ -574,35 +619,35 @@ __global__ void k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restri
       const T ax = dv[v] * x1[v] - T(0.5) * L.sc * off[v];
       o[v] = x1[v] + omega * (rv[v] - ax) / dv[v];
     }
-    stv<T>(xout + c, o);
+    stv<T>(at(xout, c), o);
   }
 }
 
 template <class T, bool DOT>
-__global__ void k_mg_smooth_v(Lev<T> L, const T* __restrict__ r, const T* __restrict__ xin, T* __restrict__ xout,
+VEC_KERNEL k_mg_smooth_v(Lev<T> L, const T* __restrict__ r, const T* __restrict__ xin, T* __restrict__ xout,
                               T omega, SolveStatus* st, double* partials, unsigned* counter, int first) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
   double acc = 0.0;
   FOR_ITEMS(L, T, i, j, kv, c) {
     T rv[V], xv[V], ax[V], dv[V], o[V];
-    ldv<T>(r + c, rv);
-    ldv<T>(xin + c, xv);
-    ldv<T>(L.diag + c, dv);
+    ldv<T>(at(r, c), rv);
+    ldv<T>(at(xin, c), xv);
+    ldv<T>(at(L.diag, c), dv);
     apply_v<T>(L, xin, c, i, j, kv, xv, ax);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       o[v] = xv[v] + omega * (rv[v] - ax[v]) / dv[v];
       if (DOT) acc += (double)rv[v] * (double)o[v];
     }
-    stv<T>(xout + c, o);
+    stv<T>(at(xout, c), o);
   }
   if (DOT) publish_rz(acc, st, partials, counter, first);
 }
 
 // Coarse residual for VW/2 coarse cells per thread (fine rows of VW cells).
 template <class T>
-__global__ void k_mg_restrict_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+VEC_KERNEL k_mg_restrict_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
                                 T* __restrict__ rc, const SolveStatus* st) {
   if (st->done) return;
   constexpr int V = VW<T>::n, H = V / 2;
@@ -619,72 +664,70 @@ __global__ void k_mg_restrict_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, con
       for (int dj = 0; dj < 2; ++dj) {
         const int i = 2 * I + di, j = 2 * J + dj;
         if (i >= F.nx || j >= F.ny) continue;
-        const long long f = ((long long)i * F.ny + j) * F.nz + (long long)kv * V;
+        const unsigned f = ((unsigned)i * (unsigned)F.ny + (unsigned)j) * (unsigned)F.nz + (unsigned)kv * V;
         T xv[V], rv[V], ax[V];
-        ldv<T>(x + f, xv);
-        ldv<T>(r + f, rv);
+        ldv<T>(at(x, f), xv);
+        ldv<T>(at(r, f), rv);
         apply_v<T>(F, x, f, i, j, kv, xv, ax);
 #pragma unroll
         for (int h = 0; h < H; ++h) s[h] += (rv[2 * h] - ax[2 * h]) + (rv[2 * h + 1] - ax[2 * h + 1]);
       }
-    const long long cc = ((long long)I * C.ny + J) * C.nz + (long long)kv * H;
+    const unsigned cc = ((unsigned)I * (unsigned)C.ny + (unsigned)J) * (unsigned)C.nz + (unsigned)kv * H;
 #pragma unroll
-    for (int h = 0; h < H; ++h) rc[cc + h] = T(0.125) * s[h];
+    for (int h = 0; h < H; ++h) *at(rc, cc + h) = T(0.125) * s[h];
   }
 }
 
 // x' = x + P xc then one sweep (VW fine cells per thread).
 template <class T, bool DOT>
-__global__ void k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+VEC_KERNEL k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
                                       const T* __restrict__ xc, T* __restrict__ xout, T omega, SolveStatus* st,
                                       double* partials, unsigned* counter, int first) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
   double acc = 0.0;
-  const long long sxs = (long long)F.ny * F.nz;
   FOR_ITEMS(F, T, i, j, kv, c) {
     // x + P xc for the vector of fine row (ii, jj) starting at fine index f (first z = kv*V)
-    auto row = [&](long long f, T(&o)[V]) {
-      const long long rr = f / F.nz;   // ii*ny + jj
-      const int jj = (int)(rr % F.ny), ii = (int)(rr / F.ny);
-      const long long pb = ((long long)(ii >> 1) * C.ny + (jj >> 1)) * C.nz + (long long)kv * (V / 2);
-      ldv<T>(x + f, o);
+    auto row = [&](unsigned f, T(&o)[V]) {
+      const unsigned rr = f / (unsigned)F.nz;   // ii*ny + jj
+      const unsigned jj = rr % (unsigned)F.ny, ii = rr / (unsigned)F.ny;
+      const unsigned pb = ((ii >> 1) * (unsigned)C.ny + (jj >> 1)) * (unsigned)C.nz + (unsigned)kv * (V / 2);
+      ldv<T>(at(x, f), o);
 #pragma unroll
-      for (int v = 0; v < V; ++v) o[v] += xc[pb + (v >> 1)];
+      for (int v = 0; v < V; ++v) o[v] += *at(xc, pb + (v >> 1));
     };
-    auto one = [&](long long f) -> T {
-      const long long rr = f / F.nz;
-      const int kk = (int)(f - rr * F.nz);
-      const int jj = (int)(rr % F.ny), ii = (int)(rr / F.ny);
-      return x[f] + xc[((long long)(ii >> 1) * C.ny + (jj >> 1)) * C.nz + (kk >> 1)];
+    auto one = [&](unsigned f) -> T {
+      const unsigned rr = f / (unsigned)F.nz;
+      const unsigned kk = f - rr * (unsigned)F.nz;
+      const unsigned jj = rr % (unsigned)F.ny, ii = rr / (unsigned)F.ny;
+      return *at(x, f) + *at(xc, ((ii >> 1) * (unsigned)C.ny + (jj >> 1)) * (unsigned)C.nz + (kk >> 1));
     };
     T x0[V], rv[V], qv[V], dv[V], off[V], o[V];
     row(c, x0);
-    ldv<T>(r + c, rv);
-    ldv<T>(F.qc + c, qv);
-    ldv<T>(F.diag + c, dv);
+    ldv<T>(at(r, c), rv);
+    ldv<T>(at(F.qc, c), qv);
+    ldv<T>(at(F.diag, c), dv);
     off_sum_v<T>(F, c, i, j, kv, qv, x0, row, one, off);
-    (void)sxs;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const T Ax = dv[v] * x0[v] - T(0.5) * F.sc * off[v];
       o[v] = x0[v] + omega * (rv[v] - Ax) / dv[v];
       if (DOT) acc += (double)rv[v] * (double)o[v];
     }
-    stv<T>(xout + c, o);
+    stv<T>(at(xout, c), o);
   }
   if (DOT) publish_rz(acc, st, partials, counter, first);
 }
 
-__global__ void k_resid64_v(Lev<double> L, const double* __restrict__ b, const double* __restrict__ x,
+VEC_KERNEL k_resid64_v(Lev<double> L, const double* __restrict__ b, const double* __restrict__ x,
                             double* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
                             int set_bnorm) {
   constexpr int V = VW<double>::n;
   double acc[2] = {0.0, 0.0};
   FOR_ITEMS(L, double, i, j, kv, c) {
     double bv[V], xv[V], ax[V], o[V];
-    ldv<double>(b + c, bv);
-    ldv<double>(x + c, xv);
+    ldv<double>(at(b, c), bv);
+    ldv<double>(at(x, c), xv);
     apply_v<double>(L, x, c, i, j, kv, xv, ax);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -692,7 +735,7 @@ __global__ void k_resid64_v(Lev<double> L, const double* __restrict__ b, const d
       acc[0] += bv[v] * bv[v];
       acc[1] += o[v] * o[v];
     }
-    stv<double>(r + c, o);
+    stv<double>(at(r, c), o);
   }
   const int ops[2] = {RSUM, RSUM};
   if (block_reduce_publish<2>(acc, ops, partials, counter)) {
@@ -713,7 +756,7 @@ __global__ void k_resid64_v(Lev<double> L, const double* __restrict__ b, const d
 }
 
 template <class T>
-__global__ void k_inner_init_v(Lev<T> L, const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ x,
+VEC_KERNEL k_inner_init_v(Lev<T> L, const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ x,
                                SolveStatus* st, double* partials, unsigned* counter) {
   constexpr int V = VW<T>::n;
   double acc[1] = {0.0};
@@ -721,12 +764,12 @@ __global__ void k_inner_init_v(Lev<T> L, const double* __restrict__ r64, T* __re
     T rv[V], zv[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      rv[v] = (T)r64[c + v];
+      rv[v] = (T)*at(r64, c + v);
       zv[v] = 0;
       acc[0] += (double)rv[v] * (double)rv[v];
     }
-    stv<T>(r + c, rv);
-    stv<T>(x + c, zv);
+    stv<T>(at(r, c), rv);
+    stv<T>(at(x, c), zv);
   }
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
@@ -745,67 +788,69 @@ __global__ void k_inner_init_v(Lev<T> L, const double* __restrict__ r64, T* __re
 }
 
 template <class T>
-__global__ void k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
+VEC_KERNEL k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
                            int first, T* __restrict__ zout) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
   double acc = 0.0;
   FOR_ITEMS(L, T, i, j, kv, c) {
     T rv[V], dv[V], zv[V];
-    ldv<T>(r + c, rv);
-    ldv<T>(L.diag + c, dv);
+    ldv<T>(at(r, c), rv);
+    ldv<T>(at(L.diag, c), dv);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       acc += (double)rv[v] * (double)rv[v] / (double)dv[v];
       zv[v] = rv[v] / dv[v];
     }
-    if (zout) stv<T>(zout + c, zv);
+    if (zout) stv<T>(at(zout, c), zv);
   }
   publish_rz(acc, st, partials, counter, first);
 }
 
-template <class T, bool JAC>
-__global__ void k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restrict__ r,
+// FIRST: p = z (the first iteration); the int argument is unused (the
+// signature matches the scalar kernel's).
+template <class T, bool JAC, bool FIRST>
+VEC_KERNEL k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restrict__ r,
                                 const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ q, SolveStatus* st,
-                                double* partials, unsigned* counter, int first) {
+                                double* partials, unsigned* counter, int) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
-  const T be = first ? T(0) : (T)st->beta;
+  const T be = FIRST ? T(0) : (T)st->beta;
   double acc[1] = {0.0};
-  auto pnv = [&](long long f, T(&o)[V]) {
+  auto pnv = [&](unsigned f, T(&o)[V]) {
     if (JAC) {
       T rv[V], dv[V];
-      ldv<T>(r + f, rv);
-      ldv<T>(L.diag + f, dv);
+      ldv<T>(at(r, f), rv);
+      ldv<T>(at(L.diag, f), dv);
 #pragma unroll
       for (int v = 0; v < V; ++v) o[v] = rv[v] / dv[v];
     } else {
-      ldv<T>(z + f, o);
+      ldv<T>(at(z, f), o);
     }
-    if (!first) {
+    if (!FIRST) {
       T pv[V];
-      ldv<T>(pin + f, pv);
+      ldv<T>(at(pin, f), pv);
 #pragma unroll
       for (int v = 0; v < V; ++v) o[v] = o[v] + be * pv[v];
     }
   };
-  auto pns = [&](long long f) -> T {
-    const T zf = JAC ? r[f] / L.diag[f] : z[f];
-    return first ? zf : zf + be * pin[f];
+  auto pns = [&](unsigned f) -> T {
+    const T zf = JAC ? *at(r, f) / *at(L.diag, f) : *at(z, f);
+    return FIRST ? zf : zf + be * *at(pin, f);
   };
   FOR_ITEMS(L, T, i, j, kv, c) {
     T pc[V], qv[V], dv[V], off[V], y[V];
     pnv(c, pc);
-    ldv<T>(L.qc + c, qv);
-    ldv<T>(L.diag + c, dv);
+    ldv<T>(at(L.qc, c), qv);
+    ldv<T>(at(L.diag, c), dv);
     off_sum_v<T>(L, c, i, j, kv, qv, pc, pnv, pns, off);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       y[v] = dv[v] * pc[v] - T(0.5) * L.sc * off[v];
       acc[0] += (double)pc[v] * (double)y[v];
     }
-    stv<T>(pout + c, pc);
-    stv<T>(q + c, y);
+    stv<T>(at(pout, c), pc);
+    stv<T>(at(q, c), y);
   }
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
@@ -816,7 +861,12 @@ __global__ void k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __re
 }
 
 template <class T, bool JAC>
-__global__ void k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+static auto dir_v(bool first) {
+  return first ? k_cg_dir_spmv_v<T, JAC, true> : k_cg_dir_spmv_v<T, JAC, false>;
+}
+
+template <class T, bool JAC>
+VEC_KERNEL k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                               const T* __restrict__ q, SolveStatus* st, double* partials, unsigned* counter,
                               T* __restrict__ zout) {
   if (st->done) return;
@@ -825,12 +875,12 @@ __global__ void k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, co
   double acc[2] = {0.0, 0.0};
   FOR_ITEMS(L, T, i, j, kv, c) {
     T xv[V], rv[V], pv[V], qv[V];
-    ldv<T>(x + c, xv);
-    ldv<T>(r + c, rv);
-    ldv<T>(p + c, pv);
-    ldv<T>(q + c, qv);
+    ldv<T>(at(x, c), xv);
+    ldv<T>(at(r, c), rv);
+    ldv<T>(at(p, c), pv);
+    ldv<T>(at(q, c), qv);
     T dv[V], zv[V];
-    if (JAC) ldv<T>(L.diag + c, dv);
+    if (JAC) ldv<T>(at(L.diag, c), dv);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       xv[v] += a * pv[v];
@@ -841,9 +891,9 @@ __global__ void k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, co
         zv[v] = rv[v] / dv[v];
       }
     }
-    stv<T>(x + c, xv);
-    stv<T>(r + c, rv);
-    if (JAC && zout) stv<T>(zout + c, zv);
+    stv<T>(at(x, c), xv);
+    stv<T>(at(r, c), rv);
+    if (JAC && zout) stv<T>(at(zout, c), zv);
   }
   const int ops[2] = {RSUM, RSUM};
   if (block_reduce_publish<2>(acc, ops, partials, counter)) {
@@ -867,7 +917,7 @@ __global__ void k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, co
 
 // FP64 CG with the FP32 multigrid preconditioner: the update also stores
 // r in FP32 for the V-cycle; the direction update reads z in FP32.
-__global__ void k_cg_update_r32_v(Lev<double> L, double* __restrict__ x, double* __restrict__ r,
+VEC_KERNEL k_cg_update_r32_v(Lev<double> L, double* __restrict__ x, double* __restrict__ r,
                                   const double* __restrict__ p, const double* __restrict__ q, float* __restrict__ r32,
                                   SolveStatus* st, double* partials, unsigned* counter) {
   if (st->done) return;
@@ -876,10 +926,10 @@ __global__ void k_cg_update_r32_v(Lev<double> L, double* __restrict__ x, double*
   double acc[1] = {0.0};
   FOR_ITEMS(L, double, i, j, kv, c) {
     double xv[V], rv[V], pv[V], qv[V];
-    ldv<double>(x + c, xv);
-    ldv<double>(r + c, rv);
-    ldv<double>(p + c, pv);
-    ldv<double>(q + c, qv);
+    ldv<double>(at(x, c), xv);
+    ldv<double>(at(r, c), rv);
+    ldv<double>(at(p, c), pv);
+    ldv<double>(at(q, c), qv);
     float2 rf;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -889,9 +939,9 @@ __global__ void k_cg_update_r32_v(Lev<double> L, double* __restrict__ x, double*
     }
     rf.x = (float)rv[0];
     rf.y = (float)rv[1];
-    stv<double>(x + c, xv);
-    stv<double>(r + c, rv);
-    *reinterpret_cast<float2*>(r32 + c) = rf;
+    stv<double>(at(x, c), xv);
+    stv<double>(at(r, c), rv);
+    *reinterpret_cast<float2*>(at(r32, c)) = rf;
   }
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
@@ -907,38 +957,39 @@ __global__ void k_cg_update_r32_v(Lev<double> L, double* __restrict__ x, double*
   }
 }
 
-__global__ void k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const double* __restrict__ pin,
+template <bool FIRST>
+VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const double* __restrict__ pin,
                                     double* __restrict__ pout, double* __restrict__ q, SolveStatus* st,
-                                    double* partials, unsigned* counter, int first) {
+                                    double* partials, unsigned* counter) {
   if (st->done) return;
   constexpr int V = VW<double>::n;
-  const double be = first ? 0.0 : st->beta;
+  const double be = FIRST ? 0.0 : st->beta;
   double acc[1] = {0.0};
-  auto pnv = [&](long long f, double(&o)[V]) {
-    const float2 zf = *reinterpret_cast<const float2*>(z + f);
+  auto pnv = [&](unsigned f, double(&o)[V]) {
+    const float2 zf = *reinterpret_cast<const float2*>(at(z, f));
     o[0] = (double)zf.x;
     o[1] = (double)zf.y;
-    if (!first) {
+    if (!FIRST) {
       double pv[V];
-      ldv<double>(pin + f, pv);
+      ldv<double>(at(pin, f), pv);
 #pragma unroll
       for (int v = 0; v < V; ++v) o[v] = o[v] + be * pv[v];
     }
   };
-  auto pns = [&](long long f) -> double { return first ? (double)z[f] : (double)z[f] + be * pin[f]; };
+  auto pns = [&](unsigned f) -> double { return FIRST ? (double)*at(z, f) : (double)*at(z, f) + be * *at(pin, f); };
   FOR_ITEMS(L, double, i, j, kv, c) {
     double pc[V], qv[V], dv[V], off[V], y[V];
     pnv(c, pc);
-    ldv<double>(L.qc + c, qv);
-    ldv<double>(L.diag + c, dv);
+    ldv<double>(at(L.qc, c), qv);
+    ldv<double>(at(L.diag, c), dv);
     off_sum_v<double>(L, c, i, j, kv, qv, pc, pnv, pns, off);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       y[v] = dv[v] * pc[v] - 0.5 * L.sc * off[v];
       acc[0] += pc[v] * y[v];
     }
-    stv<double>(pout + c, pc);
-    stv<double>(q + c, y);
+    stv<double>(at(pout, c), pc);
+    stv<double>(at(q, c), y);
   }
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
@@ -949,13 +1000,13 @@ __global__ void k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, 
 }
 
 template <class T>
-__global__ void k_add_correction_v(Lev<T> L, double* __restrict__ x, const T* __restrict__ e) {
+VEC_KERNEL k_add_correction_v(Lev<T> L, double* __restrict__ x, const T* __restrict__ e) {
   constexpr int V = VW<T>::n;
   FOR_ITEMS(L, T, i, j, kv, c) {
     T ev[V];
-    ldv<T>(e + c, ev);
+    ldv<T>(at(e, c), ev);
 #pragma unroll
-    for (int v = 0; v < V; ++v) x[c + v] += (double)ev[v];
+    for (int v = 0; v < V; ++v) *at(x, c + v) += (double)ev[v];
   }
 }
 
@@ -1062,7 +1113,7 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
   const bool vec = use_vec(L);
   const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
   if (H) {
-    auto kdir = vec ? k_cg_dir_spmv_v<T, false> : k_cg_dir_spmv<T, false>;
+    auto kdir = vec ? dir_v<T, false>(first) : k_cg_dir_spmv<T, false>;
     if (ev0) {
       // events attached to the dispatch itself: kernel start and end times
       hipExtLaunchKernelGGL(kdir, dim3(nb), dim3(BLOCK), 0, s, ev0, ev1, 0, L, (const T*)*z, (const T*)V.r,
@@ -1077,11 +1128,11 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
   } else {
     if (vec && V.zj) {
       // z = r/diag was stored by the previous update (or the start)
-      k_cg_dir_spmv_v<T, false><<<nb, BLOCK, 0, s>>>(L, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      dir_v<T, false>(first)<<<nb, BLOCK, 0, s>>>(L, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
       std::swap(V.p, V.p_alt);
       k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, V.zj);
     } else if (vec) {
-      k_cg_dir_spmv_v<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      dir_v<T, true>(first)<<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
       std::swap(V.p, V.p_alt);
       k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
     } else {
@@ -1102,7 +1153,7 @@ double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout
                               hipEvent_t e1) {
   const bool vec = use_vec(L);
   const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
-  auto kdir = vec ? k_cg_dir_spmv_v<T, false> : k_cg_dir_spmv<T, false>;
+  auto kdir = vec ? k_cg_dir_spmv_v<T, false, false> : k_cg_dir_spmv<T, false>;
   kdir<<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
   for (int t = 0; t < reps; ++t) kdir<<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
@@ -1173,7 +1224,8 @@ void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, fl
 void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V, float* r32, float** z,
                        SolveStatus* st, double* partials, unsigned* counters, bool first, hipStream_t s) {
   const int nb = vec_blocks(vec_items(L));
-  k_cg_dir_spmv_z32_v<<<nb, BLOCK, 0, s>>>(L, *z, V.p, V.p_alt, V.q, st, partials, counters, first);
+  if (first) k_cg_dir_spmv_z32_v<true><<<nb, BLOCK, 0, s>>>(L, *z, V.p, V.p_alt, V.q, st, partials, counters);
+  else k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(L, *z, V.p, V.p_alt, V.q, st, partials, counters);
   std::swap(V.p, V.p_alt);
   k_cg_update_r32_v<<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, r32, st, partials, counters + 1);
   mg_vcycle(H, 0, r32, st, partials, counters + 2, false, true, s, z);
@@ -1183,9 +1235,9 @@ double replay_operator_z32(const Lev<double>& L, const float* z, const double* p
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1) {
   const int nb = vec_blocks(vec_items(L));
-  k_cg_dir_spmv_z32_v<<<nb, BLOCK, 0, s>>>(L, z, pin, pout, q, st, partials, counter, 0);
+  k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(L, z, pin, pout, q, st, partials, counter);
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-  for (int t = 0; t < reps; ++t) k_cg_dir_spmv_z32_v<<<nb, BLOCK, 0, s>>>(L, z, pin, pout, q, st, partials, counter, 0);
+  for (int t = 0; t < reps; ++t) k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(L, z, pin, pout, q, st, partials, counter);
   if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
