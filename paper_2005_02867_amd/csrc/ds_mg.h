@@ -26,6 +26,7 @@ template <class T>
 struct Lev {
   int nx, ny, nz;
   int ytile;
+  int mch;     // chunks of x-planes per column in the marching kernels (set by the launcher)
   int ntk, ntj;
   unsigned ntiles;
   long long n;
@@ -40,6 +41,7 @@ inline void lev_dims(Lev<T>& L, int nx, int ny, int nz, double sc) {
   L.ny = ny;
   L.nz = nz;
   L.ytile = (g_vec_ytile > 0 && ny % g_vec_ytile == 0) ? g_vec_ytile : ny;
+  L.mch = 1;
   L.ntk = (nz + TK - 1) / TK;
   L.ntj = (ny + TJ - 1) / TJ;
   L.ntiles = (unsigned)L.ntk * (unsigned)L.ntj * (unsigned)nx;

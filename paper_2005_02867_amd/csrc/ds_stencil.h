@@ -11,29 +11,28 @@ __device__ __forceinline__ double alpha_or0(const DevParams& P, const double* a,
   return a[cidx(P, i, j, k)];
 }
 
-// TVD (van Leer) face value along one grid line: face f lies between cells
-// f-1 and f; `line` points at cell 0 of the line, `st` is the stride.
-__device__ __forceinline__ double face_value(const double* __restrict__ phi, long long line, long long st,
-                                             int f, int na, double uf, double amb) {
-  if (f == 0) return uf > 0.0 ? amb : phi[line];
-  if (f == na) return uf < 0.0 ? amb : phi[line + (long long)(na - 1) * st];
-  if (uf == 0.0) return 0.0;
-  double C, D, U;
-  if (uf > 0.0) {
-    C = phi[line + (long long)(f - 1) * st];
-    D = phi[line + (long long)f * st];
-    U = (f >= 2) ? phi[line + (long long)(f - 2) * st] : C;
-  } else {
-    C = phi[line + (long long)f * st];
-    D = phi[line + (long long)(f - 1) * st];
-    U = (f + 1 <= na - 1) ? phi[line + (long long)(f + 1) * st] : C;
-  }
-  // van Leer: with r = (C - U)/(D - C) and psi = (r + |r|)/(1 + |r|), the face
-  // value C + psi (D - C)/2 equals C + (C - U)(D - C)/(D - U) for r > 0 and C
-  // otherwise -- one division instead of two.
+// TVD (van Leer) value on the interior face between cells a (lower) and b
+// (upper) of a grid line, for face velocity uf; m and p are the cells beyond
+// a and b, hm/hp whether they exist (else the upwind cell stands in for the
+// far-upwind one).  Branch-free: the caller loads every candidate first.
+// With r = (C - U)/(D - C) and psi = (r + |r|)/(1 + |r|), the face value
+// C + psi (D - C)/2 equals C + (C - U)(D - C)/(D - U) for r > 0 and C
+// otherwise -- one division instead of two.
+__device__ __forceinline__ double tvd_face(double m, double a, double b, double p, bool hm, bool hp, double uf) {
+  const bool fwd = uf > 0.0;
+  const double C = fwd ? a : b, D = fwd ? b : a;
+  const double U = fwd ? (hm ? m : a) : (hp ? p : b);
   const double den = D - C, up = C - U;
-  if (!((up > 0.0 && den > 0.0) || (up < 0.0 && den < 0.0))) return C;
-  return C + up * den / (D - U);
+  const bool mono = (up > 0.0 && den > 0.0) || (up < 0.0 && den < 0.0);
+  const double v = mono ? C + up * den / (D - U) : C;
+  return uf == 0.0 ? 0.0 : v;
+}
+
+// Face value on a box face of a cell's line: the ambient value where the
+// flow enters (uf > 0 on the low side, uf < 0 on the high side), else the
+// cell's own value.
+__device__ __forceinline__ double box_face(double cell, double amb, double uf, int side) {
+  return (side == 0 ? uf > 0.0 : uf < 0.0) ? amb : cell;
 }
 
 // Liquid-marker face velocity: the divergence-free part u - G phi (phi = 0

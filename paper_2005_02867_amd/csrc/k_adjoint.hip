@@ -52,7 +52,7 @@ __device__ void grad_add(double (&acc)[NV], const int (&slot)[NV], double* parti
   }
 }
 
-// face_value() of the forward step with its partial derivatives: positions
+// The TVD face value of the forward step (tvd_face, box_face) with its partial derivatives: positions
 // along the line of the cells it reads and the derivative for each (a cell
 // that appears twice, U := C at the box edge, gets both terms).
 struct FaceD {

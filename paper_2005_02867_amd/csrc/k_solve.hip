@@ -563,6 +563,127 @@ __device__ __forceinline__ void off_sum_v(const Lev<T>& L, unsigned c, int i, in
   }
 }
 
+// ------------------------------------------------------- column marching
+// The stencil kernels of the solvers walk the grid as columns: a thread owns
+// one vector of VW cells of a y-z row, (j, kv), and steps through a chunk of
+// x-planes.  q and the operand X of planes i-1, i, i+1 stay in registers
+// across steps (the x neighbours cost no extra load), the z neighbours come
+// from the adjacent lanes (lanes hold consecutive kv of a row; a load only at
+// a wave's first and last lane), and only the y neighbours are loaded.
+// Consecutive logical blocks run on one XCD, so the rows j-1, j+1 a block
+// reads come from the same L2.
+
+// Chunks per column: enough threads for about 1024 blocks of 256.
+template <class T>
+inline Lev<T> march_lev(Lev<T> L) {
+  const long long ncol = (long long)L.ny * (L.nz / VW<T>::n);
+  const long long nch = std::min<long long>(std::max<long long>((262144 + ncol - 1) / ncol, 1), L.nx);
+  const long long clen = (L.nx + nch - 1) / nch;
+  L.mch = (int)((L.nx + clen - 1) / clen);   // no empty trailing chunks
+  return L;
+}
+// Grid of the marching kernels: one thread per (column, chunk), at most
+// 4096 blocks (threads then take several columns; every marching kernel
+// publishes at most 2 partials per block).
+template <class T>
+inline int march_blocks(const Lev<T>& L) {
+  const long long nt = (long long)L.ny * (L.nz / VW<T>::n) * L.mch;
+  const long long nb = std::min<long long>(std::max<long long>((nt + BLOCK - 1) / BLOCK, NXCD), 4096);
+  return (int)((nb + NXCD - 1) / NXCD * NXCD);
+}
+
+template <class T>
+__device__ __forceinline__ T lane_up(T v) { return __shfl_up(v, 1, 64); }     // value of lane - 1
+template <class T>
+__device__ __forceinline__ T lane_down(T v) { return __shfl_down(v, 1, 64); } // value of lane + 1
+
+// lx(f, out): operand vector at cell f; sx(f): operand at the single cell f;
+// body(c, qc, xc, off): the cells' own q and X and off = sum_nb (q + q_nb) X_nb
+// (order x-, x+, y-, y+, z-, z+, as in the scalar kernels).  Work items are
+// (chunk, j, kv), kv fastest; a grid-stride loop covers them (the stride is a
+// multiple of 64, so a wave's lanes always hold consecutive items).  Threads
+// past the end do nothing and return normally (block reductions follow).
+template <class T, class LX, class SX, class BODY>
+__device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) {
+  constexpr int V = VW<T>::n;
+  const unsigned nzv = (unsigned)L.nz / V, ny = (unsigned)L.ny, nx = (unsigned)L.nx;
+  const unsigned nch = (unsigned)L.mch, clen = (nx + nch - 1) / nch;
+  const unsigned per = gridDim.x / NXCD, lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+  const unsigned total = ny * nzv * nch;
+  const unsigned P = ny * (unsigned)L.nz, sy = (unsigned)L.nz;
+  const int lane = threadIdx.x & 63;
+  for (unsigned e = lb * BLOCK + threadIdx.x; e < total; e += gridDim.x * BLOCK) {
+  const unsigned kv = e % nzv, t = e / nzv, j = t % ny, ch = t / ny;
+  const unsigned i0 = ch * clen, i1 = min(nx, i0 + clen);
+  if (i0 >= i1) continue;
+  const bool hym = j > 0, hyp = j + 1 < ny, hzm = kv > 0, hzp = kv + 1 < nzv;
+  unsigned c = i0 * P + j * sy + kv * V;
+  T qp[V], xp[V], qc[V], xc[V];
+  {
+    const unsigned f = i0 > 0 ? c - P : c;
+    ldv<T>(at(L.qc, f), qp);
+    lx(f, xp);
+  }
+  ldv<T>(at(L.qc, c), qc);
+  lx(c, xc);
+  for (unsigned i = i0; i < i1; ++i, c += P) {
+    const bool hxm = i > 0, hxp = i + 1 < nx;
+    const unsigned fn = hxp ? c + P : c, fym = hym ? c - sy : c, fyp = hyp ? c + sy : c;
+    T qn[V], xn[V], qym[V], xym[V], qyp[V], xyp[V];
+    ldv<T>(at(L.qc, fn), qn);
+    lx(fn, xn);
+    ldv<T>(at(L.qc, fym), qym);
+    lx(fym, xym);
+    ldv<T>(at(L.qc, fyp), qyp);
+    lx(fyp, xyp);
+    T qzm = lane_up(qc[V - 1]), xzm = lane_up(xc[V - 1]);
+    T qzp = lane_down(qc[0]), xzp = lane_down(xc[0]);
+    if (hzm && lane == 0) {
+      qzm = *at(L.qc, c - 1);
+      xzm = sx(c - 1);
+    }
+    if (hzp && lane == 63) {
+      qzp = *at(L.qc, c + V);
+      xzp = sx(c + V);
+    }
+    T off[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) off[v] = 0;
+    auto nbr = [&](const T (&g)[V], const T (&x)[V], bool has) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const T tt = off[v] + (qc[v] + g[v]) * x[v];
+        off[v] = has ? tt : off[v];
+      }
+    };
+    nbr(qp, xp, hxm);
+    nbr(qn, xn, hxp);
+    nbr(qym, xym, hym);
+    nbr(qyp, xyp, hyp);
+    {
+      const T tt = off[0] + (qc[0] + qzm) * xzm;
+      off[0] = hzm ? tt : off[0];
+    }
+#pragma unroll
+    for (int v = 1; v < V; ++v) off[v] += (qc[v] + qc[v - 1]) * xc[v - 1];
+#pragma unroll
+    for (int v = 0; v < V - 1; ++v) off[v] += (qc[v] + qc[v + 1]) * xc[v + 1];
+    {
+      const T tt = off[V - 1] + (qc[V - 1] + qzp) * xzp;
+      off[V - 1] = hzp ? tt : off[V - 1];
+    }
+    body(c, qc, xc, off);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      qp[v] = qc[v];
+      xp[v] = xc[v];
+      qc[v] = qn[v];
+      xc[v] = xn[v];
+    }
+  }
+  }
+}
+
 template <class T>
 __device__ __forceinline__ void apply_v(const Lev<T>& L, const T* __restrict__ x, unsigned c, int i, int j, int kv,
                                         const T (&xc)[VW<T>::n], T (&y)[VW<T>::n]) {
@@ -606,21 +727,17 @@ VEC_KERNEL k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ 
     for (int v = 0; v < V; ++v) o[v] = omega * rv[v] / dv[v];
   };
   auto x1s = [&](unsigned f) -> T { return omega * *at(r, f) / *at(L.diag, f); };
-  FOR_ITEMS(L, T, i, j, kv, c) {
-    T rv[V], dv[V], qv[V], x1[V], off[V], o[V];
+  march<T>(L, x1v, x1s, [&](unsigned c, const T(&qv)[V], const T(&x1)[V], const T(&off)[V]) {
+    T rv[V], dv[V], o[V];
     ldv<T>(at(r, c), rv);
     ldv<T>(at(L.diag, c), dv);
-    ldv<T>(at(L.qc, c), qv);
-#pragma unroll
-    for (int v = 0; v < V; ++v) x1[v] = omega * rv[v] / dv[v];
-    off_sum_v<T>(L, c, i, j, kv, qv, x1, x1v, x1s, off);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const T ax = dv[v] * x1[v] - T(0.5) * L.sc * off[v];
       o[v] = x1[v] + omega * (rv[v] - ax) / dv[v];
     }
     stv<T>(at(xout, c), o);
-  }
+  });
 }
 
 template <class T, bool DOT>
@@ -629,19 +746,20 @@ VEC_KERNEL k_mg_smooth_v(Lev<T> L, const T* __restrict__ r, const T* __restrict_
   if (st->done) return;
   constexpr int V = VW<T>::n;
   double acc = 0.0;
-  FOR_ITEMS(L, T, i, j, kv, c) {
-    T rv[V], xv[V], ax[V], dv[V], o[V];
-    ldv<T>(at(r, c), rv);
-    ldv<T>(at(xin, c), xv);
-    ldv<T>(at(L.diag, c), dv);
-    apply_v<T>(L, xin, c, i, j, kv, xv, ax);
+  march<T>(
+      L, [&](unsigned f, T(&o)[V]) { ldv<T>(at(xin, f), o); }, [&](unsigned f) { return *at(xin, f); },
+      [&](unsigned c, const T(&qv)[V], const T(&xv)[V], const T(&off)[V]) {
+        T rv[V], dv[V], o[V];
+        ldv<T>(at(r, c), rv);
+        ldv<T>(at(L.diag, c), dv);
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      o[v] = xv[v] + omega * (rv[v] - ax[v]) / dv[v];
-      if (DOT) acc += (double)rv[v] * (double)o[v];
-    }
-    stv<T>(at(xout, c), o);
-  }
+        for (int v = 0; v < V; ++v) {
+          const T ax = dv[v] * xv[v] - T(0.5) * L.sc * off[v];
+          o[v] = xv[v] + omega * (rv[v] - ax) / dv[v];
+          if (DOT) acc += (double)rv[v] * (double)o[v];
+        }
+        stv<T>(at(xout, c), o);
+      });
   if (DOT) publish_rz(acc, st, partials, counter, first);
 }
 
@@ -686,28 +804,26 @@ VEC_KERNEL k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, co
   if (st->done) return;
   constexpr int V = VW<T>::n;
   double acc = 0.0;
-  FOR_ITEMS(F, T, i, j, kv, c) {
-    // x + P xc for the vector of fine row (ii, jj) starting at fine index f (first z = kv*V)
-    auto row = [&](unsigned f, T(&o)[V]) {
-      const unsigned rr = f / (unsigned)F.nz;   // ii*ny + jj
-      const unsigned jj = rr % (unsigned)F.ny, ii = rr / (unsigned)F.ny;
-      const unsigned pb = ((ii >> 1) * (unsigned)C.ny + (jj >> 1)) * (unsigned)C.nz + (unsigned)kv * (V / 2);
-      ldv<T>(at(x, f), o);
+  // x + P xc for the vector of VW fine cells starting at fine index f
+  auto row = [&](unsigned f, T(&o)[V]) {
+    const unsigned rr = f / (unsigned)F.nz;   // ii*ny + jj
+    const unsigned kk = f - rr * (unsigned)F.nz;
+    const unsigned jj = rr % (unsigned)F.ny, ii = rr / (unsigned)F.ny;
+    const unsigned pb = ((ii >> 1) * (unsigned)C.ny + (jj >> 1)) * (unsigned)C.nz + (kk >> 1);
+    ldv<T>(at(x, f), o);
 #pragma unroll
-      for (int v = 0; v < V; ++v) o[v] += *at(xc, pb + (v >> 1));
-    };
-    auto one = [&](unsigned f) -> T {
-      const unsigned rr = f / (unsigned)F.nz;
-      const unsigned kk = f - rr * (unsigned)F.nz;
-      const unsigned jj = rr % (unsigned)F.ny, ii = rr / (unsigned)F.ny;
-      return *at(x, f) + *at(xc, ((ii >> 1) * (unsigned)C.ny + (jj >> 1)) * (unsigned)C.nz + (kk >> 1));
-    };
-    T x0[V], rv[V], qv[V], dv[V], off[V], o[V];
-    row(c, x0);
+    for (int v = 0; v < V; ++v) o[v] += *at(xc, pb + (v >> 1));
+  };
+  auto one = [&](unsigned f) -> T {
+    const unsigned rr = f / (unsigned)F.nz;
+    const unsigned kk = f - rr * (unsigned)F.nz;
+    const unsigned jj = rr % (unsigned)F.ny, ii = rr / (unsigned)F.ny;
+    return *at(x, f) + *at(xc, ((ii >> 1) * (unsigned)C.ny + (jj >> 1)) * (unsigned)C.nz + (kk >> 1));
+  };
+  march<T>(F, row, one, [&](unsigned c, const T(&qv)[V], const T(&x0)[V], const T(&off)[V]) {
+    T rv[V], dv[V], o[V];
     ldv<T>(at(r, c), rv);
-    ldv<T>(at(F.qc, c), qv);
     ldv<T>(at(F.diag, c), dv);
-    off_sum_v<T>(F, c, i, j, kv, qv, x0, row, one, off);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const T Ax = dv[v] * x0[v] - T(0.5) * F.sc * off[v];
@@ -715,7 +831,7 @@ VEC_KERNEL k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, co
       if (DOT) acc += (double)rv[v] * (double)o[v];
     }
     stv<T>(at(xout, c), o);
-  }
+  });
   if (DOT) publish_rz(acc, st, partials, counter, first);
 }
 
@@ -724,19 +840,21 @@ VEC_KERNEL k_resid64_v(Lev<double> L, const double* __restrict__ b, const double
                             int set_bnorm) {
   constexpr int V = VW<double>::n;
   double acc[2] = {0.0, 0.0};
-  FOR_ITEMS(L, double, i, j, kv, c) {
-    double bv[V], xv[V], ax[V], o[V];
-    ldv<double>(at(b, c), bv);
-    ldv<double>(at(x, c), xv);
-    apply_v<double>(L, x, c, i, j, kv, xv, ax);
+  march<double>(
+      L, [&](unsigned f, double(&o)[V]) { ldv<double>(at(x, f), o); }, [&](unsigned f) { return *at(x, f); },
+      [&](unsigned c, const double(&qv)[V], const double(&xv)[V], const double(&off)[V]) {
+        double bv[V], dg[V], o[V];
+        ldv<double>(at(b, c), bv);
+        ldv<double>(at(L.diag, c), dg);
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      o[v] = bv[v] - ax[v];
-      acc[0] += bv[v] * bv[v];
-      acc[1] += o[v] * o[v];
-    }
-    stv<double>(at(r, c), o);
-  }
+        for (int v = 0; v < V; ++v) {
+          const double ax = dg[v] * xv[v] - 0.5 * L.sc * off[v];
+          o[v] = bv[v] - ax;
+          acc[0] += bv[v] * bv[v];
+          acc[1] += o[v] * o[v];
+        }
+        stv<double>(at(r, c), o);
+      });
   const int ops[2] = {RSUM, RSUM};
   if (block_reduce_publish<2>(acc, ops, partials, counter)) {
     double t[2];
@@ -838,12 +956,9 @@ VEC_KERNEL k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restric
     const T zf = JAC ? *at(r, f) / *at(L.diag, f) : *at(z, f);
     return FIRST ? zf : zf + be * *at(pin, f);
   };
-  FOR_ITEMS(L, T, i, j, kv, c) {
-    T pc[V], qv[V], dv[V], off[V], y[V];
-    pnv(c, pc);
-    ldv<T>(at(L.qc, c), qv);
+  march<T>(L, pnv, pns, [&](unsigned c, const T(&qv)[V], const T(&pc)[V], const T(&off)[V]) {
+    T dv[V], y[V];
     ldv<T>(at(L.diag, c), dv);
-    off_sum_v<T>(L, c, i, j, kv, qv, pc, pnv, pns, off);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       y[v] = dv[v] * pc[v] - T(0.5) * L.sc * off[v];
@@ -851,7 +966,7 @@ VEC_KERNEL k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restric
     }
     stv<T>(at(pout, c), pc);
     stv<T>(at(q, c), y);
-  }
+  });
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
     double t[1];
@@ -977,12 +1092,9 @@ VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const
     }
   };
   auto pns = [&](unsigned f) -> double { return FIRST ? (double)*at(z, f) : (double)*at(z, f) + be * *at(pin, f); };
-  FOR_ITEMS(L, double, i, j, kv, c) {
-    double pc[V], qv[V], dv[V], off[V], y[V];
-    pnv(c, pc);
-    ldv<double>(at(L.qc, c), qv);
+  march<double>(L, pnv, pns, [&](unsigned c, const double(&qv)[V], const double(&pc)[V], const double(&off)[V]) {
+    double dv[V], y[V];
     ldv<double>(at(L.diag, c), dv);
-    off_sum_v<double>(L, c, i, j, kv, qv, pc, pnv, pns, off);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       y[v] = dv[v] * pc[v] - 0.5 * L.sc * off[v];
@@ -990,7 +1102,7 @@ VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const
     }
     stv<double>(at(pout, c), pc);
     stv<double>(at(q, c), y);
-  }
+  });
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
     double t[1];
@@ -1030,13 +1142,15 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   T* b = H.t[l];
   const bool vec = use_vec(L);
   const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
+  const Lev<T> M = vec ? march_lev(L) : L;   // the marching kernels' view and grid
+  const int nbm = vec ? march_blocks(M) : nb;
   const bool coarsest = (l == H.nlev - 1);
   const int nu = l == 0 ? H.nu_fine : H.nu;
   const int pre = coarsest ? std::max(2, H.coarse_sweeps) : nu;
   auto smooth = [&](bool d, int df) {
     if (vec) {
-      if (d) k_mg_smooth_v<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, df);
-      else k_mg_smooth_v<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
+      if (d) k_mg_smooth_v<T, true><<<nbm, BLOCK, 0, s>>>(M, r, a, b, om, st, partials, counter, df);
+      else k_mg_smooth_v<T, false><<<nbm, BLOCK, 0, s>>>(M, r, a, b, om, st, partials, counter, 0);
     } else {
       if (d) k_mg_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, df);
       else k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
@@ -1050,7 +1164,7 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   }
   int t0 = 1;
   if (vec && pre >= 2 && !(coarsest && dot && pre == 2)) {
-    k_mg_smooth_two_v<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
+    k_mg_smooth_two_v<T><<<nbm, BLOCK, 0, s>>>(M, r, a, om, st);
     t0 = 2;
   } else if (vec) {
     k_mg_smooth_zero_v<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
@@ -1079,8 +1193,8 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
     const bool d = dot && t == nu - 1;
     if (t == 0) {
       if (vec) {
-        if (d) k_mg_prolong_smooth_v<T, true><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, dot_first);
-        else k_mg_prolong_smooth_v<T, false><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, 0);
+        if (d) k_mg_prolong_smooth_v<T, true><<<nbm, BLOCK, 0, s>>>(M, C, r, a, xc, b, om, st, partials, counter, dot_first);
+        else k_mg_prolong_smooth_v<T, false><<<nbm, BLOCK, 0, s>>>(M, C, r, a, xc, b, om, st, partials, counter, 0);
       } else {
         if (d) k_mg_prolong_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, dot_first);
         else k_mg_prolong_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, 0);
@@ -1112,14 +1226,16 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
                   unsigned* counters, bool first, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const bool vec = use_vec(L);
   const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
+  const Lev<T> M = vec ? march_lev(L) : L;   // the operator kernel's view and grid
+  const int nbm = vec ? march_blocks(M) : nb;
   if (H) {
     auto kdir = vec ? dir_v<T, false>(first) : k_cg_dir_spmv<T, false>;
     if (ev0) {
       // events attached to the dispatch itself: kernel start and end times
-      hipExtLaunchKernelGGL(kdir, dim3(nb), dim3(BLOCK), 0, s, ev0, ev1, 0, L, (const T*)*z, (const T*)V.r,
+      hipExtLaunchKernelGGL(kdir, dim3(nbm), dim3(BLOCK), 0, s, ev0, ev1, 0, M, (const T*)*z, (const T*)V.r,
                             (const T*)V.p, V.p_alt, V.q, st, partials, counters, (int)first);
     } else {
-      kdir<<<nb, BLOCK, 0, s>>>(L, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      kdir<<<nbm, BLOCK, 0, s>>>(M, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
     }
     std::swap(V.p, V.p_alt);
     if (vec) k_cg_update_v<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
@@ -1128,11 +1244,11 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
   } else {
     if (vec && V.zj) {
       // z = r/diag was stored by the previous update (or the start)
-      dir_v<T, false>(first)<<<nb, BLOCK, 0, s>>>(L, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      dir_v<T, false>(first)<<<nbm, BLOCK, 0, s>>>(M, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
       std::swap(V.p, V.p_alt);
       k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, V.zj);
     } else if (vec) {
-      dir_v<T, true>(first)<<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      dir_v<T, true>(first)<<<nbm, BLOCK, 0, s>>>(M, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
       std::swap(V.p, V.p_alt);
       k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
     } else {
@@ -1152,11 +1268,12 @@ double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout
                               double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                               hipEvent_t e1) {
   const bool vec = use_vec(L);
-  const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
+  const Lev<T> M = vec ? march_lev(L) : L;
+  const int nb = vec ? march_blocks(M) : tile_blocks(L.ntiles);
   auto kdir = vec ? k_cg_dir_spmv_v<T, false, false> : k_cg_dir_spmv<T, false>;
-  kdir<<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
+  kdir<<<nb, BLOCK, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter, 0);
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-  for (int t = 0; t < reps; ++t) kdir<<<nb, BLOCK, 0, s>>>(L, z, nullptr, pin, pout, q, st, partials, counter, 0);
+  for (int t = 0; t < reps; ++t) kdir<<<nb, BLOCK, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter, 0);
   if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
@@ -1168,11 +1285,12 @@ template <class T>
 double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, SolveStatus* st, int reps,
                             double omega, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const bool vec = use_vec(L);
-  const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
+  const Lev<T> M = vec ? march_lev(L) : L;
+  const int nb = vec ? march_blocks(M) : tile_blocks(L.ntiles);
   auto ks = vec ? k_mg_smooth_v<T, false> : k_mg_smooth<T, false>;
-  ks<<<nb, BLOCK, 0, s>>>(L, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
+  ks<<<nb, BLOCK, 0, s>>>(M, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-  for (int t = 0; t < reps; ++t) ks<<<nb, BLOCK, 0, s>>>(L, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
+  for (int t = 0; t < reps; ++t) ks<<<nb, BLOCK, 0, s>>>(M, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
   if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
@@ -1193,7 +1311,8 @@ template double replay_operator_kernel<float>(const Lev<float>&, const float*, c
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
                     double* partials, unsigned* counter, bool set_bnorm, hipStream_t s) {
   if (use_vec(L))
-    k_resid64_v<<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);
+    k_resid64_v<<<march_blocks(march_lev(L)), BLOCK, 0, s>>>(march_lev(L), b, x, r, st, partials, counter,
+                                                            set_bnorm ? 1 : 0);
   else
     k_resid64<<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);
 }
@@ -1224,8 +1343,10 @@ void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, fl
 void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V, float* r32, float** z,
                        SolveStatus* st, double* partials, unsigned* counters, bool first, hipStream_t s) {
   const int nb = vec_blocks(vec_items(L));
-  if (first) k_cg_dir_spmv_z32_v<true><<<nb, BLOCK, 0, s>>>(L, *z, V.p, V.p_alt, V.q, st, partials, counters);
-  else k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(L, *z, V.p, V.p_alt, V.q, st, partials, counters);
+  const Lev<double> M = march_lev(L);
+  const int nbm = march_blocks(M);
+  if (first) k_cg_dir_spmv_z32_v<true><<<nbm, BLOCK, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters);
+  else k_cg_dir_spmv_z32_v<false><<<nbm, BLOCK, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters);
   std::swap(V.p, V.p_alt);
   k_cg_update_r32_v<<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, r32, st, partials, counters + 1);
   mg_vcycle(H, 0, r32, st, partials, counters + 2, false, true, s, z);
@@ -1234,10 +1355,11 @@ bool mg32_supported(const Lev<double>& L) { return use_vec(L); }
 double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1) {
-  const int nb = vec_blocks(vec_items(L));
-  k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(L, z, pin, pout, q, st, partials, counter);
+  const Lev<double> M = march_lev(L);
+  const int nb = march_blocks(M);
+  k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(M, z, pin, pout, q, st, partials, counter);
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-  for (int t = 0; t < reps; ++t) k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(L, z, pin, pout, q, st, partials, counter);
+  for (int t = 0; t < reps; ++t) k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(M, z, pin, pout, q, st, partials, counter);
   if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;

@@ -173,46 +173,88 @@ __global__ void k_source(DevParams P, const double* __restrict__ alpha, const do
 }
 
 // ---------------------------------------------------------------- S5
-__global__ void k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
-                         const double* __restrict__ T, const double* __restrict__ c,
-                         const double* __restrict__ u, const double* __restrict__ v,
-                         const double* __restrict__ w, const double* __restrict__ phi, double* __restrict__ a_new,
-                         double* __restrict__ c_new, double* __restrict__ T_new, double* partials,
-                         unsigned* counter, double* scal) {
+// One cell per thread.  Along each axis the cell's line values at offsets
+// -2..+2 of alpha1, omega and T (and -1..+1 of phi) are loaded up front from
+// clamped positions, then both faces are formed with selects: no load waits
+// on a data-dependent branch (the upwind side).
+__global__ void __launch_bounds__(BLOCK)
+k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
+         const double* __restrict__ T, const double* __restrict__ c,
+         const double* __restrict__ u, const double* __restrict__ v,
+         const double* __restrict__ w, const double* __restrict__ phi, double* __restrict__ a_new,
+         double* __restrict__ c_new, double* __restrict__ T_new, double* partials,
+         unsigned* counter, double* scal) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   double acc[2] = {0.0, 0.0};   // outward liquid volume flux, vapour mass flux (per area)
+  const long long st[3] = {(long long)P.ny * P.nz, (long long)P.nz, 1};
+  const int nn[3] = {P.nx, P.ny, P.nz};
   for (long long cc = b0 + threadIdx.x; cc < b1; cc += BLOCK) {
     int i, j, k;
     decode(P, cc, i, j, k);
     const int pos[3] = {i, j, k};
-    const int nn[3] = {P.nx, P.ny, P.nz};
-    const long long st[3] = {(long long)P.ny * P.nz, (long long)P.nz, 1};
-    const long long line[3] = {cc - (long long)i * st[0], cc - (long long)j * st[1], cc - (long long)k};
     const double uf[3][2] = {{u[uidx(P, i, j, k)], u[uidx(P, i + 1, j, k)]},
                              {v[vidx(P, i, j, k)], v[vidx(P, i, j + 1, k)]},
                              {w[widx(P, i, j, k)], w[widx(P, i, j, k + 1)]}};
-    const double Tc = T[cc];
+    const double A0 = a1[cc], O0 = omega[cc], T0 = T[cc];
+    const double P0 = phi ? phi[cc] : 0.0;
+    // line values at offsets -2, -1, +1, +2 (index 0, 1, 2, 3); h: they exist
+    double A[3][4], O[3][4], TT[3][4], PH[3][2];
+    bool h[3][4];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int q = pos[ax], n = nn[ax];
+      h[ax][0] = q >= 2;
+      h[ax][1] = q >= 1;
+      h[ax][2] = q + 1 <= n - 1;
+      h[ax][3] = q + 2 <= n - 1;
+      const long long o[4] = {h[ax][0] ? -2 * st[ax] : 0, h[ax][1] ? -st[ax] : 0, h[ax][2] ? st[ax] : 0,
+                              h[ax][3] ? 2 * st[ax] : 0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        A[ax][t] = a1[cc + o[t]];
+        O[ax][t] = omega[cc + o[t]];
+        TT[ax][t] = T[cc + o[t]];
+      }
+      if (phi) {
+        PH[ax][0] = phi[cc + o[1]];
+        PH[ax][1] = phi[cc + o[2]];
+      }
+    }
+    const double cv = c[cc];
     double da = 0.0, dc = 0.0, dT = 0.0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
+      const int q = pos[ax], n = nn[ax];
+      const bool lo_in = q > 0, hi_in = q < n - 1;
       double F[2], G[2], H[2];
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
-        const int f = pos[ax] + sd;
         const double ufv = uf[ax][sd];
-        const double af = face_value(a1, line[ax], st[ax], f, nn[ax], ufv, 0.0);
-        const double of = face_value(omega, line[ax], st[ax], f, nn[ax], ufv, 0.0);
+        const bool in = sd == 0 ? lo_in : hi_in;
+        // interior face: (m, a, b, p) = (-2, -1, 0, +1) below the cell, (-1, 0, +1, +2) above
+        auto face = [&](const double (&L)[4], double c0, double vel) {
+          return sd == 0 ? tvd_face(L[0], L[1], c0, L[2], h[ax][0], h[ax][2], vel)
+                         : tvd_face(L[1], c0, L[2], L[3], h[ax][1], h[ax][3], vel);
+        };
+        const double af = in ? face(A[ax], A0, ufv) : box_face(A0, 0.0, ufv, sd);
+        const double of = in ? face(O[ax], O0, ufv) : box_face(O0, 0.0, ufv, sd);
         if (phi) {
-          const double ul = liquid_face_u(P, phi, ufv, line[ax], st[ax], f, nn[ax], ax);
-          F[sd] = ul * face_value(a1, line[ax], st[ax], f, nn[ax], ul, 0.0);
+          double ul;
+          if (sd == 0)
+            ul = in ? ufv - (P0 - PH[ax][0]) / P.h
+                    : (pressure_dirichlet(P.kind[ax * 2]) ? ufv - 2.0 * P0 / P.h : ufv);
+          else
+            ul = in ? ufv - (PH[ax][1] - P0) / P.h
+                    : (pressure_dirichlet(P.kind[ax * 2 + 1]) ? ufv + 2.0 * P0 / P.h : ufv);
+          F[sd] = ul * (in ? face(A[ax], A0, ul) : box_face(A0, 0.0, ul, sd));
         } else {
           F[sd] = ufv * af;
         }
         G[sd] = P.rho_G * of * (1.0 - af) * ufv;
         if (P.solve_energy) {
-          const double Tf = face_value(T, line[ax], st[ax], f, nn[ax], ufv, P.T_amb);
-          H[sd] = ufv * (Tf - Tc);
+          const double Tf = in ? face(TT[ax], T0, ufv) : box_face(T0, P.T_amb, ufv, sd);
+          H[sd] = ufv * (Tf - T0);
         } else {
           H[sd] = 0.0;
         }
@@ -220,19 +262,19 @@ __global__ void k_advect(DevParams P, const double* __restrict__ a1, const doubl
       da += F[1] - F[0];
       dc += G[1] - G[0];
       dT += H[1] - H[0];
-      if (pos[ax] == 0) {
+      if (!lo_in) {
         acc[0] -= F[0];
         acc[1] -= G[0];
       }
-      if (pos[ax] == nn[ax] - 1) {
+      if (!hi_in) {
         acc[0] += F[1];
         acc[1] += G[1];
       }
     }
     const double s = P.dt / P.h;
-    a_new[cc] = a1[cc] - s * da;
-    c_new[cc] = c[cc] - s * dc;
-    T_new[cc] = P.solve_energy ? Tc - s * dT : Tc;
+    a_new[cc] = A0 - s * da;
+    c_new[cc] = cv - s * dc;
+    T_new[cc] = P.solve_energy ? T0 - s * dT : T0;
   }
   const int ops[2] = {RSUM, RSUM};
   if (block_reduce_publish<2>(acc, ops, partials, counter)) {
