@@ -110,6 +110,16 @@ enum RedOp { RSUM = 0, RMIN = 1, RMAX = 2 };
 // Reduce NV values over the block (fixed order) and store them as this
 // block's partials.  Returns true in every thread of the last block to
 // finish (which may then combine the partials of all blocks).
+//
+// Publication without an L2 writeback: the partials are stored as
+// device-scope atomics, which on the multi-XCD part write through the XCD's
+// L2 to the device coherence point; thread 0 waits for those stores to
+// complete (s_waitcnt) before it bumps the counter, and the last block reads
+// the partials with device-scope atomic loads, which fetch from that point.
+// A device-scope release fence would instead write back every dirty line of
+// the L2 (the kernel's streamed outputs), which costs tens of microseconds per
+// block.  The last block reads nothing else that this launch wrote; the
+// outputs reach later kernels through the launch boundary.
 template <int NV>
 __device__ bool block_reduce_publish(double (&v)[NV], const int (&ops)[NV], double* partials,
                                      unsigned* counter) {
@@ -128,14 +138,13 @@ __device__ bool block_reduce_publish(double (&v)[NV], const int (&ops)[NV], doub
       double x = sh[0][q];
       for (int w = 1; w < BLOCK / 64; ++w)
         x = ops[q] == RSUM ? x + sh[w][q] : (ops[q] == RMIN ? fmin(x, sh[w][q]) : fmax(x, sh[w][q]));
-      partials[(size_t)blockIdx.x * NV + q] = x;
+      __hip_atomic_store(&partials[(size_t)blockIdx.x * NV + q], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);   // the partial stores have completed
     unsigned prev = atomicAdd(counter, 1u);
     last = (prev == gridDim.x - 1);
   }
   __syncthreads();
-  if (last) __threadfence();
   return last;
 }
 
