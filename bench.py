@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 # and WRITE_SIZE (separate runs of `bench.py --counters-pass`), each scaled by
 # the ratio of known bytes to the counter's reading for a 1 GiB device copy in
 # the same run; None until measured for the current kernel.
-# Measured for the fine-level sweep of the 256^3 workload: FETCH_SIZE 134769 KiB
-# x 2.000 (the 1 GiB copy reads 524300 KiB) + WRITE_SIZE 65536 KiB x 1.000.
-TRAFFIC_SMOOTH = (134769.0 * (1048576.0 / 524300.0) + 65536.0) * 1024.0
+# Measured for the fine-level sweep of the 256^3 workload: FETCH_SIZE 155599 KiB
+# x 2.000 (the 1 GiB copy reads 524331 KiB) + WRITE_SIZE 65536 KiB x 1.000.
+TRAFFIC_SMOOTH = (155599.0 * (1048576.0 / 524331.0) + 65536.0) * 1024.0
 
 
 def log(msg):

@@ -72,7 +72,7 @@ struct ds_grid {
   double* zj = nullptr;            // Jacobi z = r/diag (FP64 solves)
   float* zj32 = nullptr;           // the same for the FP32 rounds
   int dirmask = 0;                 // p_rgh = 0 box faces
-  int batch_p = 4;
+  int batch_p[2] = {4, 4};         // pressure, then any other pressure-type system (phi, adjoints)
   struct {
     double inner_min = 1e-3;   // smallest FP32 inner relative tolerance per round (pressure-type)
     double inner_min_jac = 1e-6;  // the same for the energy and species systems
@@ -340,9 +340,14 @@ void accumulate_timing(ds_grid* g, int did, double bytes_per_launch) {
   }
 }
 
-// Iterations enqueued between host convergence tests: about half of the
-// previous solve's count, so most solves finish in two or three batches.
-int& batch_of(ds_grid* g, int sys) { return sys == 2 ? g->batch_p : g->batch[sys]; }
+// Iterations enqueued before the first host convergence test: the previous
+// count of the same system (it barely changes from step to step), then a
+// quarter of it per test; so most solves take one test and enqueue few
+// iterations past convergence (each of those still costs its launches).
+int& batch_of(ds_grid* g, int sys, const double* x) {
+  return sys == 2 ? g->batch_p[x == g->p ? 0 : 1] : g->batch[sys];
+}
+int batch_size(int expected, bool first) { return first ? std::max(2, expected) : std::max(2, expected / 4); }
 
 // FP64 preconditioned CG on the system in qc/diag (scale sc), right-hand side
 // b, warm start in x.  sys: 0 = energy, 1 = species (Jacobi), 2 = pressure
@@ -373,7 +378,8 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
     const bool timed = g->timing && H;
     while (!g->h_status[sys].done) {
       const int it0 = g->h_status[sys].it;
-      const int m = timed ? std::min(batch_of(g, sys), (int)ds_grid::NEV) : batch_of(g, sys);
+      const int b = batch_size(batch_of(g, sys, x), first);
+      const int m = timed ? std::min(b, (int)ds_grid::NEV) : b;
       for (int t = 0; t < m; ++t) {
         cg_iteration(L, H, V, &z, ss, g->partials, g->counters + CT_SOLVE0, first, s,
                      timed ? g->ev[2 * t] : nullptr, timed ? g->ev[2 * t + 1] : nullptr);
@@ -385,7 +391,7 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
     }
   }
   const SolveStatus& h = g->h_status[sys];
-  batch_of(g, sys) = std::max(2, std::min(256, h.it / 2 + 1));
+  batch_of(g, sys, x) = std::max(2, std::min(256, h.it));
   *iters = h.it;
   *res = h.res;
   if (sys == 2) g->diag_out.refinements_p = 0;
@@ -439,7 +445,8 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     const bool timed = g->timing && H;
     do {
       const int it0 = g->h_status[3].it;
-      const int m = timed ? std::min(batch_of(g, sys), (int)ds_grid::NEV) : batch_of(g, sys);
+      const int b = batch_size(batch_of(g, sys, x), first);
+      const int m = timed ? std::min(b, (int)ds_grid::NEV) : b;
       for (int t = 0; t < m; ++t) {
         cg_iteration(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, first, s,
                      timed ? g->ev[2 * t] : nullptr, timed ? g->ev[2 * t + 1] : nullptr);
@@ -457,7 +464,7 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     if ((st = sync_status(g, sys, s)) != DS_OK) return st;
     ++rounds;
   }
-  batch_of(g, sys) = std::max(2, std::min(256, total / std::max(1, 2 * rounds) + 1));
+  batch_of(g, sys, x) = std::max(2, std::min(256, total / std::max(1, rounds)));
   *iters = total;
   *res = g->h_status[sys].res;
   if (sys == 2) g->diag_out.refinements_p = rounds;
@@ -496,7 +503,7 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
     cg_start_mg32(L, H, g->r, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, s);
     bool first = true;
     while (!g->h_status[sys].done) {
-      const int m = batch_of(g, sys);
+      const int m = batch_size(batch_of(g, sys, x), first);
       for (int t = 0; t < m; ++t) {
         cg_iteration_mg32(L, H, V, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, first, s);
         first = false;
@@ -506,7 +513,7 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
     }
   }
   const SolveStatus& h = g->h_status[sys];
-  batch_of(g, sys) = std::max(2, std::min(256, h.it / 2 + 1));
+  batch_of(g, sys, x) = std::max(2, std::min(256, h.it));
   *iters = h.it;
   *res = h.res;
   g->diag_out.refinements_p = 0;

@@ -56,6 +56,25 @@ __device__ __forceinline__ double bface_u(const DevParams& P, const double* u, c
   return w[widx(P, i, j, side ? k + 1 : k)];
 }
 
+// Values of a at the six neighbours of cell c in the order x-, x+, y-, y+,
+// z-, z+ (index ax*2 + side); has[f]: the neighbour exists.  A missing
+// neighbour reads the cell itself, so all six loads are issued before any
+// is used (no load waits behind a branch on the position).
+__device__ __forceinline__ void nbr6(const DevParams& P, const double* __restrict__ a, long long c, int i, int j,
+                                     int k, double (&o)[6], bool (&has)[6]) {
+  const long long sx = (long long)P.ny * P.nz, sy = P.nz;
+  has[0] = i > 0;
+  has[1] = i < P.nx - 1;
+  has[2] = j > 0;
+  has[3] = j < P.ny - 1;
+  has[4] = k > 0;
+  has[5] = k < P.nz - 1;
+  const long long f[6] = {has[0] ? c - sx : c, has[1] ? c + sx : c, has[2] ? c - sy : c,
+                          has[3] ? c + sy : c, has[4] ? c - 1 : c,  has[5] ? c + 1 : c};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) o[q] = a[f[q]];
+}
+
 // Neighbour of (i,j,k) across face (ax, side); returns -1 outside the box.
 __device__ __forceinline__ long long nbr(const DevParams& P, int ax, int side, int i, int j, int k) {
   const int d = side ? 1 : -1;

@@ -301,6 +301,9 @@ __global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, co
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
+    double an[6];
+    bool has[6];
+    nbr6(P, a_new, c, i, j, k, an, has);
     const double ab = clamp01(a_new[c]);
     const double rho = mix(ab, P.rho_L, P.rho_G), cp = mix(ab, P.cp_L, P.cp_G), kc = mix(ab, P.k_L, P.k_G);
     const double m = rho * cp / P.dt;
@@ -309,9 +312,8 @@ __global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, co
     for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
-        const long long nb = nbr(P, ax, sd, i, j, k);
-        if (nb >= 0) {
-          const double kn = mix(clamp01(a_new[nb]), P.k_L, P.k_G);
+        if (has[ax * 2 + sd]) {
+          const double kn = mix(clamp01(an[ax * 2 + sd]), P.k_L, P.k_G);
           d += ih2 * 0.5 * (kc + kn);
         } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
           d += Kb;
@@ -337,15 +339,17 @@ __global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, c
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
+    double an[6];
+    bool has[6];
+    nbr6(P, a_new, c, i, j, k, an, has);
     const double th = fmax(1.0 - clamp01(a_new[c]), P.theta_min);
     double d = P.rho_G * th / P.dt;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
-        const long long nb = nbr(P, ax, sd, i, j, k);
-        if (nb >= 0) {
-          const double tn = fmax(1.0 - clamp01(a_new[nb]), P.theta_min);
+        if (has[ax * 2 + sd]) {
+          const double tn = fmax(1.0 - clamp01(an[ax * 2 + sd]), P.theta_min);
           d += sc * 0.5 * (th + tn);
         } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
           d += Kb;
@@ -373,6 +377,10 @@ __global__ void k_species_update(DevParams P, const double* __restrict__ a_new, 
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
+    double an[6], on[6];
+    bool has[6];
+    nbr6(P, a_new, c, i, j, k, an, has);
+    nbr6(P, om, c, i, j, k, on, has);
     const double th = fmax(1.0 - clamp01(a_new[c]), P.theta_min);
     const double oc = om[c];
     double face = 0.0;
@@ -380,10 +388,9 @@ __global__ void k_species_update(DevParams P, const double* __restrict__ a_new, 
     for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
-        const long long nb = nbr(P, ax, sd, i, j, k);
-        if (nb >= 0) {
-          const double tn = fmax(1.0 - clamp01(a_new[nb]), P.theta_min);
-          face += sc * 0.5 * (th + tn) * (oc - om[nb]);
+        if (has[ax * 2 + sd]) {
+          const double tn = fmax(1.0 - clamp01(an[ax * 2 + sd]), P.theta_min);
+          face += sc * 0.5 * (th + tn) * (oc - on[ax * 2 + sd]);
         } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
           face += Kb * oc;
           acc[0] += Kb * oc;
@@ -477,15 +484,17 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
+    double an[6];
+    bool has[6];
+    nbr6(P, a_new, c, i, j, k, an, has);
     const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, P.rho_G);
     double d = 0.0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
-        const long long nb = nbr(P, ax, sd, i, j, k);
-        if (nb >= 0) {
-          const double bn = 1.0 / mix(clamp01(a_new[nb]), P.rho_L, P.rho_G);
+        if (has[ax * 2 + sd]) {
+          const double bn = 1.0 / mix(clamp01(an[ax * 2 + sd]), P.rho_L, P.rho_G);
           d += sc * 0.5 * (beta + bn);
         } else if (pressure_dirichlet(P.kind[ax * 2 + sd])) {
           d += 2.0 * sc * beta;
