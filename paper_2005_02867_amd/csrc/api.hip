@@ -291,7 +291,7 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Multigrid shape: damped-Jacobi sweeps, coarsest-level sweeps and the
 // smallest extent that is still coarsened (overridable for tuning through
-// DSVOF_MG_NU, DSVOF_MG_COARSE, DSVOF_MG_MINDIM).
+// DSVOF_MG_NU, DSVOF_MG_COARSE, DSVOF_MG_MINDIM, DSVOF_MG_TAIL).
 template <class T>
 void build_hier(MgHier<T>& H, int nx, int ny, int nz, double h, double dt) {
   H.nlev = 0;
@@ -302,6 +302,7 @@ void build_hier(MgHier<T>& H, int nx, int ny, int nz, double h, double dt) {
   if (const char* e = getenv("DSVOF_MG_COARSE")) H.coarse_sweeps = std::max(2, atoi(e));
   if (const char* e = getenv("DSVOF_MG_MINDIM")) mindim = std::max(4, atoi(e));
   if (const char* e = getenv("DSVOF_MG_OMEGA")) H.omega = atof(e);
+  if (const char* e = getenv("DSVOF_MG_TAIL")) H.tail = atoi(e);
   for (;;) {
     Lev<T>& L = H.lev[H.nlev++];
     lev_dims(L, nx, ny, nz, dt / (hl * hl));

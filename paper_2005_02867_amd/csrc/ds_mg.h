@@ -60,6 +60,7 @@ struct MgHier {
   int nu = 4;             // pre = post smoothing sweeps
   int nu_fine = 4;        // the same on the finest level
   int coarse_sweeps = 16; // sweeps on the coarsest level
+  int tail = 1;           // run the levels that fit in one workgroup's LDS as one launch
 };
 
 // CG work vectors of one precision.

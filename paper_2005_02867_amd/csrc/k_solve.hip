@@ -1132,6 +1132,150 @@ void mg_setup_levels(MgHier<T>& H, int dirmask, hipStream_t s) {
   }
 }
 
+// ------------------------------------------------------- V-cycle tail in LDS
+// The coarse end of the V-cycle -- every level from some level down, when
+// their r, x, t, q, diag all fit in one workgroup's LDS -- runs as one launch
+// of one 1024-thread workgroup: the same sweeps, restriction and injection as
+// the per-level kernels, each pass followed by a workgroup barrier.  It
+// replaces about nine launches of a few microseconds per V-cycle.
+constexpr int TAIL_BLOCK = 1024;
+constexpr size_t TAIL_LDS_MAX = 96 * 1024;
+
+template <class T>
+struct TailLevs {
+  int nlev;
+  int nx[MG_MAXLEV], ny[MG_MAXLEV], nz[MG_MAXLEV], nu[MG_MAXLEV];
+  int off[MG_MAXLEV];   // element offset of the level's r, x, t, q, diag block in LDS
+  T sc[MG_MAXLEV];
+  const T* q[MG_MAXLEV];
+  const T* d[MG_MAXLEV];
+};
+
+template <class T>
+inline size_t tail_bytes(const MgHier<T>& H, int l) {
+  size_t b = 0;
+  for (int m = l; m < H.nlev; ++m) b += 5 * (size_t)H.lev[m].n * sizeof(T);
+  return b;
+}
+
+// DOT: the last sweep on the first tail level publishes <r, x> (the tail
+// then starts at the hierarchy's finest level).  Arrays are addressed by
+// offsets into the LDS block (no pointer tables); bit l of `flip` says that
+// level l's iterate currently sits in its t array.
+template <class T, bool DOT>
+__global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T* __restrict__ r0,
+                                                        T* __restrict__ xout, T omega, int coarse_sweeps,
+                                                        SolveStatus* st, int first) {
+  if (st->done) return;
+  extern __shared__ double tail_smem[];
+  T* S = reinterpret_cast<T*>(tail_smem);
+  const int L = TL.nlev;
+  unsigned flip = 0;
+  auto N = [&](int l) { return TL.nx[l] * TL.ny[l] * TL.nz[l]; };
+  auto Ro = [&](int l) { return TL.off[l]; };
+  auto Xo = [&](int l) { return TL.off[l] + N(l) * (1 + (int)((flip >> l) & 1u)); };
+  auto Yo = [&](int l) { return TL.off[l] + N(l) * (2 - (int)((flip >> l) & 1u)); };
+  auto Qo = [&](int l) { return TL.off[l] + 3 * N(l); };
+  auto Do = [&](int l) { return TL.off[l] + 4 * N(l); };
+  for (int l = 0; l < L; ++l) {
+    const int n = N(l), qo = Qo(l), dg = Do(l);
+    for (int c = threadIdx.x; c < n; c += TAIL_BLOCK) {
+      S[qo + c] = TL.q[l][c];
+      S[dg + c] = TL.d[l][c];
+    }
+  }
+  for (int c = threadIdx.x; c < N(0); c += TAIL_BLOCK) S[Ro(0) + c] = r0[c];
+  __syncthreads();
+  double acc = 0.0;
+  // one damped-Jacobi sweep on level l (x -> t, then the roles swap); with
+  // dot, accumulate <r, x_new>.  zero: from x = 0, i.e. x = omega r/diag.
+  auto sweep = [&](int l, bool zero, bool dot) {
+    const int nx = TL.nx[l], ny = TL.ny[l], nz = TL.nz[l], n = nx * ny * nz, sx = ny * nz;
+    const int ro = Ro(l), xo = Xo(l), yo = Yo(l), qo = Qo(l), dg = Do(l);
+    const T sc = TL.sc[l];
+    for (int c = threadIdx.x; c < n; c += TAIL_BLOCK) {
+      T xn;
+      if (zero) {
+        xn = omega * S[ro + c] / S[dg + c];
+      } else {
+        const int k = c % nz, j = (c / nz) % ny, i = c / sx;
+        const T q = S[qo + c];
+        T off = 0;
+        if (i > 0) off += (q + S[qo + c - sx]) * S[xo + c - sx];
+        if (i < nx - 1) off += (q + S[qo + c + sx]) * S[xo + c + sx];
+        if (j > 0) off += (q + S[qo + c - nz]) * S[xo + c - nz];
+        if (j < ny - 1) off += (q + S[qo + c + nz]) * S[xo + c + nz];
+        if (k > 0) off += (q + S[qo + c - 1]) * S[xo + c - 1];
+        if (k < nz - 1) off += (q + S[qo + c + 1]) * S[xo + c + 1];
+        const T ax = S[dg + c] * S[xo + c] - T(0.5) * sc * off;
+        xn = S[xo + c] + omega * (S[ro + c] - ax) / S[dg + c];
+      }
+      S[yo + c] = xn;
+      if (DOT && dot) acc += (double)S[ro + c] * (double)xn;
+    }
+    __syncthreads();
+    flip ^= 1u << l;
+  };
+  // down: pre-smoothing (from zero) and restriction rc = (1/8) sum_children (r - A x)
+  for (int l = 0; l < L - 1; ++l) {
+    for (int t = 0; t < TL.nu[l]; ++t) sweep(l, t == 0, false);
+    const int nx = TL.nx[l], ny = TL.ny[l], nz = TL.nz[l], sx = ny * nz;
+    const int CY = TL.ny[l + 1], CZ = TL.nz[l + 1], nc = TL.nx[l + 1] * CY * CZ;
+    const int ro = Ro(l), xo = Xo(l), qo = Qo(l), dg = Do(l), rc = Ro(l + 1);
+    const T sc = TL.sc[l];
+    for (int cc = threadIdx.x; cc < nc; cc += TAIL_BLOCK) {
+      const int K = cc % CZ, J = (cc / CZ) % CY, I = cc / (CY * CZ);
+      T sres = 0;
+      for (int di = 0; di < 2; ++di)
+        for (int dj = 0; dj < 2; ++dj)
+          for (int dk = 0; dk < 2; ++dk) {
+            const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+            if (i < nx && j < ny && k < nz) {
+              const int f = (i * ny + j) * nz + k;
+              const T q = S[qo + f];
+              T off = 0;
+              if (i > 0) off += (q + S[qo + f - sx]) * S[xo + f - sx];
+              if (i < nx - 1) off += (q + S[qo + f + sx]) * S[xo + f + sx];
+              if (j > 0) off += (q + S[qo + f - nz]) * S[xo + f - nz];
+              if (j < ny - 1) off += (q + S[qo + f + nz]) * S[xo + f + nz];
+              if (k > 0) off += (q + S[qo + f - 1]) * S[xo + f - 1];
+              if (k < nz - 1) off += (q + S[qo + f + 1]) * S[xo + f + 1];
+              sres += S[ro + f] - (S[dg + f] * S[xo + f] - T(0.5) * sc * off);
+            }
+          }
+      S[rc + cc] = T(0.125) * sres;
+    }
+    __syncthreads();
+  }
+  // coarsest level
+  for (int t = 0; t < coarse_sweeps; ++t) sweep(L - 1, t == 0, L == 1 && t == coarse_sweeps - 1);
+  // up: injection of the coarse correction, then post-smoothing
+  for (int l = L - 2; l >= 0; --l) {
+    const int nx = TL.nx[l], ny = TL.ny[l], nz = TL.nz[l], n = nx * ny * nz;
+    const int CY = TL.ny[l + 1], CZ = TL.nz[l + 1], xo = Xo(l), xc = Xo(l + 1);
+    for (int c = threadIdx.x; c < n; c += TAIL_BLOCK) {
+      const int k = c % nz, j = (c / nz) % ny, i = c / (ny * nz);
+      S[xo + c] += S[xc + ((i >> 1) * CY + (j >> 1)) * CZ + (k >> 1)];
+    }
+    __syncthreads();
+    for (int t = 0; t < TL.nu[l]; ++t) sweep(l, false, l == 0 && t == TL.nu[l] - 1);
+  }
+  const int x0 = Xo(0);
+  for (int c = threadIdx.x; c < N(0); c += TAIL_BLOCK) xout[c] = S[x0 + c];
+  if (DOT) {
+    __shared__ double red[TAIL_BLOCK / 64];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < TAIL_BLOCK / 64; ++w) t += red[w];
+      if (!first) st->beta = t / st->rz;
+      st->rz = t;
+    }
+  }
+}
+
 // Approximately solve A_l x = r from x = 0; the buffer holding x is returned in *out.
 template <class T>
 static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* partials, unsigned* counter,
@@ -1147,6 +1291,34 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   const bool coarsest = (l == H.nlev - 1);
   const int nu = l == 0 ? H.nu_fine : H.nu;
   const int pre = coarsest ? std::max(2, H.coarse_sweeps) : nu;
+  const size_t tb = tail_bytes(H, l);
+  if (H.tail && tb <= TAIL_LDS_MAX) {
+    TailLevs<T> TL{};
+    TL.nlev = H.nlev - l;
+    int o = 0;
+    for (int m = 0; m < TL.nlev; ++m) {
+      const Lev<T>& Lm = H.lev[l + m];
+      TL.off[m] = o;
+      o += 5 * (int)Lm.n;
+      TL.nx[m] = Lm.nx;
+      TL.ny[m] = Lm.ny;
+      TL.nz[m] = Lm.nz;
+      TL.nu[m] = l + m == 0 ? H.nu_fine : H.nu;
+      TL.sc[m] = Lm.sc;
+      TL.q[m] = Lm.qc;
+      TL.d[m] = Lm.diag;
+    }
+    static bool attr_set[2] = {false, false};
+    auto kt = dot ? k_mg_tail<T, true> : k_mg_tail<T, false>;
+    if (!attr_set[dot ? 1 : 0]) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kt), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)TAIL_LDS_MAX);
+      attr_set[dot ? 1 : 0] = true;
+    }
+    kt<<<1, TAIL_BLOCK, tb, s>>>(TL, r, a, om, std::max(2, H.coarse_sweeps), st, dot_first ? 1 : 0);
+    *out = a;
+    return;
+  }
   auto smooth = [&](bool d, int df) {
     if (vec) {
       if (d) k_mg_smooth_v<T, true><<<nbm, BLOCK, 0, s>>>(M, r, a, b, om, st, partials, counter, df);
