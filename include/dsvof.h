@@ -178,7 +178,9 @@ int ds_get_internal(ds_grid* g, int which, double* dst, size_t count, void* stre
  * matrix-free product q = A p and <p, q>) that performs an iteration;
  * ds_get_kernel_timing returns the mean duration in microseconds, the number
  * of timed launches and the kernel's algorithmic bytes per launch (each
- * array it streams counted once: z, p, q_coef, diag read; p, q written).
+ * array it streams counted once: z, p, q_coef read, and diag unless the
+ * kernel forms it from q_coef, as it does for the multigrid-preconditioned
+ * pressure-type systems; p, q written).
  * Enabling resets the accumulators.  The event pool is created on first use
  * (host-side HIP objects, no device memory). */
 int ds_set_kernel_timing(ds_grid* g, int enable);
@@ -247,8 +249,8 @@ int ds_get_adjoint_iterations(const ds_grid* g, int* iters4);
  * mean duration (us) and algorithmic bytes per launch.
  *   DS_KERNEL_CG_OPERATOR: the conjugate-gradient operator kernel (above);
  *   DS_KERNEL_MG_SMOOTH: one damped-Jacobi sweep of the multigrid
- *     preconditioner on the fine level (reads r, x, q_coef, diag; writes x:
- *     5 arrays).  Needs pressure_precond = 1.
+ *     preconditioner on the fine level (reads r, x, q_coef and forms diag
+ *     from q_coef; writes x: 4 arrays).  Needs pressure_precond = 1.
  * Only solver scratch vectors are written.  DS_ERR_ARG for an unknown kernel. */
 enum { DS_KERNEL_CG_OPERATOR = 0, DS_KERNEL_MG_SMOOTH = 1 };
 int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* bytes_per_launch, void* stream);

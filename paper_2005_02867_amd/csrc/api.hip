@@ -350,6 +350,16 @@ int& batch_of(ds_grid* g, int sys, const double* x) {
 }
 int batch_size(int expected, bool first) { return first ? std::max(2, expected) : std::max(2, expected / 4); }
 
+// Pressure-type systems (pressure, liquid-transport potential): the marching
+// kernels form the diagonal from q and the p = 0 faces instead of loading it.
+// For the pressure the result equals the setup's stored diagonal bit for bit
+// (same terms, same order); for the potential it differs by at most an ulp.
+void pressure_type(const ds_grid* g, int sys, Lev<double>& L) {
+  if (sys != 2) return;
+  L.dfly = 1;
+  L.dmask = g->dirmask;
+}
+
 // FP64 preconditioned CG on the system in qc/diag (scale sc), right-hand side
 // b, warm start in x.  sys: 0 = energy, 1 = species (Jacobi), 2 = pressure
 // (multigrid when enabled, Jacobi otherwise).
@@ -359,6 +369,7 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
   L.sc = sc;
   L.qc = g->qc;
   L.diag = g->diag;
+  pressure_type(g, sys, L);
   MgHier<double>* H = nullptr;
   if (sys == 2 && g->prm.pressure_precond == 1) {
     H = &g->H64;
@@ -388,7 +399,7 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
       }
       HIPCHK(g, hipGetLastError());
       if ((st = sync_status(g, sys, s)) != DS_OK) return st;
-      if (timed) accumulate_timing(g, g->h_status[sys].it - it0, 48.0 * (double)g->n);
+      if (timed) accumulate_timing(g, g->h_status[sys].it - it0, (L.dfly ? 40.0 : 48.0) * (double)g->n);
     }
   }
   const SolveStatus& h = g->h_status[sys];
@@ -408,14 +419,17 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   L.sc = sc;
   L.qc = g->qc;
   L.diag = g->diag;
+  pressure_type(g, sys, L);
   Lev<float> F;
   lev_dims(F, L.nx, L.ny, L.nz, sc);
   F.qc = g->qc32;
   F.diag = g->diag32;
   launch_to_float(g->qc, g->qc32, g->n, s);
-  launch_to_float(g->diag, g->diag32, g->n, s);
+  const bool mg = sys == 2 && g->prm.pressure_precond == 1;
+  if (mg) launch_mg_diag(F, g->dirmask, g->diag32, s);   // the formula the V-cycle forms on the fly
+  else launch_to_float(g->diag, g->diag32, g->n, s);
   MgHier<float>* H = nullptr;
-  if (sys == 2 && g->prm.pressure_precond == 1) {
+  if (mg) {
     H = &g->H32;
     H->lev[0] = F;
     mg_setup_levels(*H, g->dirmask, s);
@@ -483,12 +497,13 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   L.sc = sc;
   L.qc = g->qc;
   L.diag = g->diag;
+  pressure_type(g, sys, L);
   Lev<float> F;
   lev_dims(F, L.nx, L.ny, L.nz, sc);
   F.qc = g->qc32;
   F.diag = g->diag32;
   launch_to_float(g->qc, g->qc32, g->n, s);
-  launch_to_float(g->diag, g->diag32, g->n, s);
+  launch_mg_diag(F, g->dirmask, g->diag32, s);   // the formula the V-cycle forms on the fly
   MgHier<float>& H = g->H32;
   H.lev[0] = F;
   mg_setup_levels(H, g->dirmask, s);
@@ -1081,20 +1096,27 @@ int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* byte
     lev_dims(F, P.nx, P.ny, P.nz, P.dt / (P.h * P.h));
     F.qc = g->qc32;
     F.diag = g->diag32;
+    if (g->prm.pressure_precond == 1) {   // the fine level of the pressure V-cycle
+      F.dfly = 1;
+      F.dmask = g->dirmask;
+    }
     const bool z32 = g->prm.pressure_precond == 1 && g->tune.mg32 && mg32_supported(g->L0);
     if (smooth) {
       us = replay_smooth_kernel<float>(F, g->r32, g->H32.x[0], g->H32.t[0], st, reps, g->H32.omega, s, g->ev[0],
                                        g->ev[1]);
-      if (bytes_per_launch) *bytes_per_launch = 20.0 * (double)g->n;
+      // r, x, q read and x written (diag too unless formed from q)
+      if (bytes_per_launch) *bytes_per_launch = (F.dfly ? 16.0 : 20.0) * (double)g->n;
     } else if (z32) {
       // the pressure solve's operator: FP64 with the FP32 preconditioned residual z
       Lev<double> L = g->L0;
       L.sc = P.dt / (P.h * P.h);
       L.qc = g->qc;
       L.diag = g->diag;
+      pressure_type(g, 2, L);
       us = replay_operator_z32(L, g->r32, g->pd, g->p_alt, g->q, st, g->partials, g->counters + CT_MISC, reps, s,
                                g->ev[0], g->ev[1]);
-      if (bytes_per_launch) *bytes_per_launch = 44.0 * (double)g->n;
+      // z (FP32), p, q read; p, q written (diag formed from q)
+      if (bytes_per_launch) *bytes_per_launch = 36.0 * (double)g->n;
     } else {
       us = replay_operator_kernel<float>(F, g->r32, g->p32, g->p32alt, g->q32, st, g->partials,
                                          g->counters + CT_MISC, reps, s, g->ev[0], g->ev[1]);
@@ -1105,13 +1127,14 @@ int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* byte
     L.sc = P.dt / (P.h * P.h);
     L.qc = g->qc;
     L.diag = g->diag;
+    if (g->prm.pressure_precond == 1) pressure_type(g, 2, L);
     if (smooth)
       us = replay_smooth_kernel<double>(L, g->r, g->H64.x[0], g->H64.t[0], st, reps, g->H64.omega, s, g->ev[0],
                                         g->ev[1]);
     else
       us = replay_operator_kernel<double>(L, g->r, g->pd, g->p_alt, g->q, st, g->partials, g->counters + CT_MISC,
                                           reps, s, g->ev[0], g->ev[1]);
-    if (bytes_per_launch) *bytes_per_launch = (smooth ? 40.0 : 48.0) * (double)g->n;
+    if (bytes_per_launch) *bytes_per_launch = (smooth ? 40.0 : 48.0) * (double)g->n - (L.dfly ? 8.0 * (double)g->n : 0.0);
   }
   if (us < 0) return fail(g, DS_ERR_HIP, "event timing failed");
   *avg_us = us;

@@ -27,6 +27,8 @@ struct Lev {
   int nx, ny, nz;
   int ytile;
   int mch;     // chunks of x-planes per column in the marching kernels (set by the launcher)
+  int dfly;    // 1: the marching kernels form diag from qc (pressure-type operator) instead of loading it
+  int dmask;   // with dfly: bit (axis*2 + side) set where the box face is p = 0 (Dirichlet)
   int ntk, ntj;
   unsigned ntiles;
   long long n;
@@ -42,6 +44,8 @@ inline void lev_dims(Lev<T>& L, int nx, int ny, int nz, double sc) {
   L.nz = nz;
   L.ytile = (g_vec_ytile > 0 && ny % g_vec_ytile == 0) ? g_vec_ytile : ny;
   L.mch = 1;
+  L.dfly = 0;
+  L.dmask = 0;
   L.ntk = (nz + TK - 1) / TK;
   L.ntj = (ny + TJ - 1) / TJ;
   L.ntiles = (unsigned)L.ntk * (unsigned)L.ntj * (unsigned)nx;
@@ -74,9 +78,15 @@ struct CgVecs {
   T* zj = nullptr;   // Jacobi: z = r/diag stored by the update (vectorised levels)
 };
 
-// dirmask bit (axis*2 + side) set: p_rgh = 0 on that box face.
+// dirmask bit (axis*2 + side) set: p_rgh = 0 on that box face.  Every level
+// (the finest included) is marked to form its diagonal from q on the fly;
+// the coarse levels' stored diagonals are computed here.
 template <class T>
 void mg_setup_levels(MgHier<T>& H, int dirmask, hipStream_t s);
+// diag of a pressure-type level from its q and the Dirichlet faces (the
+// formula the marching kernels apply on the fly), into dout.
+template <class T>
+void launch_mg_diag(const Lev<T>& L, int dirmask, T* dout, hipStream_t s);
 
 // Enqueue the start of a solve whose residual is already in V.r (and whose
 // status holds bnorm): z = M^-1 r, rz = <r, z>.  Then iterations.  With

@@ -598,8 +598,11 @@ template <class T>
 __device__ __forceinline__ T lane_down(T v) { return __shfl_down(v, 1, 64); } // value of lane + 1
 
 // lx(f, out): operand vector at cell f; sx(f): operand at the single cell f;
-// body(c, qc, xc, off): the cells' own q and X and off = sum_nb (q + q_nb) X_nb
-// (order x-, x+, y-, y+, z-, z+, as in the scalar kernels).  Work items are
+// body(c, qc, xc, off, dg): the cells' own q and X, off = sum_nb (q + q_nb) X_nb
+// (order x-, x+, y-, y+, z-, z+, as in the scalar kernels) and the diagonal.
+// With L.dfly the diagonal is formed from the q values already in hand --
+// sc (q + q_nb)/2 per neighbour, 2 sc q per Dirichlet box face, summed in FP64
+// in face order as the setup kernels and k_mg_diag do -- instead of loaded.  Work items are
 // (chunk, j, kv), kv fastest; a grid-stride loop covers them (the stride is a
 // multiple of 64, so a wave's lanes always hold consecutive items).  Threads
 // past the end do nothing and return normally (block reductions follow).
@@ -672,7 +675,29 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
       const T tt = off[V - 1] + (qc[V - 1] + qzp) * xzp;
       off[V - 1] = hzp ? tt : off[V - 1];
     }
-    body(c, qc, xc, off);
+    T dg[V];
+    if (L.dfly) {
+      const double sc = (double)L.sc;
+      const int dm = L.dmask;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double q = (double)qc[v], bnd = 2.0 * sc * q;
+        double d = 0.0;
+        d += hxm ? sc * 0.5 * (q + (double)qp[v]) : ((dm & 1) ? bnd : 0.0);
+        d += hxp ? sc * 0.5 * (q + (double)qn[v]) : ((dm & 2) ? bnd : 0.0);
+        d += hym ? sc * 0.5 * (q + (double)qym[v]) : ((dm & 4) ? bnd : 0.0);
+        d += hyp ? sc * 0.5 * (q + (double)qyp[v]) : ((dm & 8) ? bnd : 0.0);
+        const bool em = v > 0 || hzm, ep = v < V - 1 || hzp;
+        const double gm = v > 0 ? (double)qc[v > 0 ? v - 1 : 0] : (double)qzm;
+        const double gp = v < V - 1 ? (double)qc[v < V - 1 ? v + 1 : V - 1] : (double)qzp;
+        d += em ? sc * 0.5 * (q + gm) : ((dm & 16) ? bnd : 0.0);
+        d += ep ? sc * 0.5 * (q + gp) : ((dm & 32) ? bnd : 0.0);
+        dg[v] = (T)d;
+      }
+    } else {
+      ldv<T>(at(L.diag, c), dg);
+    }
+    body(c, qc, xc, off, dg);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       qp[v] = qc[v];
@@ -727,10 +752,9 @@ VEC_KERNEL k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ 
     for (int v = 0; v < V; ++v) o[v] = omega * rv[v] / dv[v];
   };
   auto x1s = [&](unsigned f) -> T { return omega * *at(r, f) / *at(L.diag, f); };
-  march<T>(L, x1v, x1s, [&](unsigned c, const T(&qv)[V], const T(&x1)[V], const T(&off)[V]) {
-    T rv[V], dv[V], o[V];
+  march<T>(L, x1v, x1s, [&](unsigned c, const T(&qv)[V], const T(&x1)[V], const T(&off)[V], const T(&dv)[V]) {
+    T rv[V], o[V];
     ldv<T>(at(r, c), rv);
-    ldv<T>(at(L.diag, c), dv);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const T ax = dv[v] * x1[v] - T(0.5) * L.sc * off[v];
@@ -748,10 +772,9 @@ VEC_KERNEL k_mg_smooth_v(Lev<T> L, const T* __restrict__ r, const T* __restrict_
   double acc = 0.0;
   march<T>(
       L, [&](unsigned f, T(&o)[V]) { ldv<T>(at(xin, f), o); }, [&](unsigned f) { return *at(xin, f); },
-      [&](unsigned c, const T(&qv)[V], const T(&xv)[V], const T(&off)[V]) {
-        T rv[V], dv[V], o[V];
+      [&](unsigned c, const T(&qv)[V], const T(&xv)[V], const T(&off)[V], const T(&dv)[V]) {
+        T rv[V], o[V];
         ldv<T>(at(r, c), rv);
-        ldv<T>(at(L.diag, c), dv);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const T ax = dv[v] * xv[v] - T(0.5) * L.sc * off[v];
@@ -820,10 +843,9 @@ VEC_KERNEL k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, co
     const unsigned jj = rr % (unsigned)F.ny, ii = rr / (unsigned)F.ny;
     return *at(x, f) + *at(xc, ((ii >> 1) * (unsigned)C.ny + (jj >> 1)) * (unsigned)C.nz + (kk >> 1));
   };
-  march<T>(F, row, one, [&](unsigned c, const T(&qv)[V], const T(&x0)[V], const T(&off)[V]) {
-    T rv[V], dv[V], o[V];
+  march<T>(F, row, one, [&](unsigned c, const T(&qv)[V], const T(&x0)[V], const T(&off)[V], const T(&dv)[V]) {
+    T rv[V], o[V];
     ldv<T>(at(r, c), rv);
-    ldv<T>(at(F.diag, c), dv);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const T Ax = dv[v] * x0[v] - T(0.5) * F.sc * off[v];
@@ -842,10 +864,9 @@ VEC_KERNEL k_resid64_v(Lev<double> L, const double* __restrict__ b, const double
   double acc[2] = {0.0, 0.0};
   march<double>(
       L, [&](unsigned f, double(&o)[V]) { ldv<double>(at(x, f), o); }, [&](unsigned f) { return *at(x, f); },
-      [&](unsigned c, const double(&qv)[V], const double(&xv)[V], const double(&off)[V]) {
-        double bv[V], dg[V], o[V];
+      [&](unsigned c, const double(&qv)[V], const double(&xv)[V], const double(&off)[V], const double(&dg)[V]) {
+        double bv[V], o[V];
         ldv<double>(at(b, c), bv);
-        ldv<double>(at(L.diag, c), dg);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const double ax = dg[v] * xv[v] - 0.5 * L.sc * off[v];
@@ -956,9 +977,8 @@ VEC_KERNEL k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restric
     const T zf = JAC ? *at(r, f) / *at(L.diag, f) : *at(z, f);
     return FIRST ? zf : zf + be * *at(pin, f);
   };
-  march<T>(L, pnv, pns, [&](unsigned c, const T(&qv)[V], const T(&pc)[V], const T(&off)[V]) {
-    T dv[V], y[V];
-    ldv<T>(at(L.diag, c), dv);
+  march<T>(L, pnv, pns, [&](unsigned c, const T(&qv)[V], const T(&pc)[V], const T(&off)[V], const T(&dv)[V]) {
+    T y[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       y[v] = dv[v] * pc[v] - T(0.5) * L.sc * off[v];
@@ -1092,9 +1112,10 @@ VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const
     }
   };
   auto pns = [&](unsigned f) -> double { return FIRST ? (double)*at(z, f) : (double)*at(z, f) + be * *at(pin, f); };
-  march<double>(L, pnv, pns, [&](unsigned c, const double(&qv)[V], const double(&pc)[V], const double(&off)[V]) {
-    double dv[V], y[V];
-    ldv<double>(at(L.diag, c), dv);
+  march<double>(L, pnv, pns,
+                [&](unsigned c, const double(&qv)[V], const double(&pc)[V], const double(&off)[V],
+                    const double(&dv)[V]) {
+    double y[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       y[v] = dv[v] * pc[v] - 0.5 * L.sc * off[v];
@@ -1125,6 +1146,10 @@ VEC_KERNEL k_add_correction_v(Lev<T> L, double* __restrict__ x, const T* __restr
 // ------------------------------------------------------------ host side
 template <class T>
 void mg_setup_levels(MgHier<T>& H, int dirmask, hipStream_t s) {
+  for (int l = 0; l < H.nlev; ++l) {
+    H.lev[l].dfly = 1;
+    H.lev[l].dmask = dirmask;
+  }
   for (int l = 1; l < H.nlev; ++l) {
     Lev<T>& C = H.lev[l];
     k_mg_coarsen_q<T><<<tile_blocks(C.ntiles), BLOCK, 0, s>>>(H.lev[l - 1], C, const_cast<T*>(C.qc));
@@ -1538,6 +1563,11 @@ double replay_operator_z32(const Lev<double>& L, const float* z, const double* p
   return 1e3 * (double)ms / reps;
 }
 
+template <class T>
+void launch_mg_diag(const Lev<T>& L, int dirmask, T* dout, hipStream_t s) {
+  k_mg_diag<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, dirmask, dout);
+}
+template void launch_mg_diag<float>(const Lev<float>&, int, float*, hipStream_t);
 template void mg_setup_levels<double>(MgHier<double>&, int, hipStream_t);
 template void mg_setup_levels<float>(MgHier<float>&, int, hipStream_t);
 template void cg_start<double>(const Lev<double>&, MgHier<double>*, CgVecs<double>&, double**, SolveStatus*,
