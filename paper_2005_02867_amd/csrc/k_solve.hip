@@ -1212,6 +1212,15 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
   for (int c = threadIdx.x; c < N(0); c += TAIL_BLOCK) S[Ro(0) + c] = r0[c];
   __syncthreads();
   double acc = 0.0;
+  // c -> (i, j, k) on an a x b x m level without integer division: with the
+  // offset of one half, (c + 1/2)/m lies at least 1/(2m) from an integer, far
+  // beyond the FP64 rounding of the product (c < 2^24 here).
+  auto dec = [](int c, int b, int m, int& i, int& j, int& k) {
+    const int t = (int)(((double)c + 0.5) * (1.0 / (double)m));
+    k = c - t * m;
+    i = (int)(((double)t + 0.5) * (1.0 / (double)b));
+    j = t - i * b;
+  };
   // one damped-Jacobi sweep on level l (x -> t, then the roles swap); with
   // dot, accumulate <r, x_new>.  zero: from x = 0, i.e. x = omega r/diag.
   auto sweep = [&](int l, bool zero, bool dot) {
@@ -1223,7 +1232,8 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
       if (zero) {
         xn = omega * S[ro + c] / S[dg + c];
       } else {
-        const int k = c % nz, j = (c / nz) % ny, i = c / sx;
+        int i, j, k;
+        dec(c, ny, nz, i, j, k);
         const T q = S[qo + c];
         T off = 0;
         if (i > 0) off += (q + S[qo + c - sx]) * S[xo + c - sx];
@@ -1249,7 +1259,8 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
     const int ro = Ro(l), xo = Xo(l), qo = Qo(l), dg = Do(l), rc = Ro(l + 1);
     const T sc = TL.sc[l];
     for (int cc = threadIdx.x; cc < nc; cc += TAIL_BLOCK) {
-      const int K = cc % CZ, J = (cc / CZ) % CY, I = cc / (CY * CZ);
+      int I, J, K;
+      dec(cc, CY, CZ, I, J, K);
       T sres = 0;
       for (int di = 0; di < 2; ++di)
         for (int dj = 0; dj < 2; ++dj)
@@ -1279,7 +1290,8 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
     const int nx = TL.nx[l], ny = TL.ny[l], nz = TL.nz[l], n = nx * ny * nz;
     const int CY = TL.ny[l + 1], CZ = TL.nz[l + 1], xo = Xo(l), xc = Xo(l + 1);
     for (int c = threadIdx.x; c < n; c += TAIL_BLOCK) {
-      const int k = c % nz, j = (c / nz) % ny, i = c / (ny * nz);
+      int i, j, k;
+      dec(c, ny, nz, i, j, k);
       S[xo + c] += S[xc + ((i >> 1) * CY + (j >> 1)) * CZ + (k >> 1)];
     }
     __syncthreads();
