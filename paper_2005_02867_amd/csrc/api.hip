@@ -515,6 +515,9 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   if ((st = sync_status(g, sys, s)) != DS_OK) return st;
   if (!g->h_status[sys].done) {
     CgVecs<double> V{x, g->r, g->pd, g->p_alt, g->q};
+    // iteration t writes its direction into p_odd (t odd) or p_even (t even)
+    double* const p_odd = V.p_alt;
+    double* const p_even = V.p;
     float* z = nullptr;
     cg_start_mg32(L, H, g->r, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, s);
     bool first = true;
@@ -527,6 +530,9 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
       HIPCHK(g, hipGetLastError());
       if ((st = sync_status(g, sys, s)) != DS_OK) return st;
     }
+    const int it = g->h_status[sys].it;
+    if (it > 0) launch_axpy_alpha(x, (it & 1) ? p_odd : p_even, ss, g->n, s);
+    HIPCHK(g, hipGetLastError());
   }
   const SolveStatus& h = g->h_status[sys];
   batch_of(g, sys, x) = std::max(2, std::min(256, h.it));

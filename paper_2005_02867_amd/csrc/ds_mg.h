@@ -121,8 +121,12 @@ double replay_operator_z32(const Lev<double>& L, const float* z, const double* p
                            hipEvent_t e1);
 void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, float* r32, float** z, SolveStatus* st,
                    double* partials, unsigned* counters, hipStream_t s);
+// The iteration's solution update is deferred: iteration t applies
+// x += alpha_{t-1} p_{t-1}; after the last iteration t = it, launch_axpy_alpha
+// with the direction buffer of that iteration applies alpha_it p_it.
 void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V, float* r32, float** z,
                        SolveStatus* st, double* partials, unsigned* counters, bool first, hipStream_t s);
+void launch_axpy_alpha(double* x, const double* p, const SolveStatus* st, long long n, hipStream_t s);
 
 // r = b - A x (FP64), ||b|| (if set_bnorm), ||r|| -> status (done if ||r|| <= tol ||b||).
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,

@@ -1051,30 +1051,28 @@ VEC_KERNEL k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, const T
 }
 
 // FP64 CG with the FP32 multigrid preconditioner: the update also stores
-// r in FP32 for the V-cycle; the direction update reads z in FP32.
-VEC_KERNEL k_cg_update_r32_v(Lev<double> L, double* __restrict__ x, double* __restrict__ r,
-                                  const double* __restrict__ p, const double* __restrict__ q, float* __restrict__ r32,
-                                  SolveStatus* st, double* partials, unsigned* counter) {
+// r in FP32 for the V-cycle; the direction update reads z in FP32.  The
+// solution update x += alpha p is deferred to the next direction update,
+// which reads p anyway (and, after the last iteration, to k_axpy_alpha), so
+// this kernel streams r and q only.
+VEC_KERNEL k_cg_update_r32_v(Lev<double> L, double* __restrict__ r, const double* __restrict__ q,
+                             float* __restrict__ r32, SolveStatus* st, double* partials, unsigned* counter) {
   if (st->done) return;
   constexpr int V = VW<double>::n;
   const double a = st->alpha;
   double acc[1] = {0.0};
   FOR_ITEMS(L, double, i, j, kv, c) {
-    double xv[V], rv[V], pv[V], qv[V];
-    ldv<double>(at(x, c), xv);
+    double rv[V], qv[V];
     ldv<double>(at(r, c), rv);
-    ldv<double>(at(p, c), pv);
     ldv<double>(at(q, c), qv);
     float2 rf;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      xv[v] += a * pv[v];
       rv[v] = rv[v] - a * qv[v];
       acc[0] += rv[v] * rv[v];
     }
     rf.x = (float)rv[0];
     rf.y = (float)rv[1];
-    stv<double>(at(x, c), xv);
     stv<double>(at(r, c), rv);
     *reinterpret_cast<float2*>(at(r32, c)) = rf;
   }
@@ -1092,13 +1090,17 @@ VEC_KERNEL k_cg_update_r32_v(Lev<double> L, double* __restrict__ x, double* __re
   }
 }
 
+// x (may be null): also x += alpha_prev p_old, the previous iteration's
+// solution update (alpha_prev is still in st->alpha when this kernel starts;
+// its last block replaces it).
 template <bool FIRST>
 VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const double* __restrict__ pin,
-                                    double* __restrict__ pout, double* __restrict__ q, SolveStatus* st,
-                                    double* partials, unsigned* counter) {
+                               double* __restrict__ pout, double* __restrict__ q, SolveStatus* st,
+                               double* partials, unsigned* counter, double* __restrict__ x) {
   if (st->done) return;
   constexpr int V = VW<double>::n;
   const double be = FIRST ? 0.0 : st->beta;
+  const double ap = FIRST ? 0.0 : st->alpha;
   double acc[1] = {0.0};
   auto pnv = [&](unsigned f, double(&o)[V]) {
     const float2 zf = *reinterpret_cast<const float2*>(at(z, f));
@@ -1123,6 +1125,14 @@ VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const
     }
     stv<double>(at(pout, c), pc);
     stv<double>(at(q, c), y);
+    if (!FIRST && x) {
+      double xv[V], pv[V];
+      ldv<double>(at(x, c), xv);
+      ldv<double>(at(pin, c), pv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) xv[v] += ap * pv[v];
+      stv<double>(at(x, c), xv);
+    }
   });
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
@@ -1130,6 +1140,19 @@ VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const
     block_combine<1>(ops, partials, counter, t);
     if (threadIdx.x == 0) st->alpha = st->rz / t[0];
   }
+}
+
+// x += st->alpha p: the last iteration's deferred solution update (runs
+// after the solve has been flagged done).
+__global__ void k_axpy_alpha(double* __restrict__ x, const double* __restrict__ p, const SolveStatus* st,
+                             long long n) {
+  const double a = st->alpha;
+  long long b0, b1;
+  block_range(n, b0, b1);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) x[e] += a * p[e];
+}
+void launch_axpy_alpha(double* x, const double* p, const SolveStatus* st, long long n, hipStream_t s) {
+  k_axpy_alpha<<<grid_blocks(n), BLOCK, 0, s>>>(x, p, st, n);
 }
 
 template <class T>
@@ -1554,10 +1577,10 @@ void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V
   const int nb = vec_blocks(vec_items(L));
   const Lev<double> M = march_lev(L);
   const int nbm = march_blocks(M);
-  if (first) k_cg_dir_spmv_z32_v<true><<<nbm, BLOCK, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters);
-  else k_cg_dir_spmv_z32_v<false><<<nbm, BLOCK, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters);
+  if (first) k_cg_dir_spmv_z32_v<true><<<nbm, BLOCK, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
+  else k_cg_dir_spmv_z32_v<false><<<nbm, BLOCK, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
   std::swap(V.p, V.p_alt);
-  k_cg_update_r32_v<<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, r32, st, partials, counters + 1);
+  k_cg_update_r32_v<<<nb, BLOCK, 0, s>>>(L, V.r, V.q, r32, st, partials, counters + 1);
   mg_vcycle(H, 0, r32, st, partials, counters + 2, false, true, s, z);
 }
 bool mg32_supported(const Lev<double>& L) { return use_vec(L); }
@@ -1566,9 +1589,9 @@ double replay_operator_z32(const Lev<double>& L, const float* z, const double* p
                            hipEvent_t e1) {
   const Lev<double> M = march_lev(L);
   const int nb = march_blocks(M);
-  k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(M, z, pin, pout, q, st, partials, counter);
+  k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(M, z, pin, pout, q, st, partials, counter, nullptr);
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-  for (int t = 0; t < reps; ++t) k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(M, z, pin, pout, q, st, partials, counter);
+  for (int t = 0; t < reps; ++t) k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(M, z, pin, pout, q, st, partials, counter, nullptr);
   if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
