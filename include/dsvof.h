@@ -180,7 +180,9 @@ int ds_get_internal(ds_grid* g, int which, double* dst, size_t count, void* stre
  * of timed launches and the kernel's algorithmic bytes per launch (each
  * array it streams counted once: z, p, q_coef read, and diag unless the
  * kernel forms it from q_coef, as it does for the multigrid-preconditioned
- * pressure-type systems; p, q written).
+ * pressure-type systems; p, q written; on levels with nz a multiple of the
+ * vector width also x read and written, the previous iteration's deferred
+ * solution update).
  * Enabling resets the accumulators.  The event pool is created on first use
  * (host-side HIP objects, no device memory). */
 int ds_set_kernel_timing(ds_grid* g, int enable);

@@ -384,6 +384,8 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
   if ((st = sync_status(g, sys, s)) != DS_OK) return st;
   if (!g->h_status[sys].done) {
     CgVecs<double> V{x, g->r, g->pd, g->p_alt, g->q, H ? nullptr : g->zj};
+    double* const p_odd = V.p_alt;   // direction of odd iterations (for the deferred x update)
+    double* const p_even = V.p;
     double* z = nullptr;
     cg_start(L, H, V, &z, ss, g->partials, g->counters + CT_SOLVE0, s);
     bool first = true;
@@ -399,8 +401,11 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
       }
       HIPCHK(g, hipGetLastError());
       if ((st = sync_status(g, sys, s)) != DS_OK) return st;
-      if (timed) accumulate_timing(g, g->h_status[sys].it - it0, (L.dfly ? 40.0 : 48.0) * (double)g->n);
+      if (timed) accumulate_timing(g, g->h_status[sys].it - it0,
+                                   ((L.dfly ? 40.0 : 48.0) + (cg_defers_x(L) ? 16.0 : 0.0)) * (double)g->n);
     }
+    const int it = g->h_status[sys].it;
+    if (it > 0 && cg_defers_x(L)) launch_axpy_alpha(x, (it & 1) ? p_odd : p_even, ss, g->n, s);
   }
   const SolveStatus& h = g->h_status[sys];
   batch_of(g, sys, x) = std::max(2, std::min(256, h.it));
@@ -454,6 +459,8 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     g->h_status[3].it = 0;
     g->h_status[3].done = 0;
     CgVecs<float> V{g->e32, g->r32, g->p32, g->p32alt, g->q32, H ? nullptr : g->zj32};
+    float* const p_odd = V.p_alt;   // direction of odd iterations (for the deferred x update)
+    float* const p_even = V.p;
     float* z = nullptr;
     cg_start(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, s);
     bool first = true;
@@ -471,6 +478,8 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
       if ((st = sync_status(g, 3, s)) != DS_OK) return st;
       if (timed) accumulate_timing(g, g->h_status[3].it - it0, 24.0 * (double)g->n);
     } while (!g->h_status[3].done);
+    const int it = g->h_status[3].it;
+    if (it > 0 && cg_defers_x(F)) launch_axpy_alpha(g->e32, (it & 1) ? p_odd : p_even, si, g->n, s);
     total += g->h_status[3].it;
     inner_fail = g->h_status[3].done == 2;
     launch_add_correction<float>(F, x, g->e32, s);

@@ -126,7 +126,12 @@ void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, fl
 // with the direction buffer of that iteration applies alpha_it p_it.
 void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V, float* r32, float** z,
                        SolveStatus* st, double* partials, unsigned* counters, bool first, hipStream_t s);
-void launch_axpy_alpha(double* x, const double* p, const SolveStatus* st, long long n, hipStream_t s);
+template <class T>
+void launch_axpy_alpha(T* x, const T* p, const SolveStatus* st, long long n, hipStream_t s);
+// Does cg_iteration defer x += alpha p on this level (vectorised kernels)?
+// Then the caller applies the last iteration's update with launch_axpy_alpha.
+template <class T>
+bool cg_defers_x(const Lev<T>& L);
 
 // r = b - A x (FP64), ||b|| (if set_bnorm), ||r|| -> status (done if ||r|| <= tol ||b||).
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,

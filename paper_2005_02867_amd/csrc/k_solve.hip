@@ -946,15 +946,17 @@ VEC_KERNEL k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double
   publish_rz(acc, st, partials, counter, first);
 }
 
-// FIRST: p = z (the first iteration); the int argument is unused (the
-// signature matches the scalar kernel's).
+// FIRST: p = z (the first iteration).  x (may be null): also x += alpha_prev
+// p_old, the previous iteration's deferred solution update (alpha_prev is
+// still in st->alpha when this kernel starts; its last block replaces it).
 template <class T, bool JAC, bool FIRST>
 VEC_KERNEL k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restrict__ r,
-                                const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ q, SolveStatus* st,
-                                double* partials, unsigned* counter, int) {
+                           const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ q, SolveStatus* st,
+                           double* partials, unsigned* counter, T* __restrict__ x) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
   const T be = FIRST ? T(0) : (T)st->beta;
+  const T ap = FIRST ? T(0) : (T)st->alpha;
   double acc[1] = {0.0};
   auto pnv = [&](unsigned f, T(&o)[V]) {
     if (JAC) {
@@ -986,6 +988,14 @@ VEC_KERNEL k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restric
     }
     stv<T>(at(pout, c), pc);
     stv<T>(at(q, c), y);
+    if (!FIRST && x) {
+      T xv[V], pv[V];
+      ldv<T>(at(x, c), xv);
+      ldv<T>(at(pin, c), pv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) xv[v] += ap * pv[v];
+      stv<T>(at(x, c), xv);
+    }
   });
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
@@ -1008,17 +1018,20 @@ VEC_KERNEL k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, const T
   constexpr int V = VW<T>::n;
   const T a = (T)st->alpha;
   double acc[2] = {0.0, 0.0};
+  // x null: the solution update is deferred to the next direction update
   FOR_ITEMS(L, T, i, j, kv, c) {
     T xv[V], rv[V], pv[V], qv[V];
-    ldv<T>(at(x, c), xv);
+    if (x) {
+      ldv<T>(at(x, c), xv);
+      ldv<T>(at(p, c), pv);
+    }
     ldv<T>(at(r, c), rv);
-    ldv<T>(at(p, c), pv);
     ldv<T>(at(q, c), qv);
     T dv[V], zv[V];
     if (JAC) ldv<T>(at(L.diag, c), dv);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      xv[v] += a * pv[v];
+      if (x) xv[v] += a * pv[v];
       rv[v] = rv[v] - a * qv[v];
       acc[0] += (double)rv[v] * (double)rv[v];
       if (JAC) {
@@ -1026,7 +1039,7 @@ VEC_KERNEL k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, const T
         zv[v] = rv[v] / dv[v];
       }
     }
-    stv<T>(at(x, c), xv);
+    if (x) stv<T>(at(x, c), xv);
     stv<T>(at(r, c), rv);
     if (JAC && zout) stv<T>(at(zout, c), zv);
   }
@@ -1144,16 +1157,19 @@ VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const
 
 // x += st->alpha p: the last iteration's deferred solution update (runs
 // after the solve has been flagged done).
-__global__ void k_axpy_alpha(double* __restrict__ x, const double* __restrict__ p, const SolveStatus* st,
-                             long long n) {
-  const double a = st->alpha;
+template <class T>
+__global__ void k_axpy_alpha(T* __restrict__ x, const T* __restrict__ p, const SolveStatus* st, long long n) {
+  const T a = (T)st->alpha;
   long long b0, b1;
   block_range(n, b0, b1);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) x[e] += a * p[e];
 }
-void launch_axpy_alpha(double* x, const double* p, const SolveStatus* st, long long n, hipStream_t s) {
-  k_axpy_alpha<<<grid_blocks(n), BLOCK, 0, s>>>(x, p, st, n);
+template <class T>
+void launch_axpy_alpha(T* x, const T* p, const SolveStatus* st, long long n, hipStream_t s) {
+  k_axpy_alpha<T><<<grid_blocks(n), BLOCK, 0, s>>>(x, p, st, n);
 }
+template void launch_axpy_alpha<double>(double*, const double*, const SolveStatus*, long long, hipStream_t);
+template void launch_axpy_alpha<float>(float*, const float*, const SolveStatus*, long long, hipStream_t);
 
 template <class T>
 VEC_KERNEL k_add_correction_v(Lev<T> L, double* __restrict__ x, const T* __restrict__ e) {
@@ -1460,29 +1476,40 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
   const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
   const Lev<T> M = vec ? march_lev(L) : L;   // the operator kernel's view and grid
   const int nbm = vec ? march_blocks(M) : nb;
+  // vectorised levels defer x += alpha p into the next direction update
+  T* xd = vec ? V.x : nullptr;
   if (H) {
-    auto kdir = vec ? dir_v<T, false>(first) : k_cg_dir_spmv<T, false>;
-    if (ev0) {
-      // events attached to the dispatch itself: kernel start and end times
-      hipExtLaunchKernelGGL(kdir, dim3(nbm), dim3(BLOCK), 0, s, ev0, ev1, 0, M, (const T*)*z, (const T*)V.r,
-                            (const T*)V.p, V.p_alt, V.q, st, partials, counters, (int)first);
+    if (vec) {
+      auto kdir = dir_v<T, false>(first);
+      if (ev0) {
+        // events attached to the dispatch itself: kernel start and end times
+        hipExtLaunchKernelGGL(kdir, dim3(nbm), dim3(BLOCK), 0, s, ev0, ev1, 0, M, (const T*)*z, (const T*)V.r,
+                              (const T*)V.p, V.p_alt, V.q, st, partials, counters, xd);
+      } else {
+        kdir<<<nbm, BLOCK, 0, s>>>(M, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
+      }
     } else {
-      kdir<<<nbm, BLOCK, 0, s>>>(M, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      auto kdir = k_cg_dir_spmv<T, false>;
+      if (ev0)
+        hipExtLaunchKernelGGL(kdir, dim3(nb), dim3(BLOCK), 0, s, ev0, ev1, 0, L, (const T*)*z, (const T*)V.r,
+                              (const T*)V.p, V.p_alt, V.q, st, partials, counters, (int)first);
+      else
+        kdir<<<nb, BLOCK, 0, s>>>(L, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
     }
     std::swap(V.p, V.p_alt);
-    if (vec) k_cg_update_v<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
+    if (vec) k_cg_update_v<T, false><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
     else k_cg_update<T, false><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1);
     mg_vcycle(*H, 0, V.r, st, partials, counters + 2, false, true, s, z);
   } else {
     if (vec && V.zj) {
       // z = r/diag was stored by the previous update (or the start)
-      dir_v<T, false>(first)<<<nbm, BLOCK, 0, s>>>(M, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      dir_v<T, false>(first)<<<nbm, BLOCK, 0, s>>>(M, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
       std::swap(V.p, V.p_alt);
-      k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, V.zj);
+      k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.q, st, partials, counters + 1, V.zj);
     } else if (vec) {
-      dir_v<T, true>(first)<<<nbm, BLOCK, 0, s>>>(M, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
+      dir_v<T, true>(first)<<<nbm, BLOCK, 0, s>>>(M, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
       std::swap(V.p, V.p_alt);
-      k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, V.x, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
+      k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
     } else {
       k_cg_dir_spmv<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, first);
       std::swap(V.p, V.p_alt);
@@ -1490,6 +1517,13 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
     }
   }
 }
+
+template <class T>
+bool cg_defers_x(const Lev<T>& L) {
+  return use_vec(L);
+}
+template bool cg_defers_x<double>(const Lev<double>&);
+template bool cg_defers_x<float>(const Lev<float>&);
 
 // Back-to-back launches of the multigrid CG operator kernel (direction
 // update with beta from st, matrix-free product, <p, q>) between two events;
@@ -1502,10 +1536,14 @@ double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout
   const bool vec = use_vec(L);
   const Lev<T> M = vec ? march_lev(L) : L;
   const int nb = vec ? march_blocks(M) : tile_blocks(L.ntiles);
-  auto kdir = vec ? k_cg_dir_spmv_v<T, false, false> : k_cg_dir_spmv<T, false>;
-  kdir<<<nb, BLOCK, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter, 0);
+  auto launch = [&]() {
+    if (vec) k_cg_dir_spmv_v<T, false, false><<<nb, BLOCK, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter,
+                                                                    nullptr);
+    else k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter, 0);
+  };
+  launch();
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-  for (int t = 0; t < reps; ++t) kdir<<<nb, BLOCK, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter, 0);
+  for (int t = 0; t < reps; ++t) launch();
   if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
