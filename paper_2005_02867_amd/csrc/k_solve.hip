@@ -615,6 +615,18 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
   const unsigned total = ny * nzv * nch;
   const unsigned P = ny * (unsigned)L.nz, sy = (unsigned)L.nz;
   const int lane = threadIdx.x & 63;
+  // Rows shared through LDS: when a block holds whole rows of one chunk
+  // (nzv divides BLOCK and every chunk's rows fill whole blocks), a thread's
+  // y neighbours inside the block are the threads nzv before and after it;
+  // each step they publish their (q, X) of the current plane in LDS (double
+  // buffered by step parity, one barrier per step) and only the block's
+  // first and last rows load their outer neighbour.  All threads of a block
+  // then run the same steps, so the barriers are uniform.
+  const bool coop = (BLOCK % nzv == 0) && ((ny * nzv) % BLOCK == 0);
+  __shared__ T lsq[2][BLOCK * V], lsx[2][BLOCK * V];
+  const int tid = threadIdx.x;
+  const bool inm = coop && tid >= (int)nzv, inp = coop && tid + (int)nzv < BLOCK;
+  int par = 0;
   for (unsigned e = lb * BLOCK + threadIdx.x; e < total; e += gridDim.x * BLOCK) {
   const unsigned kv = e % nzv, t = e / nzv, j = t % ny, ch = t / ny;
   const unsigned i0 = ch * clen, i1 = min(nx, i0 + clen);
@@ -635,10 +647,28 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
     T qn[V], xn[V], qym[V], xym[V], qyp[V], xyp[V];
     ldv<T>(at(L.qc, fn), qn);
     lx(fn, xn);
-    ldv<T>(at(L.qc, fym), qym);
-    lx(fym, xym);
-    ldv<T>(at(L.qc, fyp), qyp);
-    lx(fyp, xyp);
+    if (!inm) {
+      ldv<T>(at(L.qc, fym), qym);
+      lx(fym, xym);
+    }
+    if (!inp) {
+      ldv<T>(at(L.qc, fyp), qyp);
+      lx(fyp, xyp);
+    }
+    if (coop) {
+      stv<T>(&lsq[par][tid * V], qc);
+      stv<T>(&lsx[par][tid * V], xc);
+      __syncthreads();
+      if (inm) {
+        ldv<T>(&lsq[par][(tid - (int)nzv) * V], qym);
+        ldv<T>(&lsx[par][(tid - (int)nzv) * V], xym);
+      }
+      if (inp) {
+        ldv<T>(&lsq[par][(tid + (int)nzv) * V], qyp);
+        ldv<T>(&lsx[par][(tid + (int)nzv) * V], xyp);
+      }
+      par ^= 1;
+    }
     T qzm = lane_up(qc[V - 1]), xzm = lane_up(xc[V - 1]);
     T qzp = lane_down(qc[0]), xzp = lane_down(xc[0]);
     if (hzm && lane == 0) {
