@@ -849,6 +849,67 @@ VEC_KERNEL k_mg_restrict_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T*
   }
 }
 
+// Coarse residual in marching form: the fine grid is walked as in the sweeps
+// (so the fine residual r - A x costs the marching loads), each thread sums
+// the residual pairs (2K, 2K+1) of its vector over the planes 2I, 2I+1, and
+// the thread of row 2J+1 hands its sum through LDS to the thread of row 2J,
+// which writes the coarse cell.  Needs even nx, ny, nz, chunks of an even
+// number of planes and blocks of whole row pairs (restrict_marching_ok).
+template <class T>
+VEC_KERNEL k_mg_restrict_m(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+                           T* __restrict__ rc, const SolveStatus* st) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n, H = V / 2;
+  __shared__ T lsr[BLOCK * H];
+  const unsigned nzv = (unsigned)F.nz / V, P = (unsigned)F.ny * (unsigned)F.nz, sy = (unsigned)F.nz;
+  const int tid = threadIdx.x;
+  T acc[H];
+  march<T>(
+      F, [&](unsigned f, T(&o)[V]) { ldv<T>(at(x, f), o); }, [&](unsigned f) { return *at(x, f); },
+      [&](unsigned c, const T(&qv)[V], const T(&xv)[V], const T(&off)[V], const T(&dv)[V]) {
+        T rv[V];
+        ldv<T>(at(r, c), rv);
+        const unsigned i = c / P, rem = c - i * P, j = rem / sy, kv = (rem - j * sy) / V;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const T a0 = rv[2 * h] - (dv[2 * h] * xv[2 * h] - T(0.5) * F.sc * off[2 * h]);
+          const T a1 = rv[2 * h + 1] - (dv[2 * h + 1] * xv[2 * h + 1] - T(0.5) * F.sc * off[2 * h + 1]);
+          acc[h] = (i & 1u) ? acc[h] + (a0 + a1) : (a0 + a1);
+        }
+        if (i & 1u) {
+          if (j & 1u) {
+#pragma unroll
+            for (int h = 0; h < H; ++h) lsr[tid * H + h] = acc[h];
+          }
+          __syncthreads();
+          if (!(j & 1u)) {
+            const unsigned cc = ((i >> 1) * (unsigned)C.ny + (j >> 1)) * (unsigned)C.nz + kv * H;
+#pragma unroll
+            for (int h = 0; h < H; ++h) *at(rc, cc + h) = T(0.125) * (acc[h] + lsr[(tid + (int)nzv) * H + h]);
+          }
+          __syncthreads();
+        }
+      });
+}
+
+// The marching restriction applies: even extents, whole row pairs per block,
+// and the row sharing of the marching kernels (see march()).
+template <class T>
+inline bool restrict_marching_ok(const Lev<T>& F) {
+  if (!use_vec(F) || (F.nx & 1) || (F.ny & 1) || (F.nz % (2 * VW<T>::n))) return false;
+  const int nzv = F.nz / VW<T>::n;
+  return BLOCK % nzv == 0 && ((BLOCK / nzv) % 2 == 0) && ((long long)F.ny * nzv) % BLOCK == 0;
+}
+// march_lev with chunks of an even number of planes (plane pairs stay together).
+template <class T>
+inline Lev<T> march_lev_pairs(Lev<T> L) {
+  L = march_lev(L);
+  long long clen = (L.nx + L.mch - 1) / L.mch;
+  clen += clen & 1;
+  L.mch = (int)((L.nx + clen - 1) / clen);
+  return L;
+}
+
 // x' = x + P xc then one sweep (VW fine cells per thread).
 template <class T, bool DOT>
 VEC_KERNEL k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
@@ -1458,7 +1519,10 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
     return;
   }
   const Lev<T>& C = H.lev[l + 1];
-  if (vec) {
+  if (vec && restrict_marching_ok(L)) {
+    const Lev<T> Mp = march_lev_pairs(L);
+    k_mg_restrict_m<T><<<march_blocks(Mp), BLOCK, 0, s>>>(Mp, C, r, a, H.r[l + 1], st);
+  } else if (vec) {
     Lev<T> G = C;
     G.nz = L.nz;
     k_mg_restrict_v<T><<<vec_blocks(vec_items(G)), BLOCK, 0, s>>>(L, C, r, a, H.r[l + 1], st);
