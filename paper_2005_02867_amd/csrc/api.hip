@@ -73,6 +73,7 @@ struct ds_grid {
   float* zj32 = nullptr;           // the same for the FP32 rounds
   int dirmask = 0;                 // p_rgh = 0 box faces
   int batch_p[2] = {4, 4};         // pressure, then any other pressure-type system (phi, adjoints)
+  int f32_sys = -1;                // system whose FP32 copies (qc32, diag32) the last setup wrote
   struct {
     double inner_min = 1e-3;   // smallest FP32 inner relative tolerance per round (pressure-type)
     double inner_min_jac = 1e-6;  // the same for the energy and species systems
@@ -350,6 +351,25 @@ int& batch_of(ds_grid* g, int sys, const double* x) {
 }
 int batch_size(int expected, bool first) { return first ? std::max(2, expected) : std::max(2, expected / 4); }
 
+// The precision form's FP32 copies of the operator, written by the setup of
+// system sys next to the FP64 arrays; the following solve of that system then
+// skips its conversion passes.
+F32Out f32_out(ds_grid* g, int sys) {
+  F32Out fo;
+  if (g->prm.precision != DS_PREC_MIXED) return fo;
+  fo.q = g->qc32;
+  fo.d = g->diag32;
+  fo.mg = sys == 2 && g->prm.pressure_precond == 1;
+  fo.sc = (double)(float)(g->dp.dt / (g->dp.h * g->dp.h));   // scale of the FP32 fine level (sys 2)
+  g->f32_sys = sys;
+  return fo;
+}
+bool take_f32(ds_grid* g, int sys) {
+  const bool ready = g->f32_sys == sys;
+  g->f32_sys = -1;
+  return ready;
+}
+
 // Pressure-type systems (pressure, liquid-transport potential): the marching
 // kernels form the diagonal from q and the p = 0 faces instead of loading it.
 // For the pressure the result equals the setup's stored diagonal bit for bit
@@ -365,6 +385,7 @@ void pressure_type(const ds_grid* g, int sys, Lev<double>& L) {
 // (multigrid when enabled, Jacobi otherwise).
 int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
   int st;
+  g->f32_sys = -1;
   Lev<double> L = g->L0;
   L.sc = sc;
   L.qc = g->qc;
@@ -429,10 +450,12 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   lev_dims(F, L.nx, L.ny, L.nz, sc);
   F.qc = g->qc32;
   F.diag = g->diag32;
-  launch_to_float(g->qc, g->qc32, g->n, s);
   const bool mg = sys == 2 && g->prm.pressure_precond == 1;
-  if (mg) launch_mg_diag(F, g->dirmask, g->diag32, s);   // the formula the V-cycle forms on the fly
-  else launch_to_float(g->diag, g->diag32, g->n, s);
+  if (!take_f32(g, sys)) {
+    launch_to_float(g->qc, g->qc32, g->n, s);
+    if (mg) launch_mg_diag(F, g->dirmask, g->diag32, s);   // the formula the V-cycle forms on the fly
+    else launch_to_float(g->diag, g->diag32, g->n, s);
+  }
   MgHier<float>* H = nullptr;
   if (mg) {
     H = &g->H32;
@@ -511,8 +534,10 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   lev_dims(F, L.nx, L.ny, L.nz, sc);
   F.qc = g->qc32;
   F.diag = g->diag32;
-  launch_to_float(g->qc, g->qc32, g->n, s);
-  launch_mg_diag(F, g->dirmask, g->diag32, s);   // the formula the V-cycle forms on the fly
+  if (!take_f32(g, sys)) {
+    launch_to_float(g->qc, g->qc32, g->n, s);
+    launch_mg_diag(F, g->dirmask, g->diag32, s);   // the formula the V-cycle forms on the fly
+  }
   MgHier<float>& H = g->H32;
   H.lev[0] = F;
   mg_setup_levels(H, g->dirmask, s);
@@ -597,7 +622,7 @@ int one_step(ds_grid* g, hipStream_t s) {
   if ((st = evaporation_source(g, s)) != DS_OK) return st;
   // 3. advection of alpha1 with the divergence-free part of u^n, c and T with u^n
   if (g->prm.liquid_transport) {
-    launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s);
+    launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s, f32_out(g, 2));
     st = solve(g, 2, P.dt / (P.h * P.h), g->phi, s, &D.iters_phi, &D.res_phi, g->prm.tol_phi);
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
@@ -609,7 +634,8 @@ int one_step(ds_grid* g, hipStream_t s) {
                 g->a_new, g->c_new, g->T_new, g->partials, g->counters + CT_ADV, g->scal, s);
   // 5a. energy (warm start T')
   if (P.solve_energy) {
-    launch_energy_setup(P, g->a_new, g->T_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, s);
+    launch_energy_setup(P, g->a_new, g->T_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, s,
+                        f32_out(g, 0));
     st = solve(g, 0, 1.0 / (P.h * P.h), g->T_new, s, &D.iters_T, &D.res_T);
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
@@ -619,7 +645,8 @@ int one_step(ds_grid* g, hipStream_t s) {
     D.res_T = 0.0;
   }
   // 5b. species (warm start omega' = c'/(rho_G theta))
-  launch_species_setup(P, g->a_new, g->c_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, g->om_new, s);
+  launch_species_setup(P, g->a_new, g->c_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, g->om_new, s,
+                       f32_out(g, 1));
   st = solve(g, 1, P.rho_G * P.D / (P.h * P.h), g->om_new, s, &D.iters_omega, &D.res_omega);
   if (st == DS_ERR_NOT_CONVERGED) rc = st;
   else if (st != DS_OK) return st;
@@ -628,7 +655,7 @@ int one_step(ds_grid* g, hipStream_t s) {
   // 5c. momentum predictor with alpha'
   launch_predictor(P, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, s);
   // 6. pressure (warm start p^n) and correction
-  launch_pressure_setup(P, g->a_new, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s);
+  launch_pressure_setup(P, g->a_new, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s, f32_out(g, 2));
   st = solve_pressure_system(g, s, &D.iters_p, &D.res_p);
   if (st == DS_ERR_NOT_CONVERGED) rc = st;
   else if (st != DS_OK) return st;

@@ -21,6 +21,17 @@ enum Grad { GR_D = 0, GR_DH, GR_TAMB, GR_RHOG, GR_S1B, GR_S2B, GR_COUNT };
 
 int grid_blocks(long long n);   // streaming grid size (multiple of 8)
 
+// FP32 copies of an assembled operator for the precision form, written by the
+// setup kernels next to the FP64 ones (q null: none).  d: the FP32 diagonal,
+// (float) of the FP64 one, or with mg the multigrid's own formula on the FP32
+// q values (what k_mg_diag computes; sc: the FP32 level's scale, widened).
+struct F32Out {
+  float* q = nullptr;
+  float* d = nullptr;
+  int mg = 0;
+  double sc = 0.0;
+};
+
 // ---- step kernels (k_step.hip)
 void launch_xi(const DevParams& P, double* xi, hipStream_t s);
 // Interface cells in two passes (a scan writing per-block lists of interface
@@ -36,13 +47,13 @@ void launch_advect(const DevParams& P, const double* a1, const double* omega, co
                    double* a_new, double* c_new, double* T_new, double* partials, unsigned* counter, double* scal,
                    hipStream_t s);
 void launch_div_setup(const DevParams& P, const double* u, const double* v, const double* w, double* qc,
-                      double* diag, double* b, hipStream_t s);
+                      double* diag, double* b, hipStream_t s, F32Out fo = {});
 void launch_energy_setup(const DevParams& P, const double* a_new, const double* T_prime,
                          const double* mdot, const double* u, const double* v, const double* w,
-                         double* qc, double* diag, double* b, hipStream_t s);
+                         double* qc, double* diag, double* b, hipStream_t s, F32Out fo = {});
 void launch_species_setup(const DevParams& P, const double* a_new, const double* c_prime,
                           const double* mdot, const double* u, const double* v, const double* w,
-                          double* qc, double* diag, double* b, double* om0, hipStream_t s);
+                          double* qc, double* diag, double* b, double* om0, hipStream_t s, F32Out fo = {});
 void launch_species_update(const DevParams& P, const double* a_new, const double* c_prime,
                            const double* mdot, const double* om, const double* u, const double* v,
                            const double* w, double* c, double* omega, double* partials,
@@ -52,7 +63,7 @@ void launch_predictor(const DevParams& P, const double* a_new, const double* xi,
                       hipStream_t s);
 void launch_pressure_setup(const DevParams& P, const double* a_new, const double* mdot,
                            const double* us, const double* vs, const double* ws, double* qc,
-                           double* diag, double* b, hipStream_t s);
+                           double* diag, double* b, hipStream_t s, F32Out fo = {});
 void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
                     const double* vs, const double* ws, double* u, double* v, double* w,
                     hipStream_t s);

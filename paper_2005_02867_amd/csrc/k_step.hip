@@ -293,7 +293,8 @@ k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ 
 __global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ Tp,
                                const double* __restrict__ mdot, const double* __restrict__ u,
                                const double* __restrict__ v, const double* __restrict__ w,
-                               double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b) {
+                               double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b,
+                               F32Out fo) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   const double ih2 = 1.0 / (P.h * P.h);
@@ -323,6 +324,10 @@ __global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, co
     qc[c] = kc;
     diag[c] = d;
     b[c] = rhs;
+    if (fo.q) {
+      fo.q[c] = (float)kc;
+      fo.d[c] = (float)d;
+    }
   }
 }
 
@@ -331,7 +336,7 @@ __global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, c
                                 const double* __restrict__ mdot, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
                                 double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b,
-                                double* __restrict__ om0) {
+                                double* __restrict__ om0, F32Out fo) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   const double sc = P.rho_G * P.D / (P.h * P.h);
@@ -359,6 +364,10 @@ __global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, c
     diag[c] = d;
     b[c] = cp_[c] / P.dt + mdot[c];
     if (om0) om0[c] = cp_[c] / (P.rho_G * th);
+    if (fo.q) {
+      fo.q[c] = (float)th;
+      fo.d[c] = (float)d;
+    }
   }
 }
 
@@ -476,7 +485,7 @@ __global__ void k_predictor(DevParams P, const double* __restrict__ a_new, const
 __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ mdot,
                                  const double* __restrict__ us, const double* __restrict__ vs,
                                  const double* __restrict__ ws, double* __restrict__ qc,
-                                 double* __restrict__ diag, double* __restrict__ b) {
+                                 double* __restrict__ diag, double* __restrict__ b, F32Out fo) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   const double sc = P.dt / (P.h * P.h);
@@ -488,7 +497,8 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
     bool has[6];
     nbr6(P, a_new, c, i, j, k, an, has);
     const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, P.rho_G);
-    double d = 0.0;
+    const double b32 = (double)(float)beta;
+    double d = 0.0, d32 = 0.0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
@@ -496,8 +506,10 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
         if (has[ax * 2 + sd]) {
           const double bn = 1.0 / mix(clamp01(an[ax * 2 + sd]), P.rho_L, P.rho_G);
           d += sc * 0.5 * (beta + bn);
+          d32 += fo.sc * 0.5 * (b32 + (double)(float)bn);
         } else if (pressure_dirichlet(P.kind[ax * 2 + sd])) {
           d += 2.0 * sc * beta;
+          d32 += 2.0 * fo.sc * b32;
         }
       }
     const double div = ((us[uidx(P, i + 1, j, k)] - us[uidx(P, i, j, k)]) +
@@ -506,6 +518,10 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
     qc[c] = beta;
     diag[c] = d;
     b[c] = mdot[c] * Ssc - div;
+    if (fo.q) {
+      fo.q[c] = (float)beta;
+      fo.d[c] = fo.mg ? (float)d32 : (float)d;
+    }
   }
 }
 
@@ -515,26 +531,36 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
 // operator's form with q = 1/dt: (dt/h^2)(1/dt) = 1/h^2 per face.
 __global__ void k_div_setup(DevParams P, const double* __restrict__ u, const double* __restrict__ v,
                             const double* __restrict__ w, double* __restrict__ qc, double* __restrict__ diag,
-                            double* __restrict__ b) {
+                            double* __restrict__ b, F32Out fo) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   const double ih2 = 1.0 / (P.h * P.h);
+  const double q = 1.0 / P.dt, q32 = (double)(float)q;
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
-    double d = 0.0;
+    double d = 0.0, d32 = 0.0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
-        if (nbr(P, ax, sd, i, j, k) >= 0) d += ih2;
-        else if (pressure_dirichlet(P.kind[ax * 2 + sd])) d += 2.0 * ih2;
+        if (nbr(P, ax, sd, i, j, k) >= 0) {
+          d += ih2;
+          d32 += fo.sc * 0.5 * (q32 + q32);
+        } else if (pressure_dirichlet(P.kind[ax * 2 + sd])) {
+          d += 2.0 * ih2;
+          d32 += 2.0 * fo.sc * q32;
+        }
       }
     const double div = ((u[uidx(P, i + 1, j, k)] - u[uidx(P, i, j, k)]) + (v[vidx(P, i, j + 1, k)] - v[vidx(P, i, j, k)]) +
                         (w[widx(P, i, j, k + 1)] - w[widx(P, i, j, k)])) / P.h;
-    qc[c] = 1.0 / P.dt;
+    qc[c] = q;
     diag[c] = d;
     b[c] = -div;
+    if (fo.q) {
+      fo.q[c] = (float)q;
+      fo.d[c] = fo.mg ? (float)d32 : (float)d;
+    }
   }
 }
 
@@ -678,13 +704,13 @@ void launch_advect(const DevParams& P, const double* a1, const double* omega, co
 }
 void launch_energy_setup(const DevParams& P, const double* a_new, const double* T_prime,
                          const double* mdot, const double* u, const double* v, const double* w,
-                         double* qc, double* diag, double* b, hipStream_t s) {
-  k_energy_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, T_prime, mdot, u, v, w, qc, diag, b);
+                         double* qc, double* diag, double* b, hipStream_t s, F32Out fo) {
+  k_energy_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, T_prime, mdot, u, v, w, qc, diag, b, fo);
 }
 void launch_species_setup(const DevParams& P, const double* a_new, const double* c_prime,
                           const double* mdot, const double* u, const double* v, const double* w,
-                          double* qc, double* diag, double* b, double* om0, hipStream_t s) {
-  k_species_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, u, v, w, qc, diag, b, om0);
+                          double* qc, double* diag, double* b, double* om0, hipStream_t s, F32Out fo) {
+  k_species_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, u, v, w, qc, diag, b, om0, fo);
 }
 void launch_species_update(const DevParams& P, const double* a_new, const double* c_prime,
                            const double* mdot, const double* om, const double* u, const double* v,
@@ -703,12 +729,12 @@ void launch_predictor(const DevParams& P, const double* a_new, const double* xi,
 }
 void launch_pressure_setup(const DevParams& P, const double* a_new, const double* mdot,
                            const double* us, const double* vs, const double* ws, double* qc,
-                           double* diag, double* b, hipStream_t s) {
-  k_pressure_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, mdot, us, vs, ws, qc, diag, b);
+                           double* diag, double* b, hipStream_t s, F32Out fo) {
+  k_pressure_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, mdot, us, vs, ws, qc, diag, b, fo);
 }
 void launch_div_setup(const DevParams& P, const double* u, const double* v, const double* w, double* qc,
-                      double* diag, double* b, hipStream_t s) {
-  k_div_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, u, v, w, qc, diag, b);
+                      double* diag, double* b, hipStream_t s, F32Out fo) {
+  k_div_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, u, v, w, qc, diag, b, fo);
 }
 void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
                     const double* vs, const double* ws, double* u, double* v, double* w,
