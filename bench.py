@@ -28,8 +28,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 # and WRITE_SIZE (separate runs of `bench.py --counters-pass`), each scaled by
 # the ratio of known bytes to the counter's reading for a 1 GiB device copy in
 # the same run; None until measured for the current kernel.
-# Not yet measured for the current form of the sweep (diag formed from q_coef).
-TRAFFIC_SMOOTH = None
+# Measured for the fine-level sweep of the 256^3 workload: FETCH_SIZE 109725 KiB
+# x 2.000 (the 1 GiB copy reads 524331 KiB) + WRITE_SIZE 65536 KiB x 1.000.
+TRAFFIC_SMOOTH = (109725.0 * (1048576.0 / 524331.0) + 65536.0) * 1024.0
 
 
 def log(msg):
