@@ -116,6 +116,8 @@ double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, 
 bool mg32_supported(const Lev<double>& L);
 // Largest grid of the z-vectorised kernels (rounded to a multiple of 8).
 void set_vec_max_blocks(int nb);
+// Threads (columns x chunks) the marching kernels aim for.
+void set_march_threads(int n);
 double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1);

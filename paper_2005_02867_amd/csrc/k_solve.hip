@@ -574,10 +574,13 @@ __device__ __forceinline__ void off_sum_v(const Lev<T>& L, unsigned c, int i, in
 // reads come from the same L2.
 
 // Chunks per column: enough threads for about 1024 blocks of 256.
+int g_march_threads = 262144;
+void set_march_threads(int n) { g_march_threads = std::max(n, BLOCK); }
 template <class T>
 inline Lev<T> march_lev(Lev<T> L) {
   const long long ncol = (long long)L.ny * (L.nz / VW<T>::n);
-  const long long nch = std::min<long long>(std::max<long long>((262144 + ncol - 1) / ncol, 1), L.nx);
+  const long long nch =
+      std::min<long long>(std::max<long long>(((long long)g_march_threads + ncol - 1) / ncol, 1), L.nx);
   const long long clen = (L.nx + nch - 1) / nch;
   L.mch = (int)((L.nx + clen - 1) / clen);   // no empty trailing chunks
   return L;

@@ -173,10 +173,86 @@ __global__ void k_source(DevParams P, const double* __restrict__ alpha, const do
 }
 
 // ---------------------------------------------------------------- S5
-// One cell per thread.  Along each axis the cell's line values at offsets
-// -2..+2 of alpha1, omega and T (and -1..+1 of phi) are loaded up front from
-// clamped positions, then both faces are formed with selects: no load waits
-// on a data-dependent branch (the upwind side).
+// Fluxes and update of one cell from its line values: A, O, TT hold alpha1,
+// omega and T at offsets -2, -1, +1, +2 along each axis (index 0..3), h whether
+// those cells exist; PH phi at -1, +1; uf the six face velocities.  The faces
+// are formed with selects (no load waits on the upwind side).
+__device__ __forceinline__ void advect_cell(const DevParams& P, const int (&pos)[3], const double (&uf)[3][2],
+                                            double A0, double O0, double T0, double P0, const double (&A)[3][4],
+                                            const double (&O)[3][4], const double (&TT)[3][4],
+                                            const double (&PH)[3][2], const bool (&h)[3][4], bool has_phi,
+                                            double cv, double (&acc)[2], double& an, double& cn, double& tn) {
+  const int nn[3] = {P.nx, P.ny, P.nz};
+  double da = 0.0, dc = 0.0, dT = 0.0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const int q = pos[ax], n = nn[ax];
+    const bool lo_in = q > 0, hi_in = q < n - 1;
+    double F[2], G[2], H[2];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const double ufv = uf[ax][sd];
+      const bool in = sd == 0 ? lo_in : hi_in;
+      // interior face: (m, a, b, p) = (-2, -1, 0, +1) below the cell, (-1, 0, +1, +2) above
+      auto face = [&](const double (&L)[4], double c0, double vel) {
+        return sd == 0 ? tvd_face(L[0], L[1], c0, L[2], h[ax][0], h[ax][2], vel)
+                       : tvd_face(L[1], c0, L[2], L[3], h[ax][1], h[ax][3], vel);
+      };
+      const double af = in ? face(A[ax], A0, ufv) : box_face(A0, 0.0, ufv, sd);
+      const double of = in ? face(O[ax], O0, ufv) : box_face(O0, 0.0, ufv, sd);
+      if (has_phi) {
+        double ul;
+        if (sd == 0)
+          ul = in ? ufv - (P0 - PH[ax][0]) / P.h
+                  : (pressure_dirichlet(P.kind[ax * 2]) ? ufv - 2.0 * P0 / P.h : ufv);
+        else
+          ul = in ? ufv - (PH[ax][1] - P0) / P.h
+                  : (pressure_dirichlet(P.kind[ax * 2 + 1]) ? ufv + 2.0 * P0 / P.h : ufv);
+        F[sd] = ul * (in ? face(A[ax], A0, ul) : box_face(A0, 0.0, ul, sd));
+      } else {
+        F[sd] = ufv * af;
+      }
+      G[sd] = P.rho_G * of * (1.0 - af) * ufv;
+      if (P.solve_energy) {
+        const double Tf = in ? face(TT[ax], T0, ufv) : box_face(T0, P.T_amb, ufv, sd);
+        H[sd] = ufv * (Tf - T0);
+      } else {
+        H[sd] = 0.0;
+      }
+    }
+    da += F[1] - F[0];
+    dc += G[1] - G[0];
+    dT += H[1] - H[0];
+    if (!lo_in) {
+      acc[0] -= F[0];
+      acc[1] -= G[0];
+    }
+    if (!hi_in) {
+      acc[0] += F[1];
+      acc[1] += G[1];
+    }
+  }
+  const double s = P.dt / P.h;
+  an = A0 - s * da;
+  cn = cv - s * dc;
+  tn = P.solve_energy ? T0 - s * dT : T0;
+}
+
+__device__ __forceinline__ void advect_publish(const DevParams& P, double (&acc)[2], double* partials,
+                                               unsigned* counter, double* scal) {
+  const int ops[2] = {RSUM, RSUM};
+  if (block_reduce_publish<2>(acc, ops, partials, counter)) {
+    double tot[2];
+    block_combine<2>(ops, partials, counter, tot);
+    if (threadIdx.x == 0) {
+      const double area_dt = P.h * P.h * P.dt;
+      scal[SC_BL] = P.rho_L * area_dt * tot[0];
+      scal[SC_BV_ADV] = area_dt * tot[1];
+    }
+  }
+}
+
+// One cell per thread; every line value loaded up front from clamped positions.
 __global__ void __launch_bounds__(BLOCK)
 k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
          const double* __restrict__ T, const double* __restrict__ c,
@@ -198,8 +274,7 @@ k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ 
                              {w[widx(P, i, j, k)], w[widx(P, i, j, k + 1)]}};
     const double A0 = a1[cc], O0 = omega[cc], T0 = T[cc];
     const double P0 = phi ? phi[cc] : 0.0;
-    // line values at offsets -2, -1, +1, +2 (index 0, 1, 2, 3); h: they exist
-    double A[3][4], O[3][4], TT[3][4], PH[3][2];
+    double A[3][4], O[3][4], TT[3][4], PH[3][2] = {};
     bool h[3][4];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -221,71 +296,13 @@ k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ 
         PH[ax][1] = phi[cc + o[2]];
       }
     }
-    const double cv = c[cc];
-    double da = 0.0, dc = 0.0, dT = 0.0;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const int q = pos[ax], n = nn[ax];
-      const bool lo_in = q > 0, hi_in = q < n - 1;
-      double F[2], G[2], H[2];
-#pragma unroll
-      for (int sd = 0; sd < 2; ++sd) {
-        const double ufv = uf[ax][sd];
-        const bool in = sd == 0 ? lo_in : hi_in;
-        // interior face: (m, a, b, p) = (-2, -1, 0, +1) below the cell, (-1, 0, +1, +2) above
-        auto face = [&](const double (&L)[4], double c0, double vel) {
-          return sd == 0 ? tvd_face(L[0], L[1], c0, L[2], h[ax][0], h[ax][2], vel)
-                         : tvd_face(L[1], c0, L[2], L[3], h[ax][1], h[ax][3], vel);
-        };
-        const double af = in ? face(A[ax], A0, ufv) : box_face(A0, 0.0, ufv, sd);
-        const double of = in ? face(O[ax], O0, ufv) : box_face(O0, 0.0, ufv, sd);
-        if (phi) {
-          double ul;
-          if (sd == 0)
-            ul = in ? ufv - (P0 - PH[ax][0]) / P.h
-                    : (pressure_dirichlet(P.kind[ax * 2]) ? ufv - 2.0 * P0 / P.h : ufv);
-          else
-            ul = in ? ufv - (PH[ax][1] - P0) / P.h
-                    : (pressure_dirichlet(P.kind[ax * 2 + 1]) ? ufv + 2.0 * P0 / P.h : ufv);
-          F[sd] = ul * (in ? face(A[ax], A0, ul) : box_face(A0, 0.0, ul, sd));
-        } else {
-          F[sd] = ufv * af;
-        }
-        G[sd] = P.rho_G * of * (1.0 - af) * ufv;
-        if (P.solve_energy) {
-          const double Tf = in ? face(TT[ax], T0, ufv) : box_face(T0, P.T_amb, ufv, sd);
-          H[sd] = ufv * (Tf - T0);
-        } else {
-          H[sd] = 0.0;
-        }
-      }
-      da += F[1] - F[0];
-      dc += G[1] - G[0];
-      dT += H[1] - H[0];
-      if (!lo_in) {
-        acc[0] -= F[0];
-        acc[1] -= G[0];
-      }
-      if (!hi_in) {
-        acc[0] += F[1];
-        acc[1] += G[1];
-      }
-    }
-    const double s = P.dt / P.h;
-    a_new[cc] = A0 - s * da;
-    c_new[cc] = cv - s * dc;
-    T_new[cc] = P.solve_energy ? T0 - s * dT : T0;
+    double an, cn, tn;
+    advect_cell(P, pos, uf, A0, O0, T0, P0, A, O, TT, PH, h, phi != nullptr, c[cc], acc, an, cn, tn);
+    a_new[cc] = an;
+    c_new[cc] = cn;
+    T_new[cc] = tn;
   }
-  const int ops[2] = {RSUM, RSUM};
-  if (block_reduce_publish<2>(acc, ops, partials, counter)) {
-    double tot[2];
-    block_combine<2>(ops, partials, counter, tot);
-    if (threadIdx.x == 0) {
-      const double area_dt = P.h * P.h * P.dt;
-      scal[SC_BL] = P.rho_L * area_dt * tot[0];
-      scal[SC_BV_ADV] = area_dt * tot[1];
-    }
-  }
+  advect_publish(P, acc, partials, counter, scal);
 }
 
 // ---------------------------------------------------------------- S6-S8
