@@ -435,65 +435,83 @@ __global__ void k_species_update(DevParams P, const double* __restrict__ a_new, 
 }
 
 // ---------------------------------------------------------------- S9
-// Predictor on the faces normal to axis AX (eq. 30 / rho, mu = 0).
+// Predictor on the face (i, j, k) normal to axis AX (eq. 30 / rho, mu = 0),
+// indices in that face array (extent +1 along AX).
 template <int AX>
+__device__ __forceinline__ double predictor_face(const DevParams& P, const double* __restrict__ a_new,
+                                                 const double* __restrict__ xi, const double* __restrict__ u,
+                                                 const double* __restrict__ v, const double* __restrict__ w, int i,
+                                                 int j, int k) {
+  const int fx = P.nx + (AX == 0), fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
+  (void)fx;
+  const double* F = AX == 0 ? u : (AX == 1 ? v : w);
+  const long long e = ((long long)i * fy + j) * fz + k;
+  const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
+  const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
+  const double uc = F[e];
+  if (fpos == 0 || fpos == nax) {
+    const int kind = P.kind[AX * 2 + (fpos == 0 ? 0 : 1)];
+    return kind == WALL ? 0.0 : (kind == INLET ? P.w_in : uc);
+  }
+  // strides of the face array
+  const long long sx = (long long)fy * fz, sy = fz, sz = 1;
+  const long long sA = AX == 0 ? sx : (AX == 1 ? sy : sz);
+  // normal advection, first-order upwind
+  const double back = (uc - F[e - sA]) / P.h, fwd = (F[e + sA] - uc) / P.h;
+  double adv = uc * (uc > 0.0 ? back : fwd);
+  // cells on both sides of the face
+  const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
+  // transverse advection: 4-point averaged transverse velocity, zero-gradient ghosts
+#pragma unroll
+  for (int bx = 0; bx < 3; ++bx) {
+    if (bx == AX) continue;
+    double vb;
+    if (bx == 0) {   // u averaged onto the face
+      vb = 0.25 * (u[uidx(P, iL, jL, kL)] + u[uidx(P, iL + 1, jL, kL)] + u[uidx(P, i, j, k)] + u[uidx(P, i + 1, j, k)]);
+    } else if (bx == 1) {
+      vb = 0.25 * (v[vidx(P, iL, jL, kL)] + v[vidx(P, iL, jL + 1, kL)] + v[vidx(P, i, j, k)] + v[vidx(P, i, j + 1, k)]);
+    } else {
+      vb = 0.25 * (w[widx(P, iL, jL, kL)] + w[widx(P, iL, jL, kL + 1)] + w[widx(P, i, j, k)] + w[widx(P, i, j, k + 1)]);
+    }
+    const int pb = bx == 0 ? i : (bx == 1 ? j : k);
+    const int nb_ = bx == 0 ? fx : (bx == 1 ? fy : fz);
+    const long long sb = bx == 0 ? sx : (bx == 1 ? sy : sz);
+    const double lo = pb >= 1 ? F[e - sb] : uc;
+    const double hi = pb <= nb_ - 2 ? F[e + sb] : uc;
+    const double d = vb > 0.0 ? (uc - lo) / P.h : (hi - uc) / P.h;
+    adv += vb * d;
+  }
+  const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
+  const double aL = clamp01(a_new[cL]), aR = clamp01(a_new[cR]);
+  const double rL = mix(aL, P.rho_L, P.rho_G), rR = mix(aR, P.rho_L, P.rho_G);
+  const double bf = 0.5 * (1.0 / rL + 1.0 / rR);
+  const double xf = (AX == 0 ? i : i + 0.5) * P.h - P.x0[0];
+  const double yf = (AX == 1 ? j : j + 0.5) * P.h - P.x0[1];
+  const double zf = (AX == 2 ? k : k + 0.5) * P.h - P.x0[2];
+  const double gr = P.g[0] * xf + P.g[1] * yf + P.g[2] * zf;
+  const double force = -gr * (rR - rL) / P.h * bf + 0.5 * (aL + aR) * (xi[cR] - xi[cL]) / P.h;
+  return uc - P.dt * adv + P.dt * force;
+}
+
+// All three face arrays in one pass over the cells: cell (i, j, k) writes the
+// faces (i, j, k) of u*, v* and w* and, on the high box faces, the face beyond.
+// The three face computations of a cell read overlapping neighbourhoods, which
+// the caches then serve once instead of three kernels streaming them apiece.
 __global__ void k_predictor(DevParams P, const double* __restrict__ a_new, const double* __restrict__ xi,
                             const double* __restrict__ u, const double* __restrict__ v,
-                            const double* __restrict__ w, double* __restrict__ out) {
-  const int fx = P.nx + (AX == 0), fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
-  const long long nf = (long long)fx * fy * fz;
+                            const double* __restrict__ w, double* __restrict__ us, double* __restrict__ vs,
+                            double* __restrict__ ws) {
   long long b0, b1;
-  block_range(nf, b0, b1);
-  const double* F = AX == 0 ? u : (AX == 1 ? v : w);
-  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+  block_range(P.n, b0, b1);
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
-    decode3(e, fy, fz, i, j, k);
-    const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
-    const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
-    const double uc = F[e];
-    if (fpos == 0 || fpos == nax) {
-      const int kind = P.kind[AX * 2 + (fpos == 0 ? 0 : 1)];
-      out[e] = kind == WALL ? 0.0 : (kind == INLET ? P.w_in : uc);
-      continue;
-    }
-    // strides of the face array
-    const long long sx = (long long)fy * fz, sy = fz, sz = 1;
-    const long long sA = AX == 0 ? sx : (AX == 1 ? sy : sz);
-    // normal advection, first-order upwind
-    const double back = (uc - F[e - sA]) / P.h, fwd = (F[e + sA] - uc) / P.h;
-    double adv = uc * (uc > 0.0 ? back : fwd);
-    // cells on both sides of the face
-    const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
-    // transverse advection: 4-point averaged transverse velocity, zero-gradient ghosts
-#pragma unroll
-    for (int bx = 0; bx < 3; ++bx) {
-      if (bx == AX) continue;
-      double vb;
-      if (bx == 0) {   // u averaged onto the face
-        vb = 0.25 * (u[uidx(P, iL, jL, kL)] + u[uidx(P, iL + 1, jL, kL)] + u[uidx(P, i, j, k)] + u[uidx(P, i + 1, j, k)]);
-      } else if (bx == 1) {
-        vb = 0.25 * (v[vidx(P, iL, jL, kL)] + v[vidx(P, iL, jL + 1, kL)] + v[vidx(P, i, j, k)] + v[vidx(P, i, j + 1, k)]);
-      } else {
-        vb = 0.25 * (w[widx(P, iL, jL, kL)] + w[widx(P, iL, jL, kL + 1)] + w[widx(P, i, j, k)] + w[widx(P, i, j, k + 1)]);
-      }
-      const int pb = bx == 0 ? i : (bx == 1 ? j : k);
-      const int nb_ = bx == 0 ? fx : (bx == 1 ? fy : fz);
-      const long long sb = bx == 0 ? sx : (bx == 1 ? sy : sz);
-      const double lo = pb >= 1 ? F[e - sb] : uc;
-      const double hi = pb <= nb_ - 2 ? F[e + sb] : uc;
-      const double d = vb > 0.0 ? (uc - lo) / P.h : (hi - uc) / P.h;
-      adv += vb * d;
-    }
-    const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
-    const double aL = clamp01(a_new[cL]), aR = clamp01(a_new[cR]);
-    const double rL = mix(aL, P.rho_L, P.rho_G), rR = mix(aR, P.rho_L, P.rho_G);
-    const double bf = 0.5 * (1.0 / rL + 1.0 / rR);
-    const double xf = (AX == 0 ? i : i + 0.5) * P.h - P.x0[0];
-    const double yf = (AX == 1 ? j : j + 0.5) * P.h - P.x0[1];
-    const double zf = (AX == 2 ? k : k + 0.5) * P.h - P.x0[2];
-    const double gr = P.g[0] * xf + P.g[1] * yf + P.g[2] * zf;
-    const double force = -gr * (rR - rL) / P.h * bf + 0.5 * (aL + aR) * (xi[cR] - xi[cL]) / P.h;
-    out[e] = uc - P.dt * adv + P.dt * force;
+    decode(P, c, i, j, k);
+    us[uidx(P, i, j, k)] = predictor_face<0>(P, a_new, xi, u, v, w, i, j, k);
+    vs[vidx(P, i, j, k)] = predictor_face<1>(P, a_new, xi, u, v, w, i, j, k);
+    ws[widx(P, i, j, k)] = predictor_face<2>(P, a_new, xi, u, v, w, i, j, k);
+    if (i == P.nx - 1) us[uidx(P, P.nx, j, k)] = predictor_face<0>(P, a_new, xi, u, v, w, P.nx, j, k);
+    if (j == P.ny - 1) vs[vidx(P, i, P.ny, k)] = predictor_face<1>(P, a_new, xi, u, v, w, i, P.ny, k);
+    if (k == P.nz - 1) ws[widx(P, i, j, P.nz)] = predictor_face<2>(P, a_new, xi, u, v, w, i, j, P.nz);
   }
 }
 
@@ -738,11 +756,7 @@ void launch_species_update(const DevParams& P, const double* a_new, const double
 void launch_predictor(const DevParams& P, const double* a_new, const double* xi, const double* u,
                       const double* v, const double* w, double* us, double* vs, double* ws,
                       hipStream_t s) {
-  const long long nu = (long long)(P.nx + 1) * P.ny * P.nz, nv = (long long)P.nx * (P.ny + 1) * P.nz,
-                  nw = (long long)P.nx * P.ny * (P.nz + 1);
-  k_predictor<0><<<grid_blocks(nu), BLOCK, 0, s>>>(P, a_new, xi, u, v, w, us);
-  k_predictor<1><<<grid_blocks(nv), BLOCK, 0, s>>>(P, a_new, xi, u, v, w, vs);
-  k_predictor<2><<<grid_blocks(nw), BLOCK, 0, s>>>(P, a_new, xi, u, v, w, ws);
+  k_predictor<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, xi, u, v, w, us, vs, ws);
 }
 void launch_pressure_setup(const DevParams& P, const double* a_new, const double* mdot,
                            const double* us, const double* vs, const double* ws, double* qc,
