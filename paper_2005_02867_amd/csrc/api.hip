@@ -913,6 +913,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_VEC_BLOCKS")) set_vec_max_blocks(atoi(e));
   if (const char* e = getenv("DSVOF_VEC_YTILE")) g_vec_ytile = atoi(e);
   if (const char* e = getenv("DSVOF_MARCH_THREADS")) set_march_threads(atoi(e));
+  if (const char* e = getenv("DSVOF_MARCH_MIN_PLANES")) set_march_min_planes(atoi(e));
   lev_dims(g->L0, nx, ny, nz, 1.0);
   if (const char* e = getenv("DSVOF_INNER_MIN")) g->tune.inner_min = atof(e);
   if (const char* e = getenv("DSVOF_INNER_MIN_JAC")) g->tune.inner_min_jac = atof(e);

@@ -118,6 +118,8 @@ bool mg32_supported(const Lev<double>& L);
 void set_vec_max_blocks(int nb);
 // Threads (columns x chunks) the marching kernels aim for.
 void set_march_threads(int n);
+// Shortest chunk of x-planes a marching thread walks.
+void set_march_min_planes(int n);
 double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1);

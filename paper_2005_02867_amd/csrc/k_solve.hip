@@ -575,13 +575,15 @@ __device__ __forceinline__ void off_sum_v(const Lev<T>& L, unsigned c, int i, in
 
 // Chunks per column: enough threads for about 1024 blocks of 256.
 int g_march_threads = 262144;
+int g_march_min_planes = 1;
 void set_march_threads(int n) { g_march_threads = std::max(n, BLOCK); }
+void set_march_min_planes(int n) { g_march_min_planes = std::max(n, 1); }
 template <class T>
 inline Lev<T> march_lev(Lev<T> L) {
   const long long ncol = (long long)L.ny * (L.nz / VW<T>::n);
   const long long nch =
       std::min<long long>(std::max<long long>(((long long)g_march_threads + ncol - 1) / ncol, 1), L.nx);
-  const long long clen = (L.nx + nch - 1) / nch;
+  const long long clen = std::max<long long>((L.nx + nch - 1) / nch, std::min(g_march_min_planes, L.nx));
   L.mch = (int)((L.nx + clen - 1) / clen);   // no empty trailing chunks
   return L;
 }
