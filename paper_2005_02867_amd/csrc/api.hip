@@ -167,7 +167,7 @@ size_t carve(ds_grid* g, char* base) {
   g->qc = L.take<double>(base, n);
   g->adj = L.take<int>(base, n);
   g->band = L.take<int>(base, (size_t)interface_band_capacity(n));
-  g->band_count = L.take<int>(base, MAX_BLOCKS);
+  g->band_count = L.take<int>(base, 2 * MAX_BLOCKS + 1);   // counts, then offsets
   g->partials = L.take<double>(base, (size_t)MAX_BLOCKS * MAX_RED);
   g->counters = L.take<unsigned>(base, CT_COUNT);
   g->scal = L.take<double>(base, SC_COUNT);

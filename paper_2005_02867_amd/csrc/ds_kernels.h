@@ -40,6 +40,7 @@ void launch_interface(const DevParams& P, const double* alpha, const double* T, 
                       const double* u, const double* v, const double* w, double* mraw, int* adj, int* band,
                       int* band_count, double* partials, unsigned* counter, double* scal, hipStream_t s);
 long long interface_band_capacity(long long n);   // ints needed for `band`
+// band_count: 2 * MAX_BLOCKS + 1 ints (per-block counts, then their offsets).
 void launch_source(const DevParams& P, const double* alpha, const double* mraw, const double* scal,
                    double* mdot, double* a1, hipStream_t s);
 void launch_advect(const DevParams& P, const double* a1, const double* omega, const double* T,

@@ -3,6 +3,8 @@
 // streaming one contiguous range (XCD-aware order, see block_range).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ds_device.h"
 #include "ds_kernels.h"
 #include "ds_stencil.h"
@@ -80,7 +82,29 @@ __global__ void __launch_bounds__(BLOCK) k_interface_scan(DevParams P, const dou
   if (threadIdx.x == 0) band_count[blockIdx.x] = base_sh;
 }
 
-// Pass 2 (interface cells of each block's list): central-difference gradient
+// Exclusive prefix sums of the per-block interface counts, in one workgroup:
+// off[b] = sum of count[b'] over b' < b, off[nb] = the total (nb <= 2048).
+__global__ void __launch_bounds__(1024) k_band_offsets(const int* __restrict__ count, int nb, int* __restrict__ off) {
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int a = 2 * t < nb ? count[2 * t] : 0, b = 2 * t + 1 < nb ? count[2 * t + 1] : 0;
+  int v = a + b;   // inclusive scan over the wave
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  if (lane == 63) wsum[wid] = v;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wid; ++w) base += wsum[w];
+  const int excl = base + v - (a + b);
+  if (2 * t < nb) off[2 * t] = excl;
+  if (2 * t + 1 < nb) off[2 * t + 1] = excl + a;
+  if (t == 1023) off[nb] = base + v;
+}
+
+// Pass 2 (interface cells, all lists taken as one sequence in cell order and
+// dealt to full waves): central-difference gradient
 // with a zero ghost outside the box, outward normal n = -grad/|grad|, march
 // along n to the first gas cell (adj), evaporation flux at adj (eqs. 12-14)
 // times |grad alpha| (eq. 17); the sums of eq. 20 and the interface count.
@@ -89,15 +113,20 @@ __global__ void __launch_bounds__(BLOCK) k_interface_scan(DevParams P, const dou
 __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
                             const double* __restrict__ omega, const double* __restrict__ u,
                             const double* __restrict__ v, const double* __restrict__ w,
-                            const int* __restrict__ band, const int* __restrict__ band_count,
+                            const int* __restrict__ band, const int* __restrict__ off, int nlists, long long cap,
                             double* __restrict__ mraw, int* __restrict__ adj, double* partials,
                             unsigned* counter, double* scal) {
   double acc[3] = {0.0, 0.0, 0.0};
-  const long long cap = (long long)((P.n + gridDim.x - 1) / gridDim.x + BLOCK - 1) / BLOCK * BLOCK;
-  const int* list = band + (long long)blockIdx.x * cap;
-  const int cnt = band_count[blockIdx.x];
-  for (int t = threadIdx.x; t < cnt; t += BLOCK) {
-    const long long c = list[t];
+  const int total = off[nlists];
+  for (int g = blockIdx.x * BLOCK + threadIdx.x; g < total; g += gridDim.x * BLOCK) {
+    // the list holding entry g: largest b with off[b] <= g
+    int lo = 0, hi = nlists - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const long long c = band[(long long)lo * cap + (g - off[lo])];
     const double a = alpha[c];
     double m = 0.0;
     int hit = -1;
@@ -718,9 +747,15 @@ void launch_interface(const DevParams& P, const double* alpha, const double* T, 
                       const double* u, const double* v, const double* w, double* mraw, int* adj, int* band,
                       int* band_count, double* partials, unsigned* counter, double* scal, hipStream_t s) {
   const int nb = grid_blocks(P.n);
+  const long long cap = ((P.n + nb - 1) / nb + BLOCK - 1) / BLOCK * BLOCK;
+  int* off = band_count + MAX_BLOCKS;   // nb + 1 offsets after the counts
   k_interface_scan<<<nb, BLOCK, 0, s>>>(P, alpha, mraw, adj, band, band_count);
-  k_interface<<<nb, BLOCK, 0, s>>>(P, alpha, T, omega, u, v, w, band, band_count, mraw, adj, partials, counter, scal);
+  k_band_offsets<<<1, 1024, 0, s>>>(band_count, nb, off);
+  const int nbi = std::max(NXCD, nb / 8);
+  k_interface<<<nbi, BLOCK, 0, s>>>(P, alpha, T, omega, u, v, w, band, off, nb, cap, mraw, adj, partials, counter,
+                                    scal);
 }
+// band_count holds MAX_BLOCKS counts, then MAX_BLOCKS + 1 offsets.
 long long interface_band_capacity(long long n) {
   const int nb = grid_blocks(n);
   const long long cap = ((n + nb - 1) / nb + BLOCK - 1) / BLOCK * BLOCK;
