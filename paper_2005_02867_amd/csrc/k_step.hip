@@ -629,38 +629,50 @@ __global__ void k_div_setup(DevParams P, const double* __restrict__ u, const dou
 }
 
 // ---------------------------------------------------------------- S11
+// Projected velocity on the face (i, j, k) normal to axis AX, indices in that
+// face array (extent +1 along AX).
 template <int AX>
+__device__ __forceinline__ double project_face(const DevParams& P, const double* __restrict__ a_new,
+                                               const double* __restrict__ p, const double* __restrict__ Fs, int i,
+                                               int j, int k) {
+  const int fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
+  const long long e = ((long long)i * fy + j) * fz + k;
+  const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
+  const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
+  const double us = Fs[e];
+  if (fpos == 0 || fpos == nax) {
+    const int side = fpos == 0 ? 0 : 1;
+    if (!pressure_dirichlet(P.kind[AX * 2 + side])) return us;
+    const int ic = AX == 0 ? (side ? i - 1 : i) : i;
+    const int jc = AX == 1 ? (side ? j - 1 : j) : j;
+    const int kc = AX == 2 ? (side ? k - 1 : k) : k;
+    const long long c = cidx(P, ic, jc, kc);
+    const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, P.rho_G);
+    return side ? us + 2.0 * P.dt * beta * p[c] / P.h : us - 2.0 * P.dt * beta * p[c] / P.h;
+  }
+  const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
+  const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
+  const double bL = 1.0 / mix(clamp01(a_new[cL]), P.rho_L, P.rho_G);
+  const double bR = 1.0 / mix(clamp01(a_new[cR]), P.rho_L, P.rho_G);
+  return us - P.dt * 0.5 * (bL + bR) * (p[cR] - p[cL]) / P.h;
+}
+
+// All three face arrays in one pass over the cells (as the predictor).
 __global__ void k_project(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
-                          const double* __restrict__ Fs, double* __restrict__ F) {
-  const int fx = P.nx + (AX == 0), fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
-  const long long nf = (long long)fx * fy * fz;
+                          const double* __restrict__ us, const double* __restrict__ vs,
+                          const double* __restrict__ ws, double* __restrict__ u, double* __restrict__ v,
+                          double* __restrict__ w) {
   long long b0, b1;
-  block_range(nf, b0, b1);
-  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+  block_range(P.n, b0, b1);
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
-    decode3(e, fy, fz, i, j, k);
-    const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
-    const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
-    const double us = Fs[e];
-    if (fpos == 0 || fpos == nax) {
-      const int side = fpos == 0 ? 0 : 1;
-      if (!pressure_dirichlet(P.kind[AX * 2 + side])) {
-        F[e] = us;
-      } else {
-        const int ic = AX == 0 ? (side ? i - 1 : i) : i;
-        const int jc = AX == 1 ? (side ? j - 1 : j) : j;
-        const int kc = AX == 2 ? (side ? k - 1 : k) : k;
-        const long long c = cidx(P, ic, jc, kc);
-        const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, P.rho_G);
-        F[e] = side ? us + 2.0 * P.dt * beta * p[c] / P.h : us - 2.0 * P.dt * beta * p[c] / P.h;
-      }
-      continue;
-    }
-    const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
-    const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
-    const double bL = 1.0 / mix(clamp01(a_new[cL]), P.rho_L, P.rho_G);
-    const double bR = 1.0 / mix(clamp01(a_new[cR]), P.rho_L, P.rho_G);
-    F[e] = us - P.dt * 0.5 * (bL + bR) * (p[cR] - p[cL]) / P.h;
+    decode(P, c, i, j, k);
+    u[uidx(P, i, j, k)] = project_face<0>(P, a_new, p, us, i, j, k);
+    v[vidx(P, i, j, k)] = project_face<1>(P, a_new, p, vs, i, j, k);
+    w[widx(P, i, j, k)] = project_face<2>(P, a_new, p, ws, i, j, k);
+    if (i == P.nx - 1) u[uidx(P, P.nx, j, k)] = project_face<0>(P, a_new, p, us, P.nx, j, k);
+    if (j == P.ny - 1) v[vidx(P, i, P.ny, k)] = project_face<1>(P, a_new, p, vs, i, P.ny, k);
+    if (k == P.nz - 1) w[widx(P, i, j, P.nz)] = project_face<2>(P, a_new, p, ws, i, j, P.nz);
   }
 }
 
@@ -805,11 +817,7 @@ void launch_div_setup(const DevParams& P, const double* u, const double* v, cons
 void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
                     const double* vs, const double* ws, double* u, double* v, double* w,
                     hipStream_t s) {
-  const long long nu = (long long)(P.nx + 1) * P.ny * P.nz, nv = (long long)P.nx * (P.ny + 1) * P.nz,
-                  nw = (long long)P.nx * P.ny * (P.nz + 1);
-  k_project<0><<<grid_blocks(nu), BLOCK, 0, s>>>(P, a_new, p, us, u);
-  k_project<1><<<grid_blocks(nv), BLOCK, 0, s>>>(P, a_new, p, vs, v);
-  k_project<2><<<grid_blocks(nw), BLOCK, 0, s>>>(P, a_new, p, ws, w);
+  k_project<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, p, us, vs, ws, u, v, w);
 }
 void launch_diagnostics(const DevParams& P, const double* alpha, const double* c, const double* T,
                         const double* p, const double* mdot, double* partials, unsigned* counter,
