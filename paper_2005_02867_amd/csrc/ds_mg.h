@@ -89,12 +89,10 @@ template <class T>
 void launch_mg_diag(const Lev<T>& L, int dirmask, T* dout, hipStream_t s);
 
 // Enqueue the start of a solve whose residual is already in V.r (and whose
-// status holds bnorm): z = M^-1 r, rz = <r, z>.  Then iterations.  With
-// keep_direction (a residual replacement inside a running solve), also
-// beta = rz_new/rz_old, so the next iteration continues the direction in V.p.
+// status holds bnorm): z = M^-1 r, rz = <r, z>.  Then iterations.
 template <class T>
 void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
-              unsigned* counters, hipStream_t s, bool keep_direction = false);
+              unsigned* counters, hipStream_t s);
 // ev0/ev1 (may be null): events recorded just before and after the operator
 // kernel (direction update + matrix-free product) of a multigrid iteration.
 template <class T>

@@ -1556,8 +1556,8 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
 
 template <class T>
 void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
-              unsigned* counters, hipStream_t s, bool keep_direction) {
-  const int first = keep_direction ? 0 : 1;
+              unsigned* counters, hipStream_t s) {
+  const int first = 1;
   if (H) {
     mg_vcycle(*H, 0, V.r, st, partials, counters + 2, first != 0, true, s, z);
   } else {
@@ -1743,9 +1743,9 @@ template void launch_mg_diag<float>(const Lev<float>&, int, float*, hipStream_t)
 template void mg_setup_levels<double>(MgHier<double>&, int, hipStream_t);
 template void mg_setup_levels<float>(MgHier<float>&, int, hipStream_t);
 template void cg_start<double>(const Lev<double>&, MgHier<double>*, CgVecs<double>&, double**, SolveStatus*,
-                               double*, unsigned*, hipStream_t, bool);
+                               double*, unsigned*, hipStream_t);
 template void cg_start<float>(const Lev<float>&, MgHier<float>*, CgVecs<float>&, float**, SolveStatus*, double*,
-                              unsigned*, hipStream_t, bool);
+                              unsigned*, hipStream_t);
 template void cg_iteration<double>(const Lev<double>&, MgHier<double>*, CgVecs<double>&, double**, SolveStatus*,
                                    double*, unsigned*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void cg_iteration<float>(const Lev<float>&, MgHier<float>*, CgVecs<float>&, float**, SolveStatus*,
