@@ -478,14 +478,19 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     const double floor = H || sys == 2 ? g->tune.inner_min : g->tune.inner_min_jac;
     const double inner_tol = std::min(0.5, std::max(floor, need));
     if ((st = init_status(g, 3, inner_tol, g->prm.maxit, s)) != DS_OK) return st;
-    launch_inner_init<float>(F, g->r, g->r32, g->e32, si, g->partials, g->counters + CT_SOLVE1, s);
     g->h_status[3].it = 0;
     g->h_status[3].done = 0;
     CgVecs<float> V{g->e32, g->r32, g->p32, g->p32alt, g->q32, H ? nullptr : g->zj32};
     float* const p_odd = V.p_alt;   // direction of odd iterations (for the deferred x update)
     float* const p_even = V.p;
     float* z = nullptr;
-    cg_start(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, s);
+    // Jacobi rounds on vectorised levels: conversion, z = r/diag and both
+    // dot products in one pass; otherwise the conversion, then cg_start
+    if (H || !launch_inner_init_jac<float>(F, g->r, g->r32, g->e32, g->zj32, si, g->partials,
+                                          g->counters + CT_SOLVE1, s)) {
+      launch_inner_init<float>(F, g->r, g->r32, g->e32, si, g->partials, g->counters + CT_SOLVE1, s);
+      cg_start(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, s);
+    }
     bool first = true;
     const bool timed = g->timing && H;
     do {
@@ -501,11 +506,12 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
       if ((st = sync_status(g, 3, s)) != DS_OK) return st;
       if (timed) accumulate_timing(g, g->h_status[3].it - it0, 24.0 * (double)g->n);
     } while (!g->h_status[3].done);
+    // x += e, with the inner solve's last deferred e += alpha p folded in
     const int it = g->h_status[3].it;
-    if (it > 0 && cg_defers_x(F)) launch_axpy_alpha(g->e32, (it & 1) ? p_odd : p_even, si, g->n, s);
+    const float* p_last = (it > 0 && cg_defers_x(F)) ? ((it & 1) ? p_odd : p_even) : nullptr;
     total += g->h_status[3].it;
     inner_fail = g->h_status[3].done == 2;
-    launch_add_correction<float>(F, x, g->e32, s);
+    launch_add_correction<float>(F, x, g->e32, s, p_last, si);
     launch_resid64(L, g->b, x, g->r, so, g->partials, g->counters + CT_SOLVE0, false, s);
     HIPCHK(g, hipGetLastError());
     if ((st = sync_status(g, sys, s)) != DS_OK) return st;

@@ -142,8 +142,16 @@ void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipSt
 template <class T>
 void launch_inner_init(const Lev<T>& L, const double* r64, T* r, T* x, SolveStatus* st, double* partials,
                        unsigned* counter, hipStream_t s);
+// x += e (FP64 x, FP32 e); with p (may be null) first e += st->alpha p.
 template <class T>
-void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s);
+void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s, const T* p = nullptr,
+                           const SolveStatus* st = nullptr);
+// Start of a Jacobi-preconditioned round in one pass: r = (T) r64, x = 0,
+// z = r/diag, status (||r||, <r, z>).  False (nothing launched) off the
+// vectorised levels.
+template <class T>
+bool launch_inner_init_jac(const Lev<T>& L, const double* r64, T* r, T* x, T* z, SolveStatus* st, double* partials,
+                           unsigned* counter, hipStream_t s);
 void launch_to_float(const double* a, float* b, long long n, hipStream_t s);
 
 }  // namespace dsv

@@ -1022,6 +1022,45 @@ VEC_KERNEL k_inner_init_v(Lev<T> L, const double* __restrict__ r64, T* __restric
   }
 }
 
+// k_inner_init_v and k_jac_rz_v in one pass (a Jacobi-preconditioned round
+// of the precision form): r = (T) r64, x = 0, z = r/diag; ||r||^2 and <r, z>.
+template <class T>
+VEC_KERNEL k_inner_init_jac_v(Lev<T> L, const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ x,
+                              T* __restrict__ zout, SolveStatus* st, double* partials, unsigned* counter) {
+  constexpr int V = VW<T>::n;
+  double acc[2] = {0.0, 0.0};
+  FOR_ITEMS(L, T, i, j, kv, c) {
+    T rv[V], xv[V], dv[V], zv[V];
+    ldv<T>(at(L.diag, c), dv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      rv[v] = (T)*at(r64, c + v);
+      xv[v] = 0;
+      acc[0] += (double)rv[v] * (double)rv[v];
+      acc[1] += (double)rv[v] * (double)rv[v] / (double)dv[v];
+      zv[v] = rv[v] / dv[v];
+    }
+    stv<T>(at(r, c), rv);
+    stv<T>(at(x, c), xv);
+    stv<T>(at(zout, c), zv);
+  }
+  const int ops[2] = {RSUM, RSUM};
+  if (block_reduce_publish<2>(acc, ops, partials, counter)) {
+    double t[2];
+    block_combine<2>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      st->bb = t[0];
+      st->bnorm = sqrt(t[0]);
+      st->rr = t[0];
+      st->res = t[0] == 0.0 ? 0.0 : 1.0;
+      st->it = 0;
+      st->zero = t[0] == 0.0;
+      st->done = t[0] == 0.0 ? 1 : 0;
+      st->rz = t[1];
+    }
+  }
+}
+
 template <class T>
 VEC_KERNEL k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
                            int first, T* __restrict__ zout) {
@@ -1267,12 +1306,21 @@ void launch_axpy_alpha(T* x, const T* p, const SolveStatus* st, long long n, hip
 template void launch_axpy_alpha<double>(double*, const double*, const SolveStatus*, long long, hipStream_t);
 template void launch_axpy_alpha<float>(float*, const float*, const SolveStatus*, long long, hipStream_t);
 
+// x += e; with p, first e += alpha p (the inner solve's last deferred update,
+// alpha from st), as launch_axpy_alpha followed by the plain correction.
 template <class T>
-VEC_KERNEL k_add_correction_v(Lev<T> L, double* __restrict__ x, const T* __restrict__ e) {
+VEC_KERNEL k_add_correction_v(Lev<T> L, double* __restrict__ x, const T* __restrict__ e, const T* __restrict__ p,
+                              const SolveStatus* st) {
   constexpr int V = VW<T>::n;
+  const T a = p ? (T)st->alpha : T(0);
   FOR_ITEMS(L, T, i, j, kv, c) {
-    T ev[V];
+    T ev[V], pv[V];
     ldv<T>(at(e, c), ev);
+    if (p) {
+      ldv<T>(at(p, c), pv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) ev[v] += a * pv[v];
+    }
 #pragma unroll
     for (int v = 0; v < V; ++v) *at(x, c + v) += (double)ev[v];
   }
@@ -1695,10 +1743,24 @@ void launch_inner_init(const Lev<T>& L, const double* r64, T* r, T* x, SolveStat
   else k_inner_init<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, r64, r, x, st, partials, counter);
 }
 template <class T>
-void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s) {
-  if (use_vec(L)) k_add_correction_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, x, e);
-  else k_add_correction<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, x, e);
+void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s, const T* p,
+                           const SolveStatus* st) {
+  if (use_vec(L)) {
+    k_add_correction_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, x, e, p, st);
+  } else {
+    if (p) launch_axpy_alpha<T>(const_cast<T*>(e), p, st, L.n, s);
+    k_add_correction<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, x, e);
+  }
 }
+template <class T>
+bool launch_inner_init_jac(const Lev<T>& L, const double* r64, T* r, T* x, T* z, SolveStatus* st, double* partials,
+                           unsigned* counter, hipStream_t s) {
+  if (!use_vec(L)) return false;
+  k_inner_init_jac_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, r64, r, x, z, st, partials, counter);
+  return true;
+}
+template bool launch_inner_init_jac<float>(const Lev<float>&, const double*, float*, float*, float*, SolveStatus*,
+                                           double*, unsigned*, hipStream_t);
 void launch_to_float(const double* a, float* b, long long n, hipStream_t s) {
   k_to_float<<<grid_blocks(n), BLOCK, 0, s>>>(a, b, n);
 }
@@ -1752,6 +1814,7 @@ template void cg_iteration<float>(const Lev<float>&, MgHier<float>*, CgVecs<floa
                                   double*, unsigned*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_inner_init<float>(const Lev<float>&, const double*, float*, float*, SolveStatus*, double*,
                                        unsigned*, hipStream_t);
-template void launch_add_correction<float>(const Lev<float>&, double*, const float*, hipStream_t);
+template void launch_add_correction<float>(const Lev<float>&, double*, const float*, hipStream_t, const float*,
+                                          const SolveStatus*);
 
 }  // namespace dsv
