@@ -549,7 +549,7 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   mg_setup_levels(H, g->dirmask, s);
   SolveStatus* ss = g->status + sys;
   if ((st = init_status(g, sys, tol, g->prm.maxit, s)) != DS_OK) return st;
-  launch_resid64(L, g->b, x, g->r, ss, g->partials, g->counters + CT_SOLVE0, true, s);
+  launch_resid64(L, g->b, x, g->r, ss, g->partials, g->counters + CT_SOLVE0, true, s, g->r32);
   launch_zero_if_flagged(x, g->n, ss, s);
   HIPCHK(g, hipGetLastError());
   if ((st = sync_status(g, sys, s)) != DS_OK) return st;
@@ -559,7 +559,7 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
     double* const p_odd = V.p_alt;
     double* const p_even = V.p;
     float* z = nullptr;
-    cg_start_mg32(L, H, g->r, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, s);
+    cg_start_mg32(L, H, g->r, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, s, true);
     bool first = true;
     while (!g->h_status[sys].done) {
       const int m = batch_size(batch_of(g, sys, x), first);

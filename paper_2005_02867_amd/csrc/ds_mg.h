@@ -121,8 +121,9 @@ void set_march_min_planes(int n);
 double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1);
+// r32_ready: r32 already holds r64 in FP32 (launch_resid64 wrote it).
 void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, float* r32, float** z, SolveStatus* st,
-                   double* partials, unsigned* counters, hipStream_t s);
+                   double* partials, unsigned* counters, hipStream_t s, bool r32_ready = false);
 // The iteration's solution update is deferred: iteration t applies
 // x += alpha_{t-1} p_{t-1}; after the last iteration t = it, launch_axpy_alpha
 // with the direction buffer of that iteration applies alpha_it p_it.
@@ -136,8 +137,9 @@ template <class T>
 bool cg_defers_x(const Lev<T>& L);
 
 // r = b - A x (FP64), ||b|| (if set_bnorm), ||r|| -> status (done if ||r|| <= tol ||b||).
+// r32 (may be null): also store r in FP32.
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
-                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s);
+                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s, float* r32 = nullptr);
 void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s);
 template <class T>
 void launch_inner_init(const Lev<T>& L, const double* r64, T* r, T* x, SolveStatus* st, double* partials,

@@ -953,9 +953,11 @@ VEC_KERNEL k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, co
   if (DOT) publish_rz(acc, st, partials, counter, first);
 }
 
+// r32 (may be null): also r in FP32 (the V-cycle's input at the start of a
+// solve in the FP32-multigrid form).
 VEC_KERNEL k_resid64_v(Lev<double> L, const double* __restrict__ b, const double* __restrict__ x,
-                            double* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter,
-                            int set_bnorm) {
+                       double* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter, int set_bnorm,
+                       float* __restrict__ r32) {
   constexpr int V = VW<double>::n;
   double acc[2] = {0.0, 0.0};
   march<double>(
@@ -971,6 +973,12 @@ VEC_KERNEL k_resid64_v(Lev<double> L, const double* __restrict__ b, const double
           acc[1] += o[v] * o[v];
         }
         stv<double>(at(r, c), o);
+        if (r32) {
+          float2 rf;
+          rf.x = (float)o[0];
+          rf.y = (float)o[1];
+          *reinterpret_cast<float2*>(at(r32, c)) = rf;
+        }
       });
   const int ops[2] = {RSUM, RSUM};
   if (block_reduce_publish<2>(acc, ops, partials, counter)) {
@@ -1726,12 +1734,14 @@ template double replay_operator_kernel<float>(const Lev<float>&, const float*, c
                                               hipEvent_t);
 
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
-                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s) {
-  if (use_vec(L))
+                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s, float* r32) {
+  if (use_vec(L)) {
     k_resid64_v<<<march_blocks(march_lev(L)), BLOCK, 0, s>>>(march_lev(L), b, x, r, st, partials, counter,
-                                                            set_bnorm ? 1 : 0);
-  else
+                                                            set_bnorm ? 1 : 0, r32);
+  } else {
     k_resid64<<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);
+    if (r32) k_to_float<<<grid_blocks(L.n), BLOCK, 0, s>>>(r, r32, L.n);
+  }
 }
 void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s) {
   k_zero_if_flagged<<<grid_blocks(n), BLOCK, 0, s>>>(x, n, st);
@@ -1767,8 +1777,8 @@ void launch_to_float(const double* a, float* b, long long n, hipStream_t s) {
 
 // FP64 CG preconditioned by the FP32 V-cycle (levels whose nz is even).
 void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, float* r32, float** z, SolveStatus* st,
-                   double* partials, unsigned* counters, hipStream_t s) {
-  k_to_float<<<grid_blocks(L.n), BLOCK, 0, s>>>(r64, r32, L.n);
+                   double* partials, unsigned* counters, hipStream_t s, bool r32_ready) {
+  if (!r32_ready) k_to_float<<<grid_blocks(L.n), BLOCK, 0, s>>>(r64, r32, L.n);
   mg_vcycle(H, 0, r32, st, partials, counters + 2, true, true, s, z);
 }
 void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V, float* r32, float** z,
