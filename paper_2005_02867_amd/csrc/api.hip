@@ -920,6 +920,18 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_VEC_YTILE")) g_vec_ytile = atoi(e);
   if (const char* e = getenv("DSVOF_MARCH_THREADS")) set_march_threads(atoi(e));
   if (const char* e = getenv("DSVOF_MARCH_MIN_PLANES")) set_march_min_planes(atoi(e));
+  for (int cls = 0; cls < 2; ++cls) {
+    // DSVOF_MARCH_NT0 / DSVOF_MARCH_NT1: comma-separated block sizes, e.g. "512,256,384"
+    const char* e = getenv(cls ? "DSVOF_MARCH_NT1" : "DSVOF_MARCH_NT0");
+    if (!e) continue;
+    int nts[3], n = 0;
+    for (const char* c = e; *c && n < 3;) {
+      nts[n++] = atoi(c);
+      while (*c && *c != ',') ++c;
+      if (*c == ',') ++c;
+    }
+    set_march_pref(cls, nts, n);
+  }
   lev_dims(g->L0, nx, ny, nz, 1.0);
   if (const char* e = getenv("DSVOF_INNER_MIN")) g->tune.inner_min = atof(e);
   if (const char* e = getenv("DSVOF_INNER_MIN_JAC")) g->tune.inner_min_jac = atof(e);

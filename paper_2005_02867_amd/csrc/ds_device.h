@@ -120,10 +120,10 @@ enum RedOp { RSUM = 0, RMIN = 1, RMAX = 2 };
 // the L2 (the kernel's streamed outputs), which costs tens of microseconds per
 // block.  The last block reads nothing else that this launch wrote; the
 // outputs reach later kernels through the launch boundary.
-template <int NV>
+template <int NV, int NT = BLOCK>
 __device__ bool block_reduce_publish(double (&v)[NV], const int (&ops)[NV], double* partials,
                                      unsigned* counter) {
-  __shared__ double sh[BLOCK / 64][NV];
+  __shared__ double sh[NT / 64][NV];
   __shared__ bool last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -136,7 +136,7 @@ __device__ bool block_reduce_publish(double (&v)[NV], const int (&ops)[NV], doub
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       double x = sh[0][q];
-      for (int w = 1; w < BLOCK / 64; ++w)
+      for (int w = 1; w < NT / 64; ++w)
         x = ops[q] == RSUM ? x + sh[w][q] : (ops[q] == RMIN ? fmin(x, sh[w][q]) : fmax(x, sh[w][q]));
       __hip_atomic_store(&partials[(size_t)blockIdx.x * NV + q], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -148,24 +148,39 @@ __device__ bool block_reduce_publish(double (&v)[NV], const int (&ops)[NV], doub
   return last;
 }
 
+constexpr int pow2_floor(int n) { return n <= 1 ? 1 : 2 * pow2_floor(n / 2); }
+
 // In the last block: combine all partials (fixed order), result in out[q]
 // (valid in every thread).  Resets the counter.
-template <int NV>
+template <int NV, int NT = BLOCK>
 __device__ void block_combine(const int (&ops)[NV], const double* partials, unsigned* counter,
                               double (&out)[NV]) {
-  __shared__ double sh[BLOCK][NV];
+  __shared__ double sh[NT][NV];
   const int nb = gridDim.x;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     double x = ops[q] == RSUM ? 0.0 : (ops[q] == RMIN ? __builtin_inf() : -__builtin_inf());
-    for (int b = threadIdx.x; b < nb; b += BLOCK) {
+    for (int b = threadIdx.x; b < nb; b += NT) {
       double y = __hip_atomic_load(&partials[(size_t)b * NV + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       x = ops[q] == RSUM ? x + y : (ops[q] == RMIN ? fmin(x, y) : fmax(x, y));
     }
     sh[threadIdx.x][q] = x;
   }
   __syncthreads();
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+  // tree over the largest power of two P2 <= NT; the threads past P2 (NT =
+  // 384: 128 of them) are folded in first
+  constexpr int P2 = pow2_floor(NT);
+  if (P2 < NT) {
+    if (threadIdx.x < NT - P2) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        double a = sh[threadIdx.x][q], b = sh[threadIdx.x + P2][q];
+        sh[threadIdx.x][q] = ops[q] == RSUM ? a + b : (ops[q] == RMIN ? fmin(a, b) : fmax(a, b));
+      }
+    }
+    __syncthreads();
+  }
+  for (int s = P2 / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
 #pragma unroll
       for (int q = 0; q < NV; ++q) {

@@ -27,6 +27,7 @@ struct Lev {
   int nx, ny, nz;
   int ytile;
   int mch;     // chunks of x-planes per column in the marching kernels (set by the launcher)
+  int mnt;     // threads per block of the marching kernels (set by the launcher)
   int dfly;    // 1: the marching kernels form diag from qc (pressure-type operator) instead of loading it
   int dmask;   // with dfly: bit (axis*2 + side) set where the box face is p = 0 (Dirichlet)
   int ntk, ntj;
@@ -44,6 +45,7 @@ inline void lev_dims(Lev<T>& L, int nx, int ny, int nz, double sc) {
   L.nz = nz;
   L.ytile = (g_vec_ytile > 0 && ny % g_vec_ytile == 0) ? g_vec_ytile : ny;
   L.mch = 1;
+  L.mnt = 256;
   L.dfly = 0;
   L.dmask = 0;
   L.ntk = (nz + TK - 1) / TK;
@@ -118,6 +120,9 @@ void set_vec_max_blocks(int nb);
 void set_march_threads(int n);
 // Shortest chunk of x-planes a marching thread walks.
 void set_march_min_planes(int n);
+// Block sizes (256, 384, 512) the marching kernels of class cls try in order
+// (0: CG operator and FP64 residual, 1: V-cycle sweeps and restriction).
+void set_march_pref(int cls, const int* nts, int n);
 double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1);

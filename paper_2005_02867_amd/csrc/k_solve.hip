@@ -130,13 +130,14 @@ __global__ void k_mg_smooth_zero(Lev<T> L, const T* __restrict__ r, T* __restric
 }
 
 // Publish <r, z> of the preconditioned residual: beta = rz_new/rz (unless first).
+template <int NT = BLOCK>
 __device__ __forceinline__ void publish_rz(double acc0, SolveStatus* st, double* partials, unsigned* counter,
                                            int first) {
   double acc[1] = {acc0};
   const int ops[1] = {RSUM};
-  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+  if (block_reduce_publish<1, NT>(acc, ops, partials, counter)) {
     double t[1];
-    block_combine<1>(ops, partials, counter, t);
+    block_combine<1, NT>(ops, partials, counter, t);
     if (threadIdx.x == 0) {
       if (!first) st->beta = t[0] / st->rz;
       st->rz = t[0];
@@ -471,6 +472,11 @@ __device__ __forceinline__ const T* at(const T* p, unsigned e) {
 // SIMD: the compiler may use up to 128 VGPRs and keep every load of an item
 // in flight before the first wait.
 #define VEC_KERNEL __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 4)))
+// The marching kernels take their block size NT (256, 384 or 512 threads) as
+// a template parameter, chosen per level so that a block holds whole z-rows
+// (see march_lev): 384 fits rows of 24, 48, 96 or 192 vectors, 512 gives 256-
+// cell FP32 rows eight rows per block.
+#define VEC_KERNEL_M __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
 
 // Vectorised kernels: nz a multiple of the vector width and every array
 // (FP64 ones included) below 4 GiB, so 32-bit byte offsets address it.
@@ -578,8 +584,33 @@ int g_march_threads = 262144;
 int g_march_min_planes = 1;
 void set_march_threads(int n) { g_march_threads = std::max(n, BLOCK); }
 void set_march_min_planes(int n) { g_march_min_planes = std::max(n, 1); }
+// Block sizes tried in order, per kernel class (0: CG operator and FP64
+// residual, 1: V-cycle sweeps and restriction); the first that holds whole
+// z-rows of the level (every chunk's rows filling whole blocks) is taken,
+// else 256 without row sharing.  Entries: 256, 384, 512; 0 ends the list.
+int g_march_pref[2][4] = {{512, 256, 384, 0}, {256, 512, 384, 0}};
+void set_march_pref(int cls, const int* nts, int n) {
+  if (cls < 0 || cls > 1) return;
+  int k = 0;
+  for (int t = 0; t < n && k < 3; ++t)
+    if (nts[t] == 256 || nts[t] == 384 || nts[t] == 512) g_march_pref[cls][k++] = nts[t];
+  if (k == 0) g_march_pref[cls][k++] = 256;
+  for (; k < 4; ++k) g_march_pref[cls][k] = 0;
+}
+// Block size of the level for class cls; pairs: also whole row pairs per
+// block (the marching restriction).  0 when pairs is asked and none fits.
 template <class T>
-inline Lev<T> march_lev(Lev<T> L) {
+inline int march_nt(const Lev<T>& L, int cls, bool pairs) {
+  const long long nzv = L.nz / VW<T>::n, rows = (long long)L.ny * nzv;
+  for (int t = 0; t < 4 && g_march_pref[cls][t]; ++t) {
+    const int nt = g_march_pref[cls][t];
+    if (nt % nzv == 0 && rows % nt == 0 && (!pairs || ((nt / nzv) % 2 == 0))) return nt;
+  }
+  return pairs ? 0 : 256;
+}
+template <class T>
+inline Lev<T> march_lev(Lev<T> L, int cls = 0) {
+  L.mnt = march_nt(L, cls, false);
   const long long ncol = (long long)L.ny * (L.nz / VW<T>::n);
   const long long nch =
       std::min<long long>(std::max<long long>(((long long)g_march_threads + ncol - 1) / ncol, 1), L.nx);
@@ -593,7 +624,7 @@ inline Lev<T> march_lev(Lev<T> L) {
 template <class T>
 inline int march_blocks(const Lev<T>& L) {
   const long long nt = (long long)L.ny * (L.nz / VW<T>::n) * L.mch;
-  const long long nb = std::min<long long>(std::max<long long>((nt + BLOCK - 1) / BLOCK, NXCD), 4096);
+  const long long nb = std::min<long long>(std::max<long long>((nt + L.mnt - 1) / L.mnt, NXCD), 4096);
   return (int)((nb + NXCD - 1) / NXCD * NXCD);
 }
 
@@ -611,7 +642,7 @@ __device__ __forceinline__ T lane_down(T v) { return __shfl_down(v, 1, 64); } //
 // (chunk, j, kv), kv fastest; a grid-stride loop covers them (the stride is a
 // multiple of 64, so a wave's lanes always hold consecutive items).  Threads
 // past the end do nothing and return normally (block reductions follow).
-template <class T, class LX, class SX, class BODY>
+template <class T, int NT, class LX, class SX, class BODY>
 __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) {
   constexpr int V = VW<T>::n;
   const unsigned nzv = (unsigned)L.nz / V, ny = (unsigned)L.ny, nx = (unsigned)L.nx;
@@ -621,18 +652,18 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
   const unsigned P = ny * (unsigned)L.nz, sy = (unsigned)L.nz;
   const int lane = threadIdx.x & 63;
   // Rows shared through LDS: when a block holds whole rows of one chunk
-  // (nzv divides BLOCK and every chunk's rows fill whole blocks), a thread's
+  // (nzv divides NT and every chunk's rows fill whole blocks), a thread's
   // y neighbours inside the block are the threads nzv before and after it;
   // each step they publish their (q, X) of the current plane in LDS (double
   // buffered by step parity, one barrier per step) and only the block's
   // first and last rows load their outer neighbour.  All threads of a block
   // then run the same steps, so the barriers are uniform.
-  const bool coop = (BLOCK % nzv == 0) && ((ny * nzv) % BLOCK == 0);
-  __shared__ T lsq[2][BLOCK * V], lsx[2][BLOCK * V];
+  const bool coop = (NT % nzv == 0) && ((ny * nzv) % NT == 0);
+  __shared__ T lsq[2][NT * V], lsx[2][NT * V];
   const int tid = threadIdx.x;
-  const bool inm = coop && tid >= (int)nzv, inp = coop && tid + (int)nzv < BLOCK;
+  const bool inm = coop && tid >= (int)nzv, inp = coop && tid + (int)nzv < NT;
   int par = 0;
-  for (unsigned e = lb * BLOCK + threadIdx.x; e < total; e += gridDim.x * BLOCK) {
+  for (unsigned e = lb * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
   const unsigned kv = e % nzv, t = e / nzv, j = t % ny, ch = t / ny;
   const unsigned i0 = ch * clen, i1 = min(nx, i0 + clen);
   if (i0 >= i1) continue;
@@ -774,8 +805,8 @@ VEC_KERNEL k_mg_smooth_zero_v(Lev<T> L, const T* __restrict__ r, T* __restrict__
 
 // The first two sweeps from x = 0 in one pass: x1 = omega r/diag is formed
 // on the fly (also at the neighbours), x2 = x1 + omega (r - A x1)/diag.
-template <class T>
-VEC_KERNEL k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ xout, T omega,
+template <class T, int NT>
+VEC_KERNEL_M k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ xout, T omega,
                                   const SolveStatus* st) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
@@ -787,7 +818,7 @@ VEC_KERNEL k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ 
     for (int v = 0; v < V; ++v) o[v] = omega * rv[v] / dv[v];
   };
   auto x1s = [&](unsigned f) -> T { return omega * *at(r, f) / *at(L.diag, f); };
-  march<T>(L, x1v, x1s, [&](unsigned c, const T(&qv)[V], const T(&x1)[V], const T(&off)[V], const T(&dv)[V]) {
+  march<T, NT>(L, x1v, x1s, [&](unsigned c, const T(&qv)[V], const T(&x1)[V], const T(&off)[V], const T(&dv)[V]) {
     T rv[V], o[V];
     ldv<T>(at(r, c), rv);
 #pragma unroll
@@ -799,13 +830,13 @@ VEC_KERNEL k_mg_smooth_two_v(Lev<T> L, const T* __restrict__ r, T* __restrict__ 
   });
 }
 
-template <class T, bool DOT>
-VEC_KERNEL k_mg_smooth_v(Lev<T> L, const T* __restrict__ r, const T* __restrict__ xin, T* __restrict__ xout,
+template <class T, bool DOT, int NT>
+VEC_KERNEL_M k_mg_smooth_v(Lev<T> L, const T* __restrict__ r, const T* __restrict__ xin, T* __restrict__ xout,
                               T omega, SolveStatus* st, double* partials, unsigned* counter, int first) {
   if (st->done) return;
   constexpr int V = VW<T>::n;
   double acc = 0.0;
-  march<T>(
+  march<T, NT>(
       L, [&](unsigned f, T(&o)[V]) { ldv<T>(at(xin, f), o); }, [&](unsigned f) { return *at(xin, f); },
       [&](unsigned c, const T(&qv)[V], const T(&xv)[V], const T(&off)[V], const T(&dv)[V]) {
         T rv[V], o[V];
@@ -818,7 +849,7 @@ VEC_KERNEL k_mg_smooth_v(Lev<T> L, const T* __restrict__ r, const T* __restrict_
         }
         stv<T>(at(xout, c), o);
       });
-  if (DOT) publish_rz(acc, st, partials, counter, first);
+  if (DOT) publish_rz<NT>(acc, st, partials, counter, first);
 }
 
 // Coarse residual for VW/2 coarse cells per thread (fine rows of VW cells).
@@ -860,16 +891,16 @@ VEC_KERNEL k_mg_restrict_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T*
 // the thread of row 2J+1 hands its sum through LDS to the thread of row 2J,
 // which writes the coarse cell.  Needs even nx, ny, nz, chunks of an even
 // number of planes and blocks of whole row pairs (restrict_marching_ok).
-template <class T>
-VEC_KERNEL k_mg_restrict_m(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+template <class T, int NT>
+VEC_KERNEL_M k_mg_restrict_m(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
                            T* __restrict__ rc, const SolveStatus* st) {
   if (st->done) return;
   constexpr int V = VW<T>::n, H = V / 2;
-  __shared__ T lsr[BLOCK * H];
+  __shared__ T lsr[NT * H];
   const unsigned nzv = (unsigned)F.nz / V, P = (unsigned)F.ny * (unsigned)F.nz, sy = (unsigned)F.nz;
   const int tid = threadIdx.x;
   T acc[H];
-  march<T>(
+  march<T, NT>(
       F, [&](unsigned f, T(&o)[V]) { ldv<T>(at(x, f), o); }, [&](unsigned f) { return *at(x, f); },
       [&](unsigned c, const T(&qv)[V], const T(&xv)[V], const T(&off)[V], const T(&dv)[V]) {
         T rv[V];
@@ -902,13 +933,14 @@ VEC_KERNEL k_mg_restrict_m(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T*
 template <class T>
 inline bool restrict_marching_ok(const Lev<T>& F) {
   if (!use_vec(F) || (F.nx & 1) || (F.ny & 1) || (F.nz % (2 * VW<T>::n))) return false;
-  const int nzv = F.nz / VW<T>::n;
-  return BLOCK % nzv == 0 && ((BLOCK / nzv) % 2 == 0) && ((long long)F.ny * nzv) % BLOCK == 0;
+  return march_nt(F, 1, true) != 0;
 }
-// march_lev with chunks of an even number of planes (plane pairs stay together).
+// march_lev with chunks of an even number of planes (plane pairs stay
+// together) and a block size of whole row pairs.
 template <class T>
 inline Lev<T> march_lev_pairs(Lev<T> L) {
-  L = march_lev(L);
+  L = march_lev(L, 1);
+  L.mnt = march_nt(L, 1, true);
   long long clen = (L.nx + L.mch - 1) / L.mch;
   clen += clen & 1;
   L.mch = (int)((L.nx + clen - 1) / clen);
@@ -916,8 +948,8 @@ inline Lev<T> march_lev_pairs(Lev<T> L) {
 }
 
 // x' = x + P xc then one sweep (VW fine cells per thread).
-template <class T, bool DOT>
-VEC_KERNEL k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+template <class T, bool DOT, int NT>
+VEC_KERNEL_M k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
                                       const T* __restrict__ xc, T* __restrict__ xout, T omega, SolveStatus* st,
                                       double* partials, unsigned* counter, int first) {
   if (st->done) return;
@@ -939,7 +971,7 @@ VEC_KERNEL k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, co
     const unsigned jj = rr % (unsigned)F.ny, ii = rr / (unsigned)F.ny;
     return *at(x, f) + *at(xc, ((ii >> 1) * (unsigned)C.ny + (jj >> 1)) * (unsigned)C.nz + (kk >> 1));
   };
-  march<T>(F, row, one, [&](unsigned c, const T(&qv)[V], const T(&x0)[V], const T(&off)[V], const T(&dv)[V]) {
+  march<T, NT>(F, row, one, [&](unsigned c, const T(&qv)[V], const T(&x0)[V], const T(&off)[V], const T(&dv)[V]) {
     T rv[V], o[V];
     ldv<T>(at(r, c), rv);
 #pragma unroll
@@ -950,17 +982,18 @@ VEC_KERNEL k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, co
     }
     stv<T>(at(xout, c), o);
   });
-  if (DOT) publish_rz(acc, st, partials, counter, first);
+  if (DOT) publish_rz<NT>(acc, st, partials, counter, first);
 }
 
 // r32 (may be null): also r in FP32 (the V-cycle's input at the start of a
 // solve in the FP32-multigrid form).
-VEC_KERNEL k_resid64_v(Lev<double> L, const double* __restrict__ b, const double* __restrict__ x,
+template <int NT>
+VEC_KERNEL_M k_resid64_v(Lev<double> L, const double* __restrict__ b, const double* __restrict__ x,
                        double* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter, int set_bnorm,
                        float* __restrict__ r32) {
   constexpr int V = VW<double>::n;
   double acc[2] = {0.0, 0.0};
-  march<double>(
+  march<double, NT>(
       L, [&](unsigned f, double(&o)[V]) { ldv<double>(at(x, f), o); }, [&](unsigned f) { return *at(x, f); },
       [&](unsigned c, const double(&qv)[V], const double(&xv)[V], const double(&off)[V], const double(&dg)[V]) {
         double bv[V], o[V];
@@ -981,9 +1014,9 @@ VEC_KERNEL k_resid64_v(Lev<double> L, const double* __restrict__ b, const double
         }
       });
   const int ops[2] = {RSUM, RSUM};
-  if (block_reduce_publish<2>(acc, ops, partials, counter)) {
+  if (block_reduce_publish<2, NT>(acc, ops, partials, counter)) {
     double t[2];
-    block_combine<2>(ops, partials, counter, t);
+    block_combine<2, NT>(ops, partials, counter, t);
     if (threadIdx.x == 0) {
       if (set_bnorm) {
         st->bb = t[0];
@@ -1092,8 +1125,8 @@ VEC_KERNEL k_jac_rz_v(Lev<T> L, const T* __restrict__ r, SolveStatus* st, double
 // FIRST: p = z (the first iteration).  x (may be null): also x += alpha_prev
 // p_old, the previous iteration's deferred solution update (alpha_prev is
 // still in st->alpha when this kernel starts; its last block replaces it).
-template <class T, bool JAC, bool FIRST>
-VEC_KERNEL k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restrict__ r,
+template <class T, bool JAC, bool FIRST, int NT>
+VEC_KERNEL_M k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restrict__ r,
                            const T* __restrict__ pin, T* __restrict__ pout, T* __restrict__ q, SolveStatus* st,
                            double* partials, unsigned* counter, T* __restrict__ x) {
   if (st->done) return;
@@ -1122,7 +1155,7 @@ VEC_KERNEL k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restric
     const T zf = JAC ? *at(r, f) / *at(L.diag, f) : *at(z, f);
     return FIRST ? zf : zf + be * *at(pin, f);
   };
-  march<T>(L, pnv, pns, [&](unsigned c, const T(&qv)[V], const T(&pc)[V], const T(&off)[V], const T(&dv)[V]) {
+  march<T, NT>(L, pnv, pns, [&](unsigned c, const T(&qv)[V], const T(&pc)[V], const T(&off)[V], const T(&dv)[V]) {
     T y[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -1141,16 +1174,24 @@ VEC_KERNEL k_cg_dir_spmv_v(Lev<T> L, const T* __restrict__ z, const T* __restric
     }
   });
   const int ops[1] = {RSUM};
-  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+  if (block_reduce_publish<1, NT>(acc, ops, partials, counter)) {
     double t[1];
-    block_combine<1>(ops, partials, counter, t);
+    block_combine<1, NT>(ops, partials, counter, t);
     if (threadIdx.x == 0) st->alpha = st->rz / t[0];
   }
 }
 
-template <class T, bool JAC>
+template <class T, bool JAC, int NT>
 static auto dir_v(bool first) {
-  return first ? k_cg_dir_spmv_v<T, JAC, true> : k_cg_dir_spmv_v<T, JAC, false>;
+  return first ? k_cg_dir_spmv_v<T, JAC, true, NT> : k_cg_dir_spmv_v<T, JAC, false, NT>;
+}
+
+// Calls f(std::integral_constant<int, NT>) for the level's marching block size.
+template <class F>
+inline void with_nt(int nt, F&& f) {
+  if (nt == 512) f(std::integral_constant<int, 512>{});
+  else if (nt == 384) f(std::integral_constant<int, 384>{});
+  else f(std::integral_constant<int, 256>{});
 }
 
 template <class T, bool JAC>
@@ -1249,8 +1290,8 @@ VEC_KERNEL k_cg_update_r32_v(Lev<double> L, double* __restrict__ r, const double
 // x (may be null): also x += alpha_prev p_old, the previous iteration's
 // solution update (alpha_prev is still in st->alpha when this kernel starts;
 // its last block replaces it).
-template <bool FIRST>
-VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const double* __restrict__ pin,
+template <bool FIRST, int NT>
+VEC_KERNEL_M k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const double* __restrict__ pin,
                                double* __restrict__ pout, double* __restrict__ q, SolveStatus* st,
                                double* partials, unsigned* counter, double* __restrict__ x) {
   if (st->done) return;
@@ -1270,7 +1311,7 @@ VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const
     }
   };
   auto pns = [&](unsigned f) -> double { return FIRST ? (double)*at(z, f) : (double)*at(z, f) + be * *at(pin, f); };
-  march<double>(L, pnv, pns,
+  march<double, NT>(L, pnv, pns,
                 [&](unsigned c, const double(&qv)[V], const double(&pc)[V], const double(&off)[V],
                     const double(&dv)[V]) {
     double y[V];
@@ -1291,9 +1332,9 @@ VEC_KERNEL k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const
     }
   });
   const int ops[1] = {RSUM};
-  if (block_reduce_publish<1>(acc, ops, partials, counter)) {
+  if (block_reduce_publish<1, NT>(acc, ops, partials, counter)) {
     double t[1];
-    block_combine<1>(ops, partials, counter, t);
+    block_combine<1, NT>(ops, partials, counter, t);
     if (threadIdx.x == 0) st->alpha = st->rz / t[0];
   }
 }
@@ -1514,7 +1555,7 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   T* b = H.t[l];
   const bool vec = use_vec(L);
   const int nb = vec ? vec_blocks(vec_items(L)) : tile_blocks(L.ntiles);
-  const Lev<T> M = vec ? march_lev(L) : L;   // the marching kernels' view and grid
+  const Lev<T> M = vec ? march_lev(L, 1) : L;   // the marching kernels' view and grid
   const int nbm = vec ? march_blocks(M) : nb;
   const bool coarsest = (l == H.nlev - 1);
   const int nu = l == 0 ? H.nu_fine : H.nu;
@@ -1549,8 +1590,11 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   }
   auto smooth = [&](bool d, int df) {
     if (vec) {
-      if (d) k_mg_smooth_v<T, true><<<nbm, BLOCK, 0, s>>>(M, r, a, b, om, st, partials, counter, df);
-      else k_mg_smooth_v<T, false><<<nbm, BLOCK, 0, s>>>(M, r, a, b, om, st, partials, counter, 0);
+      with_nt(M.mnt, [&](auto C) {
+        constexpr int NT = decltype(C)::value;
+        if (d) k_mg_smooth_v<T, true, NT><<<nbm, NT, 0, s>>>(M, r, a, b, om, st, partials, counter, df);
+        else k_mg_smooth_v<T, false, NT><<<nbm, NT, 0, s>>>(M, r, a, b, om, st, partials, counter, 0);
+      });
     } else {
       if (d) k_mg_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, df);
       else k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
@@ -1564,7 +1608,10 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   }
   int t0 = 1;
   if (vec && pre >= 2 && !(coarsest && dot && pre == 2)) {
-    k_mg_smooth_two_v<T><<<nbm, BLOCK, 0, s>>>(M, r, a, om, st);
+    with_nt(M.mnt, [&](auto C) {
+      constexpr int NT = decltype(C)::value;
+      k_mg_smooth_two_v<T, NT><<<nbm, NT, 0, s>>>(M, r, a, om, st);
+    });
     t0 = 2;
   } else if (vec) {
     k_mg_smooth_zero_v<T><<<nb, BLOCK, 0, s>>>(L, r, a, om, st);
@@ -1582,7 +1629,10 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
   const Lev<T>& C = H.lev[l + 1];
   if (vec && restrict_marching_ok(L)) {
     const Lev<T> Mp = march_lev_pairs(L);
-    k_mg_restrict_m<T><<<march_blocks(Mp), BLOCK, 0, s>>>(Mp, C, r, a, H.r[l + 1], st);
+    with_nt(Mp.mnt, [&](auto K) {
+      constexpr int NT = decltype(K)::value;
+      k_mg_restrict_m<T, NT><<<march_blocks(Mp), NT, 0, s>>>(Mp, C, r, a, H.r[l + 1], st);
+    });
   } else if (vec) {
     Lev<T> G = C;
     G.nz = L.nz;
@@ -1596,8 +1646,13 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
     const bool d = dot && t == nu - 1;
     if (t == 0) {
       if (vec) {
-        if (d) k_mg_prolong_smooth_v<T, true><<<nbm, BLOCK, 0, s>>>(M, C, r, a, xc, b, om, st, partials, counter, dot_first);
-        else k_mg_prolong_smooth_v<T, false><<<nbm, BLOCK, 0, s>>>(M, C, r, a, xc, b, om, st, partials, counter, 0);
+        with_nt(M.mnt, [&](auto K) {
+          constexpr int NT = decltype(K)::value;
+          if (d)
+            k_mg_prolong_smooth_v<T, true, NT><<<nbm, NT, 0, s>>>(M, C, r, a, xc, b, om, st, partials, counter,
+                                                                 dot_first);
+          else k_mg_prolong_smooth_v<T, false, NT><<<nbm, NT, 0, s>>>(M, C, r, a, xc, b, om, st, partials, counter, 0);
+        });
       } else {
         if (d) k_mg_prolong_smooth<T, true><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, dot_first);
         else k_mg_prolong_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, C, r, a, xc, b, om, st, partials, counter, 0);
@@ -1635,14 +1690,17 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
   T* xd = vec ? V.x : nullptr;
   if (H) {
     if (vec) {
-      auto kdir = dir_v<T, false>(first);
-      if (ev0) {
-        // events attached to the dispatch itself: kernel start and end times
-        hipExtLaunchKernelGGL(kdir, dim3(nbm), dim3(BLOCK), 0, s, ev0, ev1, 0, M, (const T*)*z, (const T*)V.r,
-                              (const T*)V.p, V.p_alt, V.q, st, partials, counters, xd);
-      } else {
-        kdir<<<nbm, BLOCK, 0, s>>>(M, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
-      }
+      with_nt(M.mnt, [&](auto K) {
+        constexpr int NT = decltype(K)::value;
+        auto kdir = dir_v<T, false, NT>(first);
+        if (ev0) {
+          // events attached to the dispatch itself: kernel start and end times
+          hipExtLaunchKernelGGL(kdir, dim3(nbm), dim3(NT), 0, s, ev0, ev1, 0, M, (const T*)*z, (const T*)V.r,
+                                (const T*)V.p, V.p_alt, V.q, st, partials, counters, xd);
+        } else {
+          kdir<<<nbm, NT, 0, s>>>(M, *z, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
+        }
+      });
     } else {
       auto kdir = k_cg_dir_spmv<T, false>;
       if (ev0)
@@ -1658,11 +1716,17 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
   } else {
     if (vec && V.zj) {
       // z = r/diag was stored by the previous update (or the start)
-      dir_v<T, false>(first)<<<nbm, BLOCK, 0, s>>>(M, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
+      with_nt(M.mnt, [&](auto K) {
+        constexpr int NT = decltype(K)::value;
+        dir_v<T, false, NT>(first)<<<nbm, NT, 0, s>>>(M, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
+      });
       std::swap(V.p, V.p_alt);
       k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.q, st, partials, counters + 1, V.zj);
     } else if (vec) {
-      dir_v<T, true>(first)<<<nbm, BLOCK, 0, s>>>(M, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
+      with_nt(M.mnt, [&](auto K) {
+        constexpr int NT = decltype(K)::value;
+        dir_v<T, true, NT>(first)<<<nbm, NT, 0, s>>>(M, nullptr, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
+      });
       std::swap(V.p, V.p_alt);
       k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.q, st, partials, counters + 1, nullptr);
     } else {
@@ -1692,9 +1756,15 @@ double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout
   const Lev<T> M = vec ? march_lev(L) : L;
   const int nb = vec ? march_blocks(M) : tile_blocks(L.ntiles);
   auto launch = [&]() {
-    if (vec) k_cg_dir_spmv_v<T, false, false><<<nb, BLOCK, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter,
-                                                                    nullptr);
-    else k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter, 0);
+    if (vec) {
+      with_nt(M.mnt, [&](auto K) {
+        constexpr int NT = decltype(K)::value;
+        k_cg_dir_spmv_v<T, false, false, NT><<<nb, NT, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter,
+                                                               nullptr);
+      });
+    } else {
+      k_cg_dir_spmv<T, false><<<nb, BLOCK, 0, s>>>(M, z, nullptr, pin, pout, q, st, partials, counter, 0);
+    }
   };
   launch();
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
@@ -1710,12 +1780,21 @@ template <class T>
 double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, SolveStatus* st, int reps,
                             double omega, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const bool vec = use_vec(L);
-  const Lev<T> M = vec ? march_lev(L) : L;
+  const Lev<T> M = vec ? march_lev(L, 1) : L;
   const int nb = vec ? march_blocks(M) : tile_blocks(L.ntiles);
-  auto ks = vec ? k_mg_smooth_v<T, false> : k_mg_smooth<T, false>;
-  ks<<<nb, BLOCK, 0, s>>>(M, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
+  auto launch = [&]() {
+    if (vec) {
+      with_nt(M.mnt, [&](auto K) {
+        constexpr int NT = decltype(K)::value;
+        k_mg_smooth_v<T, false, NT><<<nb, NT, 0, s>>>(M, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
+      });
+    } else {
+      k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(M, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
+    }
+  };
+  launch();
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-  for (int t = 0; t < reps; ++t) ks<<<nb, BLOCK, 0, s>>>(M, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
+  for (int t = 0; t < reps; ++t) launch();
   if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
@@ -1736,8 +1815,11 @@ template double replay_operator_kernel<float>(const Lev<float>&, const float*, c
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
                     double* partials, unsigned* counter, bool set_bnorm, hipStream_t s, float* r32) {
   if (use_vec(L)) {
-    k_resid64_v<<<march_blocks(march_lev(L)), BLOCK, 0, s>>>(march_lev(L), b, x, r, st, partials, counter,
-                                                            set_bnorm ? 1 : 0, r32);
+    const Lev<double> M = march_lev(L);
+    with_nt(M.mnt, [&](auto K) {
+      constexpr int NT = decltype(K)::value;
+      k_resid64_v<NT><<<march_blocks(M), NT, 0, s>>>(M, b, x, r, st, partials, counter, set_bnorm ? 1 : 0, r32);
+    });
   } else {
     k_resid64<<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);
     if (r32) k_to_float<<<grid_blocks(L.n), BLOCK, 0, s>>>(r, r32, L.n);
@@ -1786,8 +1868,11 @@ void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V
   const int nb = vec_blocks(vec_items(L));
   const Lev<double> M = march_lev(L);
   const int nbm = march_blocks(M);
-  if (first) k_cg_dir_spmv_z32_v<true><<<nbm, BLOCK, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
-  else k_cg_dir_spmv_z32_v<false><<<nbm, BLOCK, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
+  with_nt(M.mnt, [&](auto K) {
+    constexpr int NT = decltype(K)::value;
+    if (first) k_cg_dir_spmv_z32_v<true, NT><<<nbm, NT, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
+    else k_cg_dir_spmv_z32_v<false, NT><<<nbm, NT, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
+  });
   std::swap(V.p, V.p_alt);
   k_cg_update_r32_v<<<nb, BLOCK, 0, s>>>(L, V.r, V.q, r32, st, partials, counters + 1);
   mg_vcycle(H, 0, r32, st, partials, counters + 2, false, true, s, z);
@@ -1798,9 +1883,15 @@ double replay_operator_z32(const Lev<double>& L, const float* z, const double* p
                            hipEvent_t e1) {
   const Lev<double> M = march_lev(L);
   const int nb = march_blocks(M);
-  k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(M, z, pin, pout, q, st, partials, counter, nullptr);
+  auto launch = [&]() {
+    with_nt(M.mnt, [&](auto K) {
+      constexpr int NT = decltype(K)::value;
+      k_cg_dir_spmv_z32_v<false, NT><<<nb, NT, 0, s>>>(M, z, pin, pout, q, st, partials, counter, nullptr);
+    });
+  };
+  launch();
   if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-  for (int t = 0; t < reps; ++t) k_cg_dir_spmv_z32_v<false><<<nb, BLOCK, 0, s>>>(M, z, pin, pout, q, st, partials, counter, nullptr);
+  for (int t = 0; t < reps; ++t) launch();
   if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;

@@ -191,6 +191,17 @@ def test_step_parity_jacobi_pressure():
     _run_both(prm, f, steps=2)
 
 
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_step_parity_384_thread_row_blocks(precision):
+    """48x48x96 grid: a fine-level z-row is 48 FP64 or 24 FP32 vectors, so
+    the multigrid CG's stencil kernels run 384-thread blocks of whole rows,
+    sharing y neighbours through LDS, and restrict in marching form.  Random
+    state with flow, 2 steps, both sides solving to 1e-13."""
+    prm, _ = _grid_params(n=(48, 48, 96), L=48 * 1.25e-4, precision=precision)
+    f = W.random_fields(prm, seed=5)
+    _run_both(prm, f, steps=2)
+
+
 @pytest.mark.parametrize("precond", [1, 0])
 def test_step_parity_mixed_precision_refined(precond):
     """Precision form to 1e-13 reaches the FP64 discrete solution: same 1e-9
