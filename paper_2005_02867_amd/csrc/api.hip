@@ -71,6 +71,8 @@ struct ds_grid {
   float *e32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p32alt = nullptr, *q32 = nullptr;
   double* zj = nullptr;            // Jacobi z = r/diag (FP64 solves)
   float* zj32 = nullptr;           // the same for the FP32 rounds
+  double* r_alt = nullptr;         // second residual buffer of the Neumann-preconditioned solves
+  float* r32alt = nullptr;
   int dirmask = 0;                 // p_rgh = 0 box faces
   int batch_p[2] = {4, 4};         // pressure, then any other pressure-type system (phi, adjoints)
   int f32_sys = -1;                // system whose FP32 copies (qc32, diag32) the last setup wrote
@@ -78,6 +80,7 @@ struct ds_grid {
     double inner_min = 1e-3;   // smallest FP32 inner relative tolerance per round (pressure-type)
     double inner_min_jac = 1e-6;  // the same for the energy and species systems
     int mg32 = 1;                 // multigrid systems: FP64 CG with the FP32 V-cycle
+    int neumann = 1;              // energy and species: Neumann-polynomial preconditioner (vectorised grids)
   } tune;
   // live timing of the pressure solve's fine-level operator kernel
   static constexpr int NEV = 256;
@@ -175,6 +178,7 @@ size_t carve(ds_grid* g, char* base) {
   g->p_alt = L.take<double>(base, n);
   g->phi = L.take<double>(base, n);
   g->zj = L.take<double>(base, n);
+  g->r_alt = L.take<double>(base, n);
   // FP64 multigrid levels (level 0 uses qc/diag of the pressure system)
   MgHier<double>& H = g->H64;
   H.lev[0].qc = g->qc;
@@ -211,6 +215,7 @@ size_t carve(ds_grid* g, char* base) {
     g->p32alt = L.take<float>(base, n);
     g->q32 = L.take<float>(base, n);
     g->zj32 = L.take<float>(base, n);
+    g->r32alt = L.take<float>(base, n);
   }
   return L.off;
 }
@@ -405,6 +410,7 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
   if ((st = sync_status(g, sys, s)) != DS_OK) return st;
   if (!g->h_status[sys].done) {
     CgVecs<double> V{x, g->r, g->pd, g->p_alt, g->q, H ? nullptr : g->zj};
+    if (sys != 2 && g->tune.neumann) V.r_alt = g->r_alt;
     double* const p_odd = V.p_alt;   // direction of odd iterations (for the deferred x update)
     double* const p_even = V.p;
     double* z = nullptr;
@@ -481,13 +487,18 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     g->h_status[3].it = 0;
     g->h_status[3].done = 0;
     CgVecs<float> V{g->e32, g->r32, g->p32, g->p32alt, g->q32, H ? nullptr : g->zj32};
+    if (sys != 2 && g->tune.neumann) V.r_alt = g->r32alt;
     float* const p_odd = V.p_alt;   // direction of odd iterations (for the deferred x update)
     float* const p_even = V.p;
     float* z = nullptr;
     // Jacobi rounds on vectorised levels: conversion, z = r/diag and both
-    // dot products in one pass; otherwise the conversion, then cg_start
-    if (H || !launch_inner_init_jac<float>(F, g->r, g->r32, g->e32, g->zj32, si, g->partials,
-                                          g->counters + CT_SOLVE1, s)) {
+    // dot products in one pass (the Neumann-polynomial z then in a marching
+    // pass of its own); otherwise the conversion, then cg_start
+    if (!H && V.r_alt && launch_inner_init_jac<float>(F, g->r, g->r32, g->e32, nullptr, si, g->partials,
+                                                      g->counters + CT_SOLVE1, s)) {
+      launch_neumann_start<float>(F, V.r, V.zj, si, g->partials, g->counters + CT_SOLVE0 + 2, s);
+    } else if (H || !launch_inner_init_jac<float>(F, g->r, g->r32, g->e32, g->zj32, si, g->partials,
+                                                 g->counters + CT_SOLVE1, s)) {
       launch_inner_init<float>(F, g->r, g->r32, g->e32, si, g->partials, g->counters + CT_SOLVE1, s);
       cg_start(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, s);
     }
@@ -936,6 +947,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_INNER_MIN")) g->tune.inner_min = atof(e);
   if (const char* e = getenv("DSVOF_INNER_MIN_JAC")) g->tune.inner_min_jac = atof(e);
   if (const char* e = getenv("DSVOF_MG32")) g->tune.mg32 = atoi(e);
+  if (const char* e = getenv("DSVOF_NEUMANN")) g->tune.neumann = atoi(e);
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {
     if (prm->pressure_precond == 1) build_hier(g->H32, nx, ny, nz, prm->h, prm->dt);

@@ -78,6 +78,10 @@ struct CgVecs {
   T* p_alt;
   T* q;        // A p
   T* zj = nullptr;   // Jacobi: z = r/diag stored by the update (vectorised levels)
+  // with zj on vectorised levels: second residual buffer; the preconditioner is
+  // then the first-order Neumann polynomial of the Jacobi splitting (the
+  // diagonally dominant energy and species systems)
+  T* r_alt = nullptr;
 };
 
 // dirmask bit (axis*2 + side) set: p_rgh = 0 on that box face.  Every level
@@ -154,11 +158,16 @@ template <class T>
 void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s, const T* p = nullptr,
                            const SolveStatus* st = nullptr);
 // Start of a Jacobi-preconditioned round in one pass: r = (T) r64, x = 0,
-// z = r/diag, status (||r||, <r, z>).  False (nothing launched) off the
-// vectorised levels.
+// z = r/diag (z may be null: not stored), status (||r||, <r, z>).  False
+// (nothing launched) off the vectorised levels.
 template <class T>
 bool launch_inner_init_jac(const Lev<T>& L, const double* r64, T* r, T* x, T* z, SolveStatus* st, double* partials,
                            unsigned* counter, hipStream_t s);
+// First z of a Neumann-polynomial preconditioned solve (vectorised levels):
+// z = (D^-1 + D^-1 N D^-1) r and st->rz = <r, z>.
+template <class T>
+void launch_neumann_start(const Lev<T>& L, const T* r, T* z, SolveStatus* st, double* partials, unsigned* counter,
+                          hipStream_t s);
 void launch_to_float(const double* a, float* b, long long n, hipStream_t s);
 
 }  // namespace dsv

@@ -1083,7 +1083,7 @@ VEC_KERNEL k_inner_init_jac_v(Lev<T> L, const double* __restrict__ r64, T* __res
     }
     stv<T>(at(r, c), rv);
     stv<T>(at(x, c), xv);
-    stv<T>(at(zout, c), zv);
+    if (zout) stv<T>(at(zout, c), zv);
   }
   const int ops[2] = {RSUM, RSUM};
   if (block_reduce_publish<2>(acc, ops, partials, counter)) {
@@ -1242,6 +1242,79 @@ VEC_KERNEL k_cg_update_v(Lev<T> L, T* __restrict__ x, T* __restrict__ r, const T
       } else if (JAC) {
         st->beta = t[1] / st->rz;
         st->rz = t[1];
+      }
+    }
+  }
+}
+
+// Residual update with the first-order Neumann-series polynomial preconditioner
+// of the Jacobi splitting A = D - N:
+//   r' = r - alpha q,   y = D^-1 r',   z = D^-1 (r' + N y)  (= (D^-1 + D^-1 N D^-1) r'),
+// with N y = sc/2 sum_nb (q_c + q_nb) y_nb formed by the marching stencil
+// from the neighbours' r - alpha q and diag.  For the diagonally dominant
+// energy and species systems the spectrum of D^-1 A lies in [1 - b, 1 + b]
+// with b < 1, and that of M^-1 A = I - (D^-1 N)^2 in [1 - b^2, 1], which
+// roughly halves the CG iterations for one stencil pass more in this kernel.
+// Neighbours read r, so r' goes to a second buffer (rout).  INIT: alpha = 0
+// and no q (the first z of a solve); rout is not written and only rz is set.
+// Also <r', r'> (convergence test) and <r', z> (beta), as k_cg_update_v.
+template <class T, bool INIT, int NT>
+VEC_KERNEL_M k_cg_update_neu_v(Lev<T> L, const T* __restrict__ rin, T* __restrict__ rout, const T* __restrict__ q,
+                               T* __restrict__ zout, SolveStatus* st, double* partials, unsigned* counter) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n;
+  const T a = INIT ? T(0) : (T)st->alpha;
+  double acc[2] = {0.0, 0.0};
+  auto rn_at = [&](unsigned f, T(&o)[V]) {
+    ldv<T>(at(rin, f), o);
+    if (!INIT) {
+      T qv[V];
+      ldv<T>(at(q, f), qv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) o[v] = o[v] - a * qv[v];
+    }
+  };
+  march<T, NT>(
+      L,
+      [&](unsigned f, T(&o)[V]) {
+        T dv[V];
+        rn_at(f, o);
+        ldv<T>(at(L.diag, f), dv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = o[v] / dv[v];
+      },
+      [&](unsigned f) -> T { return (INIT ? *at(rin, f) : *at(rin, f) - a * *at(q, f)) / *at(L.diag, f); },
+      [&](unsigned c, const T(&qv)[V], const T(&yv)[V], const T(&off)[V], const T(&dv)[V]) {
+        T rv[V], zv[V];
+        rn_at(c, rv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          zv[v] = (rv[v] + T(0.5) * L.sc * off[v]) / dv[v];
+          acc[0] += (double)rv[v] * (double)rv[v];
+          acc[1] += (double)rv[v] * (double)zv[v];
+        }
+        if (!INIT) stv<T>(at(rout, c), rv);
+        stv<T>(at(zout, c), zv);
+      });
+  const int ops[2] = {RSUM, RSUM};
+  if (block_reduce_publish<2, NT>(acc, ops, partials, counter)) {
+    double t[2];
+    block_combine<2, NT>(ops, partials, counter, t);
+    if (threadIdx.x == 0) {
+      if (INIT) {
+        st->rz = t[1];
+      } else {
+        st->it += 1;
+        st->rr = t[0];
+        st->res = sqrt(t[0]) / st->bnorm;
+        if (st->res <= st->tol) {
+          st->done = 1;
+        } else if (st->it >= st->maxit) {
+          st->done = 2;
+        } else {
+          st->beta = t[1] / st->rz;
+          st->rz = t[1];
+        }
       }
     }
   }
@@ -1666,6 +1739,20 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
 }
 
 template <class T>
+void launch_neumann_start(const Lev<T>& L, const T* r, T* z, SolveStatus* st, double* partials, unsigned* counter,
+                          hipStream_t s) {
+  const Lev<T> M = march_lev(L);
+  with_nt(M.mnt, [&](auto K) {
+    constexpr int NT = decltype(K)::value;
+    k_cg_update_neu_v<T, true, NT><<<march_blocks(M), NT, 0, s>>>(M, r, nullptr, nullptr, z, st, partials, counter);
+  });
+}
+template void launch_neumann_start<double>(const Lev<double>&, const double*, double*, SolveStatus*, double*,
+                                           unsigned*, hipStream_t);
+template void launch_neumann_start<float>(const Lev<float>&, const float*, float*, SolveStatus*, double*, unsigned*,
+                                          hipStream_t);
+
+template <class T>
 void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* st, double* partials,
               unsigned* counters, hipStream_t s) {
   const int first = 1;
@@ -1673,7 +1760,9 @@ void cg_start(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatus* s
     mg_vcycle(*H, 0, V.r, st, partials, counters + 2, first != 0, true, s, z);
   } else {
     *z = nullptr;
-    if (use_vec(L))
+    if (use_vec(L) && V.zj && V.r_alt)
+      launch_neumann_start(L, V.r, V.zj, st, partials, counters + 2, s);
+    else if (use_vec(L))
       k_jac_rz_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2, first, V.zj);
     else k_jac_rz<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, V.r, st, partials, counters + 2, first);
   }
@@ -1715,13 +1804,23 @@ void cg_iteration(const Lev<T>& L, MgHier<T>* H, CgVecs<T>& V, T** z, SolveStatu
     mg_vcycle(*H, 0, V.r, st, partials, counters + 2, false, true, s, z);
   } else {
     if (vec && V.zj) {
-      // z = r/diag was stored by the previous update (or the start)
+      // z = M^-1 r was stored by the previous update (or the start)
       with_nt(M.mnt, [&](auto K) {
         constexpr int NT = decltype(K)::value;
         dir_v<T, false, NT>(first)<<<nbm, NT, 0, s>>>(M, V.zj, V.r, V.p, V.p_alt, V.q, st, partials, counters, xd);
       });
       std::swap(V.p, V.p_alt);
-      k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.q, st, partials, counters + 1, V.zj);
+      if (V.r_alt) {
+        // Neumann-polynomial z; r' into the second buffer
+        with_nt(M.mnt, [&](auto K) {
+          constexpr int NT = decltype(K)::value;
+          k_cg_update_neu_v<T, false, NT><<<nbm, NT, 0, s>>>(M, V.r, V.r_alt, V.q, V.zj, st, partials,
+                                                              counters + 1);
+        });
+        std::swap(V.r, V.r_alt);
+      } else {
+        k_cg_update_v<T, true><<<nb, BLOCK, 0, s>>>(L, nullptr, V.r, V.p, V.q, st, partials, counters + 1, V.zj);
+      }
     } else if (vec) {
       with_nt(M.mnt, [&](auto K) {
         constexpr int NT = decltype(K)::value;
