@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 # and WRITE_SIZE (separate runs of `bench.py --counters-pass`), each scaled by
 # the ratio of known bytes to the counter's reading for a 1 GiB device copy in
 # the same run; None until measured for the current kernel.
-# Measured for the fine-level sweep of the 256^3 workload: FETCH_SIZE 109725 KiB
-# x 2.000 (the 1 GiB copy reads 524331 KiB) + WRITE_SIZE 65536 KiB x 1.000.
-TRAFFIC_SMOOTH = (109725.0 * (1048576.0 / 524331.0) + 65536.0) * 1024.0
+# Measured for the fine-level sweep of the 256^3 workload: FETCH_SIZE 109698 KiB
+# x 2.000 (the 1 GiB copy reads 524330 KiB) + WRITE_SIZE 65536 KiB x 1.000.
+TRAFFIC_SMOOTH = (109698.0 * (1048576.0 / 524330.0) + 65536.0) * 1024.0
 
 
 def log(msg):
@@ -261,7 +261,7 @@ def main():
     kt = mixed["kernel"]
     achieved = rs["bytes_per_launch"] / (rs["avg_us"] * 1e-6) / 1e9
     roofline = {
-        "kernel": "k_mg_smooth_v<float,false> (fine-level damped-Jacobi sweep of the multigrid preconditioner, "
+        "kernel": "k_mg_smooth_v<float,false,256> (fine-level damped-Jacobi sweep of the multigrid preconditioner, "
                   "FP32, reads r, x, q_coef, forms diag from q_coef, writes x: 16 B/cell; the largest share of "
                   "step time)",
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -272,7 +272,7 @@ def main():
     }
     ach_op = rp["bytes_per_launch"] / (rp["avg_us"] * 1e-6) / 1e9
     roofline_op = {
-        "kernel": "k_cg_dir_spmv_z32_v (pressure CG operator of the precision form: p = z + beta p with z in FP32, "
+        "kernel": "k_cg_dir_spmv_z32_v<false,512> (pressure CG operator of the precision form: p = z + beta p with z in FP32, "
                   "fused with q = A p and <p,q> in FP64, diag formed from q_coef; 36 B/cell)",
         "bound": "hbm", "achieved": ach_op, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_op / HBM_PEAK_GBS,
         "avg_us": rp["avg_us"], "bytes_per_launch": rp["bytes_per_launch"],
