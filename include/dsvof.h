@@ -116,7 +116,31 @@ typedef struct ds_diagnostics {
 } ds_diagnostics;
 
 /* Validate parameters and create a host handle for an nx*ny*nz grid
- * (each >= 2).  Host only.  Returns DS_ERR_ARG for invalid input. */
+ * (each >= 2).  Host only.  Returns DS_ERR_ARG for invalid input.
+ *
+ * Tuning variables read from the environment here (unset: the defaults in
+ * brackets, which every measurement uses).  They change launch shapes and
+ * solver schedules, never the discretisation; results stay within the
+ * solver tolerance.
+ *   DSVOF_MG_NU [4], DSVOF_MG_NU_FINE [4]: V-cycle pre/post sweeps (coarse
+ *     levels, finest level); DSVOF_MG_COARSE [16]: sweeps on the coarsest
+ *     level; DSVOF_MG_MINDIM [8]: coarsen while every side is at least this;
+ *     DSVOF_MG_OMEGA [0.9]: Jacobi damping; DSVOF_MG_TAIL [1]: run the levels
+ *     that fit in LDS in one workgroup.
+ *   DSVOF_INNER_MIN [1e-3], DSVOF_INNER_MIN_JAC [1e-6]: smallest relative
+ *     reduction an FP32 round of the precision form asks (pressure-type,
+ *     energy/species); DSVOF_MG32 [1]: multigrid systems of the precision
+ *     form as FP64 CG with the FP32 V-cycle (0: FP32 rounds).
+ *   DSVOF_NEUMANN [1]: energy and species CG preconditioned by the first-
+ *     order Neumann polynomial of the Jacobi splitting (0: Jacobi).
+ *   DSVOF_VEC_BLOCKS [1024], DSVOF_VEC_YTILE [0]: grid cap and y-slab of the
+ *     z-vectorised pointwise kernels; DSVOF_MARCH_THREADS [262144],
+ *     DSVOF_MARCH_MIN_PLANES [1]: threads and shortest x-chunk of the
+ *     marching stencil kernels; DSVOF_MARCH_NT0 ["512,256,384"],
+ *     DSVOF_MARCH_NT1 ["256,512,384"]: block sizes the marching kernels try
+ *     in order (0: CG operator and FP64 residual, 1: V-cycle).
+ * The launch-shape variables are process-wide: the last grid created sets
+ * them for every grid of the process. */
 int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out);
 
 /* Release the host handle.  The workspace is the caller's. */
