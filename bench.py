@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 # and WRITE_SIZE (separate runs of `bench.py --counters-pass`), each scaled by
 # the ratio of known bytes to the counter's reading for a 1 GiB device copy in
 # the same run; None until measured for the current kernel.
-# Measured for the fine-level sweep of the 256^3 workload: FETCH_SIZE 109698 KiB
-# x 2.000 (the 1 GiB copy reads 524330 KiB) + WRITE_SIZE 65536 KiB x 1.000.
-TRAFFIC_SMOOTH = (109698.0 * (1048576.0 / 524330.0) + 65536.0) * 1024.0
+# Measured for the fine-level coloured sweep of the 256^3 workload: FETCH_SIZE
+# 121502 KiB x 2.000 (the 1 GiB copy reads 524334 KiB) + WRITE_SIZE 65536 KiB x 1.000.
+TRAFFIC_SMOOTH = (121502.0 * (1048576.0 / 524334.0) + 65536.0) * 1024.0
 
 
 def log(msg):
@@ -261,9 +261,9 @@ def main():
     kt = mixed["kernel"]
     achieved = rs["bytes_per_launch"] / (rs["avg_us"] * 1e-6) / 1e9
     roofline = {
-        "kernel": "k_mg_smooth_v<float,false,256> (fine-level damped-Jacobi sweep of the multigrid preconditioner, "
-                  "FP32, reads r, x, q_coef, forms diag from q_coef, writes x: 16 B/cell; the largest share of "
-                  "step time)",
+        "kernel": "k_mg_rb_v<float,RB_GEN,false,256> (fine-level coloured (x-z red-black) sweep of the multigrid "
+                  "preconditioner, FP32, reads r, x, q_coef, forms diag from q_coef, writes x: 16 B/cell; the "
+                  "largest share of step time)",
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_SMOOTH,
         "avg_us": rs["avg_us"], "bytes_per_launch": rs["bytes_per_launch"],

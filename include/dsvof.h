@@ -122,11 +122,15 @@ typedef struct ds_diagnostics {
  * brackets, which every measurement uses).  They change launch shapes and
  * solver schedules, never the discretisation; results stay within the
  * solver tolerance.
- *   DSVOF_MG_NU [4], DSVOF_MG_NU_FINE [4]: V-cycle pre/post sweeps (coarse
- *     levels, finest level); DSVOF_MG_COARSE [16]: sweeps on the coarsest
- *     level; DSVOF_MG_MINDIM [8]: coarsen while every side is at least this;
- *     DSVOF_MG_OMEGA [0.9]: Jacobi damping; DSVOF_MG_TAIL [1]: run the levels
- *     that fit in LDS in one workgroup.
+ *   DSVOF_MG_NU [4], DSVOF_MG_NU_FINE [4]: V-cycle pre/post Jacobi sweeps
+ *     (coarse levels, finest level); DSVOF_MG_COARSE [16]: sweeps on the
+ *     coarsest level; DSVOF_MG_MINDIM [8]: coarsen while every side is at
+ *     least this; DSVOF_MG_OMEGA [0.9]: Jacobi damping; DSVOF_MG_TAIL [1]:
+ *     run the levels that fit in LDS in one workgroup; DSVOF_MG_RB [1]:
+ *     coloured (x-z red-black) sweeps on the levels that take them, with
+ *     DSVOF_MG_RB_NU [3] pre/post sweeps, weight DSVOF_MG_RB_W [1.0], on
+ *     levels whose marching chunks have at least DSVOF_MG_RB_MINPLANES [8]
+ *     x-planes.
  *   DSVOF_INNER_MIN [1e-3], DSVOF_INNER_MIN_JAC [1e-6]: smallest relative
  *     reduction an FP32 round of the precision form asks (pressure-type,
  *     energy/species); DSVOF_MG32 [1]: multigrid systems of the precision
@@ -274,9 +278,11 @@ int ds_get_adjoint_iterations(const ds_grid* g, int* iters4);
  * the current pressure system (as ds_time_operator_kernel) and returns its
  * mean duration (us) and algorithmic bytes per launch.
  *   DS_KERNEL_CG_OPERATOR: the conjugate-gradient operator kernel (above);
- *   DS_KERNEL_MG_SMOOTH: one damped-Jacobi sweep of the multigrid
- *     preconditioner on the fine level (reads r, x, q_coef and forms diag
- *     from q_coef; writes x: 4 arrays).  Needs pressure_precond = 1.
+ *   DS_KERNEL_MG_SMOOTH: one sweep of the multigrid preconditioner's
+ *     smoother on the fine level, the kernel the V-cycle runs there: the
+ *     coloured (x-z red-black) sweep where the level takes it, else damped
+ *     Jacobi (reads r, x, q_coef and forms diag from q_coef; writes x: 4
+ *     arrays either way).  Needs pressure_precond = 1.
  * Only solver scratch vectors are written.  DS_ERR_ARG for an unknown kernel. */
 enum { DS_KERNEL_CG_OPERATOR = 0, DS_KERNEL_MG_SMOOTH = 1 };
 int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* bytes_per_launch, void* stream);

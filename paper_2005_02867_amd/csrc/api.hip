@@ -309,6 +309,11 @@ void build_hier(MgHier<T>& H, int nx, int ny, int nz, double h, double dt) {
   if (const char* e = getenv("DSVOF_MG_MINDIM")) mindim = std::max(4, atoi(e));
   if (const char* e = getenv("DSVOF_MG_OMEGA")) H.omega = atof(e);
   if (const char* e = getenv("DSVOF_MG_TAIL")) H.tail = atoi(e);
+  if (const char* e = getenv("DSVOF_MG_RB")) H.rb = atoi(e);
+  if (const char* e = getenv("DSVOF_MG_RB_NU")) H.nu_rb = std::max(1, atoi(e));
+  if (const char* e = getenv("DSVOF_MG_RB_W")) H.w_rb = atof(e);
+  if (const char* e = getenv("DSVOF_MG_RB_MINPLANES")) H.rb_min_planes = std::max(1, atoi(e));
+  if (const char* e = getenv("DSVOF_MG_RB_THREADS")) H.rb_threads = std::max(0LL, atoll(e));
   for (;;) {
     Lev<T>& L = H.lev[H.nlev++];
     lev_dims(L, nx, ny, nz, dt / (hl * hl));
@@ -1176,7 +1181,7 @@ int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* byte
     }
     const bool z32 = g->prm.pressure_precond == 1 && g->tune.mg32 && mg32_supported(g->L0);
     if (smooth) {
-      us = replay_smooth_kernel<float>(F, g->r32, g->H32.x[0], g->H32.t[0], st, reps, g->H32.omega, s, g->ev[0],
+      us = replay_smooth_kernel<float>(F, g->H32, g->r32, g->H32.x[0], g->H32.t[0], st, reps, s, g->ev[0],
                                        g->ev[1]);
       // r, x, q read and x written (diag too unless formed from q)
       if (bytes_per_launch) *bytes_per_launch = (F.dfly ? 16.0 : 20.0) * (double)g->n;
@@ -1203,7 +1208,7 @@ int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* byte
     L.diag = g->diag;
     if (g->prm.pressure_precond == 1) pressure_type(g, 2, L);
     if (smooth)
-      us = replay_smooth_kernel<double>(L, g->r, g->H64.x[0], g->H64.t[0], st, reps, g->H64.omega, s, g->ev[0],
+      us = replay_smooth_kernel<double>(L, g->H64, g->r, g->H64.x[0], g->H64.t[0], st, reps, s, g->ev[0],
                                         g->ev[1]);
     else
       us = replay_operator_kernel<double>(L, g->r, g->pd, g->p_alt, g->q, st, g->partials, g->counters + CT_MISC,

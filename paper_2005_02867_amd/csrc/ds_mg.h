@@ -67,6 +67,11 @@ struct MgHier {
   int nu_fine = 4;        // the same on the finest level
   int coarse_sweeps = 16; // sweeps on the coarsest level
   int tail = 1;           // run the levels that fit in one workgroup's LDS as one launch
+  int rb = 1;             // coloured (x-z red-black) sweeps on the levels that allow them
+  int nu_rb = 3;          // their pre = post sweeps
+  double w_rb = 1.0;      // their relaxation weight
+  int rb_min_planes = 8;  // shortest marching chunk a level may have to take them
+  long long rb_threads = 0;   // threads their marching grid aims for (0: as the other marching kernels)
 };
 
 // CG work vectors of one precision.
@@ -110,9 +115,11 @@ double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout
                               double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                               hipEvent_t e1);
 
+// The fine level's smoother sweep as the V-cycle of H runs it (coloured or
+// damped Jacobi), replayed back to back; mean duration in microseconds.
 template <class T>
-double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, SolveStatus* st, int reps,
-                            double omega, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+double replay_smooth_kernel(const Lev<T>& L, const MgHier<T>& H, const T* r, const T* xin, T* xout, SolveStatus* st,
+                            int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 // FP64 conjugate gradients preconditioned by the FP32 multigrid V-cycle
 // (operator, vectors and dot products in FP64; the V-cycle's sweeps, its

@@ -608,12 +608,13 @@ inline int march_nt(const Lev<T>& L, int cls, bool pairs) {
   }
   return pairs ? 0 : 256;
 }
+// threads: the thread count to aim for (0: g_march_threads).
 template <class T>
-inline Lev<T> march_lev(Lev<T> L, int cls = 0) {
+inline Lev<T> march_lev(Lev<T> L, int cls = 0, long long threads = 0) {
   L.mnt = march_nt(L, cls, false);
   const long long ncol = (long long)L.ny * (L.nz / VW<T>::n);
-  const long long nch =
-      std::min<long long>(std::max<long long>(((long long)g_march_threads + ncol - 1) / ncol, 1), L.nx);
+  const long long aim = threads > 0 ? threads : (long long)g_march_threads;
+  const long long nch = std::min<long long>(std::max<long long>((aim + ncol - 1) / ncol, 1), L.nx);
   const long long clen = std::max<long long>((L.nx + nch - 1) / nch, std::min(g_march_min_planes, L.nx));
   L.mch = (int)((L.nx + clen - 1) / clen);   // no empty trailing chunks
   return L;
@@ -982,6 +983,251 @@ VEC_KERNEL_M k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, 
     }
     stv<T>(at(xout, c), o);
   });
+  if (DOT) publish_rz<NT>(acc, st, partials, counter, first);
+}
+
+// ---------------------------------------------------------------- coloured sweeps
+// One sweep of a two-colour smoother whose colours alternate along x and z:
+// colour A holds the cells with i + k + c0 even, colour B the others.  A
+// cell's x and z neighbours have the other colour, its y neighbours its own.
+// Colour A is relaxed from x0 with the damped-Jacobi formula (weight w), then
+// colour B from colour A's new values; y neighbours enter with their old
+// values (Jacobi coupling along y).  The pre-smoothing sweeps relax the even
+// colour first (c0 = 0) and the post-smoothing sweeps the odd one (c0 = 1),
+// the reverse order, which keeps the V-cycle a symmetric preconditioner.
+//
+// Marching form as in march(), with colour A one plane ahead of colour B:
+// the step for plane s relaxes plane s in colour A and finishes plane s - 1
+// in colour B, so one pass over x0, r and q does both colours.  A chunk
+// [i0, i1) also relaxes colour A on its outer planes i0 - 1 and i1, which its
+// first and last planes need.  The y-neighbour term sum (q + q_y) x0_y of a
+// plane serves both colours (old values either way) and is kept from one
+// step to the next.  Needs the rows shared through LDS and every z-row inside
+// one wave (rb_marching_ok), so each z neighbour is in an adjacent lane.
+// lx(f, o): x0 vector at cell f (X0 false: x0 = 0, nothing loaded);
+// out(c, o, rv): the finished vector of plane s - 1 and its r.
+template <class T, int NT, bool X0, class LX, class OUT>
+__device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ r, T w, int c0, LX lx, OUT out) {
+  constexpr int V = VW<T>::n;
+  const unsigned nzv = (unsigned)L.nz / V, ny = (unsigned)L.ny, nx = (unsigned)L.nx;
+  const unsigned nch = (unsigned)L.mch, clen = (nx + nch - 1) / nch;
+  const unsigned per = gridDim.x / NXCD, lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+  const unsigned total = ny * nzv * nch;
+  const unsigned P = ny * (unsigned)L.nz, sy = (unsigned)L.nz;
+  const int tid = threadIdx.x;
+  __shared__ T lsq[2][NT * V], lsx[2][X0 ? NT * V : 1];
+  const bool inm = tid >= (int)nzv, inp = tid + (int)nzv < NT;
+  const T hs = T(0.5) * L.sc;
+  int par = 0;
+  auto zero = [](T(&o)[V]) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = 0;
+  };
+  auto copy = [](T(&o)[V], const T(&a)[V]) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = a[v];
+  };
+  for (unsigned e = lb * NT + tid; e < total; e += gridDim.x * NT) {
+    const unsigned kv = e % nzv, t = e / nzv, j = t % ny, ch = t / ny;
+    const unsigned i0 = ch * clen, i1 = min(nx, i0 + clen);
+    if (i0 >= i1) continue;
+    const bool hym = j > 0, hyp = j + 1 < ny, hzm = kv > 0, hzp = kv + 1 < nzv;
+    const unsigned cj = j * sy + kv * V;
+    const unsigned s0 = i0 > 0 ? i0 - 1 : 0;
+    // q of planes s-2, s-1, s; x0 of s-1, s; colour-A results of s-2, s-1;
+    // r, diag and the y-neighbour term of s-1
+    T qa[V], qb[V], qc[V], xb[V], xc[V], ma[V], mb[V], rb[V], db[V], yb[V];
+    {
+      const unsigned fb = (s0 > 0 ? s0 - 1 : s0) * P + cj, fc = s0 * P + cj;
+      ldv<T>(at(L.qc, fb), qb);
+      ldv<T>(at(L.qc, fc), qc);
+      if (X0) {
+        lx(fb, xb);
+        lx(fc, xc);
+      } else {
+        zero(xb);
+        zero(xc);
+      }
+      copy(qa, qb);
+      zero(ma);
+      zero(mb);
+      zero(rb);
+      zero(yb);
+#pragma unroll
+      for (int v = 0; v < V; ++v) db[v] = 1;
+    }
+    for (unsigned s = s0; s <= i1; ++s) {
+      const bool live = s < nx;   // s == nx only finishes plane nx - 1
+      const unsigned c = (live ? s : nx - 1) * P + cj;
+      const bool hxm = s > 0, hxp = s + 1 < nx;
+      const unsigned fn = hxp ? c + P : c, fym = hym ? c - sy : c, fyp = hyp ? c + sy : c;
+      T qd[V], xd[V], rc[V], nqm[V], nqp[V], nxm[V], nxp[V];
+      ldv<T>(at(L.qc, fn), qd);
+      if (X0) lx(fn, xd);
+      else zero(xd);
+      ldv<T>(at(r, c), rc);
+      if (!inm) {
+        ldv<T>(at(L.qc, fym), nqm);
+        if (X0) lx(fym, nxm);
+      }
+      if (!inp) {
+        ldv<T>(at(L.qc, fyp), nqp);
+        if (X0) lx(fyp, nxp);
+      }
+      stv<T>(&lsq[par][tid * V], qc);
+      if (X0) stv<T>(&lsx[par][tid * V], xc);
+      __syncthreads();
+      if (inm) {
+        ldv<T>(&lsq[par][(tid - (int)nzv) * V], nqm);
+        if (X0) ldv<T>(&lsx[par][(tid - (int)nzv) * V], nxm);
+      }
+      if (inp) {
+        ldv<T>(&lsq[par][(tid + (int)nzv) * V], nqp);
+        if (X0) ldv<T>(&lsx[par][(tid + (int)nzv) * V], nxp);
+      }
+      par ^= 1;
+      if (!X0) {
+        zero(nxm);
+        zero(nxp);
+      }
+      const T qzm = lane_up(qc[V - 1]), qzp = lane_down(qc[0]);
+      const T xzm = lane_up(xc[V - 1]), xzp = lane_down(xc[0]);
+      // the y-neighbour term and diag of plane s
+      T yc[V], dc[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        T ty = 0;
+        ty = hym ? ty + (qc[v] + nqm[v]) * nxm[v] : ty;
+        ty = hyp ? ty + (qc[v] + nqp[v]) * nxp[v] : ty;
+        yc[v] = ty;
+      }
+      if (L.dfly) {
+        const double sc = (double)L.sc;
+        const int dm = L.dmask;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const double q = (double)qc[v], bnd = 2.0 * sc * q;
+          double d = 0.0;
+          d += hxm ? sc * 0.5 * (q + (double)qb[v]) : ((dm & 1) ? bnd : 0.0);
+          d += hxp ? sc * 0.5 * (q + (double)qd[v]) : ((dm & 2) ? bnd : 0.0);
+          d += hym ? sc * 0.5 * (q + (double)nqm[v]) : ((dm & 4) ? bnd : 0.0);
+          d += hyp ? sc * 0.5 * (q + (double)nqp[v]) : ((dm & 8) ? bnd : 0.0);
+          const bool em = v > 0 || hzm, ep = v < V - 1 || hzp;
+          const double gm = v > 0 ? (double)qc[v > 0 ? v - 1 : 0] : (double)qzm;
+          const double gp = v < V - 1 ? (double)qc[v < V - 1 ? v + 1 : V - 1] : (double)qzp;
+          d += em ? sc * 0.5 * (q + gm) : ((dm & 16) ? bnd : 0.0);
+          d += ep ? sc * 0.5 * (q + gp) : ((dm & 32) ? bnd : 0.0);
+          dc[v] = (T)d;
+        }
+      } else {
+        ldv<T>(at(L.diag, c), dc);
+      }
+      // colour A on plane s, from x0 (all neighbours old)
+      T mc[V];
+      {
+        T off[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          T o = yc[v];
+          o = hxm ? o + (qc[v] + qb[v]) * xb[v] : o;
+          o = hxp ? o + (qc[v] + qd[v]) * xd[v] : o;
+          const T gm = v > 0 ? qc[v > 0 ? v - 1 : 0] : qzm, xm = v > 0 ? xc[v > 0 ? v - 1 : 0] : xzm;
+          const T gp = v < V - 1 ? qc[v < V - 1 ? v + 1 : V - 1] : qzp;
+          const T xp = v < V - 1 ? xc[v < V - 1 ? v + 1 : V - 1] : xzp;
+          o = (v > 0 || hzm) ? o + (qc[v] + gm) * xm : o;
+          o = (v < V - 1 || hzp) ? o + (qc[v] + gp) * xp : o;
+          off[v] = o;
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const T nv = xc[v] + w * (rc[v] - (dc[v] * xc[v] - hs * off[v])) / dc[v];
+          mc[v] = (((s + (unsigned)v + (unsigned)c0) & 1u) == 0u) ? nv : xc[v];
+        }
+      }
+      // colour B on plane s - 1, from colour A's new values (y old)
+      const T mzm = lane_up(mb[V - 1]), mzp = lane_down(mb[0]);
+      const T bqzm = lane_up(qb[V - 1]), bqzp = lane_down(qb[0]);
+      if (s > i0) {
+        const unsigned sb = s - 1;
+        const bool bxm = sb > 0, bxp = s < nx;
+        T o[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          T f = yb[v];
+          f = bxm ? f + (qb[v] + qa[v]) * ma[v] : f;
+          f = bxp ? f + (qb[v] + qc[v]) * mc[v] : f;
+          const T gm = v > 0 ? qb[v > 0 ? v - 1 : 0] : bqzm, xm = v > 0 ? mb[v > 0 ? v - 1 : 0] : mzm;
+          const T gp = v < V - 1 ? qb[v < V - 1 ? v + 1 : V - 1] : bqzp;
+          const T xp = v < V - 1 ? mb[v < V - 1 ? v + 1 : V - 1] : mzp;
+          f = (v > 0 || hzm) ? f + (qb[v] + gm) * xm : f;
+          f = (v < V - 1 || hzp) ? f + (qb[v] + gp) * xp : f;
+          const T nv = mb[v] + w * (rb[v] - (db[v] * mb[v] - hs * f)) / db[v];
+          o[v] = (((sb + (unsigned)v + (unsigned)c0) & 1u) != 0u) ? nv : mb[v];
+        }
+        out(sb * P + cj, o, rb);
+      }
+      copy(qa, qb);
+      copy(qb, qc);
+      copy(qc, qd);
+      copy(xb, xc);
+      copy(xc, xd);
+      copy(ma, mb);
+      copy(mb, mc);
+      copy(rb, rc);
+      copy(db, dc);
+      copy(yb, yc);
+    }
+  }
+}
+
+// Levels that take the coloured sweeps: rows shared through LDS, z-rows
+// inside one wave, and chunks of at least min_planes x-planes (a chunk also
+// relaxes its two outer planes in colour A, which short chunks pay for more
+// than the better smoothing saves: at 128^3 the chunks are 2 planes long).
+template <class T>
+inline bool rb_marching_ok(const Lev<T>& M, int min_planes) {   // M: the level as march_lev(L, 1) returns it
+  if (!use_vec(M)) return false;
+  const long long nzv = M.nz / VW<T>::n;
+  const long long clen = (M.nx + M.mch - 1) / M.mch;
+  return nzv >= 1 && 64 % nzv == 0 && M.mnt % nzv == 0 && ((long long)M.ny * nzv) % M.mnt == 0 &&
+         clen >= min_planes;
+}
+
+enum { RB_GEN = 0, RB_ZERO = 1, RB_PROLONG = 2 };
+
+// One coloured sweep (march_rb) of F x = r.  RB_GEN: from x; RB_ZERO: from
+// x = 0 (x not read); RB_PROLONG: from x + P xc (injection from level C).
+// DOT: also <r, x_out> (the preconditioned residual's product).
+template <class T, int MODE, bool DOT, int NT>
+VEC_KERNEL_M k_mg_rb_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
+                       const T* __restrict__ xc, T* __restrict__ xout, T w, int c0, SolveStatus* st,
+                       double* partials, unsigned* counter, int first) {
+  if (st->done) return;
+  constexpr int V = VW<T>::n;
+  double acc = 0.0;
+  auto outf = [&](unsigned c, const T(&o)[V], const T(&rv)[V]) {
+    stv<T>(at(xout, c), o);
+    if (DOT) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc += (double)rv[v] * (double)o[v];
+    }
+  };
+  if constexpr (MODE == RB_PROLONG) {
+    auto row = [&](unsigned f, T(&o)[V]) {
+      const unsigned rr = f / (unsigned)F.nz;   // ii*ny + jj
+      const unsigned kk = f - rr * (unsigned)F.nz;
+      const unsigned jj = rr % (unsigned)F.ny, ii = rr / (unsigned)F.ny;
+      const unsigned pb = ((ii >> 1) * (unsigned)C.ny + (jj >> 1)) * (unsigned)C.nz + (kk >> 1);
+      ldv<T>(at(x, f), o);
+#pragma unroll
+      for (int v = 0; v < V; ++v) o[v] += *at(xc, pb + (v >> 1));
+    };
+    march_rb<T, NT, true>(F, r, w, c0, row, outf);
+  } else if constexpr (MODE == RB_GEN) {
+    march_rb<T, NT, true>(F, r, w, c0, [&](unsigned f, T(&o)[V]) { ldv<T>(at(x, f), o); }, outf);
+  } else {
+    march_rb<T, NT, false>(F, r, w, c0, [&](unsigned, T(&o)[V]) {}, outf);
+  }
   if (DOT) publish_rz<NT>(acc, st, partials, counter, first);
 }
 
@@ -1673,6 +1919,59 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
       else k_mg_smooth<T, false><<<nb, BLOCK, 0, s>>>(L, r, a, b, om, st, partials, counter, 0);
     }
   };
+  const Lev<T> Mr = vec ? march_lev(L, 1, H.rb_threads) : L;   // the coloured sweeps' view and grid
+  if (vec && H.rb && !coarsest && rb_marching_ok(Mr, H.rb_min_planes)) {
+    // coloured sweeps: pre-smoothing from x = 0 relaxing the even colour
+    // first, post-smoothing (the first with the prolongation) the odd one
+    const int nr = H.nu_rb;
+    const int nbr = march_blocks(Mr);
+    const T w = (T)H.w_rb;
+    const Lev<T>& C = H.lev[l + 1];
+    auto rb = [&](int mode, bool d, const T* xin, const T* xcs, T* xo, int c0) {
+      with_nt(Mr.mnt, [&](auto K) {
+        constexpr int NT = decltype(K)::value;
+        if (mode == RB_ZERO)
+          k_mg_rb_v<T, RB_ZERO, false, NT><<<nbr, NT, 0, s>>>(Mr, C, r, nullptr, nullptr, xo, w, c0, st, partials,
+                                                              counter, 0);
+        else if (mode == RB_PROLONG && d)
+          k_mg_rb_v<T, RB_PROLONG, true, NT><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st, partials, counter,
+                                                                dot_first);
+        else if (mode == RB_PROLONG)
+          k_mg_rb_v<T, RB_PROLONG, false, NT><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st, partials,
+                                                                 counter, 0);
+        else if (d)
+          k_mg_rb_v<T, RB_GEN, true, NT><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st, partials, counter,
+                                                            dot_first);
+        else
+          k_mg_rb_v<T, RB_GEN, false, NT><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st, partials, counter,
+                                                             0);
+      });
+    };
+    rb(RB_ZERO, false, nullptr, nullptr, a, 0);
+    for (int t = 1; t < nr; ++t) {
+      rb(RB_GEN, false, a, nullptr, b, 0);
+      std::swap(a, b);
+    }
+    if (restrict_marching_ok(L)) {
+      const Lev<T> Mp = march_lev_pairs(L);
+      with_nt(Mp.mnt, [&](auto K) {
+        constexpr int NT = decltype(K)::value;
+        k_mg_restrict_m<T, NT><<<march_blocks(Mp), NT, 0, s>>>(Mp, C, r, a, H.r[l + 1], st);
+      });
+    } else {
+      Lev<T> G = C;
+      G.nz = L.nz;
+      k_mg_restrict_v<T><<<vec_blocks(vec_items(G)), BLOCK, 0, s>>>(L, C, r, a, H.r[l + 1], st);
+    }
+    T* xc = nullptr;
+    mg_vcycle(H, l + 1, H.r[l + 1], st, partials, counter, false, false, s, &xc);
+    for (int t = 0; t < nr; ++t) {
+      rb(t == 0 ? RB_PROLONG : RB_GEN, dot && t == nr - 1, a, xc, b, 1);
+      std::swap(a, b);
+    }
+    *out = a;
+    return;
+  }
   if (coarsest && L.n <= COARSE_MAX) {
     if (dot) k_mg_coarse<T, true><<<1, BLOCK, 0, s>>>(L, r, a, om, pre, st, partials, counter, dot_first);
     else k_mg_coarse<T, false><<<1, BLOCK, 0, s>>>(L, r, a, om, pre, st, partials, counter, 0);
@@ -1873,16 +2172,27 @@ double replay_operator_kernel(const Lev<T>& L, const T* z, const T* pin, T* pout
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
   return 1e3 * (double)ms / reps;
 }
-// Back-to-back launches of the fine level's damped-Jacobi sweep (the
-// multigrid smoother) between two events; mean duration in microseconds.
+// Back-to-back launches of the fine level's smoother sweep as the V-cycle of
+// hierarchy H runs it there (a coloured sweep from x where the level takes
+// them, else damped Jacobi) between two events; mean duration in microseconds.
 template <class T>
-double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, SolveStatus* st, int reps,
-                            double omega, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+double replay_smooth_kernel(const Lev<T>& L, const MgHier<T>& H, const T* r, const T* xin, T* xout, SolveStatus* st,
+                            int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const bool vec = use_vec(L);
   const Lev<T> M = vec ? march_lev(L, 1) : L;
   const int nb = vec ? march_blocks(M) : tile_blocks(L.ntiles);
+  const double omega = H.omega;
+  const Lev<T> Mr = vec ? march_lev(L, 1, H.rb_threads) : L;
+  const bool rb = vec && H.rb && rb_marching_ok(Mr, H.rb_min_planes);
+  const int nbr = rb ? march_blocks(Mr) : 0;
   auto launch = [&]() {
-    if (vec) {
+    if (rb) {
+      with_nt(Mr.mnt, [&](auto K) {
+        constexpr int NT = decltype(K)::value;
+        k_mg_rb_v<T, RB_GEN, false, NT><<<nbr, NT, 0, s>>>(Mr, Mr, r, xin, nullptr, xout, (T)H.w_rb, 0, st, nullptr,
+                                                           nullptr, 0);
+      });
+    } else if (vec) {
       with_nt(M.mnt, [&](auto K) {
         constexpr int NT = decltype(K)::value;
         k_mg_smooth_v<T, false, NT><<<nb, NT, 0, s>>>(M, r, xin, xout, (T)omega, st, nullptr, nullptr, 0);
@@ -1899,10 +2209,10 @@ double replay_smooth_kernel(const Lev<T>& L, const T* r, const T* xin, T* xout, 
   if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
   return 1e3 * (double)ms / reps;
 }
-template double replay_smooth_kernel<double>(const Lev<double>&, const double*, const double*, double*, SolveStatus*,
-                                             int, double, hipStream_t, hipEvent_t, hipEvent_t);
-template double replay_smooth_kernel<float>(const Lev<float>&, const float*, const float*, float*, SolveStatus*, int,
-                                            double, hipStream_t, hipEvent_t, hipEvent_t);
+template double replay_smooth_kernel<double>(const Lev<double>&, const MgHier<double>&, const double*, const double*,
+                                             double*, SolveStatus*, int, hipStream_t, hipEvent_t, hipEvent_t);
+template double replay_smooth_kernel<float>(const Lev<float>&, const MgHier<float>&, const float*, const float*, float*,
+                                            SolveStatus*, int, hipStream_t, hipEvent_t, hipEvent_t);
 
 template double replay_operator_kernel<double>(const Lev<double>&, const double*, const double*, double*, double*,
                                                SolveStatus*, double*, unsigned*, int, hipStream_t, hipEvent_t,
