@@ -570,10 +570,10 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   HIPCHK(g, hipGetLastError());
   if ((st = sync_status(g, sys, s)) != DS_OK) return st;
   if (!g->h_status[sys].done) {
-    CgVecs<double> V{x, g->r, g->pd, g->p_alt, g->q};
+    CgVecsMg32 V{x, g->r, g->p32, g->p32alt, g->q};
     // iteration t writes its direction into p_odd (t odd) or p_even (t even)
-    double* const p_odd = V.p_alt;
-    double* const p_even = V.p;
+    float* const p_odd = V.p_alt;
+    float* const p_even = V.p;
     float* z = nullptr;
     cg_start_mg32(L, H, g->r, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, s, true);
     bool first = true;
@@ -1192,10 +1192,10 @@ int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* byte
       L.qc = g->qc;
       L.diag = g->diag;
       pressure_type(g, 2, L);
-      us = replay_operator_z32(L, g->r32, g->pd, g->p_alt, g->q, st, g->partials, g->counters + CT_MISC, reps, s,
+      us = replay_operator_z32(L, g->r32, g->p32, g->p32alt, g->q, st, g->partials, g->counters + CT_MISC, reps, s,
                                g->ev[0], g->ev[1]);
-      // z (FP32), p, q read; p, q written (diag formed from q)
-      if (bytes_per_launch) *bytes_per_launch = 36.0 * (double)g->n;
+      // z and p (FP32), q_coef read; p (FP32), q written (diag formed from q_coef)
+      if (bytes_per_launch) *bytes_per_launch = 28.0 * (double)g->n;
     } else {
       us = replay_operator_kernel<float>(F, g->r32, g->p32, g->p32alt, g->q32, st, g->partials,
                                          g->counters + CT_MISC, reps, s, g->ev[0], g->ev[1]);

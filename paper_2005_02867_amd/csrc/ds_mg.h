@@ -89,6 +89,20 @@ struct CgVecs {
   T* r_alt = nullptr;
 };
 
+// Vectors of the precision form's multigrid CG: FP64 solution, residual and
+// q = A p; the directions in FP32.  x and r are updated with the same
+// FP32 p and q is formed from it in FP64, so the residual recurrence keeps
+// FP64 accuracy.
+struct CgVecsMg32 {
+  double* x;
+  double* r;
+  float* p;
+  float* p_alt;
+  double* q;
+};
+// x += st->alpha p with an FP32 p (the last deferred update of that CG).
+void launch_axpy_alpha(double* x, const float* p, const SolveStatus* st, long long n, hipStream_t s);
+
 // dirmask bit (axis*2 + side) set: p_rgh = 0 on that box face.  Every level
 // (the finest included) is marked to form its diagonal from q on the fly;
 // the coarse levels' stored diagonals are computed here.
@@ -134,7 +148,7 @@ void set_march_min_planes(int n);
 // Block sizes (256, 384, 512) the marching kernels of class cls try in order
 // (0: CG operator and FP64 residual, 1: V-cycle sweeps and restriction).
 void set_march_pref(int cls, const int* nts, int n);
-double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
+double replay_operator_z32(const Lev<double>& L, const float* z, const float* pin, float* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1);
 // r32_ready: r32 already holds r64 in FP32 (launch_resid64 wrote it).
@@ -143,7 +157,7 @@ void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, fl
 // The iteration's solution update is deferred: iteration t applies
 // x += alpha_{t-1} p_{t-1}; after the last iteration t = it, launch_axpy_alpha
 // with the direction buffer of that iteration applies alpha_it p_it.
-void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V, float* r32, float** z,
+void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecsMg32& V, float* r32, float** z,
                        SolveStatus* st, double* partials, unsigned* counters, bool first, hipStream_t s);
 template <class T>
 void launch_axpy_alpha(T* x, const T* p, const SolveStatus* st, long long n, hipStream_t s);

@@ -1610,26 +1610,30 @@ VEC_KERNEL k_cg_update_r32_v(Lev<double> L, double* __restrict__ r, const double
 // solution update (alpha_prev is still in st->alpha when this kernel starts;
 // its last block replaces it).
 template <bool FIRST, int NT>
-VEC_KERNEL_M k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const double* __restrict__ pin,
-                               double* __restrict__ pout, double* __restrict__ q, SolveStatus* st,
+VEC_KERNEL_M k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const float* __restrict__ pin,
+                               float* __restrict__ pout, double* __restrict__ q, SolveStatus* st,
                                double* partials, unsigned* counter, double* __restrict__ x) {
   if (st->done) return;
   constexpr int V = VW<double>::n;
   const double be = FIRST ? 0.0 : st->beta;
   const double ap = FIRST ? 0.0 : st->alpha;
   double acc[1] = {0.0};
+  // p = z + beta p_old formed in FP64 and stored in FP32; the operator, q and
+  // the dot products use that FP32 value exactly (every thread rounds alike)
   auto pnv = [&](unsigned f, double(&o)[V]) {
     const float2 zf = *reinterpret_cast<const float2*>(at(z, f));
-    o[0] = (double)zf.x;
-    o[1] = (double)zf.y;
-    if (!FIRST) {
-      double pv[V];
-      ldv<double>(at(pin, f), pv);
-#pragma unroll
-      for (int v = 0; v < V; ++v) o[v] = o[v] + be * pv[v];
+    if (FIRST) {
+      o[0] = (double)zf.x;
+      o[1] = (double)zf.y;
+    } else {
+      const float2 pf = *reinterpret_cast<const float2*>(at(pin, f));
+      o[0] = (double)(float)((double)zf.x + be * (double)pf.x);
+      o[1] = (double)(float)((double)zf.y + be * (double)pf.y);
     }
   };
-  auto pns = [&](unsigned f) -> double { return FIRST ? (double)*at(z, f) : (double)*at(z, f) + be * *at(pin, f); };
+  auto pns = [&](unsigned f) -> double {
+    return FIRST ? (double)*at(z, f) : (double)(float)((double)*at(z, f) + be * (double)*at(pin, f));
+  };
   march<double, NT>(L, pnv, pns,
                 [&](unsigned c, const double(&qv)[V], const double(&pc)[V], const double(&off)[V],
                     const double(&dv)[V]) {
@@ -1639,14 +1643,14 @@ VEC_KERNEL_M k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, con
       y[v] = dv[v] * pc[v] - 0.5 * L.sc * off[v];
       acc[0] += pc[v] * y[v];
     }
-    stv<double>(at(pout, c), pc);
+    *reinterpret_cast<float2*>(at(pout, c)) = make_float2((float)pc[0], (float)pc[1]);
     stv<double>(at(q, c), y);
     if (!FIRST && x) {
-      double xv[V], pv[V];
+      double xv[V];
       ldv<double>(at(x, c), xv);
-      ldv<double>(at(pin, c), pv);
-#pragma unroll
-      for (int v = 0; v < V; ++v) xv[v] += ap * pv[v];
+      const float2 pf = *reinterpret_cast<const float2*>(at(pin, c));
+      xv[0] += ap * (double)pf.x;
+      xv[1] += ap * (double)pf.y;
       stv<double>(at(x, c), xv);
     }
   });
@@ -1673,6 +1677,16 @@ void launch_axpy_alpha(T* x, const T* p, const SolveStatus* st, long long n, hip
 }
 template void launch_axpy_alpha<double>(double*, const double*, const SolveStatus*, long long, hipStream_t);
 template void launch_axpy_alpha<float>(float*, const float*, const SolveStatus*, long long, hipStream_t);
+__global__ void k_axpy_alpha_p32(double* __restrict__ x, const float* __restrict__ p, const SolveStatus* st,
+                                 long long n) {
+  const double a = st->alpha;
+  long long b0, b1;
+  block_range(n, b0, b1);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) x[e] += a * (double)p[e];
+}
+void launch_axpy_alpha(double* x, const float* p, const SolveStatus* st, long long n, hipStream_t s) {
+  k_axpy_alpha_p32<<<grid_blocks(n), BLOCK, 0, s>>>(x, p, st, n);
+}
 
 // x += e; with p, first e += alpha p (the inner solve's last deferred update,
 // alpha from st), as launch_axpy_alpha followed by the plain correction.
@@ -2272,7 +2286,7 @@ void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, fl
   if (!r32_ready) k_to_float<<<grid_blocks(L.n), BLOCK, 0, s>>>(r64, r32, L.n);
   mg_vcycle(H, 0, r32, st, partials, counters + 2, true, true, s, z);
 }
-void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V, float* r32, float** z,
+void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecsMg32& V, float* r32, float** z,
                        SolveStatus* st, double* partials, unsigned* counters, bool first, hipStream_t s) {
   const int nb = vec_blocks(vec_items(L));
   const Lev<double> M = march_lev(L);
@@ -2287,7 +2301,7 @@ void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecs<double>& V
   mg_vcycle(H, 0, r32, st, partials, counters + 2, false, true, s, z);
 }
 bool mg32_supported(const Lev<double>& L) { return use_vec(L); }
-double replay_operator_z32(const Lev<double>& L, const float* z, const double* pin, double* pout, double* q,
+double replay_operator_z32(const Lev<double>& L, const float* z, const float* pin, float* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1) {
   const Lev<double> M = march_lev(L);
