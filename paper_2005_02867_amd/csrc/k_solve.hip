@@ -1035,8 +1035,8 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
     const unsigned cj = j * sy + kv * V;
     const unsigned s0 = i0 > 0 ? i0 - 1 : 0;
     // q of planes s-2, s-1, s; x0 of s-1, s; colour-A results of s-2, s-1;
-    // r, diag and the y-neighbour term of s-1
-    T qa[V], qb[V], qc[V], xb[V], xc[V], ma[V], mb[V], rb[V], db[V], yb[V];
+    // r, 1/diag and the y-neighbour term of s-1
+    T qa[V], qb[V], qc[V], xb[V], xc[V], ma[V], mb[V], rb[V], ib[V], yb[V];
     {
       const unsigned fb = (s0 > 0 ? s0 - 1 : s0) * P + cj, fc = s0 * P + cj;
       ldv<T>(at(L.qc, fb), qb);
@@ -1054,7 +1054,7 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       zero(rb);
       zero(yb);
 #pragma unroll
-      for (int v = 0; v < V; ++v) db[v] = 1;
+      for (int v = 0; v < V; ++v) ib[v] = 1;
     }
     for (unsigned s = s0; s <= i1; ++s) {
       const bool live = s < nx;   // s == nx only finishes plane nx - 1
@@ -1092,8 +1092,9 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       }
       const T qzm = lane_up(qc[V - 1]), qzp = lane_down(qc[0]);
       const T xzm = lane_up(xc[V - 1]), xzp = lane_down(xc[0]);
-      // the y-neighbour term and diag of plane s
-      T yc[V], dc[V];
+      // the y-neighbour term and 1/diag of plane s (diag formed in T from q:
+      // the smoother's own diagonal, consistent within the sweep)
+      T yc[V], ic[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         T ty = 0;
@@ -1102,70 +1103,80 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
         yc[v] = ty;
       }
       if (L.dfly) {
-        const double sc = (double)L.sc;
         const int dm = L.dmask;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          const double q = (double)qc[v], bnd = 2.0 * sc * q;
-          double d = 0.0;
-          d += hxm ? sc * 0.5 * (q + (double)qb[v]) : ((dm & 1) ? bnd : 0.0);
-          d += hxp ? sc * 0.5 * (q + (double)qd[v]) : ((dm & 2) ? bnd : 0.0);
-          d += hym ? sc * 0.5 * (q + (double)nqm[v]) : ((dm & 4) ? bnd : 0.0);
-          d += hyp ? sc * 0.5 * (q + (double)nqp[v]) : ((dm & 8) ? bnd : 0.0);
+          const T q = qc[v], bnd = T(2) * L.sc * q;
+          T d = 0;
+          d += hxm ? hs * (q + qb[v]) : ((dm & 1) ? bnd : T(0));
+          d += hxp ? hs * (q + qd[v]) : ((dm & 2) ? bnd : T(0));
+          d += hym ? hs * (q + nqm[v]) : ((dm & 4) ? bnd : T(0));
+          d += hyp ? hs * (q + nqp[v]) : ((dm & 8) ? bnd : T(0));
           const bool em = v > 0 || hzm, ep = v < V - 1 || hzp;
-          const double gm = v > 0 ? (double)qc[v > 0 ? v - 1 : 0] : (double)qzm;
-          const double gp = v < V - 1 ? (double)qc[v < V - 1 ? v + 1 : V - 1] : (double)qzp;
-          d += em ? sc * 0.5 * (q + gm) : ((dm & 16) ? bnd : 0.0);
-          d += ep ? sc * 0.5 * (q + gp) : ((dm & 32) ? bnd : 0.0);
-          dc[v] = (T)d;
+          const T gm = v > 0 ? qc[v > 0 ? v - 1 : 0] : qzm;
+          const T gp = v < V - 1 ? qc[v < V - 1 ? v + 1 : V - 1] : qzp;
+          d += em ? hs * (q + gm) : ((dm & 16) ? bnd : T(0));
+          d += ep ? hs * (q + gp) : ((dm & 32) ? bnd : T(0));
+          ic[v] = T(1) / d;
         }
       } else {
-        ldv<T>(at(L.diag, c), dc);
-      }
-      // colour A on plane s, from x0 (all neighbours old)
-      T mc[V];
-      {
-        T off[V];
+        T dl[V];
+        ldv<T>(at(L.diag, c), dl);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          T o = yc[v];
-          o = hxm ? o + (qc[v] + qb[v]) * xb[v] : o;
-          o = hxp ? o + (qc[v] + qd[v]) * xd[v] : o;
-          const T gm = v > 0 ? qc[v > 0 ? v - 1 : 0] : qzm, xm = v > 0 ? xc[v > 0 ? v - 1 : 0] : xzm;
-          const T gp = v < V - 1 ? qc[v < V - 1 ? v + 1 : V - 1] : qzp;
-          const T xp = v < V - 1 ? xc[v < V - 1 ? v + 1 : V - 1] : xzp;
-          o = (v > 0 || hzm) ? o + (qc[v] + gm) * xm : o;
-          o = (v < V - 1 || hzp) ? o + (qc[v] + gp) * xp : o;
-          off[v] = o;
-        }
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const T nv = xc[v] + w * (rc[v] - (dc[v] * xc[v] - hs * off[v])) / dc[v];
-          mc[v] = (((s + (unsigned)v + (unsigned)c0) & 1u) == 0u) ? nv : xc[v];
-        }
+        for (int v = 0; v < V; ++v) ic[v] = T(1) / dl[v];
       }
-      // colour B on plane s - 1, from colour A's new values (y old)
       const T mzm = lane_up(mb[V - 1]), mzp = lane_down(mb[0]);
       const T bqzm = lane_up(qb[V - 1]), bqzp = lane_down(qb[0]);
-      if (s > i0) {
-        const unsigned sb = s - 1;
-        const bool bxm = sb > 0, bxp = s < nx;
-        T o[V];
+      const T w1 = T(1) - w;
+      T mc[V];
+      // x + w (r - A x)/d = (1 - w) x + w (r + sc/2 off)/d, off the neighbour
+      // sum.  The lanes of colour A on plane s are those of colour B on plane
+      // s - 1 (v of parity s + c0); each lane evaluates only its colour.
+      auto relax = [&](auto PA) {
+        constexpr unsigned pa = decltype(PA)::value;
+        // colour A on plane s, from x0 (all neighbours old)
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          T f = yb[v];
-          f = bxm ? f + (qb[v] + qa[v]) * ma[v] : f;
-          f = bxp ? f + (qb[v] + qc[v]) * mc[v] : f;
-          const T gm = v > 0 ? qb[v > 0 ? v - 1 : 0] : bqzm, xm = v > 0 ? mb[v > 0 ? v - 1 : 0] : mzm;
-          const T gp = v < V - 1 ? qb[v < V - 1 ? v + 1 : V - 1] : bqzp;
-          const T xp = v < V - 1 ? mb[v < V - 1 ? v + 1 : V - 1] : mzp;
-          f = (v > 0 || hzm) ? f + (qb[v] + gm) * xm : f;
-          f = (v < V - 1 || hzp) ? f + (qb[v] + gp) * xp : f;
-          const T nv = mb[v] + w * (rb[v] - (db[v] * mb[v] - hs * f)) / db[v];
-          o[v] = (((sb + (unsigned)v + (unsigned)c0) & 1u) != 0u) ? nv : mb[v];
+          if (((unsigned)v & 1u) == pa) {
+            T o = yc[v];
+            o = hxm ? o + (qc[v] + qb[v]) * xb[v] : o;
+            o = hxp ? o + (qc[v] + qd[v]) * xd[v] : o;
+            const T gm = v > 0 ? qc[v > 0 ? v - 1 : 0] : qzm, xm = v > 0 ? xc[v > 0 ? v - 1 : 0] : xzm;
+            const T gp = v < V - 1 ? qc[v < V - 1 ? v + 1 : V - 1] : qzp;
+            const T xp = v < V - 1 ? xc[v < V - 1 ? v + 1 : V - 1] : xzp;
+            o = (v > 0 || hzm) ? o + (qc[v] + gm) * xm : o;
+            o = (v < V - 1 || hzp) ? o + (qc[v] + gp) * xp : o;
+            mc[v] = w1 * xc[v] + w * ic[v] * (rc[v] + hs * o);
+          } else {
+            mc[v] = xc[v];
+          }
         }
-        out(sb * P + cj, o, rb);
-      }
+        // colour B on plane s - 1, from colour A's new values (y old)
+        if (s > i0) {
+          const unsigned sb = s - 1;
+          const bool bxm = sb > 0, bxp = s < nx;
+          T o[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            if (((unsigned)v & 1u) == pa) {
+              T f = yb[v];
+              f = bxm ? f + (qb[v] + qa[v]) * ma[v] : f;
+              f = bxp ? f + (qb[v] + qc[v]) * mc[v] : f;
+              const T gm = v > 0 ? qb[v > 0 ? v - 1 : 0] : bqzm, xm = v > 0 ? mb[v > 0 ? v - 1 : 0] : mzm;
+              const T gp = v < V - 1 ? qb[v < V - 1 ? v + 1 : V - 1] : bqzp;
+              const T xp = v < V - 1 ? mb[v < V - 1 ? v + 1 : V - 1] : mzp;
+              f = (v > 0 || hzm) ? f + (qb[v] + gm) * xm : f;
+              f = (v < V - 1 || hzp) ? f + (qb[v] + gp) * xp : f;
+              o[v] = w1 * mb[v] + w * ib[v] * (rb[v] + hs * f);
+            } else {
+              o[v] = mb[v];
+            }
+          }
+          out(sb * P + cj, o, rb);
+        }
+      };
+      if (((s + (unsigned)c0) & 1u) == 0u) relax(std::integral_constant<unsigned, 0>{});
+      else relax(std::integral_constant<unsigned, 1>{});
       copy(qa, qb);
       copy(qb, qc);
       copy(qc, qd);
@@ -1174,7 +1185,7 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       copy(ma, mb);
       copy(mb, mc);
       copy(rb, rc);
-      copy(db, dc);
+      copy(ib, ic);
       copy(yb, yc);
     }
   }
