@@ -212,6 +212,7 @@ __device__ __forceinline__ void advect_cell(const DevParams& P, const int (&pos)
                                             const double (&PH)[3][2], const bool (&h)[3][4], bool has_phi,
                                             double cv, double (&acc)[2], double& an, double& cn, double& tn) {
   const int nn[3] = {P.nx, P.ny, P.nz};
+  const double ih = 1.0 / P.h;
   double da = 0.0, dc = 0.0, dT = 0.0;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
@@ -232,11 +233,11 @@ __device__ __forceinline__ void advect_cell(const DevParams& P, const int (&pos)
       if (has_phi) {
         double ul;
         if (sd == 0)
-          ul = in ? ufv - (P0 - PH[ax][0]) / P.h
-                  : (pressure_dirichlet(P.kind[ax * 2]) ? ufv - 2.0 * P0 / P.h : ufv);
+          ul = in ? ufv - (P0 - PH[ax][0]) * ih
+                  : (pressure_dirichlet(P.kind[ax * 2]) ? ufv - 2.0 * P0 * ih : ufv);
         else
-          ul = in ? ufv - (PH[ax][1] - P0) / P.h
-                  : (pressure_dirichlet(P.kind[ax * 2 + 1]) ? ufv + 2.0 * P0 / P.h : ufv);
+          ul = in ? ufv - (PH[ax][1] - P0) * ih
+                  : (pressure_dirichlet(P.kind[ax * 2 + 1]) ? ufv + 2.0 * P0 * ih : ufv);
         F[sd] = ul * (in ? face(A[ax], A0, ul) : box_face(A0, 0.0, ul, sd));
       } else {
         F[sd] = ufv * af;
@@ -470,7 +471,7 @@ template <int AX>
 __device__ __forceinline__ double predictor_face(const DevParams& P, const double* __restrict__ a_new,
                                                  const double* __restrict__ xi, const double* __restrict__ u,
                                                  const double* __restrict__ v, const double* __restrict__ w, int i,
-                                                 int j, int k) {
+                                                 int j, int k, double ih) {
   const int fx = P.nx + (AX == 0), fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
   (void)fx;
   const double* F = AX == 0 ? u : (AX == 1 ? v : w);
@@ -486,7 +487,7 @@ __device__ __forceinline__ double predictor_face(const DevParams& P, const doubl
   const long long sx = (long long)fy * fz, sy = fz, sz = 1;
   const long long sA = AX == 0 ? sx : (AX == 1 ? sy : sz);
   // normal advection, first-order upwind
-  const double back = (uc - F[e - sA]) / P.h, fwd = (F[e + sA] - uc) / P.h;
+  const double back = (uc - F[e - sA]) * ih, fwd = (F[e + sA] - uc) * ih;
   double adv = uc * (uc > 0.0 ? back : fwd);
   // cells on both sides of the face
   const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
@@ -507,7 +508,7 @@ __device__ __forceinline__ double predictor_face(const DevParams& P, const doubl
     const long long sb = bx == 0 ? sx : (bx == 1 ? sy : sz);
     const double lo = pb >= 1 ? F[e - sb] : uc;
     const double hi = pb <= nb_ - 2 ? F[e + sb] : uc;
-    const double d = vb > 0.0 ? (uc - lo) / P.h : (hi - uc) / P.h;
+    const double d = (vb > 0.0 ? uc - lo : hi - uc) * ih;
     adv += vb * d;
   }
   const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
@@ -518,7 +519,7 @@ __device__ __forceinline__ double predictor_face(const DevParams& P, const doubl
   const double yf = (AX == 1 ? j : j + 0.5) * P.h - P.x0[1];
   const double zf = (AX == 2 ? k : k + 0.5) * P.h - P.x0[2];
   const double gr = P.g[0] * xf + P.g[1] * yf + P.g[2] * zf;
-  const double force = -gr * (rR - rL) / P.h * bf + 0.5 * (aL + aR) * (xi[cR] - xi[cL]) / P.h;
+  const double force = -gr * (rR - rL) * ih * bf + 0.5 * (aL + aR) * (xi[cR] - xi[cL]) * ih;
   return uc - P.dt * adv + P.dt * force;
 }
 
@@ -532,15 +533,16 @@ __global__ void k_predictor(DevParams P, const double* __restrict__ a_new, const
                             double* __restrict__ ws) {
   long long b0, b1;
   block_range(P.n, b0, b1);
+  const double ih = 1.0 / P.h;
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
-    us[uidx(P, i, j, k)] = predictor_face<0>(P, a_new, xi, u, v, w, i, j, k);
-    vs[vidx(P, i, j, k)] = predictor_face<1>(P, a_new, xi, u, v, w, i, j, k);
-    ws[widx(P, i, j, k)] = predictor_face<2>(P, a_new, xi, u, v, w, i, j, k);
-    if (i == P.nx - 1) us[uidx(P, P.nx, j, k)] = predictor_face<0>(P, a_new, xi, u, v, w, P.nx, j, k);
-    if (j == P.ny - 1) vs[vidx(P, i, P.ny, k)] = predictor_face<1>(P, a_new, xi, u, v, w, i, P.ny, k);
-    if (k == P.nz - 1) ws[widx(P, i, j, P.nz)] = predictor_face<2>(P, a_new, xi, u, v, w, i, j, P.nz);
+    us[uidx(P, i, j, k)] = predictor_face<0>(P, a_new, xi, u, v, w, i, j, k, ih);
+    vs[vidx(P, i, j, k)] = predictor_face<1>(P, a_new, xi, u, v, w, i, j, k, ih);
+    ws[widx(P, i, j, k)] = predictor_face<2>(P, a_new, xi, u, v, w, i, j, k, ih);
+    if (i == P.nx - 1) us[uidx(P, P.nx, j, k)] = predictor_face<0>(P, a_new, xi, u, v, w, P.nx, j, k, ih);
+    if (j == P.ny - 1) vs[vidx(P, i, P.ny, k)] = predictor_face<1>(P, a_new, xi, u, v, w, i, P.ny, k, ih);
+    if (k == P.nz - 1) ws[widx(P, i, j, P.nz)] = predictor_face<2>(P, a_new, xi, u, v, w, i, j, P.nz, ih);
   }
 }
 
@@ -552,6 +554,7 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
                                  double* __restrict__ diag, double* __restrict__ b, F32Out fo) {
   long long b0, b1;
   block_range(P.n, b0, b1);
+  const double ih = 1.0 / P.h;
   const double sc = P.dt / (P.h * P.h);
   const double Ssc = 1.0 / P.rho_G - 1.0 / P.rho_L;
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
@@ -578,7 +581,7 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
       }
     const double div = ((us[uidx(P, i + 1, j, k)] - us[uidx(P, i, j, k)]) +
                         (vs[vidx(P, i, j + 1, k)] - vs[vidx(P, i, j, k)]) +
-                        (ws[widx(P, i, j, k + 1)] - ws[widx(P, i, j, k)])) / P.h;
+                        (ws[widx(P, i, j, k + 1)] - ws[widx(P, i, j, k)])) * ih;
     qc[c] = beta;
     diag[c] = d;
     b[c] = mdot[c] * Ssc - div;
@@ -598,6 +601,7 @@ __global__ void k_div_setup(DevParams P, const double* __restrict__ u, const dou
                             double* __restrict__ b, F32Out fo) {
   long long b0, b1;
   block_range(P.n, b0, b1);
+  const double ih = 1.0 / P.h;
   const double ih2 = 1.0 / (P.h * P.h);
   const double q = 1.0 / P.dt, q32 = (double)(float)q;
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
@@ -617,7 +621,7 @@ __global__ void k_div_setup(DevParams P, const double* __restrict__ u, const dou
         }
       }
     const double div = ((u[uidx(P, i + 1, j, k)] - u[uidx(P, i, j, k)]) + (v[vidx(P, i, j + 1, k)] - v[vidx(P, i, j, k)]) +
-                        (w[widx(P, i, j, k + 1)] - w[widx(P, i, j, k)])) / P.h;
+                        (w[widx(P, i, j, k + 1)] - w[widx(P, i, j, k)])) * ih;
     qc[c] = q;
     diag[c] = d;
     b[c] = -div;
@@ -634,7 +638,7 @@ __global__ void k_div_setup(DevParams P, const double* __restrict__ u, const dou
 template <int AX>
 __device__ __forceinline__ double project_face(const DevParams& P, const double* __restrict__ a_new,
                                                const double* __restrict__ p, const double* __restrict__ Fs, int i,
-                                               int j, int k) {
+                                               int j, int k, double ih) {
   const int fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
   const long long e = ((long long)i * fy + j) * fz + k;
   const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
@@ -648,13 +652,13 @@ __device__ __forceinline__ double project_face(const DevParams& P, const double*
     const int kc = AX == 2 ? (side ? k - 1 : k) : k;
     const long long c = cidx(P, ic, jc, kc);
     const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, P.rho_G);
-    return side ? us + 2.0 * P.dt * beta * p[c] / P.h : us - 2.0 * P.dt * beta * p[c] / P.h;
+    return side ? us + 2.0 * P.dt * beta * p[c] * ih : us - 2.0 * P.dt * beta * p[c] * ih;
   }
   const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
   const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
   const double bL = 1.0 / mix(clamp01(a_new[cL]), P.rho_L, P.rho_G);
   const double bR = 1.0 / mix(clamp01(a_new[cR]), P.rho_L, P.rho_G);
-  return us - P.dt * 0.5 * (bL + bR) * (p[cR] - p[cL]) / P.h;
+  return us - P.dt * 0.5 * (bL + bR) * (p[cR] - p[cL]) * ih;
 }
 
 // All three face arrays in one pass over the cells (as the predictor).
@@ -664,15 +668,16 @@ __global__ void k_project(DevParams P, const double* __restrict__ a_new, const d
                           double* __restrict__ w) {
   long long b0, b1;
   block_range(P.n, b0, b1);
+  const double ih = 1.0 / P.h;
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
-    u[uidx(P, i, j, k)] = project_face<0>(P, a_new, p, us, i, j, k);
-    v[vidx(P, i, j, k)] = project_face<1>(P, a_new, p, vs, i, j, k);
-    w[widx(P, i, j, k)] = project_face<2>(P, a_new, p, ws, i, j, k);
-    if (i == P.nx - 1) u[uidx(P, P.nx, j, k)] = project_face<0>(P, a_new, p, us, P.nx, j, k);
-    if (j == P.ny - 1) v[vidx(P, i, P.ny, k)] = project_face<1>(P, a_new, p, vs, i, P.ny, k);
-    if (k == P.nz - 1) w[widx(P, i, j, P.nz)] = project_face<2>(P, a_new, p, ws, i, j, P.nz);
+    u[uidx(P, i, j, k)] = project_face<0>(P, a_new, p, us, i, j, k, ih);
+    v[vidx(P, i, j, k)] = project_face<1>(P, a_new, p, vs, i, j, k, ih);
+    w[widx(P, i, j, k)] = project_face<2>(P, a_new, p, ws, i, j, k, ih);
+    if (i == P.nx - 1) u[uidx(P, P.nx, j, k)] = project_face<0>(P, a_new, p, us, P.nx, j, k, ih);
+    if (j == P.ny - 1) v[vidx(P, i, P.ny, k)] = project_face<1>(P, a_new, p, vs, i, P.ny, k, ih);
+    if (k == P.nz - 1) w[widx(P, i, j, P.nz)] = project_face<2>(P, a_new, p, ws, i, j, P.nz, ih);
   }
 }
 
