@@ -137,6 +137,10 @@ typedef struct ds_diagnostics {
  *     form as FP64 CG with the FP32 V-cycle (0: FP32 rounds).
  *   DSVOF_NEUMANN [1]: energy and species CG preconditioned by the first-
  *     order Neumann polynomial of the Jacobi splitting (0: Jacobi).
+ *   DSVOF_GRAPHS [1]: the precision form's multigrid CG replays pairs of
+ *     iterations as HIP graphs, captured on a stream of the handle's own and
+ *     launched on the caller's (0: one launch at a time; same results bit
+ *     for bit).
  *   DSVOF_VEC_BLOCKS [1024], DSVOF_VEC_YTILE [0]: grid cap and y-slab of the
  *     z-vectorised pointwise kernels; DSVOF_MARCH_THREADS [262144],
  *     DSVOF_MARCH_MIN_PLANES [1]: threads and shortest x-chunk of the

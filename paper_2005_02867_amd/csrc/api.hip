@@ -81,7 +81,23 @@ struct ds_grid {
     double inner_min_jac = 1e-6;  // the same for the energy and species systems
     int mg32 = 1;                 // multigrid systems: FP64 CG with the FP32 V-cycle
     int neumann = 1;              // energy and species: Neumann-polynomial preconditioner (vectorised grids)
+    int graphs = 1;               // replay pairs of multigrid-CG iterations as HIP graphs
   } tune;
+  // Graphs of two FP32-multigrid CG iterations, keyed by what their launches
+  // hold: solution and direction buffers, V-cycle output, system scale.  The
+  // capture stream is the handle's own (default priority); replays go to the
+  // caller's stream.
+  struct Mg32Graph {
+    hipGraphExec_t ex = nullptr;
+    const void* x = nullptr;
+    const void* p = nullptr;
+    const void* z = nullptr;
+    double sc = 0.0;
+  };
+  static constexpr int NGRAPH = 8;
+  Mg32Graph graphs[NGRAPH];
+  int graph_next = 0;
+  hipStream_t cap_stream = nullptr;
   // live timing of the pressure solve's fine-level operator kernel
   static constexpr int NEV = 256;
   bool timing = false;
@@ -139,6 +155,14 @@ struct Layout {
     return ptr;
   }
 };
+
+// Graphs hold workspace addresses: dropped whenever the workspace is bound.
+void drop_graphs(ds_grid* g) {
+  for (auto& e : g->graphs) {
+    if (e.ex) (void)hipGraphExecDestroy(e.ex);
+    e = ds_grid::Mg32Graph{};
+  }
+}
 
 size_t carve(ds_grid* g, char* base) {
   Layout L;
@@ -544,6 +568,35 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
 // gradients (operator, vectors, dot products) with the V-cycle -- the bulk of
 // each iteration's memory traffic -- in FP32 on FP32 copies of the operator.
 // No restarts: the FP64 recurrence converges to tol like cg_solve64.
+// The graph of two FP32-multigrid CG iterations for the current buffers and
+// scale, captured on first use (null: capture failed; the caller then runs
+// the iterations one by one and graphs are switched off for the handle).
+hipGraphExec_t mg32_graph(ds_grid* g, const Lev<double>& L, MgHier<float>& H, const CgVecsMg32& V, float* z,
+                          SolveStatus* st, double sc) {
+  for (auto& e : g->graphs)
+    if (e.ex && e.x == V.x && e.p == V.p && e.z == z && e.sc == sc) return e.ex;
+  if (!g->cap_stream && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    g->cap_stream = nullptr;
+    g->tune.graphs = 0;
+    return nullptr;
+  }
+  hipGraphExec_t ex = capture_mg32_pair(L, H, V, g->r32, z, st, g->partials, g->counters + CT_SOLVE0, g->cap_stream);
+  if (!ex) {
+    g->tune.graphs = 0;
+    return nullptr;
+  }
+  auto& e = g->graphs[g->graph_next];
+  g->graph_next = (g->graph_next + 1) % ds_grid::NGRAPH;
+  if (e.ex) (void)hipGraphExecDestroy(e.ex);
+  e.ex = ex;
+  e.x = V.x;
+  e.p = V.p;
+  e.z = z;
+  e.sc = sc;
+  return ex;
+}
+
 int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
   int st;
   const int sys = 2;
@@ -579,10 +632,18 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
     bool first = true;
     while (!g->h_status[sys].done) {
       const int m = batch_size(batch_of(g, sys, x), first);
-      for (int t = 0; t < m; ++t) {
-        cg_iteration_mg32(L, H, V, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, first, s);
+      int t = 0;
+      if (first) {
+        cg_iteration_mg32(L, H, V, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, true, s);
         first = false;
+        ++t;
       }
+      hipGraphExec_t ex = nullptr;
+      for (; g->tune.graphs && t + 2 <= m; t += 2) {
+        if (!ex && !(ex = mg32_graph(g, L, H, V, z, ss, sc))) break;
+        HIPCHK(g, hipGraphLaunch(ex, s));
+      }
+      for (; t < m; ++t) cg_iteration_mg32(L, H, V, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, false, s);
       HIPCHK(g, hipGetLastError());
       if ((st = sync_status(g, sys, s)) != DS_OK) return st;
     }
@@ -953,6 +1014,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_INNER_MIN_JAC")) g->tune.inner_min_jac = atof(e);
   if (const char* e = getenv("DSVOF_MG32")) g->tune.mg32 = atoi(e);
   if (const char* e = getenv("DSVOF_NEUMANN")) g->tune.neumann = atoi(e);
+  if (const char* e = getenv("DSVOF_GRAPHS")) g->tune.graphs = atoi(e);
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {
     if (prm->pressure_precond == 1) build_hier(g->H32, nx, ny, nz, prm->h, prm->dt);
@@ -973,6 +1035,8 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
 
 int ds_destroy_grid(ds_grid* g) {
   if (!g) return DS_ERR_ARG;
+  drop_graphs(g);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   for (int e = 0; e < 2 * ds_grid::NEV; ++e)
     if (g->ev[e]) (void)hipEventDestroy(g->ev[e]);
   if (g->h_scal) (void)hipHostFree(g->h_scal);
@@ -994,6 +1058,7 @@ int ds_set_fields(ds_grid* g, const double* alpha, const double* T, const double
     return fail(g, DS_ERR_ARG, "workspace too small: %zu < %zu bytes", workspace_bytes, g->ws_bytes);
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(g, DS_ERR_ARG, "workspace not 256-byte aligned");
   hipStream_t s = S(stream);
+  drop_graphs(g);
   carve(g, static_cast<char*>(workspace));
   const size_t nb = g->n * sizeof(double);
   HIPCHK(g, hipMemcpyAsync(g->alpha, alpha, nb, hipMemcpyDeviceToDevice, s));

@@ -100,6 +100,10 @@ struct CgVecsMg32 {
   float* p_alt;
   double* q;
 };
+// Two non-first iterations of the FP32-multigrid CG captured on stream cs as
+// an executable graph (null on failure); z: the V-cycle output buffer.
+hipGraphExec_t capture_mg32_pair(const Lev<double>& L, MgHier<float>& H, CgVecsMg32 V, float* r32, float* z,
+                                 SolveStatus* st, double* partials, unsigned* counters, hipStream_t cs);
 // x += st->alpha p with an FP32 p (the last deferred update of that CG).
 void launch_axpy_alpha(double* x, const float* p, const SolveStatus* st, long long n, hipStream_t s);
 

@@ -2312,6 +2312,32 @@ void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecsMg32& V, fl
   mg_vcycle(H, 0, r32, st, partials, counters + 2, false, true, s, z);
 }
 bool mg32_supported(const Lev<double>& L) { return use_vec(L); }
+// Two non-first iterations of that CG recorded on the capture stream cs into
+// an executable graph (null if capture or instantiation fails).  Replaying it
+// advances the solve by two iterations: the direction buffers swap twice, so
+// the pointers the graph holds are those of the next pair again, and the
+// V-cycle's output buffer z is the same every iteration.  Every kernel reads
+// alpha, beta and the converged flag from the device status, so a replay
+// after convergence does no work.
+hipGraphExec_t capture_mg32_pair(const Lev<double>& L, MgHier<float>& H, CgVecsMg32 V, float* r32, float* z,
+                                 SolveStatus* st, double* partials, unsigned* counters, hipStream_t cs) {
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
+  cg_iteration_mg32(L, H, V, r32, &z, st, partials, counters, false, cs);
+  cg_iteration_mg32(L, H, V, r32, &z, st, partials, counters, false, cs);
+  hipGraph_t gr = nullptr;
+  if (hipStreamEndCapture(cs, &gr) != hipSuccess || !gr) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return ex;
+}
 double replay_operator_z32(const Lev<double>& L, const float* z, const float* pin, float* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1) {

@@ -216,6 +216,33 @@ def test_step_parity_coloured_vcycle_sweeps(monkeypatch, precision):
           g.diagnostics()["iters_phi"])
 
 
+@pytest.mark.parametrize("n", [(32, 32, 32), (48, 48, 96)])
+def test_graph_replays_bitwise_equal_to_eager(monkeypatch, n):
+    """The precision form's multigrid CG replays pairs of iterations as HIP
+    graphs: every field after every step bit-identical to running the same
+    kernels one launch at a time (several solves per step, so each graph is
+    replayed many times, with eager work and synchronisations in between)."""
+    ds = _lib()
+    prm, run = _grid_params(n=n, L=n[0] * 1.25e-4, precision=W.PREC_MIXED)
+    f = W.random_fields(prm, seed=3)
+    out = {}
+    for gr in ("0", "1"):
+        monkeypatch.setenv("DSVOF_GRAPHS", gr)
+        g = ds.Grid(prm)
+        g.set_fields(f)
+        out[gr] = []
+        for step in range(4):
+            g.step(1)
+            out[gr].append((g.get_fields(), g.diagnostics()))
+        del g
+    for step in range(4):
+        (fa, da), (fb, db) = out["0"][step], out["1"][step]
+        for k in FIELDS:
+            assert torch.equal(torch.as_tensor(fa[k]), torch.as_tensor(fb[k])), (step, k)
+        assert da["iters_p"] == db["iters_p"] and da["iters_phi"] == db["iters_phi"]
+    print("iterations p/phi per step:", [(d["iters_p"], d["iters_phi"]) for _, d in out["1"]])
+
+
 @pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
 def test_neumann_preconditioner_same_solution_fewer_iterations(monkeypatch, precision):
     """Energy and species on vectorised grids use the first-order Neumann
