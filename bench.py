@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 # the ratio of known bytes to the counter's reading for a 1 GiB device copy in
 # the same run; None until measured for the current kernel.
 # Measured for the fine-level coloured sweep of the 256^3 workload: FETCH_SIZE
-# 121923 KiB x 2.000 (the 1 GiB copy reads 524328 KiB) + WRITE_SIZE 65536 KiB x 1.000.
-TRAFFIC_SMOOTH = (121923.0 * (1048576.0 / 524328.0) + 65536.0) * 1024.0
+# 117161 KiB x 2.000 (the 1 GiB copy reads 524338 KiB) + WRITE_SIZE 65536 KiB x 1.000.
+TRAFFIC_SMOOTH = (117161.0 * (1048576.0 / 524338.0) + 65536.0) * 1024.0
 
 
 def log(msg):

@@ -1027,18 +1027,28 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
 #pragma unroll
     for (int v = 0; v < V; ++v) o[v] = a[v];
   };
+  // out-of-range planes are clamped to the nearest one (loads stay inside
+  // the array; the terms they would feed are switched off)
+  auto clampp = [&](int q) { return q < 0 ? 0 : (q >= (int)nx ? (int)nx - 1 : q); };
   for (unsigned e = lb * NT + tid; e < total; e += gridDim.x * NT) {
     const unsigned kv = e % nzv, t = e / nzv, j = t % ny, ch = t / ny;
     const unsigned i0 = ch * clen, i1 = min(nx, i0 + clen);
     if (i0 >= i1) continue;
     const bool hym = j > 0, hyp = j + 1 < ny, hzm = kv > 0, hzp = kv + 1 < nzv;
     const unsigned cj = j * sy + kv * V;
-    const unsigned s0 = i0 > 0 ? i0 - 1 : 0;
-    // q of planes s-2, s-1, s; x0 of s-1, s; colour-A results of s-2, s-1;
-    // r, 1/diag and the y-neighbour term of s-1
+    // Odd chunks walk their planes downwards: a boundary plane between two
+    // chunks is then read by both at the same step (both ends of the walks
+    // meet there), so the second read can come from the L2.  Walking
+    // direction changes which registers hold the x neighbours, never the
+    // arithmetic of a cell.
+    const int dir = (ch & 1u) ? -1 : 1;
+    const int s0 = dir > 0 ? ((int)i0 > 0 ? (int)i0 - 1 : 0) : ((int)i1 < (int)nx ? (int)i1 : (int)nx - 1);
+    const int se = dir > 0 ? (int)i1 : (int)i0 - 1;
+    // q of planes s-2d, s-d, s; x0 of s-d, s; colour-A results of s-2d, s-d;
+    // r, 1/diag and the y-neighbour term of s-d (d = dir)
     T qa[V], qb[V], qc[V], xb[V], xc[V], ma[V], mb[V], rb[V], ib[V], yb[V];
     {
-      const unsigned fb = (s0 > 0 ? s0 - 1 : s0) * P + cj, fc = s0 * P + cj;
+      const unsigned fb = (unsigned)clampp(s0 - dir) * P + cj, fc = (unsigned)s0 * P + cj;
       ldv<T>(at(L.qc, fb), qb);
       ldv<T>(at(L.qc, fc), qc);
       if (X0) {
@@ -1056,11 +1066,11 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
 #pragma unroll
       for (int v = 0; v < V; ++v) ib[v] = 1;
     }
-    for (unsigned s = s0; s <= i1; ++s) {
-      const bool live = s < nx;   // s == nx only finishes plane nx - 1
-      const unsigned c = (live ? s : nx - 1) * P + cj;
-      const bool hxm = s > 0, hxp = s + 1 < nx;
-      const unsigned fn = hxp ? c + P : c, fym = hym ? c - sy : c, fyp = hyp ? c + sy : c;
+    for (int s = s0;; s += dir) {
+      const bool live = s >= 0 && s < (int)nx;   // s = nx or -1 only finishes the chunk's last plane
+      const unsigned c = (unsigned)clampp(s) * P + cj;
+      const bool hxm = s > 0, hxp = s + 1 < (int)nx;
+      const unsigned fn = (unsigned)clampp(s + dir) * P + cj, fym = hym ? c - sy : c, fyp = hyp ? c + sy : c;
       T qd[V], xd[V], rc[V], nqm[V], nqp[V], nxm[V], nxp[V];
       ldv<T>(at(L.qc, fn), qd);
       if (X0) lx(fn, xd);
@@ -1092,6 +1102,8 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       }
       const T qzm = lane_up(qc[V - 1]), qzp = lane_down(qc[0]);
       const T xzm = lane_up(xc[V - 1]), xzp = lane_down(xc[0]);
+      // x neighbours of plane s: minus side, plus side
+      const bool fw = dir > 0;
       // the y-neighbour term and 1/diag of plane s (diag formed in T from q:
       // the smoother's own diagonal, consistent within the sweep)
       T yc[V], ic[V];
@@ -1107,9 +1119,10 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const T q = qc[v], bnd = T(2) * L.sc * q;
+          const T gxm = fw ? qb[v] : qd[v], gxp = fw ? qd[v] : qb[v];
           T d = 0;
-          d += hxm ? hs * (q + qb[v]) : ((dm & 1) ? bnd : T(0));
-          d += hxp ? hs * (q + qd[v]) : ((dm & 2) ? bnd : T(0));
+          d += hxm ? hs * (q + gxm) : ((dm & 1) ? bnd : T(0));
+          d += hxp ? hs * (q + gxp) : ((dm & 2) ? bnd : T(0));
           d += hym ? hs * (q + nqm[v]) : ((dm & 4) ? bnd : T(0));
           d += hyp ? hs * (q + nqp[v]) : ((dm & 8) ? bnd : T(0));
           const bool em = v > 0 || hzm, ep = v < V - 1 || hzp;
@@ -1129,18 +1142,22 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       const T bqzm = lane_up(qb[V - 1]), bqzp = lane_down(qb[0]);
       const T w1 = T(1) - w;
       T mc[V];
+      const int sb = s - dir;   // the plane colour B finishes
+      const bool own_b = sb >= (int)i0 && sb < (int)i1;
       // x + w (r - A x)/d = (1 - w) x + w (r + sc/2 off)/d, off the neighbour
       // sum.  The lanes of colour A on plane s are those of colour B on plane
-      // s - 1 (v of parity s + c0); each lane evaluates only its colour.
+      // s - dir (v of parity s + c0); each lane evaluates only its colour.
       auto relax = [&](auto PA) {
         constexpr unsigned pa = decltype(PA)::value;
         // colour A on plane s, from x0 (all neighbours old)
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           if (((unsigned)v & 1u) == pa) {
+            const T gxm = fw ? qb[v] : qd[v], gxp = fw ? qd[v] : qb[v];
+            const T vxm = fw ? xb[v] : xd[v], vxp = fw ? xd[v] : xb[v];
             T o = yc[v];
-            o = hxm ? o + (qc[v] + qb[v]) * xb[v] : o;
-            o = hxp ? o + (qc[v] + qd[v]) * xd[v] : o;
+            o = hxm ? o + (qc[v] + gxm) * vxm : o;
+            o = hxp ? o + (qc[v] + gxp) * vxp : o;
             const T gm = v > 0 ? qc[v > 0 ? v - 1 : 0] : qzm, xm = v > 0 ? xc[v > 0 ? v - 1 : 0] : xzm;
             const T gp = v < V - 1 ? qc[v < V - 1 ? v + 1 : V - 1] : qzp;
             const T xp = v < V - 1 ? xc[v < V - 1 ? v + 1 : V - 1] : xzp;
@@ -1151,17 +1168,18 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
             mc[v] = xc[v];
           }
         }
-        // colour B on plane s - 1, from colour A's new values (y old)
-        if (s > i0) {
-          const unsigned sb = s - 1;
-          const bool bxm = sb > 0, bxp = s < nx;
+        // colour B on plane s - dir, from colour A's new values (y old)
+        if (own_b) {
+          const bool bxm = sb > 0, bxp = sb + 1 < (int)nx;
           T o[V];
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             if (((unsigned)v & 1u) == pa) {
+              const T gxm = fw ? qa[v] : qc[v], gxp = fw ? qc[v] : qa[v];
+              const T vxm = fw ? ma[v] : mc[v], vxp = fw ? mc[v] : ma[v];
               T f = yb[v];
-              f = bxm ? f + (qb[v] + qa[v]) * ma[v] : f;
-              f = bxp ? f + (qb[v] + qc[v]) * mc[v] : f;
+              f = bxm ? f + (qb[v] + gxm) * vxm : f;
+              f = bxp ? f + (qb[v] + gxp) * vxp : f;
               const T gm = v > 0 ? qb[v > 0 ? v - 1 : 0] : bqzm, xm = v > 0 ? mb[v > 0 ? v - 1 : 0] : mzm;
               const T gp = v < V - 1 ? qb[v < V - 1 ? v + 1 : V - 1] : bqzp;
               const T xp = v < V - 1 ? mb[v < V - 1 ? v + 1 : V - 1] : mzp;
@@ -1172,11 +1190,12 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
               o[v] = mb[v];
             }
           }
-          out(sb * P + cj, o, rb);
+          out((unsigned)sb * P + cj, o, rb);
         }
       };
-      if (((s + (unsigned)c0) & 1u) == 0u) relax(std::integral_constant<unsigned, 0>{});
+      if ((((unsigned)s + (unsigned)c0) & 1u) == 0u) relax(std::integral_constant<unsigned, 0>{});
       else relax(std::integral_constant<unsigned, 1>{});
+      (void)live;
       copy(qa, qb);
       copy(qb, qc);
       copy(qc, qd);
@@ -1187,14 +1206,11 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       copy(rb, rc);
       copy(ib, ic);
       copy(yb, yc);
+      if (s == se) break;
     }
   }
 }
 
-// Levels that take the coloured sweeps: rows shared through LDS, z-rows
-// inside one wave, and chunks of at least min_planes x-planes (a chunk also
-// relaxes its two outer planes in colour A, which short chunks pay for more
-// than the better smoothing saves: at 128^3 the chunks are 2 planes long).
 template <class T>
 inline bool rb_marching_ok(const Lev<T>& M, int min_planes) {   // M: the level as march_lev(L, 1) returns it
   if (!use_vec(M)) return false;
