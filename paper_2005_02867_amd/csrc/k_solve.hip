@@ -643,7 +643,12 @@ __device__ __forceinline__ T lane_down(T v) { return __shfl_down(v, 1, 64); } //
 // (chunk, j, kv), kv fastest; a grid-stride loop covers them (the stride is a
 // multiple of 64, so a wave's lanes always hold consecutive items).  Threads
 // past the end do nothing and return normally (block reductions follow).
-template <class T, int NT, class LX, class SX, class BODY>
+// ALT: odd chunks walk their planes downwards, so two neighbouring chunks
+// read their shared boundary planes at the same step (the second read can
+// come from the L2); the cell arithmetic is the same either way.  Kernels
+// whose body depends on the walking order (the marching restriction) pass
+// false.
+template <class T, int NT, bool ALT = true, class LX, class SX, class BODY>
 __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) {
   constexpr int V = VW<T>::n;
   const unsigned nzv = (unsigned)L.nz / V, ny = (unsigned)L.ny, nx = (unsigned)L.nx;
@@ -669,18 +674,28 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
   const unsigned i0 = ch * clen, i1 = min(nx, i0 + clen);
   if (i0 >= i1) continue;
   const bool hym = j > 0, hyp = j + 1 < ny, hzm = kv > 0, hzp = kv + 1 < nzv;
-  unsigned c = i0 * P + j * sy + kv * V;
+  const unsigned cj = j * sy + kv * V;
+  const bool fw = !(ALT && (ch & 1u));
+  const int dir = fw ? 1 : -1;
+  const int sfirst = fw ? (int)i0 : (int)i1 - 1, slast = fw ? (int)i1 - 1 : (int)i0;
+  auto clampp = [&](int q) { return q < 0 ? 0 : (q >= (int)nx ? (int)nx - 1 : q); };
+  // qp, xp: the plane behind (walking direction); qc, xc: the current one
   T qp[V], xp[V], qc[V], xc[V];
   {
-    const unsigned f = i0 > 0 ? c - P : c;
+    const unsigned f = (unsigned)clampp(sfirst - dir) * P + cj;
     ldv<T>(at(L.qc, f), qp);
     lx(f, xp);
   }
-  ldv<T>(at(L.qc, c), qc);
-  lx(c, xc);
-  for (unsigned i = i0; i < i1; ++i, c += P) {
-    const bool hxm = i > 0, hxp = i + 1 < nx;
-    const unsigned fn = hxp ? c + P : c, fym = hym ? c - sy : c, fyp = hyp ? c + sy : c;
+  {
+    const unsigned f = (unsigned)sfirst * P + cj;
+    ldv<T>(at(L.qc, f), qc);
+    lx(f, xc);
+  }
+  for (int i = sfirst;; i += dir) {
+    const unsigned c = (unsigned)i * P + cj;
+    const bool hxm = i > 0, hxp = i + 1 < (int)nx;
+    const unsigned fn = (unsigned)clampp(i + dir) * P + cj, fym = hym ? c - sy : c, fyp = hyp ? c + sy : c;
+    // qn, xn: the plane ahead
     T qn[V], xn[V], qym[V], xym[V], qyp[V], xyp[V];
     ldv<T>(at(L.qc, fn), qn);
     lx(fn, xn);
@@ -726,8 +741,17 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
         off[v] = has ? tt : off[v];
       }
     };
-    nbr(qp, xp, hxm);
-    nbr(qn, xn, hxp);
+    // x neighbours on the minus and plus sides
+    T qxm[V], xxm[V], qxp[V], xxp[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      qxm[v] = fw ? qp[v] : qn[v];
+      xxm[v] = fw ? xp[v] : xn[v];
+      qxp[v] = fw ? qn[v] : qp[v];
+      xxp[v] = fw ? xn[v] : xp[v];
+    }
+    nbr(qxm, xxm, hxm);
+    nbr(qxp, xxp, hxp);
     nbr(qym, xym, hym);
     nbr(qyp, xyp, hyp);
     {
@@ -750,8 +774,8 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
       for (int v = 0; v < V; ++v) {
         const double q = (double)qc[v], bnd = 2.0 * sc * q;
         double d = 0.0;
-        d += hxm ? sc * 0.5 * (q + (double)qp[v]) : ((dm & 1) ? bnd : 0.0);
-        d += hxp ? sc * 0.5 * (q + (double)qn[v]) : ((dm & 2) ? bnd : 0.0);
+        d += hxm ? sc * 0.5 * (q + (double)qxm[v]) : ((dm & 1) ? bnd : 0.0);
+        d += hxp ? sc * 0.5 * (q + (double)qxp[v]) : ((dm & 2) ? bnd : 0.0);
         d += hym ? sc * 0.5 * (q + (double)qym[v]) : ((dm & 4) ? bnd : 0.0);
         d += hyp ? sc * 0.5 * (q + (double)qyp[v]) : ((dm & 8) ? bnd : 0.0);
         const bool em = v > 0 || hzm, ep = v < V - 1 || hzp;
@@ -772,6 +796,7 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
       qc[v] = qn[v];
       xc[v] = xn[v];
     }
+    if (i == slast) break;
   }
   }
 }
@@ -901,7 +926,7 @@ VEC_KERNEL_M k_mg_restrict_m(Lev<T> F, Lev<T> C, const T* __restrict__ r, const 
   const unsigned nzv = (unsigned)F.nz / V, P = (unsigned)F.ny * (unsigned)F.nz, sy = (unsigned)F.nz;
   const int tid = threadIdx.x;
   T acc[H];
-  march<T, NT>(
+  march<T, NT, false>(
       F, [&](unsigned f, T(&o)[V]) { ldv<T>(at(x, f), o); }, [&](unsigned f) { return *at(x, f); },
       [&](unsigned c, const T(&qv)[V], const T(&xv)[V], const T(&off)[V], const T(&dv)[V]) {
         T rv[V];
