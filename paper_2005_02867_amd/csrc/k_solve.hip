@@ -1027,11 +1027,12 @@ VEC_KERNEL_M k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, 
 // [i0, i1) also relaxes colour A on its outer planes i0 - 1 and i1, which its
 // first and last planes need.  The y-neighbour term sum (q + q_y) x0_y of a
 // plane serves both colours (old values either way) and is kept from one
-// step to the next.  Needs the rows shared through LDS and every z-row inside
-// one wave (rb_marching_ok), so each z neighbour is in an adjacent lane.
+// step to the next.  Needs the rows shared through LDS (rb_marching_ok): a
+// z neighbour is then in an adjacent lane or, at a wave's edge, in the
+// adjacent thread of the same block.
 // lx(f, o): x0 vector at cell f (X0 false: x0 = 0, nothing loaded);
 // out(c, o, rv): the finished vector of plane s - 1 and its r.
-template <class T, int NT, bool X0, class LX, class OUT>
+template <class T, int NT, bool X0, bool WE, class LX, class OUT>
 __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ r, T w, int c0, LX lx, OUT out) {
   constexpr int V = VW<T>::n;
   const unsigned nzv = (unsigned)L.nz / V, ny = (unsigned)L.ny, nx = (unsigned)L.nx;
@@ -1040,8 +1041,12 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
   const unsigned total = ny * nzv * nch;
   const unsigned P = ny * (unsigned)L.nz, sy = (unsigned)L.nz;
   const int tid = threadIdx.x;
-  __shared__ T lsq[2][NT * V], lsx[2][X0 ? NT * V : 1];
+  // lsm (WE: z-rows that span or straddle waves): each thread's first and
+  // last colour-A value of the previous plane, for the wave-edge lanes whose
+  // z neighbours sit in the adjacent wave of the same block
+  __shared__ T lsq[2][NT * V], lsx[2][X0 ? NT * V : 1], lsm[2][WE ? 2 * NT : 1];
   const bool inm = tid >= (int)nzv, inp = tid + (int)nzv < NT;
+  const int lane = tid & 63;
   const T hs = T(0.5) * L.sc;
   int par = 0;
   auto zero = [](T(&o)[V]) {
@@ -1091,6 +1096,7 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
 #pragma unroll
       for (int v = 0; v < V; ++v) ib[v] = 1;
     }
+    T pqzm = 0, pqzp = 0;   // WE: z neighbours' q of plane s - dir
     for (int s = s0;; s += dir) {
       const bool live = s >= 0 && s < (int)nx;   // s = nx or -1 only finishes the chunk's last plane
       const unsigned c = (unsigned)clampp(s) * P + cj;
@@ -1111,6 +1117,10 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       }
       stv<T>(&lsq[par][tid * V], qc);
       if (X0) stv<T>(&lsx[par][tid * V], xc);
+      if (WE) {
+        lsm[par][2 * tid] = mb[0];
+        lsm[par][2 * tid + 1] = mb[V - 1];
+      }
       __syncthreads();
       if (inm) {
         ldv<T>(&lsq[par][(tid - (int)nzv) * V], nqm);
@@ -1120,13 +1130,27 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
         ldv<T>(&lsq[par][(tid + (int)nzv) * V], nqp);
         if (X0) ldv<T>(&lsx[par][(tid + (int)nzv) * V], nxp);
       }
-      par ^= 1;
       if (!X0) {
         zero(nxm);
         zero(nxp);
       }
-      const T qzm = lane_up(qc[V - 1]), qzp = lane_down(qc[0]);
-      const T xzm = lane_up(xc[V - 1]), xzp = lane_down(xc[0]);
+      // z neighbours from the adjacent lanes; at a wave's first and last lane
+      // (rows longer than or straddling a wave) from the adjacent thread's
+      // values in LDS
+      T qzm = lane_up(qc[V - 1]), qzp = lane_down(qc[0]);
+      T xzm = lane_up(xc[V - 1]), xzp = lane_down(xc[0]);
+      T mzm = lane_up(mb[V - 1]), mzp = lane_down(mb[0]);
+      if (WE && hzm && lane == 0) {
+        qzm = lsq[par][(tid - 1) * V + V - 1];
+        if (X0) xzm = lsx[par][(tid - 1) * V + V - 1];
+        mzm = lsm[par][2 * (tid - 1) + 1];
+      }
+      if (WE && hzp && lane == 63) {
+        qzp = lsq[par][(tid + 1) * V];
+        if (X0) xzp = lsx[par][(tid + 1) * V];
+        mzp = lsm[par][2 * (tid + 1)];
+      }
+      par ^= 1;
       // x neighbours of plane s: minus side, plus side
       const bool fw = dir > 0;
       // the y-neighbour term and 1/diag of plane s (diag formed in T from q:
@@ -1163,8 +1187,7 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
 #pragma unroll
         for (int v = 0; v < V; ++v) ic[v] = T(1) / dl[v];
       }
-      const T mzm = lane_up(mb[V - 1]), mzp = lane_down(mb[0]);
-      const T bqzm = lane_up(qb[V - 1]), bqzp = lane_down(qb[0]);
+      const T bqzm = WE ? pqzm : lane_up(qb[V - 1]), bqzp = WE ? pqzp : lane_down(qb[0]);
       const T w1 = T(1) - w;
       T mc[V];
       const int sb = s - dir;   // the plane colour B finishes
@@ -1231,26 +1254,43 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       copy(rb, rc);
       copy(ib, ic);
       copy(yb, yc);
+      if (WE) {
+        pqzm = qzm;
+        pqzp = qzp;
+      }
       if (s == se) break;
     }
   }
 }
 
+// Levels that take the coloured sweeps: rows shared through LDS (each z-row
+// inside one block) and chunks of at least min_planes x-planes (a chunk also
+// relaxes colour A on its two outer planes, which short chunks pay for more
+// than the better smoothing saves: at 128^3 the chunks are 2 planes long).
 template <class T>
 inline bool rb_marching_ok(const Lev<T>& M, int min_planes) {   // M: the level as march_lev(L, 1) returns it
-  if (!use_vec(M)) return false;
+  // FP32 levels only: in FP64 the kernel holds twice the registers per
+  // vector and spills (FP64 fine level at 256^3: 35.4 -> 36.6 ms per step)
+  if (!std::is_same<T, float>::value || !use_vec(M)) return false;
   const long long nzv = M.nz / VW<T>::n;
   const long long clen = (M.nx + M.mch - 1) / M.mch;
-  return nzv >= 1 && 64 % nzv == 0 && M.mnt % nzv == 0 && ((long long)M.ny * nzv) % M.mnt == 0 &&
-         clen >= min_planes;
+  return nzv >= 1 && M.mnt % nzv == 0 && ((long long)M.ny * nzv) % M.mnt == 0 && clen >= min_planes;
 }
 
 enum { RB_GEN = 0, RB_ZERO = 1, RB_PROLONG = 2 };
 
+// Do the level's z-rows span or straddle 64-lane waves (the coloured sweep
+// then exchanges wave-edge values through LDS)?
+template <class T>
+inline bool rows_cross_waves(const Lev<T>& M) {
+  const int nzv = M.nz / VW<T>::n;
+  return 64 % nzv != 0;
+}
+
 // One coloured sweep (march_rb) of F x = r.  RB_GEN: from x; RB_ZERO: from
 // x = 0 (x not read); RB_PROLONG: from x + P xc (injection from level C).
 // DOT: also <r, x_out> (the preconditioned residual's product).
-template <class T, int MODE, bool DOT, int NT>
+template <class T, int MODE, bool DOT, int NT, bool WE>
 VEC_KERNEL_M k_mg_rb_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
                        const T* __restrict__ xc, T* __restrict__ xout, T w, int c0, SolveStatus* st,
                        double* partials, unsigned* counter, int first) {
@@ -1274,11 +1314,11 @@ VEC_KERNEL_M k_mg_rb_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __r
 #pragma unroll
       for (int v = 0; v < V; ++v) o[v] += *at(xc, pb + (v >> 1));
     };
-    march_rb<T, NT, true>(F, r, w, c0, row, outf);
+    march_rb<T, NT, true, WE>(F, r, w, c0, row, outf);
   } else if constexpr (MODE == RB_GEN) {
-    march_rb<T, NT, true>(F, r, w, c0, [&](unsigned f, T(&o)[V]) { ldv<T>(at(x, f), o); }, outf);
+    march_rb<T, NT, true, WE>(F, r, w, c0, [&](unsigned f, T(&o)[V]) { ldv<T>(at(x, f), o); }, outf);
   } else {
-    march_rb<T, NT, false>(F, r, w, c0, [&](unsigned, T(&o)[V]) {}, outf);
+    march_rb<T, NT, false, WE>(F, r, w, c0, [&](unsigned, T(&o)[V]) {}, outf);
   }
   if (DOT) publish_rz<NT>(acc, st, partials, counter, first);
 }
@@ -1994,24 +2034,31 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
     const T w = (T)H.w_rb;
     const Lev<T>& C = H.lev[l + 1];
     auto rb = [&](int mode, bool d, const T* xin, const T* xcs, T* xo, int c0) {
-      with_nt(Mr.mnt, [&](auto K) {
-        constexpr int NT = decltype(K)::value;
-        if (mode == RB_ZERO)
-          k_mg_rb_v<T, RB_ZERO, false, NT><<<nbr, NT, 0, s>>>(Mr, C, r, nullptr, nullptr, xo, w, c0, st, partials,
-                                                              counter, 0);
-        else if (mode == RB_PROLONG && d)
-          k_mg_rb_v<T, RB_PROLONG, true, NT><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st, partials, counter,
-                                                                dot_first);
-        else if (mode == RB_PROLONG)
-          k_mg_rb_v<T, RB_PROLONG, false, NT><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st, partials,
-                                                                 counter, 0);
-        else if (d)
-          k_mg_rb_v<T, RB_GEN, true, NT><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st, partials, counter,
-                                                            dot_first);
-        else
-          k_mg_rb_v<T, RB_GEN, false, NT><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st, partials, counter,
-                                                             0);
-      });
+      if constexpr (std::is_same<T, float>::value) {
+        auto go = [&](auto WEc) {
+          constexpr bool WE = decltype(WEc)::value;
+          with_nt(Mr.mnt, [&](auto K) {
+            constexpr int NT = decltype(K)::value;
+            if (mode == RB_ZERO)
+              k_mg_rb_v<T, RB_ZERO, false, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, nullptr, nullptr, xo, w, c0, st,
+                                                                      partials, counter, 0);
+            else if (mode == RB_PROLONG && d)
+              k_mg_rb_v<T, RB_PROLONG, true, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st, partials,
+                                                                        counter, dot_first);
+            else if (mode == RB_PROLONG)
+              k_mg_rb_v<T, RB_PROLONG, false, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st,
+                                                                         partials, counter, 0);
+            else if (d)
+              k_mg_rb_v<T, RB_GEN, true, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st, partials,
+                                                                    counter, dot_first);
+            else
+              k_mg_rb_v<T, RB_GEN, false, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st,
+                                                                     partials, counter, 0);
+          });
+        };
+        if (rows_cross_waves(Mr)) go(std::true_type{});
+        else go(std::false_type{});
+      }
     };
     rb(RB_ZERO, false, nullptr, nullptr, a, 0);
     for (int t = 1; t < nr; ++t) {
@@ -2253,11 +2300,18 @@ double replay_smooth_kernel(const Lev<T>& L, const MgHier<T>& H, const T* r, con
   const int nbr = rb ? march_blocks(Mr) : 0;
   auto launch = [&]() {
     if (rb) {
-      with_nt(Mr.mnt, [&](auto K) {
-        constexpr int NT = decltype(K)::value;
-        k_mg_rb_v<T, RB_GEN, false, NT><<<nbr, NT, 0, s>>>(Mr, Mr, r, xin, nullptr, xout, (T)H.w_rb, 0, st, nullptr,
-                                                           nullptr, 0);
-      });
+      if constexpr (std::is_same<T, float>::value) {
+        auto go = [&](auto WEc) {
+          constexpr bool WE = decltype(WEc)::value;
+          with_nt(Mr.mnt, [&](auto K) {
+            constexpr int NT = decltype(K)::value;
+            k_mg_rb_v<T, RB_GEN, false, NT, WE><<<nbr, NT, 0, s>>>(Mr, Mr, r, xin, nullptr, xout, (T)H.w_rb, 0, st,
+                                                                   nullptr, nullptr, 0);
+          });
+        };
+        if (rows_cross_waves(Mr)) go(std::true_type{});
+        else go(std::false_type{});
+      }
     } else if (vec) {
       with_nt(M.mnt, [&](auto K) {
         constexpr int NT = decltype(K)::value;

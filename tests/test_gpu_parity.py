@@ -216,6 +216,20 @@ def test_step_parity_coloured_vcycle_sweeps(monkeypatch, precision):
           g.diagnostics()["iters_phi"])
 
 
+@pytest.mark.parametrize("n", [(16, 8, 512), (16, 16, 96)])
+def test_step_parity_coloured_sweeps_rows_across_waves(monkeypatch, n):
+    """Coloured sweeps (FP32 V-cycle of the precision form) on levels whose
+    z-rows span or straddle 64-lane waves (rows of 128 and of 24 vectors),
+    where a wave's edge lanes take their z neighbours from the adjacent
+    thread through LDS; forced on every level that allows them, 3 steps
+    against the oracle, both sides solving to 1e-13."""
+    precision = W.PREC_MIXED
+    monkeypatch.setenv("DSVOF_MG_RB_MINPLANES", "1")
+    prm, _ = _grid_params(n=n, L=n[0] * 1.25e-4, precision=precision)
+    f = W.random_fields(prm, seed=9)
+    _run_both(prm, f, steps=3)
+
+
 @pytest.mark.parametrize("n", [(32, 32, 32), (48, 48, 96)])
 def test_graph_replays_bitwise_equal_to_eager(monkeypatch, n):
     """The precision form's multigrid CG replays pairs of iterations as HIP
