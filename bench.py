@@ -218,8 +218,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "single-GPU build: the step runs on one GPU; runs on several GPUs are not "
-                                   "supported (the sharding design is described in DESIGN.md)",
+        print(json.dumps({"error": "the step runs on one GPU; runs on several GPUs are not supported (the "
+                                   "domain is not sharded)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
