@@ -1827,7 +1827,8 @@ template <class T>
 struct TailLevs {
   int nlev;
   int nx[MG_MAXLEV], ny[MG_MAXLEV], nz[MG_MAXLEV], nu[MG_MAXLEV];
-  int off[MG_MAXLEV];   // element offset of the level's r, x, t, q, diag block in LDS
+  int ly[MG_MAXLEV], lz[MG_MAXLEV];   // log2 of ny, nz when both are powers of two, else -1
+  int off[MG_MAXLEV];   // element offset of the level's r, x, t, q, 1/diag block in LDS
   T sc[MG_MAXLEV];
   const T* q[MG_MAXLEV];
   const T* d[MG_MAXLEV];
@@ -1863,7 +1864,7 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
     const int n = N(l), qo = Qo(l), dg = Do(l);
     for (int c = threadIdx.x; c < n; c += TAIL_BLOCK) {
       S[qo + c] = TL.q[l][c];
-      S[dg + c] = TL.d[l][c];
+      S[dg + c] = T(1) / TL.d[l][c];   // 1/diag: the sweeps multiply
     }
   }
   for (int c = threadIdx.x; c < N(0); c += TAIL_BLOCK) S[Ro(0) + c] = r0[c];
@@ -1878,8 +1879,20 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
     i = (int)(((double)t + 0.5) * (1.0 / (double)b));
     j = t - i * b;
   };
+  // the same by shifts on levels with power-of-two ny, nz
+  auto decl = [&](int l, int c, int& i, int& j, int& k) {
+    if (TL.lz[l] >= 0) {
+      k = c & (TL.nz[l] - 1);
+      const int t = c >> TL.lz[l];
+      j = t & (TL.ny[l] - 1);
+      i = t >> TL.ly[l];
+    } else {
+      dec(c, TL.ny[l], TL.nz[l], i, j, k);
+    }
+  };
   // one damped-Jacobi sweep on level l (x -> t, then the roles swap); with
   // dot, accumulate <r, x_new>.  zero: from x = 0, i.e. x = omega r/diag.
+  // x + omega (r - A x)/d is formed as (1 - omega) x + omega (r + sc/2 off)/d.
   auto sweep = [&](int l, bool zero, bool dot) {
     const int nx = TL.nx[l], ny = TL.ny[l], nz = TL.nz[l], n = nx * ny * nz, sx = ny * nz;
     const int ro = Ro(l), xo = Xo(l), yo = Yo(l), qo = Qo(l), dg = Do(l);
@@ -1887,10 +1900,10 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
     for (int c = threadIdx.x; c < n; c += TAIL_BLOCK) {
       T xn;
       if (zero) {
-        xn = omega * S[ro + c] / S[dg + c];
+        xn = omega * S[ro + c] * S[dg + c];
       } else {
         int i, j, k;
-        dec(c, ny, nz, i, j, k);
+        decl(l, c, i, j, k);
         const T q = S[qo + c];
         T off = 0;
         if (i > 0) off += (q + S[qo + c - sx]) * S[xo + c - sx];
@@ -1899,8 +1912,7 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
         if (j < ny - 1) off += (q + S[qo + c + nz]) * S[xo + c + nz];
         if (k > 0) off += (q + S[qo + c - 1]) * S[xo + c - 1];
         if (k < nz - 1) off += (q + S[qo + c + 1]) * S[xo + c + 1];
-        const T ax = S[dg + c] * S[xo + c] - T(0.5) * sc * off;
-        xn = S[xo + c] + omega * (S[ro + c] - ax) / S[dg + c];
+        xn = (T(1) - omega) * S[xo + c] + omega * (S[ro + c] + T(0.5) * sc * off) * S[dg + c];
       }
       S[yo + c] = xn;
       if (DOT && dot) acc += (double)S[ro + c] * (double)xn;
@@ -1917,7 +1929,7 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
     const T sc = TL.sc[l];
     for (int cc = threadIdx.x; cc < nc; cc += TAIL_BLOCK) {
       int I, J, K;
-      dec(cc, CY, CZ, I, J, K);
+      decl(l + 1, cc, I, J, K);
       T sres = 0;
       for (int di = 0; di < 2; ++di)
         for (int dj = 0; dj < 2; ++dj)
@@ -1933,7 +1945,7 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
               if (j < ny - 1) off += (q + S[qo + f + nz]) * S[xo + f + nz];
               if (k > 0) off += (q + S[qo + f - 1]) * S[xo + f - 1];
               if (k < nz - 1) off += (q + S[qo + f + 1]) * S[xo + f + 1];
-              sres += S[ro + f] - (S[dg + f] * S[xo + f] - T(0.5) * sc * off);
+              sres += S[ro + f] - (S[xo + f] / S[dg + f] - T(0.5) * sc * off);
             }
           }
       S[rc + cc] = T(0.125) * sres;
@@ -1948,7 +1960,7 @@ __global__ void __launch_bounds__(TAIL_BLOCK) k_mg_tail(TailLevs<T> TL, const T*
     const int CY = TL.ny[l + 1], CZ = TL.nz[l + 1], xo = Xo(l), xc = Xo(l + 1);
     for (int c = threadIdx.x; c < n; c += TAIL_BLOCK) {
       int i, j, k;
-      dec(c, ny, nz, i, j, k);
+      decl(l, c, i, j, k);
       S[xo + c] += S[xc + ((i >> 1) * CY + (j >> 1)) * CZ + (k >> 1)];
     }
     __syncthreads();
@@ -1997,6 +2009,9 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
       TL.nx[m] = Lm.nx;
       TL.ny[m] = Lm.ny;
       TL.nz[m] = Lm.nz;
+      const bool p2 = (Lm.ny & (Lm.ny - 1)) == 0 && (Lm.nz & (Lm.nz - 1)) == 0;
+      TL.ly[m] = p2 ? __builtin_ctz((unsigned)Lm.ny) : -1;
+      TL.lz[m] = p2 ? __builtin_ctz((unsigned)Lm.nz) : -1;
       TL.nu[m] = l + m == 0 ? H.nu_fine : H.nu;
       TL.sc[m] = Lm.sc;
       TL.q[m] = Lm.qc;
