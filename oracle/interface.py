@@ -24,6 +24,11 @@ Readings of the paper taken here (each listed in the design notes):
 * eqs. 19-21: mdot = K f(alpha) mdot_raw with f = sqrt(alpha(1-alpha)) and K
   the ratio of the two volume integrals (sums over all cells); K = 0 when the
   denominator vanishes.
+* Literal species form (species_form = 1, Section 2.5 after eq. 23): the
+  saturation value is assigned to the whole liquid (every cell with
+  alpha > eps_gas, the cells the adj march passes over) and the diffusive
+  part of j.n at adj is -rho_G D (grad omega)_adj . n, grad omega by central
+  differences of that field with zero-gradient ghosts outside the box.
 The geometry stays differentiable in alpha (|grad alpha| and the normal);
 classes, the march and adj are integer decisions and carry no derivative.
 """
@@ -100,8 +105,33 @@ def cell_velocity(u, v, w):
     return 0.5 * (u[:-1] + u[1:]), 0.5 * (v[:, :-1] + v[:, 1:]), 0.5 * (w[:, :, :-1] + w[:, :, 1:])
 
 
+def liquid_saturation(alpha, T, omega, prm):
+    """omega with the saturation value omega_sat(T) assigned to every liquid
+    cell (alpha > eps_gas), as the paper's species equation takes it (Section
+    2.5, after eq. 23); gas cells keep their value."""
+    liquid = alpha > prm["eps_gas"]
+    out = omega.clone()
+    if bool(liquid.any()):
+        out[liquid] = thermo.saturation_omega(T[liquid], prm)
+    return out
+
+
+def omega_gradient(omega, h):
+    """Central-difference grad(omega) per axis, zero-gradient ghosts outside
+    the box (a ghost takes its neighbouring cell's value)."""
+    o = torch.nn.functional.pad(omega[None, None], (1, 1, 1, 1, 1, 1), mode="replicate")[0, 0]
+    gx = (o[2:, 1:-1, 1:-1] - o[:-2, 1:-1, 1:-1]) / (2.0 * h)
+    gy = (o[1:-1, 2:, 1:-1] - o[1:-1, :-2, 1:-1]) / (2.0 * h)
+    gz = (o[1:-1, 1:-1, 2:] - o[1:-1, 1:-1, :-2]) / (2.0 * h)
+    return gx, gy, gz
+
+
 def raw_evaporation(alpha, T, omega, u, v, w, geo, prm, rho_G, D_v=None):
-    """mdot_raw (kg m^-3 s^-1) on the grid; zero off the interface (eq. 17)."""
+    """mdot_raw (kg m^-3 s^-1) on the grid; zero off the interface (eq. 17).
+
+    species_form 1 (literal): omega must already hold the liquid's saturation
+    values (liquid_saturation); the diffusive flux at adj is then
+    -rho_G D (grad omega)_adj . n instead of the two-point difference."""
     D = prm["D_v"] if D_v is None else D_v
     mraw = torch.zeros_like(alpha)
     ic, adj, found = geo["icells"], geo["adj"], geo["found"]
@@ -117,7 +147,13 @@ def raw_evaporation(alpha, T, omega, u, v, w, geo, prm, rho_G, D_v=None):
     uc, vc, wc = cell_velocity(u, v, w)
     vn = (uc[aj[:, 0], aj[:, 1], aj[:, 2]] * n[:, 0] + vc[aj[:, 0], aj[:, 1], aj[:, 2]] * n[:, 1]
           + wc[aj[:, 0], aj[:, 1], aj[:, 2]] * n[:, 2])
-    jn = rho_G * D * (w_sat - w_adj) / d + rho_G * w_adj * vn
+    if prm.get("species_form", 0) == 1:
+        gx, gy, gz = omega_gradient(omega, prm["h"])
+        gn = (gx[aj[:, 0], aj[:, 1], aj[:, 2]] * n[:, 0] + gy[aj[:, 0], aj[:, 1], aj[:, 2]] * n[:, 1]
+              + gz[aj[:, 0], aj[:, 1], aj[:, 2]] * n[:, 2])
+        jn = -rho_G * D * gn + rho_G * w_adj * vn
+    else:
+        jn = rho_G * D * (w_sat - w_adj) / d + rho_G * w_adj * vn
     gm = geo["gradmag"][ic[:, 0], ic[:, 1], ic[:, 2]]
     mraw = mraw.index_put((ic[:, 0], ic[:, 1], ic[:, 2]), jn * gm)
     return mraw

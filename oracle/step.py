@@ -22,6 +22,13 @@ moved with the gas volume flux, gains mdot, and is updated after the
 implicit solve in flux form c = c' + dt mdot - dt sum_f K_f (omega_c - omega_nb),
 so the fuel mass h^3 sum(rho_L alpha + c) changes only by what crosses the
 boundary.
+Literal species form (species_form = 1, Section 2.5): at the start of the
+step the liquid cells (alpha > eps_gas) take omega = omega_sat(T) and
+c = rho_G theta omega_sat; the flux at adj uses a central grad(omega)
+(interface.raw_evaporation); the species equation (eq. 9) has no mdot
+source, the vapour entering the gas by diffusion from the saturated liquid.
+This form does not conserve the fuel mass: the liquid loses dt mdot per
+step and the assignment sets the liquid's vapour content.
 """
 from __future__ import annotations
 
@@ -40,6 +47,16 @@ def to_state(fields, prm, rho_G=None):
     return st
 
 
+def assign_liquid_saturation(st, prm, rho_G):
+    """The literal species form's start of step: omega_sat(T) in every liquid
+    cell, c = rho_G theta omega there (a new state dict; gas cells unchanged)."""
+    om = interface.liquid_saturation(st["alpha"], st["T"], st["omega"], prm)
+    theta = torch.clamp(1.0 - torch.clamp(st["alpha"], 0.0, 1.0), min=prm["theta_min"])
+    liquid = st["alpha"] > prm["eps_gas"]
+    c = torch.where(liquid, rho_G * theta * om, st["c"])
+    return dict(st, omega=om, c=c)
+
+
 def properties(alpha, prm, rho_G):
     ab = torch.clamp(alpha, 0.0, 1.0)
     rho = ab * prm["rho_L"] + (1.0 - ab) * rho_G
@@ -54,6 +71,8 @@ def evaporation_source(st, prm, rho_G, D_v=None):
     if not prm["evaporation"]:
         z = torch.zeros_like(st["alpha"])
         return z, z, torch.zeros((), dtype=torch.float64), None
+    if prm.get("species_form", 0) == 1:
+        st = assign_liquid_saturation(st, prm, rho_G)
     geo = interface.geometry(st["alpha"], prm)
     mraw = interface.raw_evaporation(st["alpha"], st["T"], st["omega"], st["u"], st["v"], st["w"],
                                      geo, prm, rho_G, D_v=D_v)
@@ -81,6 +100,10 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     if rho_G is None:
         rho_G = thermo.gas_density(prm, Ta)
     dt, h = prm["dt"], prm["h"]
+    st_in = st
+    literal = prm.get("species_form", 0) == 1
+    if literal and prm["evaporation"]:
+        st = assign_liquid_saturation(st, prm, rho_G)
     U = [st["u"], st["v"], st["w"]]
 
     # 1. evaporation flux
@@ -109,11 +132,12 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     mS = rho_G * theta / dt
     KbS = 2.0 * rho_G * D / (h * h)
     opS, _ = operators.scalar_system(mS, theta, rho_G * D / (h * h), KbS, 0.0, U, prm)
-    bS = c_p / dt + mdot
+    msrc = torch.zeros_like(mdot) if literal else mdot
+    bS = c_p / dt + msrc
     omega_p = c_p / (rho_G * theta)
     om, itS, resS, okS = solve(opS, bS, omega_p, tol, prm["maxit"])
     face_part = opS.apply(om) - mS * om
-    c_new = c_p + dt * mdot - dt * face_part
+    c_new = c_p + dt * msrc - dt * face_part
     # vapour diffused out through ambient (Dirichlet) boundary faces
     B_diff = torch.zeros((), dtype=torch.float64)
     for axis in range(3):
@@ -138,7 +162,7 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
         K=float(K), mdot_total=float(vol * mdot.sum()), B_L=float(B_L), B_v=float(B_v),
         volume=float(vol * alpha_p.sum()),
         fuel_mass=float(vol * (prm["rho_L"] * alpha_p + c_new).sum()),
-        fuel_mass_before=float(vol * (prm["rho_L"] * st["alpha"] + st["c"]).sum()),
+        fuel_mass_before=float(vol * (prm["rho_L"] * st_in["alpha"] + st_in["c"]).sum()),
         alpha_min=float(alpha_p.min()), alpha_max=float(alpha_p.max()),
         n_interface=0 if geo is None else int(geo["icells"].shape[0]),
         iters=dict(T=itT, omega=itS, p=itP), res=dict(T=resT, omega=resS, p=resP),

@@ -48,7 +48,7 @@ _BASE = dict(
     tol=1e-10, tol_phi=1e-8, maxit=20000,
     eq_model=EQ_IDEAL, bc_mode=BC_NATURAL, precision=PREC_FP64,
     solve_energy=1, evaporation=1,
-    pressure_precond=1, liquid_transport=1,
+    pressure_precond=1, liquid_transport=1, species_form=0,
 )
 
 # name -> (overrides, run description)
