@@ -57,6 +57,14 @@ typedef enum ds_status {
 enum { DS_EQ_IDEAL = 0, DS_EQ_PENG_ROBINSON = 1 };
 enum { DS_BC_NATURAL = 0, DS_BC_FORCED = 1, DS_BC_FARFIELD = 2 };
 enum { DS_PREC_FP64 = 0, DS_PREC_MIXED = 1 };
+/* Species forms (Section 2.5).  CONSERVATIVE: vapour lives in the gas
+ * fraction, c = rho_G theta omega gains mdot and is updated in flux form, the
+ * flux at adj is rho_G D (omega_sat(T_int) - omega_adj)/d.  LITERAL: the
+ * saturation value omega_sat(T) is assigned to every liquid cell
+ * (alpha > eps_gas) at the start of a step, the diffusive flux at adj is
+ * -rho_G D grad(omega).n with a central gradient (zero-gradient ghosts), and
+ * the species equation (eq. 9) has no mdot source; not mass conserving. */
+enum { DS_SPECIES_CONSERVATIVE = 0, DS_SPECIES_LITERAL = 1 };
 
 /* Physical and numerical parameters, SI units.  Property values are constant
  * (the mixing rule of Section 2.7, eq. 31, blends liquid and gas values). */
@@ -94,6 +102,7 @@ typedef struct ds_params {
   int evaporation;     /* 0: no evaporation source */
   int pressure_precond; /* 0: Jacobi-PCG, 1: geometric-multigrid PCG */
   int liquid_transport; /* 1: alpha moves with the divergence-free part of u (default); 0: with u */
+  int species_form;    /* DS_SPECIES_* */
 } ds_params;
 
 /* Scalars of the most recent step (or evaporation/pressure call). */
@@ -180,7 +189,9 @@ int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res);
 
 /* Evaporation rate of the current state, eqs. 17-21: total h^3 sum(mdot)
  * in kg/s, and optionally the volumetric source mdot (kg m^-3 s^-1) written
- * to a caller device cell array (NULL to skip). */
+ * to a caller device cell array (NULL to skip).  In the literal species form
+ * the liquid cells' omega and c are first set to their saturation values, as
+ * at the start of a step (the gas cells and every other field are kept). */
 int ds_evaporation_rate(ds_grid* g, double* kg_per_s, double* mdot_or_null, void* stream);
 
 /* Liquid volume h^3 sum(alpha) of the current state [m^3]. */
@@ -268,7 +279,9 @@ int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t
  * field), each may be NULL.  Afterwards the handle holds the final state of
  * the run again (as after ds_forward_record).  DS_ERR_STATE without a
  * recorded run; DS_ERR_NOT_CONVERGED if an adjoint solve hit maxit (results
- * are still written); DS_ERR_NONFINITE for a non-finite gradient.
+ * are still written); DS_ERR_NONFINITE for a non-finite gradient.  The
+ * adjoint covers the conservative species form: ds_forward_record returns
+ * DS_ERR_ARG for a grid created with DS_SPECIES_LITERAL.
  * Synchronises the stream. */
 int ds_adjoint(ds_grid* g, double dJ_dV, double* grads, double* dalpha0, double* dT0, double* domega0,
                double* du0, double* dv0, double* dw0, void* stream);

@@ -47,7 +47,7 @@ class Params(C.Structure):
         ("tol", C.c_double), ("tol_phi", C.c_double),
         ("s_max", C.c_int), ("maxit", C.c_int), ("eq_model", C.c_int), ("bc_mode", C.c_int),
         ("precision", C.c_int), ("solve_energy", C.c_int), ("evaporation", C.c_int), ("pressure_precond", C.c_int),
-        ("liquid_transport", C.c_int),
+        ("liquid_transport", C.c_int), ("species_form", C.c_int),
     ]
 
 
@@ -111,6 +111,8 @@ def make_params(prm: dict) -> Params:
     for name, ctype in Params._fields_:
         if name in ("pressure_precond", "liquid_transport"):
             val = prm.get(name, 1)
+        elif name == "species_form":
+            val = prm.get(name, 0)
         elif name == "eps_gas":
             val = prm.get(name, prm["eps_int"])
         elif name == "tol_phi":

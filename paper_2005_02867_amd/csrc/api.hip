@@ -679,6 +679,8 @@ int solve_pressure_system(ds_grid* g, hipStream_t s, int* iters, double* res) {
 int evaporation_source(ds_grid* g, hipStream_t s) {
   const DevParams& P = g->dp;
   if (P.evaporation) {
+    // literal species form: the liquid holds omega_sat(T) before the flux reads omega
+    if (P.species_form == DS_SPECIES_LITERAL) launch_liquid_saturation(P, g->alpha, g->T, g->omega, g->c, s);
     launch_interface(P, g->alpha, g->T, g->omega, g->u, g->v, g->w, g->mraw, g->adj, g->band, g->band_count, g->partials,
                      g->counters + CT_IFACE, g->scal, s);
   } else {
@@ -922,7 +924,8 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
       !finite_pos(prm->theta_min) || !(prm->tol > 0) || !(prm->tol_phi > 0) || prm->maxit < 1 || prm->s_max < 1 ||
       prm->eq_model < 0 || prm->eq_model > 1 || prm->bc_mode < 0 || prm->bc_mode > 2 ||
       prm->precision < 0 || prm->precision > 1 || !finite_pos(prm->r_fib) || prm->pressure_precond < 0 ||
-      prm->pressure_precond > 1 || prm->liquid_transport < 0 || prm->liquid_transport > 1)
+      prm->pressure_precond > 1 || prm->liquid_transport < 0 || prm->liquid_transport > 1 ||
+      prm->species_form < 0 || prm->species_form > 1)
     return DS_ERR_ARG;
   if (prm->eq_model == DS_EQ_PENG_ROBINSON &&
       (!finite_pos(prm->Tc) || !finite_pos(prm->Pc) || !finite_pos(prm->Tc_G) || !finite_pos(prm->Pc_G)))
@@ -975,6 +978,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   P.eq_model = prm->eq_model;
   P.solve_energy = prm->solve_energy;
   P.evaporation = prm->evaporation;
+  P.species_form = prm->species_form;
   // gas density, eq. 24, for the ambient gas at (T_amb, p)
   const double Z = prm->eq_model == DS_EQ_PENG_ROBINSON
                        ? host_pr_Z(prm->T_amb, prm->p, prm->Tc_G, prm->Pc_G, prm->acentric_G)
@@ -1294,6 +1298,8 @@ int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t
   if (!g) return DS_ERR_ARG;
   if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
   if (nsteps < 1 || ckpt_every < 1 || !tape) return fail(g, DS_ERR_ARG, "nsteps and ckpt_every must be >= 1, tape non-null");
+  if (g->prm.species_form != DS_SPECIES_CONSERVATIVE)
+    return fail(g, DS_ERR_ARG, "the adjoint covers the conservative species form only");
   const int C = std::min(ckpt_every, nsteps);
   const size_t need = tape_total_bytes(g, nsteps, C);
   if (tape_bytes < need) return fail(g, DS_ERR_ARG, "tape too small: %zu < %zu bytes", tape_bytes, need);

@@ -26,6 +26,7 @@ struct DevParams {
   double eps, eps_gas, theta_min, rho_G;
   int kind[6];                      // box face kinds, index axis*2 + side
   int eq_model, solve_energy, evaporation;
+  int species_form;                 // 0 conservative, 1 literal (saturated liquid, central gradient at adj)
 };
 
 // Status of one iterative solve, updated on the device.

@@ -156,12 +156,27 @@ __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const
       if (hit >= 0) {
         const double di = ti - i, dj = tj - j, dk = tk - k;
         const double d = P.h * sqrt(di * di + dj * dj + dk * dk);
-        const double wsat = mass_fraction(P, equilibrium_y(P, T[c]));
         const double wa = omega[hit];
         const double va = 0.5 * (u[uidx(P, ti, tj, tk)] + u[uidx(P, ti + 1, tj, tk)]) * nx +
                           0.5 * (v[vidx(P, ti, tj, tk)] + v[vidx(P, ti, tj + 1, tk)]) * ny +
                           0.5 * (w[widx(P, ti, tj, tk)] + w[widx(P, ti, tj, tk + 1)]) * nz;
-        const double jn = P.rho_G * P.D * (wsat - wa) / d + P.rho_G * wa * va;
+        double jd;
+        if (P.species_form == 1) {
+          // literal form: central grad(omega) at adj over the saturated liquid,
+          // a ghost outside the box takes the adj value
+          const double oxm = ti > 0 ? omega[hit - (long long)P.ny * P.nz] : wa;
+          const double oxp = ti + 1 < P.nx ? omega[hit + (long long)P.ny * P.nz] : wa;
+          const double oym = tj > 0 ? omega[hit - P.nz] : wa;
+          const double oyp = tj + 1 < P.ny ? omega[hit + P.nz] : wa;
+          const double ozm = tk > 0 ? omega[hit - 1] : wa;
+          const double ozp = tk + 1 < P.nz ? omega[hit + 1] : wa;
+          const double gx = (oxp - oxm) / (2.0 * P.h), gy = (oyp - oym) / (2.0 * P.h), gz = (ozp - ozm) / (2.0 * P.h);
+          jd = -P.rho_G * P.D * (gx * nx + gy * ny + gz * nz);
+        } else {
+          const double wsat = mass_fraction(P, equilibrium_y(P, T[c]));
+          jd = P.rho_G * P.D * (wsat - wa) / d;
+        }
+        const double jn = jd + P.rho_G * wa * va;
         m = jn * (nrm / (2.0 * P.h));
       }
     }
@@ -180,6 +195,25 @@ __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const
       scal[SC_S2] = tot[1];
       scal[SC_NINT] = tot[2];
       scal[SC_K] = tot[1] != 0.0 ? tot[0] / tot[1] : 0.0;
+    }
+  }
+}
+
+// Literal species form (Section 2.5, after eq. 23): every liquid cell
+// (alpha > eps_gas, the complement of the march's gas test) takes the
+// saturation value at its own temperature, omega = omega_sat(T) and
+// c = rho_G theta omega; gas cells are left alone.
+__global__ void k_liquid_saturation(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
+                                    double* __restrict__ omega, double* __restrict__ c) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+    const double a = alpha[e];
+    if (a > P.eps_gas) {
+      const double ws = mass_fraction(P, equilibrium_y(P, T[e]));
+      const double th = fmax(1.0 - clamp01(a), P.theta_min);
+      omega[e] = ws;
+      c[e] = P.rho_G * th * ws;
     }
   }
 }
@@ -378,7 +412,8 @@ __global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, co
   }
 }
 
-// Species, eq. 9 for c = rho_G theta omega: (rho_G theta/dt) w - div(rho_G D theta grad w) = c'/dt + mdot.
+// Species, eq. 9 for c = rho_G theta omega: (rho_G theta/dt) w - div(rho_G D theta grad w) = c'/dt + mdot
+// (without mdot in the literal species form).
 __global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
                                 const double* __restrict__ mdot, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
@@ -409,7 +444,8 @@ __global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, c
       }
     qc[c] = th;
     diag[c] = d;
-    b[c] = cp_[c] / P.dt + mdot[c];
+    // the literal species form has no mdot source (the saturated liquid feeds the gas)
+    b[c] = P.species_form == 1 ? cp_[c] / P.dt : cp_[c] / P.dt + mdot[c];
     if (om0) om0[c] = cp_[c] / (P.rho_G * th);
     if (fo.q) {
       fo.q[c] = (float)th;
@@ -452,7 +488,7 @@ __global__ void k_species_update(DevParams P, const double* __restrict__ a_new, 
           acc[0] += Kb * oc;
         }
       }
-    const double cn = cp_[c] + P.dt * mdot[c] - P.dt * face;
+    const double cn = (P.species_form == 1 ? cp_[c] : cp_[c] + P.dt * mdot[c]) - P.dt * face;
     cout[c] = cn;
     omega[c] = cn / (P.rho_G * th);
   }
@@ -773,6 +809,10 @@ void launch_interface(const DevParams& P, const double* alpha, const double* T, 
                                     scal);
 }
 // band_count holds MAX_BLOCKS counts, then MAX_BLOCKS + 1 offsets.
+void launch_liquid_saturation(const DevParams& P, const double* alpha, const double* T, double* omega, double* c,
+                              hipStream_t s) {
+  k_liquid_saturation<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, alpha, T, omega, c);
+}
 long long interface_band_capacity(long long n) {
   const int nb = grid_blocks(n);
   const long long cap = ((n + nb - 1) / nb + BLOCK - 1) / BLOCK * BLOCK;

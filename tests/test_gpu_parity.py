@@ -317,3 +317,71 @@ def test_precision_form_volume_after_200_steps():
     rel = abs(vols[W.PREC_MIXED] - vols[W.PREC_FP64]) / vols[W.PREC_FP64]
     print("volume FP64", vols[W.PREC_FP64], "mixed", vols[W.PREC_MIXED], "rel", rel)
     assert rel <= 1e-6
+
+
+@pytest.mark.parametrize("mode", [W.BC_NATURAL, W.BC_FARFIELD])
+def test_step_parity_literal_species_form(mode):
+    """Literal species form (saturated liquid, central grad(omega) at adj, no
+    mdot source in eq. 9) on the ragged 17x19x23 grid with flow, 3 steps,
+    every field and the fuel mass against the oracle."""
+    prm, _ = _grid_params(n=(17, 19, 23), L=17 * 1.25e-4, bc_mode=mode, species_form=1)
+    f = W.random_fields(prm, seed=13)
+    g, st, worst = _run_both(prm, f, steps=3)
+    gd = g.diagnostics()
+    st_o = S.to_state(f, dict(prm, tol=1e-13, tol_phi=1e-13))
+    for _ in range(3):
+        st_o, d = S.step(st_o, dict(prm, tol=1e-13, tol_phi=1e-13))
+    assert gd["fuel_mass"] == pytest.approx(d["fuel_mass"], rel=1e-10)
+    assert gd["fuel_mass_before"] == pytest.approx(d["fuel_mass_before"], rel=1e-10)
+    print("worst relative errors:", worst)
+
+
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_step_parity_literal_species_peng_robinson(precision):
+    """Literal species form with the Peng-Robinson equilibrium assigned to
+    every liquid cell (20 bar, a 24^3 cut of the 256^3 workload's box with a
+    2 mm droplet, six cells across: a three-cell droplet has only diagonal
+    adj cells, whose face neighbours miss the liquid), 3 steps, both
+    precision forms."""
+    prm, run = W.scaled("C3", 24)
+    prm = dict(prm, precision=precision, species_form=1)
+    f = W.initial_fields(prm, D0=2e-3, seed=2, T_noise=0.02)
+    _run_both(prm, f, steps=3)
+
+
+def test_literal_species_evaporation_rate_and_assignment():
+    """ds_evaporation_rate in the literal form: the liquid's omega equals the
+    oracle's saturation values (gas cells untouched), the raw source and
+    mdot agree to rounding, adj decisions bit-exact."""
+    ds = _lib()
+    from oracle import interface as I, thermo as th
+    prm, _ = _grid_params(n=(24, 26, 28), L=24 * 1.25e-4, species_form=1)
+    f = W.random_fields(prm, seed=4)
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    total, mdot = g.evaporation_rate(return_field=True)
+    rho_G = th.gas_density(prm)
+    st = S.assign_liquid_saturation(S.to_state(f, prm), prm, rho_G)
+    liquid = st["alpha"] > prm["eps_gas"]
+    assert bool(liquid.any())
+    om_g = torch.as_tensor(g.get_fields()["omega"], dtype=torch.float64).cpu()
+    assert _rel(om_g[liquid], st["omega"][liquid]) < 1e-13
+    assert torch.equal(om_g[~liquid], torch.as_tensor(f["omega"], dtype=torch.float64)[~liquid])
+    geo = I.geometry(st["alpha"], prm)
+    mraw = I.raw_evaporation(st["alpha"], st["T"], st["omega"], st["u"], st["v"], st["w"], geo, prm, rho_G)
+    assert _rel(g.internal(ds.FIELD_MDOT_RAW), mraw) < 1e-12
+    mdot_o, K = I.redistribute(mraw, st["alpha"])
+    assert _rel(mdot, mdot_o) < 1e-12
+    assert total == pytest.approx(prm["h"] ** 3 * float(mdot_o.sum()), rel=1e-12)
+
+
+def test_literal_species_form_rejected_by_the_adjoint():
+    ds = _lib()
+    prm, run = W.config("C1", species_form=1)
+    f = W.initial_fields(prm, **run)
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    tape = torch.empty(ds.tape_bytes(g.h, 2, 1), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ds.DSError) as e:
+        ds.forward_record(g.h, 2, 1, tape)
+    assert e.value.code == ds.DS_ERR_ARG
