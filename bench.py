@@ -45,13 +45,14 @@ def timed_run(ds, torch, prm, fields, steps, warmup, timing=False):
     torch.cuda.synchronize()
     if timing:
         g.set_kernel_timing(True)
-    iters = []
+    iters, mdot = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         g.step(1)
         d = g.diagnostics()
         iters.append([d["iters_T"], d["iters_omega"], d["iters_p"], d["refinements_p"], d["iters_phi"]])
+        mdot.append(d["mdot_total"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = g.kernel_timing() if timing else None
@@ -59,7 +60,8 @@ def timed_run(ds, torch, prm, fields, steps, warmup, timing=False):
     # the same operator kernel replayed back to back on the live pressure system
     rep = g.time_operator_kernel(50) if timing else None
     rep_s = g.time_kernel(1, 50) if timing else None      # fine-level multigrid sweep
-    return dict(seconds=t1 - t0, iters=iters, kernel=kt, replay=rep, replay_smooth=rep_s, volume=d["volume"], diag=d)
+    return dict(seconds=t1 - t0, iters=iters, kernel=kt, replay=rep, replay_smooth=rep_s, volume=d["volume"], diag=d,
+                mdot=mdot)
 
 
 def adjoint_cost(ds, torch, W):
@@ -212,6 +214,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     ap.add_argument("--configs", action="store_true",
                     help="also time the other configurations (32^3 ... 384^3) and the 384^3 adjoint")
+    ap.add_argument("--species-literal", action="store_true",
+                    help="also time the workload in the literal species form (saturated liquid, central gradient "
+                         "at adj, no mdot source in the species equation) and compare its evaporation rate")
     ap.add_argument("--counters-pass", action="store_true",
                     help="short run for hardware-counter passes: one step of the workload, 5 replayed launches of "
                          "the fine-level sweep, then 3 device copies of 1 GiB (the counter calibration)")
@@ -302,6 +307,17 @@ def main():
                        "operator_kernel_GBs": rp64["bytes_per_launch"] / (rp64["avg_us"] * 1e-6) / 1e9}
         out["speedup_mixed_vs_fp64"] = out["value"] / v64
         out["volume_rel_diff_mixed_vs_fp64"] = abs(mixed["volume"] - fp64["volume"]) / fp64["volume"]
+    if args.species_literal:
+        log(f"literal species form, precision form: warmup {args.warmup}, timing {args.steps} steps")
+        lit = timed_run(ds, torch, dict(prm, precision=W.PREC_MIXED, species_form=1), fields, args.steps,
+                        args.warmup)
+        log(f"  {lit['seconds'] * 1e3 / args.steps:.2f} ms/step, iters {lit['iters'][-1]}")
+        out["species_literal"] = {
+            "value": ncell * args.steps / lit["seconds"], "ms_per_step": lit["seconds"] * 1e3 / args.steps,
+            "iters_T_omega_p_rounds_phi": lit["iters"][-1],
+            "mdot_total_kg_s": lit["mdot"], "mdot_total_conservative_kg_s": mixed["mdot"],
+            "step_of_first_timed": args.warmup + 1,
+        }
     if not args.no_adjoint:
         log("adjoint cost: 96^3, 100 steps")
         out["adjoint"] = adjoint_cost(ds, torch, W)

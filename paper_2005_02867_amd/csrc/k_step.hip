@@ -202,12 +202,15 @@ __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const
 // Literal species form (Section 2.5, after eq. 23): every liquid cell
 // (alpha > eps_gas, the complement of the march's gas test) takes the
 // saturation value at its own temperature, omega = omega_sat(T) and
-// c = rho_G theta omega; gas cells are left alone.
+// c = rho_G theta omega; gas cells are left alone.  One thread per cell (a
+// grid-stride loop only past 2^20 blocks): each wave holding liquid cells is
+// scheduled on its own, so the per-cell equilibrium solves of the droplet
+// run side by side on every compute unit instead of queueing in the few
+// blocks whose ranges would hold the droplet.
 __global__ void k_liquid_saturation(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
                                     double* __restrict__ omega, double* __restrict__ c) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
-  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+  const long long stride = (long long)gridDim.x * BLOCK;
+  for (long long e = (long long)blockIdx.x * BLOCK + threadIdx.x; e < P.n; e += stride) {
     const double a = alpha[e];
     if (a > P.eps_gas) {
       const double ws = mass_fraction(P, equilibrium_y(P, T[e]));
@@ -811,7 +814,8 @@ void launch_interface(const DevParams& P, const double* alpha, const double* T, 
 // band_count holds MAX_BLOCKS counts, then MAX_BLOCKS + 1 offsets.
 void launch_liquid_saturation(const DevParams& P, const double* alpha, const double* T, double* omega, double* c,
                               hipStream_t s) {
-  k_liquid_saturation<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, alpha, T, omega, c);
+  const long long nb = std::min<long long>((P.n + BLOCK - 1) / BLOCK, 1LL << 20);
+  k_liquid_saturation<<<(unsigned)nb, BLOCK, 0, s>>>(P, alpha, T, omega, c);
 }
 long long interface_band_capacity(long long n) {
   const int nb = grid_blocks(n);
