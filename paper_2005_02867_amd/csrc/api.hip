@@ -680,7 +680,7 @@ int evaporation_source(ds_grid* g, hipStream_t s) {
   const DevParams& P = g->dp;
   if (P.evaporation) {
     // literal species form: the liquid holds omega_sat(T) before the flux reads omega
-    if (P.species_form == DS_SPECIES_LITERAL) launch_liquid_saturation(P, g->alpha, g->T, g->omega, g->c, s);
+    if (P.species_form == DS_SPECIES_LITERAL) launch_liquid_saturation(P, g->alpha, g->T, g->omega, g->c, g->band, g->band_count, s);
     launch_interface(P, g->alpha, g->T, g->omega, g->u, g->v, g->w, g->mraw, g->adj, g->band, g->band_count, g->partials,
                      g->counters + CT_IFACE, g->scal, s);
   } else {

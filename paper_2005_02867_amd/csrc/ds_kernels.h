@@ -41,9 +41,10 @@ void launch_interface(const DevParams& P, const double* alpha, const double* T, 
                       int* band_count, double* partials, unsigned* counter, double* scal, hipStream_t s);
 long long interface_band_capacity(long long n);   // ints needed for `band`
 // Literal species form: omega = omega_sat(T), c = rho_G theta omega in every
-// cell with alpha > eps_gas; other cells untouched.
+// cell with alpha > eps_gas; other cells untouched.  Uses band and
+// band_count (as launch_interface) for the list of liquid cells.
 void launch_liquid_saturation(const DevParams& P, const double* alpha, const double* T, double* omega, double* c,
-                              hipStream_t s);
+                              int* band, int* band_count, hipStream_t s);
 // band_count: 2 * MAX_BLOCKS + 1 ints (per-block counts, then their offsets).
 void launch_source(const DevParams& P, const double* alpha, const double* mraw, const double* scal,
                    double* mdot, double* a1, hipStream_t s);

@@ -132,13 +132,21 @@ __device__ inline double equilibrium_y(const DevParams& P, double T) {
   double y = fmin(p0 / P.p, 1.0 - 1e-12);
   if (P.eq_model == 0) return y;
   const double L = pr_lnrhs<double>(P, T, P.dh);
+  // Stop when the step is below 1e-15 y, or below 1e-14 y and no longer
+  // shrinking: at the rounding floor of g some temperatures (about 1 in 500)
+  // alternate between two iterates 1.2e-15 apart, and without the second
+  // test they ran to the iteration cap, holding their whole wave for ten
+  // times the usual six iterations.
+  double prev = INFINITY;
   for (int it = 0; it < 60; ++it) {
     dual yd = mkd(y, 1.0);
     dual g = dlog(yd) + pr_lnphi_fuel<dual>(P, mkd(T), mkd(P.p), yd) - L;
     double ynew = y - g.v / g.d;
     if (!(ynew > 0.0)) ynew = 0.5 * y;
     ynew = fmin(ynew, 1.0 - 1e-12);
-    const bool done = fabs(ynew - y) <= 1e-15 * ynew;
+    const double step = fabs(ynew - y);
+    const bool done = step <= 1e-15 * ynew || (step <= 1e-14 * ynew && step >= prev);
+    prev = step;
     y = ynew;
     if (done) break;
   }

@@ -43,6 +43,9 @@ __global__ void k_xi(DevParams P, double* xi) {
 // interface cell (eps < alpha < 1 - eps) is appended, in cell order, to this
 // block's list (wave ballots give each lane its slot), so pass 2 runs the
 // march and the phase equilibrium only where they apply, one cell per lane.
+// LIQ: list the liquid cells (alpha > eps_gas) instead and write nothing
+// else (the literal species form's saturation pass).
+template <bool LIQ>
 __global__ void __launch_bounds__(BLOCK) k_interface_scan(DevParams P, const double* __restrict__ alpha,
                                                          double* __restrict__ mraw, int* __restrict__ adj,
                                                          int* __restrict__ band, int* __restrict__ band_count) {
@@ -61,9 +64,13 @@ __global__ void __launch_bounds__(BLOCK) k_interface_scan(DevParams P, const dou
     bool cand = false;
     if (c < b1) {
       const double a = alpha[c];
-      cand = a > P.eps && a < 1.0 - P.eps;
-      mraw[c] = 0.0;
-      adj[c] = cand ? -1 : -2;
+      if (LIQ) {
+        cand = a > P.eps_gas;
+      } else {
+        cand = a > P.eps && a < 1.0 - P.eps;
+        mraw[c] = 0.0;
+        adj[c] = cand ? -1 : -2;
+      }
     }
     const unsigned long long m = __ballot(cand);
     if (lane == 0) wave_cnt[wid] = __popcll(m);
@@ -103,6 +110,19 @@ __global__ void __launch_bounds__(1024) k_band_offsets(const int* __restrict__ c
   if (t == 1023) off[nb] = base + v;
 }
 
+// Entry g of the per-block lists taken as one sequence: the list holding it
+// is the largest b with off[b] <= g.
+__device__ __forceinline__ long long band_entry(const int* __restrict__ band, const int* __restrict__ off, int nlists,
+                                                long long cap, int g) {
+  int lo = 0, hi = nlists - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return band[(long long)lo * cap + (g - off[lo])];
+}
+
 // Pass 2 (interface cells, all lists taken as one sequence in cell order and
 // dealt to full waves): central-difference gradient
 // with a zero ghost outside the box, outward normal n = -grad/|grad|, march
@@ -119,14 +139,7 @@ __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const
   double acc[3] = {0.0, 0.0, 0.0};
   const int total = off[nlists];
   for (int g = blockIdx.x * BLOCK + threadIdx.x; g < total; g += gridDim.x * BLOCK) {
-    // the list holding entry g: largest b with off[b] <= g
-    int lo = 0, hi = nlists - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (off[mid] <= g) lo = mid;
-      else hi = mid - 1;
-    }
-    const long long c = band[(long long)lo * cap + (g - off[lo])];
+    const long long c = band_entry(band, off, nlists, cap, g);
     const double a = alpha[c];
     double m = 0.0;
     int hit = -1;
@@ -202,22 +215,22 @@ __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const
 // Literal species form (Section 2.5, after eq. 23): every liquid cell
 // (alpha > eps_gas, the complement of the march's gas test) takes the
 // saturation value at its own temperature, omega = omega_sat(T) and
-// c = rho_G theta omega; gas cells are left alone.  One thread per cell (a
-// grid-stride loop only past 2^20 blocks): each wave holding liquid cells is
-// scheduled on its own, so the per-cell equilibrium solves of the droplet
-// run side by side on every compute unit instead of queueing in the few
-// blocks whose ranges would hold the droplet.
+// c = rho_G theta omega; gas cells are left alone.  The liquid cells come
+// from the lists of k_interface_scan<true> (a light pass over all cells at
+// full occupancy) and are dealt to full waves, so the per-cell equilibrium
+// solves, whose code holds 128 VGPRs, run side by side on every compute
+// unit and no wave of this kernel streams gas cells.
 __global__ void k_liquid_saturation(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
-                                    double* __restrict__ omega, double* __restrict__ c) {
-  const long long stride = (long long)gridDim.x * BLOCK;
-  for (long long e = (long long)blockIdx.x * BLOCK + threadIdx.x; e < P.n; e += stride) {
+                                    const int* __restrict__ band, const int* __restrict__ off, int nlists,
+                                    long long cap, double* __restrict__ omega, double* __restrict__ c) {
+  const int total = off[nlists];
+  for (int g = blockIdx.x * BLOCK + threadIdx.x; g < total; g += gridDim.x * BLOCK) {
+    const long long e = band_entry(band, off, nlists, cap, g);
     const double a = alpha[e];
-    if (a > P.eps_gas) {
-      const double ws = mass_fraction(P, equilibrium_y(P, T[e]));
-      const double th = fmax(1.0 - clamp01(a), P.theta_min);
-      omega[e] = ws;
-      c[e] = P.rho_G * th * ws;
-    }
+    const double ws = mass_fraction(P, equilibrium_y(P, T[e]));
+    const double th = fmax(1.0 - clamp01(a), P.theta_min);
+    omega[e] = ws;
+    c[e] = P.rho_G * th * ws;
   }
 }
 
@@ -805,7 +818,7 @@ void launch_interface(const DevParams& P, const double* alpha, const double* T, 
   const int nb = grid_blocks(P.n);
   const long long cap = ((P.n + nb - 1) / nb + BLOCK - 1) / BLOCK * BLOCK;
   int* off = band_count + MAX_BLOCKS;   // nb + 1 offsets after the counts
-  k_interface_scan<<<nb, BLOCK, 0, s>>>(P, alpha, mraw, adj, band, band_count);
+  k_interface_scan<false><<<nb, BLOCK, 0, s>>>(P, alpha, mraw, adj, band, band_count);
   k_band_offsets<<<1, 1024, 0, s>>>(band_count, nb, off);
   const int nbi = std::max(NXCD, nb / 8);
   k_interface<<<nbi, BLOCK, 0, s>>>(P, alpha, T, omega, u, v, w, band, off, nb, cap, mraw, adj, partials, counter,
@@ -813,9 +826,13 @@ void launch_interface(const DevParams& P, const double* alpha, const double* T, 
 }
 // band_count holds MAX_BLOCKS counts, then MAX_BLOCKS + 1 offsets.
 void launch_liquid_saturation(const DevParams& P, const double* alpha, const double* T, double* omega, double* c,
-                              hipStream_t s) {
-  const long long nb = std::min<long long>((P.n + BLOCK - 1) / BLOCK, 1LL << 20);
-  k_liquid_saturation<<<(unsigned)nb, BLOCK, 0, s>>>(P, alpha, T, omega, c);
+                              int* band, int* band_count, hipStream_t s) {
+  const int nb = grid_blocks(P.n);
+  const long long cap = ((P.n + nb - 1) / nb + BLOCK - 1) / BLOCK * BLOCK;
+  int* off = band_count + MAX_BLOCKS;
+  k_interface_scan<true><<<nb, BLOCK, 0, s>>>(P, alpha, nullptr, nullptr, band, band_count);
+  k_band_offsets<<<1, 1024, 0, s>>>(band_count, nb, off);
+  k_liquid_saturation<<<std::max(NXCD, nb / 8), BLOCK, 0, s>>>(P, alpha, T, band, off, nb, cap, omega, c);
 }
 long long interface_band_capacity(long long n) {
   const int nb = grid_blocks(n);
