@@ -7,6 +7,9 @@
   form, multigrid): fuel mass conserved to 1e-10 per step, the liquid budget
   closes, and div u = mdot (1/rho_G - 1/rho_L) to the solve tolerance.
 * d^2 law on the GPU path (equal to the oracle step for step) at R/h = 8, 16.
+* Literal species form at 256^3: the liquid assignment, adj and raw source
+  against the oracle on the sub-block; the fuel balance without a vapour
+  source in the precision form.
 """
 import math
 
@@ -96,6 +99,79 @@ def test_c3_properties_in_bench_configuration():
     err = float((div - S_).abs().max())
     print("max |div u - S| / max |S|", err / scale)
     assert err <= 1e-6 * scale
+
+
+def test_c3_literal_species_sampled_parity():
+    """Literal species form at 256^3: the liquid's assigned saturation values
+    (all liquid cells lie in the sub-block), gas cells untouched, adj
+    bit-exact and the raw source (central gradient at adj) against the
+    oracle on the sub-block."""
+    ds = _lib()
+    from oracle import interface as I, thermo as th, step as S
+    prm, run = W.config("C3", species_form=1)
+    f = W.initial_fields(prm, **run)
+    print("256^3 C3 initial state, literal species form: interface source", flush=True)
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    total, mdot = g.evaporation_rate(return_field=True)
+    adj = g.internal(ds.FIELD_ADJ).cpu().numpy().astype(np.int64)
+    mraw = g.internal(ds.FIELD_MDOT_RAW).cpu().numpy()
+    om_g = g.get_fields()["omega"].cpu().numpy()
+    n = prm["nx"]
+    lo, hi = n // 2 - 40, n // 2 + 40
+    sub = dict(prm, nx=hi - lo, ny=hi - lo, nz=hi - lo)
+    cut = lambda x, e=(0, 0, 0): torch.tensor(x[lo:hi + e[0], lo:hi + e[1], lo:hi + e[2]].copy())
+    a, T, om = cut(f["alpha"]), cut(f["T"]), cut(f["omega"])
+    u, v, w = cut(f["u"], (1, 0, 0)), cut(f["v"], (0, 1, 0)), cut(f["w"], (0, 0, 1))
+    liquid_full = f["alpha"] > prm["eps_gas"]
+    assert liquid_full.sum() == liquid_full[lo:hi, lo:hi, lo:hi].sum() > 0
+    om_a = I.liquid_saturation(a, T, om, sub).numpy()
+    liq = a.numpy() > prm["eps_gas"]
+    gl = om_g[lo:hi, lo:hi, lo:hi][liq]
+    assert np.linalg.norm(gl - om_a[liq]) / np.linalg.norm(om_a[liq]) < 1e-13
+    assert np.array_equal(om_g[~liquid_full], f["omega"][~liquid_full])
+    geo = I.geometry(a, sub)
+    rho_G = th.gas_density(prm)
+    ref = I.raw_evaporation(a, T, torch.tensor(om_a), u, v, w, geo, sub, rho_G).numpy()
+    ic = geo["icells"].numpy()
+    found = geo["found"].numpy()
+    aj = geo["adj"].numpy() + lo
+    assert aj[found].max() <= hi - 2 and aj[found].min() >= lo + 1   # adj's neighbours inside the sub-block
+    flat = (aj[:, 0] * n + aj[:, 1]) * n + aj[:, 2]
+    got = adj[ic[:, 0] + lo, ic[:, 1] + lo, ic[:, 2] + lo]
+    assert np.array_equal(got[found], flat[found])
+    gpu = mraw[lo:hi, lo:hi, lo:hi]
+    err = np.linalg.norm(gpu - ref) / np.linalg.norm(ref)
+    print("interface cells", ic.shape[0], "liquid cells", int(liq.sum()), "rel err mraw", err, "total", total)
+    assert err < 1e-12
+    f_ = np.sqrt(np.clip(a.numpy() * (1 - a.numpy()), 0, None))
+    K_ref = ref.sum() / (f_ * ref).sum()
+    assert g.diagnostics()["K"] == pytest.approx(K_ref, rel=1e-12)
+
+
+def test_c3_literal_species_fuel_balance_in_bench_configuration():
+    """Literal species form at 256^3 in the precision form: from the assigned
+    state, the fuel mass falls by dt h^3 sum(mdot) (no vapour source) plus
+    what leaves the box, to 1e-10 per step."""
+    ds = _lib()
+    prm, run = W.config("C3", species_form=1)
+    f = W.initial_fields(prm, **run)
+    print("256^3 C3: 2 steps, literal species form", flush=True)
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    h = prm["h"]
+    for k in range(2):
+        g.evaporation_rate()                  # assigns the liquid's saturation values, as the step does
+        out = g.get_fields()
+        a = out["alpha"]
+        g.step(1)
+        d = g.diagnostics()
+        th_ = torch.clamp(1.0 - torch.clamp(a, 0.0, 1.0), min=prm["theta_min"])
+        M0 = h ** 3 * float((prm["rho_L"] * a + d["rho_G"] * th_ * out["omega"]).sum())
+        expect = M0 - prm["dt"] * d["mdot_total"] - d["B_L"] - d["B_v"]
+        print("step", k, "mdot", d["mdot_total"], "rel", abs(d["fuel_mass"] - expect) / M0)
+        assert abs(d["fuel_mass"] - expect) <= 1e-10 * M0
+        assert d["converged"] == 1 and d["mdot_total"] > 0
 
 
 def _d2_gpu(n, T, tend):
