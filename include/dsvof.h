@@ -184,7 +184,9 @@ int ds_step(ds_grid* g, int nsteps, void* stream);
 
 /* On the current state, without advancing alpha, T or omega: evaporation
  * source (Section 2.4), momentum predictor with gravity and f_m (eq. 30),
- * pressure solve (eq. 7) and velocity correction; p and u, v, w are updated. */
+ * pressure solve (eq. 7) and velocity correction; p and u, v, w are updated.
+ * In the literal species form the liquid cells' omega and c are first set to
+ * their saturation values (as in ds_evaporation_rate). */
 int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res);
 
 /* Evaporation rate of the current state, eqs. 17-21: total h^3 sum(mdot)
