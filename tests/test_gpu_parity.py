@@ -385,3 +385,24 @@ def test_literal_species_form_rejected_by_the_adjoint():
     with pytest.raises(ds.DSError) as e:
         ds.forward_record(g.h, 2, 1, tape)
     assert e.value.code == ds.DS_ERR_ARG
+
+
+def test_step_parity_literal_species_droplet_at_the_wall():
+    """Literal species form with the droplet's band reaching the x- wall
+    (24^3, centre 0.6 mm from it): adj cells on the box face take the
+    zero-gradient ghost in the central difference, and marches that leave
+    the box give no source.  3 steps against the oracle."""
+    n = 24
+    h = 1.25e-4
+    prm, _ = W.config("C1", species_form=1)
+    prm = W.finalize(dict(prm, nx=n, ny=n, nz=n, h=h, x0=(0.6e-3, n * h / 2, n * h / 2)))
+    f = W.initial_fields(prm, D0=1.0e-3, seed=3, T_noise=0.01)
+    _run_both(prm, f, steps=3)
+
+
+def test_step_parity_literal_species_without_evaporation():
+    """Literal species form with evaporation off: nothing is assigned to the
+    liquid and there is no source; 2 steps against the oracle."""
+    prm, _ = _grid_params(n=(17, 19, 23), L=17 * 1.25e-4, species_form=1, evaporation=0)
+    f = W.random_fields(prm, seed=17)
+    _run_both(prm, f, steps=2)
