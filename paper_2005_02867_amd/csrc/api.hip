@@ -356,10 +356,8 @@ int sync_status(ds_grid* g, int slot, hipStream_t s) {
 }
 
 int init_status(ds_grid* g, int slot, double tol, int maxit, hipStream_t s) {
-  SolveStatus init{};
-  init.tol = tol;
-  init.maxit = maxit;
-  HIPCHK(g, hipMemcpyAsync(g->status + slot, &init, sizeof(init), hipMemcpyHostToDevice, s));
+  launch_init_status(g->status + slot, tol, maxit, s);
+  HIPCHK(g, hipGetLastError());
   return DS_OK;
 }
 

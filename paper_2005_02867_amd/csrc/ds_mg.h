@@ -194,5 +194,7 @@ template <class T>
 void launch_neumann_start(const Lev<T>& L, const T* r, T* z, SolveStatus* st, double* partials, unsigned* counter,
                           hipStream_t s);
 void launch_to_float(const double* a, float* b, long long n, hipStream_t s);
+// *st = a fresh status (zeros, tol, maxit), written by a kernel on stream s.
+void launch_init_status(SolveStatus* st, double tol, int maxit, hipStream_t s);
 
 }  // namespace dsv

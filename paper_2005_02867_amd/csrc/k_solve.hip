@@ -2401,6 +2401,21 @@ void launch_to_float(const double* a, float* b, long long n, hipStream_t s) {
   k_to_float<<<grid_blocks(n), BLOCK, 0, s>>>(a, b, n);
 }
 
+// A fresh solve status (zeros, tol, maxit) written on the device: stream
+// ordered without a host-to-device copy, which from pageable memory would be
+// staged by the runtime.
+__global__ void k_init_status(SolveStatus* __restrict__ st, double tol, int maxit) {
+  if (threadIdx.x == 0) {
+    SolveStatus v{};
+    v.tol = tol;
+    v.maxit = maxit;
+    *st = v;
+  }
+}
+void launch_init_status(SolveStatus* st, double tol, int maxit, hipStream_t s) {
+  k_init_status<<<1, 64, 0, s>>>(st, tol, maxit);
+}
+
 // FP64 CG preconditioned by the FP32 V-cycle (levels whose nz is even).
 void cg_start_mg32(const Lev<double>& L, MgHier<float>& H, const double* r64, float* r32, float** z, SolveStatus* st,
                    double* partials, unsigned* counters, hipStream_t s, bool r32_ready) {
