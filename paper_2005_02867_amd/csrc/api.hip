@@ -111,6 +111,10 @@ struct ds_grid {
   ds_diagnostics diag_out{};
   double fuel_mass_prev = 0.0;
   int batch[3] = {8, 8, 8};
+  // FP32 rounds of the precision form: inner iterations the previous solve of
+  // each system took in its first, second, third (and later) round; the first
+  // round needs more than the later ones
+  int batch_round[3][3] = {{8, 8, 8}, {8, 8, 8}, {8, 8, 8}};
   // differentiation form: arrays carved from the caller's tape
   char* tape = nullptr;
   size_t tape_bytes = 0, tape_slot_off = 0;
@@ -531,9 +535,13 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     }
     bool first = true;
     const bool timed = g->timing && H;
+    int& expect = g->batch_round[sys][std::min(rounds, 2)];
     do {
       const int it0 = g->h_status[3].it;
-      const int b = batch_size(batch_of(g, sys, x), first);
+      // one iteration of margin for the Jacobi-type systems: an iteration
+      // that finds the solve converged costs two launches that return at once,
+      // well under one more host convergence test
+      const int b = batch_size(H ? expect : expect + 1, first);
       const int m = timed ? std::min(b, (int)ds_grid::NEV) : b;
       for (int t = 0; t < m; ++t) {
         cg_iteration(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, first, s,
@@ -548,6 +556,7 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     const int it = g->h_status[3].it;
     const float* p_last = (it > 0 && cg_defers_x(F)) ? ((it & 1) ? p_odd : p_even) : nullptr;
     total += g->h_status[3].it;
+    expect = std::max(2, std::min(256, g->h_status[3].it));
     inner_fail = g->h_status[3].done == 2;
     launch_add_correction<float>(F, x, g->e32, s, p_last, si);
     launch_resid64(L, g->b, x, g->r, so, g->partials, g->counters + CT_SOLVE0, false, s);
