@@ -628,8 +628,12 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   launch_resid64(L, g->b, x, g->r, ss, g->partials, g->counters + CT_SOLVE0, true, s, g->r32);
   launch_zero_if_flagged(x, g->n, ss, s);
   HIPCHK(g, hipGetLastError());
-  if ((st = sync_status(g, sys, s)) != DS_OK) return st;
-  if (!g->h_status[sys].done) {
+  // No host test of the start: the first batch is enqueued at once.  Every
+  // kernel of the solve reads the device status and returns at once when the
+  // start already meets the tolerance, and the iteration count that selects
+  // the last deferred update comes from the test after the batch.
+  g->h_status[sys].done = 0;
+  {
     CgVecsMg32 V{x, g->r, g->p32, g->p32alt, g->q};
     // iteration t writes its direction into p_odd (t odd) or p_even (t even)
     float* const p_odd = V.p_alt;
