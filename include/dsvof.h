@@ -146,6 +146,9 @@ typedef struct ds_diagnostics {
  *     form as FP64 CG with the FP32 V-cycle (0: FP32 rounds).
  *   DSVOF_NEUMANN [1]: energy and species CG preconditioned by the first-
  *     order Neumann polynomial of the Jacobi splitting (0: Jacobi).
+ *   DSVOF_ROUND_TEST [1]: each FP32 round of the energy and species solves
+ *     enqueues its expected inner iterations and takes one host convergence
+ *     test (0: the inner solve is tested as well).
  *   DSVOF_GRAPHS [1]: the precision form's multigrid CG replays pairs of
  *     iterations as HIP graphs, captured on a stream of the handle's own and
  *     launched on the caller's (0: one launch at a time; same results bit

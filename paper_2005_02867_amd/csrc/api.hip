@@ -81,6 +81,7 @@ struct ds_grid {
     double inner_min_jac = 1e-6;  // the same for the energy and species systems
     int mg32 = 1;                 // multigrid systems: FP64 CG with the FP32 V-cycle
     int neumann = 1;              // energy and species: Neumann-polynomial preconditioner (vectorised grids)
+    int round_test = 1;           // energy and species FP32 rounds: one host test per round (0: also test the inner solve)
     int graphs = 1;               // replay pairs of multigrid-CG iterations as HIP graphs
   } tune;
   // Graphs of two FP32-multigrid CG iterations, keyed by what their launches
@@ -359,6 +360,14 @@ int sync_status(ds_grid* g, int slot, hipStream_t s) {
   return DS_OK;
 }
 
+// Both status slots a and b to the host with one synchronisation.
+int sync_status2(ds_grid* g, int a, int b, hipStream_t s) {
+  HIPCHK(g, hipMemcpyAsync(g->h_status + a, g->status + a, sizeof(SolveStatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(g, hipMemcpyAsync(g->h_status + b, g->status + b, sizeof(SolveStatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(g, hipStreamSynchronize(s));
+  return DS_OK;
+}
+
 int init_status(ds_grid* g, int slot, double tol, int maxit, hipStream_t s) {
   launch_init_status(g->status + slot, tol, maxit, s);
   HIPCHK(g, hipGetLastError());
@@ -536,6 +545,31 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     bool first = true;
     const bool timed = g->timing && H;
     int& expect = g->batch_round[sys][std::min(rounds, 2)];
+    // Energy and species (diagonally dominant, a few inner iterations per
+    // round) on vectorised levels: the round's inner iterations
+    // are enqueued without a host test (the expected count plus one; each
+    // returns at once after convergence), the correction takes the last
+    // deferred direction by the device's iteration count, and the round's one
+    // host test reads the inner and outer statuses together.  A round whose
+    // inner solve stopped short only reduces the residual less: the next
+    // round goes on from there.
+    if (g->tune.round_test && sys != 2 && !H && cg_defers_x(F)) {
+      const int m = batch_size(expect + 1, true);
+      for (int t = 0; t < m; ++t) {
+        cg_iteration(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, first, s);
+        first = false;
+      }
+      launch_add_correction_by_parity(F, x, g->e32, p_even, p_odd, si, s);
+      launch_resid64(L, g->b, x, g->r, so, g->partials, g->counters + CT_SOLVE0, false, s);
+      HIPCHK(g, hipGetLastError());
+      if ((st = sync_status2(g, 3, sys, s)) != DS_OK) return st;
+      const SolveStatus& hs = g->h_status[3];
+      total += hs.it;
+      expect = hs.done ? std::max(2, std::min(256, hs.it)) : std::min(256, 2 * hs.it);
+      inner_fail = hs.done == 2;
+      ++rounds;
+      continue;
+    }
     do {
       const int it0 = g->h_status[3].it;
       // one iteration of margin for the Jacobi-type systems: an iteration
@@ -1029,6 +1063,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_INNER_MIN_JAC")) g->tune.inner_min_jac = atof(e);
   if (const char* e = getenv("DSVOF_MG32")) g->tune.mg32 = atoi(e);
   if (const char* e = getenv("DSVOF_NEUMANN")) g->tune.neumann = atoi(e);
+  if (const char* e = getenv("DSVOF_ROUND_TEST")) g->tune.round_test = atoi(e);
   if (const char* e = getenv("DSVOF_GRAPHS")) g->tune.graphs = atoi(e);
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {

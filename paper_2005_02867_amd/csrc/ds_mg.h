@@ -182,6 +182,11 @@ void launch_inner_init(const Lev<T>& L, const double* r64, T* r, T* x, SolveStat
 template <class T>
 void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s, const T* p = nullptr,
                            const SolveStatus* st = nullptr);
+// x += e + st->alpha p with p the direction of the inner solve's last
+// iteration, p_odd or p_even by the parity of st->it (read on the device;
+// nothing added before the first iteration).  Vectorised levels only.
+void launch_add_correction_by_parity(const Lev<float>& L, double* x, const float* e, const float* p_even,
+                                     const float* p_odd, const SolveStatus* st, hipStream_t s);
 // Start of a Jacobi-preconditioned round in one pass: r = (T) r64, x = 0,
 // z = r/diag (z may be null: not stored), status (||r||, <r, z>).  False
 // (nothing launched) off the vectorised levels.

@@ -1784,8 +1784,11 @@ void launch_axpy_alpha(double* x, const float* p, const SolveStatus* st, long lo
 // alpha from st), as launch_axpy_alpha followed by the plain correction.
 template <class T>
 VEC_KERNEL k_add_correction_v(Lev<T> L, double* __restrict__ x, const T* __restrict__ e, const T* __restrict__ p,
-                              const SolveStatus* st) {
+                              const SolveStatus* st, const T* __restrict__ p_odd) {
   constexpr int V = VW<T>::n;
+  // p_odd set: the deferred direction is p_odd or p (even) by the parity of
+  // the device's iteration count, none before the first iteration
+  if (p_odd) p = st->it > 0 ? ((st->it & 1) ? p_odd : p) : nullptr;
   const T a = p ? (T)st->alpha : T(0);
   FOR_ITEMS(L, T, i, j, kv, c) {
     T ev[V], pv[V];
@@ -2382,7 +2385,7 @@ template <class T>
 void launch_add_correction(const Lev<T>& L, double* x, const T* e, hipStream_t s, const T* p,
                            const SolveStatus* st) {
   if (use_vec(L)) {
-    k_add_correction_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, x, e, p, st);
+    k_add_correction_v<T><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, x, e, p, st, nullptr);
   } else {
     if (p) launch_axpy_alpha<T>(const_cast<T*>(e), p, st, L.n, s);
     k_add_correction<T><<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, x, e);
@@ -2397,6 +2400,10 @@ bool launch_inner_init_jac(const Lev<T>& L, const double* r64, T* r, T* x, T* z,
 }
 template bool launch_inner_init_jac<float>(const Lev<float>&, const double*, float*, float*, float*, SolveStatus*,
                                            double*, unsigned*, hipStream_t);
+void launch_add_correction_by_parity(const Lev<float>& L, double* x, const float* e, const float* p_even,
+                                     const float* p_odd, const SolveStatus* st, hipStream_t s) {
+  k_add_correction_v<float><<<vec_blocks(vec_items(L)), BLOCK, 0, s>>>(L, x, e, p_even, st, p_odd);
+}
 void launch_to_float(const double* a, float* b, long long n, hipStream_t s) {
   k_to_float<<<grid_blocks(n), BLOCK, 0, s>>>(a, b, n);
 }
