@@ -148,7 +148,8 @@ typedef struct ds_diagnostics {
  *     order Neumann polynomial of the Jacobi splitting (0: Jacobi).
  *   DSVOF_ROUND_TEST [1]: each FP32 round of the energy and species solves
  *     enqueues its expected inner iterations and takes one host convergence
- *     test (0: the inner solve is tested as well).
+ *     test, and the solve's start takes none (0: the start and the inner
+ *     solve are tested as well).
  *   DSVOF_GRAPHS [1]: the precision form's multigrid CG replays pairs of
  *     iterations as HIP graphs, captured on a stream of the handle's own and
  *     launched on the caller's (0: one launch at a time; same results bit

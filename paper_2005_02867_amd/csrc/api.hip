@@ -513,17 +513,27 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   const int max_rounds = 12;
   if ((st = init_status(g, sys, tol, g->prm.maxit, s)) != DS_OK) return st;
   launch_resid64(L, g->b, x, g->r, so, g->partials, g->counters + CT_SOLVE0, true, s);
-  launch_zero_if_flagged(x, g->n, so, s);
+  launch_zero_if_flagged(x, g->n, so, s, g->r);   // r too: a round may start without a host test
   HIPCHK(g, hipGetLastError());
-  if ((st = sync_status(g, sys, s)) != DS_OK) return st;
+  // Energy and species on vectorised levels (one host test per round, below):
+  // no host test of the start either; the first round's inner tolerance is
+  // formed on the device from the start's residual.  A start that already
+  // meets the tolerance then takes one round that only lowers the residual.
+  const bool one_test = g->tune.round_test && sys != 2 && !H && cg_defers_x(F);
+  if (one_test) g->h_status[sys].done = 0;
+  else if ((st = sync_status(g, sys, s)) != DS_OK) return st;
   int total = 0, rounds = 0, inner_fail = 0;
   while (!g->h_status[sys].done && rounds < max_rounds && !inner_fail) {
     // Ask the FP32 solve for the reduction still needed (with a margin), but
     // not below what FP32 arithmetic reliably attains.
-    const double need = 0.5 * tol / std::max(g->h_status[sys].res, 1e-300);
     const double floor = H || sys == 2 ? g->tune.inner_min : g->tune.inner_min_jac;
-    const double inner_tol = std::min(0.5, std::max(floor, need));
-    if ((st = init_status(g, 3, inner_tol, g->prm.maxit, s)) != DS_OK) return st;
+    if (one_test && rounds == 0) {
+      launch_init_inner_status(si, so, 0.5 * tol, floor, 0.5, g->prm.maxit, s);
+    } else {
+      const double need = 0.5 * tol / std::max(g->h_status[sys].res, 1e-300);
+      const double inner_tol = std::min(0.5, std::max(floor, need));
+      if ((st = init_status(g, 3, inner_tol, g->prm.maxit, s)) != DS_OK) return st;
+    }
     g->h_status[3].it = 0;
     g->h_status[3].done = 0;
     CgVecs<float> V{g->e32, g->r32, g->p32, g->p32alt, g->q32, H ? nullptr : g->zj32};
@@ -553,7 +563,7 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
     // host test reads the inner and outer statuses together.  A round whose
     // inner solve stopped short only reduces the residual less: the next
     // round goes on from there.
-    if (g->tune.round_test && sys != 2 && !H && cg_defers_x(F)) {
+    if (one_test) {
       const int m = batch_size(expect + 1, true);
       for (int t = 0; t < m; ++t) {
         cg_iteration(F, H, V, &z, si, g->partials, g->counters + CT_SOLVE0, first, s);

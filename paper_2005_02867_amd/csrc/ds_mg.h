@@ -174,7 +174,8 @@ bool cg_defers_x(const Lev<T>& L);
 // r32 (may be null): also store r in FP32.
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
                     double* partials, unsigned* counter, bool set_bnorm, hipStream_t s, float* r32 = nullptr);
-void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s);
+// st->zero (b = 0): x = 0 and, with r, the residual r = 0 to match.
+void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s, double* r = nullptr);
 template <class T>
 void launch_inner_init(const Lev<T>& L, const double* r64, T* r, T* x, SolveStatus* st, double* partials,
                        unsigned* counter, hipStream_t s);
@@ -201,5 +202,9 @@ void launch_neumann_start(const Lev<T>& L, const T* r, T* z, SolveStatus* st, do
 void launch_to_float(const double* a, float* b, long long n, hipStream_t s);
 // *st = a fresh status (zeros, tol, maxit), written by a kernel on stream s.
 void launch_init_status(SolveStatus* st, double tol, int maxit, hipStream_t s);
+// *st = a fresh status with tol = min(hi, max(lo, num / outer->res)), formed
+// on the device from the outer solve's residual.
+void launch_init_inner_status(SolveStatus* st, const SolveStatus* outer, double num, double lo, double hi, int maxit,
+                              hipStream_t s);
 
 }  // namespace dsv

@@ -402,11 +402,15 @@ __global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, 
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) b[c] = (float)a[c];
 }
 
-__global__ void k_zero_if_flagged(double* x, long long n, const SolveStatus* st) {
+// b = 0: the solution is x = 0, and its residual r = b - A 0 = 0 (r may be null).
+__global__ void k_zero_if_flagged(double* x, double* r, long long n, const SolveStatus* st) {
   if (!st->zero) return;
   long long b0, b1;
   block_range(n, b0, b1);
-  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) x[c] = 0.0;
+  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
+    x[c] = 0.0;
+    if (r) r[c] = 0.0;
+  }
 }
 
 // ------------------------------------------------------------ z-vectorised kernels
@@ -2372,8 +2376,8 @@ void launch_resid64(const Lev<double>& L, const double* b, const double* x, doub
     if (r32) k_to_float<<<grid_blocks(L.n), BLOCK, 0, s>>>(r, r32, L.n);
   }
 }
-void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s) {
-  k_zero_if_flagged<<<grid_blocks(n), BLOCK, 0, s>>>(x, n, st);
+void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s, double* r) {
+  k_zero_if_flagged<<<grid_blocks(n), BLOCK, 0, s>>>(x, r, n, st);
 }
 template <class T>
 void launch_inner_init(const Lev<T>& L, const double* r64, T* r, T* x, SolveStatus* st, double* partials,
@@ -2421,6 +2425,22 @@ __global__ void k_init_status(SolveStatus* __restrict__ st, double tol, int maxi
 }
 void launch_init_status(SolveStatus* st, double tol, int maxit, hipStream_t s) {
   k_init_status<<<1, 64, 0, s>>>(st, tol, maxit);
+}
+
+// An inner solve's fresh status whose tolerance is the reduction the outer
+// solve still needs: min(hi, max(lo, num / outer res)).
+__global__ void k_init_inner_status(SolveStatus* __restrict__ st, const SolveStatus* __restrict__ outer, double num,
+                                    double lo, double hi, int maxit) {
+  if (threadIdx.x == 0) {
+    SolveStatus v{};
+    v.tol = fmin(hi, fmax(lo, num / fmax(outer->res, 1e-300)));
+    v.maxit = maxit;
+    *st = v;
+  }
+}
+void launch_init_inner_status(SolveStatus* st, const SolveStatus* outer, double num, double lo, double hi, int maxit,
+                              hipStream_t s) {
+  k_init_inner_status<<<1, 64, 0, s>>>(st, outer, num, lo, hi, maxit);
 }
 
 // FP64 CG preconditioned by the FP32 V-cycle (levels whose nz is even).

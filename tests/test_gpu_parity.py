@@ -406,3 +406,15 @@ def test_step_parity_literal_species_without_evaporation():
     prm, _ = _grid_params(n=(17, 19, 23), L=17 * 1.25e-4, species_form=1, evaporation=0)
     f = W.random_fields(prm, seed=17)
     _run_both(prm, f, steps=2)
+
+
+def test_step_parity_zero_species_right_hand_side_precision_form():
+    """No evaporation and no vapour: the species system's right-hand side is
+    exactly zero, so its solve returns x = 0 (and r = 0) from the start; in
+    the precision form the first FP32 round is enqueued without a host test
+    and must leave omega at zero.  3 steps of C1 against the oracle."""
+    prm, run = W.config("C1", precision=W.PREC_MIXED, evaporation=0)
+    f = W.initial_fields(prm, **run)
+    assert float(np.abs(f["omega"]).max()) == 0.0
+    g, st, worst = _run_both(prm, f, steps=3)
+    assert float(g.get_fields()["omega"].abs().max()) == 0.0
