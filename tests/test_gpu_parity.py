@@ -418,3 +418,17 @@ def test_step_parity_zero_species_right_hand_side_precision_form():
     assert float(np.abs(f["omega"]).max()) == 0.0
     g, st, worst = _run_both(prm, f, steps=3)
     assert float(g.get_fields()["omega"].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("n,fill,form", [((12, 13, 14), 0.0, 0), ((12, 13, 14), 1.0, 0), ((12, 13, 14), 1.0, 1),
+                                         ((2, 3, 5), None, 0), ((2, 2, 2), None, 0)])
+def test_step_parity_degenerate_inputs(n, fill, form):
+    """Degenerate inputs: no liquid anywhere (no interface cell, K = 0), the
+    box full of liquid (theta at its floor everywhere; liquid leaves through
+    the open faces, both species forms), and the smallest grids (every
+    kernel on its non-vectorised path).  2 steps against the oracle."""
+    prm, _ = _grid_params(n=n, L=n[0] * 1.25e-4, species_form=form)
+    f = W.random_fields(prm, seed=21)
+    if fill is not None:
+        f["alpha"] = np.full_like(f["alpha"], fill)
+    _run_both(prm, f, steps=2)
