@@ -7,6 +7,7 @@
   form, multigrid): fuel mass conserved to 1e-10 per step, the liquid budget
   closes, and div u = mdot (1/rho_G - 1/rho_L) to the solve tolerance.
 * d^2 law on the GPU path (equal to the oracle step for step) at R/h = 8, 16.
+* The largest configuration (384^3): fuel mass, liquid budget, convergence.
 * Literal species form at 256^3: the liquid assignment, adj and raw source
   against the oracle on the sub-block; the fuel balance without a vapour
   source in the precision form.
@@ -99,6 +100,31 @@ def test_c3_properties_in_bench_configuration():
     err = float((div - S_).abs().max())
     print("max |div u - S| / max |S|", err / scale)
     assert err <= 1e-6 * scale
+
+
+def test_c5_properties_at_the_largest_configuration():
+    """The largest configuration (384^3, 56.6 M cells, forced convection,
+    Peng-Robinson), as bench.py --configs runs it: 2 steps in the precision
+    form, fuel mass conserved to 1e-10 per step, the liquid budget closes,
+    every solve converges."""
+    ds = _lib()
+    prm, run = W.config("C5")
+    f = W.initial_fields(prm, **run)
+    print("384^3 C5: 2 steps, precision form", flush=True)
+    g = ds.Grid(dict(prm, precision=W.PREC_MIXED))
+    g.set_fields(f)
+    del f
+    for k in range(2):
+        V0 = g.droplet_volume()
+        g.step(1)
+        d = g.diagnostics()
+        rel = abs(d["fuel_mass"] - d["fuel_mass_before"] + d["B_L"] + d["B_v"]) / d["fuel_mass_before"]
+        print("step", k, "fuel balance", rel, "iters", d["iters_T"], d["iters_omega"], d["iters_p"], flush=True)
+        assert rel <= 1e-10, rel
+        dV = d["volume"] - V0
+        expect = -prm["dt"] * d["mdot_total"] / prm["rho_L"] - d["B_L"] / prm["rho_L"]
+        assert dV == pytest.approx(expect, rel=1e-8, abs=1e-14 * V0)
+        assert d["converged"] == 1 and d["mdot_total"] > 0
 
 
 def test_c3_literal_species_sampled_parity():
