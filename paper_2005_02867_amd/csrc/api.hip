@@ -76,6 +76,15 @@ struct ds_grid {
   int dirmask = 0;                 // p_rgh = 0 box faces
   int batch_p[2] = {4, 4};         // pressure, then any other pressure-type system (phi, adjoints)
   int f32_sys = -1;                // system whose FP32 copies (qc32, diag32) the last setup wrote
+  // The liquid-transport potential's operator (face coefficient 1/dt everywhere, the pressure's box faces)
+  // does not change between steps: in the precision form's multigrid path it has its own FP64 q and FP32
+  // hierarchy q and diag (H32phi, whose r, x, t scratch is H32's), built by its first solve.
+  double* phi_qc = nullptr;
+  float* phi_q[MG_MAXLEV] = {};
+  float* phi_d[MG_MAXLEV] = {};
+  MgHier<float> H32phi;
+  bool phi_ready = false;          // phi_qc, phi_q, phi_d and H32phi hold the operator
+  bool phi_op = false;             // the solve in progress is the potential's, on those arrays
   struct {
     double inner_min = 1e-3;   // smallest FP32 inner relative tolerance per round (pressure-type)
     double inner_min_jac = 1e-6;  // the same for the energy and species systems
@@ -245,7 +254,13 @@ size_t carve(ds_grid* g, char* base) {
     g->q32 = L.take<float>(base, n);
     g->zj32 = L.take<float>(base, n);
     g->r32alt = L.take<float>(base, n);
+    g->phi_qc = L.take<double>(base, n);
+    for (int l = 0; l < F.nlev; ++l) {
+      g->phi_q[l] = L.take<float>(base, F.lev[l].n);
+      g->phi_d[l] = L.take<float>(base, F.lev[l].n);
+    }
   }
+  g->phi_ready = false;
   return L.off;
 }
 
@@ -656,17 +671,38 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   L.qc = g->qc;
   L.diag = g->diag;
   pressure_type(g, sys, L);
+  const bool phi = g->phi_op;   // the potential, on its own operator arrays
+  if (phi) L.qc = g->phi_qc;
   Lev<float> F;
   lev_dims(F, L.nx, L.ny, L.nz, sc);
-  F.qc = g->qc32;
-  F.diag = g->diag32;
-  if (!take_f32(g, sys)) {
+  F.qc = phi ? g->phi_q[0] : g->qc32;
+  F.diag = phi ? g->phi_d[0] : g->diag32;
+  if (phi) {
+    g->f32_sys = -1;
+    if (!g->phi_ready) {
+      launch_to_float(g->phi_qc, g->phi_q[0], g->n, s);
+      launch_mg_diag(F, g->dirmask, g->phi_d[0], s);
+      g->H32phi = g->H32;
+      for (int l = 1; l < g->H32phi.nlev; ++l) {
+        g->H32phi.lev[l].qc = g->phi_q[l];
+        g->H32phi.lev[l].diag = g->phi_d[l];
+      }
+    }
+  } else if (!take_f32(g, sys)) {
     launch_to_float(g->qc, g->qc32, g->n, s);
     launch_mg_diag(F, g->dirmask, g->diag32, s);   // the formula the V-cycle forms on the fly
   }
-  MgHier<float>& H = g->H32;
+  MgHier<float>& H = phi ? g->H32phi : g->H32;
   H.lev[0] = F;
-  mg_setup_levels(H, g->dirmask, s);
+  if (phi && g->phi_ready) {
+    for (int l = 0; l < H.nlev; ++l) {   // the coarse levels are built already
+      H.lev[l].dfly = 1;
+      H.lev[l].dmask = g->dirmask;
+    }
+  } else {
+    mg_setup_levels(H, g->dirmask, s);
+  }
+  if (phi) g->phi_ready = true;
   SolveStatus* ss = g->status + sys;
   if ((st = init_status(g, sys, tol, g->prm.maxit, s)) != DS_OK) return st;
   launch_resid64(L, g->b, x, g->r, ss, g->partials, g->counters + CT_SOLVE0, true, s, g->r32);
@@ -762,8 +798,14 @@ int one_step(ds_grid* g, hipStream_t s) {
   if ((st = evaporation_source(g, s)) != DS_OK) return st;
   // 3. advection of alpha1 with the divergence-free part of u^n, c and T with u^n
   if (g->prm.liquid_transport) {
-    launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s, f32_out(g, 2));
+    // precision form, multigrid: the potential's own operator arrays, written by its first setup only
+    const bool own = g->prm.precision == DS_PREC_MIXED && g->prm.pressure_precond == 1 && g->tune.mg32 &&
+                     mg32_supported(g->L0);
+    if (own) launch_div_setup(P, g->u, g->v, g->w, g->phi_ready ? nullptr : g->phi_qc, g->diag, g->b, s);
+    else launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s, f32_out(g, 2));
+    g->phi_op = own;
     st = solve(g, 2, P.dt / (P.h * P.h), g->phi, s, &D.iters_phi, &D.res_phi, g->prm.tol_phi);
+    g->phi_op = false;
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
   } else {

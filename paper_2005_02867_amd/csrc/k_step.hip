@@ -674,8 +674,10 @@ __global__ void k_div_setup(DevParams P, const double* __restrict__ u, const dou
       }
     const double div = ((u[uidx(P, i + 1, j, k)] - u[uidx(P, i, j, k)]) + (v[vidx(P, i, j + 1, k)] - v[vidx(P, i, j, k)]) +
                         (w[widx(P, i, j, k + 1)] - w[widx(P, i, j, k)])) * ih;
-    qc[c] = q;
-    diag[c] = d;
+    if (qc) {   // null: the right-hand side only (the operator is kept from an earlier call)
+      qc[c] = q;
+      diag[c] = d;
+    }
     b[c] = -div;
     if (fo.q) {
       fo.q[c] = (float)q;
