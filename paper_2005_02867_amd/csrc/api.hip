@@ -91,6 +91,7 @@ struct ds_grid {
     int mg32 = 1;                 // multigrid systems: FP64 CG with the FP32 V-cycle
     int neumann = 1;              // energy and species: Neumann-polynomial preconditioner (vectorised grids)
     int round_test = 1;           // energy and species FP32 rounds: one host test per round (0: also test the inner solve)
+    int const_q = 1;              // potential's fine level: the coloured sweep takes its constant q from a register
     int graphs = 1;               // replay pairs of multigrid-CG iterations as HIP graphs
   } tune;
   // Graphs of two FP32-multigrid CG iterations, keyed by what their launches
@@ -677,6 +678,8 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   lev_dims(F, L.nx, L.ny, L.nz, sc);
   F.qc = phi ? g->phi_q[0] : g->qc32;
   F.diag = phi ? g->phi_d[0] : g->diag32;
+  // the value phi_q[0] holds in every cell: 1/dt rounded to FP32, as the setup's q converted
+  if (phi && g->tune.const_q) F.qk = (float)(1.0 / g->dp.dt);
   if (phi) {
     g->f32_sys = -1;
     if (!g->phi_ready) {
@@ -1116,6 +1119,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_MG32")) g->tune.mg32 = atoi(e);
   if (const char* e = getenv("DSVOF_NEUMANN")) g->tune.neumann = atoi(e);
   if (const char* e = getenv("DSVOF_ROUND_TEST")) g->tune.round_test = atoi(e);
+  if (const char* e = getenv("DSVOF_CONST_Q")) g->tune.const_q = atoi(e);
   if (const char* e = getenv("DSVOF_GRAPHS")) g->tune.graphs = atoi(e);
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {

@@ -30,6 +30,7 @@ struct Lev {
   int mnt;     // threads per block of the marching kernels (set by the launcher)
   int dfly;    // 1: the marching kernels form diag from qc (pressure-type operator) instead of loading it
   int dmask;   // with dfly: bit (axis*2 + side) set where the box face is p = 0 (Dirichlet)
+  T qk;        // nonzero: qc holds this value in every cell (the coloured sweep then loads no q)
   int ntk, ntj;
   unsigned ntiles;
   long long n;
@@ -48,6 +49,7 @@ inline void lev_dims(Lev<T>& L, int nx, int ny, int nz, double sc) {
   L.mnt = 256;
   L.dfly = 0;
   L.dmask = 0;
+  L.qk = 0;
   L.ntk = (nz + TK - 1) / TK;
   L.ntj = (ny + TJ - 1) / TJ;
   L.ntiles = (unsigned)L.ntk * (unsigned)L.ntj * (unsigned)nx;

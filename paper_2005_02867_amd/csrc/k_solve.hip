@@ -1036,7 +1036,9 @@ VEC_KERNEL_M k_mg_prolong_smooth_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, 
 // adjacent thread of the same block.
 // lx(f, o): x0 vector at cell f (X0 false: x0 = 0, nothing loaded);
 // out(c, o, rv): the finished vector of plane s - 1 and its r.
-template <class T, int NT, bool X0, bool WE, class LX, class OUT>
+// CQ: qc holds L.qk in every cell; q is taken from that value (no q loads,
+// no q exchange through LDS or lanes), with the same arithmetic.
+template <class T, int NT, bool X0, bool WE, bool CQ, class LX, class OUT>
 __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ r, T w, int c0, LX lx, OUT out) {
   constexpr int V = VW<T>::n;
   const unsigned nzv = (unsigned)L.nz / V, ny = (unsigned)L.ny, nx = (unsigned)L.nx;
@@ -1052,6 +1054,7 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
   const bool inm = tid >= (int)nzv, inp = tid + (int)nzv < NT;
   const int lane = tid & 63;
   const T hs = T(0.5) * L.sc;
+  const T qk = L.qk;
   int par = 0;
   auto zero = [](T(&o)[V]) {
 #pragma unroll
@@ -1060,6 +1063,10 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
   auto copy = [](T(&o)[V], const T(&a)[V]) {
 #pragma unroll
     for (int v = 0; v < V; ++v) o[v] = a[v];
+  };
+  auto fillq = [&](T(&o)[V]) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = qk;
   };
   // out-of-range planes are clamped to the nearest one (loads stay inside
   // the array; the terms they would feed are switched off)
@@ -1083,8 +1090,13 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
     T qa[V], qb[V], qc[V], xb[V], xc[V], ma[V], mb[V], rb[V], ib[V], yb[V];
     {
       const unsigned fb = (unsigned)clampp(s0 - dir) * P + cj, fc = (unsigned)s0 * P + cj;
-      ldv<T>(at(L.qc, fb), qb);
-      ldv<T>(at(L.qc, fc), qc);
+      if (CQ) {
+        fillq(qb);
+        fillq(qc);
+      } else {
+        ldv<T>(at(L.qc, fb), qb);
+        ldv<T>(at(L.qc, fc), qc);
+      }
       if (X0) {
         lx(fb, xb);
         lx(fc, xc);
@@ -1107,19 +1119,20 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       const bool hxm = s > 0, hxp = s + 1 < (int)nx;
       const unsigned fn = (unsigned)clampp(s + dir) * P + cj, fym = hym ? c - sy : c, fyp = hyp ? c + sy : c;
       T qd[V], xd[V], rc[V], nqm[V], nqp[V], nxm[V], nxp[V];
-      ldv<T>(at(L.qc, fn), qd);
+      if (CQ) fillq(qd);
+      else ldv<T>(at(L.qc, fn), qd);
       if (X0) lx(fn, xd);
       else zero(xd);
       ldv<T>(at(r, c), rc);
       if (!inm) {
-        ldv<T>(at(L.qc, fym), nqm);
+        if (!CQ) ldv<T>(at(L.qc, fym), nqm);
         if (X0) lx(fym, nxm);
       }
       if (!inp) {
-        ldv<T>(at(L.qc, fyp), nqp);
+        if (!CQ) ldv<T>(at(L.qc, fyp), nqp);
         if (X0) lx(fyp, nxp);
       }
-      stv<T>(&lsq[par][tid * V], qc);
+      if (!CQ) stv<T>(&lsq[par][tid * V], qc);
       if (X0) stv<T>(&lsx[par][tid * V], xc);
       if (WE) {
         lsm[par][2 * tid] = mb[0];
@@ -1127,12 +1140,16 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       }
       __syncthreads();
       if (inm) {
-        ldv<T>(&lsq[par][(tid - (int)nzv) * V], nqm);
+        if (!CQ) ldv<T>(&lsq[par][(tid - (int)nzv) * V], nqm);
         if (X0) ldv<T>(&lsx[par][(tid - (int)nzv) * V], nxm);
       }
       if (inp) {
-        ldv<T>(&lsq[par][(tid + (int)nzv) * V], nqp);
+        if (!CQ) ldv<T>(&lsq[par][(tid + (int)nzv) * V], nqp);
         if (X0) ldv<T>(&lsx[par][(tid + (int)nzv) * V], nxp);
+      }
+      if (CQ) {
+        fillq(nqm);
+        fillq(nqp);
       }
       if (!X0) {
         zero(nxm);
@@ -1141,16 +1158,16 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
       // z neighbours from the adjacent lanes; at a wave's first and last lane
       // (rows longer than or straddling a wave) from the adjacent thread's
       // values in LDS
-      T qzm = lane_up(qc[V - 1]), qzp = lane_down(qc[0]);
+      T qzm = CQ ? qk : lane_up(qc[V - 1]), qzp = CQ ? qk : lane_down(qc[0]);
       T xzm = lane_up(xc[V - 1]), xzp = lane_down(xc[0]);
       T mzm = lane_up(mb[V - 1]), mzp = lane_down(mb[0]);
       if (WE && hzm && lane == 0) {
-        qzm = lsq[par][(tid - 1) * V + V - 1];
+        if (!CQ) qzm = lsq[par][(tid - 1) * V + V - 1];
         if (X0) xzm = lsx[par][(tid - 1) * V + V - 1];
         mzm = lsm[par][2 * (tid - 1) + 1];
       }
       if (WE && hzp && lane == 63) {
-        qzp = lsq[par][(tid + 1) * V];
+        if (!CQ) qzp = lsq[par][(tid + 1) * V];
         if (X0) xzp = lsx[par][(tid + 1) * V];
         mzp = lsm[par][2 * (tid + 1)];
       }
@@ -1191,7 +1208,7 @@ __device__ __forceinline__ void march_rb(const Lev<T>& L, const T* __restrict__ 
 #pragma unroll
         for (int v = 0; v < V; ++v) ic[v] = T(1) / dl[v];
       }
-      const T bqzm = WE ? pqzm : lane_up(qb[V - 1]), bqzp = WE ? pqzp : lane_down(qb[0]);
+      const T bqzm = CQ ? qk : (WE ? pqzm : lane_up(qb[V - 1])), bqzp = CQ ? qk : (WE ? pqzp : lane_down(qb[0]));
       const T w1 = T(1) - w;
       T mc[V];
       const int sb = s - dir;   // the plane colour B finishes
@@ -1294,7 +1311,7 @@ inline bool rows_cross_waves(const Lev<T>& M) {
 // One coloured sweep (march_rb) of F x = r.  RB_GEN: from x; RB_ZERO: from
 // x = 0 (x not read); RB_PROLONG: from x + P xc (injection from level C).
 // DOT: also <r, x_out> (the preconditioned residual's product).
-template <class T, int MODE, bool DOT, int NT, bool WE>
+template <class T, int MODE, bool DOT, int NT, bool WE, bool CQ = false>
 VEC_KERNEL_M k_mg_rb_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __restrict__ x,
                        const T* __restrict__ xc, T* __restrict__ xout, T w, int c0, SolveStatus* st,
                        double* partials, unsigned* counter, int first) {
@@ -1318,11 +1335,11 @@ VEC_KERNEL_M k_mg_rb_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __r
 #pragma unroll
       for (int v = 0; v < V; ++v) o[v] += *at(xc, pb + (v >> 1));
     };
-    march_rb<T, NT, true, WE>(F, r, w, c0, row, outf);
+    march_rb<T, NT, true, WE, CQ>(F, r, w, c0, row, outf);
   } else if constexpr (MODE == RB_GEN) {
-    march_rb<T, NT, true, WE>(F, r, w, c0, [&](unsigned f, T(&o)[V]) { ldv<T>(at(x, f), o); }, outf);
+    march_rb<T, NT, true, WE, CQ>(F, r, w, c0, [&](unsigned f, T(&o)[V]) { ldv<T>(at(x, f), o); }, outf);
   } else {
-    march_rb<T, NT, false, WE>(F, r, w, c0, [&](unsigned, T(&o)[V]) {}, outf);
+    march_rb<T, NT, false, WE, CQ>(F, r, w, c0, [&](unsigned, T(&o)[V]) {}, outf);
   }
   if (DOT) publish_rz<NT>(acc, st, partials, counter, first);
 }
@@ -2057,29 +2074,31 @@ static void mg_vcycle(MgHier<T>& H, int l, const T* r, SolveStatus* st, double* 
     const Lev<T>& C = H.lev[l + 1];
     auto rb = [&](int mode, bool d, const T* xin, const T* xcs, T* xo, int c0) {
       if constexpr (std::is_same<T, float>::value) {
-        auto go = [&](auto WEc) {
+        auto go = [&](auto WEc, auto CQc) {
           constexpr bool WE = decltype(WEc)::value;
+          constexpr bool CQ = decltype(CQc)::value;
           with_nt(Mr.mnt, [&](auto K) {
             constexpr int NT = decltype(K)::value;
             if (mode == RB_ZERO)
-              k_mg_rb_v<T, RB_ZERO, false, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, nullptr, nullptr, xo, w, c0, st,
+              k_mg_rb_v<T, RB_ZERO, false, NT, WE, CQ><<<nbr, NT, 0, s>>>(Mr, C, r, nullptr, nullptr, xo, w, c0, st,
                                                                       partials, counter, 0);
             else if (mode == RB_PROLONG && d)
-              k_mg_rb_v<T, RB_PROLONG, true, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st, partials,
+              k_mg_rb_v<T, RB_PROLONG, true, NT, WE, CQ><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st, partials,
                                                                         counter, dot_first);
             else if (mode == RB_PROLONG)
-              k_mg_rb_v<T, RB_PROLONG, false, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st,
+              k_mg_rb_v<T, RB_PROLONG, false, NT, WE, CQ><<<nbr, NT, 0, s>>>(Mr, C, r, xin, xcs, xo, w, c0, st,
                                                                          partials, counter, 0);
             else if (d)
-              k_mg_rb_v<T, RB_GEN, true, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st, partials,
+              k_mg_rb_v<T, RB_GEN, true, NT, WE, CQ><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st, partials,
                                                                     counter, dot_first);
             else
-              k_mg_rb_v<T, RB_GEN, false, NT, WE><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st,
-                                                                     partials, counter, 0);
+              k_mg_rb_v<T, RB_GEN, false, NT, WE, CQ><<<nbr, NT, 0, s>>>(Mr, C, r, xin, nullptr, xo, w, c0, st,
+                                                                         partials, counter, 0);
           });
         };
-        if (rows_cross_waves(Mr)) go(std::true_type{});
-        else go(std::false_type{});
+        if (rows_cross_waves(Mr)) go(std::true_type{}, std::false_type{});
+        else if (Mr.qk != T(0)) go(std::false_type{}, std::true_type{});   // a constant-coefficient level
+        else go(std::false_type{}, std::false_type{});
       }
     };
     rb(RB_ZERO, false, nullptr, nullptr, a, 0);

@@ -432,3 +432,28 @@ def test_step_parity_degenerate_inputs(n, fill, form):
     if fill is not None:
         f["alpha"] = np.full_like(f["alpha"], fill)
     _run_both(prm, f, steps=2)
+
+
+def test_constant_coefficient_sweep_matches_the_loading_sweep(monkeypatch):
+    """The liquid-transport potential's coloured sweeps take its constant q
+    (1/dt rounded to FP32, the value its array holds) from a register: the
+    same arithmetic as loading it.  C1 in the precision form with coloured
+    sweeps on every level that takes them, 3 steps with and without
+    (DSVOF_CONST_Q=0): equal potential iteration counts, fields within 1e-13."""
+    ds = _lib()
+    monkeypatch.setenv("DSVOF_MG_RB_MINPLANES", "1")
+    prm, run = W.config("C1", precision=W.PREC_MIXED)
+    f = W.initial_fields(prm, **run)
+    out = []
+    for cq in ("1", "0"):
+        monkeypatch.setenv("DSVOF_CONST_Q", cq)
+        g = ds.Grid(dict(prm, tol=1e-13, tol_phi=1e-13))
+        g.set_fields(f)
+        its = []
+        for _ in range(3):
+            g.step(1)
+            its.append(g.diagnostics()["iters_phi"])
+        out.append((g.get_fields(), its))
+    assert out[0][1] == out[1][1], (out[0][1], out[1][1])
+    for k in FIELDS:
+        assert _rel(out[0][0][k], out[1][0][k]) <= 1e-13, k
