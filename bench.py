@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 # the ratio of known bytes to the counter's reading for a 1 GiB device copy in
 # the same run; None until measured for the current kernel.
 # Measured for the fine-level coloured sweep of the 256^3 workload: FETCH_SIZE
-# 117204 KiB x 2.000 (the 1 GiB copy reads 524336 KiB) + WRITE_SIZE 65536 KiB x 1.000.
-TRAFFIC_SMOOTH = (117204.0 * (1048576.0 / 524336.0) + 65536.0) * 1024.0
+# 116872 KiB x 2.000 (the 1 GiB copy reads 524339 KiB) + WRITE_SIZE 65536 KiB x 1.000.
+TRAFFIC_SMOOTH = (116871.575 * (1048576.0 / 524338.75) + 65536.0 * (1048576.0 / 1048576.0)) * 1024.0
 
 
 def log(msg):
@@ -269,7 +269,7 @@ def main():
     kt = mixed["kernel"]
     achieved = rs["bytes_per_launch"] / (rs["avg_us"] * 1e-6) / 1e9
     roofline = {
-        "kernel": "k_mg_rb_v<float,RB_GEN,false,256,false> (fine-level coloured (x-z red-black) sweep of the multigrid "
+        "kernel": "k_mg_rb_v<float,RB_GEN,false,256,false,false> (fine-level coloured (x-z red-black) sweep of the multigrid "
                   "preconditioner, FP32, reads r, x, q_coef, forms diag from q_coef, writes x: 16 B/cell; the "
                   "largest share of step time)",
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
