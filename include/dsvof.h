@@ -146,6 +146,9 @@ typedef struct ds_diagnostics {
  *     form as FP64 CG with the FP32 V-cycle (0: FP32 rounds).
  *   DSVOF_NEUMANN [1]: energy and species CG preconditioned by the first-
  *     order Neumann polynomial of the Jacobi splitting (0: Jacobi).
+ *   DSVOF_CONST_Q [1]: the liquid-transport potential's fine-level
+ *     coloured sweep and CG operator take its constant face coefficient
+ *     from a register instead of loading it (same arithmetic).
  *   DSVOF_ROUND_TEST [1]: each FP32 round of the energy and species solves
  *     enqueues its expected inner iterations and takes one host convergence
  *     test, and the solve's start takes none (0: the start and the inner

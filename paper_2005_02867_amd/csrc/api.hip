@@ -680,6 +680,7 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   F.diag = phi ? g->phi_d[0] : g->diag32;
   // the value phi_q[0] holds in every cell: 1/dt rounded to FP32, as the setup's q converted
   if (phi && g->tune.const_q) F.qk = (float)(1.0 / g->dp.dt);
+  if (phi && g->tune.const_q) L.qk = 1.0 / g->dp.dt;   // and in FP64, the value phi_qc holds
   if (phi) {
     g->f32_sys = -1;
     if (!g->phi_ready) {

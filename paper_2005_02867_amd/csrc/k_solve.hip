@@ -652,9 +652,16 @@ __device__ __forceinline__ T lane_down(T v) { return __shfl_down(v, 1, 64); } //
 // come from the L2); the cell arithmetic is the same either way.  Kernels
 // whose body depends on the walking order (the marching restriction) pass
 // false.
-template <class T, int NT, bool ALT = true, class LX, class SX, class BODY>
+// CQ: qc holds L.qk in every cell; q is taken from that value (no q loads or
+// exchange), with the same arithmetic.
+template <class T, int NT, bool ALT = true, bool CQ = false, class LX, class SX, class BODY>
 __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) {
   constexpr int V = VW<T>::n;
+  const T qk = L.qk;
+  auto fillq = [&](T(&o)[V]) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = qk;
+  };
   const unsigned nzv = (unsigned)L.nz / V, ny = (unsigned)L.ny, nx = (unsigned)L.nx;
   const unsigned nch = (unsigned)L.mch, clen = (nx + nch - 1) / nch;
   const unsigned per = gridDim.x / NXCD, lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
@@ -687,12 +694,14 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
   T qp[V], xp[V], qc[V], xc[V];
   {
     const unsigned f = (unsigned)clampp(sfirst - dir) * P + cj;
-    ldv<T>(at(L.qc, f), qp);
+    if (CQ) fillq(qp);
+    else ldv<T>(at(L.qc, f), qp);
     lx(f, xp);
   }
   {
     const unsigned f = (unsigned)sfirst * P + cj;
-    ldv<T>(at(L.qc, f), qc);
+    if (CQ) fillq(qc);
+    else ldv<T>(at(L.qc, f), qc);
     lx(f, xc);
   }
   for (int i = sfirst;; i += dir) {
@@ -701,38 +710,43 @@ __device__ __forceinline__ void march(const Lev<T>& L, LX lx, SX sx, BODY body) 
     const unsigned fn = (unsigned)clampp(i + dir) * P + cj, fym = hym ? c - sy : c, fyp = hyp ? c + sy : c;
     // qn, xn: the plane ahead
     T qn[V], xn[V], qym[V], xym[V], qyp[V], xyp[V];
-    ldv<T>(at(L.qc, fn), qn);
+    if (CQ) fillq(qn);
+    else ldv<T>(at(L.qc, fn), qn);
     lx(fn, xn);
     if (!inm) {
-      ldv<T>(at(L.qc, fym), qym);
+      if (!CQ) ldv<T>(at(L.qc, fym), qym);
       lx(fym, xym);
     }
     if (!inp) {
-      ldv<T>(at(L.qc, fyp), qyp);
+      if (!CQ) ldv<T>(at(L.qc, fyp), qyp);
       lx(fyp, xyp);
     }
     if (coop) {
-      stv<T>(&lsq[par][tid * V], qc);
+      if (!CQ) stv<T>(&lsq[par][tid * V], qc);
       stv<T>(&lsx[par][tid * V], xc);
       __syncthreads();
       if (inm) {
-        ldv<T>(&lsq[par][(tid - (int)nzv) * V], qym);
+        if (!CQ) ldv<T>(&lsq[par][(tid - (int)nzv) * V], qym);
         ldv<T>(&lsx[par][(tid - (int)nzv) * V], xym);
       }
       if (inp) {
-        ldv<T>(&lsq[par][(tid + (int)nzv) * V], qyp);
+        if (!CQ) ldv<T>(&lsq[par][(tid + (int)nzv) * V], qyp);
         ldv<T>(&lsx[par][(tid + (int)nzv) * V], xyp);
       }
       par ^= 1;
     }
-    T qzm = lane_up(qc[V - 1]), xzm = lane_up(xc[V - 1]);
-    T qzp = lane_down(qc[0]), xzp = lane_down(xc[0]);
+    if (CQ) {
+      fillq(qym);
+      fillq(qyp);
+    }
+    T qzm = CQ ? qk : lane_up(qc[V - 1]), xzm = lane_up(xc[V - 1]);
+    T qzp = CQ ? qk : lane_down(qc[0]), xzp = lane_down(xc[0]);
     if (hzm && lane == 0) {
-      qzm = *at(L.qc, c - 1);
+      if (!CQ) qzm = *at(L.qc, c - 1);
       xzm = sx(c - 1);
     }
     if (hzp && lane == 63) {
-      qzp = *at(L.qc, c + V);
+      if (!CQ) qzp = *at(L.qc, c + V);
       xzp = sx(c + V);
     }
     T off[V];
@@ -1722,7 +1736,7 @@ VEC_KERNEL k_cg_update_r32_v(Lev<double> L, double* __restrict__ r, const double
 // x (may be null): also x += alpha_prev p_old, the previous iteration's
 // solution update (alpha_prev is still in st->alpha when this kernel starts;
 // its last block replaces it).
-template <bool FIRST, int NT>
+template <bool FIRST, int NT, bool CQ = false>
 VEC_KERNEL_M k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, const float* __restrict__ pin,
                                float* __restrict__ pout, double* __restrict__ q, SolveStatus* st,
                                double* partials, unsigned* counter, double* __restrict__ x) {
@@ -1747,7 +1761,7 @@ VEC_KERNEL_M k_cg_dir_spmv_z32_v(Lev<double> L, const float* __restrict__ z, con
   auto pns = [&](unsigned f) -> double {
     return FIRST ? (double)*at(z, f) : (double)(float)((double)*at(z, f) + be * (double)*at(pin, f));
   };
-  march<double, NT>(L, pnv, pns,
+  march<double, NT, true, CQ>(L, pnv, pns,
                 [&](unsigned c, const double(&qv)[V], const double(&pc)[V], const double(&off)[V],
                     const double(&dv)[V]) {
     double y[V];
@@ -2475,8 +2489,15 @@ void cg_iteration_mg32(const Lev<double>& L, MgHier<float>& H, CgVecsMg32& V, fl
   const int nbm = march_blocks(M);
   with_nt(M.mnt, [&](auto K) {
     constexpr int NT = decltype(K)::value;
-    if (first) k_cg_dir_spmv_z32_v<true, NT><<<nbm, NT, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
-    else k_cg_dir_spmv_z32_v<false, NT><<<nbm, NT, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
+    // a constant-coefficient system (M.qk set) takes q from a register
+    if (first && M.qk != 0.0)
+      k_cg_dir_spmv_z32_v<true, NT, true><<<nbm, NT, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
+    else if (first)
+      k_cg_dir_spmv_z32_v<true, NT><<<nbm, NT, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
+    else if (M.qk != 0.0)
+      k_cg_dir_spmv_z32_v<false, NT, true><<<nbm, NT, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
+    else
+      k_cg_dir_spmv_z32_v<false, NT><<<nbm, NT, 0, s>>>(M, *z, V.p, V.p_alt, V.q, st, partials, counters, V.x);
   });
   std::swap(V.p, V.p_alt);
   k_cg_update_r32_v<<<nb, BLOCK, 0, s>>>(L, V.r, V.q, r32, st, partials, counters + 1);
