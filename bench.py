@@ -280,7 +280,7 @@ def main():
     }
     ach_op = rp["bytes_per_launch"] / (rp["avg_us"] * 1e-6) / 1e9
     roofline_op = {
-        "kernel": "k_cg_dir_spmv_z32_v<false,512> (pressure CG operator of the precision form: p = z + beta p with z "
+        "kernel": "k_cg_dir_spmv_z32_v<false,512,false> (pressure CG operator of the precision form: p = z + beta p with z "
                   "and p in FP32, fused with q = A p and <p,q> in FP64, diag formed from q_coef; 28 B/cell)",
         "bound": "hbm", "achieved": ach_op, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_op / HBM_PEAK_GBS,
         "avg_us": rp["avg_us"], "bytes_per_launch": rp["bytes_per_launch"],
