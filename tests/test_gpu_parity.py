@@ -457,3 +457,13 @@ def test_constant_coefficient_sweep_matches_the_loading_sweep(monkeypatch):
     assert out[0][1] == out[1][1], (out[0][1], out[1][1])
     for k in FIELDS:
         assert _rel(out[0][0][k], out[1][0][k]) <= 1e-13, k
+
+
+def test_step_parity_round_tests_on_the_host(monkeypatch):
+    """The energy and species FP32 rounds with their start and inner solves
+    tested on the host (DSVOF_ROUND_TEST=0, the schedule before one test per
+    round): C1 in the precision form, 5 steps against the oracle."""
+    monkeypatch.setenv("DSVOF_ROUND_TEST", "0")
+    prm, run = W.config("C1", precision=W.PREC_MIXED)
+    f = W.initial_fields(prm, **run)
+    _run_both(prm, f, steps=5)
