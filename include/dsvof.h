@@ -122,10 +122,18 @@ typedef struct ds_diagnostics {
   int refinements_p;     /* outer FP64 refinement rounds of the pressure solve */
   int iters_phi;         /* iterations of the liquid-transport potential solve */
   double res_phi;
+  int rounds_T, rounds_omega;   /* FP32 rounds of the energy and species solves (precision form; 0 in FP64) */
 } ds_diagnostics;
 
 /* Validate parameters and create a host handle for an nx*ny*nz grid
- * (each >= 2).  Host only.  Returns DS_ERR_ARG for invalid input.
+ * (each >= 2).  The problem statement the handle holds is the paper's: the
+ * domain and boundary conditions (Section 3.2, mapped onto the box as above),
+ * the constant properties and their mixing rule (Section 2.7, eq. 31), the
+ * operating conditions T, p and the equilibrium model (Section 2.5, eqs.
+ * 22-25), the centripetal potential's xi0 (Section 2.6, eq. 29) and the time
+ * step of the segregated algorithm (Section 3.1).  The gas density is fixed
+ * here from eq. 24 for the ambient gas at (T_amb, p).  Host only.  Returns
+ * DS_ERR_ARG for invalid input.
  *
  * Tuning variables read from the environment here (unset: the defaults in
  * brackets, which every measurement uses).  They change launch shapes and
@@ -163,8 +171,9 @@ typedef struct ds_diagnostics {
  *     marching stencil kernels; DSVOF_MARCH_NT0 ["512,256,384"],
  *     DSVOF_MARCH_NT1 ["256,512,384"]: block sizes the marching kernels try
  *     in order (0: CG operator and FP64 residual, 1: V-cycle).
- * The launch-shape variables are process-wide: the last grid created sets
- * them for every grid of the process. */
+ * Every variable is read once, here, into the handle: two handles of one
+ * process keep their own settings (launch shapes included), whatever the
+ * environment holds when the other is created. */
 int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out);
 
 /* Release the host handle.  The workspace is the caller's. */
@@ -181,7 +190,10 @@ int ds_set_fields(ds_grid* g, const double* alpha, const double* T, const double
                   const double* u, const double* v, const double* w, const double* p,
                   void* workspace, size_t workspace_bytes, void* stream);
 
-/* Copy the state out (device pointers; any may be NULL to skip). */
+/* Copy the state out (device pointers; any may be NULL to skip): the fields
+ * the paper reads back from a run (Section 4: droplet volume from alpha,
+ * surface and mean droplet temperature from T, the vapour field omega and the
+ * flow u, v, w, p_rgh), in the layout above. */
 int ds_get_fields(ds_grid* g, double* alpha, double* T, double* omega, double* u,
                   double* v, double* w, double* p, void* stream);
 
@@ -196,6 +208,35 @@ int ds_step(ds_grid* g, int nsteps, void* stream);
  * their saturation values (as in ds_evaporation_rate). */
 int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res);
 
+/* Solver check on the current state: solve one implicit system of the step,
+ * A x = rhs, with the operator the step would assemble from the current
+ * state (its alpha in the role of the advected alpha', its face velocities
+ * for the inletOutlet switches of the open faces) and the step's solver for
+ * that system (preconditioner, precision form and tolerance of the handle):
+ *   DS_SYS_PRESSURE  eq. 7 with the velocity correction of eq. 30: face
+ *                    coefficient dt/h^2 (1/rho)_f, p_rgh = 0 half a cell
+ *                    outside open faces, no flux through walls and inlets;
+ *   DS_SYS_ENERGY    eq. 8 in implicit Euler: rho cp/dt on the diagonal,
+ *                    k_f/h^2 per face, ambient Dirichlet faces 2 k_G/h^2;
+ *   DS_SYS_SPECIES   eq. 9 for the vapour in the gas fraction: rho_G theta/dt,
+ *                    rho_G D theta_f/h^2 per face, Dirichlet faces 2 rho_G D/h^2;
+ *   DS_SYS_POTENTIAL the liquid-transport potential (interface advection,
+ *                    eq. 3, with the divergence-free part of u): the pressure
+ *                    operator with 1/rho = 1/dt; solved to tol_phi.
+ * rhs: device cell array (n doubles, read only).  x: device cell array, the
+ * initial guess on entry and the solution on exit.  The solver stops on its
+ * recursively updated residual, as in the step; rel_res is then the true FP64
+ * relative residual ||rhs - A x||/||rhs|| of the returned x, and the call
+ * returns DS_ERR_NOT_CONVERGED when it exceeds the tolerance.
+ * The state (alpha, c, omega, T, p, u, v, w) is not changed; operator and
+ * solver scratch of the workspace are overwritten.  Returns
+ * DS_ERR_NOT_CONVERGED (x holds the last iterate) when maxit is reached or
+ * the true residual misses the tolerance,
+ * DS_ERR_ARG for an unknown system or null pointer, DS_ERR_STATE before
+ * ds_set_fields.  Synchronises the stream. */
+enum { DS_SYS_PRESSURE = 0, DS_SYS_ENERGY = 1, DS_SYS_SPECIES = 2, DS_SYS_POTENTIAL = 3 };
+int ds_solve_system(ds_grid* g, int which, const double* rhs, double* x, void* stream, int* iters, double* rel_res);
+
 /* Evaporation rate of the current state, eqs. 17-21: total h^3 sum(mdot)
  * in kg/s, and optionally the volumetric source mdot (kg m^-3 s^-1) written
  * to a caller device cell array (NULL to skip).  In the literal species form
@@ -203,10 +244,17 @@ int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res);
  * at the start of a step (the gas cells and every other field are kept). */
 int ds_evaporation_rate(ds_grid* g, double* kg_per_s, double* mdot_or_null, void* stream);
 
-/* Liquid volume h^3 sum(alpha) of the current state [m^3]. */
+/* Liquid volume h^3 sum(alpha) of the current state [m^3]: the quantity
+ * whose normalised equivalent diameter (d/d0)^2 with d = (6 V/pi)^(1/3) the
+ * paper follows in time (Section 4, the d^2 law, and the comparisons of
+ * Sections 5-6).  FP64 reduction in a fixed order.  Synchronises the stream. */
 int ds_droplet_volume(ds_grid* g, double* m3, void* stream);
 
-/* Diagnostics of the last step / solve (host struct, no device work). */
+/* Diagnostics of the last step / solve (host struct, no device work): the
+ * redistribution constant K of eq. 20, the total evaporation rate h^3
+ * sum(mdot) of eqs. 17-19, droplet volume and fuel mass (liquid, eq. 4, plus
+ * vapour, eq. 9) with the boundary outflows, and each linear solve's
+ * iterations and residual (eqs. 7-9). */
 int ds_get_diagnostics(const ds_grid* g, ds_diagnostics* out);
 
 /* Internal fields of the last step, for parity tests: copies one array into

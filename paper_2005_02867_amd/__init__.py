@@ -28,8 +28,9 @@ EXPORTS = ("ds_create_grid", "ds_destroy_grid", "ds_workspace_bytes", "ds_set_fi
            "ds_step", "ds_solve_pressure", "ds_evaporation_rate", "ds_droplet_volume", "ds_get_diagnostics",
            "ds_get_internal", "ds_last_error", "ds_set_kernel_timing", "ds_get_kernel_timing",
            "ds_time_operator_kernel", "ds_tape_bytes", "ds_forward_record", "ds_adjoint",
-           "ds_get_adjoint_iterations", "ds_time_kernel")
+           "ds_get_adjoint_iterations", "ds_time_kernel", "ds_solve_system")
 KERNEL_CG_OPERATOR, KERNEL_MG_SMOOTH = 0, 1
+SYS_PRESSURE, SYS_ENERGY, SYS_SPECIES, SYS_POTENTIAL = 0, 1, 2, 3
 
 
 class Params(C.Structure):
@@ -59,7 +60,7 @@ class Diagnostics(C.Structure):
         ("res_T", C.c_double), ("res_omega", C.c_double), ("res_p", C.c_double), ("rho_G", C.c_double),
         ("iters_T", C.c_int), ("iters_omega", C.c_int), ("iters_p", C.c_int),
         ("n_interface", C.c_int), ("converged", C.c_int), ("refinements_p", C.c_int),
-        ("iters_phi", C.c_int), ("res_phi", C.c_double),
+        ("iters_phi", C.c_int), ("res_phi", C.c_double), ("rounds_T", C.c_int), ("rounds_omega", C.c_int),
     ]
 
 
@@ -72,6 +73,7 @@ _lib.ds_set_fields.argtypes = [_P] + [_P] * 7 + [_P, C.c_size_t, _P]
 _lib.ds_get_fields.argtypes = [_P] + [_P] * 7 + [_P]
 _lib.ds_step.argtypes = [_P, C.c_int, _P]
 _lib.ds_solve_pressure.argtypes = [_P, _P, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+_lib.ds_solve_system.argtypes = [_P, C.c_int, _P, _P, _P, C.POINTER(C.c_int), C.POINTER(C.c_double)]
 _lib.ds_evaporation_rate.argtypes = [_P, C.POINTER(C.c_double), _P, _P]
 _lib.ds_droplet_volume.argtypes = [_P, C.POINTER(C.c_double), _P]
 _lib.ds_get_diagnostics.argtypes = [_P, C.POINTER(Diagnostics)]
@@ -174,6 +176,14 @@ def solve_pressure(h):
     it = C.c_int()
     res = C.c_double()
     _check(h, _lib.ds_solve_pressure(h, _stream(), C.byref(it), C.byref(res)))
+    return it.value, res.value
+
+
+def solve_system(h, which, rhs, x):
+    """x: initial guess in, solution out (device float64 cell tensors)."""
+    it = C.c_int()
+    res = C.c_double()
+    _check(h, _lib.ds_solve_system(h, int(which), _dptr(rhs), _dptr(x), _stream(), C.byref(it), C.byref(res)))
     return it.value, res.value
 
 
@@ -293,6 +303,16 @@ class Grid:
 
     def solve_pressure(self):
         return solve_pressure(self.h)
+
+    def solve_system(self, which, rhs, x0=None):
+        """Solve one implicit system of the step on the current state; returns
+        (x, iterations, relative residual)."""
+        shp = (self.nx, self.ny, self.nz)
+        b = torch.as_tensor(rhs, dtype=torch.float64).to(self.device).reshape(shp).contiguous()
+        x = (torch.zeros(shp, dtype=torch.float64, device=self.device) if x0 is None else
+             torch.as_tensor(x0, dtype=torch.float64).to(self.device).reshape(shp).clone())
+        it, res = solve_system(self.h, which, b, x)
+        return x, it, res
 
     def evaporation_rate(self, return_field=False):
         if return_field:

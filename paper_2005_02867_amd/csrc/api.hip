@@ -45,6 +45,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct ds_grid {
   ds_params prm{};
   DevParams dp{};
+  LaunchShape shape{};             // launch shapes of this handle's solver kernels
   long long n = 0, nu = 0, nv = 0, nw = 0;
   size_t ws_bytes = 0;
   bool bound = false;
@@ -628,6 +629,8 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   *iters = total;
   *res = g->h_status[sys].res;
   if (sys == 2) g->diag_out.refinements_p = rounds;
+  else if (sys == 0) g->diag_out.rounds_T = rounds;
+  else g->diag_out.rounds_omega = rounds;
   return g->h_status[sys].done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
 }
 
@@ -829,6 +832,7 @@ int one_step(ds_grid* g, hipStream_t s) {
   } else {
     D.iters_T = 0;
     D.res_T = 0.0;
+    D.rounds_T = 0;
   }
   // 5b. species (warm start omega' = c'/(rho_G theta))
   launch_species_setup(P, g->a_new, g->c_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, g->om_new, s,
@@ -1098,10 +1102,11 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   for (int ax = 0; ax < 3; ++ax)
     for (int sd = 0; sd < 2; ++sd)
       if (pressure_dirichlet(P.kind[ax * 2 + sd])) g->dirmask |= 1 << (ax * 2 + sd);
-  if (const char* e = getenv("DSVOF_VEC_BLOCKS")) set_vec_max_blocks(atoi(e));
-  if (const char* e = getenv("DSVOF_VEC_YTILE")) g_vec_ytile = atoi(e);
-  if (const char* e = getenv("DSVOF_MARCH_THREADS")) set_march_threads(atoi(e));
-  if (const char* e = getenv("DSVOF_MARCH_MIN_PLANES")) set_march_min_planes(atoi(e));
+  LaunchShape& sh = g->shape;
+  if (const char* e = getenv("DSVOF_VEC_BLOCKS")) set_vec_max_blocks(sh, atoi(e));
+  if (const char* e = getenv("DSVOF_VEC_YTILE")) sh.vec_ytile = atoi(e);
+  if (const char* e = getenv("DSVOF_MARCH_THREADS")) set_march_threads(sh, atoi(e));
+  if (const char* e = getenv("DSVOF_MARCH_MIN_PLANES")) set_march_min_planes(sh, atoi(e));
   for (int cls = 0; cls < 2; ++cls) {
     // DSVOF_MARCH_NT0 / DSVOF_MARCH_NT1: comma-separated block sizes, e.g. "512,256,384"
     const char* e = getenv(cls ? "DSVOF_MARCH_NT1" : "DSVOF_MARCH_NT0");
@@ -1112,8 +1117,9 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
       while (*c && *c != ',') ++c;
       if (*c == ',') ++c;
     }
-    set_march_pref(cls, nts, n);
+    set_march_pref(sh, cls, nts, n);
   }
+  ShapeScope shape_scope(&g->shape);   // the levels below take this handle's shape
   lev_dims(g->L0, nx, ny, nz, 1.0);
   if (const char* e = getenv("DSVOF_INNER_MIN")) g->tune.inner_min = atof(e);
   if (const char* e = getenv("DSVOF_INNER_MIN_JAC")) g->tune.inner_min_jac = atof(e);
@@ -1159,6 +1165,7 @@ int ds_set_fields(ds_grid* g, const double* alpha, const double* T, const double
                   const double* v, const double* w, const double* p, void* workspace, size_t workspace_bytes,
                   void* stream) {
   if (!g) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (!alpha || !T || !omega || !u || !v || !w || !p || !workspace)
     return fail(g, DS_ERR_ARG, "null pointer argument");
   if (workspace_bytes < g->ws_bytes)
@@ -1198,6 +1205,7 @@ int ds_set_fields(ds_grid* g, const double* alpha, const double* T, const double
 int ds_get_fields(ds_grid* g, double* alpha, double* T, double* omega, double* u, double* v, double* w,
                   double* p, void* stream) {
   if (!g) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
   hipStream_t s = S(stream);
   const size_t nb = g->n * sizeof(double);
@@ -1213,6 +1221,7 @@ int ds_get_fields(ds_grid* g, double* alpha, double* T, double* omega, double* u
 
 int ds_step(ds_grid* g, int nsteps, void* stream) {
   if (!g || nsteps < 0) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
   int rc = DS_OK;
   for (int n = 0; n < nsteps; ++n) {
@@ -1227,6 +1236,7 @@ int ds_step(ds_grid* g, int nsteps, void* stream) {
 
 int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res) {
   if (!g) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
   hipStream_t s = S(stream);
   const DevParams& P = g->dp;
@@ -1248,8 +1258,81 @@ int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res) {
   return st;
 }
 
+int ds_solve_system(ds_grid* g, int which, const double* rhs, double* x, void* stream, int* iters, double* rel_res) {
+  if (!g) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
+  if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
+  if (!rhs || !x) return fail(g, DS_ERR_ARG, "null pointer argument");
+  if (which < DS_SYS_PRESSURE || which > DS_SYS_POTENTIAL) return fail(g, DS_ERR_ARG, "unknown system %d", which);
+  hipStream_t s = S(stream);
+  const DevParams& P = g->dp;
+  // Assemble the operator from the current state, exactly as the step's setup
+  // of that system does (the state's alpha in the role of alpha', its
+  // velocities for the inletOutlet switches); the setup's right-hand side is
+  // then replaced by the caller's.
+  int sys = 0;
+  double sc = 0.0, tol = g->prm.tol;
+  bool own_phi = false;
+  switch (which) {
+    case DS_SYS_PRESSURE:
+      launch_pressure_setup(P, g->alpha, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, s, f32_out(g, 2));
+      sys = 2;
+      sc = P.dt / (P.h * P.h);
+      break;
+    case DS_SYS_ENERGY:
+      launch_energy_setup(P, g->alpha, g->T, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, s, f32_out(g, 0));
+      sys = 0;
+      sc = 1.0 / (P.h * P.h);
+      break;
+    case DS_SYS_SPECIES:
+      launch_species_setup(P, g->alpha, g->c, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, nullptr, s,
+                           f32_out(g, 1));
+      sys = 1;
+      sc = P.rho_G * P.D / (P.h * P.h);
+      break;
+    default: {   // the liquid-transport potential, with the step's operator arrays
+      own_phi = g->prm.precision == DS_PREC_MIXED && g->prm.pressure_precond == 1 && g->tune.mg32 &&
+                mg32_supported(g->L0);
+      if (own_phi) launch_div_setup(P, g->u, g->v, g->w, g->phi_ready ? nullptr : g->phi_qc, g->diag, g->b, s);
+      else launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s, f32_out(g, 2));
+      sys = 2;
+      sc = P.dt / (P.h * P.h);
+      tol = g->prm.tol_phi;
+    }
+  }
+  HIPCHK(g, hipMemcpyAsync(g->b, rhs, g->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(g, hipGetLastError());
+  int it = 0;
+  double res = 0.0;
+  g->phi_op = own_phi;
+  int st = solve(g, sys, sc, x, s, &it, &res, tol);
+  g->phi_op = false;
+  if (st != DS_OK && st != DS_ERR_NOT_CONVERGED) return st;
+  // The residual reported is the true FP64 one of the returned x: the solvers
+  // test the recursively updated residual, which drifts from b - A x when the
+  // start is far from the solution (by about eps ||b - A x0||).
+  Lev<double> L = g->L0;
+  L.sc = sc;
+  L.qc = own_phi ? g->phi_qc : g->qc;
+  L.diag = g->diag;
+  pressure_type(g, sys, L);
+  if (own_phi && g->tune.const_q) L.qk = 1.0 / P.dt;
+  if ((st = init_status(g, sys, tol, g->prm.maxit, s)) != DS_OK) return st;
+  launch_resid64(L, g->b, x, g->r, g->status + sys, g->partials, g->counters + CT_SOLVE0, true, s);
+  HIPCHK(g, hipGetLastError());
+  if ((st = sync_status(g, sys, s)) != DS_OK) return st;
+  res = g->h_status[sys].res;
+  if (iters) *iters = it;
+  if (rel_res) *rel_res = res;
+  if (!(res <= tol))
+    return fail(g, DS_ERR_NOT_CONVERGED, "system %d: relative residual %.3e after %d iterations (tol %.3e)", which,
+                res, it, tol);
+  return DS_OK;
+}
+
 int ds_evaporation_rate(ds_grid* g, double* kg_per_s, double* mdot_or_null, void* stream) {
   if (!g) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
   hipStream_t s = S(stream);
   int st;
@@ -1267,6 +1350,7 @@ int ds_evaporation_rate(ds_grid* g, double* kg_per_s, double* mdot_or_null, void
 
 int ds_droplet_volume(ds_grid* g, double* m3, void* stream) {
   if (!g || !m3) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
   hipStream_t s = S(stream);
   launch_diagnostics(g->dp, g->alpha, g->c, g->T, g->p, g->mdot, g->partials, g->counters + CT_DIAG, g->scal, s);
@@ -1279,6 +1363,7 @@ int ds_droplet_volume(ds_grid* g, double* m3, void* stream) {
 
 int ds_get_internal(ds_grid* g, int which, double* dst, size_t count, void* stream) {
   if (!g || !dst) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
   hipStream_t s = S(stream);
   const double* src = nullptr;
@@ -1325,6 +1410,7 @@ int ds_time_operator_kernel(ds_grid* g, int reps, double* avg_us, double* bytes_
 
 int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* bytes_per_launch, void* stream) {
   if (!g || reps < 1 || !avg_us) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (which != DS_KERNEL_CG_OPERATOR && which != DS_KERNEL_MG_SMOOTH) return fail(g, DS_ERR_ARG, "unknown kernel %d", which);
   if (which == DS_KERNEL_MG_SMOOTH && g->prm.pressure_precond != 1)
     return fail(g, DS_ERR_ARG, "the multigrid smoother needs pressure_precond = 1");
@@ -1399,6 +1485,7 @@ size_t ds_tape_bytes(const ds_grid* g, int nsteps, int ckpt_every) {
 
 int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t tape_bytes, void* stream) {
   if (!g) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (!g->bound) return fail(g, DS_ERR_STATE, "ds_set_fields has not been called");
   if (nsteps < 1 || ckpt_every < 1 || !tape) return fail(g, DS_ERR_ARG, "nsteps and ckpt_every must be >= 1, tape non-null");
   if (g->prm.species_form != DS_SPECIES_CONSERVATIVE)
@@ -1436,6 +1523,7 @@ int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t
 int ds_adjoint(ds_grid* g, double dJ_dV, double* grads, double* dalpha0, double* dT0, double* domega0, double* du0,
                double* dv0, double* dw0, void* stream) {
   if (!g || !grads) return DS_ERR_ARG;
+  ShapeScope shape_scope(&g->shape);
   if (!g->recorded) return fail(g, DS_ERR_STATE, "ds_forward_record has not been called");
   if (!std::isfinite(dJ_dV)) return fail(g, DS_ERR_ARG, "dJ_dV is not finite");
   hipStream_t s = S(stream);

@@ -15,12 +15,35 @@ constexpr int TJ = 4;    // tile extent along y (four wavefronts per block)
 
 // One level's operator: (A x)_c = diag_c x_c - sc/2 sum_nb (q_c + q_nb) x_nb,
 // plus its 64x4 tile decomposition.
-// Rows of y per slab in the item order of the z-vectorised kernels: items
-// run z-fastest, then y within a slab of `ytile` rows, then x, then slab.
-// Neighbours in x are then one slab-plane apart instead of a full plane,
-// which keeps the x-1, x, x+1 working set of a streaming pass inside one
-// XCD's L2.  0 or a value not dividing ny: whole planes.
-extern int g_vec_ytile;
+// Launch shapes of the solver kernels.  Each handle holds its own; the entry
+// points of the library make the calling handle's shape current on the
+// calling thread (ShapeScope) before they build levels or launch kernels.
+struct LaunchShape {
+  // Rows of y per slab in the item order of the z-vectorised kernels: items
+  // run z-fastest, then y within a slab of `ytile` rows, then x, then slab.
+  // Neighbours in x are then one slab-plane apart instead of a full plane,
+  // which keeps the x-1, x, x+1 working set of a streaming pass inside one
+  // XCD's L2.  0 or a value not dividing ny: whole planes.
+  int vec_ytile = 0;
+  int vec_max_blocks = 1024;   // grid cap of the z-vectorised pointwise kernels
+  int march_threads = 262144;  // threads (columns x chunks) the marching kernels aim for
+  int march_min_planes = 1;    // shortest chunk of x-planes a marching thread walks
+  // block sizes (256, 384, 512) the marching kernels of class 0 (CG operator,
+  // FP64 residual) and class 1 (V-cycle sweeps, restriction) try in order
+  int march_pref[2][4] = {{512, 256, 384, 0}, {256, 512, 384, 0}};
+};
+// The calling thread's current shape (the defaults outside any scope).
+const LaunchShape& launch_shape();
+class ShapeScope {
+ public:
+  explicit ShapeScope(const LaunchShape* s);
+  ~ShapeScope();
+  ShapeScope(const ShapeScope&) = delete;
+  ShapeScope& operator=(const ShapeScope&) = delete;
+
+ private:
+  const LaunchShape* prev_;
+};
 
 template <class T>
 struct Lev {
@@ -44,7 +67,8 @@ inline void lev_dims(Lev<T>& L, int nx, int ny, int nz, double sc) {
   L.nx = nx;
   L.ny = ny;
   L.nz = nz;
-  L.ytile = (g_vec_ytile > 0 && ny % g_vec_ytile == 0) ? g_vec_ytile : ny;
+  const int yt = launch_shape().vec_ytile;
+  L.ytile = (yt > 0 && ny % yt == 0) ? yt : ny;
   L.mch = 1;
   L.mnt = 256;
   L.dfly = 0;
@@ -146,14 +170,14 @@ double replay_smooth_kernel(const Lev<T>& L, const MgHier<T>& H, const T* r, con
 // operator copies and r, z in FP32).  Needs mg32_supported(L).
 bool mg32_supported(const Lev<double>& L);
 // Largest grid of the z-vectorised kernels (rounded to a multiple of 8).
-void set_vec_max_blocks(int nb);
+void set_vec_max_blocks(LaunchShape& sh, int nb);
 // Threads (columns x chunks) the marching kernels aim for.
-void set_march_threads(int n);
+void set_march_threads(LaunchShape& sh, int n);
 // Shortest chunk of x-planes a marching thread walks.
-void set_march_min_planes(int n);
+void set_march_min_planes(LaunchShape& sh, int n);
 // Block sizes (256, 384, 512) the marching kernels of class cls try in order
 // (0: CG operator and FP64 residual, 1: V-cycle sweeps and restriction).
-void set_march_pref(int cls, const int* nts, int n);
+void set_march_pref(LaunchShape& sh, int cls, const int* nts, int n);
 double replay_operator_z32(const Lev<double>& L, const float* z, const float* pin, float* pout, double* q,
                            SolveStatus* st, double* partials, unsigned* counter, int reps, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1);

@@ -492,16 +492,20 @@ template <class T>
 inline long long vec_items(const Lev<T>& L) {
   return (long long)L.nx * L.ny * (L.nz / VW<T>::n);
 }
-int g_vec_ytile = 0;
-static int g_vec_max_blocks = 1024;
-void set_vec_max_blocks(int nb) {
+static const LaunchShape k_default_shape{};
+static thread_local const LaunchShape* t_shape = nullptr;
+const LaunchShape& launch_shape() { return t_shape ? *t_shape : k_default_shape; }
+ShapeScope::ShapeScope(const LaunchShape* s) : prev_(t_shape) { t_shape = s; }
+ShapeScope::~ShapeScope() { t_shape = prev_; }
+
+void set_vec_max_blocks(LaunchShape& sh, int nb) {
   // every vectorised kernel publishes at most 2 partials per block
   nb = std::min(std::max(nb, NXCD), MAX_BLOCKS * MAX_RED / 2);
-  g_vec_max_blocks = nb / NXCD * NXCD;
+  sh.vec_max_blocks = nb / NXCD * NXCD;
 }
 static int vec_blocks(long long items) {
   long long nb = (items + BLOCK - 1) / BLOCK;
-  nb = std::min<long long>(std::max<long long>(nb, NXCD), g_vec_max_blocks);
+  nb = std::min<long long>(std::max<long long>(nb, NXCD), launch_shape().vec_max_blocks);
   return (int)((nb + NXCD - 1) / NXCD * NXCD);
 }
 
@@ -584,42 +588,41 @@ __device__ __forceinline__ void off_sum_v(const Lev<T>& L, unsigned c, int i, in
 // reads come from the same L2.
 
 // Chunks per column: enough threads for about 1024 blocks of 256.
-int g_march_threads = 262144;
-int g_march_min_planes = 1;
-void set_march_threads(int n) { g_march_threads = std::max(n, BLOCK); }
-void set_march_min_planes(int n) { g_march_min_planes = std::max(n, 1); }
+void set_march_threads(LaunchShape& sh, int n) { sh.march_threads = std::max(n, BLOCK); }
+void set_march_min_planes(LaunchShape& sh, int n) { sh.march_min_planes = std::max(n, 1); }
 // Block sizes tried in order, per kernel class (0: CG operator and FP64
 // residual, 1: V-cycle sweeps and restriction); the first that holds whole
 // z-rows of the level (every chunk's rows filling whole blocks) is taken,
 // else 256 without row sharing.  Entries: 256, 384, 512; 0 ends the list.
-int g_march_pref[2][4] = {{512, 256, 384, 0}, {256, 512, 384, 0}};
-void set_march_pref(int cls, const int* nts, int n) {
+void set_march_pref(LaunchShape& sh, int cls, const int* nts, int n) {
   if (cls < 0 || cls > 1) return;
   int k = 0;
   for (int t = 0; t < n && k < 3; ++t)
-    if (nts[t] == 256 || nts[t] == 384 || nts[t] == 512) g_march_pref[cls][k++] = nts[t];
-  if (k == 0) g_march_pref[cls][k++] = 256;
-  for (; k < 4; ++k) g_march_pref[cls][k] = 0;
+    if (nts[t] == 256 || nts[t] == 384 || nts[t] == 512) sh.march_pref[cls][k++] = nts[t];
+  if (k == 0) sh.march_pref[cls][k++] = 256;
+  for (; k < 4; ++k) sh.march_pref[cls][k] = 0;
 }
 // Block size of the level for class cls; pairs: also whole row pairs per
 // block (the marching restriction).  0 when pairs is asked and none fits.
 template <class T>
 inline int march_nt(const Lev<T>& L, int cls, bool pairs) {
   const long long nzv = L.nz / VW<T>::n, rows = (long long)L.ny * nzv;
-  for (int t = 0; t < 4 && g_march_pref[cls][t]; ++t) {
-    const int nt = g_march_pref[cls][t];
+  const int* pref = launch_shape().march_pref[cls];
+  for (int t = 0; t < 4 && pref[t]; ++t) {
+    const int nt = pref[t];
     if (nt % nzv == 0 && rows % nt == 0 && (!pairs || ((nt / nzv) % 2 == 0))) return nt;
   }
   return pairs ? 0 : 256;
 }
-// threads: the thread count to aim for (0: g_march_threads).
+// threads: the thread count to aim for (0: the shape's march_threads).
 template <class T>
 inline Lev<T> march_lev(Lev<T> L, int cls = 0, long long threads = 0) {
   L.mnt = march_nt(L, cls, false);
   const long long ncol = (long long)L.ny * (L.nz / VW<T>::n);
-  const long long aim = threads > 0 ? threads : (long long)g_march_threads;
+  const LaunchShape& sh = launch_shape();
+  const long long aim = threads > 0 ? threads : (long long)sh.march_threads;
   const long long nch = std::min<long long>(std::max<long long>((aim + ncol - 1) / ncol, 1), L.nx);
-  const long long clen = std::max<long long>((L.nx + nch - 1) / nch, std::min(g_march_min_planes, L.nx));
+  const long long clen = std::max<long long>((L.nx + nch - 1) / nch, std::min(sh.march_min_planes, L.nx));
   L.mch = (int)((L.nx + clen - 1) / clen);   // no empty trailing chunks
   return L;
 }
