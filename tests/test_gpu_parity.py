@@ -1,8 +1,9 @@
 """GPU (HIP, gfx950) vs CPU oracle, through the C ABI.
 
 FP64 path: every field after every step within 1e-9 relative (per-field
-2-norm, both sides solving to 1e-13); integer decisions (interface class,
-adj association) bit-exact.
+2-norm and element by element against the field's largest magnitude, both
+sides solving to 1e-13); integer decisions (interface class, adj
+association) bit-exact.
 """
 import math
 import sys
@@ -33,10 +34,26 @@ def _rel(a, b):
     return d / nb if nb > 0 else d
 
 
+def _rel_max(a, b):
+    """max |a - b| / max |b| (absolute where b vanishes): the element-wise bar."""
+    a = torch.as_tensor(a, dtype=torch.float64).cpu()
+    b = torch.as_tensor(b, dtype=torch.float64).cpu()
+    nb = float(b.abs().max()) if b.numel() else 0.0
+    d = float((a - b).abs().max()) if b.numel() else 0.0
+    return d / nb if nb > 0 else d
+
+
+def _relx(a, b):
+    return max(_rel(a, b), _rel_max(a, b))
+
+
 def _compare(g_fields, st, where, tol=TOL):
+    """Every field within tol relative, both in the 2-norm and element by
+    element (max |a - b| <= tol max |b|), so errors confined to small-magnitude
+    regions (the alpha band, omega near the droplet, faces at walls) show."""
     errs = {}
     for k in FIELDS:
-        errs[k] = _rel(g_fields[k], st[k])
+        errs[k] = max(_rel(g_fields[k], st[k]), _rel_max(g_fields[k], st[k]))
     bad = {k: e for k, e in errs.items() if not e <= tol}
     assert not bad, f"{where}: {bad} (all: {errs})"
     return errs
@@ -124,9 +141,9 @@ def test_interface_decisions_bit_exact():
     found = geo["found"].numpy()
     expect[ic[found, 0], ic[found, 1], ic[found, 2]] = flat(geo["adj"].numpy()[found])
     assert np.array_equal(adj_gpu, expect)
-    assert _rel(g.internal(ds.FIELD_MDOT_RAW), mraw) < 1e-12
+    assert _relx(g.internal(ds.FIELD_MDOT_RAW), mraw) < 1e-12
     mdot_o, K = I.redistribute(mraw, st["alpha"])
-    assert _rel(mdot, mdot_o) < 1e-12
+    assert _relx(mdot, mdot_o) < 1e-12
     assert total == pytest.approx(prm["h"] ** 3 * float(mdot_o.sum()), rel=1e-12)
 
 
@@ -141,9 +158,9 @@ def test_solve_pressure_static_droplet():
     assert res <= 1e-13
     new, d = S.step(S.to_state(f, prm), prm)
     out = g.get_fields()
-    assert _rel(out["p"], new["p"]) < TOL
+    assert _relx(out["p"], new["p"]) < TOL
     for k in "uvw":
-        assert _rel(out[k], new[k]) < 1e-8
+        assert _relx(out[k], new[k]) < 1e-8
 
 
 def test_determinism_bitwise():
@@ -276,7 +293,7 @@ def test_neumann_preconditioner_same_solution_fewer_iterations(monkeypatch, prec
         out[nm] = (g.get_fields(), g.diagnostics())
         del g
     for k in FIELDS:
-        assert _rel(out[1][0][k], out[0][0][k]) <= 1e-11, k
+        assert _relx(out[1][0][k], out[0][0][k]) <= 1e-11, k
     d0, d1 = out[0][1], out[1][1]
     print("iterations T/omega, Jacobi:", d0["iters_T"], d0["iters_omega"], "Neumann:", d1["iters_T"], d1["iters_omega"])
     assert d1["iters_omega"] < d0["iters_omega"] and d1["iters_T"] <= d0["iters_T"]
@@ -365,13 +382,13 @@ def test_literal_species_evaporation_rate_and_assignment():
     liquid = st["alpha"] > prm["eps_gas"]
     assert bool(liquid.any())
     om_g = torch.as_tensor(g.get_fields()["omega"], dtype=torch.float64).cpu()
-    assert _rel(om_g[liquid], st["omega"][liquid]) < 1e-13
+    assert _relx(om_g[liquid], st["omega"][liquid]) < 1e-13
     assert torch.equal(om_g[~liquid], torch.as_tensor(f["omega"], dtype=torch.float64)[~liquid])
     geo = I.geometry(st["alpha"], prm)
     mraw = I.raw_evaporation(st["alpha"], st["T"], st["omega"], st["u"], st["v"], st["w"], geo, prm, rho_G)
-    assert _rel(g.internal(ds.FIELD_MDOT_RAW), mraw) < 1e-12
+    assert _relx(g.internal(ds.FIELD_MDOT_RAW), mraw) < 1e-12
     mdot_o, K = I.redistribute(mraw, st["alpha"])
-    assert _rel(mdot, mdot_o) < 1e-12
+    assert _relx(mdot, mdot_o) < 1e-12
     assert total == pytest.approx(prm["h"] ** 3 * float(mdot_o.sum()), rel=1e-12)
 
 
@@ -456,7 +473,7 @@ def test_constant_coefficient_sweep_matches_the_loading_sweep(monkeypatch):
         out.append((g.get_fields(), its))
     assert out[0][1] == out[1][1], (out[0][1], out[1][1])
     for k in FIELDS:
-        assert _rel(out[0][0][k], out[1][0][k]) <= 1e-13, k
+        assert _relx(out[0][0][k], out[1][0][k]) <= 1e-13, k
 
 
 def test_step_parity_round_tests_on_the_host(monkeypatch):
@@ -467,3 +484,15 @@ def test_step_parity_round_tests_on_the_host(monkeypatch):
     prm, run = W.config("C1", precision=W.PREC_MIXED)
     f = W.initial_fields(prm, **run)
     _run_both(prm, f, steps=5)
+
+
+def test_step_parity_forced_convection_64cubed():
+    """A 64^3 cut of the forced-convection configuration (6 mm box, 1.5 mm
+    droplet, 0.5 m/s inflow at z-, gravity on, ideal equilibrium, dt 5e-6 s):
+    every field after each of 20 steps against the oracle, both at 1e-13."""
+    prm, run = W.scaled("C2", 64)
+    f = W.initial_fields(prm, **run)
+    g, st, worst = _run_both(prm, f, steps=20)
+    d = g.diagnostics()
+    print("worst relative errors over 20 steps:", worst, "max |w|", float(st["w"].abs().max()))
+    assert d["mdot_total"] > 0 and float(st["w"].abs().max()) >= 0.5
