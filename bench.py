@@ -37,15 +37,70 @@ def log(msg):
     print(f"# {msg}", file=sys.stderr, flush=True)
 
 
-def timed_run(ds, torch, prm, fields, steps, warmup, timing=False):
+# Algorithmic bytes per cell of the precision form's kernels (each array a
+# kernel streams counted once per launch; FP64 state 8 B, FP32 solver arrays
+# 4 B; a coarse level's arrays counted in cells of that level).
+EXPLICIT_B = {            # FP64 stages, once per step
+    "k_interface_scan": 20,      # alpha read; mraw, adj written
+    "k_source": 32,              # alpha, mraw read; mdot, alpha1 written
+    "k_div_setup": 32,           # u, v, w read; potential's right-hand side written
+    "k_advect": 88,              # alpha1, omega, T, c, u, v, w, phi read; alpha', c', T' written
+    "k_energy_setup": 80,        # alpha', T', mdot, u, v, w read; q, diag, b and FP32 q, diag written
+    "k_species_setup": 88,       # ... and the warm start omega' written
+    "k_species_update": 72,      # alpha', c', mdot, omega, u, v, w read; c, omega written
+    "k_predictor": 64,           # alpha', xi, u, v, w read; u*, v*, w* written
+    "k_pressure_setup": 80,      # alpha', mdot, u*, v*, w* read; q, diag, b and FP32 q, diag written
+    "k_project": 64,             # alpha', p, u*, v*, w* read; u, v, w written
+    "k_diagnostics": 40,         # alpha, c, T, p, mdot read
+}
+RB_ZERO_B, RB_GEN_B, RB_PROLONG_B = 12, 16, 16.5    # coloured sweeps (r, q [, x, x_coarse] read; x written)
+RESTRICT_B = 12.5                                   # r, x, q read; coarse r written
+SMOOTH_TWO_B, SMOOTH_B, PROLONG_SMOOTH_B = 12, 16, 16.5
+CG_OP_B, CG_OP_CQ_B, CG_UPDATE_B = 44, 40, 28       # FP64 CG with FP32 directions; residual update (+ FP32 r)
+RESID64_B, AXPY_B = 36, 20
+INNER_ITER_B = 32 + 24                              # FP32 CG operator + Neumann-polynomial residual update
+ROUND_B = 16 + 12 + 24 + 40                         # round start, first z, correction, FP64 residual
+
+
+def vcycle_bytes(n, const_q):
+    """Bytes of one FP32 V-cycle per fine cell: coloured 3+3 sweeps on the
+    fine level, damped Jacobi 4+4 on the levels down to 32^3, the levels that
+    fit in one workgroup's LDS (16^3 and below) negligible."""
+    # from x = 0, two from x, restriction; prolongation with a sweep, two from x
+    # (a constant-coefficient level loads no q: 4 B less per sweep)
+    fine = RB_ZERO_B + 2 * RB_GEN_B + RESTRICT_B + RB_PROLONG_B + 2 * RB_GEN_B - (24 if const_q else 0)
+    coarse = 0.0
+    m, frac = n // 2, 1.0 / 8.0
+    while m > 16:
+        coarse += frac * (SMOOTH_TWO_B + 2 * SMOOTH_B + RESTRICT_B + PROLONG_SMOOTH_B + 3 * SMOOTH_B)
+        m //= 2
+        frac /= 8.0
+    return fine + coarse
+
+
+def step_bytes_per_cell(n, d):
+    """Algorithmic bytes per cell of one precision-form step of an n^3 grid,
+    from the kernels' byte table and the step's iteration counts (d: the
+    step's diagnostics: iterations of each solve, FP32 rounds of the energy
+    and species solves)."""
+    b = sum(EXPLICIT_B.values())
+    vp, vphi = vcycle_bytes(n, False), vcycle_bytes(n, True)
+    b += RESID64_B + vp + d["iters_p"] * (CG_OP_B + CG_UPDATE_B + vp) + AXPY_B
+    b += RESID64_B + vphi + d["iters_phi"] * (CG_OP_CQ_B + CG_UPDATE_B + vphi) + AXPY_B
+    for it, rounds in ((d["iters_T"], d["rounds_T"]), (d["iters_omega"], d["rounds_omega"])):
+        b += RESID64_B + rounds * ROUND_B + it * INNER_ITER_B
+    return b
+
+
+def timed_run(ds, torch, prm, fields, steps, warmup, replays=False):
+    """Time `steps` steps after `warmup` (no kernel timing inside the timed
+    region); with replays, afterwards time the pressure CG operator and the
+    fine-level multigrid sweep replayed back to back on the live system."""
     g = ds.Grid(prm)
     g.set_fields(fields)
     for _ in range(warmup):
         g.step(1)
-    torch.cuda.synchronize()
-    if timing:
-        g.set_kernel_timing(True)
-    iters, mdot = [], []
+    iters, mdot, diags = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -53,15 +108,26 @@ def timed_run(ds, torch, prm, fields, steps, warmup, timing=False):
         d = g.diagnostics()
         iters.append([d["iters_T"], d["iters_omega"], d["iters_p"], d["refinements_p"], d["iters_phi"]])
         mdot.append(d["mdot_total"])
+        diags.append(d)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kt = g.kernel_timing() if timing else None
     d = g.diagnostics()
-    # the same operator kernel replayed back to back on the live pressure system
-    rep = g.time_operator_kernel(50) if timing else None
-    rep_s = g.time_kernel(1, 50) if timing else None      # fine-level multigrid sweep
-    return dict(seconds=t1 - t0, iters=iters, kernel=kt, replay=rep, replay_smooth=rep_s, volume=d["volume"], diag=d,
-                mdot=mdot)
+    rep = g.time_operator_kernel(50) if replays else None
+    rep_s = g.time_kernel(1, 50) if replays else None      # fine-level multigrid sweep
+    del g
+    torch.cuda.empty_cache()
+    return dict(seconds=t1 - t0, iters=iters, replay=rep, replay_smooth=rep_s, volume=d["volume"], diag=d,
+                diags=diags, mdot=mdot)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def adjoint_cost(ds, torch, W):
@@ -128,10 +194,13 @@ def other_configs(ds, torch, W, steps=5, warmup=2):
     return out
 
 
-def adjoint_cost_384(ds, torch, W, steps=10, ckpt=5):
+def adjoint_cost_384(ds, torch, W, steps=100, ckpt=20):
     """Adjoint cost at 384^3 (10 bar, Peng-Robinson, forced 1 m/s, precision
-    form): reverse sweep over `steps` steps with a checkpoint every `ckpt`,
-    against the forward run of the same steps."""
+    form), the largest configuration's differentiation shape: reverse sweep
+    over `steps` steps with a checkpoint every `ckpt` (100 and 20: a tape of
+    about 125 GB), against the forward run of the same steps.  The steps start
+    from the initial state (the configuration's 400 forward steps before the
+    differentiated window only move the state)."""
     prm, run = W.config("C5")
     f = W.initial_fields(prm, **run)
     g = ds.Grid(prm)
@@ -146,15 +215,20 @@ def adjoint_cost_384(ds, torch, W, steps=10, ckpt=5):
     del g
     g = ds.Grid(prm)
     g.set_fields(f)
+    del f
+    tape = ds.tape_bytes(g.h, steps, ckpt)
+    log(f"  384^3: forward {fwd:.2f} s for {steps} steps; recording with a {tape / 1e9:.0f} GB tape")
     t0 = time.perf_counter()
     g.forward_record(steps, ckpt)
     t1 = time.perf_counter()
+    log(f"  recorded in {t1 - t0:.2f} s; reverse sweep")
     r = g.adjoint(1.0, fields=False)
     t2 = time.perf_counter()
     del g
     torch.cuda.empty_cache()
     return {"workload": f"384^3 over 10 mm, 2.0 mm droplet, 10 bar, Peng-Robinson, forced 1 m/s, precision form, "
                         f"{steps} steps from the initial state, checkpoint every {ckpt}",
+            "steps": steps, "ckpt_every": ckpt, "tape_GB": tape / 1e9,
             "forward_s": fwd, "record_s": t1 - t0, "reverse_s": t2 - t1, "reverse_over_forward": (t2 - t1) / fwd,
             "dV_dD_v": r["D_v"], "dV_ddh_ev": r["dh_ev"], "dV_dT_amb": r["T_amb"]}
 
@@ -196,6 +270,7 @@ def cpu_baseline(prm, fields, jacobi_iters_p, sample_iters=8):
     ncell = prm["nx"] * prm["ny"] * prm["nz"]
     return {
         "value": ncell / t_step, "unit": "cell-steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+        "cpu": cpu_model(), "host_cpus": os.cpu_count(),
         "sample": (f"one oracle step of the {prm['nx']}^3 workload, pressure and potential Jacobi-PCG cut at {ip} "
                    f"iterations in total ({t1 - t0:.1f} s measured: {t_fixed:.1f} s outside those solves, "
                    f"{t_iter:.3f} s per iteration); step time = {t_fixed:.1f} s + {jacobi_iters_p} iterations (the "
@@ -213,7 +288,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     ap.add_argument("--configs", action="store_true",
-                    help="also time the other configurations (32^3 ... 384^3) and the 384^3 adjoint")
+                    help="also time the other configurations (32^3 ... 384^3)")
+    ap.add_argument("--no-adjoint-384", action="store_true",
+                    help="skip the 384^3 adjoint leg (100 reverse steps, checkpoint every 20, ~125 GB tape)")
     ap.add_argument("--species-literal", action="store_true",
                     help="time the literal species form (the default; kept for older command lines)")
     ap.add_argument("--no-species-literal", action="store_true",
@@ -256,18 +333,27 @@ def main():
                           "copy_bytes": 1 << 30}))
         return
     log(f"precision form (FP32 multigrid and FP32 CG rounds, FP64 residuals): warmup {args.warmup}, timing {args.steps} steps")
-    mixed = timed_run(ds, torch, dict(prm, precision=W.PREC_MIXED), fields, args.steps, args.warmup, timing=True)
+    mixed = timed_run(ds, torch, dict(prm, precision=W.PREC_MIXED), fields, args.steps, args.warmup, replays=True)
     log(f"  {mixed['seconds'] * 1e3 / args.steps:.2f} ms/step, iters {mixed['iters'][-1]}")
     fp64 = None
     if not args.no_fp64:
         log(f"all-FP64: warmup {args.warmup}, timing {args.steps} steps")
-        fp64 = timed_run(ds, torch, dict(prm, precision=W.PREC_FP64), fields, args.steps, args.warmup, timing=True)
+        fp64 = timed_run(ds, torch, dict(prm, precision=W.PREC_FP64), fields, args.steps, args.warmup, replays=True)
         log(f"  {fp64['seconds'] * 1e3 / args.steps:.2f} ms/step, iters {fp64['iters'][-1]}")
+    # the liquid-transport potential's share of the step: the same run with the
+    # liquid moved by u^n itself (no potential setup and solve)
+    log(f"precision form without the liquid-transport potential: warmup {args.warmup}, timing {args.steps} steps")
+    nophi = timed_run(ds, torch, dict(prm, precision=W.PREC_MIXED, liquid_transport=0), fields, args.steps,
+                      args.warmup)
+    ms_mixed = mixed["seconds"] * 1e3 / args.steps
+    ms_nophi = nophi["seconds"] * 1e3 / args.steps
+    log(f"  {ms_nophi:.2f} ms/step")
 
     rs = mixed["replay_smooth"]
     rp = mixed["replay"]
-    kt = mixed["kernel"]
     achieved = rs["bytes_per_launch"] / (rs["avg_us"] * 1e-6) / 1e9
+    b_step = sum(step_bytes_per_cell(prm["nx"], d) for d in mixed["diags"]) / len(mixed["diags"])
+    step_gbs = b_step * ncell / (ms_mixed * 1e-3) / 1e9
     roofline = {
         "kernel": "k_mg_rb_v<float,RB_GEN,false,256,false,false> (fine-level coloured (x-z red-black) sweep of the multigrid "
                   "preconditioner, FP32, reads r, x, q_coef, forms diag from q_coef, writes x: 16 B/cell; the "
@@ -277,6 +363,10 @@ def main():
         "avg_us": rs["avg_us"], "bytes_per_launch": rs["bytes_per_launch"],
         "timing": f"HIP events around {rs['reps']} back-to-back launches on the live pressure system after the "
                   f"timed steps (stream of the launches)",
+        "step_bytes_per_cell": b_step, "step_achieved": step_gbs, "step_frac": step_gbs / HBM_PEAK_GBS,
+        "step_model": "algorithmic bytes of every kernel of the step (each array a kernel streams counted once per "
+                      "launch) summed with the step's own iteration counts and FP32 rounds, over the measured "
+                      "ms_per_step",
     }
     ach_op = rp["bytes_per_launch"] / (rp["avg_us"] * 1e-6) / 1e9
     roofline_op = {
@@ -299,10 +389,14 @@ def main():
                    "iters_T_omega_p_rounds_phi": mixed["iters"][-1]},
         "roofline": roofline,
         "roofline_cg_operator": roofline_op,
+        "liquid_transport_potential": {
+            "ms_per_step_without": ms_nophi, "ms_per_step_share": ms_mixed - ms_nophi,
+            "iters_phi": mixed["iters"][-1][4],
+            "note": "step time with the liquid moved by u^n itself (no potential setup and solve) against the "
+                    "default step"},
     }
     if fp64:
         v64 = ncell * args.steps / fp64["seconds"]
-        kt64 = fp64["kernel"]
         rp64 = fp64["replay"]
         out["fp64"] = {"value": v64, "ms_per_step": fp64["seconds"] * 1e3 / args.steps,
                        "iters_T_omega_p": fp64["iters"][-1],
@@ -327,12 +421,13 @@ def main():
         log(f"  forward {out['adjoint']['forward_s']:.3f} s, reverse/forward "
             f"{out['adjoint']['ckpt1']['reverse_over_forward']:.2f} (every state stored), "
             f"{out['adjoint']['ckpt10']['reverse_over_forward']:.2f} (checkpoint every 10)")
+    if not args.no_adjoint and not args.no_adjoint_384:
+        log("adjoint cost at 384^3: 100 steps, checkpoint every 20")
+        out["adjoint_384"] = adjoint_cost_384(ds, torch, W)
+        log(f"  reverse/forward {out['adjoint_384']['reverse_over_forward']:.2f}")
     if args.configs:
         log("other configurations")
         out["other_configs"] = other_configs(ds, torch, W)
-        log("adjoint cost at 384^3")
-        out["adjoint_384"] = adjoint_cost_384(ds, torch, W)
-        log(f"  reverse/forward {out['adjoint_384']['reverse_over_forward']:.2f}")
     if not args.no_cpu:
         log("GPU Jacobi-PCG step (pressure iteration count for the CPU extrapolation)")
         g = ds.Grid(dict(prm, precision=W.PREC_FP64, pressure_precond=0))
