@@ -361,7 +361,30 @@ int ds_get_adjoint_iterations(const ds_grid* g, int* iters4);
 enum { DS_KERNEL_CG_OPERATOR = 0, DS_KERNEL_MG_SMOOTH = 1 };
 int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* bytes_per_launch, void* stream);
 
-/* Message describing the last error on this handle ("" if none). */
+/* ---- For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * Liquid volume h^3 sum(alpha) of a caller's device cell array alpha
+ * (nx*ny*nz doubles, the layout above), written to the caller's device double
+ * *m3: the quantity ds_droplet_volume returns for a handle whose state holds
+ * the same alpha, bit for bit (same blocks, same fixed reduction order), with
+ * no handle and no workspace.  Asynchronous on `stream` (no synchronisation;
+ * the launches are kernels only, so the call can be captured into a graph).
+ * The call allocates nothing: its only device memory beyond alpha and *m3 is
+ * the library's own scratch, a file-scope device array of
+ * DS_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds until the
+ * process ends (block partials of the reduction and its completion counter,
+ * which each call clears itself).  Calls that overlap on one GPU (two streams
+ * or two host threads) share that array and race: serialise them.  Grids of
+ * more than DS_NOALLOC_MAX_CELLS cells, extents below 1, h <= 0 and null
+ * pointers return DS_ERR_ARG before anything is launched; the message is then
+ * ds_last_error(NULL) on the calling thread. */
+#define DS_NOALLOC_SCRATCH_BYTES 16640
+#define DS_NOALLOC_MAX_CELLS 2147483647LL
+int ds_droplet_volume_noalloc(const double* alpha, int nx, int ny, int nz, double h, double* m3, void* stream);
+
+/* Message describing the last error on this handle ("" if none); with a NULL
+ * handle, the calling thread's last failed handle-free call. */
 const char* ds_last_error(const ds_grid* g);
 
 #ifdef __cplusplus

@@ -28,7 +28,7 @@ EXPORTS = ("ds_create_grid", "ds_destroy_grid", "ds_workspace_bytes", "ds_set_fi
            "ds_step", "ds_solve_pressure", "ds_evaporation_rate", "ds_droplet_volume", "ds_get_diagnostics",
            "ds_get_internal", "ds_last_error", "ds_set_kernel_timing", "ds_get_kernel_timing",
            "ds_time_operator_kernel", "ds_tape_bytes", "ds_forward_record", "ds_adjoint",
-           "ds_get_adjoint_iterations", "ds_time_kernel", "ds_solve_system")
+           "ds_get_adjoint_iterations", "ds_time_kernel", "ds_solve_system", "ds_droplet_volume_noalloc")
 KERNEL_CG_OPERATOR, KERNEL_MG_SMOOTH = 0, 1
 SYS_PRESSURE, SYS_ENERGY, SYS_SPECIES, SYS_POTENTIAL = 0, 1, 2, 3
 
@@ -87,6 +87,7 @@ _lib.ds_forward_record.argtypes = [_P, C.c_int, C.c_int, _P, C.c_size_t, _P]
 _lib.ds_adjoint.argtypes = [_P, C.c_double, C.POINTER(C.c_double)] + [_P] * 6 + [_P]
 _lib.ds_get_adjoint_iterations.argtypes = [_P, C.POINTER(C.c_int)]
 _lib.ds_time_kernel.argtypes = [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]
+_lib.ds_droplet_volume_noalloc.argtypes = [_P, C.c_int, C.c_int, C.c_int, C.c_double, _P, _P]
 _lib.ds_last_error.argtypes = [_P]
 _lib.ds_last_error.restype = C.c_char_p
 
@@ -101,10 +102,10 @@ class NotConverged(DSError):
     pass
 
 
-def _check(handle, code):
+def _check(handle, code, handle_free=False):
     if code == DS_OK:
         return
-    msg = _lib.ds_last_error(handle).decode() if handle else ""
+    msg = _lib.ds_last_error(handle).decode() if (handle or handle_free) else ""
     raise (NotConverged if code == DS_ERR_NOT_CONVERGED else DSError)(code, msg)
 
 
@@ -197,6 +198,18 @@ def droplet_volume(h):
     v = C.c_double()
     _check(h, _lib.ds_droplet_volume(h, C.byref(v), _stream()))
     return v.value
+
+
+def droplet_volume_noalloc(alpha, h, out):
+    """h^3 sum(alpha) of a device float64 cell tensor (nx, ny, nz) into the
+    device float64 tensor out[0]; no handle, nothing allocated, asynchronous."""
+    if alpha.dim() != 3 or alpha.dtype != torch.float64 or not alpha.is_contiguous():
+        raise ValueError("alpha: a contiguous float64 (nx, ny, nz) tensor")
+    if out.dtype != torch.float64 or out.numel() < 1:
+        raise ValueError("out: a float64 tensor of at least one element")
+    nx, ny, nz = alpha.shape
+    _check(None, _lib.ds_droplet_volume_noalloc(_dptr(alpha), nx, ny, nz, float(h), _dptr(out), _stream()),
+           handle_free=True)
 
 
 def get_diagnostics(h) -> dict:

@@ -17,6 +17,8 @@
 
 using namespace dsv;
 
+const char* dsv_noalloc_last_error();   // noalloc.hip: the thread's last handle-free error
+
 namespace {
 
 // Peng-Robinson compressibility of the pure ambient gas (largest root), host side,
@@ -1596,6 +1598,6 @@ int ds_get_diagnostics(const ds_grid* g, ds_diagnostics* out) {
   return DS_OK;
 }
 
-const char* ds_last_error(const ds_grid* g) { return g ? g->err.c_str() : "null handle"; }
+const char* ds_last_error(const ds_grid* g) { return g ? g->err.c_str() : dsv_noalloc_last_error(); }
 
 }  // extern "C"
