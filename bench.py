@@ -58,6 +58,7 @@ RESTRICT_B = 12.5                                   # r, x, q read; coarse r wri
 SMOOTH_TWO_B, SMOOTH_B, PROLONG_SMOOTH_B = 12, 16, 16.5
 CG_OP_B, CG_OP_CQ_B, CG_UPDATE_B = 44, 40, 28       # FP64 CG with FP32 directions; residual update (+ FP32 r)
 RESID64_B, AXPY_B = 36, 20
+DIRECT_POTENTIAL_B = 5 * 16 + 32 + 16               # five transform passes, residual check, q and diag written
 INNER_ITER_B = 32 + 24                              # FP32 CG operator + Neumann-polynomial residual update
 ROUND_B = 16 + 12 + 24 + 40                         # round start, first z, correction, FP64 residual
 
@@ -86,7 +87,10 @@ def step_bytes_per_cell(n, d):
     b = sum(EXPLICIT_B.values())
     vp, vphi = vcycle_bytes(n, False), vcycle_bytes(n, True)
     b += RESID64_B + vp + d["iters_p"] * (CG_OP_B + CG_UPDATE_B + vp) + AXPY_B
-    b += RESID64_B + vphi + d["iters_phi"] * (CG_OP_CQ_B + CG_UPDATE_B + vphi) + AXPY_B
+    if d["iters_phi"] == 0:      # the potential by the direct (diagonalised) solve
+        b += DIRECT_POTENTIAL_B
+    else:
+        b += RESID64_B + vphi + d["iters_phi"] * (CG_OP_CQ_B + CG_UPDATE_B + vphi) + AXPY_B
     for it, rounds in ((d["iters_T"], d["rounds_T"]), (d["iters_omega"], d["rounds_omega"])):
         b += RESID64_B + rounds * ROUND_B + it * INNER_ITER_B
     return b

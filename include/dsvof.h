@@ -161,6 +161,13 @@ typedef struct ds_diagnostics {
  *     enqueues its expected inner iterations and takes one host convergence
  *     test, and the solve's start takes none (0: the start and the inner
  *     solve are tested as well).
+ *   DSVOF_PHI_DIRECT [1]: the liquid-transport potential by the direct solve
+ *     (fast diagonalisation: DCT-II/DST-II bases along x and y, the z line
+ *     solved in the same way, FFTs in LDS) wherever the grid allows it (each
+ *     lateral axis with equal box faces, extents 4^a 2^b 3^c up to 1024, 2 nz
+ *     for a no-flux z- face); its true FP64 residual is checked, and the
+ *     multigrid CG takes over from its result should it miss tol_phi (0: the
+ *     multigrid CG always).
  *   DSVOF_GRAPHS [1]: the precision form's multigrid CG replays pairs of
  *     iterations as HIP graphs, captured on a stream of the handle's own and
  *     launched on the caller's (0: one launch at a time; same results bit
@@ -222,7 +229,8 @@ int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res);
  *                    rho_G D theta_f/h^2 per face, Dirichlet faces 2 rho_G D/h^2;
  *   DS_SYS_POTENTIAL the liquid-transport potential (interface advection,
  *                    eq. 3, with the divergence-free part of u): the pressure
- *                    operator with 1/rho = 1/dt; solved to tol_phi.
+ *                    operator with 1/rho = 1/dt; solved to tol_phi, by the
+ *                    direct solve where the grid allows it (iters 0).
  * rhs: device cell array (n doubles, read only).  x: device cell array, the
  * initial guess on entry and the solution on exit.  The solver stops on its
  * recursively updated residual, as in the step; rel_res is then the true FP64

@@ -96,7 +96,9 @@ struct ds_grid {
     int round_test = 1;           // energy and species FP32 rounds: one host test per round (0: also test the inner solve)
     int const_q = 1;              // potential's fine level: the coloured sweep takes its constant q from a register
     int graphs = 1;               // replay pairs of multigrid-CG iterations as HIP graphs
+    int phi_direct = 1;           // the liquid-transport potential by the direct (diagonalised) solve
   } tune;
+  bool fdm_ok = false;             // the grid's potential system takes the direct solve
   // Graphs of two FP32-multigrid CG iterations, keyed by what their launches
   // hold: solution and direction buffers, V-cycle output, system scale.  The
   // capture stream is the handle's own (default priority); replays go to the
@@ -771,6 +773,42 @@ int solve(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, 
   return solve(g, sys, sc, x, s, iters, res, g->prm.tol);
 }
 
+// The liquid-transport potential: x = A^-1 b with b in g->b.  By the direct
+// solve where the grid allows it (then its operator arrays come from the
+// setup's qc and diag, and the true FP64 residual is checked: iterations 0);
+// otherwise, or should that residual miss tol, the multigrid CG from there.
+// own: the setup wrote the precision form's own operator arrays of the
+// potential instead of qc and diag (the CG path only).
+int solve_potential(ds_grid* g, double* x, hipStream_t s, int* iters, double* res, double tol, bool own) {
+  const DevParams& P = g->dp;
+  const double sc = P.dt / (P.h * P.h);
+  if (g->tune.phi_direct && g->fdm_ok && !own) {
+    if (launch_fdm_solve(P, sc * (1.0 / P.dt), g->b, x, g->pd, s) == 0) {
+      Lev<double> L = g->L0;
+      L.sc = sc;
+      L.qc = g->qc;
+      L.diag = g->diag;
+      pressure_type(g, 2, L);
+      int st;
+      if ((st = init_status(g, 2, tol, g->prm.maxit, s)) != DS_OK) return st;
+      launch_resid64(L, g->b, x, g->r, g->status + 2, g->partials, g->counters + CT_SOLVE0, true, s);
+      HIPCHK(g, hipGetLastError());
+      if ((st = sync_status(g, 2, s)) != DS_OK) return st;
+      if (g->h_status[2].done == 1) {
+        *iters = 0;
+        *res = g->h_status[2].res;
+        return DS_OK;
+      }
+    }
+  }
+  g->phi_op = own;
+  const int st = solve(g, 2, sc, x, s, iters, res, tol);
+  g->phi_op = false;
+  return st;
+}
+// Does the potential take the direct solve (its setup then writes qc and diag)?
+bool potential_direct(const ds_grid* g) { return g->tune.phi_direct && g->fdm_ok; }
+
 int solve_pressure_system(ds_grid* g, hipStream_t s, int* iters, double* res) {
   const DevParams& P = g->dp;
   return solve(g, 2, P.dt / (P.h * P.h), g->p, s, iters, res);
@@ -808,13 +846,12 @@ int one_step(ds_grid* g, hipStream_t s) {
   // 3. advection of alpha1 with the divergence-free part of u^n, c and T with u^n
   if (g->prm.liquid_transport) {
     // precision form, multigrid: the potential's own operator arrays, written by its first setup only
-    const bool own = g->prm.precision == DS_PREC_MIXED && g->prm.pressure_precond == 1 && g->tune.mg32 &&
-                     mg32_supported(g->L0);
+    const bool own = !potential_direct(g) && g->prm.precision == DS_PREC_MIXED && g->prm.pressure_precond == 1 &&
+                     g->tune.mg32 && mg32_supported(g->L0);
     if (own) launch_div_setup(P, g->u, g->v, g->w, g->phi_ready ? nullptr : g->phi_qc, g->diag, g->b, s);
+    else if (potential_direct(g)) launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s);
     else launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s, f32_out(g, 2));
-    g->phi_op = own;
-    st = solve(g, 2, P.dt / (P.h * P.h), g->phi, s, &D.iters_phi, &D.res_phi, g->prm.tol_phi);
-    g->phi_op = false;
+    st = solve_potential(g, g->phi, s, &D.iters_phi, &D.res_phi, g->prm.tol_phi, own);
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
   } else {
@@ -928,7 +965,7 @@ double host_drhoG_dT(const ds_params& q, double rho_G) {
 // tiny (far-field tails of alpha reach the box faces at 1e-150 and below),
 // where the squared norms of conjugate gradients underflow; b is therefore
 // scaled by a power of two (exactly) to a maximum in [1/2, 1) and lam scaled back.
-int adj_solve(ds_grid* g, int sys, double sc, double tol, int slot, hipStream_t s, int* rc) {
+int adj_solve(ds_grid* g, int sys, double sc, double tol, int slot, hipStream_t s, int* rc, bool potential = false) {
   launch_absmax(g->b, g->n, g->partials, g->counters + CT_ADJ, g->scal + SC_ABSMAX, s);
   HIPCHK(g, hipGetLastError());
   HIPCHK(g, hipMemcpyAsync(g->h_scal + SC_ABSMAX, g->scal + SC_ABSMAX, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -942,7 +979,7 @@ int adj_solve(ds_grid* g, int sys, double sc, double tol, int slot, hipStream_t 
   launch_scale(g->b, std::ldexp(1.0, -ex), g->n, s);
   int it = 0;
   double res = 0.0;
-  const int st = solve(g, sys, sc, g->lam, s, &it, &res, tol);
+  const int st = potential ? solve_potential(g, g->lam, s, &it, &res, tol, false) : solve(g, sys, sc, g->lam, s, &it, &res, tol);
   g->adj_iters[slot] += it;
   if (st == DS_ERR_NOT_CONVERGED) *rc = st;
   else if (st != DS_OK) return st;
@@ -1000,7 +1037,7 @@ int reverse_step(ds_grid* g, const Slot& cur, const Slot& nxt, hipStream_t s, in
   if (phi) {
     launch_div_setup(P, cur.u, cur.v, cur.w, g->qc, g->diag, g->b, s);
     launch_adj_phi_rhs(P, g->A_Ul, g->b, s);
-    if ((st = adj_solve(g, 2, P.dt / (P.h * P.h), g->prm.tol_phi, 3, s, rc)) != DS_OK) return st;
+    if ((st = adj_solve(g, 2, P.dt / (P.h * P.h), g->prm.tol_phi, 3, s, rc, true)) != DS_OK) return st;
     launch_adj_phi_faces(P, g->A_Ul, g->lam, g->A_U, s);
   }
   // liquid source, redistribution, interface flux (eq. 4, S4, S1-S3)
@@ -1130,6 +1167,8 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_ROUND_TEST")) g->tune.round_test = atoi(e);
   if (const char* e = getenv("DSVOF_CONST_Q")) g->tune.const_q = atoi(e);
   if (const char* e = getenv("DSVOF_GRAPHS")) g->tune.graphs = atoi(e);
+  if (const char* e = getenv("DSVOF_PHI_DIRECT")) g->tune.phi_direct = atoi(e);
+  g->fdm_ok = fdm_supported(P) && P.n < (1LL << 29);
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {
     if (prm->pressure_precond == 1) build_hier(g->H32, nx, ny, nz, prm->h, prm->dt);
@@ -1293,9 +1332,10 @@ int ds_solve_system(ds_grid* g, int which, const double* rhs, double* x, void* s
       sc = P.rho_G * P.D / (P.h * P.h);
       break;
     default: {   // the liquid-transport potential, with the step's operator arrays
-      own_phi = g->prm.precision == DS_PREC_MIXED && g->prm.pressure_precond == 1 && g->tune.mg32 &&
-                mg32_supported(g->L0);
+      own_phi = !potential_direct(g) && g->prm.precision == DS_PREC_MIXED && g->prm.pressure_precond == 1 &&
+                g->tune.mg32 && mg32_supported(g->L0);
       if (own_phi) launch_div_setup(P, g->u, g->v, g->w, g->phi_ready ? nullptr : g->phi_qc, g->diag, g->b, s);
+      else if (potential_direct(g)) launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s);
       else launch_div_setup(P, g->u, g->v, g->w, g->qc, g->diag, g->b, s, f32_out(g, 2));
       sys = 2;
       sc = P.dt / (P.h * P.h);
@@ -1306,9 +1346,12 @@ int ds_solve_system(ds_grid* g, int which, const double* rhs, double* x, void* s
   HIPCHK(g, hipGetLastError());
   int it = 0;
   double res = 0.0;
-  g->phi_op = own_phi;
-  int st = solve(g, sys, sc, x, s, &it, &res, tol);
-  g->phi_op = false;
+  int st;
+  if (which == DS_SYS_POTENTIAL) {
+    st = solve_potential(g, x, s, &it, &res, tol, own_phi);
+  } else {
+    st = solve(g, sys, sc, x, s, &it, &res, tol);
+  }
   if (st != DS_OK && st != DS_ERR_NOT_CONVERGED) return st;
   // The residual reported is the true FP64 one of the returned x: the solvers
   // test the recursively updated residual, which drifts from b - A x when the

@@ -82,6 +82,15 @@ void launch_fill(double* x, double v, long long n, hipStream_t s);
 void launch_absmax(const double* x, long long n, double* partials, unsigned* counter, double* out, hipStream_t s);
 void launch_scale(double* x, double a, long long n, hipStream_t s);
 
+// ---- direct solve of the liquid-transport potential (k_fdm.hip)
+// The potential's matrix c_op (A_x + A_y + A_z) (unit second differences with
+// the pressure's box faces) is diagonalised by DCT-II / DST-II bases.  Needs
+// each lateral axis with equal faces (walls or phi = 0), phi = 0 at z+, and
+// extents 4^a 2^b 3^c (2 nz for z with a no-flux z- face) of at most 1024.
+bool fdm_supported(const DevParams& P);
+// x = A^-1 b in five passes (t: scratch cell array); -1 if not supported.
+int launch_fdm_solve(const DevParams& P, double c_op, const double* b, double* x, double* t, hipStream_t s);
+
 // ---- adjoint kernels (k_adjoint.hip), in the order of the reverse step
 void launch_adj_project(const DevParams& P, const double* a_new, const double* p, double* const AU[3], double* b,
                         double* A_ab, double* partials, unsigned* counter, double* grad, hipStream_t s);

@@ -6,7 +6,8 @@
 * Properties at 256^3 in the benchmark's launch configuration (precision
   form, multigrid): fuel mass conserved to 1e-10 per step, the liquid budget
   closes, and div u = mdot (1/rho_G - 1/rho_L) to the solve tolerance.
-* d^2 law on the GPU path (equal to the oracle step for step) at R/h = 8, 16.
+* d^2 law on the GPU path (equal to the oracle step for step): 300 K at R/h = 4, 8, 16;
+  360 K convergence (first order, Richardson-extrapolated rate and slope within 5%).
 * The largest configuration (384^3): fuel mass, liquid budget, convergence.
 * Literal species form at 256^3: the liquid assignment, adj and raw source
   against the oracle on the sub-block; the fuel balance without a vapour
@@ -200,7 +201,11 @@ def test_c3_literal_species_fuel_balance_in_bench_configuration():
         assert d["converged"] == 1 and d["mdot_total"] > 0
 
 
-def _d2_gpu(n, T, tend):
+def _d2_gpu(n, T, tend, t_fit=None):
+    """d^2-law case on the GPU path: (R^2 of the linear fit of d_eq^2 over
+    t >= t_fit (default: the second half), slope / quasi-steady slope, mean
+    instantaneous rate / quasi-steady rate over the fit window, last such
+    rate, alpha_max, liquid mass that left the box)."""
     ds = _lib()
     from tests.d2_case import d2_case
     prm, ref = d2_case(n, T=T)
@@ -208,6 +213,7 @@ def _d2_gpu(n, T, tend):
     g.set_fields(W.initial_fields(prm, D0=ref["D0"]))
     steps = int(tend / prm["dt"])
     t, dd, rate = [], [], []
+    BL = 0.0
     for k in range(steps):
         g.step(1)
         d = g.diagnostics()
@@ -215,31 +221,100 @@ def _d2_gpu(n, T, tend):
         dd.append((6.0 * d["volume"] / math.pi) ** (2.0 / 3.0))
         a = (3.0 * d["volume"] / (4.0 * math.pi)) ** (1.0 / 3.0)
         rate.append(d["mdot_total"] / ref["mdot_qs"](a))
-    t, dd = np.array(t), np.array(dd)
-    half = steps // 2
-    A = np.polyfit(t[half:], dd[half:], 1)
-    resid = dd[half:] - np.polyval(A, t[half:])
-    R2 = 1.0 - resid.var() / dd[half:].var()
-    a_mid = 0.5 * math.sqrt(dd[3 * steps // 4])
+        BL += d["B_L"]
+    t, dd, rate = np.array(t), np.array(dd), np.array(rate)
+    sel = t >= (0.5 * tend if t_fit is None else t_fit)
+    A = np.polyfit(t[sel], dd[sel], 1)
+    resid = dd[sel] - np.polyval(A, t[sel])
+    R2 = 1.0 - resid.var() / dd[sel].var()
+    a_mid = 0.5 * math.sqrt(dd[sel][len(dd[sel]) // 2])
     slope_ratio = -A[0] / (ref["Kd2"] * ref["box_ratio"](a_mid))
-    return R2, slope_ratio, rate[-1], d["alpha_max"]
+    return R2, slope_ratio, float(rate[sel].mean()), float(rate[-1]), d["alpha_max"], BL
 
 
-def test_d2_law_gpu_resolution():
-    """300 K (B = 0.33): slope and rate within 6% at R/h = 8 and 16.
-    360 K (B = 9.5, Stefan-flow dominated): the rate approaches the
-    quasi-steady value as the droplet is resolved (monotone, > 0.75 at R/h = 16)."""
-    res = {}
-    for n in (64, 128):
+def test_d2_law_gpu_resolution_300K():
+    """300 K (B = 0.33): d^2 linear in time (R^2 >= 0.999), slope and rate
+    within 6% of the capacitance-corrected quasi-steady value at R/h = 8 and
+    16.  R/h = 4 (the oracle's own d^2 pin, at 32^3) is run and printed: its
+    error sets that pin's bar."""
+    for n in (32, 64, 128):
         print(f"d2 300 K n={n}", flush=True)
-        R2, sr, rr, amax = _d2_gpu(n, 300.0, 0.08)
-        print(n, R2, sr, rr, amax)
-        assert R2 >= 0.999 and abs(sr - 1) < 0.06 and abs(rr - 1) < 0.06 and amax > 0.99
+        R2, sr, rm, rr, amax, BL = _d2_gpu(n, 300.0, 0.08)
+        print(f"R/h={n // 8}: R2 {R2:.6f} slope/qs {sr:.4f} rate/qs {rr:.4f} (window mean {rm:.4f}) "
+              f"alpha_max {amax:.4f} B_L {BL:.2e}", flush=True)
+        assert R2 >= 0.999
+        if n >= 64:
+            assert abs(sr - 1) < 0.06 and abs(rr - 1) < 0.06 and amax > 0.99
+
+
+def test_d2_law_gpu_convergence_360K():
+    """360 K (B = 9.5, Stefan-flow dominated), the survey's isothermal d^2
+    case, fitted over 8-18 ms: after the start-up (the rate is flat to 2% from
+    8 ms on at every resolution) and before the diffuse tail of alpha, carried
+    outward on the gas side of the band, reaches the box faces (from 20-30 ms
+    on; liquid then leaves the box).  d^2 is linear (R^2 >= 0.999); the errors
+    of the slope and of the window-mean rate fall at first order per halving
+    of h (observed order >= 0.8 on the finest pair), and their Richardson
+    extrapolations (first order: 2 q(h/2) - q(h)) lie within 5% of the
+    capacitance-corrected quasi-steady values."""
+    res = {}
     for n in (32, 64, 128):
         print(f"d2 360 K n={n}", flush=True)
-        R2, sr, rr, amax = _d2_gpu(n, 360.0, 0.03)
-        res[n] = rr
-        print(n, R2, sr, rr, amax)
-        # 30 ms is still inside the initial transient at this B: linear to 0.5%
-        assert R2 >= 0.995 and amax > 0.98
-    assert res[32] < res[64] < res[128] and res[128] > 0.75
+        R2, sr, rm, rr, amax, BL = _d2_gpu(n, 360.0, 0.018, t_fit=0.008)
+        res[n] = (sr, rm)
+        print(f"R/h={n // 8}: R2 {R2:.6f} slope/qs {sr:.4f} rate/qs window mean {rm:.4f} (last {rr:.4f}) "
+              f"alpha_max {amax:.4f} B_L {BL:.2e}", flush=True)
+        assert R2 >= 0.999 and amax > 0.98
+        assert BL <= 1e-6 * (684.0 * math.pi / 6.0 * 1e-9)     # (almost) no liquid has left the box
+    for i, name in ((0, "slope"), (1, "rate")):
+        e = {n: 1.0 - res[n][i] for n in res}
+        order = math.log2(e[64] / e[128])
+        ext = 2.0 * res[128][i] - res[64][i]
+        print(f"{name}: errors {e[32]:.4f} {e[64]:.4f} {e[128]:.4f}, observed orders "
+              f"{math.log2(e[32] / e[64]):.3f} {order:.3f}, Richardson {ext:.4f}")
+        assert e[32] > e[64] > e[128] > 0
+        assert order >= 0.8
+        assert abs(ext - 1.0) < 0.05
+
+
+def test_c3_precision_form_200_steps_at_full_size():
+    """The 256^3 workload (20 bar, Peng-Robinson, natural convection) for its
+    full 200 steps of 5e-6 s at the configuration tolerance (1e-10), in the
+    launch configuration bench.py times: the precision form (FP32 sweeps,
+    FP64 refinement) against the all-FP64 GPU step.  The droplet volume must
+    agree to 1e-6 relative; every field's relative difference (2-norm and
+    element-wise) is printed.  The FP64 GPU step is itself the oracle's step
+    to 1e-9 per step (test_gpu_parity); the oracle is too slow to run 200
+    steps at this size on the host."""
+    ds = _lib()
+    prm, run = W.config("C3")
+    f = W.initial_fields(prm, **run)
+    out, vol, diag = {}, {}, {}
+    for prec in (W.PREC_FP64, W.PREC_MIXED):
+        print(f"256^3 C3: 200 steps, precision {prec}", flush=True)
+        g = ds.Grid(dict(prm, precision=prec))
+        g.set_fields(f)
+        for chunk in range(4):
+            g.step(50)
+            d = g.diagnostics()
+            print(f"  step {50 * (chunk + 1)}: volume {d['volume']:.12e} iters T/omega/p/phi "
+                  f"{d['iters_T']}/{d['iters_omega']}/{d['iters_p']}/{d['iters_phi']}", flush=True)
+            assert d["converged"] == 1
+        vol[prec] = g.droplet_volume()
+        diag[prec] = g.diagnostics()
+        out[prec] = {k: v.cpu() for k, v in g.get_fields().items()}
+        del g
+        torch.cuda.empty_cache()
+    rel = abs(vol[W.PREC_MIXED] - vol[W.PREC_FP64]) / vol[W.PREC_FP64]
+    a, b = out[W.PREC_MIXED], out[W.PREC_FP64]
+    for k in ("alpha", "T", "omega", "p", "u", "v", "w"):
+        d2 = float(torch.linalg.vector_norm(a[k] - b[k]) / torch.linalg.vector_norm(b[k]))
+        dm = float((a[k] - b[k]).abs().max() / b[k].abs().max())
+        print(f"  {k}: relative difference precision form vs FP64: 2-norm {d2:.3e}, max {dm:.3e}")
+    print("droplet volume FP64", vol[W.PREC_FP64], "precision form", vol[W.PREC_MIXED], "relative", rel)
+    V0 = prm["h"] ** 3 * float(f["alpha"].sum())
+    print("volume change over the run", (vol[W.PREC_FP64] - V0) / V0)
+    assert rel <= 1e-6
+    for prec in diag:
+        d = diag[prec]
+        assert abs(d["fuel_mass"] - d["fuel_mass_before"] + d["B_L"] + d["B_v"]) <= 1e-10 * d["fuel_mass_before"]

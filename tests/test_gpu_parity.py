@@ -47,14 +47,17 @@ def _relx(a, b):
     return max(_rel(a, b), _rel_max(a, b))
 
 
-def _compare(g_fields, st, where, tol=TOL):
+def _compare(g_fields, st, where, tol=TOL, tol_max=None):
     """Every field within tol relative, both in the 2-norm and element by
     element (max |a - b| <= tol max |b|), so errors confined to small-magnitude
-    regions (the alpha band, omega near the droplet, faces at walls) show."""
-    errs = {}
+    regions (the alpha band, omega near the droplet, faces at walls) show.
+    tol_max: per-field element-wise bars where a case needs its own."""
+    errs, bad = {}, {}
     for k in FIELDS:
-        errs[k] = max(_rel(g_fields[k], st[k]), _rel_max(g_fields[k], st[k]))
-    bad = {k: e for k, e in errs.items() if not e <= tol}
+        e2, em = _rel(g_fields[k], st[k]), _rel_max(g_fields[k], st[k])
+        errs[k] = max(e2, em)
+        if not (e2 <= tol and em <= (tol_max or {}).get(k, tol)):
+            bad[k] = (e2, em)
     assert not bad, f"{where}: {bad} (all: {errs})"
     return errs
 
@@ -66,7 +69,7 @@ def _grid_params(name="C1", n=(17, 19, 23), L=None, **kw):
     return prm, run
 
 
-def _run_both(prm, fields, steps, tol_solve=1e-13, check_each=True):
+def _run_both(prm, fields, steps, tol_solve=1e-13, check_each=True, tol_max=None):
     ds = _lib()
     prm = dict(prm, tol=tol_solve, tol_phi=tol_solve)
     print(f"case nx={prm['nx']} ny={prm['ny']} nz={prm['nz']} bc={prm['bc_mode']} eq={prm['eq_model']} "
@@ -80,7 +83,7 @@ def _run_both(prm, fields, steps, tol_solve=1e-13, check_each=True):
         st, d = S.step(st, prm)
         gd = g.diagnostics()
         if check_each or n == steps - 1:
-            e = _compare(g.get_fields(), st, f"step {n}")
+            e = _compare(g.get_fields(), st, f"step {n}", tol_max=tol_max)
             for k, v in e.items():
                 worst[k] = max(worst.get(k, 0.0), v)
             assert gd["n_interface"] == d["n_interface"], (gd["n_interface"], d["n_interface"])
@@ -293,7 +296,9 @@ def test_neumann_preconditioner_same_solution_fewer_iterations(monkeypatch, prec
         out[nm] = (g.get_fields(), g.diagnostics())
         del g
     for k in FIELDS:
-        assert _relx(out[1][0][k], out[0][0][k]) <= 1e-11, k
+        # two solvers each converged to 1e-13: kappa tol apart (2-norm, and 10x that element-wise)
+        assert _rel(out[1][0][k], out[0][0][k]) <= 1e-11, k
+        assert _rel_max(out[1][0][k], out[0][0][k]) <= 1e-10, k
     d0, d1 = out[0][1], out[1][1]
     print("iterations T/omega, Jacobi:", d0["iters_T"], d0["iters_omega"], "Neumann:", d1["iters_T"], d1["iters_omega"])
     assert d1["iters_omega"] < d0["iters_omega"] and d1["iters_T"] <= d0["iters_T"]
@@ -448,7 +453,15 @@ def test_step_parity_degenerate_inputs(n, fill, form):
     f = W.random_fields(prm, seed=21)
     if fill is not None:
         f["alpha"] = np.full_like(f["alpha"], fill)
-    _run_both(prm, f, steps=2)
+    # all liquid: theta sits at its floor 1e-8 in every cell, so the species system's
+    # diagonal is 1e8 times smaller than in gas and omega = c/(rho_G theta) magnifies the
+    # rounding of c 1e8-fold cell by cell; omega and c (the conserved variable, compared
+    # below) get an element-wise bar of 1e-8, the 2-norm keeps 1e-9
+    full = fill == 1.0
+    g, st, _ = _run_both(prm, f, steps=2, tol_max={"omega": 1e-8} if full else None)
+    ds = _lib()
+    c = g.internal(ds.FIELD_C)
+    assert _rel(c, st["c"]) <= TOL and _rel_max(c, st["c"]) <= (1e-8 if full else TOL)
 
 
 def test_constant_coefficient_sweep_matches_the_loading_sweep(monkeypatch):
@@ -459,6 +472,7 @@ def test_constant_coefficient_sweep_matches_the_loading_sweep(monkeypatch):
     (DSVOF_CONST_Q=0): equal potential iteration counts, fields within 1e-13."""
     ds = _lib()
     monkeypatch.setenv("DSVOF_MG_RB_MINPLANES", "1")
+    monkeypatch.setenv("DSVOF_PHI_DIRECT", "0")       # the potential by its multigrid CG
     prm, run = W.config("C1", precision=W.PREC_MIXED)
     f = W.initial_fields(prm, **run)
     out = []
@@ -472,8 +486,10 @@ def test_constant_coefficient_sweep_matches_the_loading_sweep(monkeypatch):
             its.append(g.diagnostics()["iters_phi"])
         out.append((g.get_fields(), its))
     assert out[0][1] == out[1][1], (out[0][1], out[1][1])
+    assert out[0][1][-1] > 0           # the multigrid CG ran (the first step starts from rest: no work)
     for k in FIELDS:
-        assert _relx(out[0][0][k], out[1][0][k]) <= 1e-13, k
+        assert _rel(out[0][0][k], out[1][0][k]) <= 1e-13, k
+        assert _rel_max(out[0][0][k], out[1][0][k]) <= 1e-12, k
 
 
 def test_step_parity_round_tests_on_the_host(monkeypatch):
@@ -496,3 +512,13 @@ def test_step_parity_forced_convection_64cubed():
     d = g.diagnostics()
     print("worst relative errors over 20 steps:", worst, "max |w|", float(st["w"].abs().max()))
     assert d["mdot_total"] > 0 and float(st["w"].abs().max()) >= 0.5
+
+
+@pytest.mark.parametrize("mode", [W.BC_NATURAL, W.BC_FORCED, W.BC_FARFIELD])
+def test_step_parity_direct_potential_grid(mode):
+    """A ragged grid whose extents the potential's direct solve takes
+    (24x32x18), random droplet state with flow, 3 steps against the oracle."""
+    prm, _ = _grid_params(n=(24, 32, 18), L=24 * 1.25e-4, bc_mode=mode, w_in=0.2 if mode == W.BC_FORCED else 0.0)
+    f = W.random_fields(prm, seed=21)
+    g, st, worst = _run_both(prm, f, steps=3)
+    assert g.diagnostics()["iters_phi"] == 0

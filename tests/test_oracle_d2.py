@@ -8,10 +8,17 @@ instantaneous rate, match the classical quasi-steady Stefan result
 where C_box/C_inf is the capacitance of the sphere in the grounded cube
 (tests/golden/cube_capacitance.json, an independent Laplace solve).
 
-At 32^3 (R/h = 4) the diffuse interface costs a few percent (the
-volume-equivalent radius of the 1.5-cell tanh profile exceeds the alpha = 1/2
-radius); the bar is 12%.  The GPU path, equal to the oracle to 1e-9 per step,
-checks the same law at 64^3-128^3 with tighter bars."""
+Bar at 32^3 (R/h = 4): 10%.  The run gives slope and rate 0.922 and 0.913
+of the quasi-steady values; the same step on the GPU (equal to the oracle to
+1e-9 per step) gives errors below 1% at R/h = 8 and 3% at R/h = 16
+(tests/test_gpu_fullsize.py), so the 8-9% here is the discretisation error of
+the coarsest grid (the diffuse tanh profile spans most of the radius), and the
+bar sits 1.3 points above it.  What the bar catches: D, rho_G or the gradient
+distance off by 15% or more, the capacitance correction dropped (24%
+here), a lost factor in the redistribution.  At B = 0.33 the Stefan-flow term
+changes the rate by only ln(1+B)/B = 0.86, inside the bar: that term is
+pinned by the 360 K case (B = 9.5, a factor 4) on the GPU path at 32^3-128^3,
+whose steps are the oracle's."""
 import math
 
 import numpy as np
@@ -44,5 +51,5 @@ def test_d2_law_oracle_32cubed():
     K_expect = ref["Kd2"] * ref["box_ratio"](a_mid)
     print("R2", R2, "slope/K", -A[0] / K_expect, "rate/qs", rate[-1])
     assert R2 >= 0.999
-    assert abs(-A[0] / K_expect - 1.0) < 0.12
-    assert abs(rate[-1] - 1.0) < 0.12
+    assert abs(-A[0] / K_expect - 1.0) < 0.10
+    assert abs(rate[-1] - 1.0) < 0.10
