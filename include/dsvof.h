@@ -103,6 +103,8 @@ typedef struct ds_params {
   int pressure_precond; /* 0: Jacobi-PCG, 1: geometric-multigrid PCG */
   int liquid_transport; /* 1: alpha moves with the divergence-free part of u (default); 0: with u */
   int species_form;    /* DS_SPECIES_* */
+  int viscous;         /* 1: implicit viscous momentum, div mu (grad v + grad v^T) of eqs. 5 and 30 (0: mu = 0) */
+  double mu_L, mu_G;   /* liquid and gas dynamic viscosity [Pa s], mixed by eq. 31 (used with viscous = 1) */
 } ds_params;
 
 /* Scalars of the most recent step (or evaporation/pressure call). */
@@ -123,6 +125,8 @@ typedef struct ds_diagnostics {
   int iters_phi;         /* iterations of the liquid-transport potential solve */
   double res_phi;
   int rounds_T, rounds_omega;   /* FP32 rounds of the energy and species solves (precision form; 0 in FP64) */
+  int iters_visc;        /* iterations of the implicit viscous solve (viscous = 1) */
+  double res_visc;
 } ds_diagnostics;
 
 /* Validate parameters and create a host handle for an nx*ny*nz grid
@@ -345,8 +349,9 @@ int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t
  * the run again (as after ds_forward_record).  DS_ERR_STATE without a
  * recorded run; DS_ERR_NOT_CONVERGED if an adjoint solve hit maxit (results
  * are still written); DS_ERR_NONFINITE for a non-finite gradient.  The
- * adjoint covers the conservative species form: ds_forward_record returns
- * DS_ERR_ARG for a grid created with DS_SPECIES_LITERAL.
+ * adjoint covers the conservative species form of the inviscid step:
+ * ds_forward_record returns DS_ERR_ARG for a grid created with
+ * DS_SPECIES_LITERAL or with viscous = 1.
  * Synchronises the stream. */
 int ds_adjoint(ds_grid* g, double dJ_dV, double* grads, double* dalpha0, double* dT0, double* domega0,
                double* du0, double* dv0, double* dw0, void* stream);

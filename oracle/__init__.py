@@ -12,6 +12,7 @@ Modules, in the order of the paper's segregated step (Section 3.1):
   vof        -- Section 2.1 (eqs. 3-4) with a flux-limited face interpolation
   operators  -- implicit diffusion / pressure operators and a Jacobi PCG
   momentum   -- Section 2.2 and 2.6 (eqs. 6, 7, 28-30): predictor, projection
+  viscous    -- eqs. 5 and 30: the implicit viscous part of the predictor
   step       -- the whole step and its diagnostics
 
 All floating point is torch.float64 on the CPU.

@@ -15,7 +15,8 @@ Order (the six steps of Section 3.1):
   2. alpha source      alpha1 = alpha - dt mdot/rho_L          (eq. 4)
   3. advection         vof.advect                              (eq. 3)
   4. properties        eq. 31 on alpha' clamped to [0, 1]; theta = max(1-alpha', theta_min)
-  5. energy, species (operators) and momentum predictor (momentum)
+  5. energy, species (operators) and momentum predictor (momentum; with
+     viscous = 1 its implicit viscous part, viscous.py)
   6. pressure (eq. 7) and velocity correction
 Species conservation reading: vapour lives in the gas fraction only; c is
 moved with the gas volume flux, gains mdot, and is updated after the
@@ -34,7 +35,7 @@ from __future__ import annotations
 
 import torch
 
-from . import interface, momentum, operators, thermo, vof
+from . import interface, momentum, operators, thermo, viscous, vof
 
 
 def to_state(fields, prm, rho_G=None):
@@ -146,8 +147,12 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
         B_diff = B_diff + (Ka[0] * oa[0]).sum() + (Ka[-1] * oa[-1]).sum()
     B_v = B_v + dt * h ** 3 * B_diff
     omega_new = c_new / (rho_G * theta)
-    # 5c. momentum predictor
+    # 5c. momentum predictor (and its implicit viscous part, eqs. 5 and 30)
     Us = momentum.predictor(U, ab, rho, prm)
+    if prm.get("viscous", 0):
+        Us, it_visc, ok_visc = viscous.implicit_viscosity(Us, U, ab, rho, prm, tol, solve)
+    else:
+        it_visc, ok_visc = [0, 0, 0], True
     # 6. pressure and correction
     beta = 1.0 / rho
     opP = operators.pressure_operator(beta, prm)
@@ -165,8 +170,8 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
         fuel_mass_before=float(vol * (prm["rho_L"] * st_in["alpha"] + st_in["c"]).sum()),
         alpha_min=float(alpha_p.min()), alpha_max=float(alpha_p.max()),
         n_interface=0 if geo is None else int(geo["icells"].shape[0]),
-        iters=dict(T=itT, omega=itS, p=itP), res=dict(T=resT, omega=resS, p=resP),
-        converged=bool(okT and okS and okP),
+        iters=dict(T=itT, omega=itS, p=itP, visc=it_visc), res=dict(T=resT, omega=resS, p=resP),
+        converged=bool(okT and okS and okP and ok_visc),
     )
     if record is not None:
         record.update(mdot=mdot, mraw=mraw, K=K, geo=geo, alpha1=alpha1, alpha_p=alpha_p, c_p=c_p,

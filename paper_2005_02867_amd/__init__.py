@@ -48,7 +48,8 @@ class Params(C.Structure):
         ("tol", C.c_double), ("tol_phi", C.c_double),
         ("s_max", C.c_int), ("maxit", C.c_int), ("eq_model", C.c_int), ("bc_mode", C.c_int),
         ("precision", C.c_int), ("solve_energy", C.c_int), ("evaporation", C.c_int), ("pressure_precond", C.c_int),
-        ("liquid_transport", C.c_int), ("species_form", C.c_int),
+        ("liquid_transport", C.c_int), ("species_form", C.c_int), ("viscous", C.c_int),
+        ("mu_L", C.c_double), ("mu_G", C.c_double),
     ]
 
 
@@ -61,6 +62,7 @@ class Diagnostics(C.Structure):
         ("iters_T", C.c_int), ("iters_omega", C.c_int), ("iters_p", C.c_int),
         ("n_interface", C.c_int), ("converged", C.c_int), ("refinements_p", C.c_int),
         ("iters_phi", C.c_int), ("res_phi", C.c_double), ("rounds_T", C.c_int), ("rounds_omega", C.c_int),
+        ("iters_visc", C.c_int), ("res_visc", C.c_double),
     ]
 
 
@@ -114,8 +116,10 @@ def make_params(prm: dict) -> Params:
     for name, ctype in Params._fields_:
         if name in ("pressure_precond", "liquid_transport"):
             val = prm.get(name, 1)
-        elif name == "species_form":
+        elif name in ("species_form", "viscous"):
             val = prm.get(name, 0)
+        elif name in ("mu_L", "mu_G"):
+            val = prm.get(name, 0.0)
         elif name == "eps_gas":
             val = prm.get(name, prm["eps_int"])
         elif name == "tol_phi":

@@ -75,6 +75,8 @@ struct ds_grid {
   double* zj = nullptr;            // Jacobi z = r/diag (FP64 solves)
   float* zj32 = nullptr;           // the same for the FP32 rounds
   double* r_alt = nullptr;         // second residual buffer of the Neumann-preconditioned solves
+  ViscVecs visc{};                 // implicit viscous solve (viscous = 1): vectors over the faces [u | v | w]
+  int batch_visc = 4;
   float* r32alt = nullptr;
   int dirmask = 0;                 // p_rgh = 0 box faces
   int batch_p[2] = {4, 4};         // pressure, then any other pressure-type system (phi, adjoints)
@@ -223,6 +225,11 @@ size_t carve(ds_grid* g, char* base) {
   g->phi = L.take<double>(base, n);
   g->zj = L.take<double>(base, n);
   g->r_alt = L.take<double>(base, n);
+  if (g->prm.viscous) {
+    const long long nf = visc_faces(g->dp);
+    double** vv[6] = {&g->visc.x, &g->visc.b, &g->visc.d, &g->visc.r, &g->visc.p, &g->visc.q};
+    for (double** v : vv) *v = L.take<double>(base, nf);
+  }
   // FP64 multigrid levels (level 0 uses qc/diag of the pressure system)
   MgHier<double>& H = g->H64;
   H.lev[0].qc = g->qc;
@@ -830,6 +837,36 @@ int evaporation_source(ds_grid* g, hipStream_t s) {
   return DS_OK;
 }
 
+// Implicit viscous momentum on (us, vs, ws) in place (eqs. 5 and 30), with
+// alpha' in a_new: Jacobi-PCG over the concatenated faces, batches of
+// iterations between host convergence tests (the status slot of the energy
+// solve, which is done by then).
+int viscous_solve(ds_grid* g, const double* a_new, hipStream_t s, int* iters, double* res) {
+  const DevParams& P = g->dp;
+  SolveStatus* ss = g->status + 0;
+  int st;
+  if ((st = init_status(g, 0, g->prm.tol, g->prm.maxit, s)) != DS_OK) return st;
+  launch_visc_start(P, a_new, g->us, g->vs, g->ws, g->u, g->v, g->w, g->visc, ss, g->partials,
+                    g->counters + CT_SOLVE1, s);
+  HIPCHK(g, hipGetLastError());
+  g->h_status[0].done = 0;
+  bool first = true;
+  while (!g->h_status[0].done) {
+    const int m = batch_size(g->batch_visc, first);
+    first = false;
+    for (int t = 0; t < m; ++t) launch_visc_iteration(P, a_new, g->visc, ss, g->partials, g->counters + CT_SOLVE1, s);
+    HIPCHK(g, hipGetLastError());
+    if ((st = sync_status(g, 0, s)) != DS_OK) return st;
+  }
+  launch_visc_store(P, g->visc, g->us, g->vs, g->ws, s);
+  HIPCHK(g, hipGetLastError());
+  const SolveStatus& h = g->h_status[0];
+  g->batch_visc = std::max(2, std::min(256, h.it));
+  *iters = h.it;
+  *res = h.res;
+  return h.done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
+}
+
 int read_scalars(ds_grid* g, hipStream_t s) {
   HIPCHK(g, hipMemcpyAsync(g->h_scal, g->scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(g, hipStreamSynchronize(s));
@@ -881,8 +918,16 @@ int one_step(ds_grid* g, hipStream_t s) {
   else if (st != DS_OK) return st;
   launch_species_update(P, g->a_new, g->c_new, g->mdot, g->om_new, g->u, g->v, g->w, g->c, g->omega,
                         g->partials, g->counters + CT_SPEC, g->scal, s);
-  // 5c. momentum predictor with alpha'
+  // 5c. momentum predictor with alpha' (and its implicit viscous part)
   launch_predictor(P, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, s);
+  if (P.viscous) {
+    st = viscous_solve(g, g->a_new, s, &D.iters_visc, &D.res_visc);
+    if (st == DS_ERR_NOT_CONVERGED) rc = st;
+    else if (st != DS_OK) return st;
+  } else {
+    D.iters_visc = 0;
+    D.res_visc = 0.0;
+  }
   // 6. pressure (warm start p^n) and correction
   launch_pressure_setup(P, g->a_new, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s, f32_out(g, 2));
   st = solve_pressure_system(g, s, &D.iters_p, &D.res_p);
@@ -1069,7 +1114,9 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
       prm->eq_model < 0 || prm->eq_model > 1 || prm->bc_mode < 0 || prm->bc_mode > 2 ||
       prm->precision < 0 || prm->precision > 1 || !finite_pos(prm->r_fib) || prm->pressure_precond < 0 ||
       prm->pressure_precond > 1 || prm->liquid_transport < 0 || prm->liquid_transport > 1 ||
-      prm->species_form < 0 || prm->species_form > 1)
+      prm->species_form < 0 || prm->species_form > 1 || prm->viscous < 0 || prm->viscous > 1 ||
+      (prm->viscous && (!(prm->mu_L >= 0.0) || !(prm->mu_G >= 0.0) || !std::isfinite(prm->mu_L) ||
+                        !std::isfinite(prm->mu_G))))
     return DS_ERR_ARG;
   if (prm->eq_model == DS_EQ_PENG_ROBINSON &&
       (!finite_pos(prm->Tc) || !finite_pos(prm->Pc) || !finite_pos(prm->Tc_G) || !finite_pos(prm->Pc_G)))
@@ -1123,6 +1170,9 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   P.solve_energy = prm->solve_energy;
   P.evaporation = prm->evaporation;
   P.species_form = prm->species_form;
+  P.viscous = prm->viscous;
+  P.mu_L = prm->mu_L;
+  P.mu_G = prm->mu_G;
   // gas density, eq. 24, for the ambient gas at (T_amb, p)
   const double Z = prm->eq_model == DS_EQ_PENG_ROBINSON
                        ? host_pr_Z(prm->T_amb, prm->p, prm->Tc_G, prm->Pc_G, prm->acentric_G)
@@ -1284,6 +1334,14 @@ int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res) {
   int st;
   if ((st = evaporation_source(g, s)) != DS_OK) return st;
   launch_predictor(P, g->alpha, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, s);
+  if (P.viscous) {
+    int itv = 0;
+    double resv = 0.0;
+    st = viscous_solve(g, g->alpha, s, &itv, &resv);
+    if (st != DS_OK && st != DS_ERR_NOT_CONVERGED) return st;
+    g->diag_out.iters_visc = itv;
+    g->diag_out.res_visc = resv;
+  }
   launch_pressure_setup(P, g->alpha, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s);
   int it = 0;
   double res = 0.0;
@@ -1535,6 +1593,7 @@ int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t
   if (nsteps < 1 || ckpt_every < 1 || !tape) return fail(g, DS_ERR_ARG, "nsteps and ckpt_every must be >= 1, tape non-null");
   if (g->prm.species_form != DS_SPECIES_CONSERVATIVE)
     return fail(g, DS_ERR_ARG, "the adjoint covers the conservative species form only");
+  if (g->prm.viscous) return fail(g, DS_ERR_ARG, "the adjoint covers the inviscid step only");
   const int C = std::min(ckpt_every, nsteps);
   const size_t need = tape_total_bytes(g, nsteps, C);
   if (tape_bytes < need) return fail(g, DS_ERR_ARG, "tape too small: %zu < %zu bytes", tape_bytes, need);

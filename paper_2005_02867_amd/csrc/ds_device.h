@@ -27,6 +27,8 @@ struct DevParams {
   int kind[6];                      // box face kinds, index axis*2 + side
   int eq_model, solve_energy, evaporation;
   int species_form;                 // 0 conservative, 1 literal (saturated liquid, central gradient at adj)
+  int viscous;                      // 1: implicit viscous momentum (mu_L, mu_G mixed by eq. 31)
+  double mu_L, mu_G;
 };
 
 // Status of one iterative solve, updated on the device.

@@ -91,6 +91,24 @@ bool fdm_supported(const DevParams& P);
 // x = A^-1 b in five passes (t: scratch cell array); -1 if not supported.
 int launch_fdm_solve(const DevParams& P, double c_op, const double* b, double* x, double* t, hipStream_t s);
 
+// ---- implicit viscous momentum (k_visc.hip)
+// Work vectors of the viscous solve, each over the concatenated faces
+// [u | v | w] (visc_faces entries).
+struct ViscVecs {
+  double *x, *b, *d, *r, *p, *q;
+};
+long long visc_faces(const DevParams& P);
+// x = (u*, v*, w*), right-hand side and diagonal, r = b - A x, p = r/d and
+// the status (bnorm, rz, residual, done) of the solve.
+void launch_visc_start(const DevParams& P, const double* a_new, const double* us, const double* vs, const double* ws,
+                       const double* u, const double* v, const double* w, const ViscVecs& X, SolveStatus* st,
+                       double* partials, unsigned* counter, hipStream_t s);
+// One Jacobi-PCG iteration (three launches; each returns at once after convergence).
+void launch_visc_iteration(const DevParams& P, const double* a_new, const ViscVecs& X, SolveStatus* st,
+                           double* partials, unsigned* counter, hipStream_t s);
+// The interior faces of x back into u*, v*, w*.
+void launch_visc_store(const DevParams& P, const ViscVecs& X, double* us, double* vs, double* ws, hipStream_t s);
+
 // ---- adjoint kernels (k_adjoint.hip), in the order of the reverse step
 void launch_adj_project(const DevParams& P, const double* a_new, const double* p, double* const AU[3], double* b,
                         double* A_ab, double* partials, unsigned* counter, double* grad, hipStream_t s);

@@ -522,3 +522,31 @@ def test_step_parity_direct_potential_grid(mode):
     f = W.random_fields(prm, seed=21)
     g, st, worst = _run_both(prm, f, steps=3)
     assert g.diagnostics()["iters_phi"] == 0
+
+
+@pytest.mark.parametrize("mode", [W.BC_NATURAL, W.BC_FORCED, W.BC_FARFIELD])
+def test_step_parity_viscous(mode):
+    """Implicit viscous momentum (div mu (grad v + grad v^T) of eqs. 5 and 30,
+    mu mixed by eq. 31): the ragged 17x19x23 grid with a random droplet state
+    and flow, 3 steps against the oracle in the three boundary modes."""
+    prm, _ = _grid_params(n=(17, 19, 23), L=17 * 1.25e-4, bc_mode=mode, w_in=0.2 if mode == W.BC_FORCED else 0.0,
+                          viscous=1)
+    f = W.random_fields(prm, seed=31)
+    g, st, worst = _run_both(prm, f, steps=3)
+    d = g.diagnostics()
+    print("viscous iterations", d["iters_visc"], "residual", d["res_visc"])
+    assert d["iters_visc"] > 0 and d["res_visc"] <= 1e-13
+
+
+def test_step_parity_viscous_precision_form_32cubed():
+    """The 32^3 configuration with viscosity in the precision form (the viscous
+    solve itself FP64), 5 steps against the oracle; the adjoint rejects the
+    viscous step."""
+    ds = _lib()
+    prm, run = W.config("C1", viscous=1, precision=W.PREC_MIXED)
+    f = W.initial_fields(prm, **run)
+    g, st, worst = _run_both(prm, f, steps=5)
+    print("worst relative errors over 5 steps:", worst)
+    with pytest.raises(ds.DSError) as e:
+        g.forward_record(2, 1)
+    assert e.value.code == ds.DS_ERR_ARG

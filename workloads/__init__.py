@@ -49,6 +49,9 @@ _BASE = dict(
     eq_model=EQ_IDEAL, bc_mode=BC_NATURAL, precision=PREC_FP64,
     solve_energy=1, evaporation=1,
     pressure_precond=1, liquid_transport=1, species_form=0,
+    # viscous momentum (off in the configurations, which give no viscosity):
+    # n-heptane near 300 K and nitrogen near 773 K (Sutherland's law)
+    viscous=0, mu_L=3.9e-4, mu_G=3.4e-5,
 )
 
 # name -> (overrides, run description)
