@@ -73,28 +73,41 @@ __device__ __forceinline__ Cx cispi(double x) {
 // gives the DCT-II: even elements first, odd ones reversed at the end.
 __device__ __forceinline__ int reorder(int n, int N) { return (n & 1) ? N - 1 - (n >> 1) : (n >> 1); }
 
+// Twiddle tables in LDS, filled once per workgroup: W[j] = e^{-2 pi i j/N}
+// (the FFT's) and H[k] = e^{-i pi k/(2N)} (the DCT's pre/post factors).
+__device__ __forceinline__ void fill_tables(Cx* W, Cx* H, int N) {
+  for (int j = threadIdx.x; j < N; j += FDM_NT) {
+    W[j] = cispi(-2.0 * (double)j / (double)N);
+    H[j] = cispi(-(double)j / (2.0 * N));
+  }
+}
+__device__ __forceinline__ Cx conjc(Cx a) { return {a.re, -a.im}; }
+
 // In-LDS FFTs of `lines` complex lines of length pl.n held in a (line-major);
 // b is scratch of the same size.  SIGN -1: forward, +1: inverse (unscaled).
 // Returns the buffer holding the result.  Stockham autosort: pass with radix
 // r after sub-transforms of length p: butterfly i (k = i mod p) reads
-// x[i + q n/r], q < r, multiplies by e^{SIGN 2 pi i q k/(p r)}, takes the
-// length-r DFT and writes y[(i - k) r + k + q p].
+// x[i + q n/r], q < r, multiplies by e^{SIGN 2 pi i q k/(p r)} (entry
+// q k n/(p r) of the table W, conjugated for the inverse), takes the length-r
+// DFT and writes y[(i - k) r + k + q p].
 template <int SIGN>
-__device__ Cx* fft_lds(Cx* a, Cx* b, int lines, const FftPlan& pl) {
+__device__ Cx* fft_lds(Cx* a, Cx* b, int lines, const FftPlan& pl, const Cx* W) {
   const int n = pl.n;
   int p = 1;
   for (int s = 0; s < pl.nr; ++s) {
     const int r = pl.r[s];
     const int m = n / r;
+    const int step = n / (p * r);   // table stride of one unit of k
     for (int t = threadIdx.x; t < lines * m; t += FDM_NT) {
       const int line = t / m, i = t - line * m;
       const int k = i % p;
       const Cx* x = a + line * n;
       Cx* y = b + line * n;
       const int j = (i - k) * r + k;
-      const double ang = (double)(SIGN * 2 * k) / (double)(p * r);   // twiddle angle / pi
+      const int e1 = k * step;
+      auto tw = [&](int e) { return SIGN < 0 ? W[e] : conjc(W[e]); };
       if (r == 4) {
-        const Cx w1 = cispi(ang), w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+        const Cx w1 = tw(e1), w2 = tw(2 * e1), w3 = tw(3 * e1);
         const Cx u0 = x[i], u1 = cmul(x[i + m], w1), u2 = cmul(x[i + 2 * m], w2), u3 = cmul(x[i + 3 * m], w3);
         const Cx s02 = cadd(u0, u2), d02 = csub(u0, u2), s13 = cadd(u1, u3), d13 = cmuli(csub(u1, u3), (double)SIGN);
         y[j] = cadd(s02, s13);
@@ -102,11 +115,11 @@ __device__ Cx* fft_lds(Cx* a, Cx* b, int lines, const FftPlan& pl) {
         y[j + 2 * p] = csub(s02, s13);
         y[j + 3 * p] = csub(d02, d13);
       } else if (r == 2) {
-        const Cx u0 = x[i], u1 = cmul(x[i + m], cispi(ang));
+        const Cx u0 = x[i], u1 = cmul(x[i + m], tw(e1));
         y[j] = cadd(u0, u1);
         y[j + p] = csub(u0, u1);
       } else {   // r == 3
-        const Cx w1 = cispi(ang), w2 = cmul(w1, w1);
+        const Cx w1 = tw(e1), w2 = tw(2 * e1);
         const Cx u0 = x[i], u1 = cmul(x[i + m], w1), u2 = cmul(x[i + 2 * m], w2);
         const Cx s12 = cadd(u1, u2);
         // e^{SIGN 2 pi i/3} = -1/2 + SIGN i sqrt(3)/2
@@ -130,25 +143,25 @@ __device__ Cx* fft_lds(Cx* a, Cx* b, int lines, const FftPlan& pl) {
 // 1: imaginary) of the complex line whose FFT is Z (length N):
 // V = (Z[k] + conj Z[N-k])/2 (comp 0) or (Z[k] - conj Z[N-k])/(2i) (comp 1);
 // C[k] = Re(V e^{-i pi k/(2N)}).
-__device__ __forceinline__ double dct_coef(const Cx* Z, int k, int N, int comp) {
+__device__ __forceinline__ double dct_coef(const Cx* Z, int k, int N, int comp, const Cx* H) {
   const Cx a = Z[k], b = Z[k == 0 ? 0 : N - k];
   Cx V;
   if (comp == 0) V = {0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
   else V = {0.5 * (a.im + b.im), -0.5 * (a.re - b.re)};
-  const Cx w = cispi(-(double)k / (2.0 * N));
+  const Cx w = H[k];
   return V.re * w.re - V.im * w.im;
 }
 
 // Packed inverse spectrum: from the DCT-II coefficients C1, C2 of two real
 // lines (R holds them line-major), Z[k] = V1[k] + i V2[k] with
 // V[k] = e^{i pi k/(2N)} (C[k] - i C[N-k]), V[0] = C[0].
-__device__ __forceinline__ Cx packed_inverse(const double* C1, const double* C2, int k, int N) {
+__device__ __forceinline__ Cx packed_inverse(const double* C1, const double* C2, int k, int N, const Cx* H) {
   Cx V1, V2;
   if (k == 0) {
     V1 = {C1[0], 0.0};
     V2 = {C2[0], 0.0};
   } else {
-    const Cx w = cispi((double)k / (2.0 * N));
+    const Cx w = conjc(H[k]);
     V1 = {w.re * C1[k] + w.im * C1[N - k], w.im * C1[k] - w.re * C1[N - k]};
     V2 = {w.re * C2[k] + w.im * C2[N - k], w.im * C2[k] - w.re * C2[N - k]};
   }
@@ -183,6 +196,9 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_lateral(FdmLat A, const double* 
   constexpr int L = FDM_LAT_LINES, P = L / 2;
   Cx* bufa = lds;
   Cx* bufb = lds + P * N;
+  Cx* W = lds + 2 * P * N;
+  Cx* H = W + N;
+  fill_tables(W, H, N);
   const int o = blockIdx.x / A.nzc, kc = blockIdx.x - o * A.nzc;
   const int k0 = kc * L;
   const long long base = (long long)o * A.so + k0;
@@ -195,11 +211,11 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_lateral(FdmLat A, const double* 
       slot[kk & 1] = v;
     }
     __syncthreads();
-    const Cx* Z = fft_lds<-1>(bufa, bufb, P, A.pl);
+    const Cx* Z = fft_lds<-1>(bufa, bufb, P, A.pl, W);
     for (int e = threadIdx.x; e < N * L; e += FDM_NT) {
       const int k = e / L, kk = e - k * L;
       if (k0 + kk >= A.nz) continue;
-      const double c = dct_coef(Z + (kk >> 1) * N, k, N, kk & 1);
+      const double c = dct_coef(Z + (kk >> 1) * N, k, N, kk & 1, H);
       dst[base + (long long)(A.dst ? N - 1 - k : k) * A.sline + kk] = c;
     }
   } else {
@@ -212,10 +228,10 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_lateral(FdmLat A, const double* 
     __syncthreads();
     for (int e = threadIdx.x; e < N * P; e += FDM_NT) {
       const int line = e / N, k = e - line * N;
-      bufa[line * N + k] = packed_inverse(R + 2 * line * N, R + (2 * line + 1) * N, k, N);
+      bufa[line * N + k] = packed_inverse(R + 2 * line * N, R + (2 * line + 1) * N, k, N, H);
     }
     __syncthreads();
-    const Cx* z = fft_lds<1>(bufa, bufb, P, A.pl);
+    const Cx* z = fft_lds<1>(bufa, bufb, P, A.pl, W);
     const double inv = 1.0 / N;
     for (int e = threadIdx.x; e < N * L; e += FDM_NT) {
       const int n = e / L, kk = e - n * L;
@@ -249,6 +265,9 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z(FdmZ A, double* __restrict__ x
   const int M = A.M, nz = A.nz, L = A.lines, P = L / 2;
   Cx* bufa = lds;
   Cx* bufb = lds + P * M;
+  Cx* W = lds + 2 * P * M;
+  Cx* H = W + M;
+  fill_tables(W, H, M);
   const long long l0 = (long long)blockIdx.x * L;
   const int nl = (int)(A.nlines - l0 < L ? A.nlines - l0 : L);
   double* line0 = x + l0 * nz;
@@ -272,7 +291,7 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z(FdmZ A, double* __restrict__ x
     }
   }
   __syncthreads();
-  const Cx* Z = fft_lds<-1>(bufa, bufb, P, A.pl);
+  const Cx* Z = fft_lds<-1>(bufa, bufb, P, A.pl, W);
   // R = coefficients divided by the eigenvalue sums, in the DCT-II order of the
   // inverse (C'[m] = S[M-1-m] / eigenvalue of DST mode M-1-m)
   double* R = reinterpret_cast<double*>(Z == bufa ? bufb : bufa);
@@ -283,18 +302,18 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z(FdmZ A, double* __restrict__ x
       const long long L_ = l0 + line;
       const int i = (int)(L_ / A.ny), j = (int)(L_ - (long long)i * A.ny);
       const double sig = lam(i, A.nx, A.dstx) + lam(j, A.ny, A.dsty) + lam(M - 1 - m, M, 1);
-      v = dct_coef(Z + (line >> 1) * M, m, M, line & 1) * A.scale / sig;
+      v = dct_coef(Z + (line >> 1) * M, m, M, line & 1, H) * A.scale / sig;
     }
     R[line * M + m] = v;
   }
   __syncthreads();
-  Cx* W = const_cast<Cx*>(Z);
+  Cx* Wb = const_cast<Cx*>(Z);
   for (int e = threadIdx.x; e < P * M; e += FDM_NT) {
     const int pr = e / M, k = e - pr * M;
-    W[pr * M + k] = packed_inverse(R + 2 * pr * M, R + (2 * pr + 1) * M, k, M);
+    Wb[pr * M + k] = packed_inverse(R + 2 * pr * M, R + (2 * pr + 1) * M, k, M, H);
   }
   __syncthreads();
-  const Cx* z = fft_lds<1>(W, reinterpret_cast<Cx*>(R), P, A.pl);
+  const Cx* z = fft_lds<1>(Wb, reinterpret_cast<Cx*>(R), P, A.pl, W);
   const double inv = 1.0 / M;
   const int off = A.mirror ? nz : 0;
   for (int e = threadIdx.x; e < nl * nz; e += FDM_NT) {
@@ -349,10 +368,10 @@ FdmGeometry geometry(const DevParams& P, double c_op) {
   // LDS: two complex buffers of the packed lines
   const size_t lmax = 160 * 1024;
   az.lines = 16;
-  while (az.lines > 2 && (size_t)az.lines * az.M * sizeof(Cx) > lmax) az.lines /= 2;
-  G.lds_z = (size_t)az.lines * az.M * sizeof(Cx);
-  G.lds_lat_x = (size_t)FDM_LAT_LINES * ax.N * sizeof(Cx);
-  G.lds_lat_y = (size_t)FDM_LAT_LINES * ay.N * sizeof(Cx);
+  while (az.lines > 2 && (size_t)(az.lines + 2) * az.M * sizeof(Cx) > lmax) az.lines /= 2;
+  G.lds_z = (size_t)(az.lines + 2) * az.M * sizeof(Cx);   // two buffers of lines/2 complex lines, two tables
+  G.lds_lat_x = (size_t)(FDM_LAT_LINES + 2) * ax.N * sizeof(Cx);
+  G.lds_lat_y = (size_t)(FDM_LAT_LINES + 2) * ay.N * sizeof(Cx);
   if (G.lds_z > lmax || G.lds_lat_x > lmax || G.lds_lat_y > lmax) return G;
   G.ax = ax;
   G.ay = ay;
