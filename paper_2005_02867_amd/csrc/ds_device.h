@@ -15,6 +15,14 @@ constexpr int MAX_RED = 8;          // values per block partial
 
 enum BoxKind { WALL = 0, INLET = 1, OPEN = 2, FARFIELD = 3 };
 
+// Tiles of the marching stencil kernels: MZ z (one wavefront) by MY y rows,
+// marching along x over chunks of xlen planes; nzb x nyb tiles per chunk.
+constexpr int MZ = 64, MY = 4;
+struct MarchGeom {
+  int nzb, nyb, xlen;
+  long long tiles;
+};
+
 // Parameters passed by value to every kernel.
 struct DevParams {
   int nx, ny, nz, smax;

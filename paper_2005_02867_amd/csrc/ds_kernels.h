@@ -20,6 +20,7 @@ enum Counter { CT_IFACE = 0, CT_ADV, CT_SPEC, CT_DIAG, CT_SOLVE0, CT_SOLVE1, CT_
 enum Grad { GR_D = 0, GR_DH, GR_TAMB, GR_RHOG, GR_S1B, GR_S2B, GR_COUNT };
 
 int grid_blocks(long long n);   // streaming grid size (multiple of 8)
+MarchGeom march_geom(const DevParams& P, int& blocks);   // tiles and grid of the marching kernels
 
 // FP32 copies of an assembled operator for the precision form, written by the
 // setup kernels next to the FP64 ones (q null: none).  d: the FP32 diagonal,

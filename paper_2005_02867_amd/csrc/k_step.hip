@@ -19,6 +19,25 @@ int grid_blocks(long long n) {
   return (int)nb;
 }
 
+// Tiles of the marching kernels: x chunks of at least 8 planes, as many as
+// keep the tile count near MAX_BLOCKS; blocks walk the tiles grid-stride
+// (a multiple of NXCD, at most MAX_BLOCKS, so per-block partials fit).
+MarchGeom march_geom(const DevParams& P, int& blocks) {
+  MarchGeom G;
+  G.nzb = (P.nz + MZ - 1) / MZ;
+  G.nyb = (P.ny + MY - 1) / MY;
+  const long long yz = (long long)G.nzb * G.nyb;
+  long long nxc = std::max(1LL, MAX_BLOCKS / yz);
+  nxc = std::min(nxc, std::max(1LL, (long long)(P.nx + 7) / 8));
+  G.xlen = (int)((P.nx + nxc - 1) / nxc);
+  nxc = (P.nx + G.xlen - 1) / G.xlen;
+  G.tiles = yz * nxc;
+  long long nb = std::min<long long>(G.tiles, MAX_BLOCKS);
+  nb = (nb + NXCD - 1) / NXCD * NXCD;
+  blocks = (int)std::min<long long>(nb, MAX_BLOCKS);
+  return G;
+}
+
 // ---------------------------------------------------------------- potential
 // xi = xi0 (Df/2) / max(r, r_fib) at cell centres (eq. 29), centre x0.
 __global__ void k_xi(DevParams P, double* xi) {
@@ -332,55 +351,257 @@ __device__ __forceinline__ void advect_publish(const DevParams& P, double (&acc)
   }
 }
 
-// One cell per thread; every line value loaded up front from clamped positions.
-__global__ void __launch_bounds__(BLOCK)
-k_advect(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
-         const double* __restrict__ T, const double* __restrict__ c,
-         const double* __restrict__ u, const double* __restrict__ v,
-         const double* __restrict__ w, const double* __restrict__ phi, double* __restrict__ a_new,
-         double* __restrict__ c_new, double* __restrict__ T_new, double* partials,
-         unsigned* counter, double* scal) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
-  double acc[2] = {0.0, 0.0};   // outward liquid volume flux, vapour mass flux (per area)
-  const long long st[3] = {(long long)P.ny * P.nz, (long long)P.nz, 1};
-  const int nn[3] = {P.nx, P.ny, P.nz};
-  for (long long cc = b0 + threadIdx.x; cc < b1; cc += BLOCK) {
-    int i, j, k;
-    decode(P, cc, i, j, k);
-    const int pos[3] = {i, j, k};
-    const double uf[3][2] = {{u[uidx(P, i, j, k)], u[uidx(P, i + 1, j, k)]},
-                             {v[vidx(P, i, j, k)], v[vidx(P, i, j + 1, k)]},
-                             {w[widx(P, i, j, k)], w[widx(P, i, j, k + 1)]}};
-    const double A0 = a1[cc], O0 = omega[cc], T0 = T[cc];
-    const double P0 = phi ? phi[cc] : 0.0;
-    double A[3][4], O[3][4], TT[3][4], PH[3][2] = {};
-    bool h[3][4];
+// ---------------------------------------------------------------- marching tiles
+// The explicit stencil kernels march along x over tiles of MZ = 64 z (one
+// wavefront per row) by MY = 4 y rows.  Each x-plane of a tile is staged in
+// LDS once with its y/z halo, three planes in flight: the loads of plane x+3
+// are issued before plane x is computed and land in plane x's slot after it,
+// so one barrier per plane separates every slot's reads from its next
+// writes.  The x neighbours of a thread's own column ride along in registers.
+
+// Tile of a block's logical number t (z tiles fastest, then y, then x chunks).
+__device__ __forceinline__ void march_tile(const MarchGeom& G, long long t, int& x0, int& y0, int& z0) {
+  const long long q = t / G.nzb;
+  z0 = (int)(t - q * G.nzb) * MZ;
+  y0 = (int)(q % G.nyb) * MY;
+  x0 = (int)(q / G.nyb) * G.xlen;
+}
+// Logical block number: the blocks one XCD receives (round-robin dealing)
+// take consecutive numbers, so neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int march_logical() {
+  const int per = gridDim.x / NXCD;
+  return (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+}
+
+// Advection tiles: alpha1, omega, T with a halo of 2 (68 x 8), phi with 1
+// (66 x 6).  The halo ring of a tile (the entries outside the 64 x 4 centre)
+// is enumerated as: H full rows on top, H full rows at the bottom, then the
+// H columns at either end of the middle rows.
+constexpr int AHZ = MZ + 4, AHY = MY + 4, ATILE = AHZ * AHY, ARING = ATILE - MZ * MY;
+constexpr int PHZ = MZ + 2, PHY = MY + 2, PTILE = PHZ * PHY, PRING = PTILE - MZ * MY;
+
+template <int H>
+__device__ __forceinline__ void ring_entry(int e, int& r, int& c) {
+  constexpr int TZ = MZ + 2 * H, top = H * TZ;
+  if (e < top) {
+    r = e / TZ;
+    c = e - r * TZ;
+  } else if (e < 2 * top) {
+    e -= top;
+    const int q = e / TZ;
+    r = MY + H + q;
+    c = e - q * TZ;
+  } else {
+    e -= 2 * top;
+    const int q = e / (2 * H), s = e - q * (2 * H);
+    r = H + q;
+    c = s < H ? s : MZ + s;
+  }
+}
+
+// One x-plane of the advection tile in registers: the thread's own centre
+// value of each field, then its share of the halo rings.
+struct AdvPlane {
+  double cA, cO, cT, cP;
+  double rA[2], rO[2], rT[2], rP;
+};
+
+__device__ __forceinline__ void adv_fetch(const DevParams& P, const double* __restrict__ a1,
+                                          const double* __restrict__ omega, const double* __restrict__ T,
+                                          const double* __restrict__ phi, int X, int xcen, int xhalo, int y0,
+                                          int z0, bool live, long long col, AdvPlane& f) {
+  const long long plane = (long long)P.ny * P.nz;
+  const bool cin = live && X >= 0 && X < xcen;
+  const long long cg = cin ? X * plane + col : 0;
+  f.cA = cin ? a1[cg] : 0.0;
+  f.cO = cin ? omega[cg] : 0.0;
+  f.cT = cin ? T[cg] : 0.0;
+  f.cP = (cin && phi) ? phi[cg] : 0.0;
+  const bool hin = X >= 0 && X < xhalo;
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const int q = pos[ax], n = nn[ax];
-      h[ax][0] = q >= 2;
-      h[ax][1] = q >= 1;
-      h[ax][2] = q + 1 <= n - 1;
-      h[ax][3] = q + 2 <= n - 1;
-      const long long o[4] = {h[ax][0] ? -2 * st[ax] : 0, h[ax][1] ? -st[ax] : 0, h[ax][2] ? st[ax] : 0,
-                              h[ax][3] ? 2 * st[ax] : 0};
+  for (int q = 0; q < 2; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    int r = 0, c = 0;
+    if (e < ARING) ring_entry<2>(e, r, c);
+    const int gj = y0 - 2 + r, gk = z0 - 2 + c;
+    const bool in = hin && e < ARING && gj >= 0 && gj < P.ny && gk >= 0 && gk < P.nz;
+    const long long g = in ? X * plane + (long long)gj * P.nz + gk : 0;
+    f.rA[q] = in ? a1[g] : 0.0;
+    f.rO[q] = in ? omega[g] : 0.0;
+    f.rT[q] = in ? T[g] : 0.0;
+  }
+  {
+    const int e = threadIdx.x;
+    int r = 0, c = 0;
+    if (e < PRING) ring_entry<1>(e, r, c);
+    const int gj = y0 - 1 + r, gk = z0 - 1 + c;
+    const bool in = phi && hin && e < PRING && gj >= 0 && gj < P.ny && gk >= 0 && gk < P.nz;
+    f.rP = in ? phi[X * plane + (long long)gj * P.nz + gk] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void adv_store(const AdvPlane& f, double (*sF)[ATILE], double* sP, int ty, int tz) {
+  const int ce = (ty + 2) * AHZ + tz + 2;
+  sF[0][ce] = f.cA;
+  sF[1][ce] = f.cO;
+  sF[2][ce] = f.cT;
+  sP[(ty + 1) * PHZ + tz + 1] = f.cP;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        A[ax][t] = a1[cc + o[t]];
-        O[ax][t] = omega[cc + o[t]];
-        TT[ax][t] = T[cc + o[t]];
-      }
-      if (phi) {
-        PH[ax][0] = phi[cc + o[1]];
-        PH[ax][1] = phi[cc + o[2]];
-      }
+  for (int q = 0; q < 2; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    if (e < ARING) {
+      int r, c;
+      ring_entry<2>(e, r, c);
+      sF[0][r * AHZ + c] = f.rA[q];
+      sF[1][r * AHZ + c] = f.rO[q];
+      sF[2][r * AHZ + c] = f.rT[q];
     }
-    double an, cn, tn;
-    advect_cell(P, pos, uf, A0, O0, T0, P0, A, O, TT, PH, h, phi != nullptr, c[cc], acc, an, cn, tn);
-    a_new[cc] = an;
-    c_new[cc] = cn;
-    T_new[cc] = tn;
+  }
+  if (threadIdx.x < PRING) {
+    int r, c;
+    ring_entry<1>(threadIdx.x, r, c);
+    sP[r * PHZ + c] = f.rP;
+  }
+}
+
+// Face velocities and c of the thread's cell in plane X.
+struct AdvFaces {
+  double u0, u1, v0, v1, w0, w1, c;
+};
+__device__ __forceinline__ void adv_faces(const DevParams& P, const double* __restrict__ u,
+                                          const double* __restrict__ v, const double* __restrict__ w,
+                                          const double* __restrict__ c, int X, int x1, int j, int k, bool live,
+                                          AdvFaces& F) {
+  const bool in = live && X < x1;
+  const int i = in ? X : 0, jj = in ? j : 0, kk = in ? k : 0;
+  F.u0 = in ? u[uidx(P, i, jj, kk)] : 0.0;
+  F.u1 = in ? u[uidx(P, i + 1, jj, kk)] : 0.0;
+  F.v0 = in ? v[vidx(P, i, jj, kk)] : 0.0;
+  F.v1 = in ? v[vidx(P, i, jj + 1, kk)] : 0.0;
+  F.w0 = in ? w[widx(P, i, jj, kk)] : 0.0;
+  F.w1 = in ? w[widx(P, i, jj, kk + 1)] : 0.0;
+  F.c = in ? c[cidx(P, i, jj, kk)] : 0.0;
+}
+
+// Advection of alpha1, c and T (eq. 3 with the liquid-transport velocity,
+// the vapour flux and the temperature transport), marching along x.
+__global__ void __launch_bounds__(BLOCK)
+k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* __restrict__ omega,
+         const double* __restrict__ T, const double* __restrict__ c, const double* __restrict__ u,
+         const double* __restrict__ v, const double* __restrict__ w, const double* __restrict__ phi,
+         double* __restrict__ a_new, double* __restrict__ c_new, double* __restrict__ T_new, double* partials,
+         unsigned* counter, double* scal) {
+  __shared__ double sF[3][3][ATILE];   // slot (x mod 3), field (alpha1, omega, T)
+  __shared__ double sP[3][PTILE];      // slot, phi
+  const int tz = threadIdx.x % MZ, ty = threadIdx.x / MZ;
+  double acc[2] = {0.0, 0.0};   // outward liquid volume flux, vapour mass flux (per area)
+  const long long plane = (long long)P.ny * P.nz;
+  for (long long t = march_logical(); t < G.tiles; t += gridDim.x) {
+    int x0, y0, z0;
+    march_tile(G, t, x0, y0, z0);
+    const int x1 = min(x0 + G.xlen, P.nx);
+    const int xcen = min(P.nx, x1 + 2);   // own columns are read up to x1 + 1, halos up to x1 - 1
+    const int j = y0 + ty, k = z0 + tz;
+    const bool live = j < P.ny && k < P.nz;
+    const long long col = live ? (long long)j * P.nz + k : 0;
+    // x window of the own column: planes x-2 .. x+2 (phi: x-1 .. x+1 used)
+    double wA[5], wO[5], wT[5], wP[5];
+    __syncthreads();   // the previous tile's last reads of the slots
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int X = x0 - 2 + q;
+      const bool in = live && X >= 0;
+      const long long g = in ? X * plane + col : 0;
+      wA[q] = in ? a1[g] : 0.0;
+      wO[q] = in ? omega[g] : 0.0;
+      wT[q] = in ? T[g] : 0.0;
+      wP[q] = (in && phi) ? phi[g] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      AdvPlane f;
+      adv_fetch(P, a1, omega, T, phi, x0 + q, xcen, x1, y0, z0, live, col, f);
+      adv_store(f, sF[(x0 + q) % 3], sP[(x0 + q) % 3], ty, tz);
+      wA[2 + q] = f.cA;
+      wO[2 + q] = f.cO;
+      wT[2 + q] = f.cT;
+      wP[2 + q] = f.cP;
+    }
+    AdvFaces F;
+    adv_faces(P, u, v, w, c, x0, x1, j, k, live, F);
+    __syncthreads();
+    int slot = x0 % 3;
+    for (int x = x0; x < x1; ++x) {
+      AdvPlane nf;
+      adv_fetch(P, a1, omega, T, phi, x + 3, xcen, x1, y0, z0, live, col, nf);
+      AdvFaces NF;
+      adv_faces(P, u, v, w, c, x + 1, x1, j, k, live, NF);
+      if (live) {
+        const double(*S)[ATILE] = sF[slot];
+        const double* SP = sP[slot];
+        const int pos[3] = {x, j, k};
+        const double uf[3][2] = {{F.u0, F.u1}, {F.v0, F.v1}, {F.w0, F.w1}};
+        const int ce = (ty + 2) * AHZ + tz + 2;
+        double A[3][4], O[3][4], TT[3][4], PH[3][2];
+        const double* fs[3] = {wA, wO, wT};
+        double(*dst[3])[4] = {A, O, TT};
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const double* wf = fs[f];
+          dst[f][0][0] = wf[0];
+          dst[f][0][1] = wf[1];
+          dst[f][0][2] = wf[3];
+          dst[f][0][3] = wf[4];
+          dst[f][1][0] = S[f][ce - 2 * AHZ];
+          dst[f][1][1] = S[f][ce - AHZ];
+          dst[f][1][2] = S[f][ce + AHZ];
+          dst[f][1][3] = S[f][ce + 2 * AHZ];
+          dst[f][2][0] = S[f][ce - 2];
+          dst[f][2][1] = S[f][ce - 1];
+          dst[f][2][2] = S[f][ce + 1];
+          dst[f][2][3] = S[f][ce + 2];
+        }
+        const int pe = (ty + 1) * PHZ + tz + 1;
+        PH[0][0] = wP[1];
+        PH[0][1] = wP[3];
+        PH[1][0] = SP[pe - PHZ];
+        PH[1][1] = SP[pe + PHZ];
+        PH[2][0] = SP[pe - 1];
+        PH[2][1] = SP[pe + 1];
+        bool h[3][4];
+        const int nn[3] = {P.nx, P.ny, P.nz};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const int q = pos[ax], n = nn[ax];
+          h[ax][0] = q >= 2;
+          h[ax][1] = q >= 1;
+          h[ax][2] = q + 1 <= n - 1;
+          h[ax][3] = q + 2 <= n - 1;
+        }
+        double an, cn, tn;
+        advect_cell(P, pos, uf, wA[2], wO[2], wT[2], wP[2], A, O, TT, PH, h, phi != nullptr, F.c, acc, an, cn,
+                    tn);
+        const long long cc = x * plane + col;
+        a_new[cc] = an;
+        c_new[cc] = cn;
+        T_new[cc] = tn;
+      }
+      __syncthreads();   // every read of this slot is done
+      adv_store(nf, sF[slot], sP[slot], ty, tz);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        wA[q] = wA[q + 1];
+        wO[q] = wO[q + 1];
+        wT[q] = wT[q + 1];
+        wP[q] = wP[q + 1];
+      }
+      wA[4] = nf.cA;
+      wO[4] = nf.cO;
+      wT[4] = nf.cT;
+      wP[4] = nf.cP;
+      F = NF;
+      slot = slot == 2 ? 0 : slot + 1;
+    }
   }
   advect_publish(P, acc, partials, counter, scal);
 }
@@ -517,84 +738,186 @@ __global__ void k_species_update(DevParams P, const double* __restrict__ a_new, 
 }
 
 // ---------------------------------------------------------------- S9
-// Predictor on the face (i, j, k) normal to axis AX (eq. 30 / rho, mu = 0),
-// indices in that face array (extent +1 along AX).
+// Predictor on an interior face normal to AX (eq. 30 / rho, mu = 0):
+// first-order upwind advection along AX (face neighbours bn, fn), transverse
+// advection along the two other axes (ascending) with the four-point
+// averaged velocity vb and the one-sided differences to lo / hi (zero-
+// gradient ghosts already substituted), gravity on the density jump and the
+// potential force on the xi jump between the cells L and R either side.
+// (i, j, k): the face's indices in its face array.
 template <int AX>
-__device__ __forceinline__ double predictor_face(const DevParams& P, const double* __restrict__ a_new,
-                                                 const double* __restrict__ xi, const double* __restrict__ u,
-                                                 const double* __restrict__ v, const double* __restrict__ w, int i,
-                                                 int j, int k, double ih) {
-  const int fx = P.nx + (AX == 0), fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
-  (void)fx;
-  const double* F = AX == 0 ? u : (AX == 1 ? v : w);
-  const long long e = ((long long)i * fy + j) * fz + k;
-  const int fpos = AX == 0 ? i : (AX == 1 ? j : k);
-  const int nax = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
-  const double uc = F[e];
-  if (fpos == 0 || fpos == nax) {
-    const int kind = P.kind[AX * 2 + (fpos == 0 ? 0 : 1)];
-    return kind == WALL ? 0.0 : (kind == INLET ? P.w_in : uc);
-  }
-  // strides of the face array
-  const long long sx = (long long)fy * fz, sy = fz, sz = 1;
-  const long long sA = AX == 0 ? sx : (AX == 1 ? sy : sz);
-  // normal advection, first-order upwind
-  const double back = (uc - F[e - sA]) * ih, fwd = (F[e + sA] - uc) * ih;
+__device__ __forceinline__ double predictor_interior(const DevParams& P, double uc, double bn, double fn,
+                                                     const double (&vb)[2], const double (&lo)[2],
+                                                     const double (&hi)[2], double aL_, double aR_, double xiL,
+                                                     double xiR, int i, int j, int k, double ih) {
+  const double back = (uc - bn) * ih, fwd = (fn - uc) * ih;
   double adv = uc * (uc > 0.0 ? back : fwd);
-  // cells on both sides of the face
-  const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
-  // transverse advection: 4-point averaged transverse velocity, zero-gradient ghosts
 #pragma unroll
-  for (int bx = 0; bx < 3; ++bx) {
-    if (bx == AX) continue;
-    double vb;
-    if (bx == 0) {   // u averaged onto the face
-      vb = 0.25 * (u[uidx(P, iL, jL, kL)] + u[uidx(P, iL + 1, jL, kL)] + u[uidx(P, i, j, k)] + u[uidx(P, i + 1, j, k)]);
-    } else if (bx == 1) {
-      vb = 0.25 * (v[vidx(P, iL, jL, kL)] + v[vidx(P, iL, jL + 1, kL)] + v[vidx(P, i, j, k)] + v[vidx(P, i, j + 1, k)]);
-    } else {
-      vb = 0.25 * (w[widx(P, iL, jL, kL)] + w[widx(P, iL, jL, kL + 1)] + w[widx(P, i, j, k)] + w[widx(P, i, j, k + 1)]);
-    }
-    const int pb = bx == 0 ? i : (bx == 1 ? j : k);
-    const int nb_ = bx == 0 ? fx : (bx == 1 ? fy : fz);
-    const long long sb = bx == 0 ? sx : (bx == 1 ? sy : sz);
-    const double lo = pb >= 1 ? F[e - sb] : uc;
-    const double hi = pb <= nb_ - 2 ? F[e + sb] : uc;
-    const double d = (vb > 0.0 ? uc - lo : hi - uc) * ih;
-    adv += vb * d;
+  for (int q = 0; q < 2; ++q) {
+    const double d = (vb[q] > 0.0 ? uc - lo[q] : hi[q] - uc) * ih;
+    adv += vb[q] * d;
   }
-  const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
-  const double aL = clamp01(a_new[cL]), aR = clamp01(a_new[cR]);
+  const double aL = clamp01(aL_), aR = clamp01(aR_);
   const double rL = mix(aL, P.rho_L, P.rho_G), rR = mix(aR, P.rho_L, P.rho_G);
   const double bf = 0.5 * (1.0 / rL + 1.0 / rR);
   const double xf = (AX == 0 ? i : i + 0.5) * P.h - P.x0[0];
   const double yf = (AX == 1 ? j : j + 0.5) * P.h - P.x0[1];
   const double zf = (AX == 2 ? k : k + 0.5) * P.h - P.x0[2];
   const double gr = P.g[0] * xf + P.g[1] * yf + P.g[2] * zf;
-  const double force = -gr * (rR - rL) * ih * bf + 0.5 * (aL + aR) * (xi[cR] - xi[cL]) * ih;
+  const double force = -gr * (rR - rL) * ih * bf + 0.5 * (aL + aR) * (xiR - xiL) * ih;
   return uc - P.dt * adv + P.dt * force;
 }
+// Box face (side 0: low, 1: high) normal to AX: walls hold 0, the inlet w_in,
+// open and far-field faces keep u^n.
+__device__ __forceinline__ double predictor_box(const DevParams& P, int ax, int side, double uc) {
+  const int kind = P.kind[ax * 2 + side];
+  return kind == WALL ? 0.0 : (kind == INLET ? P.w_in : uc);
+}
 
-// All three face arrays in one pass over the cells: cell (i, j, k) writes the
-// faces (i, j, k) of u*, v* and w* and, on the high box faces, the face beyond.
-// The three face computations of a cell read overlapping neighbourhoods, which
-// the caches then serve once instead of three kernels streaming them apiece.
-__global__ void k_predictor(DevParams P, const double* __restrict__ a_new, const double* __restrict__ xi,
-                            const double* __restrict__ u, const double* __restrict__ v,
-                            const double* __restrict__ w, double* __restrict__ us, double* __restrict__ vs,
-                            double* __restrict__ ws) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
+// Predictor tiles: u, v, w, alpha and xi planes with a halo of 1 (66 x 6,
+// rows y0-1 .. y0+4, columns z0-1 .. z0+64); v and w keep their extra face
+// row / column in it.
+constexpr int QZ = MZ + 2, QY = MY + 2, QTILE = QZ * QY;
+constexpr int QF = 5;   // u, v, w, alpha, xi
+
+struct PredPlane {
+  double e[QF][2];
+};
+// Plane X of every field, entries threadIdx.x and threadIdx.x + BLOCK of the
+// tile (row-major); X up to xmax (u has nx + 1 planes, the others nx).
+__device__ __forceinline__ void pred_fetch(const DevParams& P, const double* __restrict__ u,
+                                           const double* __restrict__ v, const double* __restrict__ w,
+                                           const double* __restrict__ a, const double* __restrict__ xi, int X,
+                                           int xmax, int y0, int z0, PredPlane& f) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    const int r = e / QZ, c = e - r * QZ;
+    const int gj = y0 - 1 + r, gk = z0 - 1 + c;
+    const bool ok = e < QTILE && X >= 0 && X <= xmax && gj >= 0 && gk >= 0;
+    const bool cell = ok && X < P.nx && gj < P.ny && gk < P.nz;
+    const bool uin = ok && gj < P.ny && gk < P.nz;                  // X <= nx
+    const bool vin = ok && X < P.nx && gj <= P.ny && gk < P.nz;
+    const bool win = ok && X < P.nx && gj < P.ny && gk <= P.nz;
+    f.e[0][q] = uin ? u[uidx(P, X, gj, gk)] : 0.0;
+    f.e[1][q] = vin ? v[vidx(P, X, gj, gk)] : 0.0;
+    f.e[2][q] = win ? w[widx(P, X, gj, gk)] : 0.0;
+    f.e[3][q] = cell ? a[cidx(P, X, gj, gk)] : 0.0;
+    f.e[4][q] = cell ? xi[cidx(P, X, gj, gk)] : 0.0;
+  }
+}
+__device__ __forceinline__ void pred_store(const PredPlane& f, double (*S)[QTILE]) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    if (e < QTILE) {
+#pragma unroll
+      for (int fl = 0; fl < QF; ++fl) S[fl][e] = f.e[fl][q];
+    }
+  }
+}
+
+// u*, v*, w* of every face, marching along x: the thread of cell (x, j, k)
+// writes the faces (x, j, k) of the three arrays and, on the high box faces,
+// the face beyond.  Plane x and x+1 tiles give the y/z neighbours and the
+// x+1 values; the x-1 values are kept from the previous plane.
+__global__ void __launch_bounds__(BLOCK)
+k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const double* __restrict__ xi,
+            const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
+            double* __restrict__ us, double* __restrict__ vs, double* __restrict__ ws) {
+  __shared__ double sQ[3][QF][QTILE];   // slot (x mod 3), field
+  const int tz = threadIdx.x % MZ, ty = threadIdx.x / MZ;
   const double ih = 1.0 / P.h;
-  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
-    int i, j, k;
-    decode(P, c, i, j, k);
-    us[uidx(P, i, j, k)] = predictor_face<0>(P, a_new, xi, u, v, w, i, j, k, ih);
-    vs[vidx(P, i, j, k)] = predictor_face<1>(P, a_new, xi, u, v, w, i, j, k, ih);
-    ws[widx(P, i, j, k)] = predictor_face<2>(P, a_new, xi, u, v, w, i, j, k, ih);
-    if (i == P.nx - 1) us[uidx(P, P.nx, j, k)] = predictor_face<0>(P, a_new, xi, u, v, w, P.nx, j, k, ih);
-    if (j == P.ny - 1) vs[vidx(P, i, P.ny, k)] = predictor_face<1>(P, a_new, xi, u, v, w, i, P.ny, k, ih);
-    if (k == P.nz - 1) ws[widx(P, i, j, P.nz)] = predictor_face<2>(P, a_new, xi, u, v, w, i, j, P.nz, ih);
+  constexpr int FU = 0, FV = 1, FW = 2, FA = 3, FX = 4;
+  for (long long t = march_logical(); t < G.tiles; t += gridDim.x) {
+    int x0, y0, z0;
+    march_tile(G, t, x0, y0, z0);
+    const int x1 = min(x0 + G.xlen, P.nx);
+    const int j = y0 + ty, k = z0 + tz;
+    const bool live = j < P.ny && k < P.nz;
+    // plane x-1 values of the own column: u, v (j, j+1), w (k, k+1), alpha, xi
+    double pu, pv0, pv1, pw0, pw1, pa, px;
+    {
+      const bool in = live && x0 >= 1;
+      const int X = in ? x0 - 1 : 0, jj = in ? j : 0, kk = in ? k : 0;
+      pu = in ? u[uidx(P, X, jj, kk)] : 0.0;
+      pv0 = in ? v[vidx(P, X, jj, kk)] : 0.0;
+      pv1 = in ? v[vidx(P, X, jj + 1, kk)] : 0.0;
+      pw0 = in ? w[widx(P, X, jj, kk)] : 0.0;
+      pw1 = in ? w[widx(P, X, jj, kk + 1)] : 0.0;
+      pa = in ? a_new[cidx(P, X, jj, kk)] : 0.0;
+      px = in ? xi[cidx(P, X, jj, kk)] : 0.0;
+    }
+    __syncthreads();   // the previous tile's last reads of the slots
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      PredPlane f;
+      pred_fetch(P, u, v, w, a_new, xi, x0 + q, x1, y0, z0, f);
+      pred_store(f, sQ[(x0 + q) % 3]);
+    }
+    __syncthreads();
+    int slot = x0 % 3;
+    for (int x = x0; x < x1; ++x) {
+      PredPlane nf;
+      pred_fetch(P, u, v, w, a_new, xi, x + 3, x1, y0, z0, nf);
+      const int s1 = slot == 2 ? 0 : slot + 1;
+      if (live) {
+        const int ce = (ty + 1) * QZ + tz + 1;
+        auto T0 = [&](int f, int dy, int dz) { return sQ[slot][f][ce + dy * QZ + dz]; };
+        auto T1 = [&](int f, int dy, int dz) { return sQ[s1][f][ce + dy * QZ + dz]; };
+        const double uc = T0(FU, 0, 0), vc = T0(FV, 0, 0), wc = T0(FW, 0, 0);
+        const double ac = T0(FA, 0, 0), xc = T0(FX, 0, 0);
+        const double un = T1(FU, 0, 0);   // u(x+1, j, k)
+        double ru, rv, rw;
+        // u face (x, j, k)
+        if (x == 0) {
+          ru = predictor_box(P, 0, 0, uc);
+        } else {
+          const double vb[2] = {0.25 * (pv0 + pv1 + vc + T0(FV, 1, 0)), 0.25 * (pw0 + pw1 + wc + T0(FW, 0, 1))};
+          const double lo[2] = {j >= 1 ? T0(FU, -1, 0) : uc, k >= 1 ? T0(FU, 0, -1) : uc};
+          const double hi[2] = {j <= P.ny - 2 ? T0(FU, 1, 0) : uc, k <= P.nz - 2 ? T0(FU, 0, 1) : uc};
+          ru = predictor_interior<0>(P, uc, pu, un, vb, lo, hi, pa, ac, px, xc, x, j, k, ih);
+        }
+        // v face (x, j, k)
+        if (j == 0) {
+          rv = predictor_box(P, 1, 0, vc);
+        } else {
+          const double vb[2] = {0.25 * (T0(FU, -1, 0) + T1(FU, -1, 0) + uc + un),
+                                0.25 * (T0(FW, -1, 0) + T0(FW, -1, 1) + wc + T0(FW, 0, 1))};
+          const double lo[2] = {x >= 1 ? pv0 : vc, k >= 1 ? T0(FV, 0, -1) : vc};
+          const double hi[2] = {x <= P.nx - 2 ? T1(FV, 0, 0) : vc, k <= P.nz - 2 ? T0(FV, 0, 1) : vc};
+          rv = predictor_interior<1>(P, vc, T0(FV, -1, 0), T0(FV, 1, 0), vb, lo, hi, T0(FA, -1, 0), ac,
+                                     T0(FX, -1, 0), xc, x, j, k, ih);
+        }
+        // w face (x, j, k)
+        if (k == 0) {
+          rw = predictor_box(P, 2, 0, wc);
+        } else {
+          const double vb[2] = {0.25 * (T0(FU, 0, -1) + T1(FU, 0, -1) + uc + un),
+                                0.25 * (T0(FV, 0, -1) + T0(FV, 1, -1) + vc + T0(FV, 1, 0))};
+          const double lo[2] = {x >= 1 ? pw0 : wc, j >= 1 ? T0(FW, -1, 0) : wc};
+          const double hi[2] = {x <= P.nx - 2 ? T1(FW, 0, 0) : wc, j <= P.ny - 2 ? T0(FW, 1, 0) : wc};
+          rw = predictor_interior<2>(P, wc, T0(FW, 0, -1), T0(FW, 0, 1), vb, lo, hi, T0(FA, 0, -1), ac,
+                                     T0(FX, 0, -1), xc, x, j, k, ih);
+        }
+        us[uidx(P, x, j, k)] = ru;
+        vs[vidx(P, x, j, k)] = rv;
+        ws[widx(P, x, j, k)] = rw;
+        if (x == P.nx - 1) us[uidx(P, P.nx, j, k)] = predictor_box(P, 0, 1, un);
+        if (j == P.ny - 1) vs[vidx(P, x, P.ny, k)] = predictor_box(P, 1, 1, T0(FV, 1, 0));
+        if (k == P.nz - 1) ws[widx(P, x, j, P.nz)] = predictor_box(P, 2, 1, T0(FW, 0, 1));
+        pu = uc;
+        pv0 = vc;
+        pv1 = T0(FV, 1, 0);
+        pw0 = wc;
+        pw1 = T0(FW, 0, 1);
+        pa = ac;
+        px = xc;
+      }
+      __syncthreads();   // every read of this slot is done
+      pred_store(nf, sQ[slot]);
+      slot = s1;
+    }
   }
 }
 
@@ -849,8 +1172,9 @@ void launch_advect(const DevParams& P, const double* a1, const double* omega, co
                    const double* c, const double* u, const double* v, const double* w, const double* phi,
                    double* a_new, double* c_new, double* T_new, double* partials, unsigned* counter, double* scal,
                    hipStream_t s) {
-  k_advect<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a1, omega, T, c, u, v, w, phi, a_new, c_new, T_new, partials, counter,
-                                              scal);
+  int nb;
+  const MarchGeom G = march_geom(P, nb);
+  k_advect<<<nb, BLOCK, 0, s>>>(P, G, a1, omega, T, c, u, v, w, phi, a_new, c_new, T_new, partials, counter, scal);
 }
 void launch_energy_setup(const DevParams& P, const double* a_new, const double* T_prime,
                          const double* mdot, const double* u, const double* v, const double* w,
@@ -871,7 +1195,9 @@ void launch_species_update(const DevParams& P, const double* a_new, const double
 void launch_predictor(const DevParams& P, const double* a_new, const double* xi, const double* u,
                       const double* v, const double* w, double* us, double* vs, double* ws,
                       hipStream_t s) {
-  k_predictor<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, xi, u, v, w, us, vs, ws);
+  int nb;
+  const MarchGeom G = march_geom(P, nb);
+  k_predictor<<<nb, BLOCK, 0, s>>>(P, G, a_new, xi, u, v, w, us, vs, ws);
 }
 void launch_pressure_setup(const DevParams& P, const double* a_new, const double* mdot,
                            const double* us, const double* vs, const double* ws, double* qc,
