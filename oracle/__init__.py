@@ -8,6 +8,7 @@ input generators in ``workloads`` feed both sides).
 
 Modules, in the order of the paper's segregated step (Section 3.1):
   thermo     -- Section 2.5 (phase equilibrium, eqs. 22-25) and eq. 24
+  gas        -- eq. 24 per cell and eq. 7's compressibility term (variable gas)
   interface  -- Section 2.4 (evaporation flux, eqs. 12-21)
   vof        -- Section 2.1 (eqs. 3-4) with a flux-limited face interpolation
   operators  -- implicit diffusion / pressure operators and a Jacobi PCG

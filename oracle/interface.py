@@ -144,6 +144,8 @@ def raw_evaporation(alpha, T, omega, u, v, w, geo, prm, rho_G, D_v=None):
     T_int = T[ic[:, 0], ic[:, 1], ic[:, 2]]
     w_sat = thermo.saturation_omega(T_int, prm)
     w_adj = omega[aj[:, 0], aj[:, 1], aj[:, 2]]
+    if isinstance(rho_G, torch.Tensor) and rho_G.dim() == 3:   # variable gas: rho_G at adj
+        rho_G = rho_G[aj[:, 0], aj[:, 1], aj[:, 2]]
     uc, vc, wc = cell_velocity(u, v, w)
     vn = (uc[aj[:, 0], aj[:, 1], aj[:, 2]] * n[:, 0] + vc[aj[:, 0], aj[:, 1], aj[:, 2]] * n[:, 1]
           + wc[aj[:, 0], aj[:, 1], aj[:, 2]] * n[:, 2])

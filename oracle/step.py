@@ -30,18 +30,36 @@ c = rho_G theta omega_sat; the flux at adj uses a central grad(omega)
 source, the vapour entering the gas by diffusion from the saturated liquid.
 This form does not conserve the fuel mass: the liquid loses dt mdot per
 step and the assignment sets the liquid's vapour content.
+Variable-density gas (gas_density = 1, gas.py): the state also holds the
+gas density field rho_G (eq. 24 for the local mixture, consistent with
+c, T and alpha).  The interface flux and the vapour advection use the
+start-of-step rho_G^n (the vapour flux carries the face value of rho_G
+omega); after the advection (T', c') give (omega', rho_G'), which serves
+the properties (rho), the species system (m = rho_G' theta/dt, K_f =
+D (rho_G' theta)_f/h^2; the Dirichlet faces keep the ambient gas's
+2 rho_G D/h^2), the predictor and the pressure; the end of the step gives
+(omega^{n+1}, rho_G^{n+1}) from (T^{n+1}, c^{n+1}), and the pressure source
+gains -(1 - alpha') ln(rho_G^{n+1}/rho_G')/dt (eq. 7).
 """
 from __future__ import annotations
 
 import torch
 
-from . import interface, momentum, operators, thermo, viscous, vof
+from . import gas, interface, momentum, operators, thermo, viscous, vof
+
+
+def variable_gas(prm):
+    return prm.get("gas_density", 0) == 1
 
 
 def to_state(fields, prm, rho_G=None):
-    """Build the oracle state from numpy/torch initial fields (omega given)."""
+    """Build the oracle state from numpy/torch initial fields (omega given;
+    with gas_density = 1 rho_G is eq. 24 at each cell's T and omega)."""
     st = {k: torch.as_tensor(v, dtype=torch.float64).clone() for k, v in fields.items()}
-    if rho_G is None:
+    if variable_gas(prm):
+        rho_G = gas.density(st["T"], st["omega"], prm)
+        st["rho_G"] = rho_G
+    elif rho_G is None:
         rho_G = thermo.gas_density(prm)
     theta = torch.clamp(1.0 - torch.clamp(st["alpha"], 0.0, 1.0), min=prm["theta_min"])
     st["c"] = rho_G * theta * st["omega"]
@@ -59,6 +77,7 @@ def assign_liquid_saturation(st, prm, rho_G):
 
 
 def properties(alpha, prm, rho_G):
+    """eq. 31 on alpha clamped to [0, 1] (rho_G a constant or a field)."""
     ab = torch.clamp(alpha, 0.0, 1.0)
     rho = ab * prm["rho_L"] + (1.0 - ab) * rho_G
     cp = ab * prm["cp_L"] + (1.0 - ab) * prm["cp_G"]
@@ -98,8 +117,11 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     D = prm["D_v"] if D_v is None else D_v
     Ta = prm["T_amb"] if T_amb is None else T_amb
     tol = prm["tol"] if tol is None else tol
-    if rho_G is None:
-        rho_G = thermo.gas_density(prm, Ta)
+    var = variable_gas(prm)
+    if var and prm.get("species_form", 0) == 1:
+        raise NotImplementedError("the literal species form is defined for a constant gas density")
+    rho_amb = thermo.gas_density(prm, Ta) if rho_G is None else rho_G
+    rho_G = st["rho_G"] if var else rho_amb
     dt, h = prm["dt"], prm["h"]
     st_in = st
     literal = prm.get("species_form", 0) == 1
@@ -116,9 +138,16 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
         U_liq, phi, it_phi = momentum.solenoidal_part(U, prm, tol=prm["tol_phi"], solver=solve)
     else:
         U_liq, phi, it_phi = None, None, 0
-    alpha_p, c_p, T_p, B_L, B_v = vof.advect(alpha1, st["omega"], st["T"], st["c"], *U, prm, rho_G,
-                                             T_amb=Ta, advect_T=bool(prm["solve_energy"]), U_liq=U_liq)
-    # 4. properties
+    if var:   # the vapour flux carries the face value of rho_G omega
+        alpha_p, c_p, T_p, B_L, B_v = vof.advect(alpha1, rho_G * st["omega"], st["T"], st["c"], *U, prm, 1.0,
+                                                 T_amb=Ta, advect_T=bool(prm["solve_energy"]), U_liq=U_liq)
+    else:
+        alpha_p, c_p, T_p, B_L, B_v = vof.advect(alpha1, st["omega"], st["T"], st["c"], *U, prm, rho_G,
+                                                 T_amb=Ta, advect_T=bool(prm["solve_energy"]), U_liq=U_liq)
+    # 4. properties (variable gas: rho_G' from the advected T' and c')
+    if var:
+        theta_p = torch.clamp(1.0 - torch.clamp(alpha_p, 0.0, 1.0), min=prm["theta_min"])
+        _, rho_G = gas.invert(T_p, c_p / theta_p, prm)
     ab, rho, cp, k, theta = properties(alpha_p, prm, rho_G)
     diag = {}
     # 5a. energy
@@ -131,8 +160,11 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
         T_new, itT, resT, okT = st["T"], 0, 0.0, True
     # 5b. species
     mS = rho_G * theta / dt
-    KbS = 2.0 * rho_G * D / (h * h)
-    opS, _ = operators.scalar_system(mS, theta, rho_G * D / (h * h), KbS, 0.0, U, prm)
+    KbS = 2.0 * rho_amb * D / (h * h)
+    if var:
+        opS, _ = operators.scalar_system(mS, rho_G * theta, D / (h * h), KbS, 0.0, U, prm)
+    else:
+        opS, _ = operators.scalar_system(mS, theta, rho_G * D / (h * h), KbS, 0.0, U, prm)
     msrc = torch.zeros_like(mdot) if literal else mdot
     bS = c_p / dt + msrc
     omega_p = c_p / (rho_G * theta)
@@ -146,7 +178,11 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
         oa = torch.movedim(om, axis, 0)
         B_diff = B_diff + (Ka[0] * oa[0]).sum() + (Ka[-1] * oa[-1]).sum()
     B_v = B_v + dt * h ** 3 * B_diff
-    omega_new = c_new / (rho_G * theta)
+    if var:
+        omega_new, rho_new = gas.invert(T_new, c_new / theta, prm)
+        S_comp = gas.compressibility_source(ab, rho_new, rho_G, dt)
+    else:
+        omega_new = c_new / (rho_G * theta)
     # 5c. momentum predictor (and its implicit viscous part, eqs. 5 and 30)
     Us = momentum.predictor(U, ab, rho, prm)
     if prm.get("viscous", 0):
@@ -157,11 +193,15 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     beta = 1.0 / rho
     opP = operators.pressure_operator(beta, prm)
     S = mdot * (1.0 / rho_G - 1.0 / prm["rho_L"])
+    if var:
+        S = S - S_comp
     bP = S - operators.divergence(*Us, h)
     p_new, itP, resP, okP = solve(opP, bP, st["p"], tol, prm["maxit"])
     Un = momentum.project(Us, p_new, rho, prm)
 
     new = dict(alpha=alpha_p, c=c_new, omega=omega_new, T=T_new, p=p_new, u=Un[0], v=Un[1], w=Un[2])
+    if var:
+        new["rho_G"] = rho_new
     vol = h ** 3
     diag.update(
         K=float(K), mdot_total=float(vol * mdot.sum()), B_L=float(B_L), B_v=float(B_v),
@@ -176,7 +216,9 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     if record is not None:
         record.update(mdot=mdot, mraw=mraw, K=K, geo=geo, alpha1=alpha1, alpha_p=alpha_p, c_p=c_p,
                       T_p=T_p, rho=rho, theta=theta, ustar=Us, bP=bP, rho_G=rho_G,
-                      B_L_adv=B_L, B_diff=B_diff)
+                      B_L_adv=B_L, B_diff=B_diff, S=S)
+        if var:
+            record.update(S_comp=S_comp, rho_G_new=rho_new)
     return new, diag
 
 

@@ -52,6 +52,8 @@ _BASE = dict(
     # viscous momentum (off in the configurations, which give no viscosity):
     # n-heptane near 300 K and nitrogen near 773 K (Sutherland's law)
     viscous=0, mu_L=3.9e-4, mu_G=3.4e-5,
+    # 0: rho_G of the ambient gas everywhere; 1: eq. 24 per cell (variable gas)
+    gas_density=0,
 )
 
 # name -> (overrides, run description)
