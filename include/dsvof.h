@@ -65,6 +65,19 @@ enum { DS_PREC_FP64 = 0, DS_PREC_MIXED = 1 };
  * -rho_G D grad(omega).n with a central gradient (zero-gradient ghosts), and
  * the species equation (eq. 9) has no mdot source; not mass conserving. */
 enum { DS_SPECIES_CONSERVATIVE = 0, DS_SPECIES_LITERAL = 1 };
+/* Gas density (Section 2.5, eq. 24; Section 2.2, eq. 7).  AMBIENT: one value,
+ * eq. 24 for the ambient gas at (T_amb, p), in every cell.  VARIABLE: eq. 24
+ * per cell for the local fuel/N2 mixture (mole fraction from omega; Z = 1 or
+ * the Peng-Robinson root of the mixture with the equilibrium's mixing rules).
+ * The state's c and T then fix omega and rho_G (rho_G omega = c/theta); a
+ * step uses the start-of-step rho_G for the interface flux and the vapour
+ * flux (face value of rho_G omega), the advected state's rho_G' for the
+ * properties, the species system (cell coefficient rho_G' theta, Dirichlet
+ * faces at the ambient gas), the predictor and the pressure, and adds eq. 7's
+ * -(1 - alpha')(1/rho_G) D rho_G/Dt = -(1 - alpha') ln(rho_G^{n+1}/rho_G')/dt
+ * to the pressure source.  Not with the literal species form or the
+ * differentiation form. */
+enum { DS_GAS_AMBIENT = 0, DS_GAS_VARIABLE = 1 };
 
 /* Physical and numerical parameters, SI units.  Property values are constant
  * (the mixing rule of Section 2.7, eq. 31, blends liquid and gas values). */
@@ -105,6 +118,7 @@ typedef struct ds_params {
   int species_form;    /* DS_SPECIES_* */
   int viscous;         /* 1: implicit viscous momentum, div mu (grad v + grad v^T) of eqs. 5 and 30 (0: mu = 0) */
   double mu_L, mu_G;   /* liquid and gas dynamic viscosity [Pa s], mixed by eq. 31 (used with viscous = 1) */
+  int gas_density;     /* DS_GAS_*: the gas density of eq. 24 */
 } ds_params;
 
 /* Scalars of the most recent step (or evaporation/pressure call). */
@@ -117,7 +131,8 @@ typedef struct ds_diagnostics {
   double B_L, B_v;       /* liquid / vapour mass that left the box during the step [kg] */
   double alpha_min, alpha_max;
   double res_T, res_omega, res_p;   /* final relative residuals */
-  double rho_G;          /* gas density used (eq. 24) */
+  double rho_G;          /* gas density of the ambient gas (eq. 24); with DS_GAS_VARIABLE the
+                            per-cell field is DS_FIELD_RHO_G */
   int iters_T, iters_omega, iters_p;
   int n_interface;       /* interface cells with a nonzero gradient */
   int converged;         /* 1 if every solve met tol */
@@ -279,8 +294,10 @@ enum {
   DS_FIELD_USTAR = 4,      /* u faces of the momentum predictor              */
   DS_FIELD_VSTAR = 5,
   DS_FIELD_WSTAR = 6,
-  DS_FIELD_ADJ = 7         /* cells: flat index of adj (as double), -1 if none,
+  DS_FIELD_ADJ = 7,        /* cells: flat index of adj (as double), -1 if none,
                               -2 off the interface                          */
+  DS_FIELD_RHO_G = 8       /* cells: gas density of the state (eq. 24; the ambient value
+                              everywhere with DS_GAS_AMBIENT)                  */
 };
 int ds_get_internal(ds_grid* g, int which, double* dst, size_t count, void* stream);
 

@@ -23,7 +23,8 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 DS_OK, DS_ERR_ARG, DS_ERR_HIP, DS_ERR_NOT_CONVERGED, DS_ERR_NONFINITE, DS_ERR_STATE = 0, -1, -2, -3, -4, -5
-FIELD_MDOT_RAW, FIELD_MDOT, FIELD_ALPHA1, FIELD_C, FIELD_USTAR, FIELD_VSTAR, FIELD_WSTAR, FIELD_ADJ = range(8)
+(FIELD_MDOT_RAW, FIELD_MDOT, FIELD_ALPHA1, FIELD_C, FIELD_USTAR, FIELD_VSTAR, FIELD_WSTAR, FIELD_ADJ,
+ FIELD_RHO_G) = range(9)
 EXPORTS = ("ds_create_grid", "ds_destroy_grid", "ds_workspace_bytes", "ds_set_fields", "ds_get_fields",
            "ds_step", "ds_solve_pressure", "ds_evaporation_rate", "ds_droplet_volume", "ds_get_diagnostics",
            "ds_get_internal", "ds_last_error", "ds_set_kernel_timing", "ds_get_kernel_timing",
@@ -49,7 +50,7 @@ class Params(C.Structure):
         ("s_max", C.c_int), ("maxit", C.c_int), ("eq_model", C.c_int), ("bc_mode", C.c_int),
         ("precision", C.c_int), ("solve_energy", C.c_int), ("evaporation", C.c_int), ("pressure_precond", C.c_int),
         ("liquid_transport", C.c_int), ("species_form", C.c_int), ("viscous", C.c_int),
-        ("mu_L", C.c_double), ("mu_G", C.c_double),
+        ("mu_L", C.c_double), ("mu_G", C.c_double), ("gas_density", C.c_int),
     ]
 
 
@@ -116,7 +117,7 @@ def make_params(prm: dict) -> Params:
     for name, ctype in Params._fields_:
         if name in ("pressure_precond", "liquid_transport"):
             val = prm.get(name, 1)
-        elif name in ("species_form", "viscous"):
+        elif name in ("species_form", "viscous", "gas_density"):
             val = prm.get(name, 0)
         elif name in ("mu_L", "mu_G"):
             val = prm.get(name, 0.0)

@@ -76,6 +76,9 @@ struct ds_grid {
   float* zj32 = nullptr;           // the same for the FP32 rounds
   double* r_alt = nullptr;         // second residual buffer of the Neumann-preconditioned solves
   ViscVecs visc{};                 // implicit viscous solve (viscous = 1): vectors over the faces [u | v | w]
+  // variable-density gas (gas_density = 1): the state's rho_G, the advected state's rho_G', eq. 7's
+  // compressibility term and the vapour mass per gas volume rho_G omega the advection carries
+  double *rg = nullptr, *rg_p = nullptr, *scomp = nullptr, *qv = nullptr;
   int batch_visc = 4;
   float* r32alt = nullptr;
   int dirmask = 0;                 // p_rgh = 0 box faces
@@ -225,6 +228,13 @@ size_t carve(ds_grid* g, char* base) {
   g->phi = L.take<double>(base, n);
   g->zj = L.take<double>(base, n);
   g->r_alt = L.take<double>(base, n);
+  if (g->prm.gas_density) {
+    g->rg = L.take<double>(base, n);
+    g->rg_p = L.take<double>(base, n);
+    g->scomp = L.take<double>(base, n);
+    g->qv = L.take<double>(base, n);
+  }
+  g->dp.rg = g->rg;   // stages read the state's gas density unless they set their own
   if (g->prm.viscous) {
     const long long nf = visc_faces(g->dp);
     double** vv[6] = {&g->visc.x, &g->visc.b, &g->visc.d, &g->visc.r, &g->visc.p, &g->visc.q};
@@ -840,9 +850,8 @@ int evaporation_source(ds_grid* g, hipStream_t s) {
 // Implicit viscous momentum on (us, vs, ws) in place (eqs. 5 and 30), with
 // alpha' in a_new: Jacobi-PCG over the concatenated faces, batches of
 // iterations between host convergence tests (the status slot of the energy
-// solve, which is done by then).
-int viscous_solve(ds_grid* g, const double* a_new, hipStream_t s, int* iters, double* res) {
-  const DevParams& P = g->dp;
+// solve, which is done by then).  P: the stage's parameters (its gas density).
+int viscous_solve(ds_grid* g, const double* a_new, hipStream_t s, int* iters, double* res, const DevParams& P) {
   SolveStatus* ss = g->status + 0;
   int st;
   if ((st = init_status(g, 0, g->prm.tol, g->prm.maxit, s)) != DS_OK) return st;
@@ -895,11 +904,27 @@ int one_step(ds_grid* g, hipStream_t s) {
     D.iters_phi = 0;
     D.res_phi = 0.0;
   }
-  launch_advect(P, g->a1, g->omega, g->T, g->c, g->u, g->v, g->w, g->prm.liquid_transport ? g->phi : nullptr,
-                g->a_new, g->c_new, g->T_new, g->partials, g->counters + CT_ADV, g->scal, s);
+  const bool var = g->prm.gas_density == DS_GAS_VARIABLE;
+  if (var) {
+    // the vapour flux carries the face value of rho_G omega (start-of-step rho_G)
+    launch_gas_partial(P, g->omega, g->rg, g->qv, s);
+    DevParams Pa = P;
+    Pa.rho_G = 1.0;
+    Pa.rg = nullptr;
+    launch_advect(Pa, g->a1, g->qv, g->T, g->c, g->u, g->v, g->w, g->prm.liquid_transport ? g->phi : nullptr,
+                  g->a_new, g->c_new, g->T_new, g->partials, g->counters + CT_ADV, g->scal, s);
+    // rho_G' of the advected state (T', c', alpha')
+    launch_gas_invert(P, P.solve_energy ? g->T_new : g->T, g->c_new, g->a_new, g->rg_p, s);
+  } else {
+    launch_advect(P, g->a1, g->omega, g->T, g->c, g->u, g->v, g->w, g->prm.liquid_transport ? g->phi : nullptr,
+                  g->a_new, g->c_new, g->T_new, g->partials, g->counters + CT_ADV, g->scal, s);
+  }
+  // stages after the advection read rho_G' (a variable gas)
+  DevParams Pp = P;
+  if (var) Pp.rg = g->rg_p;
   // 5a. energy (warm start T')
   if (P.solve_energy) {
-    launch_energy_setup(P, g->a_new, g->T_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, s,
+    launch_energy_setup(Pp, g->a_new, g->T_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, s,
                         f32_out(g, 0));
     st = solve(g, 0, 1.0 / (P.h * P.h), g->T_new, s, &D.iters_T, &D.res_T);
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
@@ -911,17 +936,19 @@ int one_step(ds_grid* g, hipStream_t s) {
     D.rounds_T = 0;
   }
   // 5b. species (warm start omega' = c'/(rho_G theta))
-  launch_species_setup(P, g->a_new, g->c_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, g->om_new, s,
+  launch_species_setup(Pp, g->a_new, g->c_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, g->om_new, s,
                        f32_out(g, 1));
-  st = solve(g, 1, P.rho_G * P.D / (P.h * P.h), g->om_new, s, &D.iters_omega, &D.res_omega);
+  st = solve(g, 1, (var ? 1.0 : P.rho_G) * P.D / (P.h * P.h), g->om_new, s, &D.iters_omega, &D.res_omega);
   if (st == DS_ERR_NOT_CONVERGED) rc = st;
   else if (st != DS_OK) return st;
-  launch_species_update(P, g->a_new, g->c_new, g->mdot, g->om_new, g->u, g->v, g->w, g->c, g->omega,
+  launch_species_update(Pp, g->a_new, g->c_new, g->mdot, g->om_new, g->u, g->v, g->w, g->c, g->omega,
                         g->partials, g->counters + CT_SPEC, g->scal, s);
+  // a variable gas: (omega, rho_G) of the new state from (T, c), and eq. 7's compressibility term
+  if (var) launch_gas_end(P, g->T, g->c, g->a_new, g->rg_p, g->omega, g->rg, g->scomp, s);
   // 5c. momentum predictor with alpha' (and its implicit viscous part)
-  launch_predictor(P, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, s);
+  launch_predictor(Pp, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, s);
   if (P.viscous) {
-    st = viscous_solve(g, g->a_new, s, &D.iters_visc, &D.res_visc);
+    st = viscous_solve(g, g->a_new, s, &D.iters_visc, &D.res_visc, Pp);
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
   } else {
@@ -929,11 +956,12 @@ int one_step(ds_grid* g, hipStream_t s) {
     D.res_visc = 0.0;
   }
   // 6. pressure (warm start p^n) and correction
-  launch_pressure_setup(P, g->a_new, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s, f32_out(g, 2));
+  launch_pressure_setup(Pp, g->a_new, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s, f32_out(g, 2),
+                        var ? g->scomp : nullptr);
   st = solve_pressure_system(g, s, &D.iters_p, &D.res_p);
   if (st == DS_ERR_NOT_CONVERGED) rc = st;
   else if (st != DS_OK) return st;
-  launch_project(P, g->a_new, g->p, g->us, g->vs, g->ws, g->u, g->v, g->w, s);
+  launch_project(Pp, g->a_new, g->p, g->us, g->vs, g->ws, g->u, g->v, g->w, s);
   std::swap(g->alpha, g->a_new);
   // diagnostics
   launch_diagnostics(P, g->alpha, g->c, g->T, g->p, g->mdot, g->partials, g->counters + CT_DIAG, g->scal, s);
@@ -1115,6 +1143,8 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
       prm->precision < 0 || prm->precision > 1 || !finite_pos(prm->r_fib) || prm->pressure_precond < 0 ||
       prm->pressure_precond > 1 || prm->liquid_transport < 0 || prm->liquid_transport > 1 ||
       prm->species_form < 0 || prm->species_form > 1 || prm->viscous < 0 || prm->viscous > 1 ||
+      prm->gas_density < 0 || prm->gas_density > 1 ||
+      (prm->gas_density == DS_GAS_VARIABLE && prm->species_form == DS_SPECIES_LITERAL) ||
       (prm->viscous && (!(prm->mu_L >= 0.0) || !(prm->mu_G >= 0.0) || !std::isfinite(prm->mu_L) ||
                         !std::isfinite(prm->mu_G))))
     return DS_ERR_ARG;
@@ -1279,8 +1309,10 @@ int ds_set_fields(ds_grid* g, const double* alpha, const double* T, const double
   HIPCHK(g, hipMemsetAsync(g->mraw, 0, nb, s));
   HIPCHK(g, hipMemsetAsync(g->phi, 0, nb, s));
   launch_xi(g->dp, g->xi, s);
-  // conservative vapour variable c = rho_G theta omega (gas fraction only)
-  launch_c_from_omega(g->dp, g->alpha, g->omega, g->c, s);
+  // conservative vapour variable c = rho_G theta omega (gas fraction only); a variable gas takes
+  // rho_G from eq. 24 at each cell's T and omega
+  if (g->prm.gas_density) launch_gas_from_omega(g->dp, g->T, g->omega, g->alpha, g->rg, g->c, s);
+  else launch_c_from_omega(g->dp, g->alpha, g->omega, g->c, s);
   HIPCHK(g, hipGetLastError());
   g->bound = true;
   int st;
@@ -1337,7 +1369,7 @@ int ds_solve_pressure(ds_grid* g, void* stream, int* iters, double* rel_res) {
   if (P.viscous) {
     int itv = 0;
     double resv = 0.0;
-    st = viscous_solve(g, g->alpha, s, &itv, &resv);
+    st = viscous_solve(g, g->alpha, s, &itv, &resv, P);
     if (st != DS_OK && st != DS_ERR_NOT_CONVERGED) return st;
     g->diag_out.iters_visc = itv;
     g->diag_out.res_visc = resv;
@@ -1387,7 +1419,7 @@ int ds_solve_system(ds_grid* g, int which, const double* rhs, double* x, void* s
       launch_species_setup(P, g->alpha, g->c, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, nullptr, s,
                            f32_out(g, 1));
       sys = 1;
-      sc = P.rho_G * P.D / (P.h * P.h);
+      sc = (P.rg ? 1.0 : P.rho_G) * P.D / (P.h * P.h);   // a variable gas: the state's rho_G in the cell coefficient
       break;
     default: {   // the liquid-transport potential, with the step's operator arrays
       own_phi = !potential_direct(g) && g->prm.precision == DS_PREC_MIXED && g->prm.pressure_precond == 1 &&
@@ -1480,10 +1512,12 @@ int ds_get_internal(ds_grid* g, int which, double* dst, size_t count, void* stre
     case DS_FIELD_VSTAR: src = g->vs; n = (size_t)g->nv; break;
     case DS_FIELD_WSTAR: src = g->ws; n = (size_t)g->nw; break;
     case DS_FIELD_ADJ: break;
+    case DS_FIELD_RHO_G: src = g->rg; break;
     default: return fail(g, DS_ERR_ARG, "unknown internal field %d", which);
   }
   if (count != n) return fail(g, DS_ERR_ARG, "buffer holds %zu values, field has %zu", count, n);
   if (which == DS_FIELD_ADJ) launch_int_to_double(g->adj, dst, g->n, s);
+  else if (which == DS_FIELD_RHO_G && !src) launch_fill(dst, g->dp.rho_G, g->n, s);
   else HIPCHK(g, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(g, hipGetLastError());
   return DS_OK;
@@ -1594,6 +1628,7 @@ int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t
   if (g->prm.species_form != DS_SPECIES_CONSERVATIVE)
     return fail(g, DS_ERR_ARG, "the adjoint covers the conservative species form only");
   if (g->prm.viscous) return fail(g, DS_ERR_ARG, "the adjoint covers the inviscid step only");
+  if (g->prm.gas_density) return fail(g, DS_ERR_ARG, "the adjoint covers the ambient gas density only");
   const int C = std::min(ckpt_every, nsteps);
   const size_t need = tape_total_bytes(g, nsteps, C);
   if (tape_bytes < need) return fail(g, DS_ERR_ARG, "tape too small: %zu < %zu bytes", tape_bytes, need);

@@ -37,6 +37,9 @@ struct DevParams {
   int species_form;                 // 0 conservative, 1 literal (saturated liquid, central gradient at adj)
   int viscous;                      // 1: implicit viscous momentum (mu_L, mu_G mixed by eq. 31)
   double mu_L, mu_G;
+  // variable-density gas: the per-cell rho_G a stage reads (nullptr: the
+  // ambient constant rho_G everywhere)
+  const double* rg;
 };
 
 // Status of one iterative solve, updated on the device.
@@ -205,6 +208,9 @@ __device__ void block_combine(const int (&ops)[NV], const double* partials, unsi
   for (int q = 0; q < NV; ++q) out[q] = sh[0][q];
   if (threadIdx.x == 0) atomicExch(counter, 0u);
 }
+
+// Gas density of cell c: the stage's field (variable gas) or the constant.
+__device__ __forceinline__ double rho_gas(const DevParams& P, long long c) { return P.rg ? P.rg[c] : P.rho_G; }
 
 // Mixing rule of the fluid properties (eq. 31) on alpha clamped to [0, 1].
 __device__ __forceinline__ double clamp01(double a) { return fmin(fmax(a, 0.0), 1.0); }

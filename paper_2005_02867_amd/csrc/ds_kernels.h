@@ -70,7 +70,8 @@ void launch_predictor(const DevParams& P, const double* a_new, const double* xi,
                       hipStream_t s);
 void launch_pressure_setup(const DevParams& P, const double* a_new, const double* mdot,
                            const double* us, const double* vs, const double* ws, double* qc,
-                           double* diag, double* b, hipStream_t s, F32Out fo = {});
+                           double* diag, double* b, hipStream_t s, F32Out fo = {},
+                           const double* scomp = nullptr);   // scomp: variable gas's compressibility term
 void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
                     const double* vs, const double* ws, double* u, double* v, double* w,
                     hipStream_t s);
@@ -78,6 +79,14 @@ void launch_diagnostics(const DevParams& P, const double* alpha, const double* c
                         const double* p, const double* mdot, double* partials, unsigned* counter,
                         double* scal, hipStream_t s);
 void launch_c_from_omega(const DevParams& P, const double* alpha, const double* omega, double* c, hipStream_t s);
+// variable-density gas (k_gas.hip)
+void launch_gas_from_omega(const DevParams& P, const double* T, const double* omega, const double* alpha, double* rg,
+                           double* c, hipStream_t s);
+void launch_gas_partial(const DevParams& P, const double* omega, const double* rg, double* q, hipStream_t s);
+void launch_gas_invert(const DevParams& P, const double* T, const double* c, const double* alpha, double* rg,
+                       hipStream_t s);
+void launch_gas_end(const DevParams& P, const double* T, const double* c, const double* alpha, const double* rg_adv,
+                    double* omega, double* rg, double* scomp, hipStream_t s);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
 // max |x| (non-finite entries give +inf) -> *out; x *= a
 void launch_absmax(const double* x, long long n, double* partials, unsigned* counter, double* out, hipStream_t s);

@@ -206,9 +206,9 @@ __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const
           jd = -P.rho_G * P.D * (gx * nx + gy * ny + gz * nz);
         } else {
           const double wsat = mass_fraction(P, equilibrium_y(P, T[c]));
-          jd = P.rho_G * P.D * (wsat - wa) / d;
+          jd = rho_gas(P, hit) * P.D * (wsat - wa) / d;
         }
-        const double jn = jd + P.rho_G * wa * va;
+        const double jn = jd + rho_gas(P, hit) * wa * va;
         m = jn * (nrm / (2.0 * P.h));
       }
     }
@@ -271,72 +271,6 @@ __global__ void k_source(DevParams P, const double* __restrict__ alpha, const do
 }
 
 // ---------------------------------------------------------------- S5
-// Fluxes and update of one cell from its line values: A, O, TT hold alpha1,
-// omega and T at offsets -2, -1, +1, +2 along each axis (index 0..3), h whether
-// those cells exist; PH phi at -1, +1; uf the six face velocities.  The faces
-// are formed with selects (no load waits on the upwind side).
-__device__ __forceinline__ void advect_cell(const DevParams& P, const int (&pos)[3], const double (&uf)[3][2],
-                                            double A0, double O0, double T0, double P0, const double (&A)[3][4],
-                                            const double (&O)[3][4], const double (&TT)[3][4],
-                                            const double (&PH)[3][2], const bool (&h)[3][4], bool has_phi,
-                                            double cv, double (&acc)[2], double& an, double& cn, double& tn) {
-  const int nn[3] = {P.nx, P.ny, P.nz};
-  const double ih = 1.0 / P.h;
-  double da = 0.0, dc = 0.0, dT = 0.0;
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    const int q = pos[ax], n = nn[ax];
-    const bool lo_in = q > 0, hi_in = q < n - 1;
-    double F[2], G[2], H[2];
-#pragma unroll
-    for (int sd = 0; sd < 2; ++sd) {
-      const double ufv = uf[ax][sd];
-      const bool in = sd == 0 ? lo_in : hi_in;
-      // interior face: (m, a, b, p) = (-2, -1, 0, +1) below the cell, (-1, 0, +1, +2) above
-      auto face = [&](const double (&L)[4], double c0, double vel) {
-        return sd == 0 ? tvd_face(L[0], L[1], c0, L[2], h[ax][0], h[ax][2], vel)
-                       : tvd_face(L[1], c0, L[2], L[3], h[ax][1], h[ax][3], vel);
-      };
-      const double af = in ? face(A[ax], A0, ufv) : box_face(A0, 0.0, ufv, sd);
-      const double of = in ? face(O[ax], O0, ufv) : box_face(O0, 0.0, ufv, sd);
-      if (has_phi) {
-        double ul;
-        if (sd == 0)
-          ul = in ? ufv - (P0 - PH[ax][0]) * ih
-                  : (pressure_dirichlet(P.kind[ax * 2]) ? ufv - 2.0 * P0 * ih : ufv);
-        else
-          ul = in ? ufv - (PH[ax][1] - P0) * ih
-                  : (pressure_dirichlet(P.kind[ax * 2 + 1]) ? ufv + 2.0 * P0 * ih : ufv);
-        F[sd] = ul * (in ? face(A[ax], A0, ul) : box_face(A0, 0.0, ul, sd));
-      } else {
-        F[sd] = ufv * af;
-      }
-      G[sd] = P.rho_G * of * (1.0 - af) * ufv;
-      if (P.solve_energy) {
-        const double Tf = in ? face(TT[ax], T0, ufv) : box_face(T0, P.T_amb, ufv, sd);
-        H[sd] = ufv * (Tf - T0);
-      } else {
-        H[sd] = 0.0;
-      }
-    }
-    da += F[1] - F[0];
-    dc += G[1] - G[0];
-    dT += H[1] - H[0];
-    if (!lo_in) {
-      acc[0] -= F[0];
-      acc[1] -= G[0];
-    }
-    if (!hi_in) {
-      acc[0] += F[1];
-      acc[1] += G[1];
-    }
-  }
-  const double s = P.dt / P.h;
-  an = A0 - s * da;
-  cn = cv - s * dc;
-  tn = P.solve_energy ? T0 - s * dT : T0;
-}
-
 __device__ __forceinline__ void advect_publish(const DevParams& P, double (&acc)[2], double* partials,
                                                unsigned* counter, double* scal) {
   const int ops[2] = {RSUM, RSUM};
@@ -376,7 +310,11 @@ __device__ __forceinline__ int march_logical() {
 // Advection tiles: alpha1, omega, T with a halo of 2 (68 x 8), phi with 1
 // (66 x 6).  The halo ring of a tile (the entries outside the 64 x 4 centre)
 // is enumerated as: H full rows on top, H full rows at the bottom, then the
-// H columns at either end of the middle rows.
+// H columns at either end of the middle rows.  Positions outside the box
+// hold ghost values: alpha1, omega and T repeat the nearest cell of the box
+// (so the far-upwind cell of a face next to the box is the upwind cell
+// itself: first order there); phi repeats it across walls and changes sign
+// across open faces (phi = 0 half a cell outside).
 constexpr int AHZ = MZ + 4, AHY = MY + 4, ATILE = AHZ * AHY, ARING = ATILE - MZ * MY;
 constexpr int PHZ = MZ + 2, PHY = MY + 2, PTILE = PHZ * PHY, PRING = PTILE - MZ * MY;
 
@@ -399,6 +337,15 @@ __device__ __forceinline__ void ring_entry(int e, int& r, int& c) {
   }
 }
 
+// Clamp of a position into [0, n); flips the phi ghost's sign where the
+// position left the box across an open face (Dirichlet phi).
+__device__ __forceinline__ int clampi(int q, int n) { return q < 0 ? 0 : (q >= n ? n - 1 : q); }
+__device__ __forceinline__ double phi_ghost_sign(const DevParams& P, int ax, int q, int n) {
+  if (q < 0) return pressure_dirichlet(P.kind[ax * 2]) ? -1.0 : 1.0;
+  if (q >= n) return pressure_dirichlet(P.kind[ax * 2 + 1]) ? -1.0 : 1.0;
+  return 1.0;
+}
+
 // One x-plane of the advection tile in registers: the thread's own centre
 // value of each field, then its share of the halo rings.
 struct AdvPlane {
@@ -408,24 +355,28 @@ struct AdvPlane {
 
 __device__ __forceinline__ void adv_fetch(const DevParams& P, const double* __restrict__ a1,
                                           const double* __restrict__ omega, const double* __restrict__ T,
-                                          const double* __restrict__ phi, int X, int xcen, int xhalo, int y0,
-                                          int z0, bool live, long long col, AdvPlane& f) {
+                                          const double* __restrict__ phi, int X, bool want, bool want_halo,
+                                          int y0, int z0, AdvPlane& f) {
   const long long plane = (long long)P.ny * P.nz;
-  const bool cin = live && X >= 0 && X < xcen;
-  const long long cg = cin ? X * plane + col : 0;
-  f.cA = cin ? a1[cg] : 0.0;
-  f.cO = cin ? omega[cg] : 0.0;
-  f.cT = cin ? T[cg] : 0.0;
-  f.cP = (cin && phi) ? phi[cg] : 0.0;
-  const bool hin = X >= 0 && X < xhalo;
+  const int Xc = clampi(X, P.nx);
+  const double sx = phi ? phi_ghost_sign(P, 0, X, P.nx) : 0.0;
+  {
+    const int ty = threadIdx.x / MZ, tz = threadIdx.x % MZ;
+    const int gj = y0 + ty, gk = z0 + tz;   // past the box in a ragged tile: ghosts too
+    const long long g = Xc * plane + (long long)clampi(gj, P.ny) * P.nz + clampi(gk, P.nz);
+    f.cA = want ? a1[g] : 0.0;
+    f.cO = want ? omega[g] : 0.0;
+    f.cT = want ? T[g] : 0.0;
+    const double sg = phi ? sx * phi_ghost_sign(P, 1, gj, P.ny) * phi_ghost_sign(P, 2, gk, P.nz) : 0.0;
+    f.cP = (want && phi) ? sg * phi[g] : 0.0;
+  }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int e = threadIdx.x + q * BLOCK;
     int r = 0, c = 0;
     if (e < ARING) ring_entry<2>(e, r, c);
-    const int gj = y0 - 2 + r, gk = z0 - 2 + c;
-    const bool in = hin && e < ARING && gj >= 0 && gj < P.ny && gk >= 0 && gk < P.nz;
-    const long long g = in ? X * plane + (long long)gj * P.nz + gk : 0;
+    const bool in = want_halo && e < ARING;
+    const long long g = Xc * plane + (long long)clampi(y0 - 2 + r, P.ny) * P.nz + clampi(z0 - 2 + c, P.nz);
     f.rA[q] = in ? a1[g] : 0.0;
     f.rO[q] = in ? omega[g] : 0.0;
     f.rT[q] = in ? T[g] : 0.0;
@@ -435,8 +386,9 @@ __device__ __forceinline__ void adv_fetch(const DevParams& P, const double* __re
     int r = 0, c = 0;
     if (e < PRING) ring_entry<1>(e, r, c);
     const int gj = y0 - 1 + r, gk = z0 - 1 + c;
-    const bool in = phi && hin && e < PRING && gj >= 0 && gj < P.ny && gk >= 0 && gk < P.nz;
-    f.rP = in ? phi[X * plane + (long long)gj * P.nz + gk] : 0.0;
+    const bool in = phi && want_halo && e < PRING;
+    const double sg = in ? sx * phi_ghost_sign(P, 1, gj, P.ny) * phi_ghost_sign(P, 2, gk, P.nz) : 0.0;
+    f.rP = in ? sg * phi[Xc * plane + (long long)clampi(gj, P.ny) * P.nz + clampi(gk, P.nz)] : 0.0;
   }
 }
 
@@ -464,141 +416,259 @@ __device__ __forceinline__ void adv_store(const AdvPlane& f, double (*sF)[ATILE]
   }
 }
 
-// Face velocities and c of the thread's cell in plane X.
+// Face velocities and c of the thread's cell in plane X.  Cell indices are
+// clamped into the box; the face indices j, k only to the face arrays'
+// extent (the row j = ny and the lane k = nz evaluate the high box faces).
 struct AdvFaces {
-  double u0, u1, v0, v1, w0, w1, c;
+  double u0, u1, v0, v1, w0, w1, c;   // u0: carried from the plane below
+  double vx, wx;                      // the tile's extra faces: v above the last row, w above the last lane
 };
 __device__ __forceinline__ void adv_faces(const DevParams& P, const double* __restrict__ u,
                                           const double* __restrict__ v, const double* __restrict__ w,
-                                          const double* __restrict__ c, int X, int x1, int j, int k, bool live,
-                                          AdvFaces& F) {
-  const bool in = live && X < x1;
-  const int i = in ? X : 0, jj = in ? j : 0, kk = in ? k : 0;
-  F.u0 = in ? u[uidx(P, i, jj, kk)] : 0.0;
-  F.u1 = in ? u[uidx(P, i + 1, jj, kk)] : 0.0;
-  F.v0 = in ? v[vidx(P, i, jj, kk)] : 0.0;
-  F.v1 = in ? v[vidx(P, i, jj + 1, kk)] : 0.0;
-  F.w0 = in ? w[widx(P, i, jj, kk)] : 0.0;
-  F.w1 = in ? w[widx(P, i, jj, kk + 1)] : 0.0;
-  F.c = in ? c[cidx(P, i, jj, kk)] : 0.0;
+                                          const double* __restrict__ c, int X, bool want, int j, int k,
+                                          bool want_vx, bool want_wx, int y0, int z0, AdvFaces& F) {
+  const int i = clampi(X, P.nx), jc = clampi(j, P.ny), kc = clampi(k, P.nz);
+  const int jf = min(j, P.ny), jf1 = min(j + 1, P.ny), kf = min(k, P.nz), kf1 = min(k + 1, P.nz);
+  F.u1 = want ? u[uidx(P, i + 1, jc, kc)] : 0.0;
+  F.v0 = want ? v[vidx(P, i, jf, kc)] : 0.0;
+  F.v1 = want ? v[vidx(P, i, jf1, kc)] : 0.0;
+  F.w0 = want ? w[widx(P, i, jc, kf)] : 0.0;
+  F.w1 = want ? w[widx(P, i, jc, kf1)] : 0.0;
+  F.c = want ? c[cidx(P, i, jc, kc)] : 0.0;
+  // the tile's extra faces: v at row y0 + MY (lane k), w at column z0 + MZ of row y0 + lane (lanes < MY)
+  const int lane = threadIdx.x % MZ;
+  F.vx = (want && want_vx) ? v[vidx(P, i, min(y0 + MY, P.ny), kc)] : 0.0;
+  F.wx = (want && want_wx && lane < MY) ? w[widx(P, i, clampi(y0 + lane, P.ny), min(z0 + MZ, P.nz))] : 0.0;
+}
+
+// Van Leer face value on a grid line (cells m, a | b, p; face between a and b)
+// for flow in +direction (fwd) or -direction: with C the upwind, D the
+// downwind and U the far-upwind cell, C + (C - U)(D - C)/(D - U) where the
+// two differences agree in sign, else C.  The reciprocal is the hardware
+// estimate refined by two Newton steps (it is only used where D - U is a sum
+// of two same-sign differences, never zero).
+__device__ __forceinline__ double vl_face(double m, double a, double b, double p, bool fwd) {
+  const double C = fwd ? a : b, D = fwd ? b : a, U = fwd ? m : p;
+  const double num = (C - U) * (D - C), q = D - U;
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(fma(-q, r, 1.0), r, r);
+  r = fma(fma(-q, r, 1.0), r, r);
+  return num > 0.0 ? fma(num, r, C) : C;
+}
+
+// Fluxes (per unit area) through one face: the liquid volume flux F = ul
+// alpha_f(ul) with the liquid-transport velocity ul, the vapour mass flux G =
+// rho_G omega_f (1 - alpha_f) u and u T_f.  A[], O[], T[] hold the four line
+// cells m, a, b, p; box: 0 interior, 1 low box face (b inside), 2 high box
+// face (a inside): the face value is the ambient one on inflow (alpha 0,
+// omega 0, T_amb), the inside cell's on outflow.
+struct FaceFlux {
+  double F, G, uT;
+};
+__device__ __forceinline__ FaceFlux face_flux(const DevParams& P, const double (&A)[4], const double (&O)[4],
+                                              const double (&T)[4], double uf, double ul, int box) {
+  const bool fwd = uf > 0.0;
+  double af = vl_face(A[0], A[1], A[2], A[3], fwd);
+  double of = vl_face(O[0], O[1], O[2], O[3], fwd);
+  double al = af;
+  const bool fwdl = ul > 0.0;
+  if (fwdl != fwd) al = vl_face(A[0], A[1], A[2], A[3], fwdl);
+  double Tf = 0.0;
+  if (P.solve_energy) Tf = vl_face(T[0], T[1], T[2], T[3], fwd);
+  if (box) {
+    const bool inflow = box == 1 ? fwd : (uf < 0.0);
+    const bool inflow_l = box == 1 ? fwdl : (ul < 0.0);
+    const double ia = box == 1 ? A[2] : A[1], io = box == 1 ? O[2] : O[1], iT = box == 1 ? T[2] : T[1];
+    af = inflow ? 0.0 : ia;
+    of = inflow ? 0.0 : io;
+    al = inflow_l ? 0.0 : ia;
+    Tf = inflow ? P.T_amb : iT;
+  }
+  return FaceFlux{ul * al, P.rho_G * of * (1.0 - af) * uf, uf * Tf};
 }
 
 // Advection of alpha1, c and T (eq. 3 with the liquid-transport velocity,
-// the vapour flux and the temperature transport), marching along x.
+// the vapour flux and the temperature transport), marching along x.  Each
+// face is evaluated once: the x face above a cell is carried to the next
+// plane as the one below it; every thread evaluates the y and z faces below
+// its cell (dead rows and lanes past the box included, for their
+// neighbours), the last row and lane also the faces above; the faces above a
+// cell come from the neighbouring row through LDS and from the next lane by a
+// shuffle.
 __global__ void __launch_bounds__(BLOCK)
 k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* __restrict__ omega,
          const double* __restrict__ T, const double* __restrict__ c, const double* __restrict__ u,
          const double* __restrict__ v, const double* __restrict__ w, const double* __restrict__ phi,
          double* __restrict__ a_new, double* __restrict__ c_new, double* __restrict__ T_new, double* partials,
          unsigned* counter, double* scal) {
-  __shared__ double sF[3][3][ATILE];   // slot (x mod 3), field (alpha1, omega, T)
-  __shared__ double sP[3][PTILE];      // slot, phi
+  __shared__ double sF[3][3][ATILE];      // slot (x mod 3), field (alpha1, omega, T)
+  __shared__ double sP[3][PTILE];         // slot, phi
+  __shared__ double sY[3][MY + 1][MZ];   // (F, G, uT), y face row, lane
+  __shared__ double sZ[3][MY];           // (F, G, uT) of the z face above the last lane, per row
   const int tz = threadIdx.x % MZ, ty = threadIdx.x / MZ;
+  const double ih = 1.0 / P.h, s = P.dt / P.h;
   double acc[2] = {0.0, 0.0};   // outward liquid volume flux, vapour mass flux (per area)
   const long long plane = (long long)P.ny * P.nz;
+  // The tile's extra faces (the y faces above the last row, the z faces above
+  // the last lane of each row) are evaluated by one wave each, chosen by block
+  // so that the extra work spreads over the SIMDs.
+  const int wave_vx = blockIdx.x % MY, wave_wx = (blockIdx.x + 2) % MY;
   for (long long t = march_logical(); t < G.tiles; t += gridDim.x) {
     int x0, y0, z0;
     march_tile(G, t, x0, y0, z0);
     const int x1 = min(x0 + G.xlen, P.nx);
-    const int xcen = min(P.nx, x1 + 2);   // own columns are read up to x1 + 1, halos up to x1 - 1
     const int j = y0 + ty, k = z0 + tz;
     const bool live = j < P.ny && k < P.nz;
     const long long col = live ? (long long)j * P.nz + k : 0;
-    // x window of the own column: planes x-2 .. x+2 (phi: x-1 .. x+1 used)
-    double wA[5], wO[5], wT[5], wP[5];
+    // x window of the own column, planes x-1 .. x+2 (ghosts as in the tiles)
+    double wA[4], wO[4], wT[4], wP[4];
     __syncthreads();   // the previous tile's last reads of the slots
+    AdvPlane f;
+    double pA[2], pO[2], pT[2], pP[2];   // planes x0-2, x0-1 (own column only)
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int X = x0 - 2 + q;
-      const bool in = live && X >= 0;
-      const long long g = in ? X * plane + col : 0;
-      wA[q] = in ? a1[g] : 0.0;
-      wO[q] = in ? omega[g] : 0.0;
-      wT[q] = in ? T[g] : 0.0;
-      wP[q] = (in && phi) ? phi[g] : 0.0;
+      adv_fetch(P, a1, omega, T, phi, x0 - 2 + q, true, false, y0, z0, f);
+      pA[q] = f.cA;
+      pO[q] = f.cO;
+      pT[q] = f.cT;
+      pP[q] = f.cP;
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      AdvPlane f;
-      adv_fetch(P, a1, omega, T, phi, x0 + q, xcen, x1, y0, z0, live, col, f);
+    for (int q = 0; q < 3; ++q) {   // planes x0 .. x0+2
+      adv_fetch(P, a1, omega, T, phi, x0 + q, x0 + q <= x1 + 1, x0 + q < x1, y0, z0, f);
       adv_store(f, sF[(x0 + q) % 3], sP[(x0 + q) % 3], ty, tz);
-      wA[2 + q] = f.cA;
-      wO[2 + q] = f.cO;
-      wT[2 + q] = f.cT;
-      wP[2 + q] = f.cP;
+      wA[q + 1] = f.cA;
+      wO[q + 1] = f.cO;
+      wT[q + 1] = f.cT;
+      wP[q + 1] = f.cP;
     }
+    wA[0] = pA[1];
+    wO[0] = pO[1];
+    wT[0] = pT[1];
+    wP[0] = pP[1];
     AdvFaces F;
-    adv_faces(P, u, v, w, c, x0, x1, j, k, live, F);
+    adv_faces(P, u, v, w, c, x0, true, j, k, ty == wave_vx, ty == wave_wx, y0, z0, F);
+    F.u0 = u[uidx(P, x0, clampi(j, P.ny), clampi(k, P.nz))];
+    // the x face below plane x0 (cells x0-2 .. x0+1)
+    FaceFlux xlo;
+    {
+      const double ul = phi ? F.u0 - (wP[1] - wP[0]) * ih : F.u0;
+      const double A4[4] = {pA[0], pA[1], wA[1], wA[2]}, O4[4] = {pO[0], pO[1], wO[1], wO[2]},
+                   T4[4] = {pT[0], pT[1], wT[1], wT[2]};
+      xlo = face_flux(P, A4, O4, T4, F.u0, ul, x0 == 0 ? 1 : 0);
+    }
     __syncthreads();
     int slot = x0 % 3;
     for (int x = x0; x < x1; ++x) {
       AdvPlane nf;
-      adv_fetch(P, a1, omega, T, phi, x + 3, xcen, x1, y0, z0, live, col, nf);
+      adv_fetch(P, a1, omega, T, phi, x + 3, x + 3 <= x1 + 1, x + 3 < x1, y0, z0, nf);
       AdvFaces NF;
-      adv_faces(P, u, v, w, c, x + 1, x1, j, k, live, NF);
-      if (live) {
-        const double(*S)[ATILE] = sF[slot];
-        const double* SP = sP[slot];
-        const int pos[3] = {x, j, k};
-        const double uf[3][2] = {{F.u0, F.u1}, {F.v0, F.v1}, {F.w0, F.w1}};
-        const int ce = (ty + 2) * AHZ + tz + 2;
-        double A[3][4], O[3][4], TT[3][4], PH[3][2];
-        const double* fs[3] = {wA, wO, wT};
-        double(*dst[3])[4] = {A, O, TT};
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-          const double* wf = fs[f];
-          dst[f][0][0] = wf[0];
-          dst[f][0][1] = wf[1];
-          dst[f][0][2] = wf[3];
-          dst[f][0][3] = wf[4];
-          dst[f][1][0] = S[f][ce - 2 * AHZ];
-          dst[f][1][1] = S[f][ce - AHZ];
-          dst[f][1][2] = S[f][ce + AHZ];
-          dst[f][1][3] = S[f][ce + 2 * AHZ];
-          dst[f][2][0] = S[f][ce - 2];
-          dst[f][2][1] = S[f][ce - 1];
-          dst[f][2][2] = S[f][ce + 1];
-          dst[f][2][3] = S[f][ce + 2];
-        }
-        const int pe = (ty + 1) * PHZ + tz + 1;
-        PH[0][0] = wP[1];
-        PH[0][1] = wP[3];
-        PH[1][0] = SP[pe - PHZ];
-        PH[1][1] = SP[pe + PHZ];
-        PH[2][0] = SP[pe - 1];
-        PH[2][1] = SP[pe + 1];
-        bool h[3][4];
-        const int nn[3] = {P.nx, P.ny, P.nz};
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          const int q = pos[ax], n = nn[ax];
-          h[ax][0] = q >= 2;
-          h[ax][1] = q >= 1;
-          h[ax][2] = q + 1 <= n - 1;
-          h[ax][3] = q + 2 <= n - 1;
-        }
-        double an, cn, tn;
-        advect_cell(P, pos, uf, wA[2], wO[2], wT[2], wP[2], A, O, TT, PH, h, phi != nullptr, F.c, acc, an, cn,
-                    tn);
-        const long long cc = x * plane + col;
-        a_new[cc] = an;
-        c_new[cc] = cn;
-        T_new[cc] = tn;
+      adv_faces(P, u, v, w, c, x + 1, x + 1 < x1, j, k, ty == wave_vx, ty == wave_wx, y0, z0, NF);
+      const double(*S)[ATILE] = sF[slot];
+      const double* SP = sP[slot];
+      const int ce = (ty + 2) * AHZ + tz + 2, pe = (ty + 1) * PHZ + tz + 1;
+      // x face above (cells x-1 .. x+2 of the own column)
+      FaceFlux xhi;
+      {
+        const double ul = phi ? F.u1 - (wP[2] - wP[1]) * ih : F.u1;
+        xhi = face_flux(P, wA, wO, wT, F.u1, ul, x == P.nx - 1 ? 2 : 0);
       }
-      __syncthreads();   // every read of this slot is done
+      // y faces below the cell (rows j-2 .. j+1 of its column); ce_/pe_ pick
+      // the column (tile centre entry) a face is evaluated for
+      auto yface = [&](int ce_, int pe_, int r0, double vf, int fpos) {
+        const double A4[4] = {S[0][ce_ + r0 * AHZ], S[0][ce_ + (r0 + 1) * AHZ], S[0][ce_ + (r0 + 2) * AHZ],
+                              S[0][ce_ + (r0 + 3) * AHZ]};
+        const double O4[4] = {S[1][ce_ + r0 * AHZ], S[1][ce_ + (r0 + 1) * AHZ], S[1][ce_ + (r0 + 2) * AHZ],
+                              S[1][ce_ + (r0 + 3) * AHZ]};
+        const double T4[4] = {S[2][ce_ + r0 * AHZ], S[2][ce_ + (r0 + 1) * AHZ], S[2][ce_ + (r0 + 2) * AHZ],
+                              S[2][ce_ + (r0 + 3) * AHZ]};
+        const double ul = phi ? vf - (SP[pe_ + (r0 + 2) * PHZ] - SP[pe_ + (r0 + 1) * PHZ]) * ih : vf;
+        return face_flux(P, A4, O4, T4, vf, ul, fpos == 0 ? 1 : (fpos == P.ny ? 2 : 0));
+      };
+      auto zface = [&](int ce_, int pe_, int c0, double wf, int fpos) {
+        const double A4[4] = {S[0][ce_ + c0], S[0][ce_ + c0 + 1], S[0][ce_ + c0 + 2], S[0][ce_ + c0 + 3]};
+        const double O4[4] = {S[1][ce_ + c0], S[1][ce_ + c0 + 1], S[1][ce_ + c0 + 2], S[1][ce_ + c0 + 3]};
+        const double T4[4] = {S[2][ce_ + c0], S[2][ce_ + c0 + 1], S[2][ce_ + c0 + 2], S[2][ce_ + c0 + 3]};
+        const double ul = phi ? wf - (SP[pe_ + c0 + 2] - SP[pe_ + c0 + 1]) * ih : wf;
+        return face_flux(P, A4, O4, T4, wf, ul, fpos == 0 ? 1 : (fpos == P.nz ? 2 : 0));
+      };
+      const FaceFlux ylo = yface(ce, pe, -2, F.v0, j);
+      sY[0][ty][tz] = ylo.F;
+      sY[1][ty][tz] = ylo.G;
+      sY[2][ty][tz] = ylo.uT;
+      if (ty == wave_vx) {   // the y faces above the last row (its rows y0+MY-2 .. y0+MY+1)
+        const FaceFlux yh = yface((MY + 1) * AHZ + tz + 2, MY * PHZ + tz + 1, -1, F.vx, y0 + MY);
+        sY[0][MY][tz] = yh.F;
+        sY[1][MY][tz] = yh.G;
+        sY[2][MY][tz] = yh.uT;
+      }
+      // z faces below the cell (columns k-2 .. k+1); the one above comes from the next lane
+      const FaceFlux zlo = zface(ce, pe, -2, F.w0, k);
+      FaceFlux zhi = {__shfl_down(zlo.F, 1, MZ), __shfl_down(zlo.G, 1, MZ), __shfl_down(zlo.uT, 1, MZ)};
+      if (ty == wave_wx && tz < MY) {   // lane r: the z face above the last lane of row r
+        const FaceFlux zx = zface((tz + 2) * AHZ + MZ + 1, (tz + 1) * PHZ + MZ, -1, F.wx, z0 + MZ);
+        sZ[0][tz] = zx.F;
+        sZ[1][tz] = zx.G;
+        sZ[2][tz] = zx.uT;
+      }
+      __syncthreads();   // y and z faces published; every read of this slot is done
+      const FaceFlux yhi = {sY[0][ty + 1][tz], sY[1][ty + 1][tz], sY[2][ty + 1][tz]};
+      if (tz == MZ - 1) zhi = FaceFlux{sZ[0][ty], sZ[1][ty], sZ[2][ty]};
+      __syncthreads();   // every read of the y and z faces is done
+      if (live) {
+        const double da = (xhi.F - xlo.F) + (yhi.F - ylo.F) + (zhi.F - zlo.F);
+        const double dc = (xhi.G - xlo.G) + (yhi.G - ylo.G) + (zhi.G - zlo.G);
+        const double T0 = wT[1];
+        const long long cc = x * plane + col;
+        a_new[cc] = wA[1] - s * da;
+        c_new[cc] = F.c - s * dc;
+        if (P.solve_energy) {
+          const double dT = (xhi.uT - xlo.uT) + (yhi.uT - ylo.uT) + (zhi.uT - zlo.uT) -
+                            T0 * ((F.u1 - F.u0) + (F.v1 - F.v0) + (F.w1 - F.w0));
+          T_new[cc] = T0 - s * dT;
+        } else {
+          T_new[cc] = T0;
+        }
+        // outflow tallies on the box faces of this cell
+        if (x == 0) {
+          acc[0] -= xlo.F;
+          acc[1] -= xlo.G;
+        }
+        if (x == P.nx - 1) {
+          acc[0] += xhi.F;
+          acc[1] += xhi.G;
+        }
+        if (j == 0) {
+          acc[0] -= ylo.F;
+          acc[1] -= ylo.G;
+        }
+        if (j == P.ny - 1) {
+          acc[0] += yhi.F;
+          acc[1] += yhi.G;
+        }
+        if (k == 0) {
+          acc[0] -= zlo.F;
+          acc[1] -= zlo.G;
+        }
+        if (k == P.nz - 1) {
+          acc[0] += zhi.F;
+          acc[1] += zhi.G;
+        }
+      }
       adv_store(nf, sF[slot], sP[slot], ty, tz);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 3; ++q) {
         wA[q] = wA[q + 1];
         wO[q] = wO[q + 1];
         wT[q] = wT[q + 1];
         wP[q] = wP[q + 1];
       }
-      wA[4] = nf.cA;
-      wO[4] = nf.cO;
-      wT[4] = nf.cT;
-      wP[4] = nf.cP;
+      wA[3] = nf.cA;
+      wO[3] = nf.cO;
+      wT[3] = nf.cT;
+      wP[3] = nf.cP;
+      xlo = xhi;
+      NF.u0 = F.u1;
       F = NF;
       slot = slot == 2 ? 0 : slot + 1;
     }
@@ -624,7 +694,7 @@ __global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, co
     bool has[6];
     nbr6(P, a_new, c, i, j, k, an, has);
     const double ab = clamp01(a_new[c]);
-    const double rho = mix(ab, P.rho_L, P.rho_G), cp = mix(ab, P.cp_L, P.cp_G), kc = mix(ab, P.k_L, P.k_G);
+    const double rho = mix(ab, P.rho_L, rho_gas(P, c)), cp = mix(ab, P.cp_L, P.cp_G), kc = mix(ab, P.k_L, P.k_G);
     const double m = rho * cp / P.dt;
     double d = m, rhs = m * Tp[c] - mdot[c] * P.dh;
 #pragma unroll
@@ -650,7 +720,9 @@ __global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, co
 }
 
 // Species, eq. 9 for c = rho_G theta omega: (rho_G theta/dt) w - div(rho_G D theta grad w) = c'/dt + mdot
-// (without mdot in the literal species form).
+// (without mdot in the literal species form).  Face coefficient K_f = sc (q_c + q_nb)/2 with the cell
+// coefficient q = theta and sc = rho_G D/h^2, or, for a variable gas, q = rho_G theta and sc = D/h^2; the
+// Dirichlet faces keep the ambient gas's 2 rho_G D/h^2.
 __global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
                                 const double* __restrict__ mdot, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
@@ -658,34 +730,37 @@ __global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, c
                                 double* __restrict__ om0, F32Out fo) {
   long long b0, b1;
   block_range(P.n, b0, b1);
-  const double sc = P.rho_G * P.D / (P.h * P.h);
-  const double Kb = 2.0 * sc;
+  const double sc = (P.rg ? 1.0 : P.rho_G) * P.D / (P.h * P.h);
+  const double Kb = 2.0 * P.rho_G * P.D / (P.h * P.h);
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
-    double an[6];
+    double an[6], rn[6];
     bool has[6];
     nbr6(P, a_new, c, i, j, k, an, has);
+    if (P.rg) nbr6(P, P.rg, c, i, j, k, rn, has);
     const double th = fmax(1.0 - clamp01(a_new[c]), P.theta_min);
-    double d = P.rho_G * th / P.dt;
+    const double rgc = rho_gas(P, c);
+    const double qcell = P.rg ? rgc * th : th;
+    double d = rgc * th / P.dt;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
         if (has[ax * 2 + sd]) {
           const double tn = fmax(1.0 - clamp01(an[ax * 2 + sd]), P.theta_min);
-          d += sc * 0.5 * (th + tn);
+          d += sc * 0.5 * (qcell + (P.rg ? rn[ax * 2 + sd] * tn : tn));
         } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
           d += Kb;
         }
       }
-    qc[c] = th;
+    qc[c] = qcell;
     diag[c] = d;
     // the literal species form has no mdot source (the saturated liquid feeds the gas)
     b[c] = P.species_form == 1 ? cp_[c] / P.dt : cp_[c] / P.dt + mdot[c];
-    if (om0) om0[c] = cp_[c] / (P.rho_G * th);
+    if (om0) om0[c] = cp_[c] / (rgc * th);
     if (fo.q) {
-      fo.q[c] = (float)th;
+      fo.q[c] = (float)qcell;
       fo.d[c] = (float)d;
     }
   }
@@ -700,17 +775,20 @@ __global__ void k_species_update(DevParams P, const double* __restrict__ a_new, 
                                  double* scal) {
   long long b0, b1;
   block_range(P.n, b0, b1);
-  const double sc = P.rho_G * P.D / (P.h * P.h);
-  const double Kb = 2.0 * sc;
+  const double sc = (P.rg ? 1.0 : P.rho_G) * P.D / (P.h * P.h);
+  const double Kb = 2.0 * P.rho_G * P.D / (P.h * P.h);
   double acc[1] = {0.0};
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
-    double an[6], on[6];
+    double an[6], on[6], rn[6];
     bool has[6];
     nbr6(P, a_new, c, i, j, k, an, has);
     nbr6(P, om, c, i, j, k, on, has);
+    if (P.rg) nbr6(P, P.rg, c, i, j, k, rn, has);
     const double th = fmax(1.0 - clamp01(a_new[c]), P.theta_min);
+    const double rgc = rho_gas(P, c);
+    const double qcell = P.rg ? rgc * th : th;
     const double oc = om[c];
     double face = 0.0;
 #pragma unroll
@@ -719,7 +797,7 @@ __global__ void k_species_update(DevParams P, const double* __restrict__ a_new, 
       for (int sd = 0; sd < 2; ++sd) {
         if (has[ax * 2 + sd]) {
           const double tn = fmax(1.0 - clamp01(an[ax * 2 + sd]), P.theta_min);
-          face += sc * 0.5 * (th + tn) * (oc - on[ax * 2 + sd]);
+          face += sc * 0.5 * (qcell + (P.rg ? rn[ax * 2 + sd] * tn : tn)) * (oc - on[ax * 2 + sd]);
         } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
           face += Kb * oc;
           acc[0] += Kb * oc;
@@ -727,7 +805,7 @@ __global__ void k_species_update(DevParams P, const double* __restrict__ a_new, 
       }
     const double cn = (P.species_form == 1 ? cp_[c] : cp_[c] + P.dt * mdot[c]) - P.dt * face;
     cout[c] = cn;
-    omega[c] = cn / (P.rho_G * th);
+    omega[c] = cn / (rgc * th);   // a variable gas replaces it from eq. 24 at the end of the step
   }
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
@@ -743,13 +821,14 @@ __global__ void k_species_update(DevParams P, const double* __restrict__ a_new, 
 // advection along the two other axes (ascending) with the four-point
 // averaged velocity vb and the one-sided differences to lo / hi (zero-
 // gradient ghosts already substituted), gravity on the density jump and the
-// potential force on the xi jump between the cells L and R either side.
-// (i, j, k): the face's indices in its face array.
+// potential force on the xi jump between the cells L and R either side (gas
+// densities gL, gR of those cells).  (i, j, k): the face's indices in its face array.
 template <int AX>
 __device__ __forceinline__ double predictor_interior(const DevParams& P, double uc, double bn, double fn,
                                                      const double (&vb)[2], const double (&lo)[2],
-                                                     const double (&hi)[2], double aL_, double aR_, double xiL,
-                                                     double xiR, int i, int j, int k, double ih) {
+                                                     const double (&hi)[2], double aL_, double aR_, double gL,
+                                                     double gR, double xiL, double xiR, int i, int j, int k,
+                                                     double ih) {
   const double back = (uc - bn) * ih, fwd = (fn - uc) * ih;
   double adv = uc * (uc > 0.0 ? back : fwd);
 #pragma unroll
@@ -758,7 +837,7 @@ __device__ __forceinline__ double predictor_interior(const DevParams& P, double 
     adv += vb[q] * d;
   }
   const double aL = clamp01(aL_), aR = clamp01(aR_);
-  const double rL = mix(aL, P.rho_L, P.rho_G), rR = mix(aR, P.rho_L, P.rho_G);
+  const double rL = mix(aL, P.rho_L, gL), rR = mix(aR, P.rho_L, gR);
   const double bf = 0.5 * (1.0 / rL + 1.0 / rR);
   const double xf = (AX == 0 ? i : i + 0.5) * P.h - P.x0[0];
   const double yf = (AX == 1 ? j : j + 0.5) * P.h - P.x0[1];
@@ -774,21 +853,22 @@ __device__ __forceinline__ double predictor_box(const DevParams& P, int ax, int 
   return kind == WALL ? 0.0 : (kind == INLET ? P.w_in : uc);
 }
 
-// Predictor tiles: u, v, w, alpha and xi planes with a halo of 1 (66 x 6,
-// rows y0-1 .. y0+4, columns z0-1 .. z0+64); v and w keep their extra face
-// row / column in it.
+// Predictor tiles: u, v, w, alpha, xi (and the gas density of a variable
+// gas) planes with a halo of 1 (66 x 6, rows y0-1 .. y0+4, columns z0-1 ..
+// z0+64); v and w keep their extra face row / column in it.
 constexpr int QZ = MZ + 2, QY = MY + 2, QTILE = QZ * QY;
-constexpr int QF = 5;   // u, v, w, alpha, xi
 
+template <int QF>
 struct PredPlane {
   double e[QF][2];
 };
 // Plane X of every field, entries threadIdx.x and threadIdx.x + BLOCK of the
 // tile (row-major); X up to xmax (u has nx + 1 planes, the others nx).
+template <int QF>
 __device__ __forceinline__ void pred_fetch(const DevParams& P, const double* __restrict__ u,
                                            const double* __restrict__ v, const double* __restrict__ w,
                                            const double* __restrict__ a, const double* __restrict__ xi, int X,
-                                           int xmax, int y0, int z0, PredPlane& f) {
+                                           int xmax, int y0, int z0, PredPlane<QF>& f) {
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int e = threadIdx.x + q * BLOCK;
@@ -804,9 +884,11 @@ __device__ __forceinline__ void pred_fetch(const DevParams& P, const double* __r
     f.e[2][q] = win ? w[widx(P, X, gj, gk)] : 0.0;
     f.e[3][q] = cell ? a[cidx(P, X, gj, gk)] : 0.0;
     f.e[4][q] = cell ? xi[cidx(P, X, gj, gk)] : 0.0;
+    if constexpr (QF > 5) f.e[QF - 1][q] = cell ? P.rg[cidx(P, X, gj, gk)] : 0.0;
   }
 }
-__device__ __forceinline__ void pred_store(const PredPlane& f, double (*S)[QTILE]) {
+template <int QF>
+__device__ __forceinline__ void pred_store(const PredPlane<QF>& f, double (*S)[QTILE]) {
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int e = threadIdx.x + q * BLOCK;
@@ -820,23 +902,26 @@ __device__ __forceinline__ void pred_store(const PredPlane& f, double (*S)[QTILE
 // u*, v*, w* of every face, marching along x: the thread of cell (x, j, k)
 // writes the faces (x, j, k) of the three arrays and, on the high box faces,
 // the face beyond.  Plane x and x+1 tiles give the y/z neighbours and the
-// x+1 values; the x-1 values are kept from the previous plane.
+// x+1 values; the x-1 values are kept from the previous plane.  VAR: a
+// variable gas (its density field P.rg rides along as a sixth tile).
+template <bool VAR>
 __global__ void __launch_bounds__(BLOCK)
 k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const double* __restrict__ xi,
             const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
             double* __restrict__ us, double* __restrict__ vs, double* __restrict__ ws) {
+  constexpr int QF = VAR ? 6 : 5;   // u, v, w, alpha, xi (, rho_G)
   __shared__ double sQ[3][QF][QTILE];   // slot (x mod 3), field
   const int tz = threadIdx.x % MZ, ty = threadIdx.x / MZ;
   const double ih = 1.0 / P.h;
-  constexpr int FU = 0, FV = 1, FW = 2, FA = 3, FX = 4;
+  constexpr int FU = 0, FV = 1, FW = 2, FA = 3, FX = 4, FR = 5;
   for (long long t = march_logical(); t < G.tiles; t += gridDim.x) {
     int x0, y0, z0;
     march_tile(G, t, x0, y0, z0);
     const int x1 = min(x0 + G.xlen, P.nx);
     const int j = y0 + ty, k = z0 + tz;
     const bool live = j < P.ny && k < P.nz;
-    // plane x-1 values of the own column: u, v (j, j+1), w (k, k+1), alpha, xi
-    double pu, pv0, pv1, pw0, pw1, pa, px;
+    // plane x-1 values of the own column: u, v (j, j+1), w (k, k+1), alpha, xi, rho_G
+    double pu, pv0, pv1, pw0, pw1, pa, px, pg;
     {
       const bool in = live && x0 >= 1;
       const int X = in ? x0 - 1 : 0, jj = in ? j : 0, kk = in ? k : 0;
@@ -847,18 +932,19 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
       pw1 = in ? w[widx(P, X, jj, kk + 1)] : 0.0;
       pa = in ? a_new[cidx(P, X, jj, kk)] : 0.0;
       px = in ? xi[cidx(P, X, jj, kk)] : 0.0;
+      pg = VAR ? (in ? P.rg[cidx(P, X, jj, kk)] : 0.0) : P.rho_G;
     }
     __syncthreads();   // the previous tile's last reads of the slots
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      PredPlane f;
+      PredPlane<QF> f;
       pred_fetch(P, u, v, w, a_new, xi, x0 + q, x1, y0, z0, f);
       pred_store(f, sQ[(x0 + q) % 3]);
     }
     __syncthreads();
     int slot = x0 % 3;
     for (int x = x0; x < x1; ++x) {
-      PredPlane nf;
+      PredPlane<QF> nf;
       pred_fetch(P, u, v, w, a_new, xi, x + 3, x1, y0, z0, nf);
       const int s1 = slot == 2 ? 0 : slot + 1;
       if (live) {
@@ -867,6 +953,8 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
         auto T1 = [&](int f, int dy, int dz) { return sQ[s1][f][ce + dy * QZ + dz]; };
         const double uc = T0(FU, 0, 0), vc = T0(FV, 0, 0), wc = T0(FW, 0, 0);
         const double ac = T0(FA, 0, 0), xc = T0(FX, 0, 0);
+        auto G0 = [&](int dy, int dz) { return VAR ? T0(FR, dy, dz) : P.rho_G; };
+        const double gc = G0(0, 0);
         const double un = T1(FU, 0, 0);   // u(x+1, j, k)
         double ru, rv, rw;
         // u face (x, j, k)
@@ -876,7 +964,7 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
           const double vb[2] = {0.25 * (pv0 + pv1 + vc + T0(FV, 1, 0)), 0.25 * (pw0 + pw1 + wc + T0(FW, 0, 1))};
           const double lo[2] = {j >= 1 ? T0(FU, -1, 0) : uc, k >= 1 ? T0(FU, 0, -1) : uc};
           const double hi[2] = {j <= P.ny - 2 ? T0(FU, 1, 0) : uc, k <= P.nz - 2 ? T0(FU, 0, 1) : uc};
-          ru = predictor_interior<0>(P, uc, pu, un, vb, lo, hi, pa, ac, px, xc, x, j, k, ih);
+          ru = predictor_interior<0>(P, uc, pu, un, vb, lo, hi, pa, ac, pg, gc, px, xc, x, j, k, ih);
         }
         // v face (x, j, k)
         if (j == 0) {
@@ -887,7 +975,7 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
           const double lo[2] = {x >= 1 ? pv0 : vc, k >= 1 ? T0(FV, 0, -1) : vc};
           const double hi[2] = {x <= P.nx - 2 ? T1(FV, 0, 0) : vc, k <= P.nz - 2 ? T0(FV, 0, 1) : vc};
           rv = predictor_interior<1>(P, vc, T0(FV, -1, 0), T0(FV, 1, 0), vb, lo, hi, T0(FA, -1, 0), ac,
-                                     T0(FX, -1, 0), xc, x, j, k, ih);
+                                     G0(-1, 0), gc, T0(FX, -1, 0), xc, x, j, k, ih);
         }
         // w face (x, j, k)
         if (k == 0) {
@@ -898,7 +986,7 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
           const double lo[2] = {x >= 1 ? pw0 : wc, j >= 1 ? T0(FW, -1, 0) : wc};
           const double hi[2] = {x <= P.nx - 2 ? T1(FW, 0, 0) : wc, j <= P.ny - 2 ? T0(FW, 1, 0) : wc};
           rw = predictor_interior<2>(P, wc, T0(FW, 0, -1), T0(FW, 0, 1), vb, lo, hi, T0(FA, 0, -1), ac,
-                                     T0(FX, 0, -1), xc, x, j, k, ih);
+                                     G0(0, -1), gc, T0(FX, 0, -1), xc, x, j, k, ih);
         }
         us[uidx(P, x, j, k)] = ru;
         vs[vidx(P, x, j, k)] = rv;
@@ -913,6 +1001,7 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
         pw1 = T0(FW, 0, 1);
         pa = ac;
         px = xc;
+        pg = gc;
       }
       __syncthreads();   // every read of this slot is done
       pred_store(nf, sQ[slot]);
@@ -926,19 +1015,21 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
 __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ mdot,
                                  const double* __restrict__ us, const double* __restrict__ vs,
                                  const double* __restrict__ ws, double* __restrict__ qc,
-                                 double* __restrict__ diag, double* __restrict__ b, F32Out fo) {
+                                 double* __restrict__ diag, double* __restrict__ b, F32Out fo,
+                                 const double* __restrict__ scomp) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   const double ih = 1.0 / P.h;
   const double sc = P.dt / (P.h * P.h);
-  const double Ssc = 1.0 / P.rho_G - 1.0 / P.rho_L;
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
-    double an[6];
+    double an[6], rn[6];
     bool has[6];
     nbr6(P, a_new, c, i, j, k, an, has);
-    const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, P.rho_G);
+    if (P.rg) nbr6(P, P.rg, c, i, j, k, rn, has);
+    const double rgc = rho_gas(P, c);
+    const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, rgc);
     const double b32 = (double)(float)beta;
     double d = 0.0, d32 = 0.0;
 #pragma unroll
@@ -946,7 +1037,7 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
         if (has[ax * 2 + sd]) {
-          const double bn = 1.0 / mix(clamp01(an[ax * 2 + sd]), P.rho_L, P.rho_G);
+          const double bn = 1.0 / mix(clamp01(an[ax * 2 + sd]), P.rho_L, P.rg ? rn[ax * 2 + sd] : P.rho_G);
           d += sc * 0.5 * (beta + bn);
           d32 += fo.sc * 0.5 * (b32 + (double)(float)bn);
         } else if (pressure_dirichlet(P.kind[ax * 2 + sd])) {
@@ -959,7 +1050,9 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
                         (ws[widx(P, i, j, k + 1)] - ws[widx(P, i, j, k)])) * ih;
     qc[c] = beta;
     diag[c] = d;
-    b[c] = mdot[c] * Ssc - div;
+    // eq. 7: mdot (1/rho_G - 1/rho_L), less the variable gas's (1 - alpha)(1/rho_G) D rho_G/Dt
+    const double src = mdot[c] * (1.0 / rgc - 1.0 / P.rho_L) - (scomp ? scomp[c] : 0.0);
+    b[c] = src - div;
     if (fo.q) {
       fo.q[c] = (float)beta;
       fo.d[c] = fo.mg ? (float)d32 : (float)d;
@@ -1028,13 +1121,13 @@ __device__ __forceinline__ double project_face(const DevParams& P, const double*
     const int jc = AX == 1 ? (side ? j - 1 : j) : j;
     const int kc = AX == 2 ? (side ? k - 1 : k) : k;
     const long long c = cidx(P, ic, jc, kc);
-    const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, P.rho_G);
+    const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, rho_gas(P, c));
     return side ? us + 2.0 * P.dt * beta * p[c] * ih : us - 2.0 * P.dt * beta * p[c] * ih;
   }
   const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
   const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
-  const double bL = 1.0 / mix(clamp01(a_new[cL]), P.rho_L, P.rho_G);
-  const double bR = 1.0 / mix(clamp01(a_new[cR]), P.rho_L, P.rho_G);
+  const double bL = 1.0 / mix(clamp01(a_new[cL]), P.rho_L, rho_gas(P, cL));
+  const double bR = 1.0 / mix(clamp01(a_new[cR]), P.rho_L, rho_gas(P, cR));
   return us - P.dt * 0.5 * (bL + bR) * (p[cR] - p[cL]) * ih;
 }
 
@@ -1197,12 +1290,13 @@ void launch_predictor(const DevParams& P, const double* a_new, const double* xi,
                       hipStream_t s) {
   int nb;
   const MarchGeom G = march_geom(P, nb);
-  k_predictor<<<nb, BLOCK, 0, s>>>(P, G, a_new, xi, u, v, w, us, vs, ws);
+  if (P.rg) k_predictor<true><<<nb, BLOCK, 0, s>>>(P, G, a_new, xi, u, v, w, us, vs, ws);
+  else k_predictor<false><<<nb, BLOCK, 0, s>>>(P, G, a_new, xi, u, v, w, us, vs, ws);
 }
 void launch_pressure_setup(const DevParams& P, const double* a_new, const double* mdot,
                            const double* us, const double* vs, const double* ws, double* qc,
-                           double* diag, double* b, hipStream_t s, F32Out fo) {
-  k_pressure_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, mdot, us, vs, ws, qc, diag, b, fo);
+                           double* diag, double* b, hipStream_t s, F32Out fo, const double* scomp) {
+  k_pressure_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, mdot, us, vs, ws, qc, diag, b, fo, scomp);
 }
 void launch_div_setup(const DevParams& P, const double* u, const double* v, const double* w, double* qc,
                       double* diag, double* b, hipStream_t s, F32Out fo) {

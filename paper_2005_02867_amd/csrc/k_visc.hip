@@ -78,8 +78,9 @@ __device__ Row row_of(const DevParams& P, const double* alpha, const Face& F) {
   const int a = F.a;
   int cl[3] = {c[0], c[1], c[2]}, cr[3] = {c[0], c[1], c[2]};
   cl[a] -= 1;   // cells on the two sides of the face along a
-  const double rl = mix(clamp01(alpha[cidx(P, cl[0], cl[1], cl[2])]), P.rho_L, P.rho_G);
-  const double rr = mix(clamp01(alpha[cidx(P, cr[0], cr[1], cr[2])]), P.rho_L, P.rho_G);
+  const long long el = cidx(P, cl[0], cl[1], cl[2]), er = cidx(P, cr[0], cr[1], cr[2]);
+  const double rl = mix(clamp01(alpha[el]), P.rho_L, rho_gas(P, el));
+  const double rr = mix(clamp01(alpha[er]), P.rho_L, rho_gas(P, er));
   R.m = 1.0 / (P.dt * (0.5 * (1.0 / rl + 1.0 / rr)));
   const double mul = mu_of(P, alpha, cl[0], cl[1], cl[2]), mur = mu_of(P, alpha, cr[0], cr[1], cr[2]);
   R.diag = R.m;

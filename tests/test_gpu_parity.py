@@ -47,13 +47,13 @@ def _relx(a, b):
     return max(_rel(a, b), _rel_max(a, b))
 
 
-def _compare(g_fields, st, where, tol=TOL, tol_max=None):
+def _compare(g_fields, st, where, tol=TOL, tol_max=None, fields=FIELDS):
     """Every field within tol relative, both in the 2-norm and element by
     element (max |a - b| <= tol max |b|), so errors confined to small-magnitude
     regions (the alpha band, omega near the droplet, faces at walls) show.
     tol_max: per-field element-wise bars where a case needs its own."""
     errs, bad = {}, {}
-    for k in FIELDS:
+    for k in fields:
         e2, em = _rel(g_fields[k], st[k]), _rel_max(g_fields[k], st[k])
         errs[k] = max(e2, em)
         if not (e2 <= tol and em <= (tol_max or {}).get(k, tol)):
