@@ -11,6 +11,7 @@ Modules, in the order of the paper's segregated step (Section 3.1):
   gas        -- eq. 24 per cell and eq. 7's compressibility term (variable gas)
   interface  -- Section 2.4 (evaporation flux, eqs. 12-21)
   vof        -- Section 2.1 (eqs. 3-4) with a flux-limited face interpolation
+  geo        -- Section 2.1's geometric advection: a plane per surface cell, swept face areas
   operators  -- implicit diffusion / pressure operators and a Jacobi PCG
   momentum   -- Section 2.2 and 2.6 (eqs. 6, 7, 28-30): predictor, projection
   viscous    -- eqs. 5 and 30: the implicit viscous part of the predictor

@@ -13,7 +13,7 @@ State (torch.float64, CPU):
 Order (the six steps of Section 3.1):
   1. evaporation flux  (interface.geometry, raw_evaporation, redistribute)
   2. alpha source      alpha1 = alpha - dt mdot/rho_L          (eq. 4)
-  3. advection         vof.advect                              (eq. 3)
+  3. advection         vof.advect (advection = 1: the liquid by geo.advect)  (eq. 3)
   4. properties        eq. 31 on alpha' clamped to [0, 1]; theta = max(1-alpha', theta_min)
   5. energy, species (operators) and momentum predictor (momentum; with
      viscous = 1 its implicit viscous part, viscous.py)
@@ -46,6 +46,7 @@ from __future__ import annotations
 import torch
 
 from . import gas, interface, momentum, operators, thermo, viscous, vof
+from . import geo as geometric
 
 
 def variable_gas(prm):
@@ -144,6 +145,9 @@ def step(st, prm, tol=None, T_amb=None, D_v=None, dh_ev=None, rho_G=None, record
     else:
         alpha_p, c_p, T_p, B_L, B_v = vof.advect(alpha1, st["omega"], st["T"], st["c"], *U, prm, rho_G,
                                                  T_amb=Ta, advect_T=bool(prm["solve_energy"]), U_liq=U_liq)
+    if prm.get("advection", 0) == 1:   # geometric liquid advection (geo.py) in place of the flux-limited one
+        alpha_p, out_vol, _ = geometric.advect(alpha1, U_liq if U_liq is not None else U, prm)
+        B_L = prm["rho_L"] * out_vol
     # 4. properties (variable gas: rho_G' from the advected T' and c')
     if var:
         theta_p = torch.clamp(1.0 - torch.clamp(alpha_p, 0.0, 1.0), min=prm["theta_min"])

@@ -54,6 +54,8 @@ _BASE = dict(
     viscous=0, mu_L=3.9e-4, mu_G=3.4e-5,
     # 0: rho_G of the ambient gas everywhere; 1: eq. 24 per cell (variable gas)
     gas_density=0,
+    # liquid advection: 0 flux-limited (TVD van Leer), 1 geometric (a plane per surface cell)
+    advection=0,
 )
 
 # name -> (overrides, run description)
