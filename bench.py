@@ -301,6 +301,9 @@ def main():
                     help="skip the leg that times the workload in the literal species form (saturated liquid, "
                          "central gradient at adj, no mdot source in the species equation) and compares its "
                          "evaporation rate with the conservative form's")
+    ap.add_argument("--no-variable-gas", action="store_true",
+                    help="skip the leg that times the workload with the variable-density gas (eq. 24 per cell, "
+                         "eq. 7's compressibility term)")
     ap.add_argument("--counters-pass", action="store_true",
                     help="short run for hardware-counter passes: one step of the workload, 5 replayed launches of "
                          "the fine-level sweep, then 3 device copies of 1 GiB (the counter calibration)")
@@ -418,6 +421,19 @@ def main():
             "iters_T_omega_p_rounds_phi": lit["iters"][-1],
             "mdot_total_kg_s": lit["mdot"], "mdot_total_conservative_kg_s": mixed["mdot"],
             "step_of_first_timed": args.warmup + 1,
+        }
+    if not args.no_variable_gas:
+        log(f"variable-density gas, precision form: warmup {args.warmup}, timing {args.steps} steps")
+        var = timed_run(ds, torch, dict(prm, precision=W.PREC_MIXED, gas_density=1), fields, args.steps,
+                        args.warmup)
+        log(f"  {var['seconds'] * 1e3 / args.steps:.2f} ms/step, iters {var['iters'][-1]}")
+        out["variable_gas"] = {
+            "value": ncell * args.steps / var["seconds"], "ms_per_step": var["seconds"] * 1e3 / args.steps,
+            "iters_T_omega_p_rounds_phi": var["iters"][-1],
+            "mdot_total_kg_s": var["mdot"], "mdot_total_ambient_gas_kg_s": mixed["mdot"],
+            "volume_rel_diff_vs_ambient_gas": abs(var["volume"] - mixed["volume"]) / mixed["volume"],
+            "note": "the same workload with rho_G from eq. 24 per cell (Peng-Robinson mixture) and eq. 7's "
+                    "compressibility term; not the headline configuration, which states constant properties",
         }
     if not args.no_adjoint:
         log("adjoint cost: 96^3, 100 steps")
