@@ -78,6 +78,18 @@ enum { DS_SPECIES_CONSERVATIVE = 0, DS_SPECIES_LITERAL = 1 };
  * to the pressure source.  Not with the literal species form or the
  * differentiation form. */
 enum { DS_GAS_AMBIENT = 0, DS_GAS_VARIABLE = 1 };
+/* Liquid advection (Section 2.1, eq. 3).  FLUX_LIMITED: TVD van Leer face
+ * values.  GEOMETRIC: the paper's choice of a geometric scheme (isoAdvector),
+ * with a plane per surface cell (1e-8 < alpha1 < 1 - 1e-8): normal
+ * -grad(alpha1)/|grad(alpha1)| by central differences (ghosts repeat the
+ * boundary cell), offset leaving alpha1 h^3 of liquid; the liquid through a
+ * face in the step is the face velocity times the time integral of the area
+ * the donor cell's plane submerges while it moves with the donor's centre
+ * velocity along the normal (exact piecewise integration); other donors give
+ * U_f alpha1 dt; no bounding step (the update stays conservative).  The
+ * vapour and temperature fluxes keep the flux-limited face values.  Not with
+ * the differentiation form. */
+enum { DS_ADV_FLUX_LIMITED = 0, DS_ADV_GEOMETRIC = 1 };
 
 /* Physical and numerical parameters, SI units.  Property values are constant
  * (the mixing rule of Section 2.7, eq. 31, blends liquid and gas values). */
@@ -119,6 +131,7 @@ typedef struct ds_params {
   int viscous;         /* 1: implicit viscous momentum, div mu (grad v + grad v^T) of eqs. 5 and 30 (0: mu = 0) */
   double mu_L, mu_G;   /* liquid and gas dynamic viscosity [Pa s], mixed by eq. 31 (used with viscous = 1) */
   int gas_density;     /* DS_GAS_*: the gas density of eq. 24 */
+  int advection;       /* DS_ADV_*: the liquid advection of eq. 3 */
 } ds_params;
 
 /* Scalars of the most recent step (or evaporation/pressure call). */

@@ -50,7 +50,7 @@ class Params(C.Structure):
         ("s_max", C.c_int), ("maxit", C.c_int), ("eq_model", C.c_int), ("bc_mode", C.c_int),
         ("precision", C.c_int), ("solve_energy", C.c_int), ("evaporation", C.c_int), ("pressure_precond", C.c_int),
         ("liquid_transport", C.c_int), ("species_form", C.c_int), ("viscous", C.c_int),
-        ("mu_L", C.c_double), ("mu_G", C.c_double), ("gas_density", C.c_int),
+        ("mu_L", C.c_double), ("mu_G", C.c_double), ("gas_density", C.c_int), ("advection", C.c_int),
     ]
 
 
@@ -117,7 +117,7 @@ def make_params(prm: dict) -> Params:
     for name, ctype in Params._fields_:
         if name in ("pressure_precond", "liquid_transport"):
             val = prm.get(name, 1)
-        elif name in ("species_form", "viscous", "gas_density"):
+        elif name in ("species_form", "viscous", "gas_density", "advection"):
             val = prm.get(name, 0)
         elif name in ("mu_L", "mu_G"):
             val = prm.get(name, 0.0)

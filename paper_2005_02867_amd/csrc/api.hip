@@ -79,6 +79,10 @@ struct ds_grid {
   // variable-density gas (gas_density = 1): the state's rho_G, the advected state's rho_G', eq. 7's
   // compressibility term and the vapour mass per gas volume rho_G omega the advection carries
   double *rg = nullptr, *rg_p = nullptr, *scomp = nullptr, *qv = nullptr;
+  // geometric advection (advection = 1): the planes of the surface cells (n_x, n_y, n_z, s) and the liquid
+  // fluxes per face; the liquid face velocities use us, vs, ws (free until the predictor)
+  double* geo_pl[4] = {};
+  double* geo_F[3] = {};
   int batch_visc = 4;
   float* r32alt = nullptr;
   int dirmask = 0;                 // p_rgh = 0 box faces
@@ -235,6 +239,12 @@ size_t carve(ds_grid* g, char* base) {
     g->qv = L.take<double>(base, n);
   }
   g->dp.rg = g->rg;   // stages read the state's gas density unless they set their own
+  if (g->prm.advection) {
+    for (int q = 0; q < 4; ++q) g->geo_pl[q] = L.take<double>(base, n);
+    g->geo_F[0] = L.take<double>(base, g->nu);
+    g->geo_F[1] = L.take<double>(base, g->nv);
+    g->geo_F[2] = L.take<double>(base, g->nw);
+  }
   if (g->prm.viscous) {
     const long long nf = visc_faces(g->dp);
     double** vv[6] = {&g->visc.x, &g->visc.b, &g->visc.d, &g->visc.r, &g->visc.p, &g->visc.q};
@@ -905,6 +915,16 @@ int one_step(ds_grid* g, hipStream_t s) {
     D.res_phi = 0.0;
   }
   const bool var = g->prm.gas_density == DS_GAS_VARIABLE;
+  // geometric advection: the liquid fluxes of every face from the planes of the surface cells
+  const bool geo = g->prm.advection == DS_ADV_GEOMETRIC;
+  if (geo) {
+    double* const pl[4] = {g->geo_pl[0], g->geo_pl[1], g->geo_pl[2], g->geo_pl[3]};
+    launch_geo_fluxes(P, g->a1, g->u, g->v, g->w, g->prm.liquid_transport ? g->phi : nullptr, g->us, g->vs, g->ws, pl,
+                      g->geo_F[0], g->geo_F[1], g->geo_F[2], s);
+  }
+  const double* Fx = geo ? g->geo_F[0] : nullptr;
+  const double* Fy = geo ? g->geo_F[1] : nullptr;
+  const double* Fz = geo ? g->geo_F[2] : nullptr;
   if (var) {
     // the vapour flux carries the face value of rho_G omega (start-of-step rho_G)
     launch_gas_partial(P, g->omega, g->rg, g->qv, s);
@@ -912,12 +932,12 @@ int one_step(ds_grid* g, hipStream_t s) {
     Pa.rho_G = 1.0;
     Pa.rg = nullptr;
     launch_advect(Pa, g->a1, g->qv, g->T, g->c, g->u, g->v, g->w, g->prm.liquid_transport ? g->phi : nullptr,
-                  g->a_new, g->c_new, g->T_new, g->partials, g->counters + CT_ADV, g->scal, s);
+                  g->a_new, g->c_new, g->T_new, g->partials, g->counters + CT_ADV, g->scal, s, Fx, Fy, Fz);
     // rho_G' of the advected state (T', c', alpha')
     launch_gas_invert(P, P.solve_energy ? g->T_new : g->T, g->c_new, g->a_new, g->rg_p, s);
   } else {
     launch_advect(P, g->a1, g->omega, g->T, g->c, g->u, g->v, g->w, g->prm.liquid_transport ? g->phi : nullptr,
-                  g->a_new, g->c_new, g->T_new, g->partials, g->counters + CT_ADV, g->scal, s);
+                  g->a_new, g->c_new, g->T_new, g->partials, g->counters + CT_ADV, g->scal, s, Fx, Fy, Fz);
   }
   // stages after the advection read rho_G' (a variable gas)
   DevParams Pp = P;
@@ -1143,7 +1163,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
       prm->precision < 0 || prm->precision > 1 || !finite_pos(prm->r_fib) || prm->pressure_precond < 0 ||
       prm->pressure_precond > 1 || prm->liquid_transport < 0 || prm->liquid_transport > 1 ||
       prm->species_form < 0 || prm->species_form > 1 || prm->viscous < 0 || prm->viscous > 1 ||
-      prm->gas_density < 0 || prm->gas_density > 1 ||
+      prm->gas_density < 0 || prm->gas_density > 1 || prm->advection < 0 || prm->advection > 1 ||
       (prm->gas_density == DS_GAS_VARIABLE && prm->species_form == DS_SPECIES_LITERAL) ||
       (prm->viscous && (!(prm->mu_L >= 0.0) || !(prm->mu_G >= 0.0) || !std::isfinite(prm->mu_L) ||
                         !std::isfinite(prm->mu_G))))
@@ -1629,6 +1649,7 @@ int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t
     return fail(g, DS_ERR_ARG, "the adjoint covers the conservative species form only");
   if (g->prm.viscous) return fail(g, DS_ERR_ARG, "the adjoint covers the inviscid step only");
   if (g->prm.gas_density) return fail(g, DS_ERR_ARG, "the adjoint covers the ambient gas density only");
+  if (g->prm.advection) return fail(g, DS_ERR_ARG, "the adjoint covers the flux-limited advection only");
   const int C = std::min(ckpt_every, nsteps);
   const size_t need = tape_total_bytes(g, nsteps, C);
   if (tape_bytes < need) return fail(g, DS_ERR_ARG, "tape too small: %zu < %zu bytes", tape_bytes, need);

@@ -1,0 +1,118 @@
+// Geometry of the geometric interface advection (Section 2.1: the paper
+// advects alpha with a geometric scheme, isoAdvector): a plane per surface
+// cell, the area it submerges on a cell face, the volume it cuts from a cell,
+// and the time integral of a face's submerged area while the plane moves.
+// FP64, one cell or face per thread.
+//
+// Cell-local coordinates: the cell is [0, h]^3, the liquid is n.x <= s.
+// The submerged area of a face is quadratic in the plane offset between the
+// offsets at which the plane passes the face's corners, the cut volume of a
+// cell cubic between those of its corners; both are integrated piecewise with
+// Simpson's rule, which is exact for quadratics.
+#pragma once
+#include "ds_device.h"
+
+namespace dsv {
+
+constexpr double GEO_SURF_TOL = 1e-8;   // surface cells: tol < alpha < 1 - tol
+constexpr double GEO_FLAT = 1e-12;      // in-face normal below this: the plane is parallel to the face
+
+// Area of {(y, z) in [0, h]^2 : a y + b z <= sig}, a >= b >= 0.
+__device__ __forceinline__ double geo_face_area(double sig, double a, double b, double h) {
+  if (a < GEO_FLAT) return sig > 0.0 ? h * h : 0.0;
+  if (b == 0.0) return h * fmin(fmax(sig / a, 0.0), h);
+  const double zA = fmin(fmax((sig - a * h) / b, 0.0), h);   // below zA the whole row is submerged
+  const double zB = fmin(fmax(sig / b, 0.0), h);             // above zB nothing is
+  return h * zA + (zB - zA) * (sig - 0.5 * b * (zA + zB)) / a;
+}
+
+// The same for a face whose in-face normal components (p, q) have any sign.
+__device__ __forceinline__ void geo_face_frame(double sig, double p, double q, double h, double& sh, double& a,
+                                               double& b) {
+  sh = sig - fmin(p, 0.0) * h - fmin(q, 0.0) * h;
+  const double ap = fabs(p), aq = fabs(q);
+  a = fmax(ap, aq);
+  b = fmin(ap, aq);
+}
+
+// Sum of Simpson's rule over [t0, t1] split at the four break points br[]
+// (clamped into the interval), for f quadratic between them.
+template <class F>
+__device__ __forceinline__ double geo_simpson(F f, double t0, double t1, double (&br)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) br[q] = fmin(fmax(br[q], t0), t1);
+  // sort the four (insertion)
+#pragma unroll
+  for (int q = 1; q < 4; ++q) {
+    const double v = br[q];
+    int r = q - 1;
+    while (r >= 0 && br[r] > v) {
+      br[r + 1] = br[r];
+      --r;
+    }
+    br[r + 1] = v;
+  }
+  const double pts[6] = {t0, br[0], br[1], br[2], br[3], t1};
+  double tot = 0.0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const double lo = pts[q], hi = pts[q + 1];
+    tot += (hi - lo) / 6.0 * (f(lo) + 4.0 * f(0.5 * (lo + hi)) + f(hi));
+  }
+  return tot;
+}
+
+// Volume of {x in [0, h]^3 : n.x <= s}.
+__device__ inline double geo_cell_volume(double s, const double (&n)[3], double h) {
+  const double sp = s - (fmin(n[0], 0.0) + fmin(n[1], 0.0) + fmin(n[2], 0.0)) * h;
+  double c[3] = {fabs(n[0]), fabs(n[1]), fabs(n[2])};
+  // descending
+  if (c[0] < c[1]) { const double t = c[0]; c[0] = c[1]; c[1] = t; }
+  if (c[1] < c[2]) { const double t = c[1]; c[1] = c[2]; c[2] = t; }
+  if (c[0] < c[1]) { const double t = c[0]; c[0] = c[1]; c[1] = t; }
+  const double c1 = c[0], c2 = c[1], c3 = c[2];
+  if (c2 < GEO_FLAT) return h * h * fmin(fmax(sp / c1, 0.0), h);   // a plane normal to an axis: a slab
+  double br[4] = {sp / c1, (sp - c3 * h) / c1, (sp - c2 * h) / c1, (sp - (c2 + c3) * h) / c1};
+  auto f = [&](double x) { return geo_face_area(sp - c1 * x, c2, c3, h); };
+  return geo_simpson(f, 0.0, h, br);
+}
+
+// Offset s of the plane with normal n that leaves alpha h^3 of liquid in the
+// cell (bisection until no double lies between the ends).
+__device__ inline double geo_plane_offset(double alpha, const double (&n)[3], double h) {
+  double lo = (fmin(n[0], 0.0) + fmin(n[1], 0.0) + fmin(n[2], 0.0)) * h;
+  double hi = (fmax(n[0], 0.0) + fmax(n[1], 0.0) + fmax(n[2], 0.0)) * h;
+  const double target = alpha * h * h * h;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid == lo || mid == hi) break;
+    if (geo_cell_volume(mid, n, h) > target) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// int_0^dt of the submerged area of a face (in-face normal components p, q)
+// whose plane offset moves as sig0 + un t.
+__device__ inline double geo_swept_area(double sig0, double un, double p, double q, double h, double dt) {
+  double sh, a, b;
+  geo_face_frame(sig0, p, q, h, sh, a, b);
+  if (a < GEO_FLAT) {   // parallel to the face: wholly submerged while the offset is positive
+    double wet;
+    if (un > 0.0) wet = dt - fmin(fmax(-sh / un, 0.0), dt);
+    else if (un < 0.0) wet = fmin(fmax(-sh / un, 0.0), dt);
+    else wet = sh > 0.0 ? dt : 0.0;
+    return h * h * wet;
+  }
+  double br[4] = {-1.0, -1.0, -1.0, -1.0};
+  if (un != 0.0) {
+    br[0] = (0.0 - sh) / un;
+    br[1] = (b * h - sh) / un;
+    br[2] = (a * h - sh) / un;
+    br[3] = ((a + b) * h - sh) / un;
+  }
+  auto f = [&](double t) { return geo_face_area(sh + un * t, a, b, h); };
+  return geo_simpson(f, 0.0, dt, br);
+}
+
+}  // namespace dsv

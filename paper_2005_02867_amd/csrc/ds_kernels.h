@@ -52,7 +52,8 @@ void launch_source(const DevParams& P, const double* alpha, const double* mraw, 
 void launch_advect(const DevParams& P, const double* a1, const double* omega, const double* T,
                    const double* c, const double* u, const double* v, const double* w, const double* phi,
                    double* a_new, double* c_new, double* T_new, double* partials, unsigned* counter, double* scal,
-                   hipStream_t s);
+                   hipStream_t s, const double* Fx = nullptr, const double* Fy = nullptr,
+                   const double* Fz = nullptr);   // Fx..Fz: given liquid fluxes (geometric advection)
 void launch_div_setup(const DevParams& P, const double* u, const double* v, const double* w, double* qc,
                       double* diag, double* b, hipStream_t s, F32Out fo = {});
 void launch_energy_setup(const DevParams& P, const double* a_new, const double* T_prime,
@@ -79,6 +80,10 @@ void launch_diagnostics(const DevParams& P, const double* alpha, const double* c
                         const double* p, const double* mdot, double* partials, unsigned* counter,
                         double* scal, hipStream_t s);
 void launch_c_from_omega(const DevParams& P, const double* alpha, const double* omega, double* c, hipStream_t s);
+// geometric interface advection (k_geo.hip): liquid faces, planes, liquid fluxes per face
+void launch_geo_fluxes(const DevParams& P, const double* a1, const double* u, const double* v, const double* w,
+                       const double* phi, double* Ux, double* Uy, double* Uz, double* const (&planes)[4],
+                       double* Fx, double* Fy, double* Fz, hipStream_t s);
 // variable-density gas (k_gas.hip)
 void launch_gas_from_omega(const DevParams& P, const double* T, const double* omega, const double* alpha, double* rg,
                            double* c, hipStream_t s);

@@ -422,11 +422,14 @@ __device__ __forceinline__ void adv_store(const AdvPlane& f, double (*sF)[ATILE]
 struct AdvFaces {
   double u0, u1, v0, v1, w0, w1, c;   // u0: carried from the plane below
   double vx, wx;                      // the tile's extra faces: v above the last row, w above the last lane
+  double g1, gv0, gw0, gvx, gwx;      // geometric advection: the given liquid fluxes of those faces
 };
 __device__ __forceinline__ void adv_faces(const DevParams& P, const double* __restrict__ u,
                                           const double* __restrict__ v, const double* __restrict__ w,
                                           const double* __restrict__ c, int X, bool want, int j, int k,
-                                          bool want_vx, bool want_wx, int y0, int z0, AdvFaces& F) {
+                                          bool want_vx, bool want_wx, int y0, int z0, AdvFaces& F,
+                                          const double* __restrict__ Fx = nullptr, const double* __restrict__ Fy = nullptr,
+                                          const double* __restrict__ Fz = nullptr) {
   const int i = clampi(X, P.nx), jc = clampi(j, P.ny), kc = clampi(k, P.nz);
   const int jf = min(j, P.ny), jf1 = min(j + 1, P.ny), kf = min(k, P.nz), kf1 = min(k + 1, P.nz);
   F.u1 = want ? u[uidx(P, i + 1, jc, kc)] : 0.0;
@@ -439,6 +442,15 @@ __device__ __forceinline__ void adv_faces(const DevParams& P, const double* __re
   const int lane = threadIdx.x % MZ;
   F.vx = (want && want_vx) ? v[vidx(P, i, min(y0 + MY, P.ny), kc)] : 0.0;
   F.wx = (want && want_wx && lane < MY) ? w[widx(P, i, clampi(y0 + lane, P.ny), min(z0 + MZ, P.nz))] : 0.0;
+  if (Fx) {
+    F.g1 = want ? Fx[uidx(P, i + 1, jc, kc)] : 0.0;
+    F.gv0 = want ? Fy[vidx(P, i, jf, kc)] : 0.0;
+    F.gw0 = want ? Fz[widx(P, i, jc, kf)] : 0.0;
+    F.gvx = (want && want_vx) ? Fy[vidx(P, i, min(y0 + MY, P.ny), kc)] : 0.0;
+    F.gwx = (want && want_wx && lane < MY) ? Fz[widx(P, i, clampi(y0 + lane, P.ny), min(z0 + MZ, P.nz))] : 0.0;
+  } else {
+    F.g1 = F.gv0 = F.gw0 = F.gvx = F.gwx = 0.0;
+  }
 }
 
 // Van Leer face value on a grid line (cells m, a | b, p; face between a and b)
@@ -461,18 +473,20 @@ __device__ __forceinline__ double vl_face(double m, double a, double b, double p
 // rho_G omega_f (1 - alpha_f) u and u T_f.  A[], O[], T[] hold the four line
 // cells m, a, b, p; box: 0 interior, 1 low box face (b inside), 2 high box
 // face (a inside): the face value is the ambient one on inflow (alpha 0,
-// omega 0, T_amb), the inside cell's on outflow.
+// omega 0, T_amb), the inside cell's on outflow.  GEO: the liquid flux is
+// given (Fl, the geometric advection's) instead.
 struct FaceFlux {
   double F, G, uT;
 };
+template <bool GEO = false>
 __device__ __forceinline__ FaceFlux face_flux(const DevParams& P, const double (&A)[4], const double (&O)[4],
-                                              const double (&T)[4], double uf, double ul, int box) {
+                                              const double (&T)[4], double uf, double ul, int box, double Fl = 0.0) {
   const bool fwd = uf > 0.0;
   double af = vl_face(A[0], A[1], A[2], A[3], fwd);
   double of = vl_face(O[0], O[1], O[2], O[3], fwd);
   double al = af;
   const bool fwdl = ul > 0.0;
-  if (fwdl != fwd) al = vl_face(A[0], A[1], A[2], A[3], fwdl);
+  if (!GEO && fwdl != fwd) al = vl_face(A[0], A[1], A[2], A[3], fwdl);
   double Tf = 0.0;
   if (P.solve_energy) Tf = vl_face(T[0], T[1], T[2], T[3], fwd);
   if (box) {
@@ -484,7 +498,7 @@ __device__ __forceinline__ FaceFlux face_flux(const DevParams& P, const double (
     al = inflow_l ? 0.0 : ia;
     Tf = inflow ? P.T_amb : iT;
   }
-  return FaceFlux{ul * al, P.rho_G * of * (1.0 - af) * uf, uf * Tf};
+  return FaceFlux{GEO ? Fl : ul * al, P.rho_G * of * (1.0 - af) * uf, uf * Tf};
 }
 
 // Advection of alpha1, c and T (eq. 3 with the liquid-transport velocity,
@@ -495,12 +509,14 @@ __device__ __forceinline__ FaceFlux face_flux(const DevParams& P, const double (
 // neighbours), the last row and lane also the faces above; the faces above a
 // cell come from the neighbouring row through LDS and from the next lane by a
 // shuffle.
+template <bool GEO>
 __global__ void __launch_bounds__(BLOCK)
 k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* __restrict__ omega,
          const double* __restrict__ T, const double* __restrict__ c, const double* __restrict__ u,
          const double* __restrict__ v, const double* __restrict__ w, const double* __restrict__ phi,
          double* __restrict__ a_new, double* __restrict__ c_new, double* __restrict__ T_new, double* partials,
-         unsigned* counter, double* scal) {
+         unsigned* counter, double* scal, const double* __restrict__ Fx, const double* __restrict__ Fy,
+         const double* __restrict__ Fz) {
   __shared__ double sF[3][3][ATILE];      // slot (x mod 3), field (alpha1, omega, T)
   __shared__ double sP[3][PTILE];         // slot, phi
   __shared__ double sY[3][MY + 1][MZ];   // (F, G, uT), y face row, lane
@@ -547,15 +563,16 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
     wT[0] = pT[1];
     wP[0] = pP[1];
     AdvFaces F;
-    adv_faces(P, u, v, w, c, x0, true, j, k, ty == wave_vx, ty == wave_wx, y0, z0, F);
+    adv_faces(P, u, v, w, c, x0, true, j, k, ty == wave_vx, ty == wave_wx, y0, z0, F, Fx, Fy, Fz);
     F.u0 = u[uidx(P, x0, clampi(j, P.ny), clampi(k, P.nz))];
+    double g0 = GEO ? Fx[uidx(P, x0, clampi(j, P.ny), clampi(k, P.nz))] : 0.0;   // given liquid flux below
     // the x face below plane x0 (cells x0-2 .. x0+1)
     FaceFlux xlo;
     {
       const double ul = phi ? F.u0 - (wP[1] - wP[0]) * ih : F.u0;
       const double A4[4] = {pA[0], pA[1], wA[1], wA[2]}, O4[4] = {pO[0], pO[1], wO[1], wO[2]},
                    T4[4] = {pT[0], pT[1], wT[1], wT[2]};
-      xlo = face_flux(P, A4, O4, T4, F.u0, ul, x0 == 0 ? 1 : 0);
+      xlo = face_flux<GEO>(P, A4, O4, T4, F.u0, ul, x0 == 0 ? 1 : 0, g0);
     }
     __syncthreads();
     int slot = x0 % 3;
@@ -563,7 +580,7 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
       AdvPlane nf;
       adv_fetch(P, a1, omega, T, phi, x + 3, x + 3 <= x1 + 1, x + 3 < x1, y0, z0, nf);
       AdvFaces NF;
-      adv_faces(P, u, v, w, c, x + 1, x + 1 < x1, j, k, ty == wave_vx, ty == wave_wx, y0, z0, NF);
+      adv_faces(P, u, v, w, c, x + 1, x + 1 < x1, j, k, ty == wave_vx, ty == wave_wx, y0, z0, NF, Fx, Fy, Fz);
       const double(*S)[ATILE] = sF[slot];
       const double* SP = sP[slot];
       const int ce = (ty + 2) * AHZ + tz + 2, pe = (ty + 1) * PHZ + tz + 1;
@@ -571,11 +588,11 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
       FaceFlux xhi;
       {
         const double ul = phi ? F.u1 - (wP[2] - wP[1]) * ih : F.u1;
-        xhi = face_flux(P, wA, wO, wT, F.u1, ul, x == P.nx - 1 ? 2 : 0);
+        xhi = face_flux<GEO>(P, wA, wO, wT, F.u1, ul, x == P.nx - 1 ? 2 : 0, F.g1);
       }
       // y faces below the cell (rows j-2 .. j+1 of its column); ce_/pe_ pick
       // the column (tile centre entry) a face is evaluated for
-      auto yface = [&](int ce_, int pe_, int r0, double vf, int fpos) {
+      auto yface = [&](int ce_, int pe_, int r0, double vf, int fpos, double gl) {
         const double A4[4] = {S[0][ce_ + r0 * AHZ], S[0][ce_ + (r0 + 1) * AHZ], S[0][ce_ + (r0 + 2) * AHZ],
                               S[0][ce_ + (r0 + 3) * AHZ]};
         const double O4[4] = {S[1][ce_ + r0 * AHZ], S[1][ce_ + (r0 + 1) * AHZ], S[1][ce_ + (r0 + 2) * AHZ],
@@ -583,30 +600,30 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
         const double T4[4] = {S[2][ce_ + r0 * AHZ], S[2][ce_ + (r0 + 1) * AHZ], S[2][ce_ + (r0 + 2) * AHZ],
                               S[2][ce_ + (r0 + 3) * AHZ]};
         const double ul = phi ? vf - (SP[pe_ + (r0 + 2) * PHZ] - SP[pe_ + (r0 + 1) * PHZ]) * ih : vf;
-        return face_flux(P, A4, O4, T4, vf, ul, fpos == 0 ? 1 : (fpos == P.ny ? 2 : 0));
+        return face_flux<GEO>(P, A4, O4, T4, vf, ul, fpos == 0 ? 1 : (fpos == P.ny ? 2 : 0), gl);
       };
-      auto zface = [&](int ce_, int pe_, int c0, double wf, int fpos) {
+      auto zface = [&](int ce_, int pe_, int c0, double wf, int fpos, double gl) {
         const double A4[4] = {S[0][ce_ + c0], S[0][ce_ + c0 + 1], S[0][ce_ + c0 + 2], S[0][ce_ + c0 + 3]};
         const double O4[4] = {S[1][ce_ + c0], S[1][ce_ + c0 + 1], S[1][ce_ + c0 + 2], S[1][ce_ + c0 + 3]};
         const double T4[4] = {S[2][ce_ + c0], S[2][ce_ + c0 + 1], S[2][ce_ + c0 + 2], S[2][ce_ + c0 + 3]};
         const double ul = phi ? wf - (SP[pe_ + c0 + 2] - SP[pe_ + c0 + 1]) * ih : wf;
-        return face_flux(P, A4, O4, T4, wf, ul, fpos == 0 ? 1 : (fpos == P.nz ? 2 : 0));
+        return face_flux<GEO>(P, A4, O4, T4, wf, ul, fpos == 0 ? 1 : (fpos == P.nz ? 2 : 0), gl);
       };
-      const FaceFlux ylo = yface(ce, pe, -2, F.v0, j);
+      const FaceFlux ylo = yface(ce, pe, -2, F.v0, j, F.gv0);
       sY[0][ty][tz] = ylo.F;
       sY[1][ty][tz] = ylo.G;
       sY[2][ty][tz] = ylo.uT;
       if (ty == wave_vx) {   // the y faces above the last row (its rows y0+MY-2 .. y0+MY+1)
-        const FaceFlux yh = yface((MY + 1) * AHZ + tz + 2, MY * PHZ + tz + 1, -1, F.vx, y0 + MY);
+        const FaceFlux yh = yface((MY + 1) * AHZ + tz + 2, MY * PHZ + tz + 1, -1, F.vx, y0 + MY, F.gvx);
         sY[0][MY][tz] = yh.F;
         sY[1][MY][tz] = yh.G;
         sY[2][MY][tz] = yh.uT;
       }
       // z faces below the cell (columns k-2 .. k+1); the one above comes from the next lane
-      const FaceFlux zlo = zface(ce, pe, -2, F.w0, k);
+      const FaceFlux zlo = zface(ce, pe, -2, F.w0, k, F.gw0);
       FaceFlux zhi = {__shfl_down(zlo.F, 1, MZ), __shfl_down(zlo.G, 1, MZ), __shfl_down(zlo.uT, 1, MZ)};
       if (ty == wave_wx && tz < MY) {   // lane r: the z face above the last lane of row r
-        const FaceFlux zx = zface((tz + 2) * AHZ + MZ + 1, (tz + 1) * PHZ + MZ, -1, F.wx, z0 + MZ);
+        const FaceFlux zx = zface((tz + 2) * AHZ + MZ + 1, (tz + 1) * PHZ + MZ, -1, F.wx, z0 + MZ, F.gwx);
         sZ[0][tz] = zx.F;
         sZ[1][tz] = zx.G;
         sZ[2][tz] = zx.uT;
@@ -1264,10 +1281,15 @@ void launch_source(const DevParams& P, const double* alpha, const double* mraw, 
 void launch_advect(const DevParams& P, const double* a1, const double* omega, const double* T,
                    const double* c, const double* u, const double* v, const double* w, const double* phi,
                    double* a_new, double* c_new, double* T_new, double* partials, unsigned* counter, double* scal,
-                   hipStream_t s) {
+                   hipStream_t s, const double* Fx, const double* Fy, const double* Fz) {
   int nb;
   const MarchGeom G = march_geom(P, nb);
-  k_advect<<<nb, BLOCK, 0, s>>>(P, G, a1, omega, T, c, u, v, w, phi, a_new, c_new, T_new, partials, counter, scal);
+  if (Fx)   // the liquid fluxes are given (geometric advection): no potential tile needed
+    k_advect<true><<<nb, BLOCK, 0, s>>>(P, G, a1, omega, T, c, u, v, w, nullptr, a_new, c_new, T_new, partials,
+                                        counter, scal, Fx, Fy, Fz);
+  else
+    k_advect<false><<<nb, BLOCK, 0, s>>>(P, G, a1, omega, T, c, u, v, w, phi, a_new, c_new, T_new, partials,
+                                         counter, scal, nullptr, nullptr, nullptr);
 }
 void launch_energy_setup(const DevParams& P, const double* a_new, const double* T_prime,
                          const double* mdot, const double* u, const double* v, const double* w,
