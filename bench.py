@@ -304,6 +304,8 @@ def main():
     ap.add_argument("--no-variable-gas", action="store_true",
                     help="skip the leg that times the workload with the variable-density gas (eq. 24 per cell, "
                          "eq. 7's compressibility term)")
+    ap.add_argument("--no-geometric", action="store_true",
+                    help="skip the leg that times the workload with the geometric interface advection")
     ap.add_argument("--counters-pass", action="store_true",
                     help="short run for hardware-counter passes: one step of the workload, 5 replayed launches of "
                          "the fine-level sweep, then 3 device copies of 1 GiB (the counter calibration)")
@@ -434,6 +436,18 @@ def main():
             "volume_rel_diff_vs_ambient_gas": abs(var["volume"] - mixed["volume"]) / mixed["volume"],
             "note": "the same workload with rho_G from eq. 24 per cell (Peng-Robinson mixture) and eq. 7's "
                     "compressibility term; not the headline configuration, which states constant properties",
+        }
+    if not args.no_geometric:
+        log(f"geometric interface advection, precision form: warmup {args.warmup}, timing {args.steps} steps")
+        geo = timed_run(ds, torch, dict(prm, precision=W.PREC_MIXED, advection=1), fields, args.steps, args.warmup)
+        log(f"  {geo['seconds'] * 1e3 / args.steps:.2f} ms/step, iters {geo['iters'][-1]}")
+        out["geometric_advection"] = {
+            "value": ncell * args.steps / geo["seconds"], "ms_per_step": geo["seconds"] * 1e3 / args.steps,
+            "iters_T_omega_p_rounds_phi": geo["iters"][-1],
+            "volume_rel_diff_vs_flux_limited": abs(geo["volume"] - mixed["volume"]) / mixed["volume"],
+            "alpha_min": geo["diag"]["alpha_min"], "alpha_max": geo["diag"]["alpha_max"],
+            "note": "the same workload with the liquid advected geometrically (a plane per surface cell, swept "
+                    "face areas); not the headline configuration, which prescribes the flux-limited scheme",
         }
     if not args.no_adjoint:
         log("adjoint cost: 96^3, 100 steps")

@@ -354,8 +354,10 @@ int ds_time_operator_kernel(ds_grid* g, int reps, double* avg_us, double* bytes_
  * first solve and carries no derivative.
  *
  * Memory: the tape is caller-owned device memory (256-byte aligned) of
- * ds_tape_bytes() bytes holding the adjoint arrays (about 25 arrays of the
- * grid) and the stored states: a checkpoint every ckpt_every steps, the final
+ * ds_tape_bytes() bytes holding the adjoint arrays (about 36 arrays of the
+ * grid, with the interface stage's per-cell records, which are summed per
+ * target in a fixed order: the reverse sweep is bitwise reproducible) and the
+ * stored states: a checkpoint every ckpt_every steps, the final
  * state, and ckpt_every-1 segment states recomputed during the reverse sweep
  * (about 10 arrays of the grid per stored state).  ckpt_every = 1 stores every
  * state and recomputes none; larger values trade one extra forward pass for

@@ -151,6 +151,7 @@ struct ds_grid {
   double *A_cp = nullptr, *A_Tp = nullptr, *A_a1 = nullptr, *lam = nullptr, *grad = nullptr;
   double *A_U[3] = {}, *A_Us[3] = {}, *A_Ul[3] = {}, *Q[6] = {};
   double* h_grad = nullptr;          // pinned host mirror of grad
+  IfaceRecords irec{};               // records of the adjoint interface stage (tape arrays)
   int adj_iters[4] = {0, 0, 0, 0};   // adjoint solve iterations: p, omega, T, phi (last ds_adjoint)
 };
 
@@ -319,7 +320,7 @@ size_t tape_adjoint_bytes(const ds_grid* g) {
   const size_t cb = align256(g->n * sizeof(double));
   const size_t fb = align256(g->nu * sizeof(double)) + align256(g->nv * sizeof(double)) +
                     align256(g->nw * sizeof(double));
-  return 10 * cb + 5 * fb + align256(GR_COUNT * sizeof(double));
+  return 21 * cb + 5 * fb + align256(GR_COUNT * sizeof(double)) + align256(sizeof(unsigned));
 }
 
 size_t tape_total_bytes(const ds_grid* g, int nsteps, int ckpt) {
@@ -350,6 +351,14 @@ void carve_tape(ds_grid* g, char* base) {
     g->Q[2 * a + 1] = L.take<double>(base, nf[a]);
   }
   g->grad = L.take<double>(base, GR_COUNT);
+  // the interface stage's records (gathered per target in a fixed order)
+  IfaceRecords& R = g->irec;
+  for (int q = 0; q < 3; ++q) R.gb[q] = L.take<double>(base, n);
+  R.om = L.take<double>(base, n);
+  for (int q = 0; q < 3; ++q) R.f[q] = L.take<double>(base, n);
+  for (int q = 0; q < 3; ++q) R.gsf[q] = L.take<double>(base, n);
+  R.hit = L.take<double>(base, n);
+  R.rmax = L.take<unsigned>(base, 1);
   g->tape_slot_off = L.off;
 }
 
@@ -1137,7 +1146,7 @@ int reverse_step(ds_grid* g, const Slot& cur, const Slot& nxt, hipStream_t s, in
   launch_adj_source(P, cur.alpha, g->mraw, g->A_a1, g->A_md, g->A_al, g->scal, g->partials, cadj, g->grad, s);
   if (P.evaporation)
     launch_adj_interface(P, cur.alpha, cur.T, cur.omega, cur.u, cur.v, cur.w, g->mraw, g->adj, g->A_md, g->scal,
-                         g->A_al, g->A_T, g->A_om, g->A_U, g->partials, cadj, g->grad, s);
+                         g->A_al, g->A_T, g->A_om, g->A_U, g->irec, g->partials, cadj, g->grad, s);
   HIPCHK(g, hipGetLastError());
   return DS_OK;
 }

@@ -154,10 +154,20 @@ void launch_adj_phi_faces(const DevParams& P, double* const AUl[3], const double
 void launch_adj_source(const DevParams& P, const double* alpha, const double* mraw, const double* A_a1, double* A_md,
                        double* A_al, const double* scal, double* partials, unsigned* counter, double* grad,
                        hipStream_t s);
+// Per-cell records of the adjoint interface stage (tape arrays): see k_adjoint.hip.
+struct IfaceRecords {
+  double* gb[3];    // to alpha of the neighbours -+q
+  double* om;       // to omega of adj
+  double* f[3];     // to each of adj's two q faces
+  double* gsf[3];   // per adj cell: sum of its band cells' f[q]
+  double* hit;      // 1 where a band cell's adj is this cell
+  unsigned* rmax;   // largest march distance (cells, Chebyshev)
+};
 void launch_adj_interface(const DevParams& P, const double* alpha, const double* T, const double* omega,
                           const double* u, const double* v, const double* w, const double* mraw, const int* adj,
                           const double* A_md, const double* scal, double* A_al, double* A_T, double* A_om,
-                          double* const AU[3], double* partials, unsigned* counter, double* grad, hipStream_t s);
+                          double* const AU[3], const IfaceRecords& R, double* partials, unsigned* counter,
+                          double* grad, hipStream_t s);
 void launch_adj_init_c(const DevParams& P, const double* alpha, const double* omega, const double* A_c, double* A_al,
                        double* A_om, double* partials, unsigned* counter, double* grad, hipStream_t s);
 void launch_int_to_double(const int* src, double* dst, long long n, hipStream_t s);

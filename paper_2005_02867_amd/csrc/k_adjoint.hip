@@ -12,8 +12,11 @@
 // forward operators, all symmetric); the species solve uses the identity
 // c^{n+1} = rho_G theta omega~ that holds for an exact solve.
 //
-// Most kernels gather (one thread per output cell or face, no atomics).  The
-// interface stage scatters from the few band cells with FP64 atomics.
+// Every kernel gathers (one thread per output cell or face, no floating-point
+// atomics), so the reverse sweep is bitwise reproducible.  The interface
+// stage, whose band cells feed their adj cell and neighbours, writes each
+// band cell's contributions into per-cell records; two gather passes then
+// sum them per target in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include "ds_device.h"
@@ -751,14 +754,16 @@ __global__ void k_adj_source(DevParams P, const double* __restrict__ alpha, cons
 // Band cells with an adj: mdotbar -> mrawbar (through K and f), then the
 // flux j.n at adj (eqs. 12-14, 17): omega_sat(T_int) (T, dh), omega_adj,
 // the adj cell velocity, the normal and |grad alpha| (six alpha neighbours),
-// D and rho_G.  Scatters with FP64 atomics.
+// D and rho_G.  The band cell's own alpha and T terms are added in place;
+// what goes to other cells is recorded: R.gb[q] (to alpha of the neighbours
+// +-q), R.om (to omega of adj), R.f[q] (to each of adj's two q faces), and
+// adj is marked in R.hit, its march distance maxed into R.rmax.
 __global__ void k_adj_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
                                 const double* __restrict__ omega, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
                                 const double* __restrict__ mraw, const int* __restrict__ adj,
                                 const double* __restrict__ A_md, const double* __restrict__ scal,
-                                double* __restrict__ A_al, double* __restrict__ A_T, double* __restrict__ A_om,
-                                double* __restrict__ Au, double* __restrict__ Av, double* __restrict__ Aw,
+                                double* __restrict__ A_al, double* __restrict__ A_T, IfaceRecords R,
                                 double* partials, unsigned* counter, double* grad) {
   long long b0, b1;
   block_range(P.n, b0, b1);
@@ -776,7 +781,7 @@ __global__ void k_adj_interface(DevParams P, const double* __restrict__ alpha, c
     const double md = A_md[c];
     const double mb = md * K * f + S1b + S2b * f;
     const double fb = md * K * m + S2b * m;
-    if (f > 0.0) unsafeAtomicAdd(&A_al[c], fb * (1.0 - 2.0 * a) / (2.0 * f));
+    if (f > 0.0) A_al[c] += fb * (1.0 - 2.0 * a) / (2.0 * f);
     // geometry (same values as the forward)
     const double dx = __dsub_rn(alpha_or0(P, alpha, i + 1, j, k), alpha_or0(P, alpha, i - 1, j, k));
     const double dy = __dsub_rn(alpha_or0(P, alpha, i, j + 1, k), alpha_or0(P, alpha, i, j - 1, k));
@@ -807,28 +812,108 @@ __global__ void k_adj_interface(DevParams P, const double* __restrict__ alpha, c
     acc[1] += wsb * dws_dy * dydh;
     acc[0] += jb * P.rho_G * (ws - wa) / d;
     acc[2] += jb * jn / P.rho_G;
-    unsafeAtomicAdd(&A_om[hit], jb * P.rho_G * (va - P.D / d));
+    R.om[c] = jb * P.rho_G * (va - P.D / d);
     const double vab = jb * P.rho_G * wa;
-    unsafeAtomicAdd(&Au[fu[0]], 0.5 * vab * n[0]);
-    unsafeAtomicAdd(&Au[fu[1]], 0.5 * vab * n[0]);
-    unsafeAtomicAdd(&Av[fv[0]], 0.5 * vab * n[1]);
-    unsafeAtomicAdd(&Av[fv[1]], 0.5 * vab * n[1]);
-    unsafeAtomicAdd(&Aw[fw[0]], 0.5 * vab * n[2]);
-    unsafeAtomicAdd(&Aw[fw[1]], 0.5 * vab * n[2]);
+    R.f[0][c] = 0.5 * vab * n[0];
+    R.f[1][c] = 0.5 * vab * n[1];
+    R.f[2][c] = 0.5 * vab * n[2];
+    R.hit[hit] = 1.0;
+    const int dist = max(abs(ti - i), max(abs(tj - j), abs(tk - k)));
+    atomicMax(R.rmax, (unsigned)dist);
     const double nb[3] = {vab * vc[0], vab * vc[1], vab * vc[2]};
     const double ndot = nb[0] * n[0] + nb[1] * n[1] + nb[2] * n[2];
     double gb[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) gb[q] = -(nb[q] - n[q] * ndot) / nrm - nrmb * n[q];
-    if (i + 1 < P.nx) unsafeAtomicAdd(&A_al[cidx(P, i + 1, j, k)], gb[0]);
-    if (i - 1 >= 0) unsafeAtomicAdd(&A_al[cidx(P, i - 1, j, k)], -gb[0]);
-    if (j + 1 < P.ny) unsafeAtomicAdd(&A_al[cidx(P, i, j + 1, k)], gb[1]);
-    if (j - 1 >= 0) unsafeAtomicAdd(&A_al[cidx(P, i, j - 1, k)], -gb[1]);
-    if (k + 1 < P.nz) unsafeAtomicAdd(&A_al[cidx(P, i, j, k + 1)], gb[2]);
-    if (k - 1 >= 0) unsafeAtomicAdd(&A_al[cidx(P, i, j, k - 1)], -gb[2]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) R.gb[q][c] = gb[q];
   }
   const int slot[3] = {GR_D, GR_DH, GR_RHOG};
   grad_add<3>(acc, slot, partials, counter, grad);
+}
+
+// Before the interface stage: no cell is an adj yet, march distance 0.
+__global__ void k_adj_iface_clear(DevParams P, IfaceRecords R) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) R.hit[e] = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *R.rmax = 0u;
+}
+
+// Gather of the interface records, per cell e in a fixed order: alpha from
+// the band neighbours' gb (the lower neighbour along q adds gb[q], the upper
+// one subtracts it); if e is an adj cell, omega from every band cell within
+// the largest march distance whose adj is e (scanned in i, j, k order), and
+// the sums of their face records, kept for the face pass.
+__global__ void k_adj_iface_gather(DevParams P, const int* __restrict__ adj, IfaceRecords R,
+                                   double* __restrict__ A_al, double* __restrict__ A_om) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  const int rm = (int)*R.rmax;
+  const long long st[3] = {(long long)P.ny * P.nz, (long long)P.nz, 1};
+  const int nn[3] = {P.nx, P.ny, P.nz};
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+    int i, j, k;
+    decode(P, e, i, j, k);
+    const int pos[3] = {i, j, k};
+    double acc = 0.0;
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (pos[q] > 0 && adj[e - st[q]] >= 0) {
+        acc += R.gb[q][e - st[q]];
+        any = true;
+      }
+      if (pos[q] < nn[q] - 1 && adj[e + st[q]] >= 0) {
+        acc -= R.gb[q][e + st[q]];
+        any = true;
+      }
+    }
+    if (any) A_al[e] += acc;
+    if (R.hit[e] == 0.0) continue;
+    double som = 0.0, sf[3] = {0.0, 0.0, 0.0};
+    for (int ci = max(i - rm, 0); ci <= min(i + rm, P.nx - 1); ++ci)
+      for (int cj = max(j - rm, 0); cj <= min(j + rm, P.ny - 1); ++cj)
+        for (int ck = max(k - rm, 0); ck <= min(k + rm, P.nz - 1); ++ck) {
+          const long long c = cidx(P, ci, cj, ck);
+          if (adj[c] != (int)e) continue;
+          som += R.om[c];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) sf[q] += R.f[q][c];
+        }
+    A_om[e] += som;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) R.gsf[q][e] = sf[q];
+  }
+}
+
+// Face pass: each face of an adj cell gets that cell's face sum; a face
+// between two adj cells gets the lower one's, then the upper one's.  The
+// thread of the cell below a face (of the cell above, for a low box face)
+// writes it.
+__global__ void k_adj_iface_faces(DevParams P, IfaceRecords R, double* __restrict__ Au, double* __restrict__ Av,
+                                  double* __restrict__ Aw) {
+  long long b0, b1;
+  block_range(P.n, b0, b1);
+  double* const AU[3] = {Au, Av, Aw};
+  const long long st[3] = {(long long)P.ny * P.nz, (long long)P.nz, 1};
+  const int nn[3] = {P.nx, P.ny, P.nz};
+  for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
+    int i, j, k;
+    decode(P, e, i, j, k);
+    const int pos[3] = {i, j, k};
+    const bool me = R.hit[e] != 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const long long lo = q == 0 ? uidx(P, i, j, k) : (q == 1 ? vidx(P, i, j, k) : widx(P, i, j, k));
+      const long long hi = q == 0 ? uidx(P, i + 1, j, k) : (q == 1 ? vidx(P, i, j + 1, k) : widx(P, i, j, k + 1));
+      if (pos[q] == 0 && me) AU[q][lo] += R.gsf[q][e];
+      const bool up = pos[q] < nn[q] - 1 && R.hit[e + st[q]] != 0.0;
+      if (me && up) AU[q][hi] += R.gsf[q][e] + R.gsf[q][e + st[q]];
+      else if (me) AU[q][hi] += R.gsf[q][e];
+      else if (up) AU[q][hi] += R.gsf[q][e + st[q]];
+    }
+  }
 }
 
 // ---------------------------------------------------------------- initial vapour c^0 = rho_G theta omega^0
@@ -931,9 +1016,14 @@ void launch_adj_source(const DevParams& P, const double* alpha, const double* mr
 void launch_adj_interface(const DevParams& P, const double* alpha, const double* T, const double* omega,
                           const double* u, const double* v, const double* w, const double* mraw, const int* adj,
                           const double* A_md, const double* scal, double* A_al, double* A_T, double* A_om,
-                          double* const AU[3], double* partials, unsigned* counter, double* grad, hipStream_t s) {
-  k_adj_interface<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, alpha, T, omega, u, v, w, mraw, adj, A_md, scal, A_al, A_T,
-                                                     A_om, AU[0], AU[1], AU[2], partials, counter, grad);
+                          double* const AU[3], const IfaceRecords& R, double* partials, unsigned* counter,
+                          double* grad, hipStream_t s) {
+  const int nb = grid_blocks(P.n);
+  k_adj_iface_clear<<<nb, BLOCK, 0, s>>>(P, R);
+  k_adj_interface<<<nb, BLOCK, 0, s>>>(P, alpha, T, omega, u, v, w, mraw, adj, A_md, scal, A_al, A_T, R, partials,
+                                       counter, grad);
+  k_adj_iface_gather<<<nb, BLOCK, 0, s>>>(P, adj, R, A_al, A_om);
+  k_adj_iface_faces<<<nb, BLOCK, 0, s>>>(P, R, AU[0], AU[1], AU[2]);
 }
 void launch_adj_init_c(const DevParams& P, const double* alpha, const double* omega, const double* A_c, double* A_al,
                        double* A_om, double* partials, unsigned* counter, double* grad, hipStream_t s) {

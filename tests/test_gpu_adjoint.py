@@ -93,10 +93,30 @@ def test_checkpointing_gives_the_same_gradient_and_final_state():
         assert V == V0 and nxt == nxt0
         for k in fin0:
             assert torch.equal(fin[k], fin0[k]), k
+        # the recomputed segments equal the stored states bit for bit, and the
+        # reverse sweep sums in a fixed order: the gradients are bitwise equal
         for k in ("D_v", "dh_ev", "T_amb"):
-            assert r[k] == pytest.approx(r0[k], rel=1e-12), k
+            assert r[k] == r0[k], k
         for k in FIELDS:
-            assert _rel(r["fields"][k], r0["fields"][k]) <= 1e-12, k
+            assert torch.equal(r["fields"][k], r0["fields"][k]), k
+
+
+def test_adjoint_bitwise_reproducible():
+    """Two independent forward-record + adjoint runs of a 40^3 droplet (20 bar,
+    Peng-Robinson, natural convection, 4 steps; hundreds of band cells share an
+    adj cell) give bitwise identical gradients: every stage gathers, the
+    interface stage through per-cell records summed per target in a fixed
+    order."""
+    prm, run = W.scaled("C3", 40)
+    prm = dict(prm, precision=W.PREC_FP64)
+    f = W.initial_fields(prm, D0=1.0e-3, seed=1, T_noise=0.02)
+    print("adjoint run-to-run: 40^3, 4 steps, twice", flush=True)
+    outs = [_gpu_adjoint(prm, f, 4, 2)[2] for _ in range(2)]
+    for k in ("D_v", "dh_ev", "T_amb"):
+        assert outs[0][k] == outs[1][k], k
+    for k in FIELDS:
+        assert torch.equal(outs[0]["fields"][k], outs[1]["fields"][k]), k
+    assert float(outs[0]["fields"]["alpha"].abs().max()) > 0.0
 
 
 def test_autograd_function_chains_the_initial_temperature():
