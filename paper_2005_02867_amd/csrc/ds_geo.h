@@ -41,17 +41,17 @@ template <class F>
 __device__ __forceinline__ double geo_simpson(F f, double t0, double t1, double (&br)[4]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) br[q] = fmin(fmax(br[q], t0), t1);
-  // sort the four (insertion)
-#pragma unroll
-  for (int q = 1; q < 4; ++q) {
-    const double v = br[q];
-    int r = q - 1;
-    while (r >= 0 && br[r] > v) {
-      br[r + 1] = br[r];
-      --r;
-    }
-    br[r + 1] = v;
-  }
+  // sort the four (a five-comparator network: fixed indices, no private array)
+  auto cs = [](double& x, double& y) {
+    const double lo = fmin(x, y), hi = fmax(x, y);
+    x = lo;
+    y = hi;
+  };
+  cs(br[0], br[1]);
+  cs(br[2], br[3]);
+  cs(br[0], br[2]);
+  cs(br[1], br[3]);
+  cs(br[1], br[2]);
   const double pts[6] = {t0, br[0], br[1], br[2], br[3], t1};
   double tot = 0.0;
 #pragma unroll

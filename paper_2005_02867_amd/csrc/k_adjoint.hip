@@ -157,7 +157,7 @@ __device__ __forceinline__ double div_transpose(const DevParams& P, const double
 // ---------------------------------------------------------------- projection (S11)
 // pbar (right-hand side of the adjoint pressure system) and the projection's
 // share of abar through beta = 1/rho.
-__global__ void k_adj_project(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
+__global__ void __launch_bounds__(BLOCK) k_adj_project(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
                               const double* __restrict__ Au, const double* __restrict__ Av,
                               const double* __restrict__ Aw, double* __restrict__ b, double* __restrict__ A_ab,
                               double* partials, unsigned* counter, double* grad) {
@@ -204,7 +204,7 @@ __global__ void k_adj_project(DevParams P, const double* __restrict__ a_new, con
 
 // ---------------------------------------------------------------- pressure (S10)
 // With lam = A_p^-1 pbar: operator coefficients (beta), source mdot and rho_G.
-__global__ void k_adj_pressure(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
+__global__ void __launch_bounds__(BLOCK) k_adj_pressure(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
                                const double* __restrict__ lam, const double* __restrict__ mdot,
                                double* __restrict__ A_ab, double* __restrict__ A_md, double* partials,
                                unsigned* counter, double* grad) {
@@ -262,7 +262,7 @@ struct QPtrs {
 // Ubar* = Ubar^{n+1} + (transpose of -div) lam_p on every face; the
 // transverse-advection weights q_{AX,b} = -dt Ubar* d_b / 4 on interior faces.
 template <int AX>
-__global__ void k_adj_pred_a(DevParams P, const double* __restrict__ A_U, const double* __restrict__ lam,
+__global__ void __launch_bounds__(BLOCK) k_adj_pred_a(DevParams P, const double* __restrict__ A_U, const double* __restrict__ lam,
                              const double* __restrict__ u, const double* __restrict__ v,
                              const double* __restrict__ w, double* __restrict__ A_Us, double* __restrict__ q0,
                              double* __restrict__ q1) {
@@ -307,7 +307,7 @@ __global__ void k_adj_pred_a(DevParams P, const double* __restrict__ A_U, const 
 // copy on open box faces), the transposed same-component advection, and the
 // transverse-velocity weights of the other two components.
 template <int AX>
-__global__ void k_adj_pred_b(DevParams P, const double* __restrict__ A_Us, const double* __restrict__ u,
+__global__ void __launch_bounds__(BLOCK) k_adj_pred_b(DevParams P, const double* __restrict__ A_Us, const double* __restrict__ u,
                              const double* __restrict__ v, const double* __restrict__ w, QPtrs Q,
                              double* __restrict__ A_U) {
   const int fx = P.nx + (AX == 0), fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
@@ -398,7 +398,7 @@ __global__ void k_adj_pred_b(DevParams P, const double* __restrict__ A_Us, const
 
 // Body forces of the predictor (gravity in p_rgh form, centripetal force):
 // their share of abar and rho_G, one thread per cell over its six faces.
-__global__ void k_adj_pred_force(DevParams P, const double* __restrict__ a_new, const double* __restrict__ xi,
+__global__ void __launch_bounds__(BLOCK) k_adj_pred_force(DevParams P, const double* __restrict__ a_new, const double* __restrict__ xi,
                                  const double* __restrict__ Usu, const double* __restrict__ Usv,
                                  const double* __restrict__ Usw, double* __restrict__ A_ab, double* partials,
                                  unsigned* counter, double* grad) {
@@ -448,7 +448,7 @@ __global__ void k_adj_pred_force(DevParams P, const double* __restrict__ a_new, 
 // Right-hand side of the adjoint species system: omega~bar = omegabar^{n+1}
 // + rho_G theta cbar^{n+1} (c^{n+1} = rho_G theta omega~), and the direct
 // theta and rho_G shares of c^{n+1}.
-__global__ void k_adj_species_rhs(DevParams P, const double* __restrict__ a_new, const double* __restrict__ omt,
+__global__ void __launch_bounds__(BLOCK) k_adj_species_rhs(DevParams P, const double* __restrict__ a_new, const double* __restrict__ omt,
                                   const double* __restrict__ A_om, const double* __restrict__ A_c,
                                   double* __restrict__ b, double* __restrict__ A_ab, double* partials,
                                   unsigned* counter, double* grad) {
@@ -469,7 +469,7 @@ __global__ void k_adj_species_rhs(DevParams P, const double* __restrict__ a_new,
 
 // With lam = A_S^-1 omega~bar: cbar' = lam/dt, mdotbar += lam, and the
 // operator's derivatives in theta, D and rho_G.
-__global__ void k_adj_species(DevParams P, const double* __restrict__ a_new, const double* __restrict__ omt,
+__global__ void __launch_bounds__(BLOCK) k_adj_species(DevParams P, const double* __restrict__ a_new, const double* __restrict__ omt,
                               const double* __restrict__ lam, const double* __restrict__ u,
                               const double* __restrict__ v, const double* __restrict__ w,
                               double* __restrict__ A_ab, double* __restrict__ A_cp, double* __restrict__ A_md,
@@ -516,7 +516,7 @@ __global__ void k_adj_species(DevParams P, const double* __restrict__ a_new, con
 // ---------------------------------------------------------------- energy (S7)
 // With lam = A_T^-1 Tbar^{n+1}: Tbar' = m lam, mdotbar -= dh lam, the mass
 // and conductivity derivatives, dh and T_amb (Dirichlet faces).
-__global__ void k_adj_energy(DevParams P, const double* __restrict__ a_new, const double* __restrict__ Tp,
+__global__ void __launch_bounds__(BLOCK) k_adj_energy(DevParams P, const double* __restrict__ a_new, const double* __restrict__ Tp,
                              const double* __restrict__ Tn, const double* __restrict__ lam,
                              const double* __restrict__ mdot, const double* __restrict__ u,
                              const double* __restrict__ v, const double* __restrict__ w,
@@ -561,7 +561,7 @@ __global__ void k_adj_energy(DevParams P, const double* __restrict__ a_new, cons
 // Ubar_liq = Fbar alpha_f (or straight into Ubar without the liquid
 // transport potential); rho_G and the inflow T_amb.
 template <int AX>
-__global__ void k_adj_adv_faces(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
+__global__ void __launch_bounds__(BLOCK) k_adj_adv_faces(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
                                 const double* __restrict__ T, const double* __restrict__ uu,
                                 const double* __restrict__ phi, const double* __restrict__ a_new,
                                 const double* __restrict__ A_al, const double* __restrict__ A_ab,
@@ -613,7 +613,7 @@ __global__ void k_adj_adv_faces(DevParams P, const double* __restrict__ a1, cons
 
 // Cell part (gather over the faces within two cells along each axis):
 // alpha1bar, omegabar^n, Tbar^n (and cbar^n = cbar').
-__global__ void k_adj_adv_cells(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
+__global__ void __launch_bounds__(BLOCK) k_adj_adv_cells(DevParams P, const double* __restrict__ a1, const double* __restrict__ omega,
                                 const double* __restrict__ T, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
                                 const double* __restrict__ phi, const double* __restrict__ a_new,
@@ -676,7 +676,7 @@ __global__ void k_adj_adv_cells(DevParams P, const double* __restrict__ a1, cons
 
 // Right-hand side of the adjoint liquid-transport potential system:
 // phibar from Ubar_liq (u_liq = u - G phi, phi = 0 half a cell outside open faces).
-__global__ void k_adj_phi_rhs(DevParams P, const double* __restrict__ Ulu, const double* __restrict__ Ulv,
+__global__ void __launch_bounds__(BLOCK) k_adj_phi_rhs(DevParams P, const double* __restrict__ Ulu, const double* __restrict__ Ulv,
                               const double* __restrict__ Ulw, double* __restrict__ b) {
   long long b0, b1;
   block_range(P.n, b0, b1);
@@ -702,7 +702,7 @@ __global__ void k_adj_phi_rhs(DevParams P, const double* __restrict__ Ulu, const
 
 // Ubar += Ubar_liq + (transpose of -div) lam_phi.
 template <int AX>
-__global__ void k_adj_phi_faces(DevParams P, const double* __restrict__ A_Ul, const double* __restrict__ lam,
+__global__ void __launch_bounds__(BLOCK) k_adj_phi_faces(DevParams P, const double* __restrict__ A_Ul, const double* __restrict__ lam,
                                 double* __restrict__ A_U) {
   const int fx = P.nx + (AX == 0), fy = P.ny + (AX == 1), fz = P.nz + (AX == 2);
   const long long nf = (long long)fx * fy * fz;
@@ -722,7 +722,7 @@ __global__ void k_adj_phi_faces(DevParams P, const double* __restrict__ A_Ul, co
 // ---------------------------------------------------------------- source (eq. 4) and redistribution (eqs. 19-21)
 // alphabar^n = alpha1bar, mdotbar -= dt alpha1bar / rho_L, and
 // Kbar = sum mdotbar f mraw -> S1bar = Kbar/S2, S2bar = -Kbar S1/S2^2.
-__global__ void k_adj_source(DevParams P, const double* __restrict__ alpha, const double* __restrict__ mraw,
+__global__ void __launch_bounds__(BLOCK) k_adj_source(DevParams P, const double* __restrict__ alpha, const double* __restrict__ mraw,
                              const double* __restrict__ A_a1, double* __restrict__ A_md,
                              double* __restrict__ A_al, const double* __restrict__ scal, double* partials,
                              unsigned* counter, double* grad) {
@@ -758,7 +758,7 @@ __global__ void k_adj_source(DevParams P, const double* __restrict__ alpha, cons
 // what goes to other cells is recorded: R.gb[q] (to alpha of the neighbours
 // +-q), R.om (to omega of adj), R.f[q] (to each of adj's two q faces), and
 // adj is marked in R.hit, its march distance maxed into R.rmax.
-__global__ void k_adj_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
+__global__ void __launch_bounds__(BLOCK) k_adj_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
                                 const double* __restrict__ omega, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
                                 const double* __restrict__ mraw, const int* __restrict__ adj,
@@ -833,7 +833,7 @@ __global__ void k_adj_interface(DevParams P, const double* __restrict__ alpha, c
 }
 
 // Before the interface stage: no cell is an adj yet, march distance 0.
-__global__ void k_adj_iface_clear(DevParams P, IfaceRecords R) {
+__global__ void __launch_bounds__(BLOCK) k_adj_iface_clear(DevParams P, IfaceRecords R) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) R.hit[e] = 0.0;
@@ -845,7 +845,7 @@ __global__ void k_adj_iface_clear(DevParams P, IfaceRecords R) {
 // one subtracts it); if e is an adj cell, omega from every band cell within
 // the largest march distance whose adj is e (scanned in i, j, k order), and
 // the sums of their face records, kept for the face pass.
-__global__ void k_adj_iface_gather(DevParams P, const int* __restrict__ adj, IfaceRecords R,
+__global__ void __launch_bounds__(BLOCK) k_adj_iface_gather(DevParams P, const int* __restrict__ adj, IfaceRecords R,
                                    double* __restrict__ A_al, double* __restrict__ A_om) {
   long long b0, b1;
   block_range(P.n, b0, b1);
@@ -891,7 +891,7 @@ __global__ void k_adj_iface_gather(DevParams P, const int* __restrict__ adj, Ifa
 // between two adj cells gets the lower one's, then the upper one's.  The
 // thread of the cell below a face (of the cell above, for a low box face)
 // writes it.
-__global__ void k_adj_iface_faces(DevParams P, IfaceRecords R, double* __restrict__ Au, double* __restrict__ Av,
+__global__ void __launch_bounds__(BLOCK) k_adj_iface_faces(DevParams P, IfaceRecords R, double* __restrict__ Au, double* __restrict__ Av,
                                   double* __restrict__ Aw) {
   long long b0, b1;
   block_range(P.n, b0, b1);
@@ -917,7 +917,7 @@ __global__ void k_adj_iface_faces(DevParams P, IfaceRecords R, double* __restric
 }
 
 // ---------------------------------------------------------------- initial vapour c^0 = rho_G theta omega^0
-__global__ void k_adj_init_c(DevParams P, const double* __restrict__ alpha, const double* __restrict__ omega,
+__global__ void __launch_bounds__(BLOCK) k_adj_init_c(DevParams P, const double* __restrict__ alpha, const double* __restrict__ omega,
                              const double* __restrict__ A_c, double* __restrict__ A_al, double* __restrict__ A_om,
                              double* partials, unsigned* counter, double* grad) {
   long long b0, b1;

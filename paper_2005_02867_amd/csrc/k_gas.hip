@@ -17,7 +17,7 @@ __device__ __forceinline__ double gas_theta(const DevParams& P, double a) {
 }
 
 // rho_G = eq. 24 at (T, omega), c = rho_G theta omega (a state from omega).
-__global__ void k_gas_from_omega(DevParams P, const double* __restrict__ T, const double* __restrict__ omega,
+__global__ void __launch_bounds__(BLOCK) k_gas_from_omega(DevParams P, const double* __restrict__ T, const double* __restrict__ omega,
                                  const double* __restrict__ alpha, double* __restrict__ rg, double* __restrict__ c) {
   long long b0, b1;
   block_range(P.n, b0, b1);
@@ -29,7 +29,7 @@ __global__ void k_gas_from_omega(DevParams P, const double* __restrict__ T, cons
 }
 
 // q = rho_G omega: the vapour mass per unit gas volume the advection carries.
-__global__ void k_gas_partial(DevParams P, const double* __restrict__ omega, const double* __restrict__ rg,
+__global__ void __launch_bounds__(BLOCK) k_gas_partial(DevParams P, const double* __restrict__ omega, const double* __restrict__ rg,
                               double* __restrict__ q) {
   long long b0, b1;
   block_range(P.n, b0, b1);
@@ -37,7 +37,7 @@ __global__ void k_gas_partial(DevParams P, const double* __restrict__ omega, con
 }
 
 // rho_G of the advected state (T', c', alpha').
-__global__ void k_gas_invert(DevParams P, const double* __restrict__ T, const double* __restrict__ c,
+__global__ void __launch_bounds__(BLOCK) k_gas_invert(DevParams P, const double* __restrict__ T, const double* __restrict__ c,
                              const double* __restrict__ alpha, double* __restrict__ rg) {
   long long b0, b1;
   block_range(P.n, b0, b1);
@@ -50,7 +50,7 @@ __global__ void k_gas_invert(DevParams P, const double* __restrict__ T, const do
 
 // End of the step: (omega, rho_G) from (T^{n+1}, c^{n+1}, alpha') and the
 // compressibility term (1 - alpha') log1p((rho^{n+1} - rho')/rho')/dt.
-__global__ void k_gas_end(DevParams P, const double* __restrict__ T, const double* __restrict__ c,
+__global__ void __launch_bounds__(BLOCK) k_gas_end(DevParams P, const double* __restrict__ T, const double* __restrict__ c,
                           const double* __restrict__ alpha, const double* __restrict__ rg_adv,
                           double* __restrict__ omega, double* __restrict__ rg, double* __restrict__ scomp) {
   long long b0, b1;

@@ -22,7 +22,7 @@ namespace dsv {
 
 namespace {
 
-__global__ void k_liquid_faces(DevParams P, const double* __restrict__ u, const double* __restrict__ v,
+__global__ void __launch_bounds__(BLOCK) k_liquid_faces(DevParams P, const double* __restrict__ u, const double* __restrict__ v,
                                const double* __restrict__ w, const double* __restrict__ phi,
                                double* __restrict__ Ux, double* __restrict__ Uy, double* __restrict__ Uz) {
   const long long nu = (long long)(P.nx + 1) * P.ny * P.nz, nv = (long long)P.nx * (P.ny + 1) * P.nz;
@@ -46,7 +46,7 @@ __global__ void k_liquid_faces(DevParams P, const double* __restrict__ u, const 
   }
 }
 
-__global__ void k_plic(DevParams P, const double* __restrict__ a1, double* __restrict__ pnx,
+__global__ void __launch_bounds__(BLOCK) k_plic(DevParams P, const double* __restrict__ a1, double* __restrict__ pnx,
                        double* __restrict__ pny, double* __restrict__ pnz, double* __restrict__ ps) {
   long long b0, b1;
   block_range(P.n, b0, b1);
@@ -109,7 +109,7 @@ __device__ __forceinline__ double geo_face(const DevParams& P, const double* __r
   return uf * sw / (h * h * P.dt);
 }
 
-__global__ void k_geo_flux(DevParams P, const double* __restrict__ a1, const double* __restrict__ Ux,
+__global__ void __launch_bounds__(BLOCK) k_geo_flux(DevParams P, const double* __restrict__ a1, const double* __restrict__ Ux,
                            const double* __restrict__ Uy, const double* __restrict__ Uz,
                            const double* __restrict__ pnx, const double* __restrict__ pny,
                            const double* __restrict__ pnz, const double* __restrict__ ps, double* __restrict__ Fx,

@@ -39,16 +39,19 @@ MarchGeom march_geom(const DevParams& P, int& blocks) {
 }
 
 // ---------------------------------------------------------------- potential
-// xi = xi0 (Df/2) / max(r, r_fib) at cell centres (eq. 29), centre x0.
-__global__ void k_xi(DevParams P, double* xi) {
+// xi = xi0 (Df/2) / max(r, r_fib) at the centre of cell (i, j, k) (eq. 29), centre x0.
+__device__ __forceinline__ double xi_at(const DevParams& P, int i, int j, int k) {
+  const double x = (i + 0.5) * P.h - P.x0[0], y = (j + 0.5) * P.h - P.x0[1], z = (k + 0.5) * P.h - P.x0[2];
+  const double r = sqrt(x * x + y * y + z * z);
+  return P.xi0 * (0.5 * P.Df) / fmax(r, P.r_fib);
+}
+__global__ void __launch_bounds__(BLOCK) k_xi(DevParams P, double* xi) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
-    const double x = (i + 0.5) * P.h - P.x0[0], y = (j + 0.5) * P.h - P.x0[1], z = (k + 0.5) * P.h - P.x0[2];
-    const double r = sqrt(x * x + y * y + z * z);
-    xi[c] = P.xi0 * (0.5 * P.Df) / fmax(r, P.r_fib);
+    xi[c] = xi_at(P, i, j, k);
   }
 }
 
@@ -149,7 +152,7 @@ __device__ __forceinline__ long long band_entry(const int* __restrict__ band, co
 // times |grad alpha| (eq. 17); the sums of eq. 20 and the interface count.
 // The march arithmetic is written with explicitly rounded operations so that
 // each product and sum rounds on its own.
-__global__ void k_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
+__global__ void __launch_bounds__(BLOCK) k_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
                             const double* __restrict__ omega, const double* __restrict__ u,
                             const double* __restrict__ v, const double* __restrict__ w,
                             const int* __restrict__ band, const int* __restrict__ off, int nlists, long long cap,
@@ -239,7 +242,7 @@ __global__ void k_interface(DevParams P, const double* __restrict__ alpha, const
 // full occupancy) and are dealt to full waves, so the per-cell equilibrium
 // solves, whose code holds 128 VGPRs, run side by side on every compute
 // unit and no wave of this kernel streams gas cells.
-__global__ void k_liquid_saturation(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
+__global__ void __launch_bounds__(BLOCK) k_liquid_saturation(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
                                     const int* __restrict__ band, const int* __restrict__ off, int nlists,
                                     long long cap, double* __restrict__ omega, double* __restrict__ c) {
   const int total = off[nlists];
@@ -255,7 +258,7 @@ __global__ void k_liquid_saturation(DevParams P, const double* __restrict__ alph
 
 // ---------------------------------------------------------------- S4 + eq. 4
 // mdot = K f(alpha) mdot_raw (eqs. 19-21), alpha1 = alpha - dt mdot / rho_L.
-__global__ void k_source(DevParams P, const double* __restrict__ alpha, const double* __restrict__ mraw,
+__global__ void __launch_bounds__(BLOCK) k_source(DevParams P, const double* __restrict__ alpha, const double* __restrict__ mraw,
                          const double* __restrict__ scal, double* __restrict__ mdot,
                          double* __restrict__ a1) {
   long long b0, b1;
@@ -422,14 +425,15 @@ __device__ __forceinline__ void adv_store(const AdvPlane& f, double (*sF)[ATILE]
 struct AdvFaces {
   double u0, u1, v0, v1, w0, w1, c;   // u0: carried from the plane below
   double vx, wx;                      // the tile's extra faces: v above the last row, w above the last lane
-  double g1, gv0, gw0, gvx, gwx;      // geometric advection: the given liquid fluxes of those faces
+};
+// Geometric advection: the given liquid fluxes of the faces above (x), below (y, z) and the extra ones.
+struct AdvGeoFlux {
+  double g1, gv0, gw0, gvx, gwx;
 };
 __device__ __forceinline__ void adv_faces(const DevParams& P, const double* __restrict__ u,
                                           const double* __restrict__ v, const double* __restrict__ w,
                                           const double* __restrict__ c, int X, bool want, int j, int k,
-                                          bool want_vx, bool want_wx, int y0, int z0, AdvFaces& F,
-                                          const double* __restrict__ Fx = nullptr, const double* __restrict__ Fy = nullptr,
-                                          const double* __restrict__ Fz = nullptr) {
+                                          bool want_vx, bool want_wx, int y0, int z0, AdvFaces& F) {
   const int i = clampi(X, P.nx), jc = clampi(j, P.ny), kc = clampi(k, P.nz);
   const int jf = min(j, P.ny), jf1 = min(j + 1, P.ny), kf = min(k, P.nz), kf1 = min(k + 1, P.nz);
   F.u1 = want ? u[uidx(P, i + 1, jc, kc)] : 0.0;
@@ -442,15 +446,19 @@ __device__ __forceinline__ void adv_faces(const DevParams& P, const double* __re
   const int lane = threadIdx.x % MZ;
   F.vx = (want && want_vx) ? v[vidx(P, i, min(y0 + MY, P.ny), kc)] : 0.0;
   F.wx = (want && want_wx && lane < MY) ? w[widx(P, i, clampi(y0 + lane, P.ny), min(z0 + MZ, P.nz))] : 0.0;
-  if (Fx) {
-    F.g1 = want ? Fx[uidx(P, i + 1, jc, kc)] : 0.0;
-    F.gv0 = want ? Fy[vidx(P, i, jf, kc)] : 0.0;
-    F.gw0 = want ? Fz[widx(P, i, jc, kf)] : 0.0;
-    F.gvx = (want && want_vx) ? Fy[vidx(P, i, min(y0 + MY, P.ny), kc)] : 0.0;
-    F.gwx = (want && want_wx && lane < MY) ? Fz[widx(P, i, clampi(y0 + lane, P.ny), min(z0 + MZ, P.nz))] : 0.0;
-  } else {
-    F.g1 = F.gv0 = F.gw0 = F.gvx = F.gwx = 0.0;
-  }
+}
+__device__ __forceinline__ void adv_geo_fluxes(const DevParams& P, const double* __restrict__ Fx,
+                                               const double* __restrict__ Fy, const double* __restrict__ Fz, int X,
+                                               bool want, int j, int k, bool want_vx, bool want_wx, int y0, int z0,
+                                               AdvGeoFlux& G) {
+  const int i = clampi(X, P.nx), jc = clampi(j, P.ny), kc = clampi(k, P.nz);
+  const int jf = min(j, P.ny), kf = min(k, P.nz);
+  const int lane = threadIdx.x % MZ;
+  G.g1 = want ? Fx[uidx(P, i + 1, jc, kc)] : 0.0;
+  G.gv0 = want ? Fy[vidx(P, i, jf, kc)] : 0.0;
+  G.gw0 = want ? Fz[widx(P, i, jc, kf)] : 0.0;
+  G.gvx = (want && want_vx) ? Fy[vidx(P, i, min(y0 + MY, P.ny), kc)] : 0.0;
+  G.gwx = (want && want_wx && lane < MY) ? Fz[widx(P, i, clampi(y0 + lane, P.ny), min(z0 + MZ, P.nz))] : 0.0;
 }
 
 // Van Leer face value on a grid line (cells m, a | b, p; face between a and b)
@@ -563,7 +571,9 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
     wT[0] = pT[1];
     wP[0] = pP[1];
     AdvFaces F;
-    adv_faces(P, u, v, w, c, x0, true, j, k, ty == wave_vx, ty == wave_wx, y0, z0, F, Fx, Fy, Fz);
+    adv_faces(P, u, v, w, c, x0, true, j, k, ty == wave_vx, ty == wave_wx, y0, z0, F);
+    AdvGeoFlux FG{};
+    if constexpr (GEO) adv_geo_fluxes(P, Fx, Fy, Fz, x0, true, j, k, ty == wave_vx, ty == wave_wx, y0, z0, FG);
     F.u0 = u[uidx(P, x0, clampi(j, P.ny), clampi(k, P.nz))];
     double g0 = GEO ? Fx[uidx(P, x0, clampi(j, P.ny), clampi(k, P.nz))] : 0.0;   // given liquid flux below
     // the x face below plane x0 (cells x0-2 .. x0+1)
@@ -580,7 +590,10 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
       AdvPlane nf;
       adv_fetch(P, a1, omega, T, phi, x + 3, x + 3 <= x1 + 1, x + 3 < x1, y0, z0, nf);
       AdvFaces NF;
-      adv_faces(P, u, v, w, c, x + 1, x + 1 < x1, j, k, ty == wave_vx, ty == wave_wx, y0, z0, NF, Fx, Fy, Fz);
+      adv_faces(P, u, v, w, c, x + 1, x + 1 < x1, j, k, ty == wave_vx, ty == wave_wx, y0, z0, NF);
+      AdvGeoFlux NFG{};
+      if constexpr (GEO)
+        adv_geo_fluxes(P, Fx, Fy, Fz, x + 1, x + 1 < x1, j, k, ty == wave_vx, ty == wave_wx, y0, z0, NFG);
       const double(*S)[ATILE] = sF[slot];
       const double* SP = sP[slot];
       const int ce = (ty + 2) * AHZ + tz + 2, pe = (ty + 1) * PHZ + tz + 1;
@@ -588,7 +601,7 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
       FaceFlux xhi;
       {
         const double ul = phi ? F.u1 - (wP[2] - wP[1]) * ih : F.u1;
-        xhi = face_flux<GEO>(P, wA, wO, wT, F.u1, ul, x == P.nx - 1 ? 2 : 0, F.g1);
+        xhi = face_flux<GEO>(P, wA, wO, wT, F.u1, ul, x == P.nx - 1 ? 2 : 0, FG.g1);
       }
       // y faces below the cell (rows j-2 .. j+1 of its column); ce_/pe_ pick
       // the column (tile centre entry) a face is evaluated for
@@ -609,21 +622,21 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
         const double ul = phi ? wf - (SP[pe_ + c0 + 2] - SP[pe_ + c0 + 1]) * ih : wf;
         return face_flux<GEO>(P, A4, O4, T4, wf, ul, fpos == 0 ? 1 : (fpos == P.nz ? 2 : 0), gl);
       };
-      const FaceFlux ylo = yface(ce, pe, -2, F.v0, j, F.gv0);
+      const FaceFlux ylo = yface(ce, pe, -2, F.v0, j, FG.gv0);
       sY[0][ty][tz] = ylo.F;
       sY[1][ty][tz] = ylo.G;
       sY[2][ty][tz] = ylo.uT;
       if (ty == wave_vx) {   // the y faces above the last row (its rows y0+MY-2 .. y0+MY+1)
-        const FaceFlux yh = yface((MY + 1) * AHZ + tz + 2, MY * PHZ + tz + 1, -1, F.vx, y0 + MY, F.gvx);
+        const FaceFlux yh = yface((MY + 1) * AHZ + tz + 2, MY * PHZ + tz + 1, -1, F.vx, y0 + MY, FG.gvx);
         sY[0][MY][tz] = yh.F;
         sY[1][MY][tz] = yh.G;
         sY[2][MY][tz] = yh.uT;
       }
       // z faces below the cell (columns k-2 .. k+1); the one above comes from the next lane
-      const FaceFlux zlo = zface(ce, pe, -2, F.w0, k, F.gw0);
+      const FaceFlux zlo = zface(ce, pe, -2, F.w0, k, FG.gw0);
       FaceFlux zhi = {__shfl_down(zlo.F, 1, MZ), __shfl_down(zlo.G, 1, MZ), __shfl_down(zlo.uT, 1, MZ)};
       if (ty == wave_wx && tz < MY) {   // lane r: the z face above the last lane of row r
-        const FaceFlux zx = zface((tz + 2) * AHZ + MZ + 1, (tz + 1) * PHZ + MZ, -1, F.wx, z0 + MZ, F.gwx);
+        const FaceFlux zx = zface((tz + 2) * AHZ + MZ + 1, (tz + 1) * PHZ + MZ, -1, F.wx, z0 + MZ, FG.gwx);
         sZ[0][tz] = zx.F;
         sZ[1][tz] = zx.G;
         sZ[2][tz] = zx.uT;
@@ -687,6 +700,7 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
       xlo = xhi;
       NF.u0 = F.u1;
       F = NF;
+      if constexpr (GEO) FG = NFG;
       slot = slot == 2 ? 0 : slot + 1;
     }
   }
@@ -695,7 +709,7 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
 
 // ---------------------------------------------------------------- S6-S8
 // Energy, eq. 8 after the advection: (rho cp/dt) T - div(k grad T) = (rho cp/dt) T' - mdot dh.
-__global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ Tp,
+__global__ void __launch_bounds__(BLOCK) k_energy_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ Tp,
                                const double* __restrict__ mdot, const double* __restrict__ u,
                                const double* __restrict__ v, const double* __restrict__ w,
                                double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b,
@@ -740,7 +754,7 @@ __global__ void k_energy_setup(DevParams P, const double* __restrict__ a_new, co
 // (without mdot in the literal species form).  Face coefficient K_f = sc (q_c + q_nb)/2 with the cell
 // coefficient q = theta and sc = rho_G D/h^2, or, for a variable gas, q = rho_G theta and sc = D/h^2; the
 // Dirichlet faces keep the ambient gas's 2 rho_G D/h^2.
-__global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
+__global__ void __launch_bounds__(BLOCK) k_species_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
                                 const double* __restrict__ mdot, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
                                 double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b,
@@ -784,7 +798,7 @@ __global__ void k_species_setup(DevParams P, const double* __restrict__ a_new, c
 }
 
 // Flux-form vapour update after the implicit solve; diffusive boundary outflow tally.
-__global__ void k_species_update(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
+__global__ void __launch_bounds__(BLOCK) k_species_update(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
                                  const double* __restrict__ mdot, const double* __restrict__ om,
                                  const double* __restrict__ u, const double* __restrict__ v,
                                  const double* __restrict__ w, double* __restrict__ cout,
@@ -1029,7 +1043,7 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
 
 // ---------------------------------------------------------------- S10 setup
 // Pressure: sum_f (dt/h^2) (1/rho)_f (p_c - p_nb) = mdot (1/rho_G - 1/rho_L) - div u*.
-__global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ mdot,
+__global__ void __launch_bounds__(BLOCK) k_pressure_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ mdot,
                                  const double* __restrict__ us, const double* __restrict__ vs,
                                  const double* __restrict__ ws, double* __restrict__ qc,
                                  double* __restrict__ diag, double* __restrict__ b, F32Out fo,
@@ -1081,7 +1095,7 @@ __global__ void k_pressure_setup(DevParams P, const double* __restrict__ a_new, 
 // System D G phi = D u for the divergence-free part u - G phi of the face
 // velocities (same boundary kinds as the pressure), written in the pressure
 // operator's form with q = 1/dt: (dt/h^2)(1/dt) = 1/h^2 per face.
-__global__ void k_div_setup(DevParams P, const double* __restrict__ u, const double* __restrict__ v,
+__global__ void __launch_bounds__(BLOCK) k_div_setup(DevParams P, const double* __restrict__ u, const double* __restrict__ v,
                             const double* __restrict__ w, double* __restrict__ qc, double* __restrict__ diag,
                             double* __restrict__ b, F32Out fo) {
   long long b0, b1;
@@ -1122,7 +1136,7 @@ __global__ void k_div_setup(DevParams P, const double* __restrict__ u, const dou
 // ---------------------------------------------------------------- S11
 // Projected velocity on the face (i, j, k) normal to axis AX, indices in that
 // face array (extent +1 along AX).
-template <int AX>
+template <int AX, bool VAR>
 __device__ __forceinline__ double project_face(const DevParams& P, const double* __restrict__ a_new,
                                                const double* __restrict__ p, const double* __restrict__ Fs, int i,
                                                int j, int k, double ih) {
@@ -1138,18 +1152,20 @@ __device__ __forceinline__ double project_face(const DevParams& P, const double*
     const int jc = AX == 1 ? (side ? j - 1 : j) : j;
     const int kc = AX == 2 ? (side ? k - 1 : k) : k;
     const long long c = cidx(P, ic, jc, kc);
-    const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, rho_gas(P, c));
+    const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, VAR ? P.rg[c] : P.rho_G);
     return side ? us + 2.0 * P.dt * beta * p[c] * ih : us - 2.0 * P.dt * beta * p[c] * ih;
   }
   const int iL = AX == 0 ? i - 1 : i, jL = AX == 1 ? j - 1 : j, kL = AX == 2 ? k - 1 : k;
   const long long cL = cidx(P, iL, jL, kL), cR = cidx(P, i, j, k);
-  const double bL = 1.0 / mix(clamp01(a_new[cL]), P.rho_L, rho_gas(P, cL));
-  const double bR = 1.0 / mix(clamp01(a_new[cR]), P.rho_L, rho_gas(P, cR));
+  const double bL = 1.0 / mix(clamp01(a_new[cL]), P.rho_L, VAR ? P.rg[cL] : P.rho_G);
+  const double bR = 1.0 / mix(clamp01(a_new[cR]), P.rho_L, VAR ? P.rg[cR] : P.rho_G);
   return us - P.dt * 0.5 * (bL + bR) * (p[cR] - p[cL]) * ih;
 }
 
 // All three face arrays in one pass over the cells (as the predictor).
-__global__ void k_project(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
+// VAR: a variable gas (its density field P.rg).
+template <bool VAR>
+__global__ void __launch_bounds__(BLOCK) k_project(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
                           const double* __restrict__ us, const double* __restrict__ vs,
                           const double* __restrict__ ws, double* __restrict__ u, double* __restrict__ v,
                           double* __restrict__ w) {
@@ -1159,17 +1175,17 @@ __global__ void k_project(DevParams P, const double* __restrict__ a_new, const d
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
-    u[uidx(P, i, j, k)] = project_face<0>(P, a_new, p, us, i, j, k, ih);
-    v[vidx(P, i, j, k)] = project_face<1>(P, a_new, p, vs, i, j, k, ih);
-    w[widx(P, i, j, k)] = project_face<2>(P, a_new, p, ws, i, j, k, ih);
-    if (i == P.nx - 1) u[uidx(P, P.nx, j, k)] = project_face<0>(P, a_new, p, us, P.nx, j, k, ih);
-    if (j == P.ny - 1) v[vidx(P, i, P.ny, k)] = project_face<1>(P, a_new, p, vs, i, P.ny, k, ih);
-    if (k == P.nz - 1) w[widx(P, i, j, P.nz)] = project_face<2>(P, a_new, p, ws, i, j, P.nz, ih);
+    u[uidx(P, i, j, k)] = project_face<0, VAR>(P, a_new, p, us, i, j, k, ih);
+    v[vidx(P, i, j, k)] = project_face<1, VAR>(P, a_new, p, vs, i, j, k, ih);
+    w[widx(P, i, j, k)] = project_face<2, VAR>(P, a_new, p, ws, i, j, k, ih);
+    if (i == P.nx - 1) u[uidx(P, P.nx, j, k)] = project_face<0, VAR>(P, a_new, p, us, P.nx, j, k, ih);
+    if (j == P.ny - 1) v[vidx(P, i, P.ny, k)] = project_face<1, VAR>(P, a_new, p, vs, i, P.ny, k, ih);
+    if (k == P.nz - 1) w[widx(P, i, j, P.nz)] = project_face<2, VAR>(P, a_new, p, ws, i, j, P.nz, ih);
   }
 }
 
 // ---------------------------------------------------------------- S12
-__global__ void k_diagnostics(DevParams P, const double* __restrict__ alpha, const double* __restrict__ c,
+__global__ void __launch_bounds__(BLOCK) k_diagnostics(DevParams P, const double* __restrict__ alpha, const double* __restrict__ c,
                               const double* __restrict__ T, const double* __restrict__ p,
                               const double* __restrict__ mdot, double* partials, unsigned* counter,
                               double* scal) {
@@ -1203,7 +1219,7 @@ __global__ void k_diagnostics(DevParams P, const double* __restrict__ alpha, con
 }
 
 // c = rho_G theta omega with theta = max(1 - alpha, theta_min).
-__global__ void k_c_from_omega(DevParams P, const double* __restrict__ alpha, const double* __restrict__ omega,
+__global__ void __launch_bounds__(BLOCK) k_c_from_omega(DevParams P, const double* __restrict__ alpha, const double* __restrict__ omega,
                                double* __restrict__ c) {
   long long b0, b1;
   block_range(P.n, b0, b1);
@@ -1211,12 +1227,12 @@ __global__ void k_c_from_omega(DevParams P, const double* __restrict__ alpha, co
     c[e] = P.rho_G * fmax(1.0 - clamp01(alpha[e]), P.theta_min) * omega[e];
 }
 
-__global__ void k_fill(double* x, double v, long long n) {
+__global__ void __launch_bounds__(BLOCK) k_fill(double* x, double v, long long n) {
   long long b0, b1;
   block_range(n, b0, b1);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) x[e] = v;
 }
-__global__ void k_absmax(const double* __restrict__ x, long long n, double* partials, unsigned* counter,
+__global__ void __launch_bounds__(BLOCK) k_absmax(const double* __restrict__ x, long long n, double* partials, unsigned* counter,
                          double* out) {
   long long b0, b1;
   block_range(n, b0, b1);
@@ -1232,12 +1248,12 @@ __global__ void k_absmax(const double* __restrict__ x, long long n, double* part
     if (threadIdx.x == 0) *out = tot[0];
   }
 }
-__global__ void k_scale(double* x, double a, long long n) {
+__global__ void __launch_bounds__(BLOCK) k_scale(double* x, double a, long long n) {
   long long b0, b1;
   block_range(n, b0, b1);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) x[e] *= a;
 }
-__global__ void k_int_to_double(const int* s, double* d, long long n) {
+__global__ void __launch_bounds__(BLOCK) k_int_to_double(const int* s, double* d, long long n) {
   long long b0, b1;
   block_range(n, b0, b1);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) d[e] = (double)s[e];
@@ -1327,7 +1343,8 @@ void launch_div_setup(const DevParams& P, const double* u, const double* v, cons
 void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
                     const double* vs, const double* ws, double* u, double* v, double* w,
                     hipStream_t s) {
-  k_project<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, p, us, vs, ws, u, v, w);
+  if (P.rg) k_project<true><<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, p, us, vs, ws, u, v, w);
+  else k_project<false><<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, p, us, vs, ws, u, v, w);
 }
 void launch_diagnostics(const DevParams& P, const double* alpha, const double* c, const double* T,
                         const double* p, const double* mdot, double* partials, unsigned* counter,

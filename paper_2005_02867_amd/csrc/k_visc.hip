@@ -187,7 +187,7 @@ struct VView {
 
 // x = u* (all faces), b = right-hand side and d = diagonal on interior faces
 // (box faces: b = d = 0).
-__global__ void k_visc_setup(DevParams P, VView V, const double* __restrict__ alpha, const double* __restrict__ us,
+__global__ void __launch_bounds__(BLOCK) k_visc_setup(DevParams P, VView V, const double* __restrict__ alpha, const double* __restrict__ us,
                              const double* __restrict__ vs, const double* __restrict__ ws,
                              const double* __restrict__ u, const double* __restrict__ v,
                              const double* __restrict__ w, double* __restrict__ x, double* __restrict__ b,
@@ -216,7 +216,7 @@ __global__ void k_visc_setup(DevParams P, VView V, const double* __restrict__ al
 }
 
 // r = b - A x, p = r/d; <r, r/d>, <b, b>, <r, r> -> status.
-__global__ void k_visc_resid(DevParams P, VView V, const double* __restrict__ alpha, const double* __restrict__ x,
+__global__ void __launch_bounds__(BLOCK) k_visc_resid(DevParams P, VView V, const double* __restrict__ alpha, const double* __restrict__ x,
                              const double* __restrict__ b, const double* __restrict__ d, double* __restrict__ r,
                              double* __restrict__ p, SolveStatus* st, double* partials, unsigned* counter) {
   long long b0, b1;
@@ -256,7 +256,7 @@ __global__ void k_visc_resid(DevParams P, VView V, const double* __restrict__ al
 }
 
 // q = A p, <p, q> -> alpha = rz / <p, q>.
-__global__ void k_visc_apply(DevParams P, VView V, const double* __restrict__ alpha, const double* __restrict__ p,
+__global__ void __launch_bounds__(BLOCK) k_visc_apply(DevParams P, VView V, const double* __restrict__ alpha, const double* __restrict__ p,
                              double* __restrict__ q, SolveStatus* st, double* partials, unsigned* counter) {
   if (st->done) return;
   long long b0, b1;
@@ -282,7 +282,7 @@ __global__ void k_visc_apply(DevParams P, VView V, const double* __restrict__ al
 }
 
 // x += alpha p, r -= alpha q; <r, r/d>, <r, r> -> beta, residual, convergence.
-__global__ void k_visc_update(VView V, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+__global__ void __launch_bounds__(BLOCK) k_visc_update(VView V, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
                               const double* __restrict__ q, const double* __restrict__ d, SolveStatus* st,
                               double* partials, unsigned* counter) {
   if (st->done) return;
@@ -315,7 +315,7 @@ __global__ void k_visc_update(VView V, double* __restrict__ x, double* __restric
 }
 
 // p = r/d + beta p (interior faces).
-__global__ void k_visc_dir(VView V, const double* __restrict__ r, const double* __restrict__ d,
+__global__ void __launch_bounds__(BLOCK) k_visc_dir(VView V, const double* __restrict__ r, const double* __restrict__ d,
                            double* __restrict__ p, const SolveStatus* st) {
   if (st->done) return;
   long long b0, b1;
@@ -329,7 +329,7 @@ __global__ void k_visc_dir(VView V, const double* __restrict__ r, const double* 
 }
 
 // u**, v**, w** on the interior faces from x.
-__global__ void k_visc_store(DevParams P, VView V, const double* __restrict__ x, double* __restrict__ us,
+__global__ void __launch_bounds__(BLOCK) k_visc_store(DevParams P, VView V, const double* __restrict__ x, double* __restrict__ us,
                              double* __restrict__ vs, double* __restrict__ ws) {
   long long b0, b1;
   block_range(V.nf, b0, b1);
