@@ -79,8 +79,8 @@ struct ds_grid {
   // variable-density gas (gas_density = 1): the state's rho_G, the advected state's rho_G', eq. 7's
   // compressibility term and the vapour mass per gas volume rho_G omega the advection carries
   double *rg = nullptr, *rg_p = nullptr, *scomp = nullptr, *qv = nullptr;
-  // geometric advection (advection = 1): the planes of the surface cells (n_x, n_y, n_z, s) and the liquid
-  // fluxes per face; the liquid face velocities use us, vs, ws (free until the predictor)
+  // geometric advection (advection = 1): the planes of the surface cells (n_x, n_y, n_z, s; written only where
+  // tol < alpha1 < 1 - tol) and the liquid fluxes per face
   double* geo_pl[4] = {};
   double* geo_F[3] = {};
   int batch_visc = 4;
@@ -928,8 +928,8 @@ int one_step(ds_grid* g, hipStream_t s) {
   const bool geo = g->prm.advection == DS_ADV_GEOMETRIC;
   if (geo) {
     double* const pl[4] = {g->geo_pl[0], g->geo_pl[1], g->geo_pl[2], g->geo_pl[3]};
-    launch_geo_fluxes(P, g->a1, g->u, g->v, g->w, g->prm.liquid_transport ? g->phi : nullptr, g->us, g->vs, g->ws, pl,
-                      g->geo_F[0], g->geo_F[1], g->geo_F[2], s);
+    launch_geo_fluxes(P, g->a1, g->u, g->v, g->w, g->prm.liquid_transport ? g->phi : nullptr, pl, g->geo_F[0],
+                      g->geo_F[1], g->geo_F[2], s);
   }
   const double* Fx = geo ? g->geo_F[0] : nullptr;
   const double* Fy = geo ? g->geo_F[1] : nullptr;

@@ -80,10 +80,10 @@ void launch_diagnostics(const DevParams& P, const double* alpha, const double* c
                         const double* p, const double* mdot, double* partials, unsigned* counter,
                         double* scal, hipStream_t s);
 void launch_c_from_omega(const DevParams& P, const double* alpha, const double* omega, double* c, hipStream_t s);
-// geometric interface advection (k_geo.hip): liquid faces, planes, liquid fluxes per face
+// geometric interface advection (k_geo.hip): planes of the surface cells, liquid fluxes per face
 void launch_geo_fluxes(const DevParams& P, const double* a1, const double* u, const double* v, const double* w,
-                       const double* phi, double* Ux, double* Uy, double* Uz, double* const (&planes)[4],
-                       double* Fx, double* Fy, double* Fz, hipStream_t s);
+                       const double* phi, double* const (&planes)[4], double* Fx, double* Fy, double* Fz,
+                       hipStream_t s);
 // variable-density gas (k_gas.hip)
 void launch_gas_from_omega(const DevParams& P, const double* T, const double* omega, const double* alpha, double* rg,
                            double* c, hipStream_t s);

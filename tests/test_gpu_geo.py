@@ -1,8 +1,9 @@
 """Geometric interface advection (advection = 1) on the GPU against the CPU
 oracle, through the C ABI.
 
-* Whole steps on a ragged grid in the three boundary modes: every field
-  within 1e-9 (2-norm and element by element).  The planes (bisection on
+* Whole steps on a ragged grid in the three boundary modes, and with the
+  liquid moved by u itself: every field within 1e-9 (2-norm and element by
+  element).  The planes (bisection on
   the exact cut volume) and the swept face areas (piecewise Simpson) are
   written independently on the two sides.
 * The C1 droplet with its Stefan flow, 5 steps.
@@ -55,6 +56,13 @@ def _run(prm, f, steps, tol=1e-13):
 def test_geometric_step_parity(mode):
     prm, _ = _grid_params(n=(17, 19, 23), L=17 * 1.25e-4, bc_mode=mode, w_in=0.2 if mode == W.BC_FORCED else 0.0)
     f = W.random_fields(prm, seed=13)
+    _run(prm, f, steps=3)
+
+
+def test_geometric_step_parity_liquid_moved_by_u():
+    """liquid_transport = 0: the liquid moved by u itself (no potential)."""
+    prm, _ = _grid_params(n=(17, 19, 23), L=17 * 1.25e-4, bc_mode=W.BC_FARFIELD, liquid_transport=0)
+    f = W.random_fields(prm, seed=14)
     _run(prm, f, steps=3)
 
 
