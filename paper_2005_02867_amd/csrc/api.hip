@@ -320,7 +320,9 @@ size_t tape_adjoint_bytes(const ds_grid* g) {
   const size_t cb = align256(g->n * sizeof(double));
   const size_t fb = align256(g->nu * sizeof(double)) + align256(g->nv * sizeof(double)) +
                     align256(g->nw * sizeof(double));
-  return 21 * cb + 5 * fb + align256(GR_COUNT * sizeof(double)) + align256(sizeof(unsigned));
+  // 10 adjoint cell arrays and 11 of interface records, the records' list of cells, 5 face arrays per axis
+  return 21 * cb + align256(g->n * sizeof(int)) + 5 * fb + align256(GR_COUNT * sizeof(double)) +
+         align256(2 * sizeof(unsigned));
 }
 
 size_t tape_total_bytes(const ds_grid* g, int nsteps, int ckpt) {
@@ -358,7 +360,9 @@ void carve_tape(ds_grid* g, char* base) {
   for (int q = 0; q < 3; ++q) R.f[q] = L.take<double>(base, n);
   for (int q = 0; q < 3; ++q) R.gsf[q] = L.take<double>(base, n);
   R.hit = L.take<double>(base, n);
-  R.rmax = L.take<unsigned>(base, 1);
+  R.list = L.take<int>(base, n);
+  R.rmax = L.take<unsigned>(base, 2);
+  R.nlist = R.rmax + 1;
   g->tape_slot_off = L.off;
 }
 
@@ -1670,6 +1674,9 @@ int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t
   g->tape_steps = nsteps;
   g->tape_ckpt = C;
   carve_tape(g, g->tape);
+  if (g->tape_slot_off != tape_adjoint_bytes(g))
+    return fail(g, DS_ERR_STATE, "internal: tape layout carves %zu bytes, sized for %zu", g->tape_slot_off,
+                tape_adjoint_bytes(g));
   const int nck = tape_nckpt(nsteps, C);
   int st, rc = DS_OK;
   if ((st = save_slot(g, slot_at(g, 0), s)) != DS_OK) return st;

@@ -161,7 +161,9 @@ struct IfaceRecords {
   double* f[3];     // to each of adj's two q faces
   double* gsf[3];   // per adj cell: sum of its band cells' f[q]
   double* hit;      // 1 where a band cell's adj is this cell
+  int* list;        // the cells marked in hit, once each (in no particular order)
   unsigned* rmax;   // largest march distance (cells, Chebyshev)
+  unsigned* nlist;  // length of list
 };
 void launch_adj_interface(const DevParams& P, const double* alpha, const double* T, const double* omega,
                           const double* u, const double* v, const double* w, const double* mraw, const int* adj,

@@ -757,7 +757,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_source(DevParams P, const double*
 // D and rho_G.  The band cell's own alpha and T terms are added in place;
 // what goes to other cells is recorded: R.gb[q] (to alpha of the neighbours
 // +-q), R.om (to omega of adj), R.f[q] (to each of adj's two q faces), and
-// adj is marked in R.hit, its march distance maxed into R.rmax.
+// adj is marked in R.hit (the first band cell to mark it also lists it), its
+// march distance maxed into R.rmax.
 __global__ void __launch_bounds__(BLOCK) k_adj_interface(DevParams P, const double* __restrict__ alpha, const double* __restrict__ T,
                                 const double* __restrict__ omega, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
@@ -817,7 +818,9 @@ __global__ void __launch_bounds__(BLOCK) k_adj_interface(DevParams P, const doub
     R.f[0][c] = 0.5 * vab * n[0];
     R.f[1][c] = 0.5 * vab * n[1];
     R.f[2][c] = 0.5 * vab * n[2];
-    R.hit[hit] = 1.0;
+    // 0x3FF0000000000000 is 1.0: the cell is listed by whichever band cell marks it first
+    if (atomicCAS(reinterpret_cast<unsigned long long*>(R.hit) + hit, 0ull, 0x3FF0000000000000ull) == 0ull)
+      R.list[atomicAdd(R.nlist, 1u)] = hit;
     const int dist = max(abs(ti - i), max(abs(tj - j), abs(tk - k)));
     atomicMax(R.rmax, (unsigned)dist);
     const double nb[3] = {vab * vc[0], vab * vc[1], vab * vc[2]};
@@ -832,24 +835,25 @@ __global__ void __launch_bounds__(BLOCK) k_adj_interface(DevParams P, const doub
   grad_add<3>(acc, slot, partials, counter, grad);
 }
 
-// Before the interface stage: no cell is an adj yet, march distance 0.
+// Before the interface stage: no cell is an adj yet, march distance 0, the
+// list empty.
 __global__ void __launch_bounds__(BLOCK) k_adj_iface_clear(DevParams P, IfaceRecords R) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) R.hit[e] = 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *R.rmax = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *R.rmax = 0u;
+    *R.nlist = 0u;
+  }
 }
 
-// Gather of the interface records, per cell e in a fixed order: alpha from
-// the band neighbours' gb (the lower neighbour along q adds gb[q], the upper
-// one subtracts it); if e is an adj cell, omega from every band cell within
-// the largest march distance whose adj is e (scanned in i, j, k order), and
-// the sums of their face records, kept for the face pass.
+// Gather of the interface records to alpha, per cell e in a fixed order:
+// from the band neighbours' gb (the lower neighbour along q adds gb[q], the
+// upper one subtracts it).
 __global__ void __launch_bounds__(BLOCK) k_adj_iface_gather(DevParams P, const int* __restrict__ adj, IfaceRecords R,
-                                   double* __restrict__ A_al, double* __restrict__ A_om) {
+                                   double* __restrict__ A_al) {
   long long b0, b1;
   block_range(P.n, b0, b1);
-  const int rm = (int)*R.rmax;
   const long long st[3] = {(long long)P.ny * P.nz, (long long)P.nz, 1};
   const int nn[3] = {P.nx, P.ny, P.nz};
   for (long long e = b0 + threadIdx.x; e < b1; e += BLOCK) {
@@ -870,20 +874,48 @@ __global__ void __launch_bounds__(BLOCK) k_adj_iface_gather(DevParams P, const i
       }
     }
     if (any) A_al[e] += acc;
-    if (R.hit[e] == 0.0) continue;
+  }
+}
+
+// Gather to the adj cells, one wavefront per listed cell e: omega of e from
+// every band cell within the largest march distance whose adj is e, and the
+// sums of their face records, kept for the face pass.  Lane l takes the
+// cells l, l + 64, ... of the cube around e in i, j, k order, and the lanes'
+// sums meet in a fixed shuffle tree: the result does not depend on the
+// order of the list.
+__global__ void __launch_bounds__(BLOCK) k_adj_iface_targets(DevParams P, const int* __restrict__ adj, IfaceRecords R,
+                                    double* __restrict__ A_om) {
+  const int rm = (int)*R.rmax;
+  const unsigned nl = *R.nlist;
+  const int lane = threadIdx.x & 63;
+  const unsigned nwave = gridDim.x * (BLOCK / 64);
+  const int side = 2 * rm + 1;
+  const int cube = side * side * side;
+  for (unsigned t = blockIdx.x * (BLOCK / 64) + threadIdx.x / 64; t < nl; t += nwave) {
+    const int e = R.list[t];
+    int i, j, k;
+    decode(P, e, i, j, k);
     double som = 0.0, sf[3] = {0.0, 0.0, 0.0};
-    for (int ci = max(i - rm, 0); ci <= min(i + rm, P.nx - 1); ++ci)
-      for (int cj = max(j - rm, 0); cj <= min(j + rm, P.ny - 1); ++cj)
-        for (int ck = max(k - rm, 0); ck <= min(k + rm, P.nz - 1); ++ck) {
-          const long long c = cidx(P, ci, cj, ck);
-          if (adj[c] != (int)e) continue;
-          som += R.om[c];
+    for (int q = lane; q < cube; q += 64) {
+      const int ci = i + q / (side * side) - rm, cj = j + (q / side) % side - rm, ck = k + q % side - rm;
+      if (ci < 0 || ci >= P.nx || cj < 0 || cj >= P.ny || ck < 0 || ck >= P.nz) continue;
+      const long long c = cidx(P, ci, cj, ck);
+      if (adj[c] != e) continue;
+      som += R.om[c];
 #pragma unroll
-          for (int q = 0; q < 3; ++q) sf[q] += R.f[q][c];
-        }
-    A_om[e] += som;
+      for (int a = 0; a < 3; ++a) sf[a] += R.f[a][c];
+    }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) R.gsf[q][e] = sf[q];
+    for (int off = 32; off > 0; off >>= 1) {
+      som += __shfl_down(som, off, 64);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sf[a] += __shfl_down(sf[a], off, 64);
+    }
+    if (lane == 0) {
+      A_om[e] += som;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) R.gsf[a][e] = sf[a];
+    }
   }
 }
 
@@ -1022,7 +1054,8 @@ void launch_adj_interface(const DevParams& P, const double* alpha, const double*
   k_adj_iface_clear<<<nb, BLOCK, 0, s>>>(P, R);
   k_adj_interface<<<nb, BLOCK, 0, s>>>(P, alpha, T, omega, u, v, w, mraw, adj, A_md, scal, A_al, A_T, R, partials,
                                        counter, grad);
-  k_adj_iface_gather<<<nb, BLOCK, 0, s>>>(P, adj, R, A_al, A_om);
+  k_adj_iface_gather<<<nb, BLOCK, 0, s>>>(P, adj, R, A_al);
+  k_adj_iface_targets<<<nb, BLOCK, 0, s>>>(P, adj, R, A_om);
   k_adj_iface_faces<<<nb, BLOCK, 0, s>>>(P, R, AU[0], AU[1], AU[2]);
 }
 void launch_adj_init_c(const DevParams& P, const double* alpha, const double* omega, const double* A_c, double* A_al,
