@@ -23,6 +23,8 @@
 // the FFTs run in LDS (Stockham, radices 4, 2 and 3).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ds_device.h"
 #include "ds_kernels.h"
 
@@ -244,6 +246,84 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_lateral(FdmLat A, const double* 
   }
 }
 
+// Pipelined form of the lateral pass: persistent workgroups (tables filled
+// once) walk the (other index, z chunk) groups with a grid stride; each
+// thread holds its FDM_PF elements of the next group in registers, loaded
+// while the current group is transformed.  Needs N * 16 <= FDM_PF * FDM_NT.
+constexpr int FDM_PF = 24;
+
+template <bool INV>
+__global__ void __launch_bounds__(FDM_NT) k_fdm_lateral_pipe(FdmLat A, const double* __restrict__ src,
+                                                            double* __restrict__ dst, int ngroups) {
+  extern __shared__ Cx lds[];
+  const int N = A.N;
+  constexpr int L = FDM_LAT_LINES, P = L / 2;
+  Cx* bufa = lds;
+  Cx* bufb = lds + P * N;
+  Cx* W = lds + 2 * P * N;
+  Cx* H = W + N;
+  fill_tables(W, H, N);   // read after the first barrier below
+  const int NL = N * L;
+  double pf[FDM_PF];
+  auto fetch = [&](int grp) {
+    const int o = grp / A.nzc, k0 = (grp - o * A.nzc) * L;
+    const long long base = (long long)o * A.so + k0;
+#pragma unroll
+    for (int q = 0; q < FDM_PF; ++q) {
+      const int e = threadIdx.x + q * FDM_NT;
+      const int n = e / L, kk = e - n * L;
+      pf[q] = (e < NL && k0 + kk < A.nz) ? src[base + n * A.sline + kk] : 0.0;
+    }
+  };
+  if ((int)blockIdx.x < ngroups) fetch(blockIdx.x);
+  for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int o = grp / A.nzc, k0 = (grp - o * A.nzc) * L;
+    const long long base = (long long)o * A.so + k0;
+    double* R = reinterpret_cast<double*>(bufb);   // inverse: coefficients, line-major (L lines of N)
+#pragma unroll
+    for (int q = 0; q < FDM_PF; ++q) {
+      const int e = threadIdx.x + q * FDM_NT;
+      if (e < NL) {
+        const int n = e / L, kk = e - n * L;
+        if (INV) {
+          R[kk * N + (A.dst ? N - 1 - n : n)] = pf[q];
+        } else {
+          const double v = (A.dst && (n & 1)) ? -pf[q] : pf[q];
+          reinterpret_cast<double*>(&bufa[(kk >> 1) * N + reorder(n, N)])[kk & 1] = v;
+        }
+      }
+    }
+    __syncthreads();
+    if (grp + (int)gridDim.x < ngroups) fetch(grp + gridDim.x);   // in flight during the transform
+    if (!INV) {
+      const Cx* Z = fft_lds<-1>(bufa, bufb, P, A.pl, W);
+      for (int e = threadIdx.x; e < NL; e += FDM_NT) {
+        const int k = e / L, kk = e - k * L;
+        if (k0 + kk >= A.nz) continue;
+        const double c = dct_coef(Z + (kk >> 1) * N, k, N, kk & 1, H);
+        dst[base + (long long)(A.dst ? N - 1 - k : k) * A.sline + kk] = c;
+      }
+    } else {
+      for (int e = threadIdx.x; e < N * P; e += FDM_NT) {
+        const int line = e / N, k = e - line * N;
+        bufa[line * N + k] = packed_inverse(R + 2 * line * N, R + (2 * line + 1) * N, k, N, H);
+      }
+      __syncthreads();
+      const Cx* z = fft_lds<1>(bufa, bufb, P, A.pl, W);
+      const double inv = 1.0 / N;
+      for (int e = threadIdx.x; e < NL; e += FDM_NT) {
+        const int n = e / L, kk = e - n * L;
+        if (k0 + kk >= A.nz) continue;
+        const Cx zv = z[(kk >> 1) * N + reorder(n, N)];
+        double v = ((kk & 1) ? zv.im : zv.re) * inv;
+        if (A.dst && (n & 1)) v = -v;
+        dst[base + n * A.sline + kk] = v;
+      }
+    }
+    __syncthreads();   // this group's LDS reads are done before the next group's writes
+  }
+}
+
 struct FdmZ {
   int nz;           // cells along z
   int M;            // transform length: nz, or 2 nz for the mirrored line
@@ -325,6 +405,92 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z(FdmZ A, double* __restrict__ x
   }
 }
 
+// Pipelined form of the z pass: persistent workgroups walk the blocks of
+// `lines` z-lines with a grid stride, each thread holding its FDM_PF
+// elements of the next block in registers while the current one is solved.
+// Needs lines * nz <= FDM_PF * FDM_NT.
+__global__ void __launch_bounds__(FDM_NT) k_fdm_z_pipe(FdmZ A, double* __restrict__ x, int ngroups) {
+  extern __shared__ Cx lds[];
+  const int M = A.M, nz = A.nz, L = A.lines, P = L / 2;
+  Cx* bufa = lds;
+  Cx* bufb = lds + P * M;
+  Cx* W = lds + 2 * P * M;
+  Cx* H = W + M;
+  fill_tables(W, H, M);   // read after the first barrier below
+  double pf[FDM_PF];
+  auto fetch = [&](int grp) {
+    const long long l0 = (long long)grp * L;
+    const int nl = (int)(A.nlines - l0 < L ? A.nlines - l0 : L);
+    const double* line0 = x + l0 * nz;
+#pragma unroll
+    for (int q = 0; q < FDM_PF; ++q) {
+      const int e = threadIdx.x + q * FDM_NT;
+      pf[q] = e < nl * nz ? line0[e] : 0.0;
+    }
+  };
+  if ((int)blockIdx.x < ngroups) fetch(blockIdx.x);
+  for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const long long l0 = (long long)grp * L;
+    const int nl = (int)(A.nlines - l0 < L ? A.nlines - l0 : L);
+    double* line0 = x + l0 * nz;
+    if (nl < L)
+      for (int e = threadIdx.x; e < L * M; e += FDM_NT) {   // zero the lines past the grid
+        const int line = e / M;
+        if (line >= nl) reinterpret_cast<double*>(&bufa[(line >> 1) * M + (e - line * M)])[line & 1] = 0.0;
+      }
+#pragma unroll
+    for (int q = 0; q < FDM_PF; ++q) {
+      const int e = threadIdx.x + q * FDM_NT;
+      if (e < nl * nz) {
+        const int line = e / nz, k = e - line * nz;
+        const double v = pf[q];
+        double* row = reinterpret_cast<double*>(&bufa[(line >> 1) * M]);
+        const int c = line & 1;
+        if (A.mirror) {
+          const int m1 = nz + k, m2 = nz - 1 - k;
+          row[2 * reorder(m1, M) + c] = (m1 & 1) ? -v : v;
+          row[2 * reorder(m2, M) + c] = (m2 & 1) ? -v : v;
+        } else {
+          row[2 * reorder(k, M) + c] = (k & 1) ? -v : v;
+        }
+      }
+    }
+    __syncthreads();
+    if (grp + (int)gridDim.x < ngroups) fetch(grp + gridDim.x);   // in flight during the solve
+    const Cx* Z = fft_lds<-1>(bufa, bufb, P, A.pl, W);
+    double* R = reinterpret_cast<double*>(Z == bufa ? bufb : bufa);
+    for (int e = threadIdx.x; e < L * M; e += FDM_NT) {
+      const int line = e / M, m = e - line * M;
+      double v = 0.0;
+      if (line < nl) {
+        const long long L_ = l0 + line;
+        const int i = (int)(L_ / A.ny), j = (int)(L_ - (long long)i * A.ny);
+        const double sig = lam(i, A.nx, A.dstx) + lam(j, A.ny, A.dsty) + lam(M - 1 - m, M, 1);
+        v = dct_coef(Z + (line >> 1) * M, m, M, line & 1, H) * A.scale / sig;
+      }
+      R[line * M + m] = v;
+    }
+    __syncthreads();
+    Cx* Wb = const_cast<Cx*>(Z);
+    for (int e = threadIdx.x; e < P * M; e += FDM_NT) {
+      const int pr = e / M, k = e - pr * M;
+      Wb[pr * M + k] = packed_inverse(R + 2 * pr * M, R + (2 * pr + 1) * M, k, M, H);
+    }
+    __syncthreads();
+    const Cx* z = fft_lds<1>(Wb, reinterpret_cast<Cx*>(R), P, A.pl, W);
+    const double inv = 1.0 / M;
+    const int off = A.mirror ? nz : 0;
+    for (int e = threadIdx.x; e < nl * nz; e += FDM_NT) {
+      const int line = e / nz, k = e - line * nz;
+      const int m = off + k;
+      const Cx zv = z[(line >> 1) * M + reorder(m, M)];
+      const double v = ((line & 1) ? zv.im : zv.re) * inv;
+      line0[e] = (m & 1) ? -v : v;
+    }
+    __syncthreads();   // this block's LDS reads are done before the next block's writes
+  }
+}
+
 struct FdmGeometry {
   bool ok = false;
   FdmLat ax, ay;
@@ -395,16 +561,45 @@ int launch_fdm_solve(const DevParams& P, double c_op, const double* b, double* x
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fdm_z), hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fdm_z_pipe), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fdm_lateral_pipe<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fdm_lateral_pipe<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
   const int gx = P.ny * G.ax.nzc, gy = P.nx * G.ay.nzc;
   const int gz = (int)((G.az.nlines + G.az.lines - 1) / G.az.lines);
+  // persistent grid of the pipelined lateral passes: as many workgroups as
+  // the compute units hold at once
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess)
+    return -1;
+  auto lateral = [&](bool inv, const FdmLat& a, size_t lds, int groups, const double* in, double* out) {
+    if (a.N * FDM_LAT_LINES <= FDM_PF * FDM_NT) {
+      const int per_cu = (int)std::max<size_t>(1, (160 * 1024) / lds);
+      const int nb = std::min(groups, per_cu * ncu);
+      if (inv) k_fdm_lateral_pipe<true><<<nb, FDM_NT, lds, s>>>(a, in, out, groups);
+      else k_fdm_lateral_pipe<false><<<nb, FDM_NT, lds, s>>>(a, in, out, groups);
+    } else if (inv) {
+      k_fdm_lateral<true><<<groups, FDM_NT, lds, s>>>(a, in, out);
+    } else {
+      k_fdm_lateral<false><<<groups, FDM_NT, lds, s>>>(a, in, out);
+    }
+  };
   // b -> t (x), t -> x (y), z solve in x, x -> t (y), t -> x (x)
-  k_fdm_lateral<false><<<gx, FDM_NT, G.lds_lat_x, s>>>(G.ax, b, t);
-  k_fdm_lateral<false><<<gy, FDM_NT, G.lds_lat_y, s>>>(G.ay, t, x);
-  k_fdm_z<<<gz, FDM_NT, G.lds_z, s>>>(G.az, x);
-  k_fdm_lateral<true><<<gy, FDM_NT, G.lds_lat_y, s>>>(G.ay, x, t);
-  k_fdm_lateral<true><<<gx, FDM_NT, G.lds_lat_x, s>>>(G.ax, t, x);
+  lateral(false, G.ax, G.lds_lat_x, gx, b, t);
+  lateral(false, G.ay, G.lds_lat_y, gy, t, x);
+  if (G.az.lines * G.az.nz <= FDM_PF * FDM_NT) {
+    const int per_cu = (int)std::max<size_t>(1, (160 * 1024) / G.lds_z);
+    k_fdm_z_pipe<<<std::min(gz, per_cu * ncu), FDM_NT, G.lds_z, s>>>(G.az, x, gz);
+  } else {
+    k_fdm_z<<<gz, FDM_NT, G.lds_z, s>>>(G.az, x);
+  }
+  lateral(true, G.ay, G.lds_lat_y, gy, x, t);
+  lateral(true, G.ax, G.lds_lat_x, gx, t, x);
   return 0;
 }
 

@@ -216,3 +216,33 @@ def test_potential_direct_and_multigrid_steps_agree(mode, monkeypatch):
     assert iters[0] == 0 and iters[1] > 0
     for k in out[0]:
         assert _err(out[0][k], out[1][k]) < 1e-10, k
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_potential_direct_solve_many_groups(mode, monkeypatch):
+    """128x128x96: more line groups per pass (768 along x and y, 1024 z-line
+    blocks; 1536 for the forced inlet's mirrored z) than the direct solve's
+    persistent workgroups, so each workgroup transforms several groups with
+    the next one's loads in flight.  0 iterations, the true residual (the
+    FP64 operator, not the transforms) at rounding level, and the solution
+    equal to the multigrid CG's (DSVOF_PHI_DIRECT=0, residual 1e-13) to 1e-8:
+    the CG's error is bounded by its residual times the condition number,
+    about (2 N / pi)^2 = 6.6e3 here."""
+    ds = _lib()
+    n = (128, 128, 96)
+    prm = _prm(n, mode, tol=1e-13, tol_phi=1e-13)
+    f = W.random_fields(prm, seed=8)
+    b = torch.tensor(np.random.default_rng(5).standard_normal(n))
+    out = []
+    for direct in ("1", "0"):
+        monkeypatch.setenv("DSVOF_PHI_DIRECT", direct)
+        print(f"{n} mode {mode}: potential, direct solve {direct}", flush=True)
+        g = ds.Grid(prm)
+        g.set_fields(f)
+        x, it, res = g.solve_system(ds.SYS_POTENTIAL, b)
+        print(f"  iterations {it}, residual {res:.2e}")
+        assert res <= 1e-13
+        assert (it == 0) == (direct == "1")
+        out.append(x)
+        del g
+    assert _err(out[0], out[1]) < 1e-8
