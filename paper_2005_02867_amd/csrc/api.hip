@@ -106,7 +106,13 @@ struct ds_grid {
     int const_q = 1;              // potential's fine level: the coloured sweep takes its constant q from a register
     int graphs = 1;               // replay pairs of multigrid-CG iterations as HIP graphs
     int phi_direct = 1;           // the liquid-transport potential by the direct (diagonalised) solve
+    int extrap = 1;               // species warm start plus the previous step's solve correction
   } tune;
+  // the species solve's correction of its warm start in the last ds_step (omega~ - omega'); valid while
+  // corr_ok (cleared by ds_set_fields; recording and the adjoint's replays neither read nor write it)
+  double* om_corr = nullptr;
+  bool corr_ok = false;
+  bool recording = false;
   bool fdm_ok = false;             // the grid's potential system takes the direct solve
   // Graphs of two FP32-multigrid CG iterations, keyed by what their launches
   // hold: solution and direction buffers, V-cycle output, system scale.  The
@@ -210,6 +216,7 @@ size_t carve(ds_grid* g, char* base) {
   g->c_new = L.take<double>(base, n);
   g->T_new = L.take<double>(base, n);
   g->om_new = L.take<double>(base, n);
+  g->om_corr = L.take<double>(base, n);
   g->mraw = L.take<double>(base, n);
   g->mdot = L.take<double>(base, n);
   g->us = L.take<double>(base, g->nu);
@@ -365,6 +372,20 @@ void carve_tape(ds_grid* g, char* base) {
   R.nlist = R.rmax + 1;
   g->tape_slot_off = L.off;
 }
+
+// Recording and the adjoint's replays run plain steps: no warm-start
+// correction read or written, none valid afterwards.
+struct RecordingScope {
+  ds_grid* g;
+  explicit RecordingScope(ds_grid* g_) : g(g_) {
+    g->recording = true;
+    g->corr_ok = false;
+  }
+  ~RecordingScope() {
+    g->recording = false;
+    g->corr_ok = false;
+  }
+};
 
 Slot slot_at(const ds_grid* g, int idx) {
   char* p = g->tape + g->tape_slot_off + (size_t)idx * slot_bytes(g);
@@ -969,13 +990,15 @@ int one_step(ds_grid* g, hipStream_t s) {
     D.rounds_T = 0;
   }
   // 5b. species (warm start omega' = c'/(rho_G theta))
+  const bool extrap = g->tune.extrap && !g->recording;
   launch_species_setup(Pp, g->a_new, g->c_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, g->om_new, s,
-                       f32_out(g, 1));
+                       f32_out(g, 1), extrap && g->corr_ok ? g->om_corr : nullptr);
   st = solve(g, 1, (var ? 1.0 : P.rho_G) * P.D / (P.h * P.h), g->om_new, s, &D.iters_omega, &D.res_omega);
   if (st == DS_ERR_NOT_CONVERGED) rc = st;
   else if (st != DS_OK) return st;
   launch_species_update(Pp, g->a_new, g->c_new, g->mdot, g->om_new, g->u, g->v, g->w, g->c, g->omega,
-                        g->partials, g->counters + CT_SPEC, g->scal, s);
+                        g->partials, g->counters + CT_SPEC, g->scal, s, extrap ? g->om_corr : nullptr);
+  g->corr_ok = extrap;
   // a variable gas: (omega, rho_G) of the new state from (T, c), and eq. 7's compressibility term
   if (var) launch_gas_end(P, g->T, g->c, g->a_new, g->rg_p, g->omega, g->rg, g->scomp, s);
   // 5c. momentum predictor with alpha' (and its implicit viscous part)
@@ -1281,6 +1304,7 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_CONST_Q")) g->tune.const_q = atoi(e);
   if (const char* e = getenv("DSVOF_GRAPHS")) g->tune.graphs = atoi(e);
   if (const char* e = getenv("DSVOF_PHI_DIRECT")) g->tune.phi_direct = atoi(e);
+  if (const char* e = getenv("DSVOF_EXTRAP")) g->tune.extrap = atoi(e);
   g->fdm_ok = fdm_supported(P) && P.n < (1LL << 29);
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {
@@ -1342,6 +1366,7 @@ int ds_set_fields(ds_grid* g, const double* alpha, const double* T, const double
   HIPCHK(g, hipMemsetAsync(g->mraw, 0, nb, s));
   HIPCHK(g, hipMemsetAsync(g->phi, 0, nb, s));
   launch_xi(g->dp, g->xi, s);
+  g->corr_ok = false;
   // conservative vapour variable c = rho_G theta omega (gas fraction only); a variable gas takes
   // rho_G from eq. 24 at each cell's T and omega
   if (g->prm.gas_density) launch_gas_from_omega(g->dp, g->T, g->omega, g->alpha, g->rg, g->c, s);
@@ -1673,6 +1698,7 @@ int ds_forward_record(ds_grid* g, int nsteps, int ckpt_every, void* tape, size_t
   g->tape_bytes = tape_bytes;
   g->tape_steps = nsteps;
   g->tape_ckpt = C;
+  RecordingScope record_scope(g);
   carve_tape(g, g->tape);
   if (g->tape_slot_off != tape_adjoint_bytes(g))
     return fail(g, DS_ERR_STATE, "internal: tape layout carves %zu bytes, sized for %zu", g->tape_slot_off,
@@ -1703,6 +1729,7 @@ int ds_adjoint(ds_grid* g, double dJ_dV, double* grads, double* dalpha0, double*
   if (!g->recorded) return fail(g, DS_ERR_STATE, "ds_forward_record has not been called");
   if (!std::isfinite(dJ_dV)) return fail(g, DS_ERR_ARG, "dJ_dV is not finite");
   hipStream_t s = S(stream);
+  RecordingScope record_scope(g);
   const DevParams& P = g->dp;
   const int N = g->tape_steps, C = g->tape_ckpt, nck = tape_nckpt(N, C);
   int st, rc = DS_OK;

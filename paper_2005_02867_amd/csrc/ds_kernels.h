@@ -61,11 +61,12 @@ void launch_energy_setup(const DevParams& P, const double* a_new, const double* 
                          double* qc, double* diag, double* b, hipStream_t s, F32Out fo = {});
 void launch_species_setup(const DevParams& P, const double* a_new, const double* c_prime,
                           const double* mdot, const double* u, const double* v, const double* w,
-                          double* qc, double* diag, double* b, double* om0, hipStream_t s, F32Out fo = {});
+                          double* qc, double* diag, double* b, double* om0, hipStream_t s, F32Out fo = {},
+                          const double* corr = nullptr);
 void launch_species_update(const DevParams& P, const double* a_new, const double* c_prime,
                            const double* mdot, const double* om, const double* u, const double* v,
                            const double* w, double* c, double* omega, double* partials,
-                           unsigned* counter, double* scal, hipStream_t s);
+                           unsigned* counter, double* scal, hipStream_t s, double* corr = nullptr);
 void launch_predictor(const DevParams& P, const double* a_new, const double* xi, const double* u,
                       const double* v, const double* w, double* us, double* vs, double* ws,
                       hipStream_t s);

@@ -758,7 +758,7 @@ __global__ void __launch_bounds__(BLOCK) k_species_setup(DevParams P, const doub
                                 const double* __restrict__ mdot, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
                                 double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b,
-                                double* __restrict__ om0, F32Out fo) {
+                                double* __restrict__ om0, F32Out fo, const double* __restrict__ corr) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   const double sc = (P.rg ? 1.0 : P.rho_G) * P.D / (P.h * P.h);
@@ -789,7 +789,10 @@ __global__ void __launch_bounds__(BLOCK) k_species_setup(DevParams P, const doub
     diag[c] = d;
     // the literal species form has no mdot source (the saturated liquid feeds the gas)
     b[c] = P.species_form == 1 ? cp_[c] / P.dt : cp_[c] / P.dt + mdot[c];
-    if (om0) om0[c] = cp_[c] / (rgc * th);
+    if (om0) {
+      const double w0 = cp_[c] / (rgc * th);
+      om0[c] = corr ? w0 + corr[c] : w0;
+    }
     if (fo.q) {
       fo.q[c] = (float)qcell;
       fo.d[c] = (float)d;
@@ -803,7 +806,7 @@ __global__ void __launch_bounds__(BLOCK) k_species_update(DevParams P, const dou
                                  const double* __restrict__ u, const double* __restrict__ v,
                                  const double* __restrict__ w, double* __restrict__ cout,
                                  double* __restrict__ omega, double* partials, unsigned* counter,
-                                 double* scal) {
+                                 double* scal, double* __restrict__ corr) {
   long long b0, b1;
   block_range(P.n, b0, b1);
   const double sc = (P.rg ? 1.0 : P.rho_G) * P.D / (P.h * P.h);
@@ -837,6 +840,7 @@ __global__ void __launch_bounds__(BLOCK) k_species_update(DevParams P, const dou
     const double cn = (P.species_form == 1 ? cp_[c] : cp_[c] + P.dt * mdot[c]) - P.dt * face;
     cout[c] = cn;
     omega[c] = cn / (rgc * th);   // a variable gas replaces it from eq. 24 at the end of the step
+    if (corr) corr[c] = oc - cp_[c] / (rgc * th);   // the solve's change of the warm start
   }
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
@@ -1314,14 +1318,16 @@ void launch_energy_setup(const DevParams& P, const double* a_new, const double* 
 }
 void launch_species_setup(const DevParams& P, const double* a_new, const double* c_prime,
                           const double* mdot, const double* u, const double* v, const double* w,
-                          double* qc, double* diag, double* b, double* om0, hipStream_t s, F32Out fo) {
-  k_species_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, u, v, w, qc, diag, b, om0, fo);
+                          double* qc, double* diag, double* b, double* om0, hipStream_t s, F32Out fo,
+                          const double* corr) {
+  k_species_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, u, v, w, qc, diag, b, om0, fo, corr);
 }
 void launch_species_update(const DevParams& P, const double* a_new, const double* c_prime,
                            const double* mdot, const double* om, const double* u, const double* v,
                            const double* w, double* c, double* omega, double* partials,
-                           unsigned* counter, double* scal, hipStream_t s) {
-  k_species_update<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, om, u, v, w, c, omega, partials, counter, scal);
+                           unsigned* counter, double* scal, hipStream_t s, double* corr) {
+  k_species_update<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, om, u, v, w, c, omega, partials, counter,
+                                                      scal, corr);
 }
 void launch_predictor(const DevParams& P, const double* a_new, const double* xi, const double* u,
                       const double* v, const double* w, double* us, double* vs, double* ws,
