@@ -75,6 +75,13 @@ __device__ __forceinline__ Cx cispi(double x) {
 // gives the DCT-II: even elements first, odd ones reversed at the end.
 __device__ __forceinline__ int reorder(int n, int N) { return (n & 1) ? N - 1 - (n >> 1) : (n >> 1); }
 
+// Position in LDS of element e of a complex line of length n: within each
+// 16-element row the low bits are XOR-ed with 5 (row mod 4), so that 16
+// consecutive lanes meet 16 different banks both on contiguous accesses and
+// on the strided writes of the first two radix-4 passes (strides 4 and 16).
+// Lines whose length is not a multiple of 16 keep the identity.
+__device__ __forceinline__ int swz(int e, int n) { return (n & 15) ? e : e ^ (5 * ((e >> 4) & 3)); }
+
 // Twiddle tables in LDS, filled once per workgroup: W[j] = e^{-2 pi i j/N}
 // (the FFT's) and H[k] = e^{-i pi k/(2N)} (the DCT's pre/post factors).
 __device__ __forceinline__ void fill_tables(Cx* W, Cx* H, int N) {
@@ -93,8 +100,9 @@ __device__ __forceinline__ Cx conjc(Cx a) { return {a.re, -a.im}; }
 // q k n/(p r) of the table W, conjugated for the inverse), takes the length-r
 // DFT and writes y[(i - k) r + k + q p].
 template <int SIGN>
-__device__ Cx* fft_lds(Cx* a, Cx* b, int lines, const FftPlan& pl, const Cx* W) {
+__device__ Cx* fft_lds(Cx* a, Cx* b, int lines, const FftPlan& pl, const Cx* W, int ls = 0) {
   const int n = pl.n;
+  if (ls == 0) ls = n;   // line stride (complex elements)
   int p = 1;
   for (int s = 0; s < pl.nr; ++s) {
     const int r = pl.r[s];
@@ -103,33 +111,34 @@ __device__ Cx* fft_lds(Cx* a, Cx* b, int lines, const FftPlan& pl, const Cx* W) 
     for (int t = threadIdx.x; t < lines * m; t += FDM_NT) {
       const int line = t / m, i = t - line * m;
       const int k = i % p;
-      const Cx* x = a + line * n;
-      Cx* y = b + line * n;
+      const Cx* x = a + line * ls;
+      Cx* y = b + line * ls;
       const int j = (i - k) * r + k;
       const int e1 = k * step;
       auto tw = [&](int e) { return SIGN < 0 ? W[e] : conjc(W[e]); };
       if (r == 4) {
         const Cx w1 = tw(e1), w2 = tw(2 * e1), w3 = tw(3 * e1);
-        const Cx u0 = x[i], u1 = cmul(x[i + m], w1), u2 = cmul(x[i + 2 * m], w2), u3 = cmul(x[i + 3 * m], w3);
+        const Cx u0 = x[swz(i, n)], u1 = cmul(x[swz(i + m, n)], w1), u2 = cmul(x[swz(i + 2 * m, n)], w2),
+                 u3 = cmul(x[swz(i + 3 * m, n)], w3);
         const Cx s02 = cadd(u0, u2), d02 = csub(u0, u2), s13 = cadd(u1, u3), d13 = cmuli(csub(u1, u3), (double)SIGN);
-        y[j] = cadd(s02, s13);
-        y[j + p] = cadd(d02, d13);
-        y[j + 2 * p] = csub(s02, s13);
-        y[j + 3 * p] = csub(d02, d13);
+        y[swz(j, n)] = cadd(s02, s13);
+        y[swz(j + p, n)] = cadd(d02, d13);
+        y[swz(j + 2 * p, n)] = csub(s02, s13);
+        y[swz(j + 3 * p, n)] = csub(d02, d13);
       } else if (r == 2) {
-        const Cx u0 = x[i], u1 = cmul(x[i + m], tw(e1));
-        y[j] = cadd(u0, u1);
-        y[j + p] = csub(u0, u1);
+        const Cx u0 = x[swz(i, n)], u1 = cmul(x[swz(i + m, n)], tw(e1));
+        y[swz(j, n)] = cadd(u0, u1);
+        y[swz(j + p, n)] = csub(u0, u1);
       } else {   // r == 3
         const Cx w1 = tw(e1), w2 = tw(2 * e1);
-        const Cx u0 = x[i], u1 = cmul(x[i + m], w1), u2 = cmul(x[i + 2 * m], w2);
+        const Cx u0 = x[swz(i, n)], u1 = cmul(x[swz(i + m, n)], w1), u2 = cmul(x[swz(i + 2 * m, n)], w2);
         const Cx s12 = cadd(u1, u2);
         // e^{SIGN 2 pi i/3} = -1/2 + SIGN i sqrt(3)/2
         const Cx d12 = cmuli(csub(u1, u2), (double)SIGN * 0.86602540378443864676);
         const Cx c = {u0.re - 0.5 * s12.re, u0.im - 0.5 * s12.im};
-        y[j] = cadd(u0, s12);
-        y[j + p] = cadd(c, d12);
-        y[j + 2 * p] = csub(c, d12);
+        y[swz(j, n)] = cadd(u0, s12);
+        y[swz(j + p, n)] = cadd(c, d12);
+        y[swz(j + 2 * p, n)] = csub(c, d12);
       }
     }
     __syncthreads();
@@ -146,7 +155,7 @@ __device__ Cx* fft_lds(Cx* a, Cx* b, int lines, const FftPlan& pl, const Cx* W) 
 // V = (Z[k] + conj Z[N-k])/2 (comp 0) or (Z[k] - conj Z[N-k])/(2i) (comp 1);
 // C[k] = Re(V e^{-i pi k/(2N)}).
 __device__ __forceinline__ double dct_coef(const Cx* Z, int k, int N, int comp, const Cx* H) {
-  const Cx a = Z[k], b = Z[k == 0 ? 0 : N - k];
+  const Cx a = Z[swz(k, N)], b = Z[swz(k == 0 ? 0 : N - k, N)];
   Cx V;
   if (comp == 0) V = {0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
   else V = {0.5 * (a.im + b.im), -0.5 * (a.re - b.re)};
@@ -209,7 +218,7 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_lateral(FdmLat A, const double* 
       const int n = e / L, kk = e - n * L;
       double v = (k0 + kk < A.nz) ? src[base + n * A.sline + kk] : 0.0;
       if (A.dst && (n & 1)) v = -v;
-      double* slot = reinterpret_cast<double*>(&bufa[(kk >> 1) * N + reorder(n, N)]);
+      double* slot = reinterpret_cast<double*>(&bufa[(kk >> 1) * N + swz(reorder(n, N), N)]);
       slot[kk & 1] = v;
     }
     __syncthreads();
@@ -230,7 +239,7 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_lateral(FdmLat A, const double* 
     __syncthreads();
     for (int e = threadIdx.x; e < N * P; e += FDM_NT) {
       const int line = e / N, k = e - line * N;
-      bufa[line * N + k] = packed_inverse(R + 2 * line * N, R + (2 * line + 1) * N, k, N, H);
+      bufa[line * N + swz(k, N)] = packed_inverse(R + 2 * line * N, R + (2 * line + 1) * N, k, N, H);
     }
     __syncthreads();
     const Cx* z = fft_lds<1>(bufa, bufb, P, A.pl, W);
@@ -238,7 +247,7 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_lateral(FdmLat A, const double* 
     for (int e = threadIdx.x; e < N * L; e += FDM_NT) {
       const int n = e / L, kk = e - n * L;
       if (k0 + kk >= A.nz) continue;
-      const Cx zv = z[(kk >> 1) * N + reorder(n, N)];
+      const Cx zv = z[(kk >> 1) * N + swz(reorder(n, N), N)];
       double v = ((kk & 1) ? zv.im : zv.re) * inv;
       if (A.dst && (n & 1)) v = -v;
       dst[base + n * A.sline + kk] = v;
@@ -258,9 +267,12 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_lateral_pipe(FdmLat A, const dou
   extern __shared__ Cx lds[];
   const int N = A.N;
   constexpr int L = FDM_LAT_LINES, P = L / 2;
+  // lines padded by one element (coefficient rows by one double): lanes that step over lines
+  // meet other LDS banks
+  const int LS = N + 1, RS = N + 1;
   Cx* bufa = lds;
-  Cx* bufb = lds + P * N;
-  Cx* W = lds + 2 * P * N;
+  Cx* bufb = lds + P * LS;
+  Cx* W = lds + 2 * P * LS;
   Cx* H = W + N;
   fill_tables(W, H, N);   // read after the first barrier below
   const int NL = N * L;
@@ -279,42 +291,42 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_lateral_pipe(FdmLat A, const dou
   for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const int o = grp / A.nzc, k0 = (grp - o * A.nzc) * L;
     const long long base = (long long)o * A.so + k0;
-    double* R = reinterpret_cast<double*>(bufb);   // inverse: coefficients, line-major (L lines of N)
+    double* R = reinterpret_cast<double*>(bufb);   // inverse: coefficients, line-major (L lines of RS)
 #pragma unroll
     for (int q = 0; q < FDM_PF; ++q) {
       const int e = threadIdx.x + q * FDM_NT;
       if (e < NL) {
         const int n = e / L, kk = e - n * L;
         if (INV) {
-          R[kk * N + (A.dst ? N - 1 - n : n)] = pf[q];
+          R[kk * RS + (A.dst ? N - 1 - n : n)] = pf[q];
         } else {
           const double v = (A.dst && (n & 1)) ? -pf[q] : pf[q];
-          reinterpret_cast<double*>(&bufa[(kk >> 1) * N + reorder(n, N)])[kk & 1] = v;
+          reinterpret_cast<double*>(&bufa[(kk >> 1) * LS + swz(reorder(n, N), N)])[kk & 1] = v;
         }
       }
     }
     __syncthreads();
     if (grp + (int)gridDim.x < ngroups) fetch(grp + gridDim.x);   // in flight during the transform
     if (!INV) {
-      const Cx* Z = fft_lds<-1>(bufa, bufb, P, A.pl, W);
+      const Cx* Z = fft_lds<-1>(bufa, bufb, P, A.pl, W, LS);
       for (int e = threadIdx.x; e < NL; e += FDM_NT) {
         const int k = e / L, kk = e - k * L;
         if (k0 + kk >= A.nz) continue;
-        const double c = dct_coef(Z + (kk >> 1) * N, k, N, kk & 1, H);
+        const double c = dct_coef(Z + (kk >> 1) * LS, k, N, kk & 1, H);
         dst[base + (long long)(A.dst ? N - 1 - k : k) * A.sline + kk] = c;
       }
     } else {
       for (int e = threadIdx.x; e < N * P; e += FDM_NT) {
         const int line = e / N, k = e - line * N;
-        bufa[line * N + k] = packed_inverse(R + 2 * line * N, R + (2 * line + 1) * N, k, N, H);
+        bufa[line * LS + swz(k, N)] = packed_inverse(R + 2 * line * RS, R + (2 * line + 1) * RS, k, N, H);
       }
       __syncthreads();
-      const Cx* z = fft_lds<1>(bufa, bufb, P, A.pl, W);
+      const Cx* z = fft_lds<1>(bufa, bufb, P, A.pl, W, LS);
       const double inv = 1.0 / N;
       for (int e = threadIdx.x; e < NL; e += FDM_NT) {
         const int n = e / L, kk = e - n * L;
         if (k0 + kk >= A.nz) continue;
-        const Cx zv = z[(kk >> 1) * N + reorder(n, N)];
+        const Cx zv = z[(kk >> 1) * LS + swz(reorder(n, N), N)];
         double v = ((kk & 1) ? zv.im : zv.re) * inv;
         if (A.dst && (n & 1)) v = -v;
         dst[base + n * A.sline + kk] = v;
@@ -364,10 +376,10 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z(FdmZ A, double* __restrict__ x
     const int c = line & 1;
     if (A.mirror) {
       const int m1 = nz + k, m2 = nz - 1 - k;
-      row[2 * reorder(m1, M) + c] = (m1 & 1) ? -v : v;
-      row[2 * reorder(m2, M) + c] = (m2 & 1) ? -v : v;
+      row[2 * swz(reorder(m1, M), M) + c] = (m1 & 1) ? -v : v;
+      row[2 * swz(reorder(m2, M), M) + c] = (m2 & 1) ? -v : v;
     } else {
-      row[2 * reorder(k, M) + c] = (k & 1) ? -v : v;
+      row[2 * swz(reorder(k, M), M) + c] = (k & 1) ? -v : v;
     }
   }
   __syncthreads();
@@ -390,7 +402,7 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z(FdmZ A, double* __restrict__ x
   Cx* Wb = const_cast<Cx*>(Z);
   for (int e = threadIdx.x; e < P * M; e += FDM_NT) {
     const int pr = e / M, k = e - pr * M;
-    Wb[pr * M + k] = packed_inverse(R + 2 * pr * M, R + (2 * pr + 1) * M, k, M, H);
+    Wb[pr * M + swz(k, M)] = packed_inverse(R + 2 * pr * M, R + (2 * pr + 1) * M, k, M, H);
   }
   __syncthreads();
   const Cx* z = fft_lds<1>(Wb, reinterpret_cast<Cx*>(R), P, A.pl, W);
@@ -399,7 +411,7 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z(FdmZ A, double* __restrict__ x
   for (int e = threadIdx.x; e < nl * nz; e += FDM_NT) {
     const int line = e / nz, k = e - line * nz;
     const int m = off + k;
-    const Cx zv = z[(line >> 1) * M + reorder(m, M)];
+    const Cx zv = z[(line >> 1) * M + swz(reorder(m, M), M)];
     const double v = ((line & 1) ? zv.im : zv.re) * inv;
     line0[e] = (m & 1) ? -v : v;
   }
@@ -417,6 +429,10 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z_pipe(FdmZ A, double* __restric
   Cx* W = lds + 2 * P * M;
   Cx* H = W + M;
   fill_tables(W, H, M);   // read after the first barrier below
+  // z eigenvalue of DST mode M-1-m at entry m; the lateral eigenvalue sum of each line of a block
+  double* lamz = reinterpret_cast<double*>(H + M);
+  double* lxy = lamz + M;
+  for (int m = threadIdx.x; m < M; m += FDM_NT) lamz[m] = lam(M - 1 - m, M, 1);
   double pf[FDM_PF];
   auto fetch = [&](int grp) {
     const long long l0 = (long long)grp * L;
@@ -433,6 +449,11 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z_pipe(FdmZ A, double* __restric
     const long long l0 = (long long)grp * L;
     const int nl = (int)(A.nlines - l0 < L ? A.nlines - l0 : L);
     double* line0 = x + l0 * nz;
+    if ((int)threadIdx.x < nl) {
+      const long long L_ = l0 + threadIdx.x;
+      const int i = (int)(L_ / A.ny), j = (int)(L_ - (long long)i * A.ny);
+      lxy[threadIdx.x] = lam(i, A.nx, A.dstx) + lam(j, A.ny, A.dsty);
+    }
     if (nl < L)
       for (int e = threadIdx.x; e < L * M; e += FDM_NT) {   // zero the lines past the grid
         const int line = e / M;
@@ -448,10 +469,10 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z_pipe(FdmZ A, double* __restric
         const int c = line & 1;
         if (A.mirror) {
           const int m1 = nz + k, m2 = nz - 1 - k;
-          row[2 * reorder(m1, M) + c] = (m1 & 1) ? -v : v;
-          row[2 * reorder(m2, M) + c] = (m2 & 1) ? -v : v;
+          row[2 * swz(reorder(m1, M), M) + c] = (m1 & 1) ? -v : v;
+          row[2 * swz(reorder(m2, M), M) + c] = (m2 & 1) ? -v : v;
         } else {
-          row[2 * reorder(k, M) + c] = (k & 1) ? -v : v;
+          row[2 * swz(reorder(k, M), M) + c] = (k & 1) ? -v : v;
         }
       }
     }
@@ -463,9 +484,7 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z_pipe(FdmZ A, double* __restric
       const int line = e / M, m = e - line * M;
       double v = 0.0;
       if (line < nl) {
-        const long long L_ = l0 + line;
-        const int i = (int)(L_ / A.ny), j = (int)(L_ - (long long)i * A.ny);
-        const double sig = lam(i, A.nx, A.dstx) + lam(j, A.ny, A.dsty) + lam(M - 1 - m, M, 1);
+        const double sig = lxy[line] + lamz[m];
         v = dct_coef(Z + (line >> 1) * M, m, M, line & 1, H) * A.scale / sig;
       }
       R[line * M + m] = v;
@@ -474,7 +493,7 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z_pipe(FdmZ A, double* __restric
     Cx* Wb = const_cast<Cx*>(Z);
     for (int e = threadIdx.x; e < P * M; e += FDM_NT) {
       const int pr = e / M, k = e - pr * M;
-      Wb[pr * M + k] = packed_inverse(R + 2 * pr * M, R + (2 * pr + 1) * M, k, M, H);
+      Wb[pr * M + swz(k, M)] = packed_inverse(R + 2 * pr * M, R + (2 * pr + 1) * M, k, M, H);
     }
     __syncthreads();
     const Cx* z = fft_lds<1>(Wb, reinterpret_cast<Cx*>(R), P, A.pl, W);
@@ -483,7 +502,7 @@ __global__ void __launch_bounds__(FDM_NT) k_fdm_z_pipe(FdmZ A, double* __restric
     for (int e = threadIdx.x; e < nl * nz; e += FDM_NT) {
       const int line = e / nz, k = e - line * nz;
       const int m = off + k;
-      const Cx zv = z[(line >> 1) * M + reorder(m, M)];
+      const Cx zv = z[(line >> 1) * M + swz(reorder(m, M), M)];
       const double v = ((line & 1) ? zv.im : zv.re) * inv;
       line0[e] = (m & 1) ? -v : v;
     }
@@ -534,10 +553,13 @@ FdmGeometry geometry(const DevParams& P, double c_op) {
   // LDS: two complex buffers of the packed lines
   const size_t lmax = 160 * 1024;
   az.lines = 16;
-  while (az.lines > 2 && (size_t)(az.lines + 2) * az.M * sizeof(Cx) > lmax) az.lines /= 2;
-  G.lds_z = (size_t)(az.lines + 2) * az.M * sizeof(Cx);   // two buffers of lines/2 complex lines, two tables
-  G.lds_lat_x = (size_t)(FDM_LAT_LINES + 2) * ax.N * sizeof(Cx);
-  G.lds_lat_y = (size_t)(FDM_LAT_LINES + 2) * ay.N * sizeof(Cx);
+  while (az.lines > 2 && (size_t)(az.lines + 2) * az.M * sizeof(Cx) + (size_t)(az.M + az.lines) * sizeof(double) > lmax)
+    az.lines /= 2;
+  // two buffers of lines/2 complex lines, two tables; the pipelined z pass also the eigenvalue tables
+  G.lds_z = (size_t)(az.lines + 2) * az.M * sizeof(Cx) + (size_t)(az.M + az.lines) * sizeof(double);
+  // (the pipelined lateral pass pads each of its 16 half-lines by one element)
+  G.lds_lat_x = (size_t)(FDM_LAT_LINES + 2) * ax.N * sizeof(Cx) + FDM_LAT_LINES * sizeof(Cx);
+  G.lds_lat_y = (size_t)(FDM_LAT_LINES + 2) * ay.N * sizeof(Cx) + FDM_LAT_LINES * sizeof(Cx);
   if (G.lds_z > lmax || G.lds_lat_x > lmax || G.lds_lat_y > lmax) return G;
   G.ax = ax;
   G.ay = ay;
