@@ -200,6 +200,10 @@ typedef struct ds_diagnostics {
  *     for a no-flux z- face); its true FP64 residual is checked, and the
  *     multigrid CG takes over from its result should it miss tol_phi (0: the
  *     multigrid CG always).
+ *   DSVOF_EXTRAP [1]: ds_step starts each species solve from omega' plus
+ *     the previous step's solve correction (omega~ - omega'), kept in the
+ *     workspace; ds_set_fields clears it, and ds_forward_record and
+ *     ds_adjoint run without it (0: from omega' alone).
  *   DSVOF_GRAPHS [1]: the precision form's multigrid CG replays pairs of
  *     iterations as HIP graphs, captured on a stream of the handle's own and
  *     launched on the caller's (0: one launch at a time; same results bit
