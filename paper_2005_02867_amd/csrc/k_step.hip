@@ -1176,12 +1176,37 @@ __global__ void __launch_bounds__(BLOCK) k_project(DevParams P, const double* __
   long long b0, b1;
   block_range(P.n, b0, b1);
   const double ih = 1.0 / P.h;
+  const long long sx = (long long)P.ny * P.nz, sy = P.nz;
   for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
     int i, j, k;
     decode(P, c, i, j, k);
-    u[uidx(P, i, j, k)] = project_face<0, VAR>(P, a_new, p, us, i, j, k, ih);
-    v[vidx(P, i, j, k)] = project_face<1, VAR>(P, a_new, p, vs, i, j, k, ih);
-    w[widx(P, i, j, k)] = project_face<2, VAR>(P, a_new, p, ws, i, j, k, ih);
+    // the cell and its neighbour below along each axis (the cell itself at a low box face), every value
+    // loaded before any is used; the faces below the cell as project_face takes them
+    const long long cn[3] = {i > 0 ? c - sx : c, j > 0 ? c - sy : c, k > 0 ? c - 1 : c};
+    const long long e[3] = {uidx(P, i, j, k), vidx(P, i, j, k), widx(P, i, j, k)};
+    const double fs[3] = {us[e[0]], vs[e[1]], ws[e[2]]};
+    const double ac = a_new[c], pc = p[c], gc = VAR ? P.rg[c] : P.rho_G;
+    double an[3], pn[3], gn[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      an[q] = a_new[cn[q]];
+      pn[q] = p[cn[q]];
+      gn[q] = VAR ? P.rg[cn[q]] : P.rho_G;
+    }
+    const double bC = 1.0 / mix(clamp01(ac), P.rho_L, gc);
+    const int pos[3] = {i, j, k};
+    double* const out[3] = {u, v, w};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double val;
+      if (pos[q] > 0) {
+        const double bL = 1.0 / mix(clamp01(an[q]), P.rho_L, gn[q]);
+        val = fs[q] - P.dt * 0.5 * (bL + bC) * (pc - pn[q]) * ih;
+      } else {
+        val = pressure_dirichlet(P.kind[q * 2]) ? fs[q] - 2.0 * P.dt * bC * pc * ih : fs[q];
+      }
+      out[q][e[q]] = val;
+    }
     if (i == P.nx - 1) u[uidx(P, P.nx, j, k)] = project_face<0, VAR>(P, a_new, p, us, P.nx, j, k, ih);
     if (j == P.ny - 1) v[vidx(P, i, P.ny, k)] = project_face<1, VAR>(P, a_new, p, vs, i, P.ny, k, ih);
     if (k == P.nz - 1) w[widx(P, i, j, P.nz)] = project_face<2, VAR>(P, a_new, p, ws, i, j, P.nz, ih);
