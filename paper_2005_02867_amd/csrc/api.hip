@@ -42,6 +42,16 @@ double host_pr_Z(double T, double p, double Tc, double Pc, double om) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Arrays of the FP32-multigrid pressure solve: its operator (FP64 and the
+// setup's FP32 copies), right-hand side, residuals, directions, A p and the
+// reduction scratch of its kernels.
+struct PBufs {
+  double *qc = nullptr, *diag = nullptr, *b = nullptr, *r = nullptr, *q = nullptr;
+  float *qc32 = nullptr, *diag32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p32alt = nullptr;
+  double* partials = nullptr;
+  unsigned* counters = nullptr;
+};
+
 }  // namespace
 
 struct ds_grid {
@@ -107,12 +117,20 @@ struct ds_grid {
     int graphs = 1;               // replay pairs of multigrid-CG iterations as HIP graphs
     int phi_direct = 1;           // the liquid-transport potential by the direct (diagonalised) solve
     int extrap = 1;               // species warm start plus the previous step's solve correction
+    int overlap = 1;              // predictor and pressure on a second stream, concurrent with energy and species
   } tune;
   // the species solve's correction of its warm start in the last ds_step (omega~ - omega'); valid while
   // corr_ok (cleared by ds_set_fields; recording and the adjoint's replays neither read nor write it)
   double* om_corr = nullptr;
   bool corr_ok = false;
   bool recording = false;
+  // The pressure solve's arrays: pb[0] the ones shared with the other solves; pb[1] its own set, carved
+  // where ds_step runs the predictor and the pressure on a second stream (s2) while the energy and species
+  // solves run on the caller's (precision form with the FP32 V-cycle, ambient gas, inviscid step)
+  PBufs pb[2];
+  bool pb_own = false;
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool fdm_ok = false;             // the grid's potential system takes the direct solve
   // Graphs of two FP32-multigrid CG iterations, keyed by what their launches
   // hold: solution and direction buffers, V-cycle output, system scale.  The
@@ -302,6 +320,25 @@ size_t carve(ds_grid* g, char* base) {
     }
   }
   g->phi_ready = false;
+  g->pb[0] = PBufs{g->qc, g->diag, g->b, g->r, g->q, g->qc32, g->diag32, g->r32, g->p32, g->p32alt, g->partials,
+                   g->counters};
+  if (g->pb_own) {
+    PBufs& B = g->pb[1];
+    B.qc = L.take<double>(base, n);
+    B.diag = L.take<double>(base, n);
+    B.b = L.take<double>(base, n);
+    B.r = L.take<double>(base, n);
+    B.q = L.take<double>(base, n);
+    B.qc32 = L.take<float>(base, n);
+    B.diag32 = L.take<float>(base, n);
+    B.r32 = L.take<float>(base, n);
+    B.p32 = L.take<float>(base, n);
+    B.p32alt = L.take<float>(base, n);
+    B.partials = L.take<double>(base, (size_t)MAX_BLOCKS * MAX_RED);
+    B.counters = L.take<unsigned>(base, CT_COUNT);
+  } else {
+    g->pb[1] = PBufs{};
+  }
   return L.off;
 }
 
@@ -489,6 +526,15 @@ F32Out f32_out(ds_grid* g, int sys) {
   fo.mg = sys == 2 && g->prm.pressure_precond == 1;
   fo.sc = (double)(float)(g->dp.dt / (g->dp.h * g->dp.h));   // scale of the FP32 fine level (sys 2)
   g->f32_sys = sys;
+  return fo;
+}
+// The pressure setup's FP32 copies into the pressure's own arrays (pb[1]).
+F32Out f32_out_own(ds_grid* g) {
+  F32Out fo;
+  fo.q = g->pb[1].qc32;
+  fo.d = g->pb[1].diag32;
+  fo.mg = true;
+  fo.sc = (double)(float)(g->dp.dt / (g->dp.h * g->dp.h));
   return fo;
 }
 bool take_f32(ds_grid* g, int sys) {
@@ -699,15 +745,11 @@ int cg_solve_mixed(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int
   return g->h_status[sys].done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
 }
 
-// Precision form of a multigrid-preconditioned solve: FP64 conjugate
-// gradients (operator, vectors, dot products) with the V-cycle -- the bulk of
-// each iteration's memory traffic -- in FP32 on FP32 copies of the operator.
-// No restarts: the FP64 recurrence converges to tol like cg_solve64.
 // The graph of two FP32-multigrid CG iterations for the current buffers and
 // scale, captured on first use (null: capture failed; the caller then runs
 // the iterations one by one and graphs are switched off for the handle).
-hipGraphExec_t mg32_graph(ds_grid* g, const Lev<double>& L, MgHier<float>& H, const CgVecsMg32& V, float* z,
-                          SolveStatus* st, double sc) {
+hipGraphExec_t mg32_graph(ds_grid* g, const PBufs& B, const Lev<double>& L, MgHier<float>& H, const CgVecsMg32& V,
+                          float* z, SolveStatus* st, double sc) {
   for (auto& e : g->graphs)
     if (e.ex && e.x == V.x && e.p == V.p && e.z == z && e.sc == sc) return e.ex;
   if (!g->cap_stream && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -716,7 +758,7 @@ hipGraphExec_t mg32_graph(ds_grid* g, const Lev<double>& L, MgHier<float>& H, co
     g->tune.graphs = 0;
     return nullptr;
   }
-  hipGraphExec_t ex = capture_mg32_pair(L, H, V, g->r32, z, st, g->partials, g->counters + CT_SOLVE0, g->cap_stream);
+  hipGraphExec_t ex = capture_mg32_pair(L, H, V, B.r32, z, st, B.partials, B.counters + CT_SOLVE0, g->cap_stream);
   if (!ex) {
     g->tune.graphs = 0;
     return nullptr;
@@ -732,25 +774,63 @@ hipGraphExec_t mg32_graph(ds_grid* g, const Lev<double>& L, MgHier<float>& H, co
   return ex;
 }
 
-int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
+// One FP32-multigrid CG solve in flight: mg32_begin enqueues its start and
+// its first batch of iterations without a host test (every kernel reads the
+// device status and returns at once once the solve has converged); mg32_end
+// takes the host tests, enqueues further batches until converged and applies
+// the last deferred update.
+struct Mg32Run {
+  Lev<double> L;
+  MgHier<float>* H = nullptr;
+  CgVecsMg32 V{};
+  float* z = nullptr;
+  SolveStatus* ss = nullptr;
+  const PBufs* B = nullptr;
+  double sc = 0.0;
+  double* x = nullptr;
+  hipStream_t s = nullptr;
+  bool first = true;
+};
+
+int mg32_batch(ds_grid* g, Mg32Run& R) {
+  const PBufs& B = *R.B;
+  const int m = batch_size(batch_of(g, 2, R.x), R.first);
+  int t = 0;
+  if (R.first) {
+    cg_iteration_mg32(R.L, *R.H, R.V, B.r32, &R.z, R.ss, B.partials, B.counters + CT_SOLVE0, true, R.s);
+    R.first = false;
+    ++t;
+  }
+  hipGraphExec_t ex = nullptr;
+  for (; g->tune.graphs && t + 2 <= m; t += 2) {
+    if (!ex && !(ex = mg32_graph(g, B, R.L, *R.H, R.V, R.z, R.ss, R.sc))) break;
+    HIPCHK(g, hipGraphLaunch(ex, R.s));
+  }
+  for (; t < m; ++t) cg_iteration_mg32(R.L, *R.H, R.V, B.r32, &R.z, R.ss, B.partials, B.counters + CT_SOLVE0, false, R.s);
+  HIPCHK(g, hipGetLastError());
+  return DS_OK;
+}
+
+// f32_ready: the setup wrote B's FP32 copies of the operator.
+int mg32_begin(ds_grid* g, const PBufs& B, bool f32_ready, double sc, double* x, hipStream_t s, double tol,
+               Mg32Run& R) {
   int st;
   const int sys = 2;
   Lev<double> L = g->L0;
   L.sc = sc;
-  L.qc = g->qc;
-  L.diag = g->diag;
+  L.qc = B.qc;
+  L.diag = B.diag;
   pressure_type(g, sys, L);
   const bool phi = g->phi_op;   // the potential, on its own operator arrays
   if (phi) L.qc = g->phi_qc;
   Lev<float> F;
   lev_dims(F, L.nx, L.ny, L.nz, sc);
-  F.qc = phi ? g->phi_q[0] : g->qc32;
-  F.diag = phi ? g->phi_d[0] : g->diag32;
+  F.qc = phi ? g->phi_q[0] : B.qc32;
+  F.diag = phi ? g->phi_d[0] : B.diag32;
   // the value phi_q[0] holds in every cell: 1/dt rounded to FP32, as the setup's q converted
   if (phi && g->tune.const_q) F.qk = (float)(1.0 / g->dp.dt);
   if (phi && g->tune.const_q) L.qk = 1.0 / g->dp.dt;   // and in FP64, the value phi_qc holds
   if (phi) {
-    g->f32_sys = -1;
     if (!g->phi_ready) {
       launch_to_float(g->phi_qc, g->phi_q[0], g->n, s);
       launch_mg_diag(F, g->dirmask, g->phi_d[0], s);
@@ -760,9 +840,9 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
         g->H32phi.lev[l].diag = g->phi_d[l];
       }
     }
-  } else if (!take_f32(g, sys)) {
-    launch_to_float(g->qc, g->qc32, g->n, s);
-    launch_mg_diag(F, g->dirmask, g->diag32, s);   // the formula the V-cycle forms on the fly
+  } else if (!f32_ready) {
+    launch_to_float(B.qc, B.qc32, g->n, s);
+    launch_mg_diag(F, g->dirmask, B.diag32, s);   // the formula the V-cycle forms on the fly
   }
   MgHier<float>& H = phi ? g->H32phi : g->H32;
   H.lev[0] = F;
@@ -777,49 +857,55 @@ int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters,
   if (phi) g->phi_ready = true;
   SolveStatus* ss = g->status + sys;
   if ((st = init_status(g, sys, tol, g->prm.maxit, s)) != DS_OK) return st;
-  launch_resid64(L, g->b, x, g->r, ss, g->partials, g->counters + CT_SOLVE0, true, s, g->r32);
+  launch_resid64(L, B.b, x, B.r, ss, B.partials, B.counters + CT_SOLVE0, true, s, B.r32);
   launch_zero_if_flagged(x, g->n, ss, s);
   HIPCHK(g, hipGetLastError());
-  // No host test of the start: the first batch is enqueued at once.  Every
-  // kernel of the solve reads the device status and returns at once when the
-  // start already meets the tolerance, and the iteration count that selects
-  // the last deferred update comes from the test after the batch.
   g->h_status[sys].done = 0;
-  {
-    CgVecsMg32 V{x, g->r, g->p32, g->p32alt, g->q};
-    // iteration t writes its direction into p_odd (t odd) or p_even (t even)
-    float* const p_odd = V.p_alt;
-    float* const p_even = V.p;
-    float* z = nullptr;
-    cg_start_mg32(L, H, g->r, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, s, true);
-    bool first = true;
-    while (!g->h_status[sys].done) {
-      const int m = batch_size(batch_of(g, sys, x), first);
-      int t = 0;
-      if (first) {
-        cg_iteration_mg32(L, H, V, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, true, s);
-        first = false;
-        ++t;
-      }
-      hipGraphExec_t ex = nullptr;
-      for (; g->tune.graphs && t + 2 <= m; t += 2) {
-        if (!ex && !(ex = mg32_graph(g, L, H, V, z, ss, sc))) break;
-        HIPCHK(g, hipGraphLaunch(ex, s));
-      }
-      for (; t < m; ++t) cg_iteration_mg32(L, H, V, g->r32, &z, ss, g->partials, g->counters + CT_SOLVE0, false, s);
-      HIPCHK(g, hipGetLastError());
-      if ((st = sync_status(g, sys, s)) != DS_OK) return st;
-    }
-    const int it = g->h_status[sys].it;
-    if (it > 0) launch_axpy_alpha(x, (it & 1) ? p_odd : p_even, ss, g->n, s);
-    HIPCHK(g, hipGetLastError());
+  R.L = L;
+  R.H = &H;
+  R.V = CgVecsMg32{x, B.r, B.p32, B.p32alt, B.q};   // iteration t writes its direction into p_alt (t odd) or p
+  R.z = nullptr;
+  R.ss = ss;
+  R.B = &B;
+  R.sc = sc;
+  R.x = x;
+  R.s = s;
+  R.first = true;
+  cg_start_mg32(L, H, B.r, B.r32, &R.z, ss, B.partials, B.counters + CT_SOLVE0, s, true);
+  return mg32_batch(g, R);
+}
+
+int mg32_end(ds_grid* g, Mg32Run& R, int* iters, double* res) {
+  int st;
+  const int sys = 2;
+  if ((st = sync_status(g, sys, R.s)) != DS_OK) return st;
+  while (!g->h_status[sys].done) {
+    if ((st = mg32_batch(g, R)) != DS_OK) return st;
+    if ((st = sync_status(g, sys, R.s)) != DS_OK) return st;
   }
+  const int it = g->h_status[sys].it;
+  if (it > 0) launch_axpy_alpha(R.x, (it & 1) ? R.V.p_alt : R.V.p, R.ss, g->n, R.s);
+  HIPCHK(g, hipGetLastError());
   const SolveStatus& h = g->h_status[sys];
-  batch_of(g, sys, x) = std::max(2, std::min(256, h.it));
+  batch_of(g, sys, R.x) = std::max(2, std::min(256, h.it));
   *iters = h.it;
   *res = h.res;
   g->diag_out.refinements_p = 0;
   return h.done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
+}
+
+// Precision form of a multigrid-preconditioned solve: FP64 conjugate
+// gradients (operator, vectors, dot products) with the V-cycle -- the bulk of
+// each iteration's memory traffic -- in FP32 on FP32 copies of the operator.
+// No restarts: the FP64 recurrence converges to tol like cg_solve64.  On the
+// shared arrays (pb[0]).
+int cg_solve64_mg32(ds_grid* g, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
+  const bool f32_ready = !g->phi_op && take_f32(g, 2);
+  if (g->phi_op) g->f32_sys = -1;
+  Mg32Run R;
+  int st = mg32_begin(g, g->pb[0], f32_ready, sc, x, s, tol, R);
+  if (st != DS_OK) return st;
+  return mg32_end(g, R, iters, res);
 }
 
 int solve(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* iters, double* res, double tol) {
@@ -976,6 +1062,37 @@ int one_step(ds_grid* g, hipStream_t s) {
   // stages after the advection read rho_G' (a variable gas)
   DevParams Pp = P;
   if (var) Pp.rg = g->rg_p;
+  // The predictor and the pressure (5c, 6) read none of what the energy and species stages write, nor write
+  // what they read: with the pressure's own arrays they run on the second stream, forked here and joined
+  // before the projection (on every return path).
+  const bool overlap = g->pb_own && !g->recording;
+  struct Join {
+    ds_grid* g;
+    hipStream_t s;
+    bool on = false;
+    ~Join() {
+      if (on) {
+        (void)hipEventRecord(g->ev_join, g->s2);
+        (void)hipStreamWaitEvent(s, g->ev_join, 0);
+      }
+    }
+  } join{g, s};
+  Mg32Run PR;
+  if (overlap) {
+    if (!g->s2) {
+      HIPCHK(g, hipStreamCreateWithFlags(&g->s2, hipStreamNonBlocking));
+      HIPCHK(g, hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+      HIPCHK(g, hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+    }
+    HIPCHK(g, hipEventRecord(g->ev_fork, s));
+    HIPCHK(g, hipStreamWaitEvent(g->s2, g->ev_fork, 0));
+    join.on = true;
+    const PBufs& B = g->pb[1];
+    launch_predictor(Pp, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, g->s2);
+    launch_pressure_setup(Pp, g->a_new, g->mdot, g->us, g->vs, g->ws, B.qc, B.diag, B.b, g->s2, f32_out_own(g),
+                          nullptr);
+    if ((st = mg32_begin(g, B, true, P.dt / (P.h * P.h), g->p, g->s2, g->prm.tol, PR)) != DS_OK) return st;
+  }
   // 5a. energy (warm start T')
   if (P.solve_energy) {
     launch_energy_setup(Pp, g->a_new, g->T_new, g->mdot, g->u, g->v, g->w, g->qc, g->diag, g->b, s,
@@ -1001,22 +1118,35 @@ int one_step(ds_grid* g, hipStream_t s) {
   g->corr_ok = extrap;
   // a variable gas: (omega, rho_G) of the new state from (T, c), and eq. 7's compressibility term
   if (var) launch_gas_end(P, g->T, g->c, g->a_new, g->rg_p, g->omega, g->rg, g->scomp, s);
-  // 5c. momentum predictor with alpha' (and its implicit viscous part)
-  launch_predictor(Pp, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, s);
-  if (P.viscous) {
-    st = viscous_solve(g, g->a_new, s, &D.iters_visc, &D.res_visc, Pp);
+  if (overlap) {
+    D.iters_visc = 0;
+    D.res_visc = 0.0;
+    st = mg32_end(g, PR, &D.iters_p, &D.res_p);
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
   } else {
-    D.iters_visc = 0;
-    D.res_visc = 0.0;
+    // 5c. momentum predictor with alpha' (and its implicit viscous part)
+    launch_predictor(Pp, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, s);
+    if (P.viscous) {
+      st = viscous_solve(g, g->a_new, s, &D.iters_visc, &D.res_visc, Pp);
+      if (st == DS_ERR_NOT_CONVERGED) rc = st;
+      else if (st != DS_OK) return st;
+    } else {
+      D.iters_visc = 0;
+      D.res_visc = 0.0;
+    }
+    // 6. pressure (warm start p^n) and correction
+    launch_pressure_setup(Pp, g->a_new, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s, f32_out(g, 2),
+                          var ? g->scomp : nullptr);
+    st = solve_pressure_system(g, s, &D.iters_p, &D.res_p);
+    if (st == DS_ERR_NOT_CONVERGED) rc = st;
+    else if (st != DS_OK) return st;
   }
-  // 6. pressure (warm start p^n) and correction
-  launch_pressure_setup(Pp, g->a_new, g->mdot, g->us, g->vs, g->ws, g->qc, g->diag, g->b, s, f32_out(g, 2),
-                        var ? g->scomp : nullptr);
-  st = solve_pressure_system(g, s, &D.iters_p, &D.res_p);
-  if (st == DS_ERR_NOT_CONVERGED) rc = st;
-  else if (st != DS_OK) return st;
+  if (join.on) {   // the projection reads p and u* from the second stream
+    HIPCHK(g, hipEventRecord(g->ev_join, g->s2));
+    HIPCHK(g, hipStreamWaitEvent(s, g->ev_join, 0));
+    join.on = false;
+  }
   launch_project(Pp, g->a_new, g->p, g->us, g->vs, g->ws, g->u, g->v, g->w, s);
   std::swap(g->alpha, g->a_new);
   // diagnostics
@@ -1305,7 +1435,10 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_GRAPHS")) g->tune.graphs = atoi(e);
   if (const char* e = getenv("DSVOF_PHI_DIRECT")) g->tune.phi_direct = atoi(e);
   if (const char* e = getenv("DSVOF_EXTRAP")) g->tune.extrap = atoi(e);
+  if (const char* e = getenv("DSVOF_OVERLAP")) g->tune.overlap = atoi(e);
   g->fdm_ok = fdm_supported(P) && P.n < (1LL << 29);
+  g->pb_own = g->tune.overlap && prm->precision == DS_PREC_MIXED && prm->pressure_precond == 1 && g->tune.mg32 &&
+              mg32_supported(g->L0) && prm->gas_density == DS_GAS_AMBIENT && !prm->viscous;
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {
     if (prm->pressure_precond == 1) build_hier(g->H32, nx, ny, nz, prm->h, prm->dt);
@@ -1328,6 +1461,9 @@ int ds_destroy_grid(ds_grid* g) {
   if (!g) return DS_ERR_ARG;
   drop_graphs(g);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  if (g->s2) (void)hipStreamDestroy(g->s2);
+  if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+  if (g->ev_join) (void)hipEventDestroy(g->ev_join);
   for (int e = 0; e < 2 * ds_grid::NEV; ++e)
     if (g->ev[e]) (void)hipEventDestroy(g->ev[e]);
   if (g->h_scal) (void)hipHostFree(g->h_scal);
@@ -1361,6 +1497,7 @@ int ds_set_fields(ds_grid* g, const double* alpha, const double* T, const double
   HIPCHK(g, hipMemcpyAsync(g->v, v, g->nv * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(g, hipMemcpyAsync(g->w, w, g->nw * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(g, hipMemsetAsync(g->counters, 0, CT_COUNT * sizeof(unsigned), s));
+  if (g->pb_own) HIPCHK(g, hipMemsetAsync(g->pb[1].counters, 0, CT_COUNT * sizeof(unsigned), s));
   HIPCHK(g, hipMemsetAsync(g->scal, 0, SC_COUNT * sizeof(double), s));
   HIPCHK(g, hipMemsetAsync(g->mdot, 0, nb, s));
   HIPCHK(g, hipMemsetAsync(g->mraw, 0, nb, s));
@@ -1624,17 +1761,19 @@ int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* byte
   const DevParams& P = g->dp;
   const bool smooth = which == DS_KERNEL_MG_SMOOTH;
   if (g->prm.precision == DS_PREC_MIXED) {
+    // the pressure's arrays: its own set where ds_step overlaps it with the energy and species solves
+    const PBufs& B = g->pb_own ? g->pb[1] : g->pb[0];
     Lev<float> F;
     lev_dims(F, P.nx, P.ny, P.nz, P.dt / (P.h * P.h));
-    F.qc = g->qc32;
-    F.diag = g->diag32;
+    F.qc = B.qc32;
+    F.diag = B.diag32;
     if (g->prm.pressure_precond == 1) {   // the fine level of the pressure V-cycle
       F.dfly = 1;
       F.dmask = g->dirmask;
     }
     const bool z32 = g->prm.pressure_precond == 1 && g->tune.mg32 && mg32_supported(g->L0);
     if (smooth) {
-      us = replay_smooth_kernel<float>(F, g->H32, g->r32, g->H32.x[0], g->H32.t[0], st, reps, s, g->ev[0],
+      us = replay_smooth_kernel<float>(F, g->H32, B.r32, g->H32.x[0], g->H32.t[0], st, reps, s, g->ev[0],
                                        g->ev[1]);
       // r, x, q read and x written (diag too unless formed from q)
       if (bytes_per_launch) *bytes_per_launch = (F.dfly ? 16.0 : 20.0) * (double)g->n;
@@ -1642,10 +1781,10 @@ int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* byte
       // the pressure solve's operator: FP64 with the FP32 preconditioned residual z
       Lev<double> L = g->L0;
       L.sc = P.dt / (P.h * P.h);
-      L.qc = g->qc;
-      L.diag = g->diag;
+      L.qc = B.qc;
+      L.diag = B.diag;
       pressure_type(g, 2, L);
-      us = replay_operator_z32(L, g->r32, g->p32, g->p32alt, g->q, st, g->partials, g->counters + CT_MISC, reps, s,
+      us = replay_operator_z32(L, B.r32, B.p32, B.p32alt, B.q, st, g->partials, g->counters + CT_MISC, reps, s,
                                g->ev[0], g->ev[1]);
       // z and p (FP32), q_coef read; p (FP32), q written (diag formed from q_coef)
       if (bytes_per_launch) *bytes_per_launch = 28.0 * (double)g->n;
