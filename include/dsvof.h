@@ -204,14 +204,14 @@ typedef struct ds_diagnostics {
  *     the previous step's solve correction (omega~ - omega'), kept in the
  *     workspace; ds_set_fields clears it, and ds_forward_record and
  *     ds_adjoint run without it (0: from omega' alone).
- *   DSVOF_OVERLAP [1]: in the precision form with the FP32 V-cycle (ambient
- *     gas, inviscid step), ds_step runs the momentum predictor and the
- *     pressure solve on a second stream of the handle's own (non-blocking,
- *     default priority), on arrays of their own in the workspace (ten more
- *     arrays of the grid: five FP64, five FP32), concurrently with the energy
- *     and species solves on the caller's stream; the projection waits for
- *     both.  Results are the same bit for bit (0: one stream; the workspace
- *     is then smaller).
+ *   DSVOF_OVERLAP [1]: with the multigrid pressure (ambient gas, inviscid
+ *     step, either precision form), ds_step runs the momentum predictor and
+ *     the pressure solve on a second stream of the handle's own (non-blocking,
+ *     default priority), on arrays of their own in the workspace (five FP64
+ *     arrays of the grid, and five FP32 or two FP64 more), concurrently with
+ *     the energy and species solves on the caller's stream; the projection
+ *     waits for both.  Results are the same bit for bit (0: one stream; the
+ *     workspace is then smaller).
  *   DSVOF_GRAPHS [1]: the precision form's multigrid CG replays pairs of
  *     iterations as HIP graphs, captured on a stream of the handle's own and
  *     launched on the caller's (0: one launch at a time; same results bit

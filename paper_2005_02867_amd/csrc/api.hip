@@ -47,6 +47,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // reduction scratch of its kernels.
 struct PBufs {
   double *qc = nullptr, *diag = nullptr, *b = nullptr, *r = nullptr, *q = nullptr;
+  double *pd = nullptr, *p_alt = nullptr;   // FP64 directions (the FP64 form)
   float *qc32 = nullptr, *diag32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p32alt = nullptr;
   double* partials = nullptr;
   unsigned* counters = nullptr;
@@ -320,20 +321,26 @@ size_t carve(ds_grid* g, char* base) {
     }
   }
   g->phi_ready = false;
-  g->pb[0] = PBufs{g->qc, g->diag, g->b, g->r, g->q, g->qc32, g->diag32, g->r32, g->p32, g->p32alt, g->partials,
-                   g->counters};
+  g->pb[0] = PBufs{g->qc,   g->diag,   g->b,   g->r,      g->q,        g->pd,       g->p_alt,
+                   g->qc32, g->diag32, g->r32, g->p32, g->p32alt, g->partials, g->counters};
   if (g->pb_own) {
     PBufs& B = g->pb[1];
+    B = PBufs{};
     B.qc = L.take<double>(base, n);
     B.diag = L.take<double>(base, n);
     B.b = L.take<double>(base, n);
     B.r = L.take<double>(base, n);
     B.q = L.take<double>(base, n);
-    B.qc32 = L.take<float>(base, n);
-    B.diag32 = L.take<float>(base, n);
-    B.r32 = L.take<float>(base, n);
-    B.p32 = L.take<float>(base, n);
-    B.p32alt = L.take<float>(base, n);
+    if (g->prm.precision == DS_PREC_MIXED) {
+      B.qc32 = L.take<float>(base, n);
+      B.diag32 = L.take<float>(base, n);
+      B.r32 = L.take<float>(base, n);
+      B.p32 = L.take<float>(base, n);
+      B.p32alt = L.take<float>(base, n);
+    } else {
+      B.pd = L.take<double>(base, n);
+      B.p_alt = L.take<double>(base, n);
+    }
     B.partials = L.take<double>(base, (size_t)MAX_BLOCKS * MAX_RED);
     B.counters = L.take<unsigned>(base, CT_COUNT);
   } else {
@@ -607,6 +614,84 @@ int cg_solve64(ds_grid* g, int sys, double sc, double* x, hipStream_t s, int* it
   *iters = h.it;
   *res = h.res;
   if (sys == 2) g->diag_out.refinements_p = 0;
+  return h.done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
+}
+
+// The FP64 form's multigrid pressure solve in flight on a set of pressure
+// arrays (as Mg32Run for the precision form): cg64p_begin enqueues the start
+// and the first batch of iterations without a host test (the CG and V-cycle
+// kernels read the device status and return at once once it has converged),
+// cg64p_end takes the host tests and applies the last deferred update.
+struct Cg64Run {
+  Lev<double> L;
+  MgHier<double>* H = nullptr;
+  CgVecs<double> V{};
+  double* z = nullptr;
+  SolveStatus* ss = nullptr;
+  const PBufs* B = nullptr;
+  double* x = nullptr;
+  hipStream_t s = nullptr;
+  bool first = true;
+  double *p_odd = nullptr, *p_even = nullptr;   // directions of odd and even iterations
+};
+
+int cg64p_batch(ds_grid* g, Cg64Run& R) {
+  const int m = batch_size(batch_of(g, 2, R.x), R.first);
+  for (int t = 0; t < m; ++t) {
+    cg_iteration(R.L, R.H, R.V, &R.z, R.ss, R.B->partials, R.B->counters + CT_SOLVE0, R.first, R.s, nullptr,
+                 nullptr);
+    R.first = false;
+  }
+  HIPCHK(g, hipGetLastError());
+  return DS_OK;
+}
+
+int cg64p_begin(ds_grid* g, const PBufs& B, double sc, double* x, hipStream_t s, double tol, Cg64Run& R) {
+  int st;
+  Lev<double> L = g->L0;
+  L.sc = sc;
+  L.qc = B.qc;
+  L.diag = B.diag;
+  pressure_type(g, 2, L);
+  MgHier<double>& H = g->H64;
+  H.lev[0] = L;
+  mg_setup_levels(H, g->dirmask, s);
+  SolveStatus* ss = g->status + 2;
+  if ((st = init_status(g, 2, tol, g->prm.maxit, s)) != DS_OK) return st;
+  launch_resid64(L, B.b, x, B.r, ss, B.partials, B.counters + CT_SOLVE0, true, s);
+  launch_zero_if_flagged(x, g->n, ss, s);
+  HIPCHK(g, hipGetLastError());
+  g->h_status[2].done = 0;
+  R.L = L;
+  R.H = &H;
+  R.V = CgVecs<double>{x, B.r, B.pd, B.p_alt, B.q, nullptr};
+  R.z = nullptr;
+  R.ss = ss;
+  R.B = &B;
+  R.x = x;
+  R.s = s;
+  R.first = true;
+  R.p_odd = R.V.p_alt;
+  R.p_even = R.V.p;
+  cg_start(L, &H, R.V, &R.z, ss, B.partials, B.counters + CT_SOLVE0, s);
+  return cg64p_batch(g, R);
+}
+
+int cg64p_end(ds_grid* g, Cg64Run& R, int* iters, double* res) {
+  int st;
+  if ((st = sync_status(g, 2, R.s)) != DS_OK) return st;
+  while (!g->h_status[2].done) {
+    if ((st = cg64p_batch(g, R)) != DS_OK) return st;
+    if ((st = sync_status(g, 2, R.s)) != DS_OK) return st;
+  }
+  const int it = g->h_status[2].it;
+  if (it > 0 && cg_defers_x(R.L)) launch_axpy_alpha(R.x, (it & 1) ? R.p_odd : R.p_even, R.ss, g->n, R.s);
+  HIPCHK(g, hipGetLastError());
+  const SolveStatus& h = g->h_status[2];
+  batch_of(g, 2, R.x) = std::max(2, std::min(256, h.it));
+  *iters = h.it;
+  *res = h.res;
+  g->diag_out.refinements_p = 0;
   return h.done == 1 ? DS_OK : DS_ERR_NOT_CONVERGED;
 }
 
@@ -1065,7 +1150,8 @@ int one_step(ds_grid* g, hipStream_t s) {
   // The predictor and the pressure (5c, 6) read none of what the energy and species stages write, nor write
   // what they read: with the pressure's own arrays they run on the second stream, forked here and joined
   // before the projection (on every return path).
-  const bool overlap = g->pb_own && !g->recording;
+  const bool overlap = g->pb_own && !g->recording && !g->timing;
+  const bool mixed = g->prm.precision == DS_PREC_MIXED;
   struct Join {
     ds_grid* g;
     hipStream_t s;
@@ -1078,6 +1164,7 @@ int one_step(ds_grid* g, hipStream_t s) {
     }
   } join{g, s};
   Mg32Run PR;
+  Cg64Run PR64;
   if (overlap) {
     if (!g->s2) {
       HIPCHK(g, hipStreamCreateWithFlags(&g->s2, hipStreamNonBlocking));
@@ -1089,9 +1176,12 @@ int one_step(ds_grid* g, hipStream_t s) {
     join.on = true;
     const PBufs& B = g->pb[1];
     launch_predictor(Pp, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, g->s2);
-    launch_pressure_setup(Pp, g->a_new, g->mdot, g->us, g->vs, g->ws, B.qc, B.diag, B.b, g->s2, f32_out_own(g),
-                          nullptr);
-    if ((st = mg32_begin(g, B, true, P.dt / (P.h * P.h), g->p, g->s2, g->prm.tol, PR)) != DS_OK) return st;
+    launch_pressure_setup(Pp, g->a_new, g->mdot, g->us, g->vs, g->ws, B.qc, B.diag, B.b, g->s2,
+                          mixed ? f32_out_own(g) : F32Out{}, nullptr);
+    const double sc = P.dt / (P.h * P.h);
+    st = mixed ? mg32_begin(g, B, true, sc, g->p, g->s2, g->prm.tol, PR)
+               : cg64p_begin(g, B, sc, g->p, g->s2, g->prm.tol, PR64);
+    if (st != DS_OK) return st;
   }
   // 5a. energy (warm start T')
   if (P.solve_energy) {
@@ -1121,7 +1211,7 @@ int one_step(ds_grid* g, hipStream_t s) {
   if (overlap) {
     D.iters_visc = 0;
     D.res_visc = 0.0;
-    st = mg32_end(g, PR, &D.iters_p, &D.res_p);
+    st = mixed ? mg32_end(g, PR, &D.iters_p, &D.res_p) : cg64p_end(g, PR64, &D.iters_p, &D.res_p);
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
   } else {
@@ -1437,8 +1527,8 @@ int ds_create_grid(int nx, int ny, int nz, const ds_params* prm, ds_grid** out) 
   if (const char* e = getenv("DSVOF_EXTRAP")) g->tune.extrap = atoi(e);
   if (const char* e = getenv("DSVOF_OVERLAP")) g->tune.overlap = atoi(e);
   g->fdm_ok = fdm_supported(P) && P.n < (1LL << 29);
-  g->pb_own = g->tune.overlap && prm->precision == DS_PREC_MIXED && prm->pressure_precond == 1 && g->tune.mg32 &&
-              mg32_supported(g->L0) && prm->gas_density == DS_GAS_AMBIENT && !prm->viscous;
+  g->pb_own = g->tune.overlap && prm->pressure_precond == 1 && prm->gas_density == DS_GAS_AMBIENT && !prm->viscous &&
+              (prm->precision == DS_PREC_FP64 || (g->tune.mg32 && mg32_supported(g->L0)));
   if (prm->pressure_precond == 1) build_hier(g->H64, nx, ny, nz, prm->h, prm->dt);
   if (prm->precision == DS_PREC_MIXED) {
     if (prm->pressure_precond == 1) build_hier(g->H32, nx, ny, nz, prm->h, prm->dt);
@@ -1794,16 +1884,17 @@ int ds_time_kernel(ds_grid* g, int which, int reps, double* avg_us, double* byte
       if (bytes_per_launch) *bytes_per_launch = 24.0 * (double)g->n;
     }
   } else {
+    const PBufs& B = g->pb_own ? g->pb[1] : g->pb[0];
     Lev<double> L = g->L0;
     L.sc = P.dt / (P.h * P.h);
-    L.qc = g->qc;
-    L.diag = g->diag;
+    L.qc = B.qc;
+    L.diag = B.diag;
     if (g->prm.pressure_precond == 1) pressure_type(g, 2, L);
     if (smooth)
-      us = replay_smooth_kernel<double>(L, g->H64, g->r, g->H64.x[0], g->H64.t[0], st, reps, s, g->ev[0],
+      us = replay_smooth_kernel<double>(L, g->H64, B.r, g->H64.x[0], g->H64.t[0], st, reps, s, g->ev[0],
                                         g->ev[1]);
     else
-      us = replay_operator_kernel<double>(L, g->r, g->pd, g->p_alt, g->q, st, g->partials, g->counters + CT_MISC,
+      us = replay_operator_kernel<double>(L, B.r, B.pd, B.p_alt, B.q, st, g->partials, g->counters + CT_MISC,
                                           reps, s, g->ev[0], g->ev[1]);
     if (bytes_per_launch) *bytes_per_launch = (smooth ? 40.0 : 48.0) * (double)g->n - (L.dfly ? 8.0 * (double)g->n : 0.0);
   }

@@ -276,29 +276,31 @@ def test_species_warm_start_correction(mode, monkeypatch):
         assert _err(out[0][k], out[1][k]) < 1e-9, k
 
 
+@pytest.mark.parametrize("precision", [W.PREC_MIXED, W.PREC_FP64])
 @pytest.mark.parametrize("case", ["C1-natural", "C1-forced", "C1-farfield", "C2-64"])
-def test_overlapped_pressure_is_bit_identical(case, monkeypatch):
-    """In the precision form ds_step runs the predictor and the pressure solve
-    on a second stream, on the pressure's own arrays, while the energy and
-    species solves run on the caller's stream (DSVOF_OVERLAP=0: all on one
-    stream, on the shared arrays).  The two stages touch disjoint data, so
-    five steps give every field bit for bit the same, with the same iteration
-    counts; the 64^3 cut of the forced-convection configuration takes several
-    batches of pressure iterations per step."""
+def test_overlapped_pressure_is_bit_identical(case, precision, monkeypatch):
+    """With the multigrid pressure, ds_step runs the predictor and the
+    pressure solve on a second stream, on the pressure's own arrays, while the
+    energy and species solves run on the caller's stream (DSVOF_OVERLAP=0: all
+    on one stream, on the shared arrays).  The two stages touch disjoint data,
+    so five steps give every field bit for bit the same, with the same
+    iteration counts, in both precision forms; the 64^3 cut of the
+    forced-convection configuration takes several batches of pressure
+    iterations per step."""
     ds = _lib()
     name, tag = case.split("-")
     if name == "C1":
         mode = {"natural": W.BC_NATURAL, "forced": W.BC_FORCED, "farfield": W.BC_FARFIELD}[tag]
-        prm, run = W.config("C1", bc_mode=mode, w_in=0.2 if mode == W.BC_FORCED else 0.0, precision=W.PREC_MIXED)
+        prm, run = W.config("C1", bc_mode=mode, w_in=0.2 if mode == W.BC_FORCED else 0.0, precision=precision)
         f = W.initial_fields(prm, **run)
     else:
-        prm, run = W.config("C2", precision=W.PREC_MIXED)
+        prm, run = W.config("C2", precision=precision)
         prm = W.finalize(dict(prm, nx=64, ny=64, nz=64, h=6e-3 / 64, x0=None))
         f = W.initial_fields(prm, D0=run["D0"])
     out, its = [], []
     for ov in ("1", "0"):
         monkeypatch.setenv("DSVOF_OVERLAP", ov)
-        print(f"{case}: overlap {ov}", flush=True)
+        print(f"{case} precision {precision}: overlap {ov}", flush=True)
         g = ds.Grid(prm)
         g.set_fields(f)
         n_it = []
