@@ -209,9 +209,10 @@ typedef struct ds_diagnostics {
  *     the pressure solve on a second stream of the handle's own (non-blocking,
  *     default priority), on arrays of their own in the workspace (five FP64
  *     arrays of the grid, and five FP32 or two FP64 more), concurrently with
- *     the energy and species solves on the caller's stream; the projection
- *     waits for both.  Results are the same bit for bit (0: one stream; the
- *     workspace is then smaller).
+ *     the energy and species solves on the caller's stream (recording and
+ *     the adjoint's replays included); the projection waits for both.
+ *     Results are the same bit for bit (0: one stream; the workspace is then
+ *     smaller).
  *   DSVOF_GRAPHS [1]: the precision form's multigrid CG replays pairs of
  *     iterations as HIP graphs, captured on a stream of the handle's own and
  *     launched on the caller's (0: one launch at a time; same results bit

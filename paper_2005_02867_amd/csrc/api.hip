@@ -417,8 +417,9 @@ void carve_tape(ds_grid* g, char* base) {
   g->tape_slot_off = L.off;
 }
 
-// Recording and the adjoint's replays run plain steps: no warm-start
-// correction read or written, none valid afterwards.
+// Recording and the adjoint's replays run steps without the species
+// warm-start correction (which moves a solve within its tolerance); none is
+// valid afterwards.  (The second stream stays: it changes no result.)
 struct RecordingScope {
   ds_grid* g;
   explicit RecordingScope(ds_grid* g_) : g(g_) {
@@ -1150,7 +1151,7 @@ int one_step(ds_grid* g, hipStream_t s) {
   // The predictor and the pressure (5c, 6) read none of what the energy and species stages write, nor write
   // what they read: with the pressure's own arrays they run on the second stream, forked here and joined
   // before the projection (on every return path).
-  const bool overlap = g->pb_own && !g->recording && !g->timing;
+  const bool overlap = g->pb_own && !g->timing;
   const bool mixed = g->prm.precision == DS_PREC_MIXED;
   struct Join {
     ds_grid* g;
