@@ -28,6 +28,10 @@
  *
  * Streams: every call enqueues work on `stream` (a hipStream_t; NULL means
  * the null stream).  Calls that return host scalars synchronise that stream.
+ * A step may also run part of its work on a stream of the handle's own
+ * (DSVOF_OVERLAP below); it forks from `stream` with an event and `stream`
+ * waits for it with another before the step's next stage, so every call's
+ * work is ordered on `stream` as a whole.
  *
  * Errors: every call returns a ds_status; ds_last_error() gives a message.
  * No call throws.  A handle is not thread-safe.
