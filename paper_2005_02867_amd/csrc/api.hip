@@ -130,6 +130,7 @@ struct ds_grid {
   // solves run on the caller's (precision form with the FP32 V-cycle, ambient gas, inviscid step)
   PBufs pb[2];
   bool pb_own = false;
+  bool s2_failed = false;   // the second stream or its events could not be created: one stream
   hipStream_t s2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool fdm_ok = false;             // the grid's potential system takes the direct solve
@@ -1103,10 +1104,75 @@ int one_step(ds_grid* g, hipStream_t s) {
   ds_diagnostics& D = g->diag_out;
   int rc = DS_OK, st;
   D.fuel_mass_before = g->fuel_mass_prev;
+  // The second stream (where the pressure has arrays of its own): forked from s with an event and joined back
+  // into s with another, on every return path too.
+  if (g->pb_own && !g->s2 && !g->s2_failed) {
+    if (hipStreamCreateWithFlags(&g->s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      g->s2_failed = true;
+    }
+  }
+  const bool overlap = g->pb_own && !g->timing && !g->s2_failed;
+  struct Join {
+    ds_grid* g;
+    hipStream_t s;
+    bool on = false;
+    ~Join() {
+      if (on) {
+        (void)hipEventRecord(g->ev_join, g->s2);
+        (void)hipStreamWaitEvent(s, g->ev_join, 0);
+      }
+    }
+  } join{g, s};
+  auto fork = [&]() -> int {
+    HIPCHK(g, hipEventRecord(g->ev_fork, s));
+    HIPCHK(g, hipStreamWaitEvent(g->s2, g->ev_fork, 0));
+    join.on = true;
+    return DS_OK;
+  };
+  auto join_now = [&]() -> int {
+    HIPCHK(g, hipEventRecord(g->ev_join, g->s2));
+    HIPCHK(g, hipStreamWaitEvent(s, g->ev_join, 0));
+    join.on = false;
+    return DS_OK;
+  };
+  // 3 (first part).  The liquid-transport potential reads only u^n: by the direct solve it runs on the second
+  // stream (on the pressure's own arrays, their A p array as the transforms' scratch) while the evaporation and
+  // liquid sources run on s.
+  const bool phi_fork = overlap && g->prm.liquid_transport && potential_direct(g);
+  if (phi_fork) {
+    const PBufs& B = g->pb[1];
+    const double sc = P.dt / (P.h * P.h);
+    if ((st = fork()) != DS_OK) return st;
+    launch_div_setup(P, g->u, g->v, g->w, B.qc, B.diag, B.b, g->s2);
+    if (launch_fdm_solve(P, sc * (1.0 / P.dt), B.b, g->phi, B.q, g->s2) != 0)
+      return fail(g, DS_ERR_STATE, "internal: the direct potential solve refused the grid");
+    Lev<double> L = g->L0;
+    L.sc = sc;
+    L.qc = B.qc;
+    L.diag = B.diag;
+    pressure_type(g, 2, L);
+    if ((st = init_status(g, 2, g->prm.tol_phi, g->prm.maxit, g->s2)) != DS_OK) return st;
+    launch_resid64(L, B.b, g->phi, B.r, g->status + 2, B.partials, B.counters + CT_SOLVE0, true, g->s2);
+    HIPCHK(g, hipGetLastError());
+  }
   // 1-2. evaporation source and liquid source
   if ((st = evaporation_source(g, s)) != DS_OK) return st;
+  bool phi_done = false;
+  if (phi_fork) {
+    if ((st = sync_status(g, 2, g->s2)) != DS_OK) return st;
+    if ((st = join_now()) != DS_OK) return st;
+    if (g->h_status[2].done == 1) {
+      D.iters_phi = 0;
+      D.res_phi = g->h_status[2].res;
+      phi_done = true;
+    }
+    // otherwise the path below solves again on s (the multigrid CG from the direct solve's result)
+  }
   // 3. advection of alpha1 with the divergence-free part of u^n, c and T with u^n
-  if (g->prm.liquid_transport) {
+  if (g->prm.liquid_transport && !phi_done) {
     // precision form, multigrid: the potential's own operator arrays, written by its first setup only
     const bool own = !potential_direct(g) && g->prm.precision == DS_PREC_MIXED && g->prm.pressure_precond == 1 &&
                      g->tune.mg32 && mg32_supported(g->L0);
@@ -1151,30 +1217,11 @@ int one_step(ds_grid* g, hipStream_t s) {
   // The predictor and the pressure (5c, 6) read none of what the energy and species stages write, nor write
   // what they read: with the pressure's own arrays they run on the second stream, forked here and joined
   // before the projection (on every return path).
-  const bool overlap = g->pb_own && !g->timing;
   const bool mixed = g->prm.precision == DS_PREC_MIXED;
-  struct Join {
-    ds_grid* g;
-    hipStream_t s;
-    bool on = false;
-    ~Join() {
-      if (on) {
-        (void)hipEventRecord(g->ev_join, g->s2);
-        (void)hipStreamWaitEvent(s, g->ev_join, 0);
-      }
-    }
-  } join{g, s};
   Mg32Run PR;
   Cg64Run PR64;
   if (overlap) {
-    if (!g->s2) {
-      HIPCHK(g, hipStreamCreateWithFlags(&g->s2, hipStreamNonBlocking));
-      HIPCHK(g, hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
-      HIPCHK(g, hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
-    }
-    HIPCHK(g, hipEventRecord(g->ev_fork, s));
-    HIPCHK(g, hipStreamWaitEvent(g->s2, g->ev_fork, 0));
-    join.on = true;
+    if ((st = fork()) != DS_OK) return st;
     const PBufs& B = g->pb[1];
     launch_predictor(Pp, g->a_new, g->xi, g->u, g->v, g->w, g->us, g->vs, g->ws, g->s2);
     launch_pressure_setup(Pp, g->a_new, g->mdot, g->us, g->vs, g->ws, B.qc, B.diag, B.b, g->s2,
@@ -1233,11 +1280,7 @@ int one_step(ds_grid* g, hipStream_t s) {
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
   }
-  if (join.on) {   // the projection reads p and u* from the second stream
-    HIPCHK(g, hipEventRecord(g->ev_join, g->s2));
-    HIPCHK(g, hipStreamWaitEvent(s, g->ev_join, 0));
-    join.on = false;
-  }
+  if (join.on && (st = join_now()) != DS_OK) return st;   // the projection reads p and u* from the second stream
   launch_project(Pp, g->a_new, g->p, g->us, g->vs, g->ws, g->u, g->v, g->w, s);
   std::swap(g->alpha, g->a_new);
   // diagnostics
