@@ -282,9 +282,11 @@ def test_overlapped_pressure_is_bit_identical(case, precision, monkeypatch):
     """With the multigrid pressure, ds_step runs the predictor and the
     pressure solve on a second stream, on the pressure's own arrays, while the
     energy and species solves run on the caller's stream (DSVOF_OVERLAP=0: all
-    on one stream, on the shared arrays).  The two stages touch disjoint data,
-    so five steps give every field bit for bit the same, with the same
-    iteration counts, in both precision forms; the 64^3 cut of the
+    on one stream, on the shared arrays); with the direct potential solve the
+    potential runs on the second stream too, beside the evaporation source.
+    The stages touch disjoint data, so five steps give every field bit for
+    bit the same, with the same iteration counts and budget terms (B_L, B_v,
+    fuel mass), in both precision forms; the 64^3 cut of the
     forced-convection configuration takes several batches of pressure
     iterations per step."""
     ds = _lib()
@@ -307,11 +309,11 @@ def test_overlapped_pressure_is_bit_identical(case, precision, monkeypatch):
         for _ in range(5):
             g.step(1)
             d = g.diagnostics()
-            n_it.append((d["iters_T"], d["iters_omega"], d["iters_p"]))
+            n_it.append((d["iters_T"], d["iters_omega"], d["iters_p"], d["B_L"], d["B_v"], d["fuel_mass"]))
         out.append({k: v.cpu() for k, v in g.get_fields().items()})
         its.append(n_it)
         del g
-    print("iterations T/omega/p per step, overlapped:", its[0])
+    print("iterations T/omega/p, B_L, B_v, fuel mass per step, overlapped:", its[0])
     assert its[0] == its[1]
     for k in out[0]:
         assert torch.equal(out[0][k], out[1][k]), k
