@@ -937,15 +937,19 @@ __device__ __forceinline__ void pred_store(const PredPlane<QF>& f, double (*S)[Q
 // u*, v*, w* of every face, marching along x: the thread of cell (x, j, k)
 // writes the faces (x, j, k) of the three arrays and, on the high box faces,
 // the face beyond.  Plane x and x+1 tiles give the y/z neighbours and the
-// x+1 values; the x-1 values are kept from the previous plane.  VAR: a
-// variable gas (its density field P.rg rides along as a sixth tile).
+// x+1 values; the x-1 values are kept from the previous plane.  Two LDS
+// slots: the loads of plane x+2 are issued before plane x is computed and
+// land in plane x's slot after it (two barriers per plane), which keeps the
+// block at 31.7 KB of LDS so that the registers, not the LDS, bound the
+// occupancy.  VAR: a variable gas (its density field P.rg rides along as a
+// sixth tile).
 template <bool VAR>
 __global__ void __launch_bounds__(BLOCK)
 k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const double* __restrict__ xi,
             const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
             double* __restrict__ us, double* __restrict__ vs, double* __restrict__ ws) {
   constexpr int QF = VAR ? 6 : 5;   // u, v, w, alpha, xi (, rho_G)
-  __shared__ double sQ[3][QF][QTILE];   // slot (x mod 3), field
+  __shared__ double sQ[2][QF][QTILE];   // slot ((x - x0) mod 2), field
   const int tz = threadIdx.x % MZ, ty = threadIdx.x / MZ;
   const double ih = 1.0 / P.h;
   constexpr int FU = 0, FV = 1, FW = 2, FA = 3, FX = 4, FR = 5;
@@ -969,19 +973,19 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
       px = in ? xi[cidx(P, X, jj, kk)] : 0.0;
       pg = VAR ? (in ? P.rg[cidx(P, X, jj, kk)] : 0.0) : P.rho_G;
     }
-    __syncthreads();   // the previous tile's last reads of the slots
+    __syncthreads();   // the previous tile's last reads and writes of the slots
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 2; ++q) {
       PredPlane<QF> f;
       pred_fetch(P, u, v, w, a_new, xi, x0 + q, x1, y0, z0, f);
-      pred_store(f, sQ[(x0 + q) % 3]);
+      pred_store(f, sQ[q]);
     }
-    __syncthreads();
-    int slot = x0 % 3;
+    int slot = 0;
     for (int x = x0; x < x1; ++x) {
       PredPlane<QF> nf;
-      pred_fetch(P, u, v, w, a_new, xi, x + 3, x1, y0, z0, nf);
-      const int s1 = slot == 2 ? 0 : slot + 1;
+      pred_fetch(P, u, v, w, a_new, xi, x + 2, x1, y0, z0, nf);
+      __syncthreads();   // plane x+1 (stored after the previous plane, or before the loop) is visible
+      const int s1 = slot ^ 1;
       if (live) {
         const int ce = (ty + 1) * QZ + tz + 1;
         auto T0 = [&](int f, int dy, int dz) { return sQ[slot][f][ce + dy * QZ + dz]; };
