@@ -461,6 +461,67 @@ __device__ __forceinline__ void adv_geo_fluxes(const DevParams& P, const double*
   G.gwx = (want && want_wx && lane < MY) ? Fz[widx(P, i, clampi(y0 + lane, P.ny), min(z0 + MZ, P.nz))] : 0.0;
 }
 
+// Cell walk of the per-cell setup kernels, marching along x over the same
+// tiles (MZ z by MY y rows, one wavefront per row): each thread keeps its
+// column's values of the NF fields at x-1, x, x+1 in registers, takes the z
+// neighbours from the adjacent lanes (a load only at a wave's first and last
+// lane) and loads the y neighbours.  body(c, i, j, k, ctr, nb, has) runs for
+// every cell of the box with ctr[f] the cell's value of field f and
+// nb[f][0..5] its neighbours at x-1, x+1, y-1, y+1, z-1, z+1 (the cell's own
+// value across a box face, where has[] is false).
+template <int NF, class Body>
+__device__ __forceinline__ void march_cells(const DevParams& P, const MarchGeom& G,
+                                            const double* const (&fld)[NF], Body&& body) {
+  const int tz = threadIdx.x % MZ, ty = threadIdx.x / MZ;
+  const long long sx = (long long)P.ny * P.nz;
+  for (long long t = march_logical(); t < G.tiles; t += gridDim.x) {
+    int x0, y0, z0;
+    march_tile(G, t, x0, y0, z0);
+    const int x1 = min(x0 + G.xlen, P.nx);
+    const int j = y0 + ty, k = z0 + tz;
+    const bool live = j < P.ny && k < P.nz;
+    // rows and lanes past the box hold the nearest cell (their values only feed shuffles no live lane uses)
+    const long long col = (long long)min(j, P.ny - 1) * P.nz + min(k, P.nz - 1);
+    bool has[6];
+    has[2] = j > 0;
+    has[3] = j < P.ny - 1;
+    has[4] = k > 0;
+    has[5] = k < P.nz - 1;
+    double xm[NF], xc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      xc[f] = fld[f][x0 * sx + col];
+      xm[f] = x0 > 0 ? fld[f][(x0 - 1) * sx + col] : xc[f];
+    }
+    for (int x = x0; x < x1; ++x) {
+      const long long c = x * sx + col;
+      has[0] = x > 0;
+      has[1] = x < P.nx - 1;
+      double nb[NF][6], xp[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        xp[f] = has[1] ? fld[f][c + sx] : xc[f];
+        const double ym = fld[f][has[2] ? c - P.nz : c], yp = fld[f][has[3] ? c + P.nz : c];
+        double zm = __shfl_up(xc[f], 1), zp = __shfl_down(xc[f], 1);
+        if (tz == 0) zm = fld[f][has[4] ? c - 1 : c];
+        if (tz == MZ - 1) zp = fld[f][has[5] ? c + 1 : c];
+        nb[f][0] = has[0] ? xm[f] : xc[f];
+        nb[f][1] = xp[f];
+        nb[f][2] = ym;
+        nb[f][3] = yp;
+        nb[f][4] = has[4] ? zm : xc[f];
+        nb[f][5] = has[5] ? zp : xc[f];
+      }
+      if (live) body(c, x, j, k, xc, nb, has);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        xm[f] = xc[f];
+        xc[f] = xp[f];
+      }
+    }
+  }
+}
+
 // Van Leer face value on a grid line (cells m, a | b, p; face between a and b)
 // for flow in +direction (fwd) or -direction: with C the upwind, D the
 // downwind and U the far-upwind cell, C + (C - U)(D - C)/(D - U) where the
@@ -709,22 +770,18 @@ k_advect(DevParams P, MarchGeom G, const double* __restrict__ a1, const double* 
 
 // ---------------------------------------------------------------- S6-S8
 // Energy, eq. 8 after the advection: (rho cp/dt) T - div(k grad T) = (rho cp/dt) T' - mdot dh.
-__global__ void __launch_bounds__(BLOCK) k_energy_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ Tp,
+__global__ void __launch_bounds__(BLOCK) k_energy_setup(DevParams P, MarchGeom G, const double* __restrict__ a_new, const double* __restrict__ Tp,
                                const double* __restrict__ mdot, const double* __restrict__ u,
                                const double* __restrict__ v, const double* __restrict__ w,
                                double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b,
                                F32Out fo) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
   const double ih2 = 1.0 / (P.h * P.h);
   const double Kb = 2.0 * P.k_G * ih2;
-  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
-    int i, j, k;
-    decode(P, c, i, j, k);
-    double an[6];
-    bool has[6];
-    nbr6(P, a_new, c, i, j, k, an, has);
-    const double ab = clamp01(a_new[c]);
+  const double* const fl[1] = {a_new};
+  march_cells<1>(P, G, fl, [&](long long c, int i, int j, int k, const double (&ctr)[1], const double (&nb)[1][6],
+                               const bool (&has)[6]) {
+    const double(&an)[6] = nb[0];
+    const double ab = clamp01(ctr[0]);
     const double rho = mix(ab, P.rho_L, rho_gas(P, c)), cp = mix(ab, P.cp_L, P.cp_G), kc = mix(ab, P.k_L, P.k_G);
     const double m = rho * cp / P.dt;
     double d = m, rhs = m * Tp[c] - mdot[c] * P.dh;
@@ -747,32 +804,33 @@ __global__ void __launch_bounds__(BLOCK) k_energy_setup(DevParams P, const doubl
       fo.q[c] = (float)kc;
       fo.d[c] = (float)d;
     }
-  }
+  });
 }
 
 // Species, eq. 9 for c = rho_G theta omega: (rho_G theta/dt) w - div(rho_G D theta grad w) = c'/dt + mdot
 // (without mdot in the literal species form).  Face coefficient K_f = sc (q_c + q_nb)/2 with the cell
 // coefficient q = theta and sc = rho_G D/h^2, or, for a variable gas, q = rho_G theta and sc = D/h^2; the
 // Dirichlet faces keep the ambient gas's 2 rho_G D/h^2.
-__global__ void __launch_bounds__(BLOCK) k_species_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
+// VAR: a variable gas (P.rg set; its density marched beside alpha').
+template <bool VAR>
+__global__ void __launch_bounds__(BLOCK) k_species_setup(DevParams P, MarchGeom G, const double* __restrict__ a_new, const double* __restrict__ cp_,
                                 const double* __restrict__ mdot, const double* __restrict__ u,
                                 const double* __restrict__ v, const double* __restrict__ w,
                                 double* __restrict__ qc, double* __restrict__ diag, double* __restrict__ b,
                                 double* __restrict__ om0, F32Out fo, const double* __restrict__ corr) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
-  const double sc = (P.rg ? 1.0 : P.rho_G) * P.D / (P.h * P.h);
+  const double sc = (VAR ? 1.0 : P.rho_G) * P.D / (P.h * P.h);
   const double Kb = 2.0 * P.rho_G * P.D / (P.h * P.h);
-  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
-    int i, j, k;
-    decode(P, c, i, j, k);
-    double an[6], rn[6];
-    bool has[6];
-    nbr6(P, a_new, c, i, j, k, an, has);
-    if (P.rg) nbr6(P, P.rg, c, i, j, k, rn, has);
-    const double th = fmax(1.0 - clamp01(a_new[c]), P.theta_min);
-    const double rgc = rho_gas(P, c);
-    const double qcell = P.rg ? rgc * th : th;
+  constexpr int NF = VAR ? 2 : 1;   // alpha' (, rho_G)
+  const double* fl[NF];
+  fl[0] = a_new;
+  if constexpr (VAR) fl[NF - 1] = P.rg;
+  march_cells<NF>(P, G, fl, [&](long long c, int i, int j, int k, const double (&ctr)[NF], const double (&nb)[NF][6],
+                                const bool (&has)[6]) {
+    const double(&an)[6] = nb[0];
+    const double(&rn)[6] = nb[NF - 1];
+    const double th = fmax(1.0 - clamp01(ctr[0]), P.theta_min);
+    const double rgc = VAR ? ctr[NF - 1] : P.rho_G;
+    const double qcell = VAR ? rgc * th : th;
     double d = rgc * th / P.dt;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax)
@@ -780,7 +838,7 @@ __global__ void __launch_bounds__(BLOCK) k_species_setup(DevParams P, const doub
       for (int sd = 0; sd < 2; ++sd) {
         if (has[ax * 2 + sd]) {
           const double tn = fmax(1.0 - clamp01(an[ax * 2 + sd]), P.theta_min);
-          d += sc * 0.5 * (qcell + (P.rg ? rn[ax * 2 + sd] * tn : tn));
+          d += sc * 0.5 * (qcell + (VAR ? rn[ax * 2 + sd] * tn : tn));
         } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
           d += Kb;
         }
@@ -797,33 +855,34 @@ __global__ void __launch_bounds__(BLOCK) k_species_setup(DevParams P, const doub
       fo.q[c] = (float)qcell;
       fo.d[c] = (float)d;
     }
-  }
+  });
 }
 
 // Flux-form vapour update after the implicit solve; diffusive boundary outflow tally.
-__global__ void __launch_bounds__(BLOCK) k_species_update(DevParams P, const double* __restrict__ a_new, const double* __restrict__ cp_,
+template <bool VAR>
+__global__ void __launch_bounds__(BLOCK) k_species_update(DevParams P, MarchGeom G, const double* __restrict__ a_new, const double* __restrict__ cp_,
                                  const double* __restrict__ mdot, const double* __restrict__ om,
                                  const double* __restrict__ u, const double* __restrict__ v,
                                  const double* __restrict__ w, double* __restrict__ cout,
                                  double* __restrict__ omega, double* partials, unsigned* counter,
                                  double* scal, double* __restrict__ corr) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
-  const double sc = (P.rg ? 1.0 : P.rho_G) * P.D / (P.h * P.h);
+  const double sc = (VAR ? 1.0 : P.rho_G) * P.D / (P.h * P.h);
   const double Kb = 2.0 * P.rho_G * P.D / (P.h * P.h);
   double acc[1] = {0.0};
-  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
-    int i, j, k;
-    decode(P, c, i, j, k);
-    double an[6], on[6], rn[6];
-    bool has[6];
-    nbr6(P, a_new, c, i, j, k, an, has);
-    nbr6(P, om, c, i, j, k, on, has);
-    if (P.rg) nbr6(P, P.rg, c, i, j, k, rn, has);
-    const double th = fmax(1.0 - clamp01(a_new[c]), P.theta_min);
-    const double rgc = rho_gas(P, c);
-    const double qcell = P.rg ? rgc * th : th;
-    const double oc = om[c];
+  constexpr int NF = VAR ? 3 : 2;   // alpha', omega~ (, rho_G)
+  const double* fl[NF];
+  fl[0] = a_new;
+  fl[1] = om;
+  if constexpr (VAR) fl[NF - 1] = P.rg;
+  march_cells<NF>(P, G, fl, [&](long long c, int i, int j, int k, const double (&ctr)[NF], const double (&nb)[NF][6],
+                                const bool (&has)[6]) {
+    const double(&an)[6] = nb[0];
+    const double(&on)[6] = nb[1];
+    const double(&rn)[6] = nb[NF - 1];
+    const double th = fmax(1.0 - clamp01(ctr[0]), P.theta_min);
+    const double rgc = VAR ? ctr[NF - 1] : P.rho_G;
+    const double qcell = VAR ? rgc * th : th;
+    const double oc = ctr[1];
     double face = 0.0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax)
@@ -831,7 +890,7 @@ __global__ void __launch_bounds__(BLOCK) k_species_update(DevParams P, const dou
       for (int sd = 0; sd < 2; ++sd) {
         if (has[ax * 2 + sd]) {
           const double tn = fmax(1.0 - clamp01(an[ax * 2 + sd]), P.theta_min);
-          face += sc * 0.5 * (qcell + (P.rg ? rn[ax * 2 + sd] * tn : tn)) * (oc - on[ax * 2 + sd]);
+          face += sc * 0.5 * (qcell + (VAR ? rn[ax * 2 + sd] * tn : tn)) * (oc - on[ax * 2 + sd]);
         } else if (scalar_dirichlet(P.kind[ax * 2 + sd], bface_u(P, u, v, w, ax, sd, i, j, k), sd)) {
           face += Kb * oc;
           acc[0] += Kb * oc;
@@ -841,7 +900,7 @@ __global__ void __launch_bounds__(BLOCK) k_species_update(DevParams P, const dou
     cout[c] = cn;
     omega[c] = cn / (rgc * th);   // a variable gas replaces it from eq. 24 at the end of the step
     if (corr) corr[c] = oc - cp_[c] / (rgc * th);   // the solve's change of the warm start
-  }
+  });
   const int ops[1] = {RSUM};
   if (block_reduce_publish<1>(acc, ops, partials, counter)) {
     double tot[1];
@@ -1051,24 +1110,24 @@ k_predictor(DevParams P, MarchGeom G, const double* __restrict__ a_new, const do
 
 // ---------------------------------------------------------------- S10 setup
 // Pressure: sum_f (dt/h^2) (1/rho)_f (p_c - p_nb) = mdot (1/rho_G - 1/rho_L) - div u*.
-__global__ void __launch_bounds__(BLOCK) k_pressure_setup(DevParams P, const double* __restrict__ a_new, const double* __restrict__ mdot,
+template <bool VAR>
+__global__ void __launch_bounds__(BLOCK) k_pressure_setup(DevParams P, MarchGeom G, const double* __restrict__ a_new, const double* __restrict__ mdot,
                                  const double* __restrict__ us, const double* __restrict__ vs,
                                  const double* __restrict__ ws, double* __restrict__ qc,
                                  double* __restrict__ diag, double* __restrict__ b, F32Out fo,
                                  const double* __restrict__ scomp) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
   const double ih = 1.0 / P.h;
   const double sc = P.dt / (P.h * P.h);
-  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
-    int i, j, k;
-    decode(P, c, i, j, k);
-    double an[6], rn[6];
-    bool has[6];
-    nbr6(P, a_new, c, i, j, k, an, has);
-    if (P.rg) nbr6(P, P.rg, c, i, j, k, rn, has);
-    const double rgc = rho_gas(P, c);
-    const double beta = 1.0 / mix(clamp01(a_new[c]), P.rho_L, rgc);
+  constexpr int NF = VAR ? 2 : 1;   // alpha' (, rho_G)
+  const double* fl[NF];
+  fl[0] = a_new;
+  if constexpr (VAR) fl[NF - 1] = P.rg;
+  march_cells<NF>(P, G, fl, [&](long long c, int i, int j, int k, const double (&ctr)[NF], const double (&nb)[NF][6],
+                                const bool (&has)[6]) {
+    const double(&an)[6] = nb[0];
+    const double(&rn)[6] = nb[NF - 1];
+    const double rgc = VAR ? ctr[NF - 1] : P.rho_G;
+    const double beta = 1.0 / mix(clamp01(ctr[0]), P.rho_L, rgc);
     const double b32 = (double)(float)beta;
     double d = 0.0, d32 = 0.0;
 #pragma unroll
@@ -1076,7 +1135,7 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(DevParams P, const dou
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
         if (has[ax * 2 + sd]) {
-          const double bn = 1.0 / mix(clamp01(an[ax * 2 + sd]), P.rho_L, P.rg ? rn[ax * 2 + sd] : P.rho_G);
+          const double bn = 1.0 / mix(clamp01(an[ax * 2 + sd]), P.rho_L, VAR ? rn[ax * 2 + sd] : P.rho_G);
           d += sc * 0.5 * (beta + bn);
           d32 += fo.sc * 0.5 * (b32 + (double)(float)bn);
         } else if (pressure_dirichlet(P.kind[ax * 2 + sd])) {
@@ -1096,7 +1155,7 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(DevParams P, const dou
       fo.q[c] = (float)beta;
       fo.d[c] = fo.mg ? (float)d32 : (float)d;
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------- liquid transport velocity
@@ -1343,20 +1402,31 @@ void launch_advect(const DevParams& P, const double* a1, const double* omega, co
 void launch_energy_setup(const DevParams& P, const double* a_new, const double* T_prime,
                          const double* mdot, const double* u, const double* v, const double* w,
                          double* qc, double* diag, double* b, hipStream_t s, F32Out fo) {
-  k_energy_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, T_prime, mdot, u, v, w, qc, diag, b, fo);
+  int nb;
+  const MarchGeom G = march_geom(P, nb);
+  k_energy_setup<<<nb, BLOCK, 0, s>>>(P, G, a_new, T_prime, mdot, u, v, w, qc, diag, b, fo);
 }
 void launch_species_setup(const DevParams& P, const double* a_new, const double* c_prime,
                           const double* mdot, const double* u, const double* v, const double* w,
                           double* qc, double* diag, double* b, double* om0, hipStream_t s, F32Out fo,
                           const double* corr) {
-  k_species_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, u, v, w, qc, diag, b, om0, fo, corr);
+  int nb;
+  const MarchGeom G = march_geom(P, nb);
+  if (P.rg) k_species_setup<true><<<nb, BLOCK, 0, s>>>(P, G, a_new, c_prime, mdot, u, v, w, qc, diag, b, om0, fo, corr);
+  else k_species_setup<false><<<nb, BLOCK, 0, s>>>(P, G, a_new, c_prime, mdot, u, v, w, qc, diag, b, om0, fo, corr);
 }
 void launch_species_update(const DevParams& P, const double* a_new, const double* c_prime,
                            const double* mdot, const double* om, const double* u, const double* v,
                            const double* w, double* c, double* omega, double* partials,
                            unsigned* counter, double* scal, hipStream_t s, double* corr) {
-  k_species_update<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, c_prime, mdot, om, u, v, w, c, omega, partials, counter,
-                                                      scal, corr);
+  int nb;
+  const MarchGeom G = march_geom(P, nb);
+  if (P.rg)
+    k_species_update<true><<<nb, BLOCK, 0, s>>>(P, G, a_new, c_prime, mdot, om, u, v, w, c, omega, partials, counter,
+                                                scal, corr);
+  else
+    k_species_update<false><<<nb, BLOCK, 0, s>>>(P, G, a_new, c_prime, mdot, om, u, v, w, c, omega, partials, counter,
+                                                 scal, corr);
 }
 void launch_predictor(const DevParams& P, const double* a_new, const double* xi, const double* u,
                       const double* v, const double* w, double* us, double* vs, double* ws,
@@ -1369,7 +1439,10 @@ void launch_predictor(const DevParams& P, const double* a_new, const double* xi,
 void launch_pressure_setup(const DevParams& P, const double* a_new, const double* mdot,
                            const double* us, const double* vs, const double* ws, double* qc,
                            double* diag, double* b, hipStream_t s, F32Out fo, const double* scomp) {
-  k_pressure_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, mdot, us, vs, ws, qc, diag, b, fo, scomp);
+  int nb;
+  const MarchGeom G = march_geom(P, nb);
+  if (P.rg) k_pressure_setup<true><<<nb, BLOCK, 0, s>>>(P, G, a_new, mdot, us, vs, ws, qc, diag, b, fo, scomp);
+  else k_pressure_setup<false><<<nb, BLOCK, 0, s>>>(P, G, a_new, mdot, us, vs, ws, qc, diag, b, fo, scomp);
 }
 void launch_div_setup(const DevParams& P, const double* u, const double* v, const double* w, double* qc,
                       double* diag, double* b, hipStream_t s, F32Out fo) {
