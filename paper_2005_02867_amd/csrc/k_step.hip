@@ -468,8 +468,9 @@ __device__ __forceinline__ void adv_geo_fluxes(const DevParams& P, const double*
 // lane) and loads the y neighbours.  body(c, i, j, k, ctr, nb, has) runs for
 // every cell of the box with ctr[f] the cell's value of field f and
 // nb[f][0..5] its neighbours at x-1, x+1, y-1, y+1, z-1, z+1 (the cell's own
-// value across a box face, where has[] is false).
-template <int NF, class Body>
+// value across a box face, where has[] is false).  HIGH = false: the y+1 and
+// z+1 entries are not formed (the cell's own value stands there).
+template <int NF, bool HIGH = true, class Body>
 __device__ __forceinline__ void march_cells(const DevParams& P, const MarchGeom& G,
                                             const double* const (&fld)[NF], Body&& body) {
   const int tz = threadIdx.x % MZ, ty = threadIdx.x / MZ;
@@ -501,16 +502,17 @@ __device__ __forceinline__ void march_cells(const DevParams& P, const MarchGeom&
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         xp[f] = has[1] ? fld[f][c + sx] : xc[f];
-        const double ym = fld[f][has[2] ? c - P.nz : c], yp = fld[f][has[3] ? c + P.nz : c];
-        double zm = __shfl_up(xc[f], 1), zp = __shfl_down(xc[f], 1);
+        const double ym = fld[f][has[2] ? c - P.nz : c];
+        const double yp = HIGH ? fld[f][has[3] ? c + P.nz : c] : xc[f];
+        double zm = __shfl_up(xc[f], 1), zp = HIGH ? __shfl_down(xc[f], 1) : xc[f];
         if (tz == 0) zm = fld[f][has[4] ? c - 1 : c];
-        if (tz == MZ - 1) zp = fld[f][has[5] ? c + 1 : c];
+        if (HIGH && tz == MZ - 1) zp = fld[f][has[5] ? c + 1 : c];
         nb[f][0] = has[0] ? xm[f] : xc[f];
         nb[f][1] = xp[f];
         nb[f][2] = ym;
         nb[f][3] = yp;
         nb[f][4] = has[4] ? zm : xc[f];
-        nb[f][5] = has[5] ? zp : xc[f];
+        nb[f][5] = (HIGH && has[5]) ? zp : xc[f];
       }
       if (live) body(c, x, j, k, xc, nb, has);
 #pragma unroll
@@ -1232,29 +1234,29 @@ __device__ __forceinline__ double project_face(const DevParams& P, const double*
 // All three face arrays in one pass over the cells (as the predictor).
 // VAR: a variable gas (its density field P.rg).
 template <bool VAR>
-__global__ void __launch_bounds__(BLOCK) k_project(DevParams P, const double* __restrict__ a_new, const double* __restrict__ p,
+__global__ void __launch_bounds__(BLOCK) k_project(DevParams P, MarchGeom G, const double* __restrict__ a_new, const double* __restrict__ p,
                           const double* __restrict__ us, const double* __restrict__ vs,
                           const double* __restrict__ ws, double* __restrict__ u, double* __restrict__ v,
                           double* __restrict__ w) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
   const double ih = 1.0 / P.h;
-  const long long sx = (long long)P.ny * P.nz, sy = P.nz;
-  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
-    int i, j, k;
-    decode(P, c, i, j, k);
-    // the cell and its neighbour below along each axis (the cell itself at a low box face), every value
-    // loaded before any is used; the faces below the cell as project_face takes them
-    const long long cn[3] = {i > 0 ? c - sx : c, j > 0 ? c - sy : c, k > 0 ? c - 1 : c};
+  // the cell and its neighbour below along each axis (the cell itself at a low box face), walked along x;
+  // the faces below the cell as project_face takes them
+  constexpr int NF = VAR ? 3 : 2;   // alpha', p (, rho_G)
+  const double* fl[NF];
+  fl[0] = a_new;
+  fl[1] = p;
+  if constexpr (VAR) fl[NF - 1] = P.rg;
+  march_cells<NF, false>(P, G, fl, [&](long long c, int i, int j, int k, const double (&ctr)[NF],
+                                       const double (&nb)[NF][6], const bool (&has)[6]) {
     const long long e[3] = {uidx(P, i, j, k), vidx(P, i, j, k), widx(P, i, j, k)};
     const double fs[3] = {us[e[0]], vs[e[1]], ws[e[2]]};
-    const double ac = a_new[c], pc = p[c], gc = VAR ? P.rg[c] : P.rho_G;
+    const double ac = ctr[0], pc = ctr[1], gc = VAR ? ctr[NF - 1] : P.rho_G;
     double an[3], pn[3], gn[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      an[q] = a_new[cn[q]];
-      pn[q] = p[cn[q]];
-      gn[q] = VAR ? P.rg[cn[q]] : P.rho_G;
+      an[q] = nb[0][2 * q];
+      pn[q] = nb[1][2 * q];
+      gn[q] = VAR ? nb[NF - 1][2 * q] : P.rho_G;
     }
     const double bC = 1.0 / mix(clamp01(ac), P.rho_L, gc);
     const int pos[3] = {i, j, k};
@@ -1273,7 +1275,7 @@ __global__ void __launch_bounds__(BLOCK) k_project(DevParams P, const double* __
     if (i == P.nx - 1) u[uidx(P, P.nx, j, k)] = project_face<0, VAR>(P, a_new, p, us, P.nx, j, k, ih);
     if (j == P.ny - 1) v[vidx(P, i, P.ny, k)] = project_face<1, VAR>(P, a_new, p, vs, i, P.ny, k, ih);
     if (k == P.nz - 1) w[widx(P, i, j, P.nz)] = project_face<2, VAR>(P, a_new, p, ws, i, j, P.nz, ih);
-  }
+  });
 }
 
 // ---------------------------------------------------------------- S12
@@ -1451,8 +1453,10 @@ void launch_div_setup(const DevParams& P, const double* u, const double* v, cons
 void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
                     const double* vs, const double* ws, double* u, double* v, double* w,
                     hipStream_t s) {
-  if (P.rg) k_project<true><<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, p, us, vs, ws, u, v, w);
-  else k_project<false><<<grid_blocks(P.n), BLOCK, 0, s>>>(P, a_new, p, us, vs, ws, u, v, w);
+  int nb;
+  const MarchGeom G = march_geom(P, nb);
+  if (P.rg) k_project<true><<<nb, BLOCK, 0, s>>>(P, G, a_new, p, us, vs, ws, u, v, w);
+  else k_project<false><<<nb, BLOCK, 0, s>>>(P, G, a_new, p, us, vs, ws, u, v, w);
 }
 void launch_diagnostics(const DevParams& P, const double* alpha, const double* c, const double* T,
                         const double* p, const double* mdot, double* partials, unsigned* counter,
