@@ -1022,10 +1022,11 @@ int solve_potential(ds_grid* g, double* x, hipStream_t s, int* iters, double* re
       L.sc = sc;
       L.qc = g->qc;
       L.diag = g->diag;
+      L.qk = 1.0 / P.dt;   // the value qc holds in every cell
       pressure_type(g, 2, L);
       int st;
       if ((st = init_status(g, 2, tol, g->prm.maxit, s)) != DS_OK) return st;
-      launch_resid64(L, g->b, x, g->r, g->status + 2, g->partials, g->counters + CT_SOLVE0, true, s);
+      launch_resid64(L, g->b, x, g->r, g->status + 2, g->partials, g->counters + CT_SOLVE0, true, s, nullptr, true);
       HIPCHK(g, hipGetLastError());
       if ((st = sync_status(g, 2, s)) != DS_OK) return st;
       if (g->h_status[2].done == 1) {
@@ -1140,22 +1141,27 @@ int one_step(ds_grid* g, hipStream_t s) {
   };
   // 3 (first part).  The liquid-transport potential reads only u^n: by the direct solve it runs on the second
   // stream (on the pressure's own arrays, their A p array as the transforms' scratch) while the evaporation and
-  // liquid sources run on s.
+  // liquid sources run on s.  Its residual check takes the constant coefficient 1/dt from its value (no
+  // operator arrays written or read) and keeps only the status (no residual array) where the marching
+  // residual kernel runs; the multigrid CG that would take over on s sets up its own.
   const bool phi_fork = overlap && g->prm.liquid_transport && potential_direct(g);
   if (phi_fork) {
     const PBufs& B = g->pb[1];
     const double sc = P.dt / (P.h * P.h);
-    if ((st = fork()) != DS_OK) return st;
-    launch_div_setup(P, g->u, g->v, g->w, B.qc, B.diag, B.b, g->s2);
-    if (launch_fdm_solve(P, sc * (1.0 / P.dt), B.b, g->phi, B.q, g->s2) != 0)
-      return fail(g, DS_ERR_STATE, "internal: the direct potential solve refused the grid");
     Lev<double> L = g->L0;
     L.sc = sc;
     L.qc = B.qc;
     L.diag = B.diag;
+    L.qk = 1.0 / P.dt;
     pressure_type(g, 2, L);
+    const bool cq = resid64_cq_ok(L);
+    if ((st = fork()) != DS_OK) return st;
+    launch_div_setup(P, g->u, g->v, g->w, cq ? nullptr : B.qc, cq ? nullptr : B.diag, B.b, g->s2);
+    if (launch_fdm_solve(P, sc * (1.0 / P.dt), B.b, g->phi, B.q, g->s2) != 0)
+      return fail(g, DS_ERR_STATE, "internal: the direct potential solve refused the grid");
     if ((st = init_status(g, 2, g->prm.tol_phi, g->prm.maxit, g->s2)) != DS_OK) return st;
-    launch_resid64(L, B.b, g->phi, B.r, g->status + 2, B.partials, B.counters + CT_SOLVE0, true, g->s2);
+    launch_resid64(L, B.b, g->phi, cq ? nullptr : B.r, g->status + 2, B.partials, B.counters + CT_SOLVE0, true,
+                   g->s2, nullptr, cq);
     HIPCHK(g, hipGetLastError());
   }
   // 1-2. evaporation source and liquid source
@@ -1182,7 +1188,7 @@ int one_step(ds_grid* g, hipStream_t s) {
     st = solve_potential(g, g->phi, s, &D.iters_phi, &D.res_phi, g->prm.tol_phi, own);
     if (st == DS_ERR_NOT_CONVERGED) rc = st;
     else if (st != DS_OK) return st;
-  } else {
+  } else if (!g->prm.liquid_transport) {
     D.iters_phi = 0;
     D.res_phi = 0.0;
   }

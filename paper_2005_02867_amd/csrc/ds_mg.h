@@ -197,9 +197,15 @@ template <class T>
 bool cg_defers_x(const Lev<T>& L);
 
 // r = b - A x (FP64), ||b|| (if set_bnorm), ||r|| -> status (done if ||r|| <= tol ||b||).
-// r32 (may be null): also store r in FP32.
+// r32 (may be null): also store r in FP32.  r may be null where only the
+// status is wanted (the marching form; see resid64_cq_ok).  cq: the operator's
+// coefficient is L.qk in every cell (nonzero), taken from that value instead
+// of loaded from L.qc -- the same arithmetic -- where resid64_cq_ok(L).
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
-                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s, float* r32 = nullptr);
+                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s, float* r32 = nullptr,
+                    bool cq = false);
+// Does launch_resid64 take the marching form on L (which honours cq and a null r)?
+bool resid64_cq_ok(const Lev<double>& L);
 // st->zero (b = 0): x = 0 and, with r, the residual r = 0 to match.
 void launch_zero_if_flagged(double* x, long long n, const SolveStatus* st, hipStream_t s, double* r = nullptr);
 template <class T>

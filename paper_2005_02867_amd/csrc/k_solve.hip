@@ -1363,13 +1363,15 @@ VEC_KERNEL_M k_mg_rb_v(Lev<T> F, Lev<T> C, const T* __restrict__ r, const T* __r
 
 // r32 (may be null): also r in FP32 (the V-cycle's input at the start of a
 // solve in the FP32-multigrid form).
-template <int NT>
+// CQ: the coefficient is L.qk in every cell (no q loads).  r may be null
+// (the status only).
+template <int NT, bool CQ = false>
 VEC_KERNEL_M k_resid64_v(Lev<double> L, const double* __restrict__ b, const double* __restrict__ x,
                        double* __restrict__ r, SolveStatus* st, double* partials, unsigned* counter, int set_bnorm,
                        float* __restrict__ r32) {
   constexpr int V = VW<double>::n;
   double acc[2] = {0.0, 0.0};
-  march<double, NT>(
+  march<double, NT, true, CQ>(
       L, [&](unsigned f, double(&o)[V]) { ldv<double>(at(x, f), o); }, [&](unsigned f) { return *at(x, f); },
       [&](unsigned c, const double(&qv)[V], const double(&xv)[V], const double(&off)[V], const double(&dg)[V]) {
         double bv[V], o[V];
@@ -1381,7 +1383,7 @@ VEC_KERNEL_M k_resid64_v(Lev<double> L, const double* __restrict__ b, const doub
           acc[0] += bv[v] * bv[v];
           acc[1] += o[v] * o[v];
         }
-        stv<double>(at(r, c), o);
+        if (r) stv<double>(at(r, c), o);
         if (r32) {
           float2 rf;
           rf.x = (float)o[0];
@@ -2399,13 +2401,18 @@ template double replay_operator_kernel<float>(const Lev<float>&, const float*, c
                                               SolveStatus*, double*, unsigned*, int, hipStream_t, hipEvent_t,
                                               hipEvent_t);
 
+bool resid64_cq_ok(const Lev<double>& L) { return use_vec(L); }
 void launch_resid64(const Lev<double>& L, const double* b, const double* x, double* r, SolveStatus* st,
-                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s, float* r32) {
+                    double* partials, unsigned* counter, bool set_bnorm, hipStream_t s, float* r32, bool cq) {
   if (use_vec(L)) {
     const Lev<double> M = march_lev(L);
     with_nt(M.mnt, [&](auto K) {
       constexpr int NT = decltype(K)::value;
-      k_resid64_v<NT><<<march_blocks(M), NT, 0, s>>>(M, b, x, r, st, partials, counter, set_bnorm ? 1 : 0, r32);
+      if (cq && M.qk != 0.0)
+        k_resid64_v<NT, true><<<march_blocks(M), NT, 0, s>>>(M, b, x, r, st, partials, counter, set_bnorm ? 1 : 0,
+                                                             r32);
+      else
+        k_resid64_v<NT><<<march_blocks(M), NT, 0, s>>>(M, b, x, r, st, partials, counter, set_bnorm ? 1 : 0, r32);
     });
   } else {
     k_resid64<<<tile_blocks(L.ntiles), BLOCK, 0, s>>>(L, b, x, r, st, partials, counter, set_bnorm ? 1 : 0);

@@ -285,9 +285,9 @@ def test_overlapped_pressure_is_bit_identical(case, precision, monkeypatch):
     on one stream, on the shared arrays); with the direct potential solve the
     potential runs on the second stream too, beside the evaporation source.
     The stages touch disjoint data, so five steps give every field bit for
-    bit the same, with the same iteration counts and budget terms (B_L, B_v,
-    fuel mass), in both precision forms; the 64^3 cut of the
-    forced-convection configuration takes several batches of pressure
+    bit the same, with the same iteration counts, budget terms (B_L, B_v,
+    fuel mass) and potential residual, in both precision forms; the 64^3 cut
+    of the forced-convection configuration takes several batches of pressure
     iterations per step."""
     ds = _lib()
     name, tag = case.split("-")
@@ -309,11 +309,16 @@ def test_overlapped_pressure_is_bit_identical(case, precision, monkeypatch):
         for _ in range(5):
             g.step(1)
             d = g.diagnostics()
-            n_it.append((d["iters_T"], d["iters_omega"], d["iters_p"], d["B_L"], d["B_v"], d["fuel_mass"]))
+            n_it.append((d["iters_T"], d["iters_omega"], d["iters_p"], d["B_L"], d["B_v"], d["fuel_mass"],
+                         d["iters_phi"], d["res_phi"]))
         out.append({k: v.cpu() for k, v in g.get_fields().items()})
         its.append(n_it)
         del g
-    print("iterations T/omega/p, B_L, B_v, fuel mass per step, overlapped:", its[0])
+    print("iterations T/omega/p, B_L, B_v, fuel mass, potential iterations and residual per step, overlapped:",
+          its[0])
     assert its[0] == its[1]
+    # the potential's residual is reported (the first step's u^0 = 0 gives b = 0 and a zero residual)
+    res_phi = [t[-1] for t in its[0]]
+    assert all(0.0 <= r <= prm["tol_phi"] for r in res_phi) and max(res_phi) > 0.0, res_phi
     for k in out[0]:
         assert torch.equal(out[0][k], out[1][k]), k
