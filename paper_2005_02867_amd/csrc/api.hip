@@ -1287,10 +1287,10 @@ int one_step(ds_grid* g, hipStream_t s) {
     else if (st != DS_OK) return st;
   }
   if (join.on && (st = join_now()) != DS_OK) return st;   // the projection reads p and u* from the second stream
-  launch_project(Pp, g->a_new, g->p, g->us, g->vs, g->ws, g->u, g->v, g->w, s);
+  // 7. projection, and the diagnostics of the new state (alpha = alpha') in the same pass
+  launch_project_diagnostics(Pp, g->a_new, g->p, g->us, g->vs, g->ws, g->u, g->v, g->w, g->c, g->T, g->mdot,
+                             g->partials, g->counters + CT_DIAG, g->scal, s);
   std::swap(g->alpha, g->a_new);
-  // diagnostics
-  launch_diagnostics(P, g->alpha, g->c, g->T, g->p, g->mdot, g->partials, g->counters + CT_DIAG, g->scal, s);
   HIPCHK(g, hipGetLastError());
   if ((st = read_scalars(g, s)) != DS_OK) return st;
   const double* sc = g->h_scal;

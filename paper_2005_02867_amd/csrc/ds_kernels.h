@@ -77,6 +77,12 @@ void launch_pressure_setup(const DevParams& P, const double* a_new, const double
 void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
                     const double* vs, const double* ws, double* u, double* v, double* w,
                     hipStream_t s);
+// The projection and, in the same pass, the diagnostics of launch_diagnostics
+// over alpha = a_new (the state after the step), c, T, p and mdot.
+void launch_project_diagnostics(const DevParams& P, const double* a_new, const double* p, const double* us,
+                                const double* vs, const double* ws, double* u, double* v, double* w,
+                                const double* c, const double* T, const double* mdot, double* partials,
+                                unsigned* counter, double* scal, hipStream_t s);
 void launch_diagnostics(const DevParams& P, const double* alpha, const double* c, const double* T,
                         const double* p, const double* mdot, double* partials, unsigned* counter,
                         double* scal, hipStream_t s);

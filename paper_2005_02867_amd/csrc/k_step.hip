@@ -1232,13 +1232,17 @@ __device__ __forceinline__ double project_face(const DevParams& P, const double*
 }
 
 // All three face arrays in one pass over the cells (as the predictor).
-// VAR: a variable gas (its density field P.rg).
-template <bool VAR>
+// VAR: a variable gas (its density field P.rg).  DIAG: the step's closing
+// diagnostics in the same pass (the sums, extremes and finiteness test of
+// k_diagnostics over alpha = a_new, c, T, p and mdot).
+template <bool VAR, bool DIAG>
 __global__ void __launch_bounds__(BLOCK) k_project(DevParams P, MarchGeom G, const double* __restrict__ a_new, const double* __restrict__ p,
                           const double* __restrict__ us, const double* __restrict__ vs,
                           const double* __restrict__ ws, double* __restrict__ u, double* __restrict__ v,
-                          double* __restrict__ w) {
+                          double* __restrict__ w, const double* __restrict__ cf, const double* __restrict__ Tf,
+                          const double* __restrict__ mdot, double* partials, unsigned* counter, double* scal) {
   const double ih = 1.0 / P.h;
+  double acc[6] = {0.0, 0.0, 0.0, __builtin_inf(), -__builtin_inf(), 0.0};
   // the cell and its neighbour below along each axis (the cell itself at a low box face), walked along x;
   // the faces below the cell as project_face takes them
   constexpr int NF = VAR ? 3 : 2;   // alpha', p (, rho_G)
@@ -1275,7 +1279,32 @@ __global__ void __launch_bounds__(BLOCK) k_project(DevParams P, MarchGeom G, con
     if (i == P.nx - 1) u[uidx(P, P.nx, j, k)] = project_face<0, VAR>(P, a_new, p, us, P.nx, j, k, ih);
     if (j == P.ny - 1) v[vidx(P, i, P.ny, k)] = project_face<1, VAR>(P, a_new, p, vs, i, P.ny, k, ih);
     if (k == P.nz - 1) w[widx(P, i, j, P.nz)] = project_face<2, VAR>(P, a_new, p, ws, i, j, P.nz, ih);
+    if constexpr (DIAG) {
+      const double cv = cf[c];
+      acc[0] += ac;
+      acc[1] += P.rho_L * ac + cv;
+      acc[2] += mdot[c];
+      acc[3] = fmin(acc[3], ac);
+      acc[4] = fmax(acc[4], ac);
+      if (!isfinite(ac + cv + Tf[c] + pc)) acc[5] += 1.0;
+    }
   });
+  if constexpr (DIAG) {
+    const int ops[6] = {RSUM, RSUM, RSUM, RMIN, RMAX, RSUM};
+    if (block_reduce_publish<6>(acc, ops, partials, counter)) {
+      double tot[6];
+      block_combine<6>(ops, partials, counter, tot);
+      if (threadIdx.x == 0) {
+        const double vol = P.h * P.h * P.h;
+        scal[SC_VOL] = vol * tot[0];
+        scal[SC_FUEL] = vol * tot[1];
+        scal[SC_MDOT] = vol * tot[2];
+        scal[SC_AMIN] = tot[3];
+        scal[SC_AMAX] = tot[4];
+        scal[SC_NONFINITE] = tot[5];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------- S12
@@ -1455,8 +1484,25 @@ void launch_project(const DevParams& P, const double* a_new, const double* p, co
                     hipStream_t s) {
   int nb;
   const MarchGeom G = march_geom(P, nb);
-  if (P.rg) k_project<true><<<nb, BLOCK, 0, s>>>(P, G, a_new, p, us, vs, ws, u, v, w);
-  else k_project<false><<<nb, BLOCK, 0, s>>>(P, G, a_new, p, us, vs, ws, u, v, w);
+  if (P.rg)
+    k_project<true, false><<<nb, BLOCK, 0, s>>>(P, G, a_new, p, us, vs, ws, u, v, w, nullptr, nullptr, nullptr,
+                                                nullptr, nullptr, nullptr);
+  else
+    k_project<false, false><<<nb, BLOCK, 0, s>>>(P, G, a_new, p, us, vs, ws, u, v, w, nullptr, nullptr, nullptr,
+                                                 nullptr, nullptr, nullptr);
+}
+void launch_project_diagnostics(const DevParams& P, const double* a_new, const double* p, const double* us,
+                                const double* vs, const double* ws, double* u, double* v, double* w,
+                                const double* c, const double* T, const double* mdot, double* partials,
+                                unsigned* counter, double* scal, hipStream_t s) {
+  int nb;
+  const MarchGeom G = march_geom(P, nb);
+  if (P.rg)
+    k_project<true, true><<<nb, BLOCK, 0, s>>>(P, G, a_new, p, us, vs, ws, u, v, w, c, T, mdot, partials, counter,
+                                               scal);
+  else
+    k_project<false, true><<<nb, BLOCK, 0, s>>>(P, G, a_new, p, us, vs, ws, u, v, w, c, T, mdot, partials, counter,
+                                                scal);
 }
 void launch_diagnostics(const DevParams& P, const double* alpha, const double* c, const double* T,
                         const double* p, const double* mdot, double* partials, unsigned* counter,
