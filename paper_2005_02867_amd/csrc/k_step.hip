@@ -1164,40 +1164,62 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(DevParams P, MarchGeom
 // System D G phi = D u for the divergence-free part u - G phi of the face
 // velocities (same boundary kinds as the pressure), written in the pressure
 // operator's form with q = 1/dt: (dt/h^2)(1/dt) = 1/h^2 per face.
-__global__ void __launch_bounds__(BLOCK) k_div_setup(DevParams P, const double* __restrict__ u, const double* __restrict__ v,
+// Walks the x-plane tiles: u at the face above a cell is the next plane's
+// face below, w above a cell comes from the next lane (lanes past the box
+// load the box face's w), only v's two faces are loaded per cell.
+__global__ void __launch_bounds__(BLOCK) k_div_setup(DevParams P, MarchGeom G, const double* __restrict__ u, const double* __restrict__ v,
                             const double* __restrict__ w, double* __restrict__ qc, double* __restrict__ diag,
                             double* __restrict__ b, F32Out fo) {
-  long long b0, b1;
-  block_range(P.n, b0, b1);
   const double ih = 1.0 / P.h;
   const double ih2 = 1.0 / (P.h * P.h);
   const double q = 1.0 / P.dt, q32 = (double)(float)q;
-  for (long long c = b0 + threadIdx.x; c < b1; c += BLOCK) {
-    int i, j, k;
-    decode(P, c, i, j, k);
-    double d = 0.0, d32 = 0.0;
+  const bool op = qc || fo.q;   // the operator is written too
+  const int tz = threadIdx.x % MZ, ty = threadIdx.x / MZ;
+  const long long sx = (long long)P.ny * P.nz;
+  for (long long t = march_logical(); t < G.tiles; t += gridDim.x) {
+    int x0, y0, z0;
+    march_tile(G, t, x0, y0, z0);
+    const int x1 = min(x0 + G.xlen, P.nx);
+    const int j = y0 + ty, k = z0 + tz;
+    const bool live = j < P.ny && k < P.nz;
+    const int jc = min(j, P.ny - 1), kc = min(k, P.nz - 1), kf = min(k, P.nz);
+    double u0 = u[uidx(P, x0, jc, kc)];
+    for (int x = x0; x < x1; ++x) {
+      const double u1 = u[uidx(P, x + 1, jc, kc)];
+      const double v0 = v[vidx(P, x, jc, kc)], v1 = v[vidx(P, x, jc + 1, kc)];
+      const double w0 = w[widx(P, x, jc, kf)];
+      double w1 = __shfl_down(w0, 1);
+      if (tz == MZ - 1) w1 = w[widx(P, x, jc, min(k + 1, P.nz))];
+      if (live) {
+        const long long c = x * sx + (long long)j * P.nz + k;
+        if (op) {
+          const int pos[3] = {x, j, k}, ext[3] = {P.nx, P.ny, P.nz};
+          double d = 0.0, d32 = 0.0;
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax)
+          for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-      for (int sd = 0; sd < 2; ++sd) {
-        if (nbr(P, ax, sd, i, j, k) >= 0) {
-          d += ih2;
-          d32 += fo.sc * 0.5 * (q32 + q32);
-        } else if (pressure_dirichlet(P.kind[ax * 2 + sd])) {
-          d += 2.0 * ih2;
-          d32 += 2.0 * fo.sc * q32;
+            for (int sd = 0; sd < 2; ++sd) {
+              if (sd ? pos[ax] < ext[ax] - 1 : pos[ax] > 0) {
+                d += ih2;
+                d32 += fo.sc * 0.5 * (q32 + q32);
+              } else if (pressure_dirichlet(P.kind[ax * 2 + sd])) {
+                d += 2.0 * ih2;
+                d32 += 2.0 * fo.sc * q32;
+              }
+            }
+          if (qc) {   // null: the right-hand side only (the operator is kept from an earlier call)
+            qc[c] = q;
+            diag[c] = d;
+          }
+          if (fo.q) {
+            fo.q[c] = (float)q;
+            fo.d[c] = fo.mg ? (float)d32 : (float)d;
+          }
         }
+        const double div = ((u1 - u0) + (v1 - v0) + (w1 - w0)) * ih;
+        b[c] = -div;
       }
-    const double div = ((u[uidx(P, i + 1, j, k)] - u[uidx(P, i, j, k)]) + (v[vidx(P, i, j + 1, k)] - v[vidx(P, i, j, k)]) +
-                        (w[widx(P, i, j, k + 1)] - w[widx(P, i, j, k)])) * ih;
-    if (qc) {   // null: the right-hand side only (the operator is kept from an earlier call)
-      qc[c] = q;
-      diag[c] = d;
-    }
-    b[c] = -div;
-    if (fo.q) {
-      fo.q[c] = (float)q;
-      fo.d[c] = fo.mg ? (float)d32 : (float)d;
+      u0 = u1;
     }
   }
 }
@@ -1477,7 +1499,9 @@ void launch_pressure_setup(const DevParams& P, const double* a_new, const double
 }
 void launch_div_setup(const DevParams& P, const double* u, const double* v, const double* w, double* qc,
                       double* diag, double* b, hipStream_t s, F32Out fo) {
-  k_div_setup<<<grid_blocks(P.n), BLOCK, 0, s>>>(P, u, v, w, qc, diag, b, fo);
+  int nb;
+  const MarchGeom G = march_geom(P, nb);
+  k_div_setup<<<nb, BLOCK, 0, s>>>(P, G, u, v, w, qc, diag, b, fo);
 }
 void launch_project(const DevParams& P, const double* a_new, const double* p, const double* us,
                     const double* vs, const double* ws, double* u, double* v, double* w,
