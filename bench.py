@@ -50,15 +50,15 @@ EXPLICIT_B = {            # FP64 stages, once per step
     "k_species_update": 72,      # alpha', c', mdot, omega, u, v, w read; c, omega written
     "k_predictor": 64,           # alpha', xi, u, v, w read; u*, v*, w* written
     "k_pressure_setup": 80,      # alpha', mdot, u*, v*, w* read; q, diag, b and FP32 q, diag written
-    "k_project": 64,             # alpha', p, u*, v*, w* read; u, v, w written
-    "k_diagnostics": 40,         # alpha, c, T, p, mdot read
+    "k_project": 88,             # alpha', p, u*, v*, w* read; u, v, w written; c, T, mdot read for the
+                                 # step's diagnostics, taken in the same pass
 }
 RB_ZERO_B, RB_GEN_B, RB_PROLONG_B = 12, 16, 16.5    # coloured sweeps (r, q [, x, x_coarse] read; x written)
 RESTRICT_B = 12.5                                   # r, x, q read; coarse r written
 SMOOTH_TWO_B, SMOOTH_B, PROLONG_SMOOTH_B = 12, 16, 16.5
 CG_OP_B, CG_OP_CQ_B, CG_UPDATE_B = 44, 40, 28       # FP64 CG with FP32 directions; residual update (+ FP32 r)
 RESID64_B, AXPY_B = 36, 20
-DIRECT_POTENTIAL_B = 5 * 16 + 32 + 16               # five transform passes, residual check, q and diag written
+DIRECT_POTENTIAL_B = 5 * 16 + 16                    # five transform passes; residual check (phi, b read)
 INNER_ITER_B = 32 + 24                              # FP32 CG operator + Neumann-polynomial residual update
 ROUND_B = 16 + 12 + 24 + 40                         # round start, first z, correction, FP64 residual
 
