@@ -1001,8 +1001,8 @@ __device__ __forceinline__ void pred_store(const PredPlane<QF>& f, double (*S)[Q
 // x+1 values; the x-1 values are kept from the previous plane.  Two LDS
 // slots: the loads of plane x+2 are issued before plane x is computed and
 // land in plane x's slot after it (two barriers per plane), which keeps the
-// block at 31.7 KB of LDS so that the registers, not the LDS, bound the
-// occupancy.  VAR: a variable gas (its density field P.rg rides along as a
+// block at 31.7 KB of LDS (38 KB with the gas density) so that the
+// registers, not the LDS, bound the occupancy.  VAR: a variable gas (its density field P.rg rides along as a
 // sixth tile).
 template <bool VAR>
 __global__ void __launch_bounds__(BLOCK)
