@@ -550,3 +550,36 @@ def test_step_parity_viscous_precision_form_32cubed():
     with pytest.raises(ds.DSError) as e:
         g.forward_record(2, 1)
     assert e.value.code == ds.DS_ERR_ARG
+
+
+@pytest.mark.parametrize("case", ["ragged", "C1"])
+def test_step_diagnostics_match_the_fields(case):
+    """The step's closing diagnostics, computed in the projection's pass,
+    against the same quantities taken from the state the step leaves, summed
+    with torch in FP64: h^3 sum(alpha) (and the handle's own volume reduction,
+    a separate kernel), h^3 sum(rho_L alpha + c) and h^3 sum(mdot) to 1e-12,
+    alpha's extremes exactly; three steps on a ragged grid and of the C1
+    droplet."""
+    ds = _lib()
+    if case == "ragged":
+        prm, _ = _grid_params(n=(17, 19, 23), L=17 * 1.25e-4)
+        f = W.random_fields(prm, seed=21)
+    else:
+        prm, run = W.config("C1")
+        f = W.initial_fields(prm, **run)
+    print(f"step diagnostics against the fields: {case}", flush=True)
+    g = ds.Grid(prm)
+    g.set_fields(f)
+    h3 = prm["h"] ** 3
+    for n in range(3):
+        g.step(1)
+        d = g.diagnostics()
+        a = g.get_fields()["alpha"].double()
+        c = g.internal(ds.FIELD_C)
+        mdot = g.internal(ds.FIELD_MDOT)
+        assert d["volume"] == pytest.approx(h3 * float(a.sum()), rel=1e-12), n
+        assert d["volume"] == pytest.approx(g.droplet_volume(), rel=1e-13), n
+        assert d["fuel_mass"] == pytest.approx(h3 * float((prm["rho_L"] * a + c).sum()), rel=1e-12), n
+        assert d["mdot_total"] == pytest.approx(h3 * float(mdot.sum()), rel=1e-12,
+                                                abs=1e-12 * h3 * float(mdot.abs().sum())), n
+        assert d["alpha_min"] == float(a.min()) and d["alpha_max"] == float(a.max()), n
